@@ -1,0 +1,552 @@
+/*
+ * Oracle for the accelerated-expression primitives -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, sequential CPU interpreter of what the parallel keywords of
+ * the paper's source language compute (Appendix A, the Futhark and CUDA
+ * extensions of the core language; Figure "Extensions of expressions"):
+ *
+ *   map f s        apply f to every element of s
+ *   map2 f s1 s2   apply f elementwise to two sequences of equal length
+ *   reduce f ne s  combine s with the associative f and neutral element ne;
+ *                  evaluated here as the sequential left fold (Listing 1 uses
+ *                  `reduce addi 0` and `foldl addi 0` interchangeably, and the
+ *                  dynamic assumptions of Appendix "Dynamic Assumptions" make
+ *                  every bracketing give the same value)
+ *   flatten s      concatenation of inner sequences
+ *   loop n f       f i for every i in [0, n); run here in ascending order
+ *
+ * Every floating-point quantity is carried in IEEE binary64 and every integer in
+ * int64 (the paper's compiler always uses 64-bit integers, Section 5.1).  Build
+ * with -O2 -ffp-contract=off and without -ffast-math, so each operation below
+ * is one correctly rounded IEEE operation in the order written.
+ *
+ * The config programs (dot product, ragged row sums, dense map-map-reduce,
+ * N-body loop, k-means step, batched dot/matvec) are written as compositions
+ * of these combinators, with no blocking, fusion or reordering.
+ *
+ * Only tests, the smoke check and the bench's CPU-baseline leg may call this
+ * code.  It shares no source with the GPU library.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- operator tables (numbering mirrors the public enum values so that the
+ *      same integer names the same operator on both sides; the code is separate) */
+enum { OR_ADD = 0, OR_MUL = 1, OR_MIN = 2, OR_MAX = 3 };
+enum { OR_U_ID = 0, OR_U_NEG = 1, OR_U_ABS = 2, OR_U_SQ = 3, OR_U_AFFINE = 4,
+       OR_U_EXP = 5, OR_U_LOG = 6, OR_U_SQRT = 7, OR_U_RSQRT = 8 };
+enum { OR_B_ADD = 0, OR_B_SUB = 1, OR_B_MUL = 2, OR_B_DIV = 3, OR_B_MIN = 4, OR_B_MAX = 5 };
+
+/* ------------------------------------------------------------------------ */
+/* Binary operators f : T -> T -> T used as reduce operators.                */
+/* ------------------------------------------------------------------------ */
+static double red_f64(int op, double x, double y)
+{
+    switch (op) {
+    case OR_ADD: return x + y;
+    case OR_MUL: return x * y;
+    case OR_MIN: return y < x ? y : x;
+    case OR_MAX: return y > x ? y : x;
+    }
+    return NAN;
+}
+
+static int64_t red_i64(int op, int64_t x, int64_t y)
+{
+    /* two's-complement wrap-around, computed in unsigned arithmetic */
+    switch (op) {
+    case OR_ADD: return (int64_t)((uint64_t)x + (uint64_t)y);
+    case OR_MUL: return (int64_t)((uint64_t)x * (uint64_t)y);
+    case OR_MIN: return y < x ? y : x;
+    case OR_MAX: return y > x ? y : x;
+    }
+    return 0;
+}
+
+/* Map bodies.  AFFINE is x -> p0*x + p1 (a lambda with two captured
+ * constants, e.g. the body `muli c (addi x 1)` of Listing 2 is p0 = p1 = c). */
+static double un_f64(int f, double x, double p0, double p1)
+{
+    switch (f) {
+    case OR_U_ID: return x;
+    case OR_U_NEG: return -x;
+    case OR_U_ABS: return fabs(x);
+    case OR_U_SQ: return x * x;
+    case OR_U_AFFINE: return p0 * x + p1;
+    case OR_U_EXP: return exp(x);
+    case OR_U_LOG: return log(x);
+    case OR_U_SQRT: return sqrt(x);
+    case OR_U_RSQRT: return 1.0 / sqrt(x);
+    }
+    return NAN;
+}
+
+static int64_t un_i64(int f, int64_t x, int64_t p0, int64_t p1)
+{
+    switch (f) {
+    case OR_U_ID: return x;
+    case OR_U_NEG: return (int64_t)(0u - (uint64_t)x);
+    case OR_U_ABS: return x < 0 ? (int64_t)(0u - (uint64_t)x) : x;
+    case OR_U_SQ: return (int64_t)((uint64_t)x * (uint64_t)x);
+    case OR_U_AFFINE: return (int64_t)((uint64_t)p0 * (uint64_t)x + (uint64_t)p1);
+    }
+    return 0;
+}
+
+static double bin_f64(int f, double x, double y)
+{
+    switch (f) {
+    case OR_B_ADD: return x + y;
+    case OR_B_SUB: return x - y;
+    case OR_B_MUL: return x * y;
+    case OR_B_DIV: return x / y;
+    case OR_B_MIN: return y < x ? y : x;
+    case OR_B_MAX: return y > x ? y : x;
+    }
+    return NAN;
+}
+
+static int64_t bin_i64(int f, int64_t x, int64_t y)
+{
+    switch (f) {
+    case OR_B_ADD: return (int64_t)((uint64_t)x + (uint64_t)y);
+    case OR_B_SUB: return (int64_t)((uint64_t)x - (uint64_t)y);
+    case OR_B_MUL: return (int64_t)((uint64_t)x * (uint64_t)y);
+    case OR_B_MIN: return y < x ? y : x;
+    case OR_B_MAX: return y > x ? y : x;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* map / map2 (Appendix A: `map e1 e2`, `map2 e1 e2 e3`)                     */
+/* ------------------------------------------------------------------------ */
+void or_map_f64(int f, double p0, double p1, const double *s, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = un_f64(f, s[i], p0, p1);
+}
+
+void or_map_i64(int f, int64_t p0, int64_t p1, const int64_t *s, int64_t n, int64_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = un_i64(f, s[i], p0, p1);
+}
+
+void or_map2_f64(int f, const double *s1, const double *s2, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bin_f64(f, s1[i], s2[i]);
+}
+
+void or_map2_i64(int f, const int64_t *s1, const int64_t *s2, int64_t n, int64_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bin_i64(f, s1[i], s2[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* reduce f ne s = foldl f ne s (Appendix A `reduce`; Listing 1)             */
+/* ------------------------------------------------------------------------ */
+double or_foldl_f64(int op, double ne, const double *s, int64_t n)
+{
+    double acc = ne;
+    for (int64_t i = 0; i < n; ++i) acc = red_f64(op, acc, s[i]);
+    return acc;
+}
+
+int64_t or_foldl_i64(int op, int64_t ne, const int64_t *s, int64_t n)
+{
+    int64_t acc = ne;
+    for (int64_t i = 0; i < n; ++i) acc = red_i64(op, acc, s[i]);
+    return acc;
+}
+
+/* The fused form of Listing 2 and of a dot product: reduce op ne (map2 f a b),
+ * computed literally as the map2 into a temporary and then the fold. */
+double or_map2_foldl_f64(int f, int op, double ne, const double *a, const double *b, int64_t n)
+{
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    or_map2_f64(f, a, b, n, tmp);
+    double r = or_foldl_f64(op, ne, tmp, n);
+    free(tmp);
+    return r;
+}
+
+int64_t or_map2_foldl_i64(int f, int op, int64_t ne, const int64_t *a, const int64_t *b, int64_t n)
+{
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    or_map2_i64(f, a, b, n, tmp);
+    int64_t r = or_foldl_i64(op, ne, tmp, n);
+    free(tmp);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Marshaling of a ragged sequence [[T]] (Section 4.3): the flat layout is    */
+/* the concatenation of the rows (what `flatten` returns) plus offsets, where */
+/* offsets[0] = 0 and offsets[r+1] = offsets[r] + |row r|.                    */
+/* ------------------------------------------------------------------------ */
+void or_offsets_from_lengths(const int64_t *lengths, int64_t nseg, int64_t *offsets)
+{
+    offsets[0] = 0;
+    for (int64_t r = 0; r < nseg; ++r) offsets[r + 1] = offsets[r] + lengths[r];
+}
+
+/* map (reduce op ne) over the rows of a marshalled ragged sequence */
+void or_segmented_foldl_f64(int op, double ne, const double *values, const int64_t *offsets,
+                            int64_t nseg, double *out)
+{
+    for (int64_t r = 0; r < nseg; ++r)
+        out[r] = or_foldl_f64(op, ne, values + offsets[r], offsets[r + 1] - offsets[r]);
+}
+
+void or_segmented_foldl_i64(int op, int64_t ne, const int64_t *values, const int64_t *offsets,
+                            int64_t nseg, int64_t *out)
+{
+    for (int64_t r = 0; r < nseg; ++r)
+        out[r] = or_foldl_i64(op, ne, values + offsets[r], offsets[r + 1] - offsets[r]);
+}
+
+/* Reverse of the row sum map (reduce (+) 0): every element of row r receives
+ * the upstream gradient of out[r] (the adjoint of a sum is a broadcast). */
+void or_segmented_sum_adjoint_f64(const double *gout, const int64_t *offsets, int64_t nseg,
+                                  double *gvalues)
+{
+    for (int64_t r = 0; r < nseg; ++r)
+        for (int64_t e = offsets[r]; e < offsets[r + 1]; ++e) gvalues[e] = gout[r];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense nested map-map-reduce (the sgemm pattern of Table 1):               */
+/*   C[i][j] = reduce (+) 0 (map2 (*) (row i of op(A)) (column j of op(B)))  */
+/* op(A) is A (M x K row-major) or, with ta = 1, the transpose of A stored   */
+/* K x M row-major; likewise op(B) is K x N, or with tb = 1 stored N x K.    */
+/* ------------------------------------------------------------------------ */
+void or_matmul_f64(const double *A, const double *B, double *C, int64_t M, int64_t N,
+                   int64_t K, int ta, int tb)
+{
+    double *row = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+    double *col = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+    for (int64_t i = 0; i < M; ++i) {
+        for (int64_t k = 0; k < K; ++k) row[k] = ta ? A[k * M + i] : A[i * K + k];
+        for (int64_t j = 0; j < N; ++j) {
+            for (int64_t k = 0; k < K; ++k) col[k] = tb ? B[j * K + k] : B[k * N + j];
+            C[i * N + j] = or_map2_foldl_f64(OR_B_MUL, OR_ADD, 0.0, row, col, K);
+        }
+    }
+    free(row);
+    free(col);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sequential loop around a pairwise map(reduce): gravitational N-body with  */
+/* Plummer softening, integrated by explicit (forward) Euler.  This is the   */
+/* ODE-solver pattern of the CUDA-backend evaluation (Table 2).              */
+/*   a_i = G * sum_j m_j d_ij (|d_ij|^2 + eps2)^(-3/2),  d_ij = x_j - x_i    */
+/*   x_{t+1} = x_t + dt v_t,   v_{t+1} = v_t + dt a(x_t)                     */
+/* The fold over j runs over every body including j = i, whose term is       */
+/* exactly zero because d_ii = 0.                                            */
+/* Layout: x is [N][3], m is [N].                                            */
+/* ------------------------------------------------------------------------ */
+void or_nbody_accel(const double *x, const double *m, int64_t N, double eps2, double G,
+                    double *acc)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            double dx = x[3 * j + 0] - x[3 * i + 0];
+            double dy = x[3 * j + 1] - x[3 * i + 1];
+            double dz = x[3 * j + 2] - x[3 * i + 2];
+            double s = dx * dx + dy * dy + dz * dz + eps2;
+            double phi = 1.0 / (s * sqrt(s));
+            double w = G * m[j] * phi;
+            ax = ax + w * dx;
+            ay = ay + w * dy;
+            az = az + w * dz;
+        }
+        acc[3 * i + 0] = ax;
+        acc[3 * i + 1] = ay;
+        acc[3 * i + 2] = az;
+    }
+}
+
+/* One forward-Euler step: both updates read the state at time t. */
+void or_nbody_step(const double *x, const double *v, const double *m, int64_t N, double eps2,
+                   double G, double dt, double *x_out, double *v_out)
+{
+    double *a = (double *)malloc(sizeof(double) * (size_t)(3 * (N > 0 ? N : 1)));
+    or_nbody_accel(x, m, N, eps2, G, a);
+    for (int64_t c = 0; c < 3 * N; ++c) {
+        x_out[c] = x[c] + dt * v[c];
+        v_out[c] = v[c] + dt * a[c];
+    }
+    free(a);
+}
+
+/* Kinetic energy 1/2 * sum_i m_i |v_i|^2 as a left fold over bodies. */
+double or_nbody_kinetic(const double *v, const double *m, int64_t N)
+{
+    double ke = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        double v2 = v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
+        ke = ke + 0.5 * m[i] * v2;
+    }
+    return ke;
+}
+
+/* Forward loop of nsteps; writes the final state.  If traj_x is not NULL it
+ * receives x_t for t = 0 .. nsteps (layout [nsteps+1][N][3]). */
+void or_nbody_forward(const double *x0, const double *v0, const double *m, int64_t N,
+                      double eps2, double G, double dt, int64_t nsteps, double *x_out,
+                      double *v_out, double *traj_x)
+{
+    size_t bytes = sizeof(double) * (size_t)(3 * (N > 0 ? N : 1));
+    double *x = (double *)malloc(bytes), *v = (double *)malloc(bytes);
+    double *xn = (double *)malloc(bytes), *vn = (double *)malloc(bytes);
+    memcpy(x, x0, sizeof(double) * (size_t)(3 * N));
+    memcpy(v, v0, sizeof(double) * (size_t)(3 * N));
+    for (int64_t t = 0; t < nsteps; ++t) {
+        if (traj_x) memcpy(traj_x + t * 3 * N, x, sizeof(double) * (size_t)(3 * N));
+        or_nbody_step(x, v, m, N, eps2, G, dt, xn, vn);
+        double *tx = x; x = xn; xn = tx;
+        double *tv = v; v = vn; vn = tv;
+    }
+    if (traj_x) memcpy(traj_x + nsteps * 3 * N, x, sizeof(double) * (size_t)(3 * N));
+    memcpy(x_out, x, sizeof(double) * (size_t)(3 * N));
+    memcpy(v_out, v, sizeof(double) * (size_t)(3 * N));
+    free(x); free(v); free(xn); free(vn);
+}
+
+/* Transposed-Jacobian product of the acceleration map, out = J_a(x)^T abar.
+ * Differentiating a_i gives, for d = x_j - x_k, s = |d|^2 + eps2,
+ *   M_kj = s^(-3/2) I - 3 s^(-5/2) d d^T   (symmetric in k and j),
+ *   out_k = G * sum_j M_kj (m_k abar_j - m_j abar_k),
+ * folded over j = 0..N-1 (the j = k term is exactly zero). */
+void or_nbody_accel_vjp(const double *x, const double *m, int64_t N, double eps2, double G,
+                        const double *abar, double *out)
+{
+    for (int64_t k = 0; k < N; ++k) {
+        double ox = 0.0, oy = 0.0, oz = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            double dx = x[3 * j + 0] - x[3 * k + 0];
+            double dy = x[3 * j + 1] - x[3 * k + 1];
+            double dz = x[3 * j + 2] - x[3 * k + 2];
+            double s = dx * dx + dy * dy + dz * dz + eps2;
+            double phi = 1.0 / (s * sqrt(s));
+            double psi = 3.0 * phi / s;
+            double wx = m[k] * abar[3 * j + 0] - m[j] * abar[3 * k + 0];
+            double wy = m[k] * abar[3 * j + 1] - m[j] * abar[3 * k + 1];
+            double wz = m[k] * abar[3 * j + 2] - m[j] * abar[3 * k + 2];
+            double dw = dx * wx + dy * wy + dz * wz;
+            ox = ox + G * (phi * wx - psi * dx * dw);
+            oy = oy + G * (phi * wy - psi * dy * dw);
+            oz = oz + G * (phi * wz - psi * dz * dw);
+        }
+        out[3 * k + 0] = ox;
+        out[3 * k + 1] = oy;
+        out[3 * k + 2] = oz;
+    }
+}
+
+/* One reverse step of the discrete adjoint of forward Euler:
+ *   xbar_t = xbar_{t+1} + dt * J_a(x_t)^T vbar_{t+1}
+ *   vbar_t = vbar_{t+1} + dt * xbar_{t+1}                                   */
+static void adjoint_step(const double *x_t, const double *m, int64_t N, double eps2, double G,
+                         double dt, double *xbar, double *vbar, double *tmp)
+{
+    or_nbody_accel_vjp(x_t, m, N, eps2, G, vbar, tmp);
+    for (int64_t c = 0; c < 3 * N; ++c) {
+        double xb_new = xbar[c] + dt * tmp[c];
+        double vb_new = vbar[c] + dt * xbar[c];
+        xbar[c] = xb_new;
+        vbar[c] = vb_new;
+    }
+}
+
+/* Gradient of the final kinetic energy with respect to the initial positions
+ * (and velocities), reverse sweep over a full tape of x_t. */
+double or_nbody_ke_grad_tape(const double *x0, const double *v0, const double *m, int64_t N,
+                             double eps2, double G, double dt, int64_t nsteps, double *gx0,
+                             double *gv0)
+{
+    size_t n3 = (size_t)(3 * (N > 0 ? N : 1));
+    double *traj = (double *)malloc(sizeof(double) * n3 * (size_t)(nsteps + 1));
+    double *xT = (double *)malloc(sizeof(double) * n3), *vT = (double *)malloc(sizeof(double) * n3);
+    double *tmp = (double *)malloc(sizeof(double) * n3);
+    or_nbody_forward(x0, v0, m, N, eps2, G, dt, nsteps, xT, vT, traj);
+    double ke = or_nbody_kinetic(vT, m, N);
+    for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            gx0[3 * i + c] = 0.0;
+            gv0[3 * i + c] = m[i] * vT[3 * i + c];
+        }
+    for (int64_t t = nsteps - 1; t >= 0; --t)
+        adjoint_step(traj + t * 3 * N, m, N, eps2, G, dt, gx0, gv0, tmp);
+    free(traj); free(xT); free(vT); free(tmp);
+    return ke;
+}
+
+/* Same gradient with checkpoints of (x, v) every k steps; each segment is
+ * recomputed forward from its checkpoint before its reverse sweep. */
+double or_nbody_ke_grad_ckpt(const double *x0, const double *v0, const double *m, int64_t N,
+                             double eps2, double G, double dt, int64_t nsteps, int64_t k,
+                             double *gx0, double *gv0)
+{
+    int64_t nck = (nsteps + k - 1) / k;
+    size_t n3 = (size_t)(3 * (N > 0 ? N : 1));
+    double *ckx = (double *)malloc(sizeof(double) * n3 * (size_t)(nck > 0 ? nck : 1));
+    double *ckv = (double *)malloc(sizeof(double) * n3 * (size_t)(nck > 0 ? nck : 1));
+    double *x = (double *)malloc(sizeof(double) * n3), *v = (double *)malloc(sizeof(double) * n3);
+    double *xn = (double *)malloc(sizeof(double) * n3), *vn = (double *)malloc(sizeof(double) * n3);
+    double *seg = (double *)malloc(sizeof(double) * n3 * (size_t)k);
+    double *tmp = (double *)malloc(sizeof(double) * n3);
+    memcpy(x, x0, sizeof(double) * n3);
+    memcpy(v, v0, sizeof(double) * n3);
+    for (int64_t t = 0; t < nsteps; ++t) {
+        if (t % k == 0) {
+            memcpy(ckx + (t / k) * 3 * N, x, sizeof(double) * (size_t)(3 * N));
+            memcpy(ckv + (t / k) * 3 * N, v, sizeof(double) * (size_t)(3 * N));
+        }
+        or_nbody_step(x, v, m, N, eps2, G, dt, xn, vn);
+        double *tx = x; x = xn; xn = tx;
+        double *tv = v; v = vn; vn = tv;
+    }
+    double ke = or_nbody_kinetic(v, m, N);
+    for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            gx0[3 * i + c] = 0.0;
+            gv0[3 * i + c] = m[i] * v[3 * i + c];
+        }
+    for (int64_t c0 = nck - 1; c0 >= 0; --c0) {
+        int64_t t0 = c0 * k, t1 = t0 + k < nsteps ? t0 + k : nsteps;
+        memcpy(x, ckx + c0 * 3 * N, sizeof(double) * (size_t)(3 * N));
+        memcpy(v, ckv + c0 * 3 * N, sizeof(double) * (size_t)(3 * N));
+        for (int64_t t = t0; t < t1; ++t) {
+            memcpy(seg + (t - t0) * 3 * N, x, sizeof(double) * (size_t)(3 * N));
+            or_nbody_step(x, v, m, N, eps2, G, dt, xn, vn);
+            double *tx = x; x = xn; xn = tx;
+            double *tv = v; v = vn; vn = tv;
+        }
+        for (int64_t t = t1 - 1; t >= t0; --t)
+            adjoint_step(seg + (t - t0) * 3 * N, m, N, eps2, G, dt, gx0, gv0, tmp);
+    }
+    free(ckx); free(ckv); free(x); free(v); free(xn); free(vn); free(seg); free(tmp);
+    return ke;
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-means step: map (argmin-reduce) + reduce-by-key (the histo pattern).    */
+/*   dist(i, j) = foldl (+) 0 over dims d of (x_id - c_jd)^2                 */
+/*   label_i    = the j minimising (dist(i, j), j) lexicographically         */
+/*   count_j    = #{i : label_i = j},   sum_j = foldl (+) 0 of x_i, label j  */
+/*   c'_j       = sum_j / count_j, or c_j if count_j = 0                     */
+/* X is [n][d] and C is [k][d], both row-major.                              */
+/* ------------------------------------------------------------------------ */
+double or_sqdist(const double *x, const double *c, int64_t d)
+{
+    double acc = 0.0;
+    for (int64_t t = 0; t < d; ++t) {
+        double diff = x[t] - c[t];
+        acc = acc + diff * diff;
+    }
+    return acc;
+}
+
+void or_kmeans_assign(const double *X, int64_t n, int64_t d, const double *C, int64_t k,
+                      int32_t *labels)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double best = 0.0;
+        int64_t arg = -1;
+        for (int64_t j = 0; j < k; ++j) {
+            double dj = or_sqdist(X + i * d, C + j * d, d);
+            /* (value, index) lexicographic minimum: strict < keeps the lowest index */
+            if (arg < 0 || dj < best) { best = dj; arg = j; }
+        }
+        labels[i] = (int32_t)arg;
+    }
+}
+
+void or_kmeans_update(const double *X, int64_t n, int64_t d, const int32_t *labels, int64_t k,
+                      const double *C_old, int64_t *counts, double *sums, double *C_new)
+{
+    for (int64_t j = 0; j < k; ++j) {
+        counts[j] = 0;
+        for (int64_t t = 0; t < d; ++t) sums[j * d + t] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = labels[i];
+        counts[j] = counts[j] + 1;
+        for (int64_t t = 0; t < d; ++t) sums[j * d + t] = sums[j * d + t] + X[i * d + t];
+    }
+    for (int64_t j = 0; j < k; ++j)
+        for (int64_t t = 0; t < d; ++t)
+            C_new[j * d + t] = counts[j] > 0 ? sums[j * d + t] / (double)counts[j] : C_old[j * d + t];
+}
+
+/* Within-cluster sum of squares SSE = sum_i dist(x_i, c_{label_i}) and its
+ * gradient with respect to the points, dSSE/dx_i = 2 (x_i - c_{label_i})
+ * (labels and centroids held fixed). */
+double or_kmeans_sse(const double *X, int64_t n, int64_t d, const double *C,
+                     const int32_t *labels)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc = acc + or_sqdist(X + i * d, C + (int64_t)labels[i] * d, d);
+    return acc;
+}
+
+void or_kmeans_sse_grad(const double *X, int64_t n, int64_t d, const double *C,
+                        const int32_t *labels, double gscale, double *G)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t t = 0; t < d; ++t)
+            G[i * d + t] = gscale * (2.0 * (X[i * d + t] - C[(int64_t)labels[i] * d + t]));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batched independent expressions: each task is evaluated on its own by the  */
+/* single-expression definitions above.  Task rows of the table are          */
+/* (kind, rows, cols, a_off, b_off, out_off); kind 0 = dot, 1 = matvec.      */
+/* ------------------------------------------------------------------------ */
+void or_batch_forward(const int64_t *table, int64_t ntasks, const double *A, const double *B,
+                      double *out)
+{
+    for (int64_t t = 0; t < ntasks; ++t) {
+        const int64_t *r = table + 6 * t;
+        int64_t kind = r[0], rows = r[1], cols = r[2];
+        const double *a = A + r[3], *b = B + r[4];
+        double *o = out + r[5];
+        if (kind == 0) {
+            o[0] = or_map2_foldl_f64(OR_B_MUL, OR_ADD, 0.0, a, b, cols);
+        } else {
+            for (int64_t i = 0; i < rows; ++i)
+                o[i] = or_map2_foldl_f64(OR_B_MUL, OR_ADD, 0.0, a + i * cols, b, cols);
+        }
+    }
+}
+
+/* Reverse of each task.  dot: (gA, gB) = (g * b, g * a).  matvec y = A x:
+ * gA = g x^T (outer product) and gx = A^T g, the latter as a fold over rows. */
+void or_batch_backward(const int64_t *table, int64_t ntasks, const double *A, const double *B,
+                       const double *gout, double *gA, double *gB)
+{
+    for (int64_t t = 0; t < ntasks; ++t) {
+        const int64_t *r = table + 6 * t;
+        int64_t kind = r[0], rows = r[1], cols = r[2];
+        const double *a = A + r[3], *b = B + r[4], *g = gout + r[5];
+        double *ga = gA + r[3], *gb = gB + r[4];
+        if (kind == 0) {
+            for (int64_t i = 0; i < cols; ++i) {
+                ga[i] = g[0] * b[i];
+                gb[i] = g[0] * a[i];
+            }
+        } else {
+            for (int64_t i = 0; i < rows; ++i)
+                for (int64_t c = 0; c < cols; ++c) ga[i * cols + c] = g[i] * b[c];
+            for (int64_t c = 0; c < cols; ++c) {
+                double acc = 0.0;
+                for (int64_t i = 0; i < rows; ++i) acc = acc + a[i * cols + c] * g[i];
+                gb[c] = acc;
+            }
+        }
+    }
+}
