@@ -1,0 +1,281 @@
+/*
+ * mx.h -- C ABI of the MI355X (gfx950) data-parallel primitives for
+ * accelerated expressions.
+ *
+ * The paper marks an expression `accelerate e`; its free variables are
+ * marshalled from the host language's representation into flat backend arrays,
+ * the expression's parallel keywords (map, map2, reduce, flatten, loop) run on
+ * the GPU, and the result is marshalled back (Sections 2.1, 4.3; Appendix A).
+ * This library is the run-time half of that scheme for one GPU: each entry
+ * point evaluates one parallel keyword, or one fixed composition of them, on
+ * flat device arrays.  There is no compiler: operators are enumerations, since
+ * accelerated code may not pass higher-order functions (Section 4.4,
+ * Appendix "Static Rules").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: MX_OK (0) or a negative mx_status.  On error nothing was
+ *   launched, except MX_ERR_HIP, which reports a failed HIP call; the text of
+ *   the last error of the calling thread is returned by mx_last_error().
+ * - Pointers named *_dev or documented "device" are device addresses in the
+ *   current HIP device's memory; pointers named *_host are host addresses.
+ *   The caller owns every buffer (inputs, outputs and workspaces).  The library
+ *   never frees caller memory and calls no allocator on the launch path
+ *   (mx_batch_plan_create is the documented exception).
+ * - Every call is asynchronous on the given stream (0 = the null stream) unless
+ *   documented otherwise.  Scalar results are written to device memory.
+ * - Sizes are element counts of type int64_t; n = 0 is valid everywhere and
+ *   yields the empty result (a reduce of an empty sequence returns ne).
+ * - Reduction operators must be associative and ne must be their neutral
+ *   element; this is the caller's responsibility, as in the paper (Appendix
+ *   "Dynamic Assumptions").  For any associative op the result equals the left
+ *   fold foldl op ne s; integer results are exact (two's-complement wrap);
+ *   floating-point results are one bracketing of that fold, fixed for a given
+ *   size and launch configuration, so repeated calls are bit-identical.
+ * - Debug mode (mx_set_debug(1)) adds the dynamic checks of the paper's debug
+ *   compilation mode (Section 2.2; Appendix "Dynamic Assumptions"): ragged
+ *   offsets are validated on the device before use and the stream is
+ *   synchronised to report violations as MX_ERR_SHAPE.  Accelerate mode (the
+ *   default) omits those checks.
+ * - Workspaces: entry points taking (ws, ws_bytes) need at least
+ *   mx_workspace_bytes(kind, ...) bytes of device memory, 256-byte aligned, which
+ *   must be zero-filled before its first use.  Every successful call leaves the
+ *   workspace's counters zero again, so one buffer can be reused (and captured in
+ *   a HIP graph) without clearing.  Calls that share a workspace must be ordered
+ *   on one stream.
+ */
+#ifndef MX_H
+#define MX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mx_status {
+    MX_OK = 0,
+    MX_ERR_INVALID = -1,     /* null pointer, bad enum or flag, bad alignment */
+    MX_ERR_SHAPE = -2,       /* mismatched lengths, bad offsets, size limits */
+    MX_ERR_DTYPE = -3,       /* unsupported element type for this entry point */
+    MX_ERR_UNSUPPORTED = -4, /* valid request that this library does not implement */
+    MX_ERR_HIP = -5,         /* a HIP runtime call failed */
+    MX_ERR_WORKSPACE = -6    /* workspace missing or too small */
+} mx_status;
+
+/* Element types.  Integers accumulate in int64 (the paper's compiler always
+ * uses 64-bit integers, Section 5.1); I32 inputs widen to I64 results. */
+typedef enum mx_dtype { MX_F32 = 0, MX_F64 = 1, MX_I32 = 2, MX_I64 = 3 } mx_dtype;
+
+/* Associative, commutative reduce operators. */
+typedef enum mx_redop { MX_ADD = 0, MX_MUL = 1, MX_MIN = 2, MX_MAX = 3 } mx_redop;
+
+/* Map bodies.  MX_U_AFFINE is x -> p0 * x + p1 with two captured constants
+ * (Listing 2's `muli c (addi x 1)` is p0 = p1 = c).  EXP, LOG, SQRT and RSQRT
+ * are floating-point only. */
+typedef enum mx_unop {
+    MX_U_ID = 0, MX_U_NEG = 1, MX_U_ABS = 2, MX_U_SQ = 3, MX_U_AFFINE = 4,
+    MX_U_EXP = 5, MX_U_LOG = 6, MX_U_SQRT = 7, MX_U_RSQRT = 8
+} mx_unop;
+
+/* map2 bodies.  MX_B_DIV is floating-point only. */
+typedef enum mx_binop {
+    MX_B_ADD = 0, MX_B_SUB = 1, MX_B_MUL = 2, MX_B_DIV = 3, MX_B_MIN = 4, MX_B_MAX = 5
+} mx_binop;
+
+/* Workspace kinds for mx_workspace_bytes. */
+typedef enum mx_ws_kind {
+    MX_WS_REDUCE = 0, /* mx_reduce, mx_map2_reduce: n = sequence length */
+    MX_WS_SCAN = 1,   /* mx_lengths_to_offsets, mx_marshal_rows: n = number of rows */
+    MX_WS_KMEANS = 2, /* mx_kmeans_step: n = points, aux = k * d */
+    MX_WS_NBODY = 3   /* mx_nbody_ke_grad: n = bodies, aux = number of checkpoints */
+} mx_ws_kind;
+
+/* ======================================================================= */
+/* Runtime                                                                  */
+/* ======================================================================= */
+
+/* Selects `device` as the current HIP device of the calling thread and caches
+ * its properties (compute-unit count, LDS size).  Optional: every entry point
+ * initialises the current device lazily.  Errors: MX_ERR_HIP. */
+mx_status mx_init(int device);
+
+/* Text of the last error raised on the calling thread ("" if none).  The
+ * pointer stays valid until the thread's next failing call. */
+const char *mx_last_error(void);
+
+/* Library version string, e.g. "mx 0.1.0 gfx950". */
+const char *mx_version(void);
+
+/* Debug mode on (1) or off (0), process-wide.  See the header comment. */
+mx_status mx_set_debug(int on);
+int mx_get_debug(void);
+
+/* Bytes of device workspace an entry point of the given kind needs for n
+ * elements (aux as documented per kind).  Always a multiple of 256. */
+size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux);
+
+/* Plain device-to-device copy of n 32-bit words through the library's
+ * streaming kernel (the reference kernel used to calibrate hardware byte
+ * counters).  dst and src must not overlap.  Errors: MX_ERR_INVALID. */
+mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t stream);
+
+/* ======================================================================= */
+/* Marshaling (Section 4.3): nested sequences -> flat values + offsets      */
+/* ======================================================================= */
+
+/* Exclusive scan of row lengths into offsets (device):
+ *   offsets[0] = 0, offsets[r+1] = offsets[r] + lengths[r],  r < nseg,
+ * i.e. the offsets array of the flat layout of a ragged sequence [[T]].
+ * lengths: int64[nseg] device; offsets: int64[nseg+1] device (may not alias
+ * lengths).  Negative lengths are the caller's error (checked in debug mode,
+ * MX_ERR_SHAPE).  Workspace kind MX_WS_SCAN with n = nseg. */
+mx_status mx_lengths_to_offsets(const int64_t *lengths_dev, int64_t nseg, int64_t *offsets_dev,
+                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Marshals a ragged sequence held as nseg separate host rows (the host
+ * language's boxed representation) into the flat device layout: the rows are
+ * gathered, in order, into the caller's pinned host staging buffer by host
+ * threads, copied to values_dev with one host-to-device transfer, and the
+ * offsets are computed on the device by mx_lengths_to_offsets.
+ *   rows_host[r]      host pointer to lengths_host[r] elements of elem_bytes
+ *   staging_host      pinned host memory (hipHostMalloc) of at least
+ *                     sum(lengths) * elem_bytes + nseg * 8 bytes, 16-byte aligned
+ *   values_dev        device, sum(lengths) * elem_bytes bytes
+ *   lengths_dev       device int64[nseg] (receives a copy of lengths_host)
+ *   offsets_dev       device int64[nseg + 1]
+ * The staging buffer must stay untouched until the stream has passed this
+ * call.  Workspace kind MX_WS_SCAN with n = nseg.  Errors: MX_ERR_INVALID,
+ * MX_ERR_WORKSPACE, MX_ERR_HIP. */
+mx_status mx_marshal_rows(const void *const *rows_host, const int64_t *lengths_host, int64_t nseg,
+                          size_t elem_bytes, void *staging_host, size_t staging_bytes,
+                          void *values_dev, int64_t *lengths_dev, int64_t *offsets_dev, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
+
+/* Inverse of mx_marshal_rows: copies the flat device values back and scatters
+ * row r into rows_host[r] (offsets_host[r] .. offsets_host[r+1]).  Synchronous:
+ * waits for the stream.  staging_host: pinned host buffer of at least
+ * offsets_host[nseg] * elem_bytes bytes.  Errors: MX_ERR_INVALID, MX_ERR_HIP. */
+mx_status mx_unmarshal_rows(const void *values_dev, const int64_t *offsets_host, int64_t nseg,
+                            size_t elem_bytes, void *staging_host, size_t staging_bytes,
+                            void *const *rows_host, hipStream_t stream);
+
+/* Records {l_1 = e_1, ..., l_f = e_f} with f fields of 4 or 8 bytes each:
+ * array-of-records (interleaved, record i field j at aos[i*f + j]) <-> one
+ * flat device array per field (field j of record i at soa[j][i]).
+ * soa_fields_host is a host array of f device pointers.  1 <= f <= 16.
+ * Errors: MX_ERR_INVALID. */
+mx_status mx_records_to_fields(const void *aos_dev, int64_t n, int nfields, size_t field_bytes,
+                               void *const *soa_fields_host, hipStream_t stream);
+mx_status mx_fields_to_records(const void *const *soa_fields_host, int64_t n, int nfields,
+                               size_t field_bytes, void *aos_dev, hipStream_t stream);
+
+/* `map flatten` over a depth-3 ragged sequence [[[T]]] given by outer offsets
+ * (nouter+1 entries, counting middle rows) and inner offsets (counting values):
+ * the flattened inner rows of outer element i span values
+ * inner[outer[i]] .. inner[outer[i+1]], so out[i] = inner[outer[i]] for
+ * i <= nouter.  Flattening the outermost level itself needs no call (drop the
+ * outer offsets).  All pointers device.  Errors: MX_ERR_INVALID. */
+mx_status mx_compose_offsets(const int64_t *outer_dev, int64_t nouter, const int64_t *inner_dev,
+                             int64_t *out_dev, hipStream_t stream);
+
+/* ======================================================================= */
+/* map / map2 (Appendix A)                                                  */
+/* ======================================================================= */
+
+/* out[i] = f(x[i]) for i < n.  dtype is the element type of x; out has the
+ * accumulator type (F32->F32, F64->F64, I32->I64, I64->I64).  params_host
+ * points to two values of the output type (p0, p1), used by MX_U_AFFINE; may
+ * be NULL otherwise.  out may alias x when the types have equal size.
+ * Errors: MX_ERR_INVALID, MX_ERR_DTYPE (float-only f on an integer type). */
+mx_status mx_map(mx_unop f, mx_dtype dtype, const void *x_dev, int64_t n, const void *params_host,
+                 void *out_dev, hipStream_t stream);
+
+/* out[i] = f(a[i], b[i]) for i < n, both inputs of type dtype, out of the
+ * accumulator type; map2 requires sequences of equal length, so the caller
+ * passes one n.  out may alias a or b when the types have equal size (the
+ * in-place update of Listing 1's axpy loop).  Errors: MX_ERR_INVALID,
+ * MX_ERR_DTYPE. */
+mx_status mx_map2(mx_binop f, mx_dtype dtype, const void *a_dev, const void *b_dev, int64_t n,
+                  void *out_dev, hipStream_t stream);
+
+/* ======================================================================= */
+/* reduce (Appendix A; Appendix "Dynamic Assumptions" for associativity)    */
+/* ======================================================================= */
+
+/* *out = reduce op ne x = foldl op ne x, as op(ne, tree_op(x)).
+ * ne_host: one host value of the accumulator type.  out_dev: one device value
+ * of the accumulator type.  Workspace kind MX_WS_REDUCE with n.
+ * Errors: MX_ERR_INVALID, MX_ERR_DTYPE, MX_ERR_WORKSPACE. */
+mx_status mx_reduce(mx_redop op, mx_dtype dtype, const void *x_dev, int64_t n, const void *ne_host,
+                    void *out_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Fused *out = reduce op ne (map2 f a b) without materialising the map2
+ * result (the dot product is f = MX_B_MUL, op = MX_ADD; Listing 2 composes a
+ * map with a reduce the same way).  I32 inputs are widened before f.
+ * Workspace kind MX_WS_REDUCE with n.  Errors as mx_reduce. */
+mx_status mx_map2_reduce(mx_binop f, mx_redop op, mx_dtype dtype, const void *a_dev,
+                         const void *b_dev, int64_t n, const void *ne_host, void *out_dev, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* Reverse of the fused dot product *out = sum_i a[i] * b[i] (F32 only):
+ * ga[i] = g * b[i], gb[i] = g * a[i] with g = *gout_dev (device scalar), so no
+ * host synchronisation is needed.  ga/gb may be NULL to skip that gradient.
+ * Errors: MX_ERR_INVALID. */
+mx_status mx_dot_adjoint_f32(const float *a_dev, const float *b_dev, int64_t n,
+                             const float *gout_dev, float *ga_dev, float *gb_dev,
+                             hipStream_t stream);
+
+/* ======================================================================= */
+/* Nested map (reduce) over a ragged sequence                               */
+/* ======================================================================= */
+
+/* out[r] = reduce op ne (row r) for r < nseg, where row r is
+ * values[offsets[r] .. offsets[r+1]) of the flat layout made by marshaling.
+ * offsets: device int64[nseg+1], non-decreasing, offsets[0] = 0 (validated in
+ * debug mode).  Empty rows give ne.  out: device, accumulator type, nseg
+ * values.  Errors: MX_ERR_INVALID, MX_ERR_DTYPE, MX_ERR_SHAPE (debug mode). */
+mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_dev,
+                              const int64_t *offsets_dev, int64_t nseg, const void *ne_host,
+                              void *out_dev, hipStream_t stream);
+
+/* Reference "plain" form of mx_segmented_reduce: one thread folds one row
+ * sequentially (no load balancing, uncoalesced).  Same contract. */
+mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *values_dev,
+                                    const int64_t *offsets_dev, int64_t nseg, const void *ne_host,
+                                    void *out_dev, hipStream_t stream);
+
+/* Reverse of the row sums out[r] = sum(row r) (F32): every element of row r
+ * receives gout[r]: gvalues[e] = gout[r] for offsets[r] <= e < offsets[r+1].
+ * Errors: MX_ERR_INVALID, MX_ERR_SHAPE (debug mode). */
+mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *offsets_dev,
+                                       int64_t nseg, float *gvalues_dev, hipStream_t stream);
+
+/* ======================================================================= */
+/* Dense nested map (map (reduce (+) 0 (map2 (*) row col))) -- FP32 on MFMA */
+/* ======================================================================= */
+
+/* C[i][j] = sum_k op(A)[i][k] * op(B)[k][j], i < M, j < N, k < K, FP32 inputs
+ * and FP32 accumulation on the matrix cores.  Row-major, densely packed:
+ * op(A) = A stored M x K (ta = 0) or its transpose stored K x M (ta = 1);
+ * op(B) = B stored K x N (tb = 0) or its transpose stored N x K (tb = 1).
+ * C (M x N) must not alias A or B.  The reverse of C = A B is
+ * dA = dC B^T (ta = 0, tb = 1) and dB = A^T dC (ta = 1, tb = 0).
+ * Errors: MX_ERR_INVALID. */
+mx_status mx_map_map_reduce_f32(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A_dev,
+                                const float *B_dev, float *C_dev, hipStream_t stream);
+
+/* Reference "plain" form: one thread per output element folding over k from
+ * global memory.  Same contract. */
+mx_status mx_map_map_reduce_plain_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
+                                      const float *A_dev, const float *B_dev, float *C_dev,
+                                      hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MX_H */

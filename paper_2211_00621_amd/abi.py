@@ -1,0 +1,253 @@
+"""Thin Python binding of the C ABI in include/mx.h.
+
+Each function has the name of the C entry point and does argument marshalling
+only: it takes torch tensors (device memory) or numpy arrays (host memory),
+passes their addresses, sizes and the stream to libmx.so, and raises MxError if
+the call returns a non-zero status.  All computation happens in the library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+# ---------------------------------------------------------------- enums (values of mx.h)
+MX_OK, MX_ERR_INVALID, MX_ERR_SHAPE, MX_ERR_DTYPE, MX_ERR_UNSUPPORTED, MX_ERR_HIP, MX_ERR_WORKSPACE = \
+    0, -1, -2, -3, -4, -5, -6
+MX_F32, MX_F64, MX_I32, MX_I64 = 0, 1, 2, 3
+MX_ADD, MX_MUL, MX_MIN, MX_MAX = 0, 1, 2, 3
+(MX_U_ID, MX_U_NEG, MX_U_ABS, MX_U_SQ, MX_U_AFFINE, MX_U_EXP, MX_U_LOG, MX_U_SQRT,
+ MX_U_RSQRT) = range(9)
+MX_B_ADD, MX_B_SUB, MX_B_MUL, MX_B_DIV, MX_B_MIN, MX_B_MAX = range(6)
+MX_WS_REDUCE, MX_WS_SCAN, MX_WS_KMEANS, MX_WS_NBODY = 0, 1, 2, 3
+
+DTYPE_OF = {torch.float32: MX_F32, torch.float64: MX_F64, torch.int32: MX_I32, torch.int64: MX_I64}
+ACC_OF = {torch.float32: torch.float32, torch.float64: torch.float64, torch.int32: torch.int64,
+          torch.int64: torch.int64}
+
+
+class MxError(RuntimeError):
+    """A libmx entry point returned a non-zero status."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+def _L():
+    return _lib.load()
+
+
+def _check(status: int, name: str) -> None:
+    if status != MX_OK:
+        msg = _L().mx_last_error().decode(errors="replace")
+        raise MxError(status, f"{name}: {msg}")
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dptr(t):
+    """Device address of a contiguous tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr() if t.numel() else (t.data_ptr() or None)
+
+
+def _nbytes(t) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def _dtype(t) -> int:
+    try:
+        return DTYPE_OF[t.dtype]
+    except KeyError:
+        raise MxError(MX_ERR_DTYPE, f"unsupported dtype {t.dtype}") from None
+
+
+def _acc_scalar(value, dtype: torch.dtype):
+    """A host scalar of the accumulator type of `dtype` (for ne / params)."""
+    acc = ACC_OF[dtype]
+    if acc == torch.float32:
+        return ctypes.c_float(float(value))
+    if acc == torch.float64:
+        return ctypes.c_double(float(value))
+    return ctypes.c_int64(int(value))
+
+
+# ---------------------------------------------------------------- runtime
+def mx_init(device: int = 0) -> None:
+    _check(_L().mx_init(int(device)), "mx_init")
+
+
+def mx_last_error() -> str:
+    return _L().mx_last_error().decode(errors="replace")
+
+
+def mx_version() -> str:
+    return _L().mx_version().decode()
+
+
+def mx_set_debug(on: bool) -> None:
+    _check(_L().mx_set_debug(1 if on else 0), "mx_set_debug")
+
+
+def mx_get_debug() -> bool:
+    return bool(_L().mx_get_debug())
+
+
+def mx_workspace_bytes(kind: int, n: int, aux: int = 0) -> int:
+    return int(_L().mx_workspace_bytes(int(kind), int(n), int(aux)))
+
+
+def mx_copy32(src, dst, stream=None) -> None:
+    n = src.numel() * src.element_size() // 4
+    _check(_L().mx_copy32(_dptr(src), _dptr(dst), n, _stream(stream)), "mx_copy32")
+
+
+# ---------------------------------------------------------------- marshaling
+def mx_lengths_to_offsets(lengths, offsets, ws, stream=None) -> None:
+    _check(_L().mx_lengths_to_offsets(_dptr(lengths), lengths.numel(), _dptr(offsets), _dptr(ws),
+                                      _nbytes(ws), _stream(stream)), "mx_lengths_to_offsets")
+
+
+def mx_marshal_rows(rows, staging, values, lengths_dev, offsets, ws, stream=None) -> None:
+    """rows: list of contiguous numpy arrays of one dtype; staging: pinned uint8 tensor."""
+    nseg = len(rows)
+    elem = rows[0].dtype.itemsize if nseg else values.element_size()
+    for r in rows:
+        if not r.flags["C_CONTIGUOUS"]:
+            raise ValueError("rows must be C-contiguous")
+    ptrs = (ctypes.c_void_p * max(nseg, 1))(*[r.ctypes.data if r.size else None for r in rows])
+    lengths = np.ascontiguousarray([r.size for r in rows], dtype=np.int64)
+    if not staging.is_pinned():
+        raise ValueError("staging must be pinned host memory")
+    _check(_L().mx_marshal_rows(ptrs, lengths.ctypes.data, nseg, elem, staging.data_ptr(),
+                                _nbytes(staging), _dptr(values), _dptr(lengths_dev), _dptr(offsets),
+                                _dptr(ws), _nbytes(ws), _stream(stream)), "mx_marshal_rows")
+
+
+def mx_unmarshal_rows(values, offsets_host: np.ndarray, staging, rows, stream=None) -> None:
+    """Synchronous: fills the numpy arrays in `rows` (preallocated, row r of the right length)."""
+    off = np.ascontiguousarray(offsets_host, dtype=np.int64)
+    nseg = off.size - 1
+    ptrs = (ctypes.c_void_p * max(nseg, 1))(*[r.ctypes.data if r.size else None for r in rows])
+    elem = values.element_size()
+    _check(_L().mx_unmarshal_rows(_dptr(values), off.ctypes.data, nseg, elem, staging.data_ptr(),
+                                  _nbytes(staging), ptrs, _stream(stream)), "mx_unmarshal_rows")
+
+
+def mx_records_to_fields(aos, fields, stream=None) -> None:
+    """aos: device tensor [n, f]; fields: list of f device tensors [n] of the same element size."""
+    n, f = aos.shape
+    ptrs = (ctypes.c_void_p * f)(*[_dptr(t) for t in fields])
+    _check(_L().mx_records_to_fields(_dptr(aos), n, f, aos.element_size(), ptrs, _stream(stream)),
+           "mx_records_to_fields")
+
+
+def mx_fields_to_records(fields, aos, stream=None) -> None:
+    n, f = aos.shape
+    ptrs = (ctypes.c_void_p * f)(*[_dptr(t) for t in fields])
+    _check(_L().mx_fields_to_records(ptrs, n, f, aos.element_size(), _dptr(aos), _stream(stream)),
+           "mx_fields_to_records")
+
+
+def mx_compose_offsets(outer, inner, out, stream=None) -> None:
+    _check(_L().mx_compose_offsets(_dptr(outer), outer.numel() - 1, _dptr(inner), _dptr(out),
+                                   _stream(stream)), "mx_compose_offsets")
+
+
+# ---------------------------------------------------------------- map / map2
+def mx_map(f: int, x, params, out, stream=None) -> None:
+    dt = x.dtype
+    pbuf = None
+    if params is not None:
+        acc = ACC_OF[dt]
+        ctype = {torch.float32: ctypes.c_float, torch.float64: ctypes.c_double}.get(acc, ctypes.c_int64)
+        pbuf = (ctype * 2)(*(float(p) if acc.is_floating_point else int(p) for p in params))
+    _check(_L().mx_map(int(f), _dtype(x), _dptr(x), x.numel(),
+                       ctypes.cast(pbuf, ctypes.c_void_p) if pbuf is not None else None,
+                       _dptr(out), _stream(stream)), "mx_map")
+
+
+def mx_map2(f: int, a, b, out, stream=None) -> None:
+    if a.numel() != b.numel() or a.dtype != b.dtype:
+        raise MxError(MX_ERR_SHAPE, "mx_map2: operands differ in length or dtype")
+    _check(_L().mx_map2(int(f), _dtype(a), _dptr(a), _dptr(b), a.numel(), _dptr(out),
+                        _stream(stream)), "mx_map2")
+
+
+# ---------------------------------------------------------------- reduce
+def mx_reduce(op: int, x, ne, out, ws, stream=None) -> None:
+    nb = _acc_scalar(ne, x.dtype)
+    _check(_L().mx_reduce(int(op), _dtype(x), _dptr(x), x.numel(), ctypes.byref(nb), _dptr(out),
+                          _dptr(ws), _nbytes(ws), _stream(stream)), "mx_reduce")
+
+
+def mx_map2_reduce(f: int, op: int, a, b, ne, out, ws, stream=None) -> None:
+    if a.numel() != b.numel() or a.dtype != b.dtype:
+        raise MxError(MX_ERR_SHAPE, "mx_map2_reduce: operands differ in length or dtype")
+    nb = _acc_scalar(ne, a.dtype)
+    _check(_L().mx_map2_reduce(int(f), int(op), _dtype(a), _dptr(a), _dptr(b), a.numel(),
+                               ctypes.byref(nb), _dptr(out), _dptr(ws), _nbytes(ws), _stream(stream)),
+           "mx_map2_reduce")
+
+
+def mx_dot_adjoint_f32(a, b, gout, ga, gb, stream=None) -> None:
+    n = a.numel() if a is not None else b.numel()
+    _check(_L().mx_dot_adjoint_f32(_dptr(a), _dptr(b), n, _dptr(gout), _dptr(ga), _dptr(gb),
+                                   _stream(stream)), "mx_dot_adjoint_f32")
+
+
+# ---------------------------------------------------------------- ragged
+def mx_segmented_reduce(op: int, values, offsets, ne, out, stream=None) -> None:
+    nb = _acc_scalar(ne, values.dtype)
+    _check(_L().mx_segmented_reduce(int(op), _dtype(values), _dptr(values), _dptr(offsets),
+                                    offsets.numel() - 1, ctypes.byref(nb), _dptr(out), _stream(stream)),
+           "mx_segmented_reduce")
+
+
+def mx_segmented_reduce_plain(op: int, values, offsets, ne, out, stream=None) -> None:
+    nb = _acc_scalar(ne, values.dtype)
+    _check(_L().mx_segmented_reduce_plain(int(op), _dtype(values), _dptr(values), _dptr(offsets),
+                                          offsets.numel() - 1, ctypes.byref(nb), _dptr(out),
+                                          _stream(stream)), "mx_segmented_reduce_plain")
+
+
+def mx_segmented_sum_adjoint_f32(gout, offsets, gvalues, stream=None) -> None:
+    _check(_L().mx_segmented_sum_adjoint_f32(_dptr(gout), _dptr(offsets), offsets.numel() - 1,
+                                             _dptr(gvalues), _stream(stream)),
+           "mx_segmented_sum_adjoint_f32")
+
+
+# ---------------------------------------------------------------- dense
+def _mmr_dims(ta, tb, A, B):
+    M, K = (A.shape[1], A.shape[0]) if ta else (A.shape[0], A.shape[1])
+    N, Kb = (B.shape[0], B.shape[1]) if tb else (B.shape[1], B.shape[0])
+    if K != Kb:
+        raise MxError(MX_ERR_SHAPE, f"inner dimensions differ: {K} vs {Kb}")
+    return M, N, K
+
+
+def mx_map_map_reduce_f32(ta: int, tb: int, A, B, C, stream=None) -> None:
+    M, N, K = _mmr_dims(ta, tb, A, B)
+    _check(_L().mx_map_map_reduce_f32(int(ta), int(tb), M, N, K, _dptr(A), _dptr(B), _dptr(C),
+                                      _stream(stream)), "mx_map_map_reduce_f32")
+
+
+def mx_map_map_reduce_plain_f32(ta: int, tb: int, A, B, C, stream=None) -> None:
+    M, N, K = _mmr_dims(ta, tb, A, B)
+    _check(_L().mx_map_map_reduce_plain_f32(int(ta), int(tb), M, N, K, _dptr(A), _dptr(B), _dptr(C),
+                                            _stream(stream)), "mx_map_map_reduce_plain_f32")

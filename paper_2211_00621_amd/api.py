@@ -1,0 +1,214 @@
+"""Convenience layer over the C ABI: output allocation, cached workspaces and
+torch.autograd.Function wrappers whose backward calls the library's adjoint
+entry points.  Every numeric step runs in libmx.so.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import abi
+from .abi import (MX_ADD, MX_B_MUL, MX_WS_REDUCE, MX_WS_SCAN, ACC_OF)
+
+# ---------------------------------------------------------------- workspaces
+_WS: dict = {}
+
+
+def workspace(kind: int, n: int, aux: int = 0, device=None, stream=None) -> torch.Tensor:
+    """A zero-initialised device workspace for (device, stream, kind), grown on demand.
+
+    The library leaves its counters at zero after each call, so the buffer is
+    reused as is; calls sharing it are ordered on the one stream.
+    """
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    sid = abi._stream(stream)
+    need = abi.mx_workspace_bytes(kind, n, aux)
+    key = (device.index, sid, kind)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < need:
+        buf = torch.zeros(max(need, 256), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf
+
+
+# ---------------------------------------------------------------- map / map2 / reduce
+def map(f: int, x: torch.Tensor, params=None) -> torch.Tensor:  # noqa: A001 - the paper's keyword
+    out = torch.empty(x.shape, dtype=ACC_OF[x.dtype], device=x.device)
+    abi.mx_map(f, x.contiguous(), params, out)
+    return out
+
+
+def map2(f: int, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(a.shape, dtype=ACC_OF[a.dtype], device=a.device)
+    abi.mx_map2(f, a.contiguous(), b.contiguous(), out)
+    return out
+
+
+def reduce(op: int, x: torch.Tensor, ne) -> torch.Tensor:
+    x = x.contiguous().view(-1)
+    out = torch.empty((), dtype=ACC_OF[x.dtype], device=x.device)
+    abi.mx_reduce(op, x, ne, out, workspace(MX_WS_REDUCE, x.numel(), device=x.device))
+    return out
+
+
+def map2_reduce(f: int, op: int, a: torch.Tensor, b: torch.Tensor, ne) -> torch.Tensor:
+    a, b = a.contiguous().view(-1), b.contiguous().view(-1)
+    out = torch.empty((), dtype=ACC_OF[a.dtype], device=a.device)
+    abi.mx_map2_reduce(f, op, a, b, ne, out, workspace(MX_WS_REDUCE, a.numel(), device=a.device))
+    return out
+
+
+class _Dot(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a, b):
+        ctx.save_for_backward(a, b)
+        return map2_reduce(MX_B_MUL, MX_ADD, a, b, 0)
+
+    @staticmethod
+    def backward(ctx, g):
+        a, b = ctx.saved_tensors
+        ga = torch.empty_like(a) if ctx.needs_input_grad[0] else None
+        gb = torch.empty_like(b) if ctx.needs_input_grad[1] else None
+        abi.mx_dot_adjoint_f32(a, b, g.contiguous().view(1), ga, gb)
+        return ga, gb
+
+
+def dot(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """reduce (+) 0 (map2 (*) a b); differentiable for float32."""
+    a, b = a.contiguous().view(-1), b.contiguous().view(-1)
+    if a.dtype == torch.float32 and (a.requires_grad or b.requires_grad):
+        return _Dot.apply(a, b)
+    return map2_reduce(MX_B_MUL, MX_ADD, a, b, 0)
+
+
+# ---------------------------------------------------------------- ragged sequences
+@dataclass
+class Ragged:
+    """A marshalled ragged sequence [[T]]: flat values plus int64 offsets (device)."""
+    values: torch.Tensor
+    offsets: torch.Tensor
+
+    @property
+    def nseg(self) -> int:
+        return self.offsets.numel() - 1
+
+    def flatten(self) -> torch.Tensor:
+        """flatten [[T]] -> [T]: the values themselves (no copy)."""
+        return self.values
+
+
+def offsets_from_lengths(lengths: torch.Tensor) -> torch.Tensor:
+    lengths = lengths.contiguous()
+    off = torch.empty(lengths.numel() + 1, dtype=torch.int64, device=lengths.device)
+    abi.mx_lengths_to_offsets(lengths, off, workspace(MX_WS_SCAN, lengths.numel(), device=lengths.device))
+    return off
+
+
+def ragged_from_lengths(values: torch.Tensor, lengths: torch.Tensor) -> Ragged:
+    return Ragged(values, offsets_from_lengths(lengths))
+
+
+def marshal_rows(rows, device="cuda") -> Ragged:
+    """Marshal a list of numpy rows (one dtype) into a device Ragged."""
+    nseg = len(rows)
+    dt = rows[0].dtype if nseg else np.dtype(np.float32)
+    total = int(sum(r.size for r in rows))
+    elem = dt.itemsize
+    staging = torch.empty(((total * elem + 255) // 256) * 256 + 8 * max(nseg, 1), dtype=torch.uint8,
+                          pin_memory=True)
+    values = torch.empty(total, dtype=torch.from_numpy(np.zeros(0, dt)).dtype, device=device)
+    lengths = torch.empty(nseg, dtype=torch.int64, device=device)
+    offsets = torch.empty(nseg + 1, dtype=torch.int64, device=device)
+    rows = [np.ascontiguousarray(r) for r in rows]
+    abi.mx_marshal_rows(rows, staging, values, lengths, offsets, workspace(MX_WS_SCAN, nseg, device=device))
+    torch.cuda.current_stream().synchronize()  # staging is local to this call
+    return Ragged(values, offsets)
+
+
+def unmarshal_rows(r: Ragged):
+    off = r.offsets.cpu().numpy()
+    np_dt = torch.empty(0, dtype=r.values.dtype).numpy().dtype
+    rows = [np.empty(int(off[i + 1] - off[i]), dtype=np_dt) for i in range(r.nseg)]
+    staging = torch.empty(max(r.values.numel() * r.values.element_size(), 1), dtype=torch.uint8,
+                          pin_memory=True)
+    abi.mx_unmarshal_rows(r.values, off, staging, rows)
+    return rows
+
+
+def records_to_fields(aos: torch.Tensor):
+    fields = [torch.empty(aos.shape[0], dtype=aos.dtype, device=aos.device) for _ in range(aos.shape[1])]
+    abi.mx_records_to_fields(aos.contiguous(), fields)
+    return fields
+
+
+def fields_to_records(fields) -> torch.Tensor:
+    aos = torch.empty((fields[0].numel(), len(fields)), dtype=fields[0].dtype, device=fields[0].device)
+    abi.mx_fields_to_records([f.contiguous() for f in fields], aos)
+    return aos
+
+
+def segmented_reduce(op: int, r: Ragged, ne, plain: bool = False) -> torch.Tensor:
+    out = torch.empty(r.nseg, dtype=ACC_OF[r.values.dtype], device=r.values.device)
+    fn = abi.mx_segmented_reduce_plain if plain else abi.mx_segmented_reduce
+    fn(op, r.values, r.offsets, ne, out)
+    return out
+
+
+class _SegSum(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, values, offsets):
+        ctx.save_for_backward(offsets)
+        ctx.n = values.numel()
+        out = torch.empty(offsets.numel() - 1, dtype=values.dtype, device=values.device)
+        abi.mx_segmented_reduce(MX_ADD, values, offsets, 0.0, out)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (offsets,) = ctx.saved_tensors
+        gv = torch.empty(ctx.n, dtype=g.dtype, device=g.device)
+        abi.mx_segmented_sum_adjoint_f32(g.contiguous(), offsets, gv)
+        return gv, None
+
+
+def segmented_sum(r: Ragged) -> torch.Tensor:
+    """map (reduce (+) 0) over the rows; differentiable for float32 values."""
+    if r.values.dtype == torch.float32 and r.values.requires_grad:
+        return _SegSum.apply(r.values, r.offsets)
+    return segmented_reduce(MX_ADD, r, 0)
+
+
+# ---------------------------------------------------------------- dense
+class _MapMapReduce(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, B):
+        ctx.save_for_backward(A, B)
+        C = torch.empty((A.shape[0], B.shape[1]), dtype=torch.float32, device=A.device)
+        abi.mx_map_map_reduce_f32(0, 0, A, B, C)
+        return C
+
+    @staticmethod
+    def backward(ctx, gC):
+        A, B = ctx.saved_tensors
+        gC = gC.contiguous()
+        gA = gB = None
+        if ctx.needs_input_grad[0]:
+            gA = torch.empty_like(A)
+            abi.mx_map_map_reduce_f32(0, 1, gC, B, gA)  # dC B^T
+        if ctx.needs_input_grad[1]:
+            gB = torch.empty_like(B)
+            abi.mx_map_map_reduce_f32(1, 0, A, gC, gB)  # A^T dC
+        return gA, gB
+
+
+def matmul(A: torch.Tensor, B: torch.Tensor, plain: bool = False) -> torch.Tensor:
+    """C[i][j] = reduce (+) 0 (map2 (*) A[i,:] B[:,j]) in FP32 on the matrix cores."""
+    A, B = A.contiguous(), B.contiguous()
+    if not plain and (A.requires_grad or B.requires_grad):
+        return _MapMapReduce.apply(A, B)
+    C = torch.empty((A.shape[0], B.shape[1]), dtype=torch.float32, device=A.device)
+    (abi.mx_map_map_reduce_plain_f32 if plain else abi.mx_map_map_reduce_f32)(0, 0, A, B, C)
+    return C

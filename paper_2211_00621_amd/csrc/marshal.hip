@@ -1,0 +1,222 @@
+// Marshaling (Section 4.3): the host language's boxed nested sequences and
+// records <-> the flat device layout (values + offsets, one array per field).
+//
+// Ragged rows: host threads gather the rows, in order, into the caller's
+// pinned staging buffer (followed by the lengths), one host-to-device copy moves
+// both, and the offsets are computed on the device by the lengths scan.
+// Records: an interleaved array of records is split into one array per field
+// on the device (and joined back), 16-byte vectors per thread where possible.
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+#include "mx_internal.h"
+
+namespace mx {
+mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, void *ws,
+                             size_t ws_bytes, hipStream_t s);
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int kMaxFields = 16;
+
+struct FieldPtrs {
+    void *p[kMaxFields];
+};
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_aos_to_soa(const T *__restrict__ aos, int64_t n, int f,
+                                                   FieldPtrs soa) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        const T *rec = aos + i * f;
+        for (int j = 0; j < f; ++j) reinterpret_cast<T *>(soa.p[j])[i] = rec[j];
+    }
+}
+
+// Four fields of 4 bytes: one 16-byte load per record.
+__global__ void __launch_bounds__(NT) k_aos4_to_soa(const float4 *__restrict__ aos, int64_t n,
+                                                    FieldPtrs soa) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        float4 r = aos[i];
+        reinterpret_cast<float *>(soa.p[0])[i] = r.x;
+        reinterpret_cast<float *>(soa.p[1])[i] = r.y;
+        reinterpret_cast<float *>(soa.p[2])[i] = r.z;
+        reinterpret_cast<float *>(soa.p[3])[i] = r.w;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_soa_to_aos(FieldPtrs soa, int64_t n, int f, T *__restrict__ aos) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        T *rec = aos + i * f;
+        for (int j = 0; j < f; ++j) rec[j] = reinterpret_cast<const T *>(soa.p[j])[i];
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_soa_to_aos4(FieldPtrs soa, int64_t n, float4 *__restrict__ aos) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride)
+        aos[i] = make_float4(reinterpret_cast<const float *>(soa.p[0])[i], reinterpret_cast<const float *>(soa.p[1])[i],
+                             reinterpret_cast<const float *>(soa.p[2])[i], reinterpret_cast<const float *>(soa.p[3])[i]);
+}
+
+int grid_for(int64_t n, const DeviceInfo *d) {
+    int64_t g = ceil_div(n > 0 ? n : 1, NT);
+    int64_t cap = (int64_t)d->num_cus * 8;
+    return (int)(g < cap ? g : cap);
+}
+
+// Copies rows into a contiguous host buffer with up to 16 threads, each
+// taking a contiguous range of rows of about equal byte count.
+void gather_rows(const void *const *rows, const int64_t *lengths, const int64_t *starts, int64_t nseg,
+                 size_t eb, char *dst, int64_t total) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int nth = (int)std::min<int64_t>(std::max(1u, std::min(hw, 16u)), std::max<int64_t>(1, total * (int64_t)eb / (4 << 20)));
+    auto work = [&](int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r)
+            if (lengths[r] > 0) std::memcpy(dst + starts[r] * eb, rows[r], (size_t)lengths[r] * eb);
+    };
+    if (nth <= 1) {
+        work(0, nseg);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t r = 0;
+    for (int t = 0; t < nth && r < nseg; ++t) {
+        const int64_t goal = total * (t + 1) / nth;
+        int64_t r1 = r;
+        while (r1 < nseg && starts[r1] < goal) ++r1;
+        if (t == nth - 1) r1 = nseg;
+        th.emplace_back(work, r, r1);
+        r = r1;
+    }
+    for (auto &x : th) x.join();
+}
+
+}  // namespace
+}  // namespace mx
+
+using namespace mx;
+
+extern "C" {
+
+mx_status mx_marshal_rows(const void *const *rows_host, const int64_t *lengths_host, int64_t nseg,
+                          size_t elem_bytes, void *staging_host, size_t staging_bytes,
+                          void *values_dev, int64_t *lengths_dev, int64_t *offsets_dev, void *ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "mx_marshal_rows: nseg < 0");
+    MX_REQUIRE(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8, MX_ERR_INVALID,
+               "mx_marshal_rows: elem_bytes must be 1, 2, 4 or 8");
+    MX_REQUIRE(offsets_dev, MX_ERR_INVALID, "mx_marshal_rows: null offsets");
+    MX_REQUIRE(nseg == 0 || (rows_host && lengths_host && lengths_dev && staging_host), MX_ERR_INVALID,
+               "mx_marshal_rows: null pointer");
+    std::vector<int64_t> starts((size_t)nseg + 1, 0);
+    for (int64_t r = 0; r < nseg; ++r) {
+        MX_REQUIRE(lengths_host[r] >= 0, MX_ERR_SHAPE, "mx_marshal_rows: negative length at row %lld", (long long)r);
+        MX_REQUIRE(lengths_host[r] == 0 || rows_host[r], MX_ERR_INVALID, "mx_marshal_rows: null row %lld", (long long)r);
+        starts[r + 1] = starts[r] + lengths_host[r];
+    }
+    const int64_t total = starts[nseg];
+    const size_t vbytes = (size_t)total * elem_bytes;
+    const size_t lpos = align256(vbytes);
+    const size_t need = lpos + (size_t)nseg * 8;
+    MX_REQUIRE(staging_bytes >= need, MX_ERR_INVALID, "mx_marshal_rows: staging needs %zu bytes", need);
+    MX_REQUIRE(total == 0 || values_dev, MX_ERR_INVALID, "mx_marshal_rows: null values");
+    if (nseg > 0) {
+        // the previous use of the staging buffer on this stream must be finished
+        MX_TRY_HIP(hipStreamSynchronize(stream));
+        char *st = (char *)staging_host;
+        gather_rows(rows_host, lengths_host, starts.data(), nseg, elem_bytes, st, total);
+        std::memcpy(st + lpos, lengths_host, (size_t)nseg * 8);
+        if (vbytes) MX_TRY_HIP(hipMemcpyAsync(values_dev, st, vbytes, hipMemcpyHostToDevice, stream));
+        MX_TRY_HIP(hipMemcpyAsync(lengths_dev, st + lpos, (size_t)nseg * 8, hipMemcpyHostToDevice, stream));
+    }
+    return lengths_to_offsets(lengths_dev, nseg, offsets_dev, ws, ws_bytes, stream);
+}
+
+mx_status mx_unmarshal_rows(const void *values_dev, const int64_t *offsets_host, int64_t nseg,
+                            size_t elem_bytes, void *staging_host, size_t staging_bytes,
+                            void *const *rows_host, hipStream_t stream) {
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "mx_unmarshal_rows: nseg < 0");
+    MX_REQUIRE(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8, MX_ERR_INVALID,
+               "mx_unmarshal_rows: elem_bytes must be 1, 2, 4 or 8");
+    if (nseg == 0) return MX_OK;
+    MX_REQUIRE(offsets_host && rows_host && staging_host, MX_ERR_INVALID, "mx_unmarshal_rows: null pointer");
+    MX_REQUIRE(offsets_host[0] == 0, MX_ERR_SHAPE, "mx_unmarshal_rows: offsets[0] != 0");
+    for (int64_t r = 0; r < nseg; ++r)
+        MX_REQUIRE(offsets_host[r + 1] >= offsets_host[r], MX_ERR_SHAPE, "mx_unmarshal_rows: offsets decrease at %lld",
+                   (long long)r);
+    const int64_t total = offsets_host[nseg];
+    const size_t vbytes = (size_t)total * elem_bytes;
+    MX_REQUIRE(staging_bytes >= vbytes, MX_ERR_INVALID, "mx_unmarshal_rows: staging needs %zu bytes", vbytes);
+    MX_REQUIRE(total == 0 || values_dev, MX_ERR_INVALID, "mx_unmarshal_rows: null values");
+    if (vbytes) MX_TRY_HIP(hipMemcpyAsync(staging_host, values_dev, vbytes, hipMemcpyDeviceToHost, stream));
+    MX_TRY_HIP(hipStreamSynchronize(stream));
+    const char *st = (const char *)staging_host;
+    for (int64_t r = 0; r < nseg; ++r) {
+        const int64_t len = offsets_host[r + 1] - offsets_host[r];
+        if (len > 0) {
+            MX_REQUIRE(rows_host[r], MX_ERR_INVALID, "mx_unmarshal_rows: null row %lld", (long long)r);
+            std::memcpy(rows_host[r], st + offsets_host[r] * elem_bytes, (size_t)len * elem_bytes);
+        }
+    }
+    return MX_OK;
+}
+
+mx_status mx_records_to_fields(const void *aos_dev, int64_t n, int nfields, size_t field_bytes,
+                               void *const *soa_fields_host, hipStream_t stream) {
+    MX_REQUIRE(n >= 0, MX_ERR_SHAPE, "mx_records_to_fields: n < 0");
+    MX_REQUIRE(nfields >= 1 && nfields <= kMaxFields, MX_ERR_INVALID, "mx_records_to_fields: 1..16 fields");
+    MX_REQUIRE(field_bytes == 4 || field_bytes == 8, MX_ERR_INVALID, "mx_records_to_fields: fields of 4 or 8 bytes");
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(aos_dev && soa_fields_host, MX_ERR_INVALID, "mx_records_to_fields: null pointer");
+    FieldPtrs fp{};
+    for (int j = 0; j < nfields; ++j) {
+        MX_REQUIRE(soa_fields_host[j], MX_ERR_INVALID, "mx_records_to_fields: null field %d", j);
+        fp.p[j] = soa_fields_host[j];
+    }
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    const int grid = grid_for(n, d);
+    if (nfields == 4 && field_bytes == 4 && ((uintptr_t)aos_dev % 16) == 0)
+        hipLaunchKernelGGL(k_aos4_to_soa, dim3(grid), dim3(NT), 0, stream, (const float4 *)aos_dev, n, fp);
+    else if (field_bytes == 4)
+        hipLaunchKernelGGL(k_aos_to_soa<uint32_t>, dim3(grid), dim3(NT), 0, stream, (const uint32_t *)aos_dev, n,
+                           nfields, fp);
+    else
+        hipLaunchKernelGGL(k_aos_to_soa<uint64_t>, dim3(grid), dim3(NT), 0, stream, (const uint64_t *)aos_dev, n,
+                           nfields, fp);
+    return last_launch("mx_records_to_fields");
+}
+
+mx_status mx_fields_to_records(const void *const *soa_fields_host, int64_t n, int nfields,
+                               size_t field_bytes, void *aos_dev, hipStream_t stream) {
+    MX_REQUIRE(n >= 0, MX_ERR_SHAPE, "mx_fields_to_records: n < 0");
+    MX_REQUIRE(nfields >= 1 && nfields <= kMaxFields, MX_ERR_INVALID, "mx_fields_to_records: 1..16 fields");
+    MX_REQUIRE(field_bytes == 4 || field_bytes == 8, MX_ERR_INVALID, "mx_fields_to_records: fields of 4 or 8 bytes");
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(aos_dev && soa_fields_host, MX_ERR_INVALID, "mx_fields_to_records: null pointer");
+    FieldPtrs fp{};
+    for (int j = 0; j < nfields; ++j) {
+        MX_REQUIRE(soa_fields_host[j], MX_ERR_INVALID, "mx_fields_to_records: null field %d", j);
+        fp.p[j] = const_cast<void *>(soa_fields_host[j]);
+    }
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    const int grid = grid_for(n, d);
+    if (nfields == 4 && field_bytes == 4 && ((uintptr_t)aos_dev % 16) == 0)
+        hipLaunchKernelGGL(k_soa_to_aos4, dim3(grid), dim3(NT), 0, stream, fp, n, (float4 *)aos_dev);
+    else if (field_bytes == 4)
+        hipLaunchKernelGGL(k_soa_to_aos<uint32_t>, dim3(grid), dim3(NT), 0, stream, fp, n, nfields,
+                           (uint32_t *)aos_dev);
+    else
+        hipLaunchKernelGGL(k_soa_to_aos<uint64_t>, dim3(grid), dim3(NT), 0, stream, fp, n, nfields,
+                           (uint64_t *)aos_dev);
+    return last_launch("mx_fields_to_records");
+}
+
+}  // extern "C"

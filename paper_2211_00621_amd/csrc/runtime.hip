@@ -1,0 +1,146 @@
+// Runtime: error text, per-device property cache, debug flag, workspace
+// sizing and the plain streaming copy kernel.
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+
+#include "mx_internal.h"
+
+namespace mx {
+
+namespace {
+thread_local char g_err[512] = "";
+std::atomic<int> g_debug{0};
+std::mutex g_dev_mu;
+DeviceInfo g_devs[64];
+bool g_dev_ok[64] = {};
+}  // namespace
+
+mx_status set_error(mx_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+mx_status hip_error(hipError_t e, const char *what) {
+    return set_error(MX_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+mx_status last_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, what);
+    return MX_OK;
+}
+
+mx_status device_info(const DeviceInfo **out) {
+    int dev = 0;
+    MX_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(MX_ERR_INVALID, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_dev_ok[dev]) {
+        hipDeviceProp_t p;
+        MX_TRY_HIP(hipGetDeviceProperties(&p, dev));
+        DeviceInfo &d = g_devs[dev];
+        d.device = dev;
+        d.num_cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+        d.lds_bytes = (int)p.sharedMemPerBlock;
+        d.warp = p.warpSize;
+        g_dev_ok[dev] = true;
+    }
+    *out = &g_devs[dev];
+    return MX_OK;
+}
+
+bool debug_mode() { return g_debug.load(std::memory_order_relaxed) != 0; }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Streaming copy: grid-stride over 16-byte vectors, two in flight per thread.
+__global__ void __launch_bounds__(256) k_copy32(const uint32_t *__restrict__ src,
+                                                uint32_t *__restrict__ dst, int64_t n) {
+    const int64_t nv = n / 4;
+    const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+    u32x4 *d4 = reinterpret_cast<u32x4 *>(dst);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + stride < nv; i += 2 * stride) {
+        u32x4 a = __builtin_nontemporal_load(s4 + i);
+        u32x4 b = __builtin_nontemporal_load(s4 + i + stride);
+        __builtin_nontemporal_store(a, d4 + i);
+        __builtin_nontemporal_store(b, d4 + i + stride);
+    }
+    for (; i < nv; i += stride) d4[i] = s4[i];
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) dst[nv * 4 + threadIdx.x] = src[nv * 4 + threadIdx.x];
+}
+
+}  // namespace mx
+
+using namespace mx;
+
+extern "C" {
+
+mx_status mx_init(int device) {
+    MX_TRY_HIP(hipSetDevice(device));
+    const DeviceInfo *d;
+    return device_info(&d);
+}
+
+const char *mx_last_error(void) { return g_err; }
+
+const char *mx_version(void) { return "mx 0.1.0 gfx950"; }
+
+mx_status mx_set_debug(int on) {
+    g_debug.store(on ? 1 : 0);
+    return MX_OK;
+}
+
+int mx_get_debug(void) { return g_debug.load(); }
+
+size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux) {
+    if (n < 0) n = 0;
+    switch (kind) {
+    case MX_WS_REDUCE:
+        // counters + one 8-byte partial per block (at most 4096 blocks)
+        return kCounterBytes + align256(8 * 4096);
+    case MX_WS_SCAN: {
+        // counters + one int64 per scan tile of 4096 rows (+1)
+        int64_t tiles = (n + 4095) / 4096 + 1;
+        return kCounterBytes + align256((size_t)tiles * 8);
+    }
+    case MX_WS_KMEANS: {
+        // counters + per-block partial sums (fp32, k*d) and counts (int32, k)
+        int64_t blocks = 2048;
+        int64_t kd = aux > 0 ? aux : 1;
+        return kCounterBytes + align256((size_t)blocks * (size_t)kd * 4) + align256((size_t)blocks * 256 * 4);
+    }
+    case MX_WS_NBODY: {
+        // checkpoints of (pos4, vel4), a segment tape and adjoint ping-pong buffers
+        int64_t nck = aux > 0 ? aux : 1;
+        return kCounterBytes + align256((size_t)n * 16) * (size_t)(2 * nck + 16) + align256(8 * 4096);
+    }
+    }
+    return 0;
+}
+
+mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t stream) {
+    MX_REQUIRE(n >= 0, MX_ERR_SHAPE, "mx_copy32: n < 0");
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(src_dev && dst_dev, MX_ERR_INVALID, "mx_copy32: null pointer");
+    MX_REQUIRE(((uintptr_t)src_dev % 16) == 0 && ((uintptr_t)dst_dev % 16) == 0, MX_ERR_INVALID,
+               "mx_copy32: pointers must be 16-byte aligned");
+    const DeviceInfo *d;
+    mx_status st = device_info(&d);
+    if (st) return st;
+    int64_t nv = n / 4;
+    int64_t blocks = ceil_div(nv > 0 ? nv : 1, 256 * 2);
+    int64_t cap = (int64_t)d->num_cus * 8;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(k_copy32, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       (const uint32_t *)src_dev, (uint32_t *)dst_dev, n);
+    return last_launch("mx_copy32");
+}
+
+}  // extern "C"

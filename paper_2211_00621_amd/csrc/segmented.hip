@@ -1,0 +1,423 @@
+// Ragged sequences in the flat marshalled layout (values + int64 offsets):
+// nested map (reduce) over rows, its reverse (broadcast), the lengths ->
+// offsets scan of marshaling, offset composition for `map flatten`, and the
+// debug-mode validation of offsets (Appendix "Dynamic Assumptions").
+#include <mutex>
+
+#include "mx_internal.h"
+
+namespace mx {
+namespace {
+
+constexpr int NT = 256;
+constexpr int kRowsPerBlock = NT / kWave;
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// ---------------------------------------------------------------- debug validation
+// flag bit 0: offsets[0] != 0; bit 1: a decreasing pair; bit 2: negative length
+__global__ void __launch_bounds__(NT) k_check_offsets(const int64_t *__restrict__ off, int64_t nseg,
+                                                      unsigned *flag) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x; r < nseg; r += stride)
+        if (off[r + 1] < off[r]) atomicOr(flag, 2u);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && off[0] != 0) atomicOr(flag, 1u);
+}
+
+__global__ void __launch_bounds__(NT) k_check_lengths(const int64_t *__restrict__ len, int64_t n,
+                                                      unsigned *flag) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x; r < n; r += stride)
+        if (len[r] < 0) atomicOr(flag, 4u);
+}
+
+std::mutex g_flag_mu;
+unsigned *g_flag[64] = {};
+
+// Debug mode only: runs a validation kernel and waits for it.
+mx_status debug_flag(int dev, unsigned **out) {
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    if (!g_flag[dev]) MX_TRY_HIP(hipMalloc(&g_flag[dev], sizeof(unsigned)));
+    *out = g_flag[dev];
+    return MX_OK;
+}
+
+mx_status validate_offsets(const char *who, const int64_t *off, int64_t nseg, hipStream_t s,
+                           const DeviceInfo *d) {
+    unsigned *flag;
+    if (mx_status st = debug_flag(d->device, &flag)) return st;
+    MX_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned), s));
+    int grid = (int)ceil_div(nseg > 0 ? nseg : 1, NT);
+    if (grid > d->num_cus * 4) grid = d->num_cus * 4;
+    hipLaunchKernelGGL(k_check_offsets, dim3(grid), dim3(NT), 0, s, off, nseg, flag);
+    if (mx_status st = last_launch(who)) return st;
+    unsigned h = 0;
+    MX_TRY_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, s));
+    MX_TRY_HIP(hipStreamSynchronize(s));
+    if (h & 1u) return set_error(MX_ERR_SHAPE, "%s: offsets[0] != 0", who);
+    if (h & 2u) return set_error(MX_ERR_SHAPE, "%s: offsets are not non-decreasing", who);
+    return MX_OK;
+}
+
+mx_status validate_lengths(const char *who, const int64_t *len, int64_t n, hipStream_t s,
+                           const DeviceInfo *d) {
+    unsigned *flag;
+    if (mx_status st = debug_flag(d->device, &flag)) return st;
+    MX_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned), s));
+    int grid = (int)ceil_div(n > 0 ? n : 1, NT);
+    if (grid > d->num_cus * 4) grid = d->num_cus * 4;
+    hipLaunchKernelGGL(k_check_lengths, dim3(grid), dim3(NT), 0, s, len, n, flag);
+    if (mx_status st = last_launch(who)) return st;
+    unsigned h = 0;
+    MX_TRY_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, s));
+    MX_TRY_HIP(hipStreamSynchronize(s));
+    if (h & 4u) return set_error(MX_ERR_SHAPE, "%s: negative row length", who);
+    return MX_OK;
+}
+
+// ---------------------------------------------------------------- wave-per-row reduce
+// One wave64 folds one row: an unaligned head and tail of at most V-1
+// elements, and the 16-byte-aligned body with four vectors in flight per lane.
+template <mx_dtype D, int OP>
+__global__ void __launch_bounds__(NT) k_seg_wave(const typename DT<D>::In *__restrict__ values,
+                                                 const int64_t *__restrict__ offsets, int64_t nseg,
+                                                 typename DT<D>::Acc ne,
+                                                 typename DT<D>::Acc *__restrict__ out, int vec) {
+    using In = typename DT<D>::In;
+    using Acc = typename DT<D>::Acc;
+    using Vec = typename DT<D>::Vec;
+    using R = Red<OP, Acc>;
+    constexpr int V = DT<D>::kVec;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (row >= nseg) return;  // wave-uniform
+    const int64_t s = offsets[row], e = offsets[row + 1];
+    Acc acc = R::id();
+    if (vec) {
+        const int64_t vs = (s + V - 1) / V, ve = e / V;  // whole vectors inside [s, e)
+        const int64_t head_end = vs * V < e ? vs * V : e;
+        if (s + lane < head_end) acc = R::ap(acc, Acc(values[s + lane]));
+        const Vec *vv = reinterpret_cast<const Vec *>(values);
+        Acc a1 = R::id(), a2 = R::id(), a3 = R::id();
+        int64_t i = vs + lane;
+        for (; i + 3 * kWave < ve; i += 4 * kWave) {
+            Vec x0 = vv[i], x1 = vv[i + kWave], x2 = vv[i + 2 * kWave], x3 = vv[i + 3 * kWave];
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                acc = R::ap(acc, Acc(vget<Vec, In>(x0, j)));
+                a1 = R::ap(a1, Acc(vget<Vec, In>(x1, j)));
+                a2 = R::ap(a2, Acc(vget<Vec, In>(x2, j)));
+                a3 = R::ap(a3, Acc(vget<Vec, In>(x3, j)));
+            }
+        }
+        for (; i < ve; i += kWave) {
+            Vec x0 = vv[i];
+#pragma unroll
+            for (int j = 0; j < V; ++j) acc = R::ap(acc, Acc(vget<Vec, In>(x0, j)));
+        }
+        acc = R::ap(R::ap(acc, a1), R::ap(a2, a3));
+        const int64_t tail_start = ve * V > head_end ? ve * V : head_end;
+        if (tail_start + lane < e) acc = R::ap(acc, Acc(values[tail_start + lane]));
+    } else {
+        for (int64_t i = s + lane; i < e; i += kWave) acc = R::ap(acc, Acc(values[i]));
+    }
+    acc = wave_reduce<R>(acc);
+    if (lane == 0) out[row] = R::ap(ne, acc);
+}
+
+// Plain: one thread folds one row left to right.
+template <mx_dtype D, int OP>
+__global__ void __launch_bounds__(NT) k_seg_thread(const typename DT<D>::In *__restrict__ values,
+                                                   const int64_t *__restrict__ offsets,
+                                                   int64_t nseg, typename DT<D>::Acc ne,
+                                                   typename DT<D>::Acc *__restrict__ out) {
+    using Acc = typename DT<D>::Acc;
+    using R = Red<OP, Acc>;
+    const int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (row >= nseg) return;
+    Acc acc = ne;
+    for (int64_t i = offsets[row]; i < offsets[row + 1]; ++i) acc = R::ap(acc, Acc(values[i]));
+    out[row] = acc;
+}
+
+// Reverse of the row sums: broadcast gout[r] over row r, one wave per row.
+__global__ void __launch_bounds__(NT) k_seg_broadcast(const float *__restrict__ gout,
+                                                      const int64_t *__restrict__ offsets,
+                                                      int64_t nseg, float *__restrict__ gval,
+                                                      int vec) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (row >= nseg) return;
+    const int64_t s = offsets[row], e = offsets[row + 1];
+    const float g = gout[row];
+    if (vec) {
+        const int64_t vs = (s + 3) / 4, ve = e / 4;
+        const int64_t head_end = vs * 4 < e ? vs * 4 : e;
+        if (s + lane < head_end) gval[s + lane] = g;
+        float4 *gv = reinterpret_cast<float4 *>(gval);
+        const float4 g4 = make_float4(g, g, g, g);
+        for (int64_t i = vs + lane; i < ve; i += kWave) gv[i] = g4;
+        const int64_t tail_start = ve * 4 > head_end ? ve * 4 : head_end;
+        if (tail_start + lane < e) gval[tail_start + lane] = g;
+    } else {
+        for (int64_t i = s + lane; i < e; i += kWave) gval[i] = g;
+    }
+}
+
+// ---------------------------------------------------------------- lengths -> offsets
+// Tiles of 4096 rows (16 per thread).  Pass 1 sums each tile; pass 2 gives each
+// tile its prefix (the sum of earlier tile sums, or a pre-scanned prefix for
+// very many tiles) and scans the tile in LDS.
+constexpr int kScanPer = 16;
+constexpr int kScanTile = NT * kScanPer;
+// one pad slot per 16 entries keeps the per-thread runs of 16 on distinct banks
+__device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *wsum, int64_t *total) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int64_t incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int64_t o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) {
+        if (w < wave) before += wsum[w];
+        all += wsum[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+__global__ void __launch_bounds__(NT) k_scan_tilesum(const int64_t *__restrict__ len, int64_t n,
+                                                     int64_t *__restrict__ tile_sum) {
+    __shared__ int64_t smem[NT / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        int64_t i = base + j * NT + threadIdx.x;
+        if (i < n) s += len[i];
+    }
+    s = block_reduce<Red<MX_ADD, int64_t>, NT>(s, smem);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+// Single block: exclusive scan of the tile sums in place (used when there are
+// too many tiles for each tile to sum its predecessors).
+__global__ void __launch_bounds__(NT) k_scan_tilesum_prefix(int64_t *tile_sum, int64_t ntiles) {
+    __shared__ int64_t wsum[NT / kWave];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += NT) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = i < ntiles ? tile_sum[i] : 0;
+        int64_t total;
+        int64_t ex = block_excl_scan(v, wsum, &total);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ len, int64_t n,
+                                                   int64_t *__restrict__ off,
+                                                   const int64_t *__restrict__ tile_sum,
+                                                   int prefix_mode) {
+    __shared__ int64_t tile[kScanTile + kScanTile / 16];
+    __shared__ int64_t wsum[NT / kWave];
+    __shared__ int64_t red[NT / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // prefix of this tile
+    int64_t prefix = 0;
+    if (prefix_mode == 1) {
+        int64_t p = 0;
+        for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += NT) p += tile_sum[t];
+        prefix = block_reduce<Red<MX_ADD, int64_t>, NT>(p, red);
+    } else if (prefix_mode == 2) {
+        prefix = tile_sum[blockIdx.x];
+    }
+    // coalesced load into LDS
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        int64_t i = base + j * NT + threadIdx.x;
+        tile[spad(j * NT + threadIdx.x)] = i < n ? len[i] : 0;
+    }
+    __syncthreads();
+    int64_t mine[kScanPer];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        mine[j] = tile[spad(threadIdx.x * kScanPer + j)];
+        s += mine[j];
+    }
+    int64_t total;
+    int64_t run = prefix + block_excl_scan(s, wsum, &total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        tile[spad(threadIdx.x * kScanPer + j)] = run;
+        run += mine[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        int64_t i = base + j * NT + threadIdx.x;
+        if (i < n) off[i] = tile[spad(j * NT + threadIdx.x)];
+    }
+    if (base + kScanTile >= n && threadIdx.x == 0) off[n] = prefix + total;
+}
+
+__global__ void __launch_bounds__(NT) k_compose(const int64_t *__restrict__ outer, int64_t nouter,
+                                                const int64_t *__restrict__ inner,
+                                                int64_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i <= nouter; i += stride)
+        out[i] = inner[outer[i]];
+}
+
+// ---------------------------------------------------------------- dispatch
+template <mx_dtype D, int OP>
+mx_status launch_seg(bool plain, const void *values, const int64_t *off, int64_t nseg,
+                     const void *ne_host, void *out, hipStream_t s) {
+    using In = typename DT<D>::In;
+    using Acc = typename DT<D>::Acc;
+    Acc ne;
+    __builtin_memcpy(&ne, ne_host, sizeof(Acc));
+    if (plain) {
+        int grid = (int)ceil_div(nseg, NT);
+        hipLaunchKernelGGL((k_seg_thread<D, OP>), dim3(grid), dim3(NT), 0, s, (const In *)values, off,
+                           nseg, ne, (Acc *)out);
+    } else {
+        int64_t grid = ceil_div(nseg, kRowsPerBlock);
+        MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "mx_segmented_reduce: too many rows");
+        hipLaunchKernelGGL((k_seg_wave<D, OP>), dim3((unsigned)grid), dim3(NT), 0, s, (const In *)values,
+                           off, nseg, ne, (Acc *)out, (int)aligned16(values));
+    }
+    return last_launch("mx_segmented_reduce");
+}
+
+template <mx_dtype D>
+mx_status seg_by_op(bool plain, int op, const void *v, const int64_t *off, int64_t nseg,
+                    const void *ne, void *out, hipStream_t s) {
+    switch (op) {
+    case MX_ADD: return launch_seg<D, MX_ADD>(plain, v, off, nseg, ne, out, s);
+    case MX_MUL: return launch_seg<D, MX_MUL>(plain, v, off, nseg, ne, out, s);
+    case MX_MIN: return launch_seg<D, MX_MIN>(plain, v, off, nseg, ne, out, s);
+    case MX_MAX: return launch_seg<D, MX_MAX>(plain, v, off, nseg, ne, out, s);
+    }
+    return set_error(MX_ERR_INVALID, "mx_segmented_reduce: unknown operator %d", op);
+}
+
+mx_status segmented(const char *who, bool plain, int op, mx_dtype dtype, const void *values,
+                    const int64_t *off, int64_t nseg, const void *ne, void *out, hipStream_t s) {
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "%s: nseg < 0", who);
+    MX_REQUIRE(dtype_valid(dtype), MX_ERR_DTYPE, "%s: bad dtype %d", who, (int)dtype);
+    MX_REQUIRE(op >= MX_ADD && op <= MX_MAX, MX_ERR_INVALID, "%s: unknown operator %d", who, op);
+    MX_REQUIRE(ne, MX_ERR_INVALID, "%s: null ne", who);
+    if (nseg == 0) return MX_OK;
+    MX_REQUIRE(off && out, MX_ERR_INVALID, "%s: null offsets or out", who);
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    if (debug_mode())
+        if (mx_status st = validate_offsets(who, off, nseg, s, d)) return st;
+    switch (dtype) {
+    case MX_F32: return seg_by_op<MX_F32>(plain, op, values, off, nseg, ne, out, s);
+    case MX_F64: return seg_by_op<MX_F64>(plain, op, values, off, nseg, ne, out, s);
+    case MX_I32: return seg_by_op<MX_I32>(plain, op, values, off, nseg, ne, out, s);
+    case MX_I64: return seg_by_op<MX_I64>(plain, op, values, off, nseg, ne, out, s);
+    }
+    return MX_ERR_DTYPE;
+}
+
+}  // namespace
+
+// Also used by marshaling.
+mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, void *ws,
+                             size_t ws_bytes, hipStream_t s) {
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "mx_lengths_to_offsets: nseg < 0");
+    MX_REQUIRE(off, MX_ERR_INVALID, "mx_lengths_to_offsets: null offsets");
+    MX_REQUIRE(nseg == 0 || len, MX_ERR_INVALID, "mx_lengths_to_offsets: null lengths");
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    if (nseg > 0 && debug_mode())
+        if (mx_status st = validate_lengths("mx_lengths_to_offsets", len, nseg, s, d)) return st;
+    const int64_t ntiles = ceil_div(nseg, kScanTile);
+    MX_REQUIRE(ntiles <= 0x7fffffff, MX_ERR_SHAPE, "mx_lengths_to_offsets: too many rows");
+    if (ntiles <= 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(NT), 0, s, len, nseg, off, (const int64_t *)nullptr, 0);
+        return last_launch("mx_lengths_to_offsets");
+    }
+    size_t need = mx_workspace_bytes(MX_WS_SCAN, nseg, 0);
+    MX_REQUIRE(ws && ws_bytes >= need, MX_ERR_WORKSPACE, "mx_lengths_to_offsets: workspace needs %zu bytes", need);
+    int64_t *tile_sum = (int64_t *)((char *)ws + kCounterBytes);
+    hipLaunchKernelGGL(k_scan_tilesum, dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, tile_sum);
+    int mode = 1;
+    if (ntiles > 2048) {
+        hipLaunchKernelGGL(k_scan_tilesum_prefix, dim3(1), dim3(NT), 0, s, tile_sum, ntiles);
+        mode = 2;
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, off,
+                       (const int64_t *)tile_sum, mode);
+    return last_launch("mx_lengths_to_offsets");
+}
+
+}  // namespace mx
+
+using namespace mx;
+
+extern "C" {
+
+mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_dev,
+                              const int64_t *offsets_dev, int64_t nseg, const void *ne_host,
+                              void *out_dev, hipStream_t stream) {
+    return segmented("mx_segmented_reduce", false, op, dtype, values_dev, offsets_dev, nseg, ne_host,
+                     out_dev, stream);
+}
+
+mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *values_dev,
+                                    const int64_t *offsets_dev, int64_t nseg, const void *ne_host,
+                                    void *out_dev, hipStream_t stream) {
+    return segmented("mx_segmented_reduce_plain", true, op, dtype, values_dev, offsets_dev, nseg,
+                     ne_host, out_dev, stream);
+}
+
+mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *offsets_dev,
+                                       int64_t nseg, float *gvalues_dev, hipStream_t stream) {
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "mx_segmented_sum_adjoint_f32: nseg < 0");
+    if (nseg == 0) return MX_OK;
+    MX_REQUIRE(gout_dev && offsets_dev && gvalues_dev, MX_ERR_INVALID,
+               "mx_segmented_sum_adjoint_f32: null pointer");
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    if (debug_mode())
+        if (mx_status st = validate_offsets("mx_segmented_sum_adjoint_f32", offsets_dev, nseg, stream, d))
+            return st;
+    int64_t grid = ceil_div(nseg, kRowsPerBlock);
+    MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "mx_segmented_sum_adjoint_f32: too many rows");
+    hipLaunchKernelGGL(k_seg_broadcast, dim3((unsigned)grid), dim3(NT), 0, stream, gout_dev,
+                       offsets_dev, nseg, gvalues_dev, (int)aligned16(gvalues_dev));
+    return last_launch("mx_segmented_sum_adjoint_f32");
+}
+
+mx_status mx_lengths_to_offsets(const int64_t *lengths_dev, int64_t nseg, int64_t *offsets_dev,
+                                void *ws, size_t ws_bytes, hipStream_t stream) {
+    return lengths_to_offsets(lengths_dev, nseg, offsets_dev, ws, ws_bytes, stream);
+}
+
+mx_status mx_compose_offsets(const int64_t *outer_dev, int64_t nouter, const int64_t *inner_dev,
+                             int64_t *out_dev, hipStream_t stream) {
+    MX_REQUIRE(nouter >= 0, MX_ERR_SHAPE, "mx_compose_offsets: nouter < 0");
+    MX_REQUIRE(outer_dev && inner_dev && out_dev, MX_ERR_INVALID, "mx_compose_offsets: null pointer");
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    int grid = (int)ceil_div(nouter + 1, NT);
+    if (grid > d->num_cus * 8) grid = d->num_cus * 8;
+    hipLaunchKernelGGL(k_compose, dim3(grid), dim3(NT), 0, stream, outer_dev, nouter, inner_dev, out_dev);
+    return last_launch("mx_compose_offsets");
+}
+
+}  // extern "C"

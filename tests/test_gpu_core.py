@@ -1,0 +1,405 @@
+"""GPU parity of map, map2, reduce, the fused dot, marshaling and ragged /
+dense nested map(reduce) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from parity import check_scalar, check_vector, say, ulp_diff_f32
+
+pytestmark = pytest.mark.gpu
+
+import paper_2211_00621_amd as mx  # noqa: E402  (no skip: a missing library must fail)
+abi = mx.abi
+api = mx.api
+
+DEV = "cuda"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SIZES = [0, 1, 3, 63, 64, 65, 255, 256, 257, 1000, 4095, 4097, 65537, (1 << 20) + 3]
+
+
+# ------------------------------------------------------------------ map / map2
+@pytest.mark.parametrize("f,np_op", [(abi.MX_B_ADD, np.add), (abi.MX_B_SUB, np.subtract),
+                                     (abi.MX_B_MUL, np.multiply), (abi.MX_B_DIV, np.divide),
+                                     (abi.MX_B_MIN, np.minimum), (abi.MX_B_MAX, np.maximum)])
+@pytest.mark.parametrize("n", [1, 5, 4099, 1 << 18])
+def test_map2_f32_bit_exact(f, np_op, n):
+    say("map2 f32", f, n)
+    a, b = W.dot_f32(n, seed=n)
+    out = api.map2(f, dev(a), dev(b))
+    ref = O.map2(f, a, b).astype(np.float32)  # one IEEE binary32 rounding of the exact value
+    assert np.array_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.int64])
+@pytest.mark.parametrize("f", [abi.MX_B_ADD, abi.MX_B_SUB, abi.MX_B_MUL, abi.MX_B_MIN, abi.MX_B_MAX])
+def test_map2_int_exact(dt, f):
+    say("map2 int", dt, f)
+    rng = np.random.default_rng(f)
+    n = 10007
+    hi = 2 ** 31 - 1 if dt == np.int32 else 2 ** 62
+    a = rng.integers(-hi, hi, n).astype(dt)
+    b = rng.integers(-hi, hi, n).astype(dt)
+    out = api.map2(f, dev(a), dev(b))
+    assert np.array_equal(host(out), O.map2(f, a, b))
+
+
+def test_map2_unaligned_views_and_inplace():
+    say("map2 views")
+    a, b = W.dot_f32(5001, seed=3)
+    ta, tb = dev(a), dev(b)
+    out = api.map2(abi.MX_B_ADD, ta[1:], tb[1:])  # offset by 4 bytes: scalar path
+    assert np.array_equal(host(out), (a[1:] + b[1:]))
+    # Listing 1's axpy loop as an in-place map2: t1 <- t1 + 2 t2
+    t1 = dev(np.arange(1000, dtype=np.int64))
+    t2 = dev(np.ones(1000, dtype=np.int64))
+    two_t2 = api.map(abi.MX_U_AFFINE, t2, (2, 0))
+    abi.mx_map2(abi.MX_B_ADD, t1, two_t2, t1)
+    assert np.array_equal(host(t1), np.arange(1000) + 2)
+
+
+@pytest.mark.parametrize("f", [abi.MX_U_ID, abi.MX_U_NEG, abi.MX_U_ABS, abi.MX_U_SQ])
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32, np.int64])
+def test_map_exact_bodies(f, dt):
+    say("map", f, dt)
+    rng = np.random.default_rng(1)
+    x = (rng.uniform(-1000, 1000, 3001)).astype(dt)
+    out = host(api.map(f, dev(x)))
+    ref = O.map(f, x)
+    if dt == np.float32:
+        ref = ref.astype(np.float32)
+    assert np.array_equal(out, ref)
+
+
+def test_map_affine_listing2_int():
+    say("map affine int")
+    s = np.arange(-5000, 5000, dtype=np.int32)
+    c = 13
+    out = host(api.map(abi.MX_U_AFFINE, dev(s), (c, c)))
+    assert out.dtype == np.int64
+    assert np.array_equal(out, O.map(O.U_AFFINE, s, (c, c)))
+
+
+@pytest.mark.parametrize("f,maxulp", [(abi.MX_U_EXP, 2), (abi.MX_U_LOG, 2), (abi.MX_U_SQRT, 1),
+                                      (abi.MX_U_RSQRT, 2), (abi.MX_U_AFFINE, 2)])
+def test_map_float_bodies_within_ulps(f, maxulp):
+    say("map float", f)
+    x = np.random.default_rng(2).uniform(0.01, 20.0, 20000).astype(np.float32)
+    params = (1.5, 0.25) if f == abi.MX_U_AFFINE else None
+    out = host(api.map(f, dev(x), params))
+    ref = O.map(f, x, params or (0, 0)).astype(np.float32)
+    assert ulp_diff_f32(out, ref).max() <= maxulp
+
+
+# ------------------------------------------------------------------ reduce / fused dot
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("op", [abi.MX_ADD, abi.MX_MUL, abi.MX_MIN, abi.MX_MAX])
+def test_reduce_int64_exact(n, op):
+    say("reduce i64", n, op)
+    rng = np.random.default_rng(n + op)
+    x = rng.integers(-2 ** 40, 2 ** 40, n).astype(np.int64)
+    ne = {abi.MX_ADD: 0, abi.MX_MUL: 1, abi.MX_MIN: 2 ** 63 - 1, abi.MX_MAX: -2 ** 63}[op]
+    got = int(host(api.reduce(op, dev(x), ne)))
+    assert got == O.reduce(op, ne, x)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_reduce_int32_widens(n):
+    say("reduce i32", n)
+    a, _ = W.dot_i32(n, seed=n)
+    got = api.reduce(abi.MX_ADD, dev(a), 0)
+    assert got.dtype == torch.int64 and int(host(got)) == O.reduce(O.ADD, 0, a)
+
+
+def test_reduce_nonneutral_ne_is_left_fold():
+    say("reduce ne")
+    x = np.arange(1, 101, dtype=np.int64)
+    assert int(host(api.reduce(abi.MX_ADD, dev(x), 1000))) == 1000 + 5050
+    assert int(host(api.reduce(abi.MX_MAX, dev(x), 7000))) == 7000
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_reduce_f32_within_tolerance(n):
+    say("reduce f32", n)
+    a, _ = W.dot_f32(n, seed=n + 1)
+    got = float(host(api.reduce(abi.MX_ADD, dev(a), 0.0)))
+    R = O.reduce(O.ADD, 0.0, a)
+    check_scalar(got, R, float(np.abs(a.astype(np.float64)).sum()), n, what=f"sum n={n}")
+    mn = float(host(api.reduce(abi.MX_MIN, dev(a), np.inf)))
+    assert mn == (O.reduce(O.MIN, np.inf, a) if n else np.inf)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dot_f32_config(seed):
+    """map2 (*) + reduce (+), two float32 vectors of 2^20, uniform [-1, 1]."""
+    n = 1 << 20
+    say("dot f32 2^20 seed", seed)
+    a, b = W.dot_f32(n, seed)
+    got = float(host(api.dot(dev(a), dev(b))))
+    R = O.dot(a, b)
+    S = O.map2_reduce(O.B_MUL, O.ADD, 0, np.abs(a), np.abs(b))
+    check_scalar(got, R, S, n, what="dot")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dot_i32_config_exact(seed):
+    """int32 variant, values in [-1000, 1000], products and sum in int64: bit-exact."""
+    n = 1 << 20
+    say("dot i32 2^20 seed", seed)
+    a, b = W.dot_i32(n, seed)
+    got = int(host(api.map2_reduce(abi.MX_B_MUL, abi.MX_ADD, dev(a), dev(b), 0)))
+    assert got == O.dot(a, b)
+    assert int(host(api.reduce(abi.MX_ADD, dev(a), 0))) == O.reduce(O.ADD, 0, a)
+
+
+@pytest.mark.parametrize("k", [10, 14, 18, 22, 24])
+def test_dot_f32_accuracy_sweep(k):
+    n = (1 << k) + 7
+    say("dot sweep", n)
+    a, b = W.dot_f32(n, seed=k)
+    got = float(host(api.dot(dev(a), dev(b))))
+    R = O.dot(a, b)
+    S = O.map2_reduce(O.B_MUL, O.ADD, 0, np.abs(a), np.abs(b))
+    check_scalar(got, R, S, n, what=f"dot n={n}")
+
+
+def test_dot_dyadic_constants_exact():
+    n = 1 << 24
+    say("dot dyadic")
+    a = torch.full((n,), 0.5, device=DEV)
+    b = torch.full((n,), 0.25, device=DEV)
+    assert float(host(api.dot(a, b))) == n / 8
+
+
+def test_reduce_deterministic_and_unaligned():
+    say("reduce determinism")
+    a, b = W.dot_f32((1 << 22) + 1, seed=9)
+    ta, tb = dev(a), dev(b)
+    r1 = host(api.dot(ta, tb))
+    r2 = host(api.dot(ta, tb))
+    assert r1.tobytes() == r2.tobytes()
+    r3 = float(host(api.dot(ta[1:], tb[1:])))
+    R = O.dot(a[1:], b[1:])
+    check_scalar(r3, R, O.map2_reduce(O.B_MUL, O.ADD, 0, np.abs(a[1:]), np.abs(b[1:])), a.size - 1)
+
+
+def test_dot_gradient_closed_form():
+    say("dot adjoint")
+    a, b = W.dot_f32(100003, seed=4)
+    ta = dev(a).requires_grad_()
+    tb = dev(b).requires_grad_()
+    y = api.dot(ta, tb)
+    (3.0 * y).backward()
+    assert np.array_equal(host(ta.grad), (np.float32(3.0) * b).astype(np.float32))
+    assert np.array_equal(host(tb.grad), (np.float32(3.0) * a).astype(np.float32))
+
+
+# ------------------------------------------------------------------ marshaling
+@pytest.mark.parametrize("nseg", [0, 1, 4095, 4096, 4097, 65536, 9_000_001])
+def test_lengths_to_offsets_exact(nseg):
+    say("offsets", nseg)
+    L = W.ragged_lengths(nseg, seed=3, lmax=100) if nseg else np.zeros(0, dtype=np.int64)
+    off = host(api.offsets_from_lengths(dev(L)))
+    assert np.array_equal(off, O.offsets_from_lengths(L))
+
+
+def test_marshal_rows_roundtrip_and_flatten():
+    say("marshal rows")
+    L, v = W.ragged_f32(3000, seed=5, lmax=700, empty_rows=40)
+    offs = O.offsets_from_lengths(L)
+    rows = [v[offs[r]:offs[r + 1]] for r in range(len(L))]
+    rg = api.marshal_rows(rows)
+    values_o, offsets_o = O.marshal_rows(rows)
+    assert np.array_equal(host(rg.offsets), offsets_o)
+    assert np.array_equal(host(rg.flatten()), values_o)
+    back = api.unmarshal_rows(rg)
+    assert all(np.array_equal(x, y) for x, y in zip(back, rows))
+
+
+def test_records_fields_roundtrip():
+    say("records")
+    rng = np.random.default_rng(0)
+    recs = [{"x": float(rng.normal()), "y": float(rng.normal()), "z": float(rng.normal()),
+             "m": float(rng.uniform(0.5, 1.5))} for _ in range(1001)]
+    fields = ["x", "y", "z", "m"]
+    aos = np.array([[r[f] for f in fields] for r in recs], dtype=np.float32)
+    soa = api.records_to_fields(dev(aos))
+    ref = O.marshal_records([{f: np.float32(r[f]) for f in fields} for r in recs], fields)
+    for f, t in zip(fields, soa):
+        assert np.array_equal(host(t), ref[f])
+    assert np.array_equal(host(api.fields_to_records(soa)), aos)
+    aos3 = np.arange(3 * 77, dtype=np.int64).reshape(77, 3)
+    soa3 = api.records_to_fields(dev(aos3))
+    assert np.array_equal(host(soa3[2]), aos3[:, 2])
+    assert np.array_equal(host(api.fields_to_records(soa3)), aos3)
+
+
+def test_compose_offsets_map_flatten():
+    say("compose offsets")
+    rng = np.random.default_rng(4)
+    nested = [[list(rng.integers(0, 9, int(rng.integers(0, 4)))) for _ in range(int(rng.integers(0, 5)))]
+              for _ in range(200)]
+    values, (o1, o2) = O.marshal_nested(nested, 3)
+    out = host(_compose(o1, o2))
+    flat_rows = [[v for inner in outer for v in inner] for outer in nested]
+    _, ref = O.marshal_nested(flat_rows, 2)
+    assert np.array_equal(out, ref[0])
+
+
+def _compose(o1, o2):
+    out = torch.empty(len(o1), dtype=torch.int64, device=DEV)
+    abi.mx_compose_offsets(dev(o1), dev(o2), out)
+    return out
+
+
+# ------------------------------------------------------------------ ragged nested map(reduce)
+def _ragged(nseg, seed, lmax=4096, empty_rows=0):
+    L, v = W.ragged_f32(nseg, seed, lmax, empty_rows)
+    return L, v, O.offsets_from_lengths(L)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("plain", [False, True])
+def test_segmented_sum_config(seed, plain):
+    """65536 float32 rows, lengths log-uniform in [1, 4096]: every row vs the oracle."""
+    say("segmented config seed", seed, "plain", plain)
+    L, v, off = _ragged(65536, seed)
+    rg = api.Ragged(dev(v), dev(off))
+    got = host(api.segmented_reduce(abi.MX_ADD, rg, 0.0, plain=plain))
+    R = O.segmented_reduce(O.ADD, 0.0, v, off)
+    S = O.segmented_reduce(O.ADD, 0.0, np.abs(v), off)
+    check_vector(got, R, S, L, what="row sums")
+
+
+@pytest.mark.parametrize("op", [abi.MX_ADD, abi.MX_MUL, abi.MX_MIN, abi.MX_MAX])
+@pytest.mark.parametrize("dt", [np.int32, np.int64])
+def test_segmented_int_exact_with_empty_rows(op, dt):
+    say("segmented int", op, dt)
+    L = W.ragged_lengths(5000, seed=op, lmax=3000)
+    L[::13] = 0
+    off = O.offsets_from_lengths(L)
+    rng = np.random.default_rng(op)
+    v = rng.integers(-3, 4, int(off[-1])).astype(dt) if op == abi.MX_MUL else \
+        rng.integers(-10 ** 6, 10 ** 6, int(off[-1])).astype(dt)
+    ne = {abi.MX_ADD: 0, abi.MX_MUL: 1, abi.MX_MIN: 2 ** 63 - 1, abi.MX_MAX: -2 ** 63}[op]
+    rg = api.Ragged(dev(v), dev(off))
+    for plain in (False, True):
+        got = host(api.segmented_reduce(op, rg, ne, plain=plain))
+        assert np.array_equal(got, O.segmented_reduce(op, ne, v, off)), plain
+
+
+def test_segmented_unaligned_values_view():
+    say("segmented view")
+    L, v, off = _ragged(777, 8, lmax=300)
+    full = dev(np.concatenate([[np.float32(7.0)], v]))
+    rg = api.Ragged(full[1:], dev(off))
+    got = host(api.segmented_reduce(abi.MX_ADD, rg, 0.0))
+    check_vector(got, O.segmented_reduce(O.ADD, 0.0, v, off),
+                 O.segmented_reduce(O.ADD, 0.0, np.abs(v), off), L)
+
+
+def test_segmented_sum_adjoint_broadcast_exact():
+    say("segmented adjoint")
+    L, v, off = _ragged(4000, 3, lmax=2000, empty_rows=30)
+    g = np.random.default_rng(0).uniform(-1, 1, len(L)).astype(np.float32)
+    vals = dev(v).requires_grad_()
+    out = api.segmented_sum(api.Ragged(vals, dev(off)))
+    out.backward(dev(g))
+    assert np.array_equal(host(vals.grad), O.segmented_sum_adjoint(g, off).astype(np.float32))
+
+
+def test_debug_mode_rejects_bad_offsets():
+    say("debug offsets")
+    bad = dev(np.array([0, 5, 3, 9], dtype=np.int64))
+    vals = dev(np.zeros(9, dtype=np.float32))
+    out = torch.empty(3, device=DEV)
+    abi.mx_set_debug(True)
+    try:
+        with pytest.raises(abi.MxError) as e:
+            abi.mx_segmented_reduce(abi.MX_ADD, vals, bad, 0.0, out)
+        assert e.value.status == abi.MX_ERR_SHAPE
+        with pytest.raises(abi.MxError):
+            api.offsets_from_lengths(dev(np.array([3, -1, 2], dtype=np.int64)))
+    finally:
+        abi.mx_set_debug(False)
+    # accelerate mode does not check: the call is accepted
+    abi.mx_segmented_reduce(abi.MX_ADD, vals, dev(np.array([0, 3, 5, 9], dtype=np.int64)), 0.0, out)
+    assert np.array_equal(host(out), np.zeros(3, dtype=np.float32))
+
+
+# ------------------------------------------------------------------ dense map-map-reduce
+def _abs_prod_sum(A, B):
+    return O.matmul(np.abs(A), np.abs(B))
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (128, 128, 32), (200, 130, 70), (257, 511, 33),
+                                   (64, 300, 1000), (129, 127, 129), (3, 1025, 5)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_mmr_shapes_vs_oracle(M, N, K, ta, tb):
+    say("mmr", M, N, K, ta, tb)
+    A, B = W.dense_f32(M, N, K, seed=M + N + K)
+    As = A.T.copy() if ta else A
+    Bs = B.T.copy() if tb else B
+    C = torch.empty((M, N), device=DEV)
+    abi.mx_map_map_reduce_f32(ta, tb, dev(As), dev(Bs), C)
+    R = O.matmul(A, B)
+    check_vector(host(C).ravel(), R.ravel(), _abs_prod_sum(A, B).ravel(), K, what="C")
+    Cp = torch.empty((M, N), device=DEV)
+    abi.mx_map_map_reduce_plain_f32(ta, tb, dev(As), dev(Bs), Cp)
+    check_vector(host(Cp).ravel(), R.ravel(), _abs_prod_sum(A, B).ravel(), K, what="C plain")
+
+
+def test_mmr_rank_one_exact():
+    say("mmr rank one")
+    M, N, K = 256, 384, 512
+    u = (np.arange(M) % 7 - 3).astype(np.float32) * 0.25
+    v = (np.arange(N) % 5 - 2).astype(np.float32) * 0.5
+    A = np.outer(u, np.ones(K, dtype=np.float32))
+    B = np.outer(np.ones(K, dtype=np.float32), v)
+    C = api.matmul(dev(A), dev(B))
+    assert np.array_equal(host(C), (K * np.outer(u, v)).astype(np.float32))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mmr_config_2048_sampled(seed):
+    """2048 x 2048 x 2048, uniform [-1, 1]: 512 sampled elements vs the oracle one by one."""
+    say("mmr 2048 seed", seed)
+    M = N = K = 2048
+    A, B = W.dense_f32(M, N, K, seed)
+    C = host(api.matmul(dev(A), dev(B)))
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(0, M, 512)
+    jj = rng.integers(0, N, 512)
+    ii[:4] = [0, M - 1, 0, M - 1]
+    jj[:4] = [0, 0, N - 1, N - 1]
+    for i, j in zip(ii, jj):
+        R = O.dot(A[i], B[:, j])
+        S = O.dot(np.abs(A[i]), np.abs(B[:, j]))
+        check_scalar(C[i, j], R, S, K, what=f"C[{i},{j}]")
+
+
+def test_mmr_deterministic_and_gradients():
+    say("mmr grad")
+    M, N, K = 192, 160, 96
+    A, B = W.dense_f32(M, N, K, seed=5)
+    G = np.random.default_rng(1).uniform(-1, 1, (M, N)).astype(np.float32)
+    tA, tB = dev(A).requires_grad_(), dev(B).requires_grad_()
+    C = api.matmul(tA, tB)
+    C2 = api.matmul(tA.detach(), tB.detach())
+    assert host(C.detach()).tobytes() == host(C2).tobytes()
+    C.backward(dev(G))
+    gA_ref = O.matmul(G, B.T)
+    gB_ref = O.matmul(A.T, G)
+    check_vector(host(tA.grad).ravel(), gA_ref.ravel(), O.matmul(np.abs(G), np.abs(B.T)).ravel(), N)
+    check_vector(host(tB.grad).ravel(), gB_ref.ravel(), O.matmul(np.abs(A.T), np.abs(G)).ravel(), M)
