@@ -291,7 +291,222 @@ def bench_dot(args):
     }
 
 
-WORKLOADS = {"nested": bench_nested, "dot": bench_dot}
+# ============================================================ N-body loop
+# VALU instructions per pair interaction in the inner loop of the fused
+# forward pair kernel (gfx950 ISA of k_pairs<STEP>: 3 sub, 3 mul/fma for |d|^2
+# plus eps2, 2 mul for the cube, 1 mul by the mass, 3 fma into the sums) and
+# one transcendental (v_rsq_f32) issued at a quarter of the VALU rate.
+NBODY_VALU_PER_PAIR = 13
+NBODY_TRANS_PER_PAIR = 1
+# 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz (no packed FP32).
+LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def nbody_peak_pairs_per_s(valu, trans):
+    return LANE_OPS_PER_S / (valu + 4 * trans)
+
+
+def bench_nbody(args):
+    import torch
+    import workloads as W
+    from paper_2211_00621_amd import abi, api
+    dev = torch.device("cuda:0")
+    n, T, K, eps2, G, dt = 16384, 20, 5, 1e-6, 1.0, 1e-4
+    pos, m, vel = W.nbody(n, 0)
+    p4 = torch.zeros((n, 4), device=dev)
+    p4[:, :3] = torch.from_numpy(pos).to(dev)
+    p4[:, 3] = torch.from_numpy(m).to(dev)
+    v4 = torch.zeros((n, 4), device=dev)
+    ke = torch.empty((), device=dev)
+    gx, gv = torch.empty_like(p4), torch.empty_like(p4)
+    ws = torch.zeros(abi.mx_nbody_workspace_bytes(n, T, K), dtype=torch.uint8, device=dev)
+    pws = torch.zeros(abi.mx_nbody_pair_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    xa, va, xb, vb = (torch.zeros_like(p4) for _ in range(4))
+    acc = torch.empty_like(p4)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    # graph of the whole loop and its checkpointed reverse
+    with torch.cuda.stream(side):
+        abi.mx_nbody_ke_grad_f32(p4, v4, eps2, G, dt, T, K, ke, gx, gv, ws, stream=side)  # warm
+        side.synchronize()
+        abi.mx_graph_begin(side)
+        abi.mx_nbody_ke_grad_f32(p4, v4, eps2, G, dt, T, K, ke, gx, gv, ws, stream=side)
+        g_full = abi.mx_graph_end(side)
+        abi.mx_graph_begin(side)
+        for t in range(T):
+            src = (p4, v4) if t == 0 else ((xa, va) if t % 2 else (xb, vb))
+            dst = (xb, vb) if t % 2 else (xa, va)
+            abi.mx_nbody_step_f32(*src, eps2, G, dt, *dst, pws, stream=side)
+        g_fwd = abi.mx_graph_end(side)
+    side.synchronize()
+
+    def run_graph(g, pt):
+        g.launch(side)
+
+    def timed_on(stream, fn, steps, warmup):
+        for _ in range(warmup):
+            fn(None)
+        stream.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn(None)
+        b.record(stream)
+        stream.synchronize()
+        return a.elapsed_time(b) / steps
+
+    log("nbody: graph-captured loop + checkpointed reverse")
+    ms = timed_on(side, lambda pt: run_graph(g_full, pt), args.steps, args.warmup)
+    ms_fwd = timed_on(side, lambda pt: run_graph(g_fwd, pt), args.steps, args.warmup)
+    log(f"nbody: fwd+bwd {ms:.3f} ms, fwd {ms_fwd:.3f} ms")
+
+    # per-launch durations of the pair kernels (eager, events on the launch stream)
+    def one_step(pt):
+        m_ = pt.mark if pt else (lambda: None)
+        m_(); abi.mx_nbody_step_f32(p4, v4, eps2, G, dt, xa, va, pws)
+        m_(); abi.mx_nbody_adjoint_step_f32(p4, xb, va, eps2, G, dt, gx, gv, pws)
+        m_()
+    _, parts = timed(one_step, 10, 2, ["step", "adjoint_step"])
+
+    # plain: eager untiled pair loop + separate update, forward only
+    def plain_fwd(pt):
+        x, v = p4, v4
+        for t in range(T):
+            dst = (xb, vb) if t % 2 else (xa, va)
+            abi.mx_nbody_step_plain_f32(x, v, eps2, G, dt, acc, *dst)
+            x, v = dst
+    pms = timed_on(torch.cuda.current_stream(), plain_fwd, max(1, min(args.steps, 3)), 1)
+    log(f"nbody: plain fwd {pms:.3f} ms")
+
+    pairs_fwd = T * n * n
+    pairs_bwd = (T - T // K) * n * n + T * n * n  # recomputed steps + adjoint steps
+    peak = nbody_peak_pairs_per_s(NBODY_VALU_PER_PAIR, NBODY_TRANS_PER_PAIR)
+    ach = n * n / (parts["step"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": (pairs_fwd + pairs_bwd) / (ms * 1e-3), "unit": "pair-interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "loop around pairwise map(reduce): N-body N=16384, 20 Euler steps, dt=1e-4, "
+                               "eps=1e-3, fwd + adjoint of final KE wrt x0 with checkpoints every 5 steps",
+                   "n": n, "steps": T, "ckpt_every": K},
+        "roofline": {"bound": "alu", "kernel": "k_pairs<STEP> (+ slice finish)",
+                     "achieved": round(ach / 1e9, 1), "peak": round(peak / 1e9, 1), "unit": "Gpair/s",
+                     "frac": round(ach / peak, 4), "traffic": None,
+                     "peak_basis": f"256 CU x 64 lanes x 2.4 GHz / ({NBODY_VALU_PER_PAIR} VALU + "
+                                   f"4 x {NBODY_TRANS_PER_PAIR} transcendental) per pair"},
+        "parts": {"fwd_20_steps_ms": round(ms_fwd, 3), "reverse_ms": round(ms - ms_fwd, 3),
+                  "step_launch_us": round(parts["step"] * 1e3, 1),
+                  "adjoint_step_launch_us": round(parts["adjoint_step"] * 1e3, 1)},
+        "plain": {"fwd_20_steps_ms": round(pms, 3), "fused_speedup_fwd": round(pms / ms_fwd, 2)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("nbody: cpu baseline (oracle)")
+        x0 = pos.astype(np.float64)
+        t0 = time.perf_counter()
+        O.nbody_step(x0, vel, m, eps2, G, dt)
+        O.nbody_accel_vjp(x0, m, np.ones_like(x0), eps2, G)
+        secs = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 2 * n * n / secs, "unit": "pair-interactions/s", "cores": cpu_threads(),
+                                "kind": "oracle", "seconds": round(secs, 2),
+                                "sample": "one forward Euler step and one transposed-Jacobian product at N=16384"}
+    del g_full, g_fwd
+    return line
+
+
+# ============================================================ k-means
+def bench_kmeans(args):
+    import torch
+    import workloads as W
+    from paper_2211_00621_amd import abi, api
+    dev = torch.device("cuda:0")
+    n, d, k, iters = 1 << 20, 32, 64, 10
+    X, _, _ = W.kmeans_blobs(n, d, k, seed=0)
+    Xt = torch.from_numpy(X).to(dev)
+    Cs = [Xt[:k].clone()] + [torch.empty((k, d), device=dev) for _ in range(iters)]
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    counts = torch.empty(k, dtype=torch.int64, device=dev)
+    ws = torch.zeros(abi.mx_kmeans_workspace_bytes(n, d, k), dtype=torch.uint8, device=dev)
+    sse = torch.empty((), device=dev)
+    sse_ws = torch.zeros(256 + 4096, dtype=torch.uint8, device=dev)
+    one = torch.ones(1, device=dev)
+    G = torch.empty_like(Xt)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    def body(step_fn, stream):
+        for it in range(iters):
+            step_fn(Xt, Cs[it], labels, counts, Cs[it + 1], ws, stream=stream)
+        abi.mx_kmeans_sse_f32(Xt, Cs[iters], labels, sse, sse_ws, stream=stream)
+        abi.mx_kmeans_sse_grad_f32(Xt, Cs[iters], labels, one, G, stream=stream)
+
+    with torch.cuda.stream(side):
+        body(abi.mx_kmeans_step_f32, side)
+        side.synchronize()
+        abi.mx_graph_begin(side)
+        body(abi.mx_kmeans_step_f32, side)
+        graph = abi.mx_graph_end(side)
+    side.synchronize()
+
+    def timed_on(stream, fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        stream.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        stream.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
+    cur = torch.cuda.current_stream()
+    pms = timed_on(cur, lambda: body(abi.mx_kmeans_step_plain_f32, None), max(1, min(args.steps, 5)), 1)
+
+    def parts_step(pt):
+        m_ = pt.mark if pt else (lambda: None)
+        m_(); abi.mx_kmeans_step_f32(Xt, Cs[0], labels, counts, Cs[1], ws)
+        m_(); abi.mx_kmeans_sse_grad_f32(Xt, Cs[1], labels, one, G)
+        m_()
+    _, parts = timed(parts_step, 10, 2, ["kmeans_step", "sse_grad"])
+    log(f"kmeans: fused {ms:.3f} ms, plain {pms:.3f} ms")
+    flops_step = 2.0 * n * k * d
+    ach = flops_step / (parts["kmeans_step"] * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": iters * n * k / (ms * 1e-3), "unit": "point-centroid evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "k-means: 2^20 float32 points in d=32 from 64 Gaussian blobs, k=64, 10 steps of "
+                               "map(argmin reduce)+reduce-by-key, then SSE and its gradient wrt the points",
+                   "n": n, "d": d, "k": k, "iterations": iters},
+        "roofline": {"bound": "mfma", "kernel": "k_kmeans_fused<32,64>", "achieved": round(ach, 2),
+                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4),
+                     "traffic": None},
+        "parts": {"kmeans_step_us": round(parts["kmeans_step"] * 1e3, 1),
+                  "kmeans_step_GB/s": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]), 1),
+                  "sse_grad_us": round(parts["sse_grad"] * 1e3, 1),
+                  "sse_grad_GB/s": round(gbs(8 * n * d + 4 * n, parts["sse_grad"]), 1)},
+        "plain": {"ms_per_step": round(pms, 3), "fused_speedup": round(pms / ms, 2)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("kmeans: cpu baseline (oracle)")
+        sample = 1 << 16
+        t0 = time.perf_counter()
+        lab = O.kmeans_assign(X[:sample], X[:k])
+        O.kmeans_update(X[:sample], lab, X[:k])
+        secs = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": sample * k / secs, "unit": "point-centroid evals/s", "cores": cpu_threads(),
+                                "kind": "oracle", "seconds": round(secs, 2),
+                                "sample": "one assignment + update step over the first 2^16 of the 2^20 points"}
+    del graph
+    return line
+
+
+WORKLOADS = {"nested": bench_nested, "dot": bench_dot, "nbody": bench_nbody, "kmeans": bench_kmeans}
 
 
 def main(argv=None):

@@ -86,12 +86,11 @@ typedef enum mx_binop {
     MX_B_ADD = 0, MX_B_SUB = 1, MX_B_MUL = 2, MX_B_DIV = 3, MX_B_MIN = 4, MX_B_MAX = 5
 } mx_binop;
 
-/* Workspace kinds for mx_workspace_bytes. */
+/* Workspace kinds for mx_workspace_bytes (other entry points have their own
+ * size queries next to them). */
 typedef enum mx_ws_kind {
     MX_WS_REDUCE = 0, /* mx_reduce, mx_map2_reduce: n = sequence length */
-    MX_WS_SCAN = 1,   /* mx_lengths_to_offsets, mx_marshal_rows: n = number of rows */
-    MX_WS_KMEANS = 2, /* mx_kmeans_step: n = points, aux = k * d */
-    MX_WS_NBODY = 3   /* mx_nbody_ke_grad: n = bodies, aux = number of checkpoints */
+    MX_WS_SCAN = 1    /* mx_lengths_to_offsets, mx_marshal_rows: n = number of rows */
 } mx_ws_kind;
 
 /* ======================================================================= */
@@ -143,12 +142,14 @@ mx_status mx_lengths_to_offsets(const int64_t *lengths_dev, int64_t nseg, int64_
  * offsets are computed on the device by mx_lengths_to_offsets.
  *   rows_host[r]      host pointer to lengths_host[r] elements of elem_bytes
  *   staging_host      pinned host memory (hipHostMalloc) of at least
- *                     sum(lengths) * elem_bytes + nseg * 8 bytes, 16-byte aligned
+ *                     round_up(sum(lengths) * elem_bytes, 256) + nseg * 8 bytes
  *   values_dev        device, sum(lengths) * elem_bytes bytes
  *   lengths_dev       device int64[nseg] (receives a copy of lengths_host)
  *   offsets_dev       device int64[nseg + 1]
- * The staging buffer must stay untouched until the stream has passed this
- * call.  Workspace kind MX_WS_SCAN with n = nseg.  Errors: MX_ERR_INVALID,
+ * The call first waits for work already queued on the stream (an earlier
+ * transfer may still read the staging buffer); the staging buffer must then
+ * stay untouched until the stream has passed this call.  Workspace kind
+ * MX_WS_SCAN with n = nseg.  Errors: MX_ERR_INVALID,
  * MX_ERR_WORKSPACE, MX_ERR_HIP. */
 mx_status mx_marshal_rows(const void *const *rows_host, const int64_t *lengths_host, int64_t nseg,
                           size_t elem_bytes, void *staging_host, size_t staging_bytes,
@@ -273,6 +274,124 @@ mx_status mx_map_map_reduce_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
 mx_status mx_map_map_reduce_plain_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
                                       const float *A_dev, const float *B_dev, float *C_dev,
                                       hipStream_t stream);
+
+/* ======================================================================= */
+/* Sequential loops around map (reduce): N-body (the ODE-solver pattern of   */
+/* the paper's CUDA-backend evaluation, Table 2) and its adjoint             */
+/* ======================================================================= */
+/* Bodies are float4 records (x, y, z, m) -- the record {x, y, z, m} marshalled
+ * as one 16-byte element -- and velocities / adjoints are float4 (x, y, z, 0).
+ * All pointers are device pointers, 16-byte aligned.  Gravitational
+ * acceleration with Plummer softening eps2 > 0:
+ *   a_i = G sum_j m_j d_ij (|d_ij|^2 + eps2)^(-3/2),  d_ij = x_j - x_i,
+ * a map over bodies of a reduce over bodies (the j = i term is zero).
+ * Forward Euler: x_{t+1} = x_t + dt v_t, v_{t+1} = v_t + dt a(x_t).
+ * The pair loop is split into slices of j; slice partials are added in slice
+ * order, so results are deterministic and independent of the device.
+ * Pair entry points need a workspace of mx_nbody_pair_workspace_bytes(n). */
+size_t mx_nbody_pair_workspace_bytes(int64_t n);
+
+/* acc4[i] = (a_i, 0).  Errors: MX_ERR_INVALID, MX_ERR_SHAPE, MX_ERR_WORKSPACE. */
+mx_status mx_nbody_accel_f32(const float *pos4_dev, int64_t n, float eps2, float G, float *acc4_dev,
+                             void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* One fused Euler step (pair loop, slice sum and update).  Outputs must not
+ * alias inputs.  Errors as mx_nbody_accel_f32. */
+mx_status mx_nbody_step_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
+                            float dt, float *pos4_out_dev, float *vel4_out_dev, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* Reference "plain" form of one step: an untiled pair loop reading bodies from
+ * global memory (one thread per body, no j split) into acc4_dev, then a
+ * separate update kernel. */
+mx_status mx_nbody_step_plain_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2,
+                                  float G, float dt, float *acc4_dev, float *pos4_out_dev,
+                                  float *vel4_out_dev, hipStream_t stream);
+
+/* Transposed-Jacobian product of the acceleration map:
+ *   out_k = G sum_j M_kj (m_k abar_j - m_j abar_k),
+ *   M_kj = s^(-3/2) I - 3 s^(-5/2) d d^T,  d = x_j - x_k,  s = |d|^2 + eps2.
+ * Errors as mx_nbody_accel_f32. */
+mx_status mx_nbody_accel_vjp_f32(const float *pos4_dev, const float *abar4_dev, int64_t n, float eps2,
+                                 float G, float *out4_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* One reverse step of the discrete adjoint of the Euler step at state x_t:
+ *   xbar_t = xbar_{t+1} + dt J_a(x_t)^T vbar_{t+1},  vbar_t = vbar_{t+1} + dt xbar_{t+1}.
+ * Outputs must not alias inputs. */
+mx_status mx_nbody_adjoint_step_f32(const float *pos4_dev, const float *xbar4_dev, const float *vbar4_dev,
+                                    int64_t n, float eps2, float G, float dt, float *xbar4_out_dev,
+                                    float *vbar4_out_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Kinetic energy 1/2 sum_i m_i |v_i|^2 into one device float. */
+mx_status mx_nbody_kinetic_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float *ke_dev,
+                               hipStream_t stream);
+
+/* The loop and its reverse: runs nsteps Euler steps from (pos4, vel4), writes
+ * the final kinetic energy to ke_dev, and the gradients of that energy with
+ * respect to the initial positions (gx4) and velocities (gv4) by the reverse
+ * sweep of the discrete adjoint, storing states only every ckpt_every steps
+ * and recomputing each segment forward before its reverse sweep.  The
+ * recomputation reproduces the forward states bit for bit.  Launches only
+ * (no allocation, no host synchronisation), so the call can be captured in a
+ * HIP graph.  1 <= ckpt_every <= 64.  Workspace: mx_nbody_workspace_bytes. */
+size_t mx_nbody_workspace_bytes(int64_t n, int nsteps, int ckpt_every);
+mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
+                               float dt, int nsteps, int ckpt_every, float *ke_dev, float *gx4_dev,
+                               float *gv4_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ======================================================================= */
+/* k-means step: map (argmin-reduce) + reduce-by-key (the histo pattern of  */
+/* the paper's Parboil evaluation, Table 1)                                  */
+/* ======================================================================= */
+/* X: n x d row-major float32 points; C: k x d float32 centroids (device).
+ *   labels[i]  = the j minimising (dist(x_i, c_j), j) lexicographically, with
+ *                dist the squared Euclidean distance: bit-exact to the binary64
+ *                definition (an FP32 matrix-core filter whose error bound is
+ *                certified per point, binary64 recomputation otherwise)
+ *   counts[j]  = #{i : labels[i] = j}                      (int64, exact)
+ *   C_out[j]   = mean of the points labelled j, or C[j] when count is 0
+ * Supported sizes: 1 <= d <= 64, 1 <= k <= 256, k * d <= 4096 (and LDS needs
+ * at most 64 KiB, which holds for the configurations used here), else
+ * MX_ERR_UNSUPPORTED.  Deterministic: no float atomics.  C_out must not alias
+ * C.  Workspace: mx_kmeans_workspace_bytes(n, d, k), zero-filled once. */
+size_t mx_kmeans_workspace_bytes(int64_t n, int d, int k);
+mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *C_dev, int k,
+                             int32_t *labels_dev, int64_t *counts_dev, float *C_out_dev, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Reference "plain" form: one thread per point with distances from global
+ * memory (same certified labels), then float atomics for the sums (result
+ * order not fixed), then a divide kernel.  Same contract otherwise. */
+mx_status mx_kmeans_step_plain_f32(const float *X_dev, int64_t n, int d, const float *C_dev, int k,
+                                   int32_t *labels_dev, int64_t *counts_dev, float *C_out_dev, void *ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Within-cluster sum of squares sum_i |x_i - C[labels[i]]|^2 into one device
+ * float.  Workspace of at least 256 + 4096 bytes, 256-byte aligned. */
+mx_status mx_kmeans_sse_f32(const float *X_dev, int64_t n, int d, const float *C_dev, const int32_t *labels_dev,
+                            float *sse_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Its gradient with respect to the points (labels and centroids held fixed):
+ * G[i] = g * 2 (x_i - C[labels[i]]) with g = *gscale_dev, the upstream
+ * gradient of the SSE (device scalar). */
+mx_status mx_kmeans_sse_grad_f32(const float *X_dev, int64_t n, int d, const float *C_dev,
+                                 const int32_t *labels_dev, const float *gscale_dev, float *G_dev,
+                                 hipStream_t stream);
+
+/* ======================================================================= */
+/* HIP graphs of launch sequences (loop bodies, forward + backward passes)  */
+/* ======================================================================= */
+/* Any sequence of this library's launches on one stream can be captured once
+ * and replayed: mx_graph_begin starts capturing `stream` (which must not be the
+ * null stream), the following entry points record their kernels instead of
+ * running them, and mx_graph_end instantiates the graph.  Capture entry points
+ * that only launch (debug mode off; no marshal / unmarshal / plan creation).
+ * A replay reuses the captured pointers and sizes. */
+typedef struct mx_graph mx_graph;
+mx_status mx_graph_begin(hipStream_t stream);
+mx_status mx_graph_end(hipStream_t stream, mx_graph **graph);
+mx_status mx_graph_launch(mx_graph *graph, hipStream_t stream);
+mx_status mx_graph_destroy(mx_graph *graph);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,26 @@ SIGNATURES = {
     "mx_segmented_sum_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_p]),
     "mx_map_map_reduce_f32": (c_status, [c_int, c_int, c_i64, c_i64, c_i64, c_p, c_p, c_p, c_p]),
     "mx_map_map_reduce_plain_f32": (c_status, [c_int, c_int, c_i64, c_i64, c_i64, c_p, c_p, c_p, c_p]),
+    "mx_nbody_pair_workspace_bytes": (c_size, [c_i64]),
+    "mx_nbody_accel_f32": (c_status, [c_p, c_i64, c_f32, c_f32, c_p, c_p, c_size, c_p]),
+    "mx_nbody_step_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_p, c_p, c_p, c_size, c_p]),
+    "mx_nbody_step_plain_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_p, c_p, c_p, c_p]),
+    "mx_nbody_accel_vjp_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_p, c_p, c_size, c_p]),
+    "mx_nbody_adjoint_step_f32": (c_status, [c_p, c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_p, c_p, c_p, c_size,
+                                             c_p]),
+    "mx_nbody_kinetic_f32": (c_status, [c_p, c_p, c_i64, c_p, c_p]),
+    "mx_nbody_workspace_bytes": (c_size, [c_i64, c_int, c_int]),
+    "mx_nbody_ke_grad_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_int, c_int, c_p, c_p, c_p, c_p,
+                                        c_size, c_p]),
+    "mx_kmeans_workspace_bytes": (c_size, [c_i64, c_int, c_int]),
+    "mx_kmeans_step_f32": (c_status, [c_p, c_i64, c_int, c_p, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_kmeans_step_plain_f32": (c_status, [c_p, c_i64, c_int, c_p, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_kmeans_sse_f32": (c_status, [c_p, c_i64, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_kmeans_sse_grad_f32": (c_status, [c_p, c_i64, c_int, c_p, c_p, c_p, c_p, c_p]),
+    "mx_graph_begin": (c_status, [c_p]),
+    "mx_graph_end": (c_status, [c_p, c_pp]),
+    "mx_graph_launch": (c_status, [c_p, c_p]),
+    "mx_graph_destroy": (c_status, [c_p]),
 }
 
 _lib = None

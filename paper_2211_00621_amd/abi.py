@@ -22,7 +22,7 @@ MX_ADD, MX_MUL, MX_MIN, MX_MAX = 0, 1, 2, 3
 (MX_U_ID, MX_U_NEG, MX_U_ABS, MX_U_SQ, MX_U_AFFINE, MX_U_EXP, MX_U_LOG, MX_U_SQRT,
  MX_U_RSQRT) = range(9)
 MX_B_ADD, MX_B_SUB, MX_B_MUL, MX_B_DIV, MX_B_MIN, MX_B_MAX = range(6)
-MX_WS_REDUCE, MX_WS_SCAN, MX_WS_KMEANS, MX_WS_NBODY = 0, 1, 2, 3
+MX_WS_REDUCE, MX_WS_SCAN = 0, 1
 
 DTYPE_OF = {torch.float32: MX_F32, torch.float64: MX_F64, torch.int32: MX_I32, torch.int64: MX_I64}
 ACC_OF = {torch.float32: torch.float32, torch.float64: torch.float64, torch.int32: torch.int64,
@@ -251,3 +251,129 @@ def mx_map_map_reduce_plain_f32(ta: int, tb: int, A, B, C, stream=None) -> None:
     M, N, K = _mmr_dims(ta, tb, A, B)
     _check(_L().mx_map_map_reduce_plain_f32(int(ta), int(tb), M, N, K, _dptr(A), _dptr(B), _dptr(C),
                                             _stream(stream)), "mx_map_map_reduce_plain_f32")
+
+
+# ---------------------------------------------------------------- N-body loop
+def _n4(t):
+    """Number of float4 records in a [n, 4] float32 tensor."""
+    if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != 4:
+        raise MxError(MX_ERR_SHAPE, "expected a float32 tensor of shape [n, 4]")
+    return t.shape[0]
+
+
+def mx_nbody_pair_workspace_bytes(n: int) -> int:
+    return int(_L().mx_nbody_pair_workspace_bytes(int(n)))
+
+
+def mx_nbody_accel_f32(pos4, eps2, G, acc4, ws, stream=None) -> None:
+    _check(_L().mx_nbody_accel_f32(_dptr(pos4), _n4(pos4), eps2, G, _dptr(acc4), _dptr(ws), _nbytes(ws),
+                                   _stream(stream)), "mx_nbody_accel_f32")
+
+
+def mx_nbody_step_f32(pos4, vel4, eps2, G, dt, pos4_out, vel4_out, ws, stream=None) -> None:
+    _check(_L().mx_nbody_step_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), eps2, G, dt, _dptr(pos4_out),
+                                  _dptr(vel4_out), _dptr(ws), _nbytes(ws), _stream(stream)), "mx_nbody_step_f32")
+
+
+def mx_nbody_step_plain_f32(pos4, vel4, eps2, G, dt, acc4, pos4_out, vel4_out, stream=None) -> None:
+    _check(_L().mx_nbody_step_plain_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), eps2, G, dt, _dptr(acc4),
+                                        _dptr(pos4_out), _dptr(vel4_out), _stream(stream)),
+           "mx_nbody_step_plain_f32")
+
+
+def mx_nbody_accel_vjp_f32(pos4, abar4, eps2, G, out4, ws, stream=None) -> None:
+    _check(_L().mx_nbody_accel_vjp_f32(_dptr(pos4), _dptr(abar4), _n4(pos4), eps2, G, _dptr(out4), _dptr(ws),
+                                       _nbytes(ws), _stream(stream)), "mx_nbody_accel_vjp_f32")
+
+
+def mx_nbody_adjoint_step_f32(pos4, xbar4, vbar4, eps2, G, dt, xbar4_out, vbar4_out, ws, stream=None) -> None:
+    _check(_L().mx_nbody_adjoint_step_f32(_dptr(pos4), _dptr(xbar4), _dptr(vbar4), _n4(pos4), eps2, G, dt,
+                                          _dptr(xbar4_out), _dptr(vbar4_out), _dptr(ws), _nbytes(ws),
+                                          _stream(stream)), "mx_nbody_adjoint_step_f32")
+
+
+def mx_nbody_kinetic_f32(pos4, vel4, ke, stream=None) -> None:
+    _check(_L().mx_nbody_kinetic_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), _dptr(ke), _stream(stream)),
+           "mx_nbody_kinetic_f32")
+
+
+def mx_nbody_workspace_bytes(n: int, nsteps: int, ckpt_every: int) -> int:
+    return int(_L().mx_nbody_workspace_bytes(int(n), int(nsteps), int(ckpt_every)))
+
+
+def mx_nbody_ke_grad_f32(pos4, vel4, eps2, G, dt, nsteps, ckpt_every, ke, gx4, gv4, ws, stream=None) -> None:
+    _check(_L().mx_nbody_ke_grad_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), eps2, G, dt, int(nsteps),
+                                     int(ckpt_every), _dptr(ke), _dptr(gx4), _dptr(gv4), _dptr(ws), _nbytes(ws),
+                                     _stream(stream)), "mx_nbody_ke_grad_f32")
+
+
+# ---------------------------------------------------------------- k-means
+def _nd(X):
+    if X.dtype != torch.float32 or X.dim() != 2:
+        raise MxError(MX_ERR_SHAPE, "expected a float32 matrix [n, d]")
+    return X.shape[0], X.shape[1]
+
+
+def mx_kmeans_workspace_bytes(n: int, d: int, k: int) -> int:
+    return int(_L().mx_kmeans_workspace_bytes(int(n), int(d), int(k)))
+
+
+def mx_kmeans_step_f32(X, C, labels, counts, C_out, ws, stream=None) -> None:
+    n, d = _nd(X)
+    _check(_L().mx_kmeans_step_f32(_dptr(X), n, d, _dptr(C), C.shape[0], _dptr(labels), _dptr(counts),
+                                   _dptr(C_out), _dptr(ws), _nbytes(ws), _stream(stream)), "mx_kmeans_step_f32")
+
+
+def mx_kmeans_step_plain_f32(X, C, labels, counts, C_out, ws, stream=None) -> None:
+    n, d = _nd(X)
+    _check(_L().mx_kmeans_step_plain_f32(_dptr(X), n, d, _dptr(C), C.shape[0], _dptr(labels), _dptr(counts),
+                                         _dptr(C_out), _dptr(ws), _nbytes(ws), _stream(stream)),
+           "mx_kmeans_step_plain_f32")
+
+
+def mx_kmeans_sse_f32(X, C, labels, sse, ws, stream=None) -> None:
+    n, d = _nd(X)
+    _check(_L().mx_kmeans_sse_f32(_dptr(X), n, d, _dptr(C), _dptr(labels), _dptr(sse), _dptr(ws), _nbytes(ws),
+                                  _stream(stream)), "mx_kmeans_sse_f32")
+
+
+def mx_kmeans_sse_grad_f32(X, C, labels, gscale, G, stream=None) -> None:
+    n, d = _nd(X)
+    _check(_L().mx_kmeans_sse_grad_f32(_dptr(X), n, d, _dptr(C), _dptr(labels), _dptr(gscale), _dptr(G),
+                                       _stream(stream)), "mx_kmeans_sse_grad_f32")
+
+
+# ---------------------------------------------------------------- graphs
+class Graph:
+    """An instantiated capture of library launches (opaque mx_graph handle)."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def launch(self, stream=None) -> None:
+        mx_graph_launch(self, stream)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _L().mx_graph_destroy(self.handle)
+            self.handle = None
+
+
+def mx_graph_begin(stream=None) -> None:
+    _check(_L().mx_graph_begin(_stream(stream)), "mx_graph_begin")
+
+
+def mx_graph_end(stream=None) -> Graph:
+    h = ctypes.c_void_p()
+    _check(_L().mx_graph_end(_stream(stream), ctypes.byref(h)), "mx_graph_end")
+    return Graph(h.value)
+
+
+def mx_graph_launch(graph: Graph, stream=None) -> None:
+    _check(_L().mx_graph_launch(graph.handle, _stream(stream)), "mx_graph_launch")
+
+
+def mx_graph_destroy(graph: Graph) -> None:
+    if graph.handle:
+        _check(_L().mx_graph_destroy(graph.handle), "mx_graph_destroy")
+        graph.handle = None

@@ -212,3 +212,121 @@ def matmul(A: torch.Tensor, B: torch.Tensor, plain: bool = False) -> torch.Tenso
     C = torch.empty((A.shape[0], B.shape[1]), dtype=torch.float32, device=A.device)
     (abi.mx_map_map_reduce_plain_f32 if plain else abi.mx_map_map_reduce_f32)(0, 0, A, B, C)
     return C
+
+
+# ---------------------------------------------------------------- N-body loop
+_BYTES_WS: dict = {}
+
+
+def bytes_workspace(nbytes: int, tag: str, device=None, stream=None) -> torch.Tensor:
+    """A zero-initialised device workspace of at least nbytes for (device, stream, tag)."""
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = (device.index, abi._stream(stream), tag)
+    buf = _BYTES_WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _BYTES_WS[key] = buf
+    return buf
+
+
+def bodies(pos: torch.Tensor, mass: torch.Tensor) -> torch.Tensor:
+    """The record {x, y, z, m} of each body as one float4 row (marshalling on the device)."""
+    return fields_to_records([pos[:, 0].contiguous(), pos[:, 1].contiguous(), pos[:, 2].contiguous(),
+                              mass.contiguous()])
+
+
+def vec4(v: torch.Tensor) -> torch.Tensor:
+    out = torch.zeros((v.shape[0], 4), dtype=torch.float32, device=v.device)
+    out[:, :3] = v
+    return out
+
+
+def nbody_accel(pos4: torch.Tensor, eps2: float, G: float = 1.0) -> torch.Tensor:
+    acc = torch.empty_like(pos4)
+    ws = bytes_workspace(abi.mx_nbody_pair_workspace_bytes(pos4.shape[0]), "nbody_pair", pos4.device)
+    abi.mx_nbody_accel_f32(pos4, eps2, G, acc, ws)
+    return acc
+
+
+def nbody_step(pos4, vel4, eps2, G, dt, plain: bool = False):
+    xo, vo = torch.empty_like(pos4), torch.empty_like(vel4)
+    if plain:
+        acc = torch.empty_like(pos4)
+        abi.mx_nbody_step_plain_f32(pos4, vel4, eps2, G, dt, acc, xo, vo)
+    else:
+        ws = bytes_workspace(abi.mx_nbody_pair_workspace_bytes(pos4.shape[0]), "nbody_pair", pos4.device)
+        abi.mx_nbody_step_f32(pos4, vel4, eps2, G, dt, xo, vo, ws)
+    return xo, vo
+
+
+def nbody_accel_vjp(pos4, abar4, eps2, G=1.0):
+    out = torch.empty_like(pos4)
+    ws = bytes_workspace(abi.mx_nbody_pair_workspace_bytes(pos4.shape[0]), "nbody_pair", pos4.device)
+    abi.mx_nbody_accel_vjp_f32(pos4, abar4, eps2, G, out, ws)
+    return out
+
+
+def nbody_ke_grad(pos4, vel4, eps2, G, dt, nsteps, ckpt_every):
+    """(KE at t = nsteps, dKE/dx0 [n,4], dKE/dv0 [n,4]) with checkpointed reverse."""
+    n = pos4.shape[0]
+    ke = torch.empty((), dtype=torch.float32, device=pos4.device)
+    gx, gv = torch.empty_like(pos4), torch.empty_like(pos4)
+    ws = bytes_workspace(abi.mx_nbody_workspace_bytes(n, nsteps, ckpt_every), "nbody_loop", pos4.device)
+    abi.mx_nbody_ke_grad_f32(pos4, vel4, eps2, G, dt, nsteps, ckpt_every, ke, gx, gv, ws)
+    return ke, gx, gv
+
+
+class _NBodyKE(torch.autograd.Function):
+    """KE after an Euler loop as a differentiable function of (x0, v0)."""
+
+    @staticmethod
+    def forward(ctx, pos, vel, mass, eps2, G, dt, nsteps, ckpt_every):
+        p4 = bodies(pos, mass)
+        v4 = vec4(vel)
+        ke, gx, gv = nbody_ke_grad(p4, v4, eps2, G, dt, nsteps, ckpt_every)
+        ctx.save_for_backward(gx, gv)
+        return ke
+
+    @staticmethod
+    def backward(ctx, g):
+        gx, gv = ctx.saved_tensors
+        return (g * gx[:, :3], g * gv[:, :3], None, None, None, None, None, None)
+
+
+def nbody_kinetic_energy(pos, vel, mass, eps2, G, dt, nsteps, ckpt_every=5):
+    """KE(t = nsteps) of the Euler loop; backward runs the checkpointed reverse sweep."""
+    return _NBodyKE.apply(pos, vel, mass, eps2, G, dt, nsteps, ckpt_every)
+
+
+# ---------------------------------------------------------------- k-means
+def kmeans_step(X: torch.Tensor, C: torch.Tensor, plain: bool = False):
+    """(labels int32[n], counts int64[k], C' float32[k, d]) of one k-means step."""
+    n, d = X.shape
+    k = C.shape[0]
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    counts = torch.empty(k, dtype=torch.int64, device=X.device)
+    C_out = torch.empty_like(C)
+    ws = bytes_workspace(abi.mx_kmeans_workspace_bytes(n, d, k), "kmeans", X.device)
+    (abi.mx_kmeans_step_plain_f32 if plain else abi.mx_kmeans_step_f32)(X, C, labels, counts, C_out, ws)
+    return labels, counts, C_out
+
+
+class _KMeansSSE(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, X, C, labels):
+        ctx.save_for_backward(X, C, labels)
+        out = torch.empty((), dtype=torch.float32, device=X.device)
+        abi.mx_kmeans_sse_f32(X, C, labels, out, bytes_workspace(256 + 4096, "kmeans_sse", X.device))
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        X, C, labels = ctx.saved_tensors
+        G = torch.empty_like(X)
+        abi.mx_kmeans_sse_grad_f32(X, C, labels, g.contiguous().view(1), G)
+        return G, None, None
+
+
+def kmeans_sse(X: torch.Tensor, C: torch.Tensor, labels: torch.Tensor) -> torch.Tensor:
+    """Within-cluster sum of squares; differentiable with respect to X."""
+    return _KMeansSSE.apply(X, C, labels)

@@ -1,0 +1,592 @@
+// k-means step as map (argmin-reduce) + reduce-by-key (the histo pattern of
+// the paper's Parboil evaluation, Table 1), and the within-cluster SSE with its
+// gradient with respect to the points.
+//
+//   label_i = the j minimising (dist(x_i, c_j), j) lexicographically
+//   count_j = #{i : label_i = j},  sum_j = sum of x_i with label j
+//   c'_j = sum_j / count_j, or c_j when count_j = 0
+//
+// Assignment on the matrix cores: argmin_j dist(x, c_j) = argmin_j f_j with
+// f_j = |c_j|^2 - 2 x.c_j, the x.c_j products of 64 points x 64 centroids per
+// wave on v_mfma_f32_16x16x4_f32 (X straight from HBM into registers, C in
+// LDS).  The FP32 values f~_j satisfy |f~_j - f_j| <= E = (d + 8) u (|x| +
+// max_j |c_j|)^2 with u = 2^-24 (d products, two rounded additions per MFMA
+// step of four, the norm and the final subtraction), so when the two smallest
+// f~ differ by more than 2E the smallest is the exact, unique minimiser and
+// also the binary64 oracle's.  Otherwise (about one point in a million on
+// Gaussian blobs) the lane recomputes every distance in binary64 in the
+// oracle's operation order -- subtract, square, add, no fused multiply-add --
+// and takes the lexicographic minimum, so labels are bit-exact in all cases.
+//
+// Reduce-by-key without float atomics: each wave adds its points, one point at
+// a time with lanes = dimensions, into wave-private LDS sums in point order;
+// the block adds its waves in wave order and writes one partial per block; a
+// finish kernel adds the block partials in block order in binary64, divides
+// and writes the new centroids and the int64 counts.
+#include <algorithm>
+#include <cfloat>
+
+#include "mx_internal.h"
+
+namespace mx {
+namespace {
+
+constexpr int NT = 256;       // 4 waves
+constexpr int kWaves = NT / kWave;
+constexpr int kPtsWave = 64;  // points per wave per tile
+constexpr int kTile = kWaves * kPtsWave;
+constexpr int kTilesPerBlock = 4;
+constexpr int kPtsBlock = kTile * kTilesPerBlock;
+constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct Best {
+    float b1;
+    int i1;
+    float b2;
+};
+
+__device__ __forceinline__ Best merge(Best a, Best b) {
+    // lexicographic (value, index) minimum, and the smallest remaining value
+    const bool take_b = (b.b1 < a.b1) || (b.b1 == a.b1 && b.i1 < a.i1);
+    Best r;
+    if (take_b) {
+        r.b1 = b.b1; r.i1 = b.i1;
+        r.b2 = fminf(a.b1, b.b2);
+    } else {
+        r.b1 = a.b1; r.i1 = a.i1;
+        r.b2 = fminf(b.b1, a.b2);
+    }
+    return r;
+}
+
+template <int CTRL>
+__device__ __forceinline__ Best dpp_best(Best v) {
+    Best o;
+    o.b1 = dpp_move<CTRL, 0xF>(v.b1, v.b1);
+    o.i1 = dpp_move<CTRL, 0xF>(v.i1, v.i1);
+    o.b2 = dpp_move<CTRL, 0xF>(v.b2, v.b2);
+    return o;
+}
+
+// Merge over the 16 lanes of a DPP row; every lane of the row ends with the result.
+__device__ __forceinline__ Best row_merge(Best v) {
+    v = merge(v, dpp_best<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = merge(v, dpp_best<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = merge(v, dpp_best<0x141>(v));  // row_half_mirror
+    v = merge(v, dpp_best<0x140>(v));  // row_mirror
+    return v;
+}
+
+// binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
+__device__ __forceinline__ double dist64(const float *__restrict__ x, const float *c, int d) {
+    double acc = 0.0;
+    for (int t = 0; t < d; ++t) {
+        const double diff = __dsub_rn((double)x[t], (double)c[t]);
+        acc = __dadd_rn(acc, __dmul_rn(diff, diff));
+    }
+    return acc;
+}
+
+struct KmArgs {
+    const float *X;
+    int64_t n;
+    int d, k;
+    const float *C;
+    int32_t *labels;
+    float *part_sums;   // [nblocks][k*d]
+    int *part_counts;   // [nblocks][k]
+    unsigned long long *fallbacks;  // optional counter of binary64 recomputations
+};
+
+// DP: d padded to a multiple of 32; KP: k padded to a multiple of 64.
+template <int DP, int KP>
+__global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
+    constexpr int LDC = DP + 4;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    float *Cs = smem;                            // [KP][LDC]
+    float *cnorm = Cs + KP * LDC;                // [KP]
+    float *sums = cnorm + KP;                    // [kWaves][k*d]
+    const int kd = a.k * a.d;
+    int *counts = (int *)(sums + kWaves * kd);   // [kWaves][k]
+    float *xnorm = (float *)(counts + kWaves * a.k);  // [kWaves][64]
+    float *best1 = xnorm + kWaves * kPtsWave;
+    float *best2 = best1 + kWaves * kPtsWave;
+    int *bidx = (int *)(best2 + kWaves * kPtsWave);
+    int *lab = bidx + kWaves * kPtsWave;         // [kWaves][64]
+    __shared__ float cmax_s;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int d = a.d, k = a.k;
+
+    // centroids into LDS (zero padded), their squared norms, the largest norm
+    for (int e = tid; e < KP * LDC; e += NT) {
+        const int j = e / LDC, t = e - j * LDC;
+        Cs[e] = (j < k && t < d) ? a.C[(int64_t)j * d + t] : 0.f;
+    }
+    for (int e = tid; e < kWaves * kd; e += NT) sums[e] = 0.f;
+    for (int e = tid; e < kWaves * k; e += NT) counts[e] = 0;
+    __syncthreads();
+    if (tid < KP) {
+        float s = 0.f;
+        for (int t = 0; t < d; ++t) s += Cs[tid * LDC + t] * Cs[tid * LDC + t];
+        cnorm[tid] = tid < k ? s : INFINITY;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float m = 0.f;
+        for (int j = 0; j < k; ++j) m = fmaxf(m, cnorm[j]);
+        cmax_s = sqrtf(m);
+    }
+    __syncthreads();
+    const float cmax = cmax_s;
+    const float eps_factor = 2.0f * (float)(d + 8) * 5.9604645e-8f;  // 2 (d + 8) 2^-24
+
+    const bool vec_x = (d == DP) && ((uintptr_t)a.X % 16 == 0);
+    for (int tile = 0; tile < kTilesPerBlock; ++tile) {
+        // the exit test is block-uniform: every wave reaches the same barriers
+        if ((int64_t)blockIdx.x * kPtsBlock + (int64_t)tile * kTile >= a.n) break;
+        const int64_t p0 = (int64_t)blockIdx.x * kPtsBlock + (int64_t)tile * kTile + wave * kPtsWave;
+        // ---- A fragments: point p0 + mi*16 + l16, dims kc*32 + 8g .. +7
+        float4 xa[4][DP / 32][2];
+        float xs[4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            const int64_t p = p0 + mi * 16 + l16;
+            float s = 0.f;
+#pragma unroll
+            for (int kc = 0; kc < DP / 32; ++kc) {
+                const int t0 = kc * 32 + 8 * g;
+                if (vec_x && p < a.n) {
+                    const float4 *q = reinterpret_cast<const float4 *>(a.X + p * d + t0);
+                    xa[mi][kc][0] = q[0];
+                    xa[mi][kc][1] = q[1];
+                } else {
+                    float v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v[q] = (p < a.n && t0 + q < d) ? a.X[p * d + t0 + q] : 0.f;
+                    xa[mi][kc][0] = make_float4(v[0], v[1], v[2], v[3]);
+                    xa[mi][kc][1] = make_float4(v[4], v[5], v[6], v[7]);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float4 u = xa[mi][kc][h];
+                    s += u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w;
+                }
+            }
+            xs[mi] = s;
+        }
+        // |x|^2: add the four lane groups g (lanes l16, l16+16, l16+32, l16+48)
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            float s = xs[mi];
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            if (g == 0) xnorm[wave * kPtsWave + mi * 16 + l16] = s;
+        }
+
+        // ---- f = |c|^2 - 2 x.c over column chunks of 64 centroids
+        Best bt[4][4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bt[mi][r] = Best{INFINITY, 0x7fffffff, INFINITY};
+#pragma unroll
+        for (int cc = 0; cc < KP / 64; ++cc) {
+            v4f acc[4][4];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < DP / 32; ++kc) {
+                float4 cb[4][2];
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    const float *q = Cs + (cc * 64 + ni * 16 + l16) * LDC + kc * 32 + 8 * g;
+                    cb[ni][0] = *reinterpret_cast<const float4 *>(q);
+                    cb[ni][1] = *reinterpret_cast<const float4 *>(q + 4);
+                }
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi) {
+                        const float av = vget<float4, float>(xa[mi][kc][kk >> 2], kk & 3);
+#pragma unroll
+                        for (int ni = 0; ni < 4; ++ni) {
+                            const float bv = vget<float4, float>(cb[ni][kk >> 2], kk & 3);
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[mi][ni], 0, 0, 0);
+                        }
+                    }
+            }
+            // lane holds rows 4g + r of column l16 of each (mi, ni) block
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                const int j = cc * 64 + ni * 16 + l16;
+                const float cn = cnorm[j];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float f = cn - 2.0f * acc[mi][ni][r];
+                        bt[mi][r] = merge(bt[mi][r], Best{f, j, INFINITY});
+                    }
+            }
+        }
+        // merge over the 16 columns held by one DPP row; lane l16 == 0 publishes
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const Best b = row_merge(bt[mi][r]);
+                if (l16 == 0) {
+                    const int pt = wave * kPtsWave + mi * 16 + 4 * g + r;
+                    best1[pt] = b.b1;
+                    best2[pt] = b.b2;
+                    bidx[pt] = b.i1;
+                }
+            }
+        __syncthreads();
+        // ---- certify each label, or recompute it in binary64
+        {
+            const int64_t p = p0 + lane;
+            const int pt = wave * kPtsWave + lane;
+            int label = -1;
+            if (p < a.n) {
+                const float xn = sqrtf(xnorm[pt]) + cmax;
+                const float E = eps_factor * xn * xn;
+                if (best2[pt] - best1[pt] > 2.0f * E) {
+                    label = bidx[pt];
+                } else {
+                    const float *x = a.X + p * d;
+                    double bd = 0.0;
+                    for (int j = 0; j < k; ++j) {
+                        const double dj = dist64(x, Cs + j * LDC, d);
+                        if (label < 0 || dj < bd) { bd = dj; label = j; }
+                    }
+                    if (a.fallbacks) atomicAdd(a.fallbacks, 1ull);
+                }
+                a.labels[p] = label;
+            }
+            lab[pt] = label;
+        }
+        __syncthreads();
+        // ---- reduce-by-key into wave-private sums, point order, lanes = dims
+        float *ws = sums + wave * kd;
+        int *wc = counts + wave * k;
+        for (int q0 = 0; q0 < kPtsWave; q0 += 16) {
+            float xv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int64_t p = p0 + q0 + q;
+                xv[q] = (p < a.n && lane < d) ? a.X[p * d + lane] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int l = lab[wave * kPtsWave + q0 + q];
+                if (l >= 0) {
+                    if (lane < d) ws[l * d + lane] += xv[q];
+                    if (lane == 0) wc[l] += 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // ---- block partial: waves added in wave order
+    float *ps = a.part_sums + (int64_t)blockIdx.x * kd;
+    for (int e = tid; e < kd; e += NT) {
+        float s = sums[e];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) s += sums[w * kd + e];
+        ps[e] = s;
+    }
+    int *pc = a.part_counts + (int64_t)blockIdx.x * k;
+    for (int j = tid; j < k; j += NT) {
+        int c = counts[j];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) c += counts[w * k + j];
+        pc[j] = c;
+    }
+}
+
+// Adds the block partials in block order (binary64), divides, writes C' and counts.
+__global__ void __launch_bounds__(NT) k_kmeans_finish(const float *__restrict__ part_sums,
+                                                      const int *__restrict__ part_counts, int nblocks,
+                                                      int d, int k, const float *__restrict__ C,
+                                                      int64_t *__restrict__ counts, float *__restrict__ C_out) {
+    const int e = blockIdx.x * NT + threadIdx.x;
+    const int kd = k * d;
+    if (e >= kd) return;
+    const int j = e / d;
+    double s = 0.0;
+    int64_t c = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        s += (double)part_sums[(int64_t)b * kd + e];
+        c += part_counts[(int64_t)b * k + j];
+    }
+    C_out[e] = c > 0 ? (float)(s / (double)c) : C[e];
+    if (e == j * d) counts[j] = c;
+}
+
+// ---------------------------------------------------------------- plain form
+// assignment: one thread per point, FP32 distances read from global memory,
+// the same certification (bound for the direct form) and binary64 fallback
+__global__ void __launch_bounds__(NT) k_kmeans_assign_plain(const float *__restrict__ X, int64_t n, int d,
+                                                            const float *__restrict__ C, int k,
+                                                            int32_t *__restrict__ labels) {
+    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (p >= n) return;
+    const float *x = X + p * d;
+    float b1 = INFINITY, b2 = INFINITY;
+    int i1 = 0;
+    for (int j = 0; j < k; ++j) {
+        float s = 0.f;
+        for (int t = 0; t < d; ++t) {
+            const float diff = x[t] - C[(int64_t)j * d + t];
+            s += diff * diff;
+        }
+        if (s < b1) { b2 = b1; b1 = s; i1 = j; }
+        else if (s < b2) b2 = s;
+    }
+    // |D~ - D| <= (d + 3) u D for the direct form; certify with a factor 2
+    const float E = 2.0f * (float)(d + 3) * 5.9604645e-8f * b2;
+    int label = i1;
+    if (!(b2 - b1 > 2.0f * E)) {
+        double bd = 0.0;
+        label = -1;
+        for (int j = 0; j < k; ++j) {
+            const double dj = dist64(x, C + (int64_t)j * d, d);
+            if (label < 0 || dj < bd) { bd = dj; label = j; }
+        }
+    }
+    labels[p] = label;
+}
+
+__global__ void __launch_bounds__(NT) k_zero_words(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(NT) k_kmeans_accum_plain(const float *__restrict__ X, int64_t n, int d,
+                                                           const int32_t *__restrict__ labels,
+                                                           float *__restrict__ sums, int *__restrict__ cnt) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= n * d) return;
+    const int64_t p = e / d;
+    const int t = (int)(e - p * d);
+    const int l = labels[p];
+    atomicAdd(&sums[(int64_t)l * d + t], X[e]);
+    if (t == 0) atomicAdd(&cnt[l], 1);
+}
+
+__global__ void __launch_bounds__(NT) k_kmeans_divide_plain(const float *__restrict__ sums,
+                                                            const int *__restrict__ cnt, int d, int k,
+                                                            const float *__restrict__ C,
+                                                            int64_t *__restrict__ counts, float *__restrict__ C_out) {
+    const int e = blockIdx.x * NT + threadIdx.x;
+    if (e >= k * d) return;
+    const int j = e / d;
+    const int c = cnt[j];
+    C_out[e] = c > 0 ? sums[e] / (float)c : C[e];
+    if (e == j * d) counts[j] = c;
+}
+
+// ---------------------------------------------------------------- SSE and its gradient
+__global__ void __launch_bounds__(NT) k_sse_partial(const float *__restrict__ X, int64_t n, int d,
+                                                    const float *__restrict__ C,
+                                                    const int32_t *__restrict__ labels, float *__restrict__ part) {
+    __shared__ float red[NT / kWave];
+    float acc = 0.f;
+    const int64_t total = n * d;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+        const int64_t p = e / d;
+        const float diff = X[e] - C[(int64_t)labels[p] * d + (e - p * d)];
+        acc += diff * diff;
+    }
+    acc = block_reduce<Red<MX_ADD, float>, NT>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(NT) k_sse_final(const float *__restrict__ part, int nb, float *__restrict__ out) {
+    __shared__ double red[NT / kWave];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += NT) acc += (double)part[b];
+    acc = block_reduce<Red<MX_ADD, double>, NT>(acc, red);
+    if (threadIdx.x == 0) out[0] = (float)acc;
+}
+
+__global__ void __launch_bounds__(NT) k_sse_grad(const float *__restrict__ X, int64_t n, int d,
+                                                 const float *__restrict__ C, const int32_t *__restrict__ labels,
+                                                 const float *__restrict__ gscale, float *__restrict__ G, int vec) {
+    const float g2 = 2.0f * gscale[0];
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    if (vec) {  // d % 4 == 0, 16-byte aligned
+        const int64_t nv = n * d / 4;
+        const int dv = d / 4;
+        for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nv; i += stride) {
+            const int64_t p = i / dv;
+            const float4 x = reinterpret_cast<const float4 *>(X)[i];
+            const float4 c = reinterpret_cast<const float4 *>(C)[(int64_t)labels[p] * dv + (i - p * dv)];
+            reinterpret_cast<float4 *>(G)[i] =
+                make_float4(g2 * (x.x - c.x), g2 * (x.y - c.y), g2 * (x.z - c.z), g2 * (x.w - c.w));
+        }
+    } else {
+        for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n * d; e += stride) {
+            const int64_t p = e / d;
+            G[e] = g2 * (X[e] - C[(int64_t)labels[p] * d + (e - p * d)]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- sizes and dispatch
+int64_t fused_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kPtsBlock); }
+
+size_t fused_lds_bytes(int DP, int KP, int k, int d) {
+    return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * d * 4 + (size_t)kWaves * k * 4 +
+           (size_t)kWaves * kPtsWave * 4 * 5;
+}
+
+size_t ws_layout(int64_t n, int d, int k, size_t *sums_off, size_t *counts_off, size_t *plain_off) {
+    const int64_t nb = fused_blocks(n);
+    size_t off = kCounterBytes;
+    *sums_off = off;
+    off += align256((size_t)nb * (size_t)k * (size_t)d * 4);
+    *counts_off = off;
+    off += align256((size_t)nb * (size_t)k * 4);
+    *plain_off = off;  // plain: sums [k*d] floats then counts [k] ints
+    off += align256((size_t)k * d * 4) + align256((size_t)k * 4);
+    return off;
+}
+
+mx_status check(const char *who, const float *X, int64_t n, int d, const float *C, int k) {
+    MX_REQUIRE(n >= 0, MX_ERR_SHAPE, "%s: n < 0", who);
+    MX_REQUIRE(d >= 1 && d <= kMaxD, MX_ERR_UNSUPPORTED, "%s: need 1 <= d <= %d", who, kMaxD);
+    MX_REQUIRE(k >= 1 && k <= kMaxK && k * d <= kMaxKD, MX_ERR_UNSUPPORTED,
+               "%s: need 1 <= k <= %d and k*d <= %d", who, kMaxK, kMaxKD);
+    MX_REQUIRE(C && (n == 0 || X), MX_ERR_INVALID, "%s: null input", who);
+    return MX_OK;
+}
+
+template <int DP, int KP>
+void launch_fused(const KmArgs &a, int64_t nb, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_kmeans_fused<DP, KP>), dim3((unsigned)nb), dim3(NT), lds, s, a);
+}
+
+}  // namespace
+}  // namespace mx
+
+using namespace mx;
+
+extern "C" {
+
+size_t mx_kmeans_workspace_bytes(int64_t n, int d, int k) {
+    if (n < 0 || d < 1 || k < 1) return 0;
+    size_t so, co, po;
+    return align256(ws_layout(n, d, k, &so, &co, &po));
+}
+
+mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *C_dev, int k,
+                             int32_t *labels_dev, int64_t *counts_dev, float *C_out_dev, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    const char *who = "mx_kmeans_step_f32";
+    if (mx_status st = check(who, X_dev, n, d, C_dev, k)) return st;
+    MX_REQUIRE(counts_dev && C_out_dev && (n == 0 || labels_dev), MX_ERR_INVALID, "%s: null output", who);
+    MX_REQUIRE(C_out_dev != C_dev, MX_ERR_INVALID, "%s: C_out must not alias C", who);
+    size_t so, co, po;
+    const size_t need = align256(ws_layout(n, d, k, &so, &co, &po));
+    MX_REQUIRE(ws && ws_bytes >= need && ((uintptr_t)ws & 255) == 0, MX_ERR_WORKSPACE,
+               "%s: workspace needs %zu bytes, 256-byte aligned", who, need);
+    const int64_t nb = fused_blocks(n);
+    MX_REQUIRE(nb < (1LL << 31), MX_ERR_SHAPE, "%s: too many points", who);
+    const int DP = d <= 32 ? 32 : 64;
+    const int KP = (int)ceil_div(k, 64) * 64;
+    const size_t lds = fused_lds_bytes(DP, KP, k, d);
+    MX_REQUIRE(lds <= 65536, MX_ERR_UNSUPPORTED, "%s: k = %d, d = %d needs %zu bytes of LDS (limit 65536)", who, k,
+               d, lds);
+    KmArgs a{X_dev, n, d, k, C_dev, labels_dev, (float *)((char *)ws + so), (int *)((char *)ws + co), nullptr};
+    if (n > 0) {
+        if (DP == 32) {
+            switch (KP) {
+            case 64: launch_fused<32, 64>(a, nb, lds, stream); break;
+            case 128: launch_fused<32, 128>(a, nb, lds, stream); break;
+            case 192: launch_fused<32, 192>(a, nb, lds, stream); break;
+            default: launch_fused<32, 256>(a, nb, lds, stream); break;
+            }
+        } else {
+            switch (KP) {
+            case 64: launch_fused<64, 64>(a, nb, lds, stream); break;
+            default: launch_fused<64, 128>(a, nb, lds, stream); break;  // k*d <= 4096 bounds k to 64 at d = 64
+            }
+        }
+        if (mx_status st = last_launch(who)) return st;
+    }
+    const int kd = k * d;
+    hipLaunchKernelGGL(k_kmeans_finish, dim3((unsigned)ceil_div(kd, NT)), dim3(NT), 0, stream, a.part_sums,
+                       a.part_counts, n > 0 ? (int)nb : 0, d, k, C_dev, counts_dev, C_out_dev);
+    return last_launch(who);
+}
+
+mx_status mx_kmeans_step_plain_f32(const float *X_dev, int64_t n, int d, const float *C_dev, int k,
+                                   int32_t *labels_dev, int64_t *counts_dev, float *C_out_dev, void *ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+    const char *who = "mx_kmeans_step_plain_f32";
+    if (mx_status st = check(who, X_dev, n, d, C_dev, k)) return st;
+    MX_REQUIRE(counts_dev && C_out_dev && (n == 0 || labels_dev), MX_ERR_INVALID, "%s: null output", who);
+    size_t so, co, po;
+    const size_t need = align256(ws_layout(n, d, k, &so, &co, &po));
+    MX_REQUIRE(ws && ws_bytes >= need && ((uintptr_t)ws & 255) == 0, MX_ERR_WORKSPACE,
+               "%s: workspace needs %zu bytes, 256-byte aligned", who, need);
+    float *sums = (float *)((char *)ws + po);
+    int *cnt = (int *)((char *)sums + align256((size_t)k * d * 4));
+    const int64_t words = (int64_t)(align256((size_t)k * d * 4) + align256((size_t)k * 4)) / 4;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)ceil_div(words, NT)), dim3(NT), 0, stream, (uint32_t *)sums,
+                       words);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_kmeans_assign_plain, dim3((unsigned)ceil_div(n, NT)), dim3(NT), 0, stream, X_dev, n, d,
+                           C_dev, k, labels_dev);
+        hipLaunchKernelGGL(k_kmeans_accum_plain, dim3((unsigned)ceil_div(n * d, NT)), dim3(NT), 0, stream, X_dev, n,
+                           d, labels_dev, sums, cnt);
+    }
+    hipLaunchKernelGGL(k_kmeans_divide_plain, dim3((unsigned)ceil_div(k * d, NT)), dim3(NT), 0, stream, sums, cnt,
+                       d, k, C_dev, counts_dev, C_out_dev);
+    return last_launch(who);
+}
+
+mx_status mx_kmeans_sse_f32(const float *X_dev, int64_t n, int d, const float *C_dev, const int32_t *labels_dev,
+                            float *sse_dev, void *ws, size_t ws_bytes, hipStream_t stream) {
+    const char *who = "mx_kmeans_sse_f32";
+    MX_REQUIRE(n >= 0 && d >= 1, MX_ERR_SHAPE, "%s: bad sizes", who);
+    MX_REQUIRE(sse_dev && C_dev && (n == 0 || (X_dev && labels_dev)), MX_ERR_INVALID, "%s: null pointer", who);
+    const size_t need = kCounterBytes + align256(4 * 1024);
+    MX_REQUIRE(ws && ws_bytes >= need && ((uintptr_t)ws & 255) == 0, MX_ERR_WORKSPACE,
+               "%s: workspace needs %zu bytes, 256-byte aligned", who, need);
+    float *part = (float *)((char *)ws + kCounterBytes);
+    int nb = (int)std::min<int64_t>(1024, ceil_div(n * d > 0 ? n * d : 1, NT * 4));
+    hipLaunchKernelGGL(k_sse_partial, dim3(nb), dim3(NT), 0, stream, X_dev, n, d, C_dev, labels_dev, part);
+    hipLaunchKernelGGL(k_sse_final, dim3(1), dim3(NT), 0, stream, part, nb, sse_dev);
+    return last_launch(who);
+}
+
+mx_status mx_kmeans_sse_grad_f32(const float *X_dev, int64_t n, int d, const float *C_dev,
+                                 const int32_t *labels_dev, const float *gscale_dev, float *G_dev,
+                                 hipStream_t stream) {
+    const char *who = "mx_kmeans_sse_grad_f32";
+    MX_REQUIRE(n >= 0 && d >= 1, MX_ERR_SHAPE, "%s: bad sizes", who);
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(X_dev && C_dev && labels_dev && gscale_dev && G_dev, MX_ERR_INVALID, "%s: null pointer", who);
+    const DeviceInfo *dv;
+    if (mx_status st = device_info(&dv)) return st;
+    const int vec = (d % 4 == 0) && ((uintptr_t)X_dev % 16 == 0) && ((uintptr_t)C_dev % 16 == 0) &&
+                    ((uintptr_t)G_dev % 16 == 0);
+    const int64_t items = vec ? n * d / 4 : n * d;
+    int64_t grid = ceil_div(items, NT);
+    if (grid > (int64_t)dv->num_cus * 16) grid = (int64_t)dv->num_cus * 16;
+    hipLaunchKernelGGL(k_sse_grad, dim3((unsigned)grid), dim3(NT), 0, stream, X_dev, n, d, C_dev, labels_dev,
+                       gscale_dev, G_dev, vec);
+    return last_launch(who);
+}
+
+}  // extern "C"

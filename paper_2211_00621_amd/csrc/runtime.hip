@@ -110,19 +110,51 @@ size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux) {
         int64_t tiles = (n + 4095) / 4096 + 1;
         return kCounterBytes + align256((size_t)tiles * 8);
     }
-    case MX_WS_KMEANS: {
-        // counters + per-block partial sums (fp32, k*d) and counts (int32, k)
-        int64_t blocks = 2048;
-        int64_t kd = aux > 0 ? aux : 1;
-        return kCounterBytes + align256((size_t)blocks * (size_t)kd * 4) + align256((size_t)blocks * 256 * 4);
-    }
-    case MX_WS_NBODY: {
-        // checkpoints of (pos4, vel4), a segment tape and adjoint ping-pong buffers
-        int64_t nck = aux > 0 ? aux : 1;
-        return kCounterBytes + align256((size_t)n * 16) * (size_t)(2 * nck + 16) + align256(8 * 4096);
-    }
     }
     return 0;
+}
+
+struct mx_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+mx_status mx_graph_begin(hipStream_t stream) {
+    MX_REQUIRE(stream != nullptr, MX_ERR_INVALID, "mx_graph_begin: the null stream cannot be captured");
+    MX_REQUIRE(!debug_mode(), MX_ERR_INVALID, "mx_graph_begin: debug mode synchronises and cannot be captured");
+    MX_TRY_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    return MX_OK;
+}
+
+mx_status mx_graph_end(hipStream_t stream, mx_graph **graph) {
+    MX_REQUIRE(graph, MX_ERR_INVALID, "mx_graph_end: null output");
+    *graph = nullptr;
+    hipGraph_t g = nullptr;
+    MX_TRY_HIP(hipStreamEndCapture(stream, &g));
+    hipGraphExec_t e = nullptr;
+    hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_error(err, "hipGraphInstantiate");
+    }
+    *graph = new mx_graph{g, e};
+    return MX_OK;
+}
+
+mx_status mx_graph_launch(mx_graph *graph, hipStream_t stream) {
+    MX_REQUIRE(graph, MX_ERR_INVALID, "mx_graph_launch: null graph");
+    MX_TRY_HIP(hipGraphLaunch(graph->exec, stream));
+    return MX_OK;
+}
+
+mx_status mx_graph_destroy(mx_graph *graph) {
+    if (!graph) return MX_OK;
+    hipError_t e1 = hipGraphExecDestroy(graph->exec);
+    hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    if (e1 != hipSuccess) return hip_error(e1, "hipGraphExecDestroy");
+    if (e2 != hipSuccess) return hip_error(e2, "hipGraphDestroy");
+    return MX_OK;
 }
 
 mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t stream) {
