@@ -506,7 +506,106 @@ def bench_kmeans(args):
     return line
 
 
-WORKLOADS = {"nested": bench_nested, "dot": bench_dot, "nbody": bench_nbody, "kmeans": bench_kmeans}
+# ============================================================ batched uneven expressions
+def bench_batched(args):
+    import tempfile
+    import torch
+    import workloads as W
+    from paper_2211_00621_amd import abi, api
+    dev = torch.device("cuda:0")
+    bt = W.batched_tasks(2048, seed=0)
+    tb = bt.table()
+    A = torch.from_numpy(bt.A).to(dev)
+    B = torch.from_numpy(bt.B).to(dev)
+    g = torch.from_numpy(bt.gout).to(dev)
+    out = torch.empty(bt.out_len, device=dev)
+    gA = torch.empty_like(A)
+    gB = torch.empty_like(B)
+    batch = api.Batch(tb, device=dev)
+    cache = os.environ.get("MX_TUNE_CACHE") or os.path.join(tempfile.gettempdir(), "mx_batch_tune.jsonl")
+    log("batched: autotune")
+    chosen = batch.autotune(A, B, out, g, gA, gB, cache_path=cache)
+    log(f"batched: chosen tile_elems={chosen[0]} blocks_per_cu={chosen[1]}")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        batch.forward(A, B, out, stream=side)
+        batch.backward(A, B, g, gA, gB, stream=side)
+        side.synchronize()
+        abi.mx_graph_begin(side)
+        batch.forward(A, B, out, stream=side)
+        batch.backward(A, B, g, gA, gB, stream=side)
+        graph = abi.mx_graph_end(side)
+    side.synchronize()
+
+    def timed_on(stream, fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        stream.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        stream.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
+    cur = torch.cuda.current_stream()
+
+    def plain():
+        batch.forward(A, B, out, plain=True)
+        batch.backward(A, B, g, gA, gB, plain=True)
+    pms = timed_on(cur, plain, max(1, min(args.steps, 5)), 1)
+
+    def parts_step(pt):
+        m_ = pt.mark if pt else (lambda: None)
+        m_(); batch.forward(A, B, out)
+        m_(); batch.backward(A, B, g, gA, gB)
+        m_()
+    _, parts = timed(parts_step, 10, 2, ["forward", "backward"])
+    log(f"batched: graph {ms:.3f} ms, plain {pms:.3f} ms")
+
+    rows, cols, kind = bt.rows, bt.cols, bt.kind
+    elems = int((rows * cols).sum())
+    dot = kind == W.TASK_DOT
+    fwd_bytes = int((8 * cols[dot]).sum() + (4 * rows[~dot] * cols[~dot] + 4 * cols[~dot] + 4 * rows[~dot]).sum())
+    bwd_bytes = int((16 * cols[dot] + 4).sum()
+                    + (8 * rows[~dot] * cols[~dot] + 8 * cols[~dot] + 4 * rows[~dot]).sum())
+    ach = gbs(bwd_bytes, parts["backward"])
+    line = {
+        "metric": METRIC, "value": 2 * elems / (ms * 1e-3), "unit": "elem/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched uneven: 2048 dot/matvec expressions, sizes log-uniform 1e2..1e6, "
+                               "forward + backward, autotuned persistent launches in a HIP graph",
+                   "tasks": 2048, "elements": elems, "tile_elems": chosen[0], "blocks_per_cu": chosen[1]},
+        "roofline": {"bound": "hbm", "kernel": "k_batch_bwd (+ combine)", "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+        "parts": {"forward_us": round(parts["forward"] * 1e3, 1),
+                  "forward_GB/s": round(gbs(fwd_bytes, parts["forward"]), 1),
+                  "backward_us": round(parts["backward"] * 1e3, 1), "backward_GB/s": round(ach, 1)},
+        "plain": {"ms_per_step": round(pms, 3), "batched_speedup": round(pms / ms, 2)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("batched: cpu baseline (oracle)")
+        sample = 512
+        t0 = time.perf_counter()
+        O.batch_forward(tb[:sample], bt.A, bt.B, bt.out_len)
+        O.batch_backward(tb[:sample], bt.A, bt.B, bt.gout)
+        secs = time.perf_counter() - t0
+        se = int((rows[:sample] * cols[:sample]).sum())
+        line["cpu_baseline"] = {"value": 2 * se / secs, "unit": "elem/s", "cores": cpu_threads(), "kind": "oracle",
+                                "seconds": round(secs, 2),
+                                "sample": f"forward + backward of the first {sample} of the 2048 tasks"}
+    del graph
+    return line
+
+
+WORKLOADS = {"nested": bench_nested, "dot": bench_dot, "nbody": bench_nbody, "kmeans": bench_kmeans,
+             "batched": bench_batched}
 
 
 def main(argv=None):

@@ -359,6 +359,11 @@ mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *
                              int32_t *labels_dev, int64_t *counts_dev, float *C_out_dev, void *ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* Debug mode only: the number of points whose label the last
+ * mx_kmeans_step_f32 call (in debug mode) recomputed in binary64 because the
+ * FP32 margin was not certified; -1 before any such call. */
+int64_t mx_kmeans_debug_fallbacks(void);
+
 /* Reference "plain" form: one thread per point with distances from global
  * memory (same certified labels), then float atomics for the sums (result
  * order not fixed), then a divide kernel.  Same contract otherwise. */
@@ -377,6 +382,67 @@ mx_status mx_kmeans_sse_f32(const float *X_dev, int64_t n, int d, const float *C
 mx_status mx_kmeans_sse_grad_f32(const float *X_dev, int64_t n, int d, const float *C_dev,
                                  const int32_t *labels_dev, const float *gscale_dev, float *G_dev,
                                  hipStream_t stream);
+
+/* ======================================================================= */
+/* Batches of uneven independent expressions in one persistent launch       */
+/* ======================================================================= */
+/* The paper observes that acceleration pays off when work is concentrated in
+ * few `accelerate` uses and that small problems leave the GPU idle (Section
+ * 5.2).  A batch evaluates many small independent expressions together.
+ * Task table (host, int64, one row of 6 per task):
+ *   (kind, rows, cols, a_off, b_off, out_off)
+ *   kind 0, dot:    out[out_off] = sum_i A[a_off + i] * B[b_off + i], i < cols
+ *                   (rows must be 1)
+ *   kind 1, matvec: out[out_off + r] = sum_c A[a_off + r*cols + c] * B[b_off + c]
+ * over three float32 device pools A, B and out.  Tasks may not overlap in
+ * their outputs.  Reverse (upstream gradient gout shaped like out):
+ *   dot:    gA[a_off + i] = g * B[b_off + i], gB[b_off + i] = g * A[a_off + i]
+ *   matvec: gA[a_off + r*cols + c] = g[r] * B[b_off + c],
+ *           gB[b_off + c] = sum_r A[a_off + r*cols + c] * g[r].
+ * A plan cuts tasks into tiles of about tile_elems elements, longest first;
+ * forward and backward each run as one persistent launch (blocks_per_cu blocks
+ * per compute unit pulling tiles with an atomic ticket) plus one combine
+ * launch that adds multi-tile partials in tile order.  Results are
+ * deterministic for a given configuration. */
+typedef struct mx_batch_config {
+    int32_t tile_elems;     /* >= 4096; default 16384 */
+    int32_t blocks_per_cu;  /* 1 .. 32; default 8 */
+    int32_t reserved[2];
+} mx_batch_config;
+typedef struct mx_batch_plan mx_batch_plan;
+
+/* Builds a plan (host work plus small device tables: the documented
+ * allocation outside the launch path).  cfg may be NULL for defaults.
+ * Errors: MX_ERR_INVALID, MX_ERR_SHAPE (bad task row), MX_ERR_HIP. */
+mx_status mx_batch_plan_create(const int64_t *table_host, int64_t ntasks, const mx_batch_config *cfg,
+                               mx_batch_plan **plan);
+mx_status mx_batch_plan_destroy(mx_batch_plan *plan);
+
+/* Workspace for forward, backward and autotuning with any configuration. */
+size_t mx_batch_workspace_bytes(const mx_batch_plan *plan);
+mx_status mx_batch_get_config(const mx_batch_plan *plan, mx_batch_config *cfg);
+mx_status mx_batch_set_config(mx_batch_plan *plan, const mx_batch_config *cfg);
+
+mx_status mx_batch_forward(const mx_batch_plan *plan, const float *A_dev, const float *B_dev, float *out_dev,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
+mx_status mx_batch_backward(const mx_batch_plan *plan, const float *A_dev, const float *B_dev, const float *gout_dev,
+                            float *gA_dev, float *gB_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Reference "plain" forms: one launch per task. */
+mx_status mx_batch_forward_plain(const mx_batch_plan *plan, const float *A_dev, const float *B_dev, float *out_dev,
+                                 hipStream_t stream);
+mx_status mx_batch_backward_plain(const mx_batch_plan *plan, const float *A_dev, const float *B_dev,
+                                  const float *gout_dev, float *gA_dev, float *gB_dev, hipStream_t stream);
+
+/* Picks tile_elems in {4096 .. 65536} and blocks_per_cu in {2, 4, 8, 16} by
+ * timing forward + backward on the given buffers (which it overwrites), and
+ * sets it on the plan.  If cache_path (may be NULL) names a JSON-lines file
+ * holding an entry for this task shape and device, that entry is used without
+ * timing; otherwise the choice is appended to it.  Synchronises the stream.
+ * The chosen configuration is returned in *chosen (may be NULL). */
+mx_status mx_batch_autotune(mx_batch_plan *plan, const float *A_dev, const float *B_dev, float *out_dev,
+                            const float *gout_dev, float *gA_dev, float *gB_dev, void *ws, size_t ws_bytes,
+                            const char *cache_path, hipStream_t stream, mx_batch_config *chosen);
 
 /* ======================================================================= */
 /* HIP graphs of launch sequences (loop bodies, forward + backward passes)  */

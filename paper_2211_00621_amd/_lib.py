@@ -58,9 +58,20 @@ SIGNATURES = {
                                         c_size, c_p]),
     "mx_kmeans_workspace_bytes": (c_size, [c_i64, c_int, c_int]),
     "mx_kmeans_step_f32": (c_status, [c_p, c_i64, c_int, c_p, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_kmeans_debug_fallbacks": (c_i64, []),
     "mx_kmeans_step_plain_f32": (c_status, [c_p, c_i64, c_int, c_p, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
     "mx_kmeans_sse_f32": (c_status, [c_p, c_i64, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
     "mx_kmeans_sse_grad_f32": (c_status, [c_p, c_i64, c_int, c_p, c_p, c_p, c_p, c_p]),
+    "mx_batch_plan_create": (c_status, [c_p, c_i64, c_p, c_pp]),
+    "mx_batch_plan_destroy": (c_status, [c_p]),
+    "mx_batch_workspace_bytes": (c_size, [c_p]),
+    "mx_batch_get_config": (c_status, [c_p, c_p]),
+    "mx_batch_set_config": (c_status, [c_p, c_p]),
+    "mx_batch_forward": (c_status, [c_p, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_batch_backward": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_batch_forward_plain": (c_status, [c_p, c_p, c_p, c_p, c_p]),
+    "mx_batch_backward_plain": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "mx_batch_autotune": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_size, ctypes.c_char_p, c_p, c_p]),
     "mx_graph_begin": (c_status, [c_p]),
     "mx_graph_end": (c_status, [c_p, c_pp]),
     "mx_graph_launch": (c_status, [c_p, c_p]),
@@ -76,7 +87,7 @@ def load() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2211_00621_amd.build` "
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2211_00621_amd/build.py` "
                           "(the primitives have no CPU fallback)")
     try:
         lib = ctypes.CDLL(LIB_PATH)

@@ -324,6 +324,10 @@ def mx_kmeans_step_f32(X, C, labels, counts, C_out, ws, stream=None) -> None:
                                    _dptr(C_out), _dptr(ws), _nbytes(ws), _stream(stream)), "mx_kmeans_step_f32")
 
 
+def mx_kmeans_debug_fallbacks() -> int:
+    return int(_L().mx_kmeans_debug_fallbacks())
+
+
 def mx_kmeans_step_plain_f32(X, C, labels, counts, C_out, ws, stream=None) -> None:
     n, d = _nd(X)
     _check(_L().mx_kmeans_step_plain_f32(_dptr(X), n, d, _dptr(C), C.shape[0], _dptr(labels), _dptr(counts),
@@ -341,6 +345,84 @@ def mx_kmeans_sse_grad_f32(X, C, labels, gscale, G, stream=None) -> None:
     n, d = _nd(X)
     _check(_L().mx_kmeans_sse_grad_f32(_dptr(X), n, d, _dptr(C), _dptr(labels), _dptr(gscale), _dptr(G),
                                        _stream(stream)), "mx_kmeans_sse_grad_f32")
+
+
+# ---------------------------------------------------------------- batches
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("tile_elems", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class BatchPlan:
+    """Owns an mx_batch_plan handle."""
+
+    def __init__(self, handle: int, ntasks: int):
+        self.handle = handle
+        self.ntasks = ntasks
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _L().mx_batch_plan_destroy(self.handle)
+            self.handle = None
+
+
+def mx_batch_plan_create(table: np.ndarray, cfg: tuple | None = None) -> BatchPlan:
+    tb = np.ascontiguousarray(table, dtype=np.int64).reshape(-1, 6)
+    h = ctypes.c_void_p()
+    c = BatchConfig(cfg[0], cfg[1]) if cfg else None
+    _check(_L().mx_batch_plan_create(tb.ctypes.data, tb.shape[0], ctypes.byref(c) if c else None,
+                                     ctypes.byref(h)), "mx_batch_plan_create")
+    return BatchPlan(h.value, tb.shape[0])
+
+
+def mx_batch_plan_destroy(plan: BatchPlan) -> None:
+    if plan.handle:
+        _check(_L().mx_batch_plan_destroy(plan.handle), "mx_batch_plan_destroy")
+        plan.handle = None
+
+
+def mx_batch_workspace_bytes(plan: BatchPlan) -> int:
+    return int(_L().mx_batch_workspace_bytes(plan.handle))
+
+
+def mx_batch_get_config(plan: BatchPlan) -> tuple:
+    c = BatchConfig()
+    _check(_L().mx_batch_get_config(plan.handle, ctypes.byref(c)), "mx_batch_get_config")
+    return (c.tile_elems, c.blocks_per_cu)
+
+
+def mx_batch_set_config(plan: BatchPlan, cfg: tuple) -> None:
+    c = BatchConfig(cfg[0], cfg[1])
+    _check(_L().mx_batch_set_config(plan.handle, ctypes.byref(c)), "mx_batch_set_config")
+
+
+def mx_batch_forward(plan: BatchPlan, A, B, out, ws, stream=None) -> None:
+    _check(_L().mx_batch_forward(plan.handle, _dptr(A), _dptr(B), _dptr(out), _dptr(ws), _nbytes(ws),
+                                 _stream(stream)), "mx_batch_forward")
+
+
+def mx_batch_backward(plan: BatchPlan, A, B, gout, gA, gB, ws, stream=None) -> None:
+    _check(_L().mx_batch_backward(plan.handle, _dptr(A), _dptr(B), _dptr(gout), _dptr(gA), _dptr(gB), _dptr(ws),
+                                  _nbytes(ws), _stream(stream)), "mx_batch_backward")
+
+
+def mx_batch_forward_plain(plan: BatchPlan, A, B, out, stream=None) -> None:
+    _check(_L().mx_batch_forward_plain(plan.handle, _dptr(A), _dptr(B), _dptr(out), _stream(stream)),
+           "mx_batch_forward_plain")
+
+
+def mx_batch_backward_plain(plan: BatchPlan, A, B, gout, gA, gB, stream=None) -> None:
+    _check(_L().mx_batch_backward_plain(plan.handle, _dptr(A), _dptr(B), _dptr(gout), _dptr(gA), _dptr(gB),
+                                        _stream(stream)), "mx_batch_backward_plain")
+
+
+def mx_batch_autotune(plan: BatchPlan, A, B, out, gout, gA, gB, ws, cache_path: str | None = None,
+                      stream=None) -> tuple:
+    c = BatchConfig()
+    _check(_L().mx_batch_autotune(plan.handle, _dptr(A), _dptr(B), _dptr(out), _dptr(gout), _dptr(gA), _dptr(gB),
+                                  _dptr(ws), _nbytes(ws), cache_path.encode() if cache_path else None,
+                                  _stream(stream), ctypes.byref(c)), "mx_batch_autotune")
+    return (c.tile_elems, c.blocks_per_cu)
 
 
 # ---------------------------------------------------------------- graphs

@@ -330,3 +330,34 @@ class _KMeansSSE(torch.autograd.Function):
 def kmeans_sse(X: torch.Tensor, C: torch.Tensor, labels: torch.Tensor) -> torch.Tensor:
     """Within-cluster sum of squares; differentiable with respect to X."""
     return _KMeansSSE.apply(X, C, labels)
+
+
+# ---------------------------------------------------------------- batches
+class Batch:
+    """A plan for many uneven dot / matvec expressions and its workspace."""
+
+    def __init__(self, table, cfg=None, device=None):
+        self.plan = abi.mx_batch_plan_create(np.asarray(table), cfg)
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.ws = torch.zeros(max(abi.mx_batch_workspace_bytes(self.plan), 256), dtype=torch.uint8, device=device)
+
+    @property
+    def config(self):
+        return abi.mx_batch_get_config(self.plan)
+
+    def forward(self, A, B, out, plain=False, stream=None):
+        if plain:
+            abi.mx_batch_forward_plain(self.plan, A, B, out, stream)
+        else:
+            abi.mx_batch_forward(self.plan, A, B, out, self.ws, stream)
+        return out
+
+    def backward(self, A, B, gout, gA, gB, plain=False, stream=None):
+        if plain:
+            abi.mx_batch_backward_plain(self.plan, A, B, gout, gA, gB, stream)
+        else:
+            abi.mx_batch_backward(self.plan, A, B, gout, gA, gB, self.ws, stream)
+        return gA, gB
+
+    def autotune(self, A, B, out, gout, gA, gB, cache_path=None, stream=None):
+        return abi.mx_batch_autotune(self.plan, A, B, out, gout, gA, gB, self.ws, cache_path, stream)

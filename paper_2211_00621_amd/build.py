@@ -1,8 +1,9 @@
 """Builds libmx.so (the HIP library behind include/mx.h) in-tree for gfx950.
 
 Every ``csrc/*.hip`` file is compiled with hipcc in parallel into ``_build/`` and
-linked into ``paper_2211_00621_amd/libmx.so``.  Run ``python -m
-paper_2211_00621_amd.build`` or call ``build()``.
+linked into ``paper_2211_00621_amd/libmx.so``.  Run it as a script,
+``python paper_2211_00621_amd/build.py`` (running it as a module of the package
+would first load the library being rebuilt), or call ``build()``.
 """
 from __future__ import annotations
 

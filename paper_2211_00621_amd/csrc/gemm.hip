@@ -1,30 +1,36 @@
 // Dense nested map (map (reduce (+) 0 (map2 (*) row col))): FP32 matrix
 // product on the CDNA matrix cores (v_mfma_f32_16x16x4_f32), FP32 accumulate.
 //
-// Block tile 128 x 128, K-slice 32, 256 threads = 4 waves in a 2 x 2 grid,
-// each wave owning a 64 x 64 sub-tile as 4 x 4 MFMA blocks of 16 x 16 (64
-// accumulator registers per lane).  Both operand tiles live in LDS with k
-// contiguous ([row][k], row stride 36 floats), double-buffered with one
-// barrier per K-slice; the next slice's global loads are issued before the
+// A block owns a BM x BN tile of C and walks K in slices of 32; its waves form
+// a WM x WN grid, each owning a (BM/WM) x (BN/WN) sub-tile of 16 x 16 MFMA
+// blocks.  Each operand slice is staged in LDS in the orientation it has in
+// memory -- [row][k] (row stride 36 floats) when k is contiguous, [k][row]
+// (row stride BM + 16) when rows are contiguous -- so every global load is a
+// 16-byte vector and every LDS store a 16-byte store.  Two LDS buffers, one
+// barrier per slice; the next slice's global loads are issued before the
 // current slice's MFMAs.
 //
-// The reduction over k is associative, so the k values of a slice may be
-// dealt to the MFMA steps in any order as long as A and B agree: lane group
-// g = lane / 16 takes k = 8g .. 8g+7 for steps 0 .. 7, which makes each lane's
-// eight A (and B) values contiguous in LDS and readable with two 16-byte loads.
+// MFMA step s of a slice takes k = 4s + g in lane group g = lane / 16, which
+// reads both layouts without LDS bank conflicts (the strides are 4 and 16
+// banks apart).  The reduction over k is associative, so when both operands
+// are [row][k] the slice's k values are instead dealt as k = 8g + s, making
+// each lane's eight values contiguous (two 16-byte LDS reads per fragment).
+#include <cstdlib>
+#include <cstring>
+
 #include "mx_internal.h"
 
 namespace mx {
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 32, NT = 256;
-constexpr int LDK = BK + 4;  // LDS row stride in floats ([row][k] tiles)
+constexpr int BK = 32;
+constexpr int LDK = BK + 4;  // [row][k] stride in floats
 constexpr int kGroupM = 4;   // tile rows per scheduling group
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Element (r, c) of a row-major R x C matrix with leading dimension ld, as
-// a float4 of columns c .. c+3, zero outside the matrix.
+// Element (r, c..c+3) of a row-major R x C matrix with leading dimension ld
+// as a float4, zero outside the matrix.
 __device__ __forceinline__ float4 ld4(const float *__restrict__ p, int64_t ld, int64_t r, int64_t c,
                                       int64_t R, int64_t C, bool fast) {
     if (fast) return *reinterpret_cast<const float4 *>(p + r * ld + c);
@@ -39,42 +45,54 @@ __device__ __forceinline__ float4 ld4(const float *__restrict__ p, int64_t ld, i
     return v;
 }
 
-// Loads one K-slice of an operand into 4 float4 registers per thread.
-// ROWK: the operand is stored [row][k] (k contiguous) -- A with ta = 0, B with
-// tb = 1; otherwise it is stored [k][row] (row contiguous).
-template <bool ROWK>
-__device__ __forceinline__ void load_slice(float4 (&r)[4], const float *__restrict__ p, int64_t ld,
-                                           int64_t row0, int64_t k0, int64_t rows, int64_t K,
+template <int ROWS, bool ROWK> struct Operand {
+    static constexpr int LD = ROWK ? LDK : ROWS + 16;             // LDS stride in floats
+    static constexpr int FLOATS = ROWK ? ROWS * LDK : BK * (ROWS + 16);
+};
+
+// One K-slice of an operand (ROWS rows) into registers, NT threads.
+template <int ROWS, bool ROWK, int NT>
+__device__ __forceinline__ void load_slice(float4 (&r)[ROWS * BK / 4 / NT], const float *__restrict__ p,
+                                           int64_t ld, int64_t row0, int64_t k0, int64_t rows, int64_t K,
                                            bool fast) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < ROWS * BK / 4 / NT; ++i) {
         const int idx = threadIdx.x + NT * i;
         if constexpr (ROWK) {
-            const int row = idx >> 3, kq = idx & 7;  // 128 rows x 8 quads of k
+            const int row = idx >> 3, kq = idx & 7;  // rows x 8 quads of k
             r[i] = ld4(p, ld, row0 + row, k0 + 4 * kq, rows, K, fast);
         } else {
-            const int k = idx >> 5, rq = idx & 31;  // 32 k x 32 quads of rows
+            constexpr int Q = ROWS / 4;  // quads of rows per k
+            const int k = idx / Q, rq = idx % Q;
             r[i] = ld4(p, ld, k0 + k, row0 + 4 * rq, K, rows, fast);
         }
     }
 }
 
-template <bool ROWK>
-__device__ __forceinline__ void store_slice(float *__restrict__ s, const float4 (&r)[4]) {
+template <int ROWS, bool ROWK, int NT>
+__device__ __forceinline__ void store_slice(float *__restrict__ s, const float4 (&r)[ROWS * BK / 4 / NT]) {
+    using Op = Operand<ROWS, ROWK>;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < ROWS * BK / 4 / NT; ++i) {
         const int idx = threadIdx.x + NT * i;
         if constexpr (ROWK) {
             const int row = idx >> 3, kq = idx & 7;
-            *reinterpret_cast<float4 *>(s + row * LDK + 4 * kq) = r[i];
+            *reinterpret_cast<float4 *>(s + row * Op::LD + 4 * kq) = r[i];
         } else {
-            const int k = idx >> 5, rq = idx & 31;
-            s[(4 * rq + 0) * LDK + k] = r[i].x;
-            s[(4 * rq + 1) * LDK + k] = r[i].y;
-            s[(4 * rq + 2) * LDK + k] = r[i].z;
-            s[(4 * rq + 3) * LDK + k] = r[i].w;
+            constexpr int Q = ROWS / 4;
+            const int k = idx / Q, rq = idx % Q;
+            *reinterpret_cast<float4 *>(s + k * Op::LD + 4 * rq) = r[i];
         }
     }
+}
+
+// Value for MFMA step `step` of a slice, row `row` of the operand tile.
+template <int ROWS, bool ROWK, bool PERM>
+__device__ __forceinline__ float frag(const float *__restrict__ s, int row, int g, int step) {
+    using Op = Operand<ROWS, ROWK>;
+    if constexpr (PERM) return s[row * Op::LD + 8 * g + step];
+    else if constexpr (ROWK) return s[row * Op::LD + 4 * step + g];
+    else return s[(4 * step + g) * Op::LD + row];
 }
 
 // Tile scheduling: consecutive blocks land on different XCDs (round robin over
@@ -86,97 +104,95 @@ __device__ __forceinline__ void tile_of(int b, int tiles_m, int tiles_n, int &tm
     int L = b;
     if ((nt & 7) == 0) L = (b & 7) * (nt >> 3) + (b >> 3);
     const int per_group = kGroupM * tiles_n;
-    const int g = L / per_group;
-    const int first_m = g * kGroupM;
+    const int gi = L / per_group;
+    const int first_m = gi * kGroupM;
     const int gm = min(tiles_m - first_m, kGroupM);
-    const int in = L - g * per_group;
+    const int in = L - gi * per_group;
     tm = first_m + in % gm;
     tn = in / gm;
 }
 
-template <int TA, int TB>
-__global__ void __launch_bounds__(NT) k_gemm_mfma(const float *__restrict__ A,
-                                                  const float *__restrict__ B, float *__restrict__ C,
-                                                  int64_t M, int64_t N, int64_t K, int tiles_m,
-                                                  int tiles_n, int vec_ok) {
-    __shared__ __attribute__((aligned(16))) float As[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) float Bs[2][BN * LDK];
+template <int BM, int BN, int WM, int WN, int TA, int TB>
+__global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restrict__ A, const float *__restrict__ B,
+                                                            float *__restrict__ C, int64_t M, int64_t N, int64_t K,
+                                                            int tiles_m, int tiles_n, int vec_ok) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr bool RA = !TA, RB = TB;  // [row][k] in memory
+    constexpr bool PERM = RA && RB;
+    constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
+    using OA = Operand<BM, RA>;
+    using OB = Operand<BN, RB>;
+    __shared__ __attribute__((aligned(16))) float As[2][OA::FLOATS];
+    __shared__ __attribute__((aligned(16))) float Bs[2][OB::FLOATS];
 
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
     const int l16 = lane & 15, g = lane >> 4;
-
     const int64_t lda = TA ? M : K;
     const int64_t ldb = TB ? K : N;
     const bool interior = vec_ok && (m0 + BM <= M) && (n0 + BN <= N);
     const int nk = (int)((K + BK - 1) / BK);
 
-    v4f acc[4][4];
+    v4f acc[MI][NI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    float4 ra[4], rb[4];
+    float4 ra[BM * BK / 4 / NT], rb[BN * BK / 4 / NT];
     {
         const bool fast = interior && (BK <= K);
-        load_slice<!TA>(ra, A, lda, m0, 0, M, K, fast);
-        load_slice<(bool)TB>(rb, B, ldb, n0, 0, N, K, fast);
-        store_slice<!TA>(As[0], ra);
-        store_slice<(bool)TB>(Bs[0], rb);
+        load_slice<BM, RA, NT>(ra, A, lda, m0, 0, M, K, fast);
+        load_slice<BN, RB, NT>(rb, B, ldb, n0, 0, N, K, fast);
+        store_slice<BM, RA, NT>(As[0], ra);
+        store_slice<BN, RB, NT>(Bs[0], rb);
     }
     __syncthreads();
 
+    const int arow = wm * (BM / WM) + l16, brow = wn * (BN / WN) + l16;
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) {
             const int64_t k0 = (int64_t)(kt + 1) * BK;
             const bool fast = interior && (k0 + BK <= K);
-            load_slice<!TA>(ra, A, lda, m0, k0, M, K, fast);
-            load_slice<(bool)TB>(rb, B, ldb, n0, k0, N, K, fast);
+            load_slice<BM, RA, NT>(ra, A, lda, m0, k0, M, K, fast);
+            load_slice<BN, RB, NT>(rb, B, ldb, n0, k0, N, K, fast);
         }
-        const float *as = As[buf] + (wm * 64 + l16) * LDK + 8 * g;
-        const float *bs = Bs[buf] + (wn * 64 + l16) * LDK + 8 * g;
-        float4 a0[4], a1[4], b0[4], b1[4];
+        const float *as = As[buf];
+        const float *bs = Bs[buf];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            a0[i] = *reinterpret_cast<const float4 *>(as + i * 16 * LDK);
-            a1[i] = *reinterpret_cast<const float4 *>(as + i * 16 * LDK + 4);
-            b0[i] = *reinterpret_cast<const float4 *>(bs + i * 16 * LDK);
-            b1[i] = *reinterpret_cast<const float4 *>(bs + i * 16 * LDK + 4);
-        }
+        for (int step = 0; step < 8; ++step) {
+            float av[MI], bv[NI];
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
+            for (int i = 0; i < MI; ++i) av[i] = frag<BM, RA, PERM>(as, arow + 16 * i, g, step);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float av = kk < 4 ? vget<float4, float>(a0[i], kk) : vget<float4, float>(a1[i], kk - 4);
+            for (int j = 0; j < NI; ++j) bv[j] = frag<BN, RB, PERM>(bs, brow + 16 * j, g, step);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float bv = kk < 4 ? vget<float4, float>(b0[j], kk) : vget<float4, float>(b1[j], kk - 4);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
-                }
-            }
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int j = 0; j < NI; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
         if (more) {
-            store_slice<!TA>(As[buf ^ 1], ra);
-            store_slice<(bool)TB>(Bs[buf ^ 1], rb);
+            store_slice<BM, RA, NT>(As[buf ^ 1], ra);
+            store_slice<BN, RB, NT>(Bs[buf ^ 1], rb);
         }
         __syncthreads();
     }
 
     // D block (i, j): lane holds rows 4g .. 4g+3 of column l16
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < MI; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t col = n0 + wn * 64 + j * 16 + l16;
+        for (int j = 0; j < NI; ++j) {
+            const int64_t col = n0 + wn * (BN / WN) + j * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * 64 + i * 16 + 4 * g + r;
+                const int64_t row = m0 + wm * (BM / WM) + i * 16 + 4 * g + r;
                 if (interior || (row < M && col < N)) C[row * N + col] = acc[i][j][r];
             }
         }
@@ -211,6 +227,37 @@ mx_status check(const char *who, int ta, int tb, int64_t M, int64_t N, int64_t K
     return MX_OK;
 }
 
+// Tile shape: 128 x 128 with 4 waves, or 128 x 64 with 4 waves when that
+// still gives at most one tile per CU (two blocks per CU hide each other's
+// barriers); MX_GEMM_TILE=128x128|128x64 in the environment forces one.
+template <int BM, int BN, int WM, int WN>
+mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A, const float *B, float *C,
+                      int vec_ok, hipStream_t s) {
+    const int64_t tiles_m = ceil_div(M, BM), tiles_n = ceil_div(N, BN);
+    MX_REQUIRE(tiles_m * tiles_n < (1LL << 31), MX_ERR_SHAPE, "mx_map_map_reduce_f32: too many tiles");
+    const dim3 grid((unsigned)(tiles_m * tiles_n)), block(64 * WM * WN);
+#define MX_GEMM(TA, TB)                                                                                    \
+    hipLaunchKernelGGL((k_gemm_mfma<BM, BN, WM, WN, TA, TB>), grid, block, 0, s, A, B, C, M, N, K, (int)tiles_m, \
+                       (int)tiles_n, vec_ok)
+    if (!ta && !tb) MX_GEMM(0, 0);
+    else if (!ta && tb) MX_GEMM(0, 1);
+    else if (ta && !tb) MX_GEMM(1, 0);
+    else MX_GEMM(1, 1);
+#undef MX_GEMM
+    return last_launch("mx_map_map_reduce_f32");
+}
+
+int gemm_tile_choice(int64_t M, int64_t N, const DeviceInfo *d) {
+    static int forced = -1;
+    if (forced < 0) {
+        const char *e = getenv("MX_GEMM_TILE");
+        forced = (e && !strcmp(e, "128x128")) ? 1 : (e && !strcmp(e, "128x64")) ? 2 : 0;
+    }
+    if (forced) return forced;
+    const int64_t big = ceil_div(M, 128) * ceil_div(N, 128);
+    return big <= d->num_cus ? 2 : 1;
+}
+
 }  // namespace
 }  // namespace mx
 
@@ -224,21 +271,12 @@ mx_status mx_map_map_reduce_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
     if (M == 0 || N == 0) return MX_OK;
     const DeviceInfo *d;
     if (mx_status st = device_info(&d)) return st;
-    const int64_t tiles_m = ceil_div(M, BM), tiles_n = ceil_div(N, BN);
-    MX_REQUIRE(tiles_m * tiles_n < (1LL << 31), MX_ERR_SHAPE, "mx_map_map_reduce_f32: too many tiles");
     const int64_t lda = ta ? M : K, ldb = tb ? K : N;
     const int vec_ok = ((uintptr_t)A_dev % 16 == 0) && ((uintptr_t)B_dev % 16 == 0) && (lda % 4 == 0) &&
                        (ldb % 4 == 0);
-    const dim3 grid((unsigned)(tiles_m * tiles_n));
-#define MX_GEMM(TA, TB)                                                                              \
-    hipLaunchKernelGGL((k_gemm_mfma<TA, TB>), grid, dim3(NT), 0, stream, A_dev, B_dev, C_dev, M, N, \
-                       K, (int)tiles_m, (int)tiles_n, vec_ok)
-    if (!ta && !tb) MX_GEMM(0, 0);
-    else if (!ta && tb) MX_GEMM(0, 1);
-    else if (ta && !tb) MX_GEMM(1, 0);
-    else MX_GEMM(1, 1);
-#undef MX_GEMM
-    return last_launch("mx_map_map_reduce_f32");
+    if (gemm_tile_choice(M, N, d) == 2)
+        return launch_gemm<128, 64, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    return launch_gemm<128, 128, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
 }
 
 mx_status mx_map_map_reduce_plain_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,

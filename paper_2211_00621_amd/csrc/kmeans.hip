@@ -24,6 +24,7 @@
 // finish kernel adds the block partials in block order in binary64, divides
 // and writes the new centroids and the int64 counts.
 #include <algorithm>
+#include <atomic>
 #include <cfloat>
 
 #include "mx_internal.h"
@@ -470,6 +471,10 @@ mx_status check(const char *who, const float *X, int64_t n, int d, const float *
     return MX_OK;
 }
 
+// Debug mode: number of binary64 recomputations in the last step (per process).
+std::atomic<long long> g_last_fallbacks{-1};
+unsigned long long *g_fb_counter[64] = {};
+
 template <int DP, int KP>
 void launch_fused(const KmArgs &a, int64_t nb, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_kmeans_fused<DP, KP>), dim3((unsigned)nb), dim3(NT), lds, s, a);
@@ -507,6 +512,14 @@ mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *
     MX_REQUIRE(lds <= 65536, MX_ERR_UNSUPPORTED, "%s: k = %d, d = %d needs %zu bytes of LDS (limit 65536)", who, k,
                d, lds);
     KmArgs a{X_dev, n, d, k, C_dev, labels_dev, (float *)((char *)ws + so), (int *)((char *)ws + co), nullptr};
+    const bool dbg = debug_mode();
+    if (dbg) {
+        const DeviceInfo *dv;
+        if (mx_status st = device_info(&dv)) return st;
+        if (!g_fb_counter[dv->device]) MX_TRY_HIP(hipMalloc(&g_fb_counter[dv->device], sizeof(unsigned long long)));
+        MX_TRY_HIP(hipMemsetAsync(g_fb_counter[dv->device], 0, sizeof(unsigned long long), stream));
+        a.fallbacks = g_fb_counter[dv->device];
+    }
     if (n > 0) {
         if (DP == 32) {
             switch (KP) {
@@ -526,8 +539,17 @@ mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *
     const int kd = k * d;
     hipLaunchKernelGGL(k_kmeans_finish, dim3((unsigned)ceil_div(kd, NT)), dim3(NT), 0, stream, a.part_sums,
                        a.part_counts, n > 0 ? (int)nb : 0, d, k, C_dev, counts_dev, C_out_dev);
-    return last_launch(who);
+    if (mx_status st = last_launch(who)) return st;
+    if (dbg) {
+        unsigned long long h = 0;
+        MX_TRY_HIP(hipMemcpyAsync(&h, a.fallbacks, sizeof h, hipMemcpyDeviceToHost, stream));
+        MX_TRY_HIP(hipStreamSynchronize(stream));
+        g_last_fallbacks.store((long long)h);
+    }
+    return MX_OK;
 }
+
+int64_t mx_kmeans_debug_fallbacks(void) { return g_last_fallbacks.load(); }
 
 mx_status mx_kmeans_step_plain_f32(const float *X_dev, int64_t n, int d, const float *C_dev, int k,
                                    int32_t *labels_dev, int64_t *counts_dev, float *C_out_dev, void *ws,
