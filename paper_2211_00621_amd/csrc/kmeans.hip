@@ -250,27 +250,40 @@ __global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
                 }
             }
         __syncthreads();
-        // ---- certify each label, or recompute it in binary64
+        // ---- certify each label; uncertified points are recomputed in binary64
+        //      by the whole wave, one point at a time, lanes over centroids
         {
             const int64_t p = p0 + lane;
             const int pt = wave * kPtsWave + lane;
             int label = -1;
+            bool certified = true;
             if (p < a.n) {
                 const float xn = sqrtf(xnorm[pt]) + cmax;
                 const float E = eps_factor * xn * xn;
-                if (best2[pt] - best1[pt] > 2.0f * E) {
-                    label = bidx[pt];
-                } else {
-                    const float *x = a.X + p * d;
-                    double bd = 0.0;
-                    for (int j = 0; j < k; ++j) {
-                        const double dj = dist64(x, Cs + j * LDC, d);
-                        if (label < 0 || dj < bd) { bd = dj; label = j; }
-                    }
-                    if (a.fallbacks) atomicAdd(a.fallbacks, 1ull);
-                }
-                a.labels[p] = label;
+                certified = best2[pt] - best1[pt] > 2.0f * E;
+                label = bidx[pt];
             }
+            uint64_t todo = __ballot(!certified);
+            if (todo && a.fallbacks && lane == 0) atomicAdd(a.fallbacks, (unsigned long long)__popcll(todo));
+            while (todo) {
+                const int q = __builtin_ctzll(todo);  // wave-uniform
+                todo &= todo - 1;
+                const float *x = a.X + (p0 + q) * d;
+                double bd = INFINITY;
+                int bj = 0x7fffffff;
+                for (int j = lane; j < k; j += kWave) {
+                    const double dj = dist64(x, Cs + j * LDC, d);
+                    if (dj < bd || (dj == bd && j < bj)) { bd = dj; bj = j; }
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double od = __shfl_xor(bd, off, kWave);
+                    const int oj = __shfl_xor(bj, off, kWave);
+                    if (od < bd || (od == bd && oj < bj)) { bd = od; bj = oj; }
+                }
+                if (lane == q) label = bj;
+            }
+            if (p < a.n) a.labels[p] = label;
             lab[pt] = label;
         }
         __syncthreads();
@@ -313,23 +326,59 @@ __global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
     }
 }
 
-// Adds the block partials in block order (binary64), divides, writes C' and counts.
+// Adds the block partials in a fixed order (binary64), divides, writes C' and
+// counts.  A block owns 8 entries (j, t); its 32 thread groups take block
+// partials b = group, group + 32, ... and the 32 group sums are added in group
+// order, so the result does not depend on scheduling.
+constexpr int kFinEntries = 8, kFinGroups = NT / kFinEntries;
+
 __global__ void __launch_bounds__(NT) k_kmeans_finish(const float *__restrict__ part_sums,
                                                       const int *__restrict__ part_counts, int nblocks,
                                                       int d, int k, const float *__restrict__ C,
                                                       int64_t *__restrict__ counts, float *__restrict__ C_out) {
-    const int e = blockIdx.x * NT + threadIdx.x;
+    __shared__ double ssum[kFinGroups][kFinEntries];
+    __shared__ long long scnt[kFinGroups][kFinEntries];
     const int kd = k * d;
-    if (e >= kd) return;
-    const int j = e / d;
+    const int le = threadIdx.x % kFinEntries, grp = threadIdx.x / kFinEntries;
+    const int e = blockIdx.x * kFinEntries + le;
+    const int j = e < kd ? e / d : 0;
     double s = 0.0;
-    int64_t c = 0;
-    for (int b = 0; b < nblocks; ++b) {
-        s += (double)part_sums[(int64_t)b * kd + e];
-        c += part_counts[(int64_t)b * k + j];
+    long long c = 0;
+    if (e < kd) {
+        int b = grp;
+        for (; b + 3 * kFinGroups < nblocks; b += 4 * kFinGroups) {
+            const float p0 = part_sums[(int64_t)b * kd + e];
+            const float p1 = part_sums[(int64_t)(b + kFinGroups) * kd + e];
+            const float p2 = part_sums[(int64_t)(b + 2 * kFinGroups) * kd + e];
+            const float p3 = part_sums[(int64_t)(b + 3 * kFinGroups) * kd + e];
+            const int c0 = part_counts[(int64_t)b * k + j];
+            const int c1 = part_counts[(int64_t)(b + kFinGroups) * k + j];
+            const int c2 = part_counts[(int64_t)(b + 2 * kFinGroups) * k + j];
+            const int c3 = part_counts[(int64_t)(b + 3 * kFinGroups) * k + j];
+            s += (double)p0;
+            s += (double)p1;
+            s += (double)p2;
+            s += (double)p3;
+            c += (long long)c0 + c1 + c2 + c3;
+        }
+        for (; b < nblocks; b += kFinGroups) {
+            s += (double)part_sums[(int64_t)b * kd + e];
+            c += part_counts[(int64_t)b * k + j];
+        }
     }
-    C_out[e] = c > 0 ? (float)(s / (double)c) : C[e];
-    if (e == j * d) counts[j] = c;
+    ssum[grp][le] = s;
+    scnt[grp][le] = c;
+    __syncthreads();
+    if (grp == 0 && e < kd) {
+        double tot = 0.0;
+        long long ctot = 0;
+        for (int q = 0; q < kFinGroups; ++q) {
+            tot += ssum[q][le];
+            ctot += scnt[q][le];
+        }
+        C_out[e] = ctot > 0 ? (float)(tot / (double)ctot) : C[e];
+        if (e == j * d) counts[j] = ctot;
+    }
 }
 
 // ---------------------------------------------------------------- plain form
@@ -537,7 +586,7 @@ mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *
         if (mx_status st = last_launch(who)) return st;
     }
     const int kd = k * d;
-    hipLaunchKernelGGL(k_kmeans_finish, dim3((unsigned)ceil_div(kd, NT)), dim3(NT), 0, stream, a.part_sums,
+    hipLaunchKernelGGL(k_kmeans_finish, dim3((unsigned)ceil_div(kd, kFinEntries)), dim3(NT), 0, stream, a.part_sums,
                        a.part_counts, n > 0 ? (int)nb : 0, d, k, C_dev, counts_dev, C_out_dev);
     if (mx_status st = last_launch(who)) return st;
     if (dbg) {

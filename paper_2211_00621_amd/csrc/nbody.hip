@@ -45,7 +45,7 @@ struct PairArgs {
 __device__ __forceinline__ void pair_accel(const float4 xi, const float4 xj, float eps2, float &ax,
                                            float &ay, float &az) {
     const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-    const float s = dx * dx + dy * dy + dz * dz + eps2;
+    const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));  // eps2 folded into the first FMA
     const float inv = __frsqrt_rn(s);
     const float w = xj.w * (inv * inv * inv);
     ax += w * dx;
@@ -57,14 +57,16 @@ __device__ __forceinline__ void pair_vjp(const float4 xk, const float4 ak, const
                                          const float4 aj, float eps2, float &ox, float &oy,
                                          float &oz) {
     const float dx = xj.x - xk.x, dy = xj.y - xk.y, dz = xj.z - xk.z;
-    const float s = dx * dx + dy * dy + dz * dz + eps2;
+    const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
     const float inv = __frsqrt_rn(s);
     const float inv2 = inv * inv;
     const float phi = inv2 * inv;
     const float psi = 3.0f * phi * inv2;
-    const float wx = xk.w * aj.x - xj.w * ak.x;
-    const float wy = xk.w * aj.y - xj.w * ak.y;
-    const float wz = xk.w * aj.z - xj.w * ak.z;
+    // both products rounded before the subtraction (no FMA contraction), so the
+    // self term j = k, where phi = eps^-3 is huge, is exactly zero as it must be
+    const float wx = __fmul_rn(xk.w, aj.x) - __fmul_rn(xj.w, ak.x);
+    const float wy = __fmul_rn(xk.w, aj.y) - __fmul_rn(xj.w, ak.y);
+    const float wz = __fmul_rn(xk.w, aj.z) - __fmul_rn(xj.w, ak.z);
     const float t = psi * (dx * wx + dy * wy + dz * wz);
     ox += phi * wx - t * dx;
     oy += phi * wy - t * dy;

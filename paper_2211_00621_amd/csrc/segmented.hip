@@ -77,7 +77,8 @@ mx_status validate_lengths(const char *who, const int64_t *len, int64_t n, hipSt
 
 // ---------------------------------------------------------------- wave-per-row reduce
 // One wave64 folds one row: an unaligned head and tail of at most V-1
-// elements, and the 16-byte-aligned body with four vectors in flight per lane.
+// elements, and the 16-byte-aligned body with up to eight vectors in flight
+// per lane.
 template <mx_dtype D, int OP>
 __global__ void __launch_bounds__(NT) k_seg_wave(const typename DT<D>::In *__restrict__ values,
                                                  const int64_t *__restrict__ offsets, int64_t nseg,
@@ -98,24 +99,24 @@ __global__ void __launch_bounds__(NT) k_seg_wave(const typename DT<D>::In *__res
         const int64_t head_end = vs * V < e ? vs * V : e;
         if (s + lane < head_end) acc = R::ap(acc, Acc(values[s + lane]));
         const Vec *vv = reinterpret_cast<const Vec *>(values);
-        Acc a1 = R::id(), a2 = R::id(), a3 = R::id();
-        int64_t i = vs + lane;
-        for (; i + 3 * kWave < ve; i += 4 * kWave) {
-            Vec x0 = vv[i], x1 = vv[i + kWave], x2 = vv[i + 2 * kWave], x3 = vv[i + 3 * kWave];
+        // up to eight vectors in flight per lane: rows up to 2048 elements take
+        // one round trip, 4096-element rows two
+        Acc ac[8];
 #pragma unroll
-            for (int j = 0; j < V; ++j) {
-                acc = R::ap(acc, Acc(vget<Vec, In>(x0, j)));
-                a1 = R::ap(a1, Acc(vget<Vec, In>(x1, j)));
-                a2 = R::ap(a2, Acc(vget<Vec, In>(x2, j)));
-                a3 = R::ap(a3, Acc(vget<Vec, In>(x3, j)));
-            }
-        }
-        for (; i < ve; i += kWave) {
-            Vec x0 = vv[i];
+        for (int u = 0; u < 8; ++u) ac[u] = R::id();
+        for (int64_t i = vs + lane; i < ve; i += 8 * kWave) {
+            Vec x[8];
 #pragma unroll
-            for (int j = 0; j < V; ++j) acc = R::ap(acc, Acc(vget<Vec, In>(x0, j)));
+            for (int u = 0; u < 8; ++u)
+                if (i + u * kWave < ve) x[u] = vv[i + u * kWave];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i + u * kWave < ve)
+#pragma unroll
+                    for (int j = 0; j < V; ++j) ac[u] = R::ap(ac[u], Acc(vget<Vec, In>(x[u], j)));
         }
-        acc = R::ap(R::ap(acc, a1), R::ap(a2, a3));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = R::ap(acc, ac[u]);
         const int64_t tail_start = ve * V > head_end ? ve * V : head_end;
         if (tail_start + lane < e) acc = R::ap(acc, Acc(values[tail_start + lane]));
     } else {
