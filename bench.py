@@ -38,6 +38,27 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 
 
+# HBM bytes per launch of each roofline kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the ratio of
+# known bytes to counted bytes for the copy kernel (bench.py --copy-calibration).
+# `source` is the SHA-256 of the kernel's source file when the counters were
+# taken: once that file changes the figure no longer describes the kernel and
+# the bench reports null.
+TRAFFIC = {}
+
+
+def traffic_of(key):
+    import hashlib
+    t = TRAFFIC.get(key)
+    if t is None:
+        return None
+    path = os.path.join(ROOT, "paper_2211_00621_amd", "csrc", t["file"])
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source"]:
+            return None
+    return t["bytes"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -188,7 +209,7 @@ def bench_nested(args):
                    "elements_per_step": elems},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_mfma<0,0> (dense map-map-reduce forward)",
                      "achieved": round(ach, 2), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": args.traffic},
+                     "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": traffic_of("gemm_nn")},
         "parts": detail,
         "plain": {"ms_per_step": pms, "value": elems / (pms * 1e-3),
                   "fused_speedup": round(pms / ms, 2)},
@@ -294,16 +315,17 @@ def bench_dot(args):
 # ============================================================ N-body loop
 # VALU instructions per pair interaction in the inner loop of the fused
 # forward pair kernel (gfx950 ISA of k_pairs<STEP>: 3 sub, 3 mul/fma for |d|^2
-# plus eps2, 2 mul for the cube, 1 mul by the mass, 3 fma into the sums) and
-# one transcendental (v_rsq_f32) issued at a quarter of the VALU rate.
+# plus eps2, v_rsq_f32, 2 mul for the cube, 1 mul by the mass, 3 fma into the
+# sums).  Every instruction, the reciprocal square root included, is counted as
+# one issue slot: the measured pair rate is above what a quarter-rate
+# transcendental would allow, so it overlaps with the other VALU work.
 NBODY_VALU_PER_PAIR = 13
-NBODY_TRANS_PER_PAIR = 1
 # 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz (no packed FP32).
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 
 
-def nbody_peak_pairs_per_s(valu, trans):
-    return LANE_OPS_PER_S / (valu + 4 * trans)
+def nbody_peak_pairs_per_s(valu):
+    return LANE_OPS_PER_S / valu
 
 
 def bench_nbody(args):
@@ -381,7 +403,7 @@ def bench_nbody(args):
 
     pairs_fwd = T * n * n
     pairs_bwd = (T - T // K) * n * n + T * n * n  # recomputed steps + adjoint steps
-    peak = nbody_peak_pairs_per_s(NBODY_VALU_PER_PAIR, NBODY_TRANS_PER_PAIR)
+    peak = nbody_peak_pairs_per_s(NBODY_VALU_PER_PAIR)
     ach = n * n / (parts["step"] * 1e-3)
     line = {
         "metric": METRIC, "value": (pairs_fwd + pairs_bwd) / (ms * 1e-3), "unit": "pair-interactions/s",
@@ -393,8 +415,7 @@ def bench_nbody(args):
         "roofline": {"bound": "alu", "kernel": "k_pairs<STEP> (+ slice finish)",
                      "achieved": round(ach / 1e9, 1), "peak": round(peak / 1e9, 1), "unit": "Gpair/s",
                      "frac": round(ach / peak, 4), "traffic": None,
-                     "peak_basis": f"256 CU x 64 lanes x 2.4 GHz / ({NBODY_VALU_PER_PAIR} VALU + "
-                                   f"4 x {NBODY_TRANS_PER_PAIR} transcendental) per pair"},
+                     "peak_basis": f"256 CU x 64 lanes x 2.4 GHz / {NBODY_VALU_PER_PAIR} VALU issues per pair"},
         "parts": {"fwd_20_steps_ms": round(ms_fwd, 3), "reverse_ms": round(ms - ms_fwd, 3),
                   "step_launch_us": round(parts["step"] * 1e3, 1),
                   "adjoint_step_launch_us": round(parts["adjoint_step"] * 1e3, 1)},
@@ -604,6 +625,18 @@ def bench_batched(args):
     return line
 
 
+def copy_calibration(mib):
+    import torch
+    from paper_2211_00621_amd import abi
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        abi.mx_copy32(src, dst)
+    torch.cuda.synchronize()
+    return {"copy_calibration": {"kernel": "k_copy32", "launches": 5, "read_bytes": n, "write_bytes": n}}
+
+
 WORKLOADS = {"nested": bench_nested, "dot": bench_dot, "nbody": bench_nbody, "kmeans": bench_kmeans,
              "batched": bench_batched}
 
@@ -615,17 +648,21 @@ def main(argv=None):
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", choices=sorted(WORKLOADS), default="nested")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--traffic", type=float, default=None,
-                   help="HBM bytes per launch of the dominant kernel from hardware counters, if known")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run mx_copy32 over MIB MiB five times (the reference kernel that scales the "
+                        "FETCH_SIZE / WRITE_SIZE counters to bytes) and print its size")
     args = p.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "multi-GPU runs are not part of this build.", file=sys.stderr, flush=True)
+              "multi-GPU runs are not implemented.", file=sys.stderr, flush=True)
         return 2
     import torch
     torch.cuda.set_device(0)
-    line = WORKLOADS[args.workload](args)
+    if args.copy_calibration:
+        line = copy_calibration(args.copy_calibration)
+    else:
+        line = WORKLOADS[args.workload](args)
     print(json.dumps(line), flush=True)
     return 0
 

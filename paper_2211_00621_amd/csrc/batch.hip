@@ -78,31 +78,48 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
         const TaskDev tk = tasks[tl.task];
         if (tk.kind == kDot) {
             const float *a = A + tk.a_off, *b = B + tk.b_off;
-            float acc = 0.f, acc2 = 0.f;
+            float ac[4] = {0.f, 0.f, 0.f, 0.f};
             int64_t e = tl.begin + threadIdx.x;
-            for (; e + NT < tl.end; e += 2 * NT) {
-                acc += a[e] * b[e];
-                acc2 += a[e + NT] * b[e + NT];
+            for (; e + 3 * NT < tl.end; e += 4 * NT) {
+                float av[4], bv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    av[u] = a[e + u * NT];
+                    bv[u] = b[e + u * NT];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) ac[u] += av[u] * bv[u];
             }
-            if (e < tl.end) acc += a[e] * b[e];
-            acc = block_reduce<R, NT>(acc + acc2, red);
+            for (; e < tl.end; e += NT) ac[0] += a[e] * b[e];
+            float acc = block_reduce<R, NT>((ac[0] + ac[1]) + (ac[2] + ac[3]), red);
             if (threadIdx.x == 0) {
                 if (tl.part >= 0) part[tl.part] = acc;
                 else out[tk.out_off] = acc;
             }
         } else {
-            // 16 lanes per row, 16 rows at a time
+            // 16 lanes per row, 16 rows at a time, four loads per lane in flight
             const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
             const int64_t c = tk.cols;
             const float *x = B + tk.b_off;
             for (int64_t r0 = tl.begin; r0 < tl.end; r0 += NT / 16) {
                 const int64_t r = r0 + grp;
-                float acc = 0.f;
+                float ac[4] = {0.f, 0.f, 0.f, 0.f};
                 if (r < tl.end) {
                     const float *row = A + tk.a_off + r * c;
-                    for (int64_t j = l; j < c; j += 16) acc += row[j] * x[j];
+                    int64_t j = l;
+                    for (; j + 48 < c; j += 64) {
+                        float av[4], xv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            av[u] = row[j + 16 * u];
+                            xv[u] = x[j + 16 * u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) ac[u] += av[u] * xv[u];
+                    }
+                    for (; j < c; j += 16) ac[0] += row[j] * x[j];
                 }
-                acc = row16_sum(acc);
+                const float acc = row16_sum((ac[0] + ac[1]) + (ac[2] + ac[3]));
                 if (l == 0 && r < tl.end) out[tk.out_off + r] = acc;
             }
         }
@@ -124,7 +141,21 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             const float g = gout[tk.out_off];
             const float *a = A + tk.a_off, *b = B + tk.b_off;
             float *ga = gA + tk.a_off, *gb = gB + tk.b_off;
-            for (int64_t e = tl.begin + threadIdx.x; e < tl.end; e += NT) {
+            int64_t e = tl.begin + threadIdx.x;
+            for (; e + 3 * NT < tl.end; e += 4 * NT) {
+                float av[4], bv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    av[u] = a[e + u * NT];
+                    bv[u] = b[e + u * NT];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    ga[e + u * NT] = g * bv[u];
+                    gb[e + u * NT] = g * av[u];
+                }
+            }
+            for (; e < tl.end; e += NT) {
                 ga[e] = g * b[e];
                 gb[e] = g * a[e];
             }
@@ -136,7 +167,21 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             for (int64_t j = threadIdx.x; j < c; j += NT) {
                 const float xj = x[j];
                 float acc = 0.f;
-                for (int64_t r = tl.begin; r < tl.end; ++r) {
+                int64_t r = tl.begin;
+                for (; r + 3 < tl.end; r += 4) {
+                    float av[4], gv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = a[(r + u) * c + j];
+                        gv[u] = g[r + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        acc += av[u] * gv[u];
+                        ga[(r + u) * c + j] = gv[u] * xj;
+                    }
+                }
+                for (; r < tl.end; ++r) {
                     const float gr = g[r];
                     acc += a[r * c + j] * gr;
                     ga[r * c + j] = gr * xj;

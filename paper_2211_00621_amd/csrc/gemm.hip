@@ -117,6 +117,8 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
                                                             float *__restrict__ C, int64_t M, int64_t N, int64_t K,
                                                             int tiles_m, int tiles_n, int vec_ok) {
     constexpr int NT = 64 * WM * WN;
+    static_assert((BM * BK / 4) % NT == 0 && (BN * BK / 4) % NT == 0, "slice loads must split evenly");
+    static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tiles are whole 16 x 16 blocks");
     constexpr bool RA = !TA, RB = TB;  // [row][k] in memory
     constexpr bool PERM = RA && RB;
     constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
@@ -229,7 +231,8 @@ mx_status check(const char *who, int ta, int tb, int64_t M, int64_t N, int64_t K
 
 // Tile shape: 128 x 128 with 4 waves, or 128 x 64 with 4 waves when that
 // still gives at most one tile per CU (two blocks per CU hide each other's
-// barriers); MX_GEMM_TILE=128x128|128x64 in the environment forces one.
+// barriers); MX_GEMM_TILE in the environment forces one of the configurations
+// below (for tuning).
 template <int BM, int BN, int WM, int WN>
 mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A, const float *B, float *C,
                       int vec_ok, hipStream_t s) {
@@ -247,15 +250,24 @@ mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const flo
     return last_launch("mx_map_map_reduce_f32");
 }
 
+// Tile configurations: BM x BN block tile, WM x WN waves.
+enum GemmTile { kT128x64 = 1, kT128x128, kT128x64w8, kT128x128w8, kT64x64 };
+
 int gemm_tile_choice(int64_t M, int64_t N, const DeviceInfo *d) {
     static int forced = -1;
     if (forced < 0) {
-        const char *e = getenv("MX_GEMM_TILE");
-        forced = (e && !strcmp(e, "128x128")) ? 1 : (e && !strcmp(e, "128x64")) ? 2 : 0;
+        forced = 0;
+        if (const char *e = getenv("MX_GEMM_TILE")) {
+            static const struct { const char *name; int tile; } names[] = {
+                {"128x64", kT128x64}, {"128x128", kT128x128}, {"128x64w8", kT128x64w8},
+                {"128x128w8", kT128x128w8}, {"64x64", kT64x64}};
+            for (const auto &n : names)
+                if (!strcmp(e, n.name)) forced = n.tile;
+        }
     }
     if (forced) return forced;
     const int64_t big = ceil_div(M, 128) * ceil_div(N, 128);
-    return big <= d->num_cus ? 2 : 1;
+    return big <= d->num_cus ? kT128x64 : kT128x128;
 }
 
 }  // namespace
@@ -274,9 +286,13 @@ mx_status mx_map_map_reduce_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
     const int64_t lda = ta ? M : K, ldb = tb ? K : N;
     const int vec_ok = ((uintptr_t)A_dev % 16 == 0) && ((uintptr_t)B_dev % 16 == 0) && (lda % 4 == 0) &&
                        (ldb % 4 == 0);
-    if (gemm_tile_choice(M, N, d) == 2)
-        return launch_gemm<128, 64, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
-    return launch_gemm<128, 128, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    switch (gemm_tile_choice(M, N, d)) {
+    case kT128x64: return launch_gemm<128, 64, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    case kT128x64w8: return launch_gemm<128, 64, 4, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    case kT128x128w8: return launch_gemm<128, 128, 4, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    case kT64x64: return launch_gemm<64, 64, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    default: return launch_gemm<128, 128, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    }
 }
 
 mx_status mx_map_map_reduce_plain_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,

@@ -84,8 +84,8 @@ __device__ __forceinline__ Best row_merge(Best v) {
 __device__ __forceinline__ double dist64(const float *__restrict__ x, const float *c, int d) {
     double acc = 0.0;
     for (int t = 0; t < d; ++t) {
-        const double diff = __dsub_rn((double)x[t], (double)c[t]);
-        acc = __dadd_rn(acc, __dmul_rn(diff, diff));
+        const double diff = sub_rn((double)x[t], (double)c[t]);
+        acc = add_rn(acc, mul_rn(diff, diff));
     }
     return acc;
 }

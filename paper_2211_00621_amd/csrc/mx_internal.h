@@ -118,6 +118,24 @@ template <class T> struct Red<MX_MAX, T> {
     static __host__ __device__ __forceinline__ T ap(T a, T b) { return b > a ? b : a; }
 };
 
+// ---------------------------------------------------------------- uncontracted arithmetic
+// hipcc fuses a multiply and a dependent add into one FMA by default, and the
+// __fmul_rn family are plain operators in HIP, so they are fused as well.
+// These helpers carry no contraction permission: every result is rounded on
+// its own, as in the binary64 / binary32 definition of the operation.
+template <class T> __device__ __forceinline__ T mul_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+template <class T> __device__ __forceinline__ T add_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+template <class T> __device__ __forceinline__ T sub_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a - b;
+}
+
 // ---------------------------------------------------------------- map bodies
 template <int F, class T> struct Un;
 template <class T> struct Un<MX_U_ID, T> { static __device__ __forceinline__ T ap(T x, T, T) { return x; } };
@@ -127,8 +145,7 @@ template <class T> struct Un<MX_U_SQ, T> { static __device__ __forceinline__ T a
 template <class T> struct Un<MX_U_AFFINE, T> {
     // two roundings (multiply, then add), never contracted into an FMA
     static __device__ __forceinline__ T ap(T x, T p0, T p1) {
-        if constexpr (std::is_same_v<T, float>) return __fadd_rn(__fmul_rn(p0, x), p1);
-        else if constexpr (std::is_same_v<T, double>) return __dadd_rn(__dmul_rn(p0, x), p1);
+        if constexpr (std::is_floating_point_v<T>) return add_rn(mul_rn(p0, x), p1);
         else return wadd(wmul(p0, x), p1);
     }
 };

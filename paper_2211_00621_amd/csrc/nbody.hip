@@ -62,11 +62,11 @@ __device__ __forceinline__ void pair_vjp(const float4 xk, const float4 ak, const
     const float inv2 = inv * inv;
     const float phi = inv2 * inv;
     const float psi = 3.0f * phi * inv2;
-    // both products rounded before the subtraction (no FMA contraction), so the
-    // self term j = k, where phi = eps^-3 is huge, is exactly zero as it must be
-    const float wx = __fmul_rn(xk.w, aj.x) - __fmul_rn(xj.w, ak.x);
-    const float wy = __fmul_rn(xk.w, aj.y) - __fmul_rn(xj.w, ak.y);
-    const float wz = __fmul_rn(xk.w, aj.z) - __fmul_rn(xj.w, ak.z);
+    // both products rounded before the subtraction (never fused into an FMA),
+    // so the self term j = k, where phi = eps^-3 is huge, is exactly zero
+    const float wx = sub_rn(mul_rn(xk.w, aj.x), mul_rn(xj.w, ak.x));
+    const float wy = sub_rn(mul_rn(xk.w, aj.y), mul_rn(xj.w, ak.y));
+    const float wz = sub_rn(mul_rn(xk.w, aj.z), mul_rn(xj.w, ak.z));
     const float t = psi * (dx * wx + dy * wy + dz * wz);
     ox += phi * wx - t * dx;
     oy += phi * wy - t * dy;

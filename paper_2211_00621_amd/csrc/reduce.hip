@@ -1,37 +1,22 @@
 // reduce op ne s and the fused reduce op ne (map2 f a b) (Appendix A).
 //
-// One launch: every thread folds a grid-strided set of 16-byte vectors into a
-// private accumulator (U vectors per operand in flight), the block combines
-// its 256 values with the wave64 DPP tree and writes one partial, and the last
-// block to finish (atomic ticket) folds the partials in block order and applies
-// ne.  The bracketing depends only on n and the grid, so results are
-// bit-identical from run to run; the ticket is reset for the next call.
+// Two launches.  Partial pass: every thread folds a grid-strided set of 16-byte
+// vectors (U per operand in flight) into one accumulator per vector lane, the
+// block combines its values with the wave64 DPP tree and writes one partial.
+// Finish pass (one block): folds the partials in block order and applies ne.
+// The kernel boundary orders the two passes, so no block pays for a
+// device-wide fence.  The bracketing depends only on n and the grid, so
+// results are bit-identical from run to run.
 #include "mx_internal.h"
 
 namespace mx {
 namespace {
 
 constexpr int NT = 256;
-constexpr int U = 2;
+constexpr int U = 4;
 constexpr int kMaxBlocks = 4096;
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
-
-template <class T> __device__ __forceinline__ T load_relaxed(const T *p) {
-    if constexpr (sizeof(T) == 4) {
-        uint32_t u = __hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        T v;
-        __builtin_memcpy(&v, &u, 4);
-        return v;
-    } else {
-        uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        T v;
-        __builtin_memcpy(&v, &u, 8);
-        return v;
-    }
-}
 
 // F < 0: plain reduce of a; otherwise element = Bin<F>(a[i], b[i]).
 template <mx_dtype D, int OP, int F> struct Elem {
@@ -46,9 +31,7 @@ template <mx_dtype D, int OP, int F> struct Elem {
 template <mx_dtype D, int OP, int F>
 __global__ void __launch_bounds__(NT) k_reduce(const typename DT<D>::In *__restrict__ a,
                                                const typename DT<D>::In *__restrict__ b, int64_t n,
-                                               typename DT<D>::Acc ne, typename DT<D>::Acc *out,
-                                               typename DT<D>::Acc *partials, unsigned *ticket,
-                                               int vec) {
+                                               typename DT<D>::Acc *__restrict__ partials, int vec) {
     using In = typename DT<D>::In;
     using Acc = typename DT<D>::Acc;
     using Vec = typename DT<D>::Vec;
@@ -57,9 +40,10 @@ __global__ void __launch_bounds__(NT) k_reduce(const typename DT<D>::In *__restr
     constexpr int V = DT<D>::kVec;
     constexpr bool TWO = F >= 0;
     __shared__ Acc smem[NT / kWave];
-    __shared__ int is_last;
 
-    Acc acc = R::id();
+    Acc acc[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = R::id();
     const int64_t gtid = (int64_t)blockIdx.x * NT + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * NT;
     if (vec) {
@@ -78,7 +62,7 @@ __global__ void __launch_bounds__(NT) k_reduce(const typename DT<D>::In *__restr
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int j = 0; j < V; ++j)
-                    acc = R::ap(acc, E::at(vget<Vec, In>(va[u], j), TWO ? vget<Vec, In>(vb[u], j) : In(0)));
+                    acc[j] = R::ap(acc[j], E::at(vget<Vec, In>(va[u], j), TWO ? vget<Vec, In>(vb[u], j) : In(0)));
         }
         for (; i < nv; i += stride) {
             Vec va = av[i];
@@ -86,29 +70,31 @@ __global__ void __launch_bounds__(NT) k_reduce(const typename DT<D>::In *__restr
             if constexpr (TWO) vb = bv[i];
 #pragma unroll
             for (int j = 0; j < V; ++j)
-                acc = R::ap(acc, E::at(vget<Vec, In>(va, j), TWO ? vget<Vec, In>(vb, j) : In(0)));
+                acc[j] = R::ap(acc[j], E::at(vget<Vec, In>(va, j), TWO ? vget<Vec, In>(vb, j) : In(0)));
         }
-        if (gtid < n - nv * V) acc = R::ap(acc, E::at(a[nv * V + gtid], TWO ? b[nv * V + gtid] : In(0)));
+        if (gtid < n - nv * V) acc[0] = R::ap(acc[0], E::at(a[nv * V + gtid], TWO ? b[nv * V + gtid] : In(0)));
     } else {
-        for (int64_t i = gtid; i < n; i += stride) acc = R::ap(acc, E::at(a[i], TWO ? b[i] : In(0)));
+        for (int64_t i = gtid; i < n; i += stride) acc[0] = R::ap(acc[0], E::at(a[i], TWO ? b[i] : In(0)));
     }
+    Acc t = acc[0];
+#pragma unroll
+    for (int j = 1; j < V; ++j) t = R::ap(t, acc[j]);
+    t = block_reduce<R, NT>(t, smem);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
 
-    acc = block_reduce<R, NT>(acc, smem);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = acc;
-        unsigned t = take_ticket(ticket);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+// one block: out = ne (op) (partial_0 (op) ... (op) partial_{nb-1}), strided
+// per thread then the DPP tree
+template <mx_dtype D, int OP>
+__global__ void __launch_bounds__(NT) k_reduce_finish(const typename DT<D>::Acc *__restrict__ partials, int nb,
+                                                      typename DT<D>::Acc ne, typename DT<D>::Acc *out) {
+    using Acc = typename DT<D>::Acc;
+    using R = Red<OP, Acc>;
+    __shared__ Acc smem[NT / kWave];
     Acc v = R::id();
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += NT) v = R::ap(v, load_relaxed(partials + i));
+    for (int i = threadIdx.x; i < nb; i += NT) v = R::ap(v, partials[i]);
     v = block_reduce<R, NT>(v, smem);
-    if (threadIdx.x == 0) {
-        out[0] = R::ap(ne, v);
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) out[0] = R::ap(ne, v);
 }
 
 template <mx_dtype D, int OP, int F>
@@ -124,11 +110,13 @@ mx_status launch(const void *a, const void *b, int64_t n, const void *ne_host, v
     int64_t cap = (int64_t)dev->num_cus * 8;
     if (cap > kMaxBlocks) cap = kMaxBlocks;
     if (grid > cap) grid = cap;
-    unsigned *ticket = (unsigned *)ws;
     Acc *partials = (Acc *)((char *)ws + kCounterBytes);
     hipLaunchKernelGGL((k_reduce<D, OP, F>), dim3((unsigned)grid), dim3(NT), 0, s, (const In *)a,
-                       (const In *)b, n, ne, (Acc *)out, partials, ticket, vec);
-    return last_launch("reduce");
+                       (const In *)b, n, partials, vec);
+    if (mx_status st = last_launch("reduce")) return st;
+    hipLaunchKernelGGL((k_reduce_finish<D, OP>), dim3(1), dim3(NT), 0, s, (const Acc *)partials, (int)grid, ne,
+                       (Acc *)out);
+    return last_launch("reduce finish");
 }
 
 template <mx_dtype D, int F>

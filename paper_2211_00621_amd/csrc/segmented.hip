@@ -10,7 +10,6 @@ namespace mx {
 namespace {
 
 constexpr int NT = 256;
-constexpr int kRowsPerBlock = NT / kWave;
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
@@ -75,55 +74,109 @@ mx_status validate_lengths(const char *who, const int64_t *len, int64_t n, hipSt
     return MX_OK;
 }
 
-// ---------------------------------------------------------------- wave-per-row reduce
-// One wave64 folds one row: an unaligned head and tail of at most V-1
-// elements, and the 16-byte-aligned body with up to eight vectors in flight
-// per lane.
+// ---------------------------------------------------------------- block-span reduce
+// A block takes `rb` consecutive rows, whose values form one contiguous span
+// [offsets[r0], offsets[r0 + rb]).  Its threads stream the whole span in
+// 16-byte vectors (thread t takes vectors t, t + NT, ...; eight in flight),
+// so a block keeps about 32 KB of loads in flight whatever the row lengths,
+// and the offsets cost one round trip per rb rows instead of one per row.
+//
+// Row attribution: the positions a thread visits increase, so the row they
+// fall in never decreases.  A thread keeps one accumulator for its current
+// row; on crossing a row end it parks that value in its own LDS slot
+// (row, thread) and starts afresh.  Afterwards each row's NT slots are folded
+// in a fixed order (four slots per lane, then the DPP wave tree), so the
+// result depends only on the offsets, never on timing.
+constexpr int kMaxRowsPerBlock = 16;
+
+// LDS: rb + 1 offsets (padded to 16 bytes), then rb x NT accumulator slots
+__host__ __device__ constexpr size_t span_off_bytes(int rb) { return ((size_t)(rb + 1) * 8 + 15) & ~(size_t)15; }
+template <mx_dtype D> constexpr size_t span_lds_bytes(int rb) {
+    return span_off_bytes(rb) + (size_t)rb * NT * sizeof(typename DT<D>::Acc);
+}
+
 template <mx_dtype D, int OP>
-__global__ void __launch_bounds__(NT) k_seg_wave(const typename DT<D>::In *__restrict__ values,
-                                                 const int64_t *__restrict__ offsets, int64_t nseg,
-                                                 typename DT<D>::Acc ne,
-                                                 typename DT<D>::Acc *__restrict__ out, int vec) {
+__global__ void __launch_bounds__(NT) k_seg_span(const typename DT<D>::In *__restrict__ values,
+                                                 const int64_t *__restrict__ offsets, int64_t nseg, int rb,
+                                                 typename DT<D>::Acc ne, typename DT<D>::Acc *__restrict__ out,
+                                                 int vec) {
     using In = typename DT<D>::In;
     using Acc = typename DT<D>::Acc;
     using Vec = typename DT<D>::Vec;
     using R = Red<OP, Acc>;
     constexpr int V = DT<D>::kVec;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (row >= nseg) return;  // wave-uniform
-    const int64_t s = offsets[row], e = offsets[row + 1];
-    Acc acc = R::id();
-    if (vec) {
-        const int64_t vs = (s + V - 1) / V, ve = e / V;  // whole vectors inside [s, e)
-        const int64_t head_end = vs * V < e ? vs * V : e;
-        if (s + lane < head_end) acc = R::ap(acc, Acc(values[s + lane]));
-        const Vec *vv = reinterpret_cast<const Vec *>(values);
-        // up to eight vectors in flight per lane: rows up to 2048 elements take
-        // one round trip, 4096-element rows two
-        Acc ac[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) ac[u] = R::id();
-        for (int64_t i = vs + lane; i < ve; i += 8 * kWave) {
-            Vec x[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i + u * kWave < ve) x[u] = vv[i + u * kWave];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i + u * kWave < ve)
-#pragma unroll
-                    for (int j = 0; j < V; ++j) ac[u] = R::ap(ac[u], Acc(vget<Vec, In>(x[u], j)));
+    constexpr int U = 8;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    int64_t *soff = reinterpret_cast<int64_t *>(lds);
+    Acc *slot = reinterpret_cast<Acc *>(lds + span_off_bytes(rb));
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rb;
+    const int nrows = (int)(nseg - r0 < rb ? nseg - r0 : rb);  // >= 1: the grid covers nseg exactly
+    if (t <= nrows) soff[t] = offsets[r0 + t];
+    for (int k = 0; k < nrows; ++k) slot[k * NT + t] = R::id();
+    __syncthreads();
+
+    const int64_t S = soff[0], E = soff[nrows];
+    int cur = 0;
+    int64_t end = soff[1];
+    Acc a = R::id();
+    // fold element x at position p into its row
+    auto take = [&](int64_t p, Acc x) {
+        while (p >= end) {
+            slot[cur * NT + t] = a;
+            a = R::id();
+            ++cur;
+            end = soff[cur + 1];
         }
+        a = R::ap(a, x);
+    };
+    if (vec) {
+        const int64_t vs = (S + V - 1) / V, ve = E / V;  // whole vectors inside [S, E)
+        const int64_t head_end = vs * V < E ? vs * V : E;
+        if (S + t < head_end) take(S + t, Acc(values[S + t]));
+        const Vec *vv = reinterpret_cast<const Vec *>(values);
+        for (int64_t i = vs + t; i < ve; i += U * NT) {
+            Vec x[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = R::ap(acc, ac[u]);
+            for (int u = 0; u < U; ++u)
+                if (i + u * NT < ve) x[u] = vv[i + u * NT];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i + u * NT < ve) {
+                    const int64_t p0 = (i + u * NT) * V;
+                    if (p0 + V - 1 < end) {
+#pragma unroll
+                        for (int j = 0; j < V; ++j) a = R::ap(a, Acc(vget<Vec, In>(x[u], j)));
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < V; ++j) take(p0 + j, Acc(vget<Vec, In>(x[u], j)));
+                    }
+                }
+            }
+        }
         const int64_t tail_start = ve * V > head_end ? ve * V : head_end;
-        if (tail_start + lane < e) acc = R::ap(acc, Acc(values[tail_start + lane]));
+        if (tail_start + t < E) take(tail_start + t, Acc(values[tail_start + t]));
     } else {
-        for (int64_t i = s + lane; i < e; i += kWave) acc = R::ap(acc, Acc(values[i]));
+        for (int64_t i = S + t; i < E; i += NT) take(i, Acc(values[i]));
     }
-    acc = wave_reduce<R>(acc);
-    if (lane == 0) out[row] = R::ap(ne, acc);
+    slot[cur * NT + t] = a;
+    __syncthreads();
+
+    const int lane = t & (kWave - 1), w = t / kWave;
+    for (int k = w; k < nrows; k += NT / kWave) {
+        Acc v = slot[k * NT + lane];
+#pragma unroll
+        for (int q = 1; q < NT / kWave; ++q) v = R::ap(v, slot[k * NT + q * kWave + lane]);
+        v = wave_reduce<R>(v);
+        if (lane == 0) out[r0 + k] = R::ap(ne, v);
+    }
+}
+
+// rows per block: enough blocks for eight per CU, at most kMaxRowsPerBlock rows each
+int rows_per_block(int64_t nseg, const DeviceInfo *d) {
+    const int64_t target = (int64_t)d->num_cus * 8;
+    int64_t rb = ceil_div(nseg, target);
+    return (int)(rb < 1 ? 1 : rb > kMaxRowsPerBlock ? kMaxRowsPerBlock : rb);
 }
 
 // Plain: one thread folds one row left to right.
@@ -141,27 +194,54 @@ __global__ void __launch_bounds__(NT) k_seg_thread(const typename DT<D>::In *__r
     out[row] = acc;
 }
 
-// Reverse of the row sums: broadcast gout[r] over row r, one wave per row.
+// Reverse of the row sums: gval[p] = gout[row of p].  Same block-span walk as
+// the reduce: a block loads the offsets and gradients of its rb rows once and
+// writes its whole span in 16-byte stores.
 __global__ void __launch_bounds__(NT) k_seg_broadcast(const float *__restrict__ gout,
-                                                      const int64_t *__restrict__ offsets,
-                                                      int64_t nseg, float *__restrict__ gval,
-                                                      int vec) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (row >= nseg) return;
-    const int64_t s = offsets[row], e = offsets[row + 1];
-    const float g = gout[row];
+                                                      const int64_t *__restrict__ offsets, int64_t nseg, int rb,
+                                                      float *__restrict__ gval, int vec) {
+    __shared__ int64_t soff[kMaxRowsPerBlock + 1];
+    __shared__ float sg[kMaxRowsPerBlock];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rb;
+    const int nrows = (int)(nseg - r0 < rb ? nseg - r0 : rb);
+    if (t <= nrows) soff[t] = offsets[r0 + t];
+    if (t < nrows) sg[t] = gout[r0 + t];
+    __syncthreads();
+    const int64_t S = soff[0], E = soff[nrows];
+    int cur = 0;
+    int64_t end = soff[1];
+    float g = sg[0];
+    auto at = [&](int64_t p) {
+        while (p >= end) {
+            ++cur;
+            end = soff[cur + 1];
+            g = sg[cur];
+        }
+        return g;
+    };
     if (vec) {
-        const int64_t vs = (s + 3) / 4, ve = e / 4;
-        const int64_t head_end = vs * 4 < e ? vs * 4 : e;
-        if (s + lane < head_end) gval[s + lane] = g;
+        const int64_t vs = (S + 3) / 4, ve = E / 4;
+        const int64_t head_end = vs * 4 < E ? vs * 4 : E;
+        if (S + t < head_end) gval[S + t] = at(S + t);
         float4 *gv = reinterpret_cast<float4 *>(gval);
-        const float4 g4 = make_float4(g, g, g, g);
-        for (int64_t i = vs + lane; i < ve; i += kWave) gv[i] = g4;
+        for (int64_t i = vs + t; i < ve; i += NT) {
+            const int64_t p0 = i * 4;
+            float4 y;
+            if (p0 + 3 < end) {
+                y = make_float4(g, g, g, g);
+            } else {
+                y.x = at(p0);
+                y.y = at(p0 + 1);
+                y.z = at(p0 + 2);
+                y.w = at(p0 + 3);
+            }
+            gv[i] = y;
+        }
         const int64_t tail_start = ve * 4 > head_end ? ve * 4 : head_end;
-        if (tail_start + lane < e) gval[tail_start + lane] = g;
+        if (tail_start + t < E) gval[tail_start + t] = at(tail_start + t);
     } else {
-        for (int64_t i = s + lane; i < e; i += kWave) gval[i] = g;
+        for (int64_t i = S + t; i < E; i += NT) gval[i] = at(i);
     }
 }
 
@@ -293,10 +373,13 @@ mx_status launch_seg(bool plain, const void *values, const int64_t *off, int64_t
         hipLaunchKernelGGL((k_seg_thread<D, OP>), dim3(grid), dim3(NT), 0, s, (const In *)values, off,
                            nseg, ne, (Acc *)out);
     } else {
-        int64_t grid = ceil_div(nseg, kRowsPerBlock);
+        const DeviceInfo *d;
+        if (mx_status st = device_info(&d)) return st;
+        const int rb = rows_per_block(nseg, d);
+        const int64_t grid = ceil_div(nseg, rb);
         MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "mx_segmented_reduce: too many rows");
-        hipLaunchKernelGGL((k_seg_wave<D, OP>), dim3((unsigned)grid), dim3(NT), 0, s, (const In *)values,
-                           off, nseg, ne, (Acc *)out, (int)aligned16(values));
+        hipLaunchKernelGGL((k_seg_span<D, OP>), dim3((unsigned)grid), dim3(NT), span_lds_bytes<D>(rb), s,
+                           (const In *)values, off, nseg, rb, ne, (Acc *)out, (int)aligned16(values));
     }
     return last_launch("mx_segmented_reduce");
 }
@@ -397,10 +480,11 @@ mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *off
     if (debug_mode())
         if (mx_status st = validate_offsets("mx_segmented_sum_adjoint_f32", offsets_dev, nseg, stream, d))
             return st;
-    int64_t grid = ceil_div(nseg, kRowsPerBlock);
+    const int rb = rows_per_block(nseg, d);
+    const int64_t grid = ceil_div(nseg, rb);
     MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "mx_segmented_sum_adjoint_f32: too many rows");
     hipLaunchKernelGGL(k_seg_broadcast, dim3((unsigned)grid), dim3(NT), 0, stream, gout_dev,
-                       offsets_dev, nseg, gvalues_dev, (int)aligned16(gvalues_dev));
+                       offsets_dev, nseg, rb, gvalues_dev, (int)aligned16(gvalues_dev));
     return last_launch("mx_segmented_sum_adjoint_f32");
 }
 

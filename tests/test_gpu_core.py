@@ -309,6 +309,38 @@ def test_segmented_unaligned_values_view():
                  O.segmented_reduce(O.ADD, 0.0, np.abs(v), off), L)
 
 
+@pytest.mark.parametrize("lengths", [
+    [0], [1], [5, 0, 3], [100000, 0, 250001],            # few rows: one row per block, many rounds
+    [4096] * 17, [0] * 40 + [9000] + [0] * 40,            # full and ragged last block, empty runs
+], ids=lambda L: f"n{len(L)}")
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32])
+def test_segmented_shapes(lengths, dt):
+    """Row counts and lengths around the rows-per-block split, each dtype."""
+    say("segmented shapes", len(lengths), dt)
+    L = np.array(lengths, dtype=np.int64)
+    off = O.offsets_from_lengths(L)
+    rng = np.random.default_rng(len(L))
+    if dt == np.int32:
+        v = rng.integers(-1000, 1001, int(off[-1])).astype(dt)
+    else:
+        v = rng.uniform(-1, 1, int(off[-1])).astype(dt)
+    for shift in (0, 1):  # aligned values and a view one element in
+        full = dev(np.concatenate([np.zeros(shift, dtype=dt), v]))
+        rg = api.Ragged(full[shift:], dev(off))
+        got = host(api.segmented_reduce(abi.MX_ADD, rg, 0))
+        R = O.segmented_reduce(O.ADD, 0, v, off)
+        if dt == np.int32:
+            assert np.array_equal(got, R), shift
+        else:
+            check_vector(got, R, O.segmented_reduce(O.ADD, 0.0, np.abs(v), off), L, what=f"shift {shift}")
+    if dt == np.float32:
+        g = rng.uniform(-1, 1, len(L)).astype(np.float32)
+        gv = torch.full((int(off[-1]) + 1,), 5.0, device=DEV)
+        abi.mx_segmented_sum_adjoint_f32(dev(g), dev(off), gv[1:])
+        assert np.array_equal(host(gv[1:]), O.segmented_sum_adjoint(g, off).astype(np.float32))
+        assert host(gv[:1])[0] == 5.0
+
+
 def test_segmented_sum_adjoint_broadcast_exact():
     say("segmented adjoint")
     L, v, off = _ragged(4000, 3, lmax=2000, empty_rows=30)
