@@ -41,8 +41,9 @@
  *   mx_workspace_bytes(kind, ...) bytes of device memory, 256-byte aligned, which
  *   must be zero-filled before its first use.  Every successful call leaves the
  *   workspace's counters zero again, so one buffer can be reused (and captured in
- *   a HIP graph) without clearing.  Calls that share a workspace must be ordered
- *   on one stream.
+ *   a HIP graph) without clearing.  A buffer serves one workspace kind: other
+ *   kinds leave partial results in it.  Calls that share a workspace must be
+ *   ordered on one stream.
  */
 #ifndef MX_H
 #define MX_H
@@ -131,7 +132,10 @@ mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t s
  * i.e. the offsets array of the flat layout of a ragged sequence [[T]].
  * lengths: int64[nseg] device; offsets: int64[nseg+1] device (may not alias
  * lengths).  Negative lengths are the caller's error (checked in debug mode,
- * MX_ERR_SHAPE).  Workspace kind MX_WS_SCAN with n = nseg. */
+ * MX_ERR_SHAPE); offsets must stay below 2^62.  Workspace kind MX_WS_SCAN with
+ * n = nseg (unused for nseg <= 4096); the call leaves it all zero again.
+ * One pass over the lengths: tiles of 4096 rows chained by decoupled
+ * look-back through status words in the workspace. */
 mx_status mx_lengths_to_offsets(const int64_t *lengths_dev, int64_t nseg, int64_t *offsets_dev,
                                 void *ws, size_t ws_bytes, hipStream_t stream);
 

@@ -10,11 +10,18 @@
 // barrier per slice; the next slice's global loads are issued before the
 // current slice's MFMAs.
 //
-// MFMA step s of a slice takes k = 4s + g in lane group g = lane / 16, which
-// reads both layouts without LDS bank conflicts (the strides are 4 and 16
-// banks apart).  The reduction over k is associative, so when both operands
-// are [row][k] the slice's k values are instead dealt as k = 8g + s, making
-// each lane's eight values contiguous (two 16-byte LDS reads per fragment).
+// Fragments.  MFMA step s of a slice takes k = 8g + s in lane group
+// g = lane / 16 (the reduction over k is associative, so any fixed dealing of
+// the 32 k values over steps and lane groups is valid), and every operand is
+// read from LDS in vectors:
+//  * [row][k] operand: lane (g, l16) needs the 8 consecutive k values 8g..8g+7
+//    of one row per 16-row block -- two 16-byte reads per block per slice;
+//  * [k][row] operand with R 16-row blocks per wave: at step s the lane reads
+//    rows R*l16 .. R*l16 + R-1 of LDS row k = 8g + s in one 8- or 16-byte
+//    read, and value c feeds the MFMA of block c.  Block c thus covers the
+//    interleaved rows R*rho + c of the wave's tile (rho = 0..15), which the
+//    epilogue maps back; for C's columns this makes each lane's R outputs
+//    contiguous, so they are stored as one vector.
 #include <cstdlib>
 #include <cstring>
 
@@ -86,13 +93,15 @@ __device__ __forceinline__ void store_slice(float *__restrict__ s, const float4 
     }
 }
 
-// Value for MFMA step `step` of a slice, row `row` of the operand tile.
-template <int ROWS, bool ROWK, bool PERM>
-__device__ __forceinline__ float frag(const float *__restrict__ s, int row, int g, int step) {
-    using Op = Operand<ROWS, ROWK>;
-    if constexpr (PERM) return s[row * Op::LD + 8 * g + step];
-    else if constexpr (ROWK) return s[row * Op::LD + 4 * step + g];
-    else return s[(4 * step + g) * Op::LD + row];
+template <int R> struct VecOf;
+template <> struct VecOf<1> { using T = float; };
+template <> struct VecOf<2> { using T = float2; };
+template <> struct VecOf<4> { using T = float4; };
+
+// R consecutive floats from LDS (16-byte aligned for R = 4, 8-byte for R = 2)
+template <int R> __device__ __forceinline__ void lds_read(float (&v)[R], const float *p) {
+    const typename VecOf<R>::T t = *reinterpret_cast<const typename VecOf<R>::T *>(p);
+    __builtin_memcpy(v, &t, sizeof t);
 }
 
 // Tile scheduling: consecutive blocks land on different XCDs (round robin over
@@ -115,13 +124,14 @@ __device__ __forceinline__ void tile_of(int b, int tiles_m, int tiles_n, int &tm
 template <int BM, int BN, int WM, int WN, int TA, int TB>
 __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restrict__ A, const float *__restrict__ B,
                                                             float *__restrict__ C, int64_t M, int64_t N, int64_t K,
-                                                            int tiles_m, int tiles_n, int vec_ok) {
+                                                            int tiles_m, int tiles_n, int vec_ok, int cvec) {
     constexpr int NT = 64 * WM * WN;
     static_assert((BM * BK / 4) % NT == 0 && (BN * BK / 4) % NT == 0, "slice loads must split evenly");
     static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tiles are whole 16 x 16 blocks");
     constexpr bool RA = !TA, RB = TB;  // [row][k] in memory
-    constexpr bool PERM = RA && RB;
     constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
+    static_assert(RA || MI == 1 || MI == 2 || MI == 4, "[k][row] A: reads of 1, 2 or 4 rows");
+    static_assert(RB || NI == 1 || NI == 2 || NI == 4, "[k][row] B: reads of 1, 2 or 4 columns");
     using OA = Operand<BM, RA>;
     using OB = Operand<BN, RB>;
     __shared__ __attribute__((aligned(16))) float As[2][OA::FLOATS];
@@ -154,7 +164,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
     }
     __syncthreads();
 
-    const int arow = wm * (BM / WM) + l16, brow = wn * (BN / WN) + l16;
+    const int wrow0 = wm * (BM / WM), wcol0 = wn * (BN / WN);
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
@@ -166,13 +176,40 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
         }
         const float *as = As[buf];
         const float *bs = Bs[buf];
+        float a8[RA ? MI : 1][8], b8[RB ? NI : 1][8];
+        if constexpr (RA) {
+#pragma unroll
+            for (int i = 0; i < MI; ++i) {
+                const float *q = as + (wrow0 + 16 * i + l16) * OA::LD + 8 * g;
+                float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
+                a8[i][0] = lo.x; a8[i][1] = lo.y; a8[i][2] = lo.z; a8[i][3] = lo.w;
+                a8[i][4] = hi.x; a8[i][5] = hi.y; a8[i][6] = hi.z; a8[i][7] = hi.w;
+            }
+        }
+        if constexpr (RB) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                const float *q = bs + (wcol0 + 16 * j + l16) * OB::LD + 8 * g;
+                float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
+                b8[j][0] = lo.x; b8[j][1] = lo.y; b8[j][2] = lo.z; b8[j][3] = lo.w;
+                b8[j][4] = hi.x; b8[j][5] = hi.y; b8[j][6] = hi.z; b8[j][7] = hi.w;
+            }
+        }
 #pragma unroll
         for (int step = 0; step < 8; ++step) {
             float av[MI], bv[NI];
+            if constexpr (RA) {
 #pragma unroll
-            for (int i = 0; i < MI; ++i) av[i] = frag<BM, RA, PERM>(as, arow + 16 * i, g, step);
+                for (int i = 0; i < MI; ++i) av[i] = a8[i][step];
+            } else {
+                lds_read<MI>(av, as + (8 * g + step) * OA::LD + wrow0 + MI * l16);
+            }
+            if constexpr (RB) {
 #pragma unroll
-            for (int j = 0; j < NI; ++j) bv[j] = frag<BN, RB, PERM>(bs, brow + 16 * j, g, step);
+                for (int j = 0; j < NI; ++j) bv[j] = b8[j][step];
+            } else {
+                lds_read<NI>(bv, bs + (8 * g + step) * OB::LD + wcol0 + NI * l16);
+            }
 #pragma unroll
             for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -186,16 +223,35 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
         __syncthreads();
     }
 
-    // D block (i, j): lane holds rows 4g .. 4g+3 of column l16
+    // D block (i, j): lane holds block rows rho = 4g .. 4g+3 of block column
+    // l16; blocked or interleaved as the operand layout dealt them
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
 #pragma unroll
-        for (int j = 0; j < NI; ++j) {
-            const int64_t col = n0 + wn * (BN / WN) + j * 16 + l16;
+        for (int r = 0; r < 4; ++r) {
+            const int rho = 4 * g + r;
+            const int64_t row = m0 + wrow0 + (RA ? 16 * i + rho : MI * rho + i);
+            if constexpr (!RB) {
+                // the lane's NI columns NI*l16 .. NI*l16 + NI-1 are contiguous
+                const int64_t col = n0 + wcol0 + NI * l16;
+                if (interior && cvec) {
+                    float v[NI];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * (BM / WM) + i * 16 + 4 * g + r;
-                if (interior || (row < M && col < N)) C[row * N + col] = acc[i][j][r];
+                    for (int j = 0; j < NI; ++j) v[j] = acc[i][j][r];
+                    typename VecOf<NI>::T t;
+                    __builtin_memcpy(&t, v, sizeof t);
+                    *reinterpret_cast<typename VecOf<NI>::T *>(C + row * N + col) = t;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NI; ++j)
+                        if (row < M && col + j < N) C[row * N + col + j] = acc[i][j][r];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NI; ++j) {
+                    const int64_t col = n0 + wcol0 + 16 * j + l16;
+                    if (interior || (row < M && col < N)) C[row * N + col] = acc[i][j][r];
+                }
             }
         }
     }
@@ -236,12 +292,13 @@ mx_status check(const char *who, int ta, int tb, int64_t M, int64_t N, int64_t K
 template <int BM, int BN, int WM, int WN>
 mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A, const float *B, float *C,
                       int vec_ok, hipStream_t s) {
+    const int cvec = ((uintptr_t)C % 16 == 0) && (N % 4 == 0);
     const int64_t tiles_m = ceil_div(M, BM), tiles_n = ceil_div(N, BN);
     MX_REQUIRE(tiles_m * tiles_n < (1LL << 31), MX_ERR_SHAPE, "mx_map_map_reduce_f32: too many tiles");
     const dim3 grid((unsigned)(tiles_m * tiles_n)), block(64 * WM * WN);
 #define MX_GEMM(TA, TB)                                                                                    \
     hipLaunchKernelGGL((k_gemm_mfma<BM, BN, WM, WN, TA, TB>), grid, block, 0, s, A, B, C, M, N, K, (int)tiles_m, \
-                       (int)tiles_n, vec_ok)
+                       (int)tiles_n, vec_ok, cvec)
     if (!ta && !tb) MX_GEMM(0, 0);
     else if (!ta && tb) MX_GEMM(0, 1);
     else if (ta && !tb) MX_GEMM(1, 0);

@@ -246,11 +246,18 @@ __global__ void __launch_bounds__(NT) k_seg_broadcast(const float *__restrict__ 
 }
 
 // ---------------------------------------------------------------- lengths -> offsets
-// Tiles of 4096 rows (16 per thread).  Pass 1 sums each tile; pass 2 gives each
-// tile its prefix (the sum of earlier tile sums, or a pre-scanned prefix for
-// very many tiles) and scans the tile in LDS.
+// Tiles of 4096 rows (16 per thread), scanned in LDS (padded against bank
+// conflicts).  One tile: one block.  More: a single pass with decoupled
+// look-back -- blocks claim tiles in order from a counter, publish their
+// tile's total, then walk back over earlier tiles' published totals until one
+// carries its inclusive prefix, and publish their own.  A status word packs
+// the flag (2 bits) with the value (62 bits), so one relaxed device-scope
+// atomic carries both; tile i waits only on tiles claimed before it, whose
+// blocks are running, so the wait always ends.  The last block to finish
+// clears the status words and counters for the next call.
 constexpr int kScanPer = 16;
 constexpr int kScanTile = NT * kScanPer;
+constexpr uint64_t kStatAgg = 1ull << 62, kStatPre = 2ull << 62, kStatVal = (1ull << 62) - 1;
 // one pad slot per 16 entries keeps the per-thread runs of 16 on distinct banks
 __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 
@@ -275,53 +282,29 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *wsum, int
     return before + incl - v;
 }
 
-__global__ void __launch_bounds__(NT) k_scan_tilesum(const int64_t *__restrict__ len, int64_t n,
-                                                     int64_t *__restrict__ tile_sum) {
-    __shared__ int64_t smem[NT / kWave];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int64_t s = 0;
-#pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
-        int64_t i = base + j * NT + threadIdx.x;
-        if (i < n) s += len[i];
-    }
-    s = block_reduce<Red<MX_ADD, int64_t>, NT>(s, smem);
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+__device__ __forceinline__ uint64_t status_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Single block: exclusive scan of the tile sums in place (used when there are
-// too many tiles for each tile to sum its predecessors).
-__global__ void __launch_bounds__(NT) k_scan_tilesum_prefix(int64_t *tile_sum, int64_t ntiles) {
-    __shared__ int64_t wsum[NT / kWave];
-    int64_t carry = 0;
-    for (int64_t base = 0; base < ntiles; base += NT) {
-        int64_t i = base + threadIdx.x;
-        int64_t v = i < ntiles ? tile_sum[i] : 0;
-        int64_t total;
-        int64_t ex = block_excl_scan(v, wsum, &total);
-        if (i < ntiles) tile_sum[i] = carry + ex;
-        carry += total;
-        __syncthreads();
-    }
-}
-
+// counters[0]: next tile to claim; counters[1]: blocks finished.  LOOKBACK
+// false: a single block scans the single tile.
+template <bool LOOKBACK>
 __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ len, int64_t n,
-                                                   int64_t *__restrict__ off,
-                                                   const int64_t *__restrict__ tile_sum,
-                                                   int prefix_mode) {
+                                                   int64_t *__restrict__ off, unsigned *counters,
+                                                   uint64_t *status, int ntiles) {
     __shared__ int64_t tile[kScanTile + kScanTile / 16];
     __shared__ int64_t wsum[NT / kWave];
-    __shared__ int64_t red[NT / kWave];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    // prefix of this tile
-    int64_t prefix = 0;
-    if (prefix_mode == 1) {
-        int64_t p = 0;
-        for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += NT) p += tile_sum[t];
-        prefix = block_reduce<Red<MX_ADD, int64_t>, NT>(p, red);
-    } else if (prefix_mode == 2) {
-        prefix = tile_sum[blockIdx.x];
+    __shared__ int64_t sh_prefix;
+    __shared__ int sh_tile, sh_last;
+    if (LOOKBACK) {
+        if (threadIdx.x == 0) sh_tile = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
     }
+    const int t = LOOKBACK ? sh_tile : 0;
+    const int64_t base = (int64_t)t * kScanTile;
     // coalesced load into LDS
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
@@ -337,7 +320,28 @@ __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ l
         s += mine[j];
     }
     int64_t total;
-    int64_t run = prefix + block_excl_scan(s, wsum, &total);
+    const int64_t ex = block_excl_scan(s, wsum, &total);
+    if (threadIdx.x == 0) {
+        int64_t prefix = 0;
+        if (LOOKBACK) {
+            if (t == 0) {
+                status_store(&status[0], kStatPre | ((uint64_t)total & kStatVal));
+            } else {
+                status_store(&status[t], kStatAgg | ((uint64_t)total & kStatVal));
+                for (int p = t - 1;; --p) {
+                    uint64_t w;
+                    while (((w = status_load(&status[p])) >> 62) == 0) __builtin_amdgcn_s_sleep(1);
+                    prefix += (int64_t)(w & kStatVal);
+                    if ((w >> 62) == 2 || p == 0) break;
+                }
+                status_store(&status[t], kStatPre | ((uint64_t)(prefix + total) & kStatVal));
+            }
+        }
+        sh_prefix = prefix;
+    }
+    __syncthreads();
+    const int64_t prefix = sh_prefix;
+    int64_t run = prefix + ex;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
         tile[spad(threadIdx.x * kScanPer + j)] = run;
@@ -350,6 +354,18 @@ __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ l
         if (i < n) off[i] = tile[spad(j * NT + threadIdx.x)];
     }
     if (base + kScanTile >= n && threadIdx.x == 0) off[n] = prefix + total;
+    if (LOOKBACK) {
+        // every other block has finished its look-back when the last one arrives
+        if (threadIdx.x == 0) sh_last = atomicAdd(&counters[1], 1u) == (unsigned)ntiles - 1;
+        __syncthreads();
+        if (sh_last) {
+            for (int i = threadIdx.x; i < ntiles; i += NT) status_store(&status[i], 0);
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(&counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(NT) k_compose(const int64_t *__restrict__ outer, int64_t nouter,
@@ -432,20 +448,17 @@ mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, voi
     const int64_t ntiles = ceil_div(nseg, kScanTile);
     MX_REQUIRE(ntiles <= 0x7fffffff, MX_ERR_SHAPE, "mx_lengths_to_offsets: too many rows");
     if (ntiles <= 1) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(NT), 0, s, len, nseg, off, (const int64_t *)nullptr, 0);
+        hipLaunchKernelGGL(k_scan_tiles<false>, dim3(1), dim3(NT), 0, s, len, nseg, off, (unsigned *)nullptr,
+                           (uint64_t *)nullptr, 1);
         return last_launch("mx_lengths_to_offsets");
     }
     size_t need = mx_workspace_bytes(MX_WS_SCAN, nseg, 0);
     MX_REQUIRE(ws && ws_bytes >= need, MX_ERR_WORKSPACE, "mx_lengths_to_offsets: workspace needs %zu bytes", need);
-    int64_t *tile_sum = (int64_t *)((char *)ws + kCounterBytes);
-    hipLaunchKernelGGL(k_scan_tilesum, dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, tile_sum);
-    int mode = 1;
-    if (ntiles > 2048) {
-        hipLaunchKernelGGL(k_scan_tilesum_prefix, dim3(1), dim3(NT), 0, s, tile_sum, ntiles);
-        mode = 2;
-    }
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, off,
-                       (const int64_t *)tile_sum, mode);
+    MX_REQUIRE(((uintptr_t)ws & 255) == 0, MX_ERR_INVALID, "mx_lengths_to_offsets: workspace must be 256-byte aligned");
+    unsigned *counters = (unsigned *)ws;
+    uint64_t *status = (uint64_t *)((char *)ws + kCounterBytes);
+    hipLaunchKernelGGL(k_scan_tiles<true>, dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, off, counters, status,
+                       (int)ntiles);
     return last_launch("mx_lengths_to_offsets");
 }
 

@@ -214,6 +214,19 @@ def test_lengths_to_offsets_exact(nseg):
     assert np.array_equal(off, O.offsets_from_lengths(L))
 
 
+def test_lengths_to_offsets_reuse_and_wide_values():
+    """Consecutive scans of different sizes share one workspace (the look-back
+    status words must come back cleared), and sums beyond 32 bits stay exact."""
+    say("offsets reuse")
+    ws = api.workspace(abi.MX_WS_SCAN, 9_000_001)
+    for nseg, lmax in ((65536, 4096), (4097, 10), (9_000_001, 100), (8193, 1 << 40), (65536, 4096)):
+        L = W.ragged_lengths(nseg, seed=nseg, lmax=lmax)
+        off = torch.empty(nseg + 1, dtype=torch.int64, device=DEV)
+        abi.mx_lengths_to_offsets(dev(L), off, ws)
+        assert np.array_equal(host(off), O.offsets_from_lengths(L)), nseg
+    assert not host(ws).any(), "scan workspace not left zero"
+
+
 def test_marshal_rows_roundtrip_and_flatten():
     say("marshal rows")
     L, v = W.ragged_f32(3000, seed=5, lmax=700, empty_rows=40)
