@@ -35,6 +35,8 @@ constexpr int NT = 256;
 constexpr int kDot = 0, kMatvec = 1;
 constexpr int kMinTile = 4096;
 
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 struct TaskDev {
     int32_t kind, pad;
     int64_t rows, cols, a_off, b_off, out_off;
@@ -67,7 +69,7 @@ __device__ __forceinline__ int64_t next_tile(unsigned *ticket, int64_t *slot) {
 __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ tasks, const TileDev *__restrict__ tiles,
                                                   int64_t ntiles, const float *__restrict__ A,
                                                   const float *__restrict__ B, float *__restrict__ out,
-                                                  float *__restrict__ part, unsigned *ticket) {
+                                                  float *__restrict__ part, unsigned *ticket, int vec) {
     __shared__ int64_t slot;
     __shared__ float red[NT / kWave];
     using R = Red<MX_ADD, float>;
@@ -79,18 +81,40 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
         if (tk.kind == kDot) {
             const float *a = A + tk.a_off, *b = B + tk.b_off;
             float ac[4] = {0.f, 0.f, 0.f, 0.f};
-            int64_t e = tl.begin + threadIdx.x;
-            for (; e + 3 * NT < tl.end; e += 4 * NT) {
-                float av[4], bv[4];
+            if (vec && ((tk.a_off | tk.b_off | tl.begin) & 3) == 0) {
+                // 16-byte vectors, four per operand in flight, scalar tail
+                const float4 *a4 = reinterpret_cast<const float4 *>(a), *b4 = reinterpret_cast<const float4 *>(b);
+                const int64_t ve = tl.end >> 2;
+                int64_t i = (tl.begin >> 2) + threadIdx.x;
+                for (; i + 3 * NT < ve; i += 4 * NT) {
+                    float4 x[4], y[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    av[u] = a[e + u * NT];
-                    bv[u] = b[e + u * NT];
+                    for (int u = 0; u < 4; ++u) {
+                        x[u] = a4[i + u * NT];
+                        y[u] = b4[i + u * NT];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) ac[u] += x[u].x * y[u].x + x[u].y * y[u].y + x[u].z * y[u].z + x[u].w * y[u].w;
                 }
+                for (; i < ve; i += NT) {
+                    const float4 x = a4[i], y = b4[i];
+                    ac[0] += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+                }
+                for (int64_t e = 4 * ve + threadIdx.x; e < tl.end; e += NT) ac[1] += a[e] * b[e];
+            } else {
+                int64_t e = tl.begin + threadIdx.x;
+                for (; e + 3 * NT < tl.end; e += 4 * NT) {
+                    float av[4], bv[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) ac[u] += av[u] * bv[u];
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = a[e + u * NT];
+                        bv[u] = b[e + u * NT];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) ac[u] += av[u] * bv[u];
+                }
+                for (; e < tl.end; e += NT) ac[0] += a[e] * b[e];
             }
-            for (; e < tl.end; e += NT) ac[0] += a[e] * b[e];
             float acc = block_reduce<R, NT>((ac[0] + ac[1]) + (ac[2] + ac[3]), red);
             if (threadIdx.x == 0) {
                 if (tl.part >= 0) part[tl.part] = acc;
@@ -101,23 +125,46 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
             const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
             const int64_t c = tk.cols;
             const float *x = B + tk.b_off;
+            const bool v4 = vec && ((tk.a_off | tk.b_off | c) & 3) == 0;
             for (int64_t r0 = tl.begin; r0 < tl.end; r0 += NT / 16) {
                 const int64_t r = r0 + grp;
                 float ac[4] = {0.f, 0.f, 0.f, 0.f};
                 if (r < tl.end) {
                     const float *row = A + tk.a_off + r * c;
-                    int64_t j = l;
-                    for (; j + 48 < c; j += 64) {
-                        float av[4], xv[4];
+                    if (v4) {
+                        const float4 *row4 = reinterpret_cast<const float4 *>(row);
+                        const float4 *x4 = reinterpret_cast<const float4 *>(x);
+                        const int64_t c4 = c >> 2;
+                        int64_t j = l;
+                        for (; j + 48 < c4; j += 64) {
+                            float4 av[4], xv[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            av[u] = row[j + 16 * u];
-                            xv[u] = x[j + 16 * u];
+                            for (int u = 0; u < 4; ++u) {
+                                av[u] = row4[j + 16 * u];
+                                xv[u] = x4[j + 16 * u];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                ac[u] += av[u].x * xv[u].x + av[u].y * xv[u].y + av[u].z * xv[u].z + av[u].w * xv[u].w;
                         }
+                        for (; j < c4; j += 16) {
+                            const float4 av = row4[j], xv = x4[j];
+                            ac[0] += av.x * xv.x + av.y * xv.y + av.z * xv.z + av.w * xv.w;
+                        }
+                    } else {
+                        int64_t j = l;
+                        for (; j + 48 < c; j += 64) {
+                            float av[4], xv[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) ac[u] += av[u] * xv[u];
+                            for (int u = 0; u < 4; ++u) {
+                                av[u] = row[j + 16 * u];
+                                xv[u] = x[j + 16 * u];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) ac[u] += av[u] * xv[u];
+                        }
+                        for (; j < c; j += 16) ac[0] += row[j] * x[j];
                     }
-                    for (; j < c; j += 16) ac[0] += row[j] * x[j];
                 }
                 const float acc = row16_sum((ac[0] + ac[1]) + (ac[2] + ac[3]));
                 if (l == 0 && r < tl.end) out[tk.out_off + r] = acc;
@@ -130,7 +177,7 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
                                                   int64_t ntiles, const float *__restrict__ A,
                                                   const float *__restrict__ B, const float *__restrict__ gout,
                                                   float *__restrict__ gA, float *__restrict__ gB,
-                                                  float *__restrict__ part, unsigned *ticket) {
+                                                  float *__restrict__ part, unsigned *ticket, int vec) {
     __shared__ int64_t slot;
     for (;;) {
         const int64_t t = next_tile(ticket, &slot);
@@ -142,17 +189,43 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             const float *a = A + tk.a_off, *b = B + tk.b_off;
             float *ga = gA + tk.a_off, *gb = gB + tk.b_off;
             int64_t e = tl.begin + threadIdx.x;
-            for (; e + 3 * NT < tl.end; e += 4 * NT) {
-                float av[4], bv[4];
+            if (vec && ((tk.a_off | tk.b_off | tl.begin) & 3) == 0) {
+                const float4 *a4 = reinterpret_cast<const float4 *>(a), *b4 = reinterpret_cast<const float4 *>(b);
+                float4 *ga4 = reinterpret_cast<float4 *>(ga), *gb4 = reinterpret_cast<float4 *>(gb);
+                const int64_t ve = tl.end >> 2;
+                int64_t i = (tl.begin >> 2) + threadIdx.x;
+                for (; i + 3 * NT < ve; i += 4 * NT) {
+                    float4 x[4], y[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    av[u] = a[e + u * NT];
-                    bv[u] = b[e + u * NT];
+                    for (int u = 0; u < 4; ++u) {
+                        x[u] = a4[i + u * NT];
+                        y[u] = b4[i + u * NT];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ga4[i + u * NT] = make_float4(g * y[u].x, g * y[u].y, g * y[u].z, g * y[u].w);
+                        gb4[i + u * NT] = make_float4(g * x[u].x, g * x[u].y, g * x[u].z, g * x[u].w);
+                    }
                 }
+                for (; i < ve; i += NT) {
+                    const float4 x = a4[i], y = b4[i];
+                    ga4[i] = make_float4(g * y.x, g * y.y, g * y.z, g * y.w);
+                    gb4[i] = make_float4(g * x.x, g * x.y, g * x.z, g * x.w);
+                }
+                e = 4 * ve + threadIdx.x;
+            } else {
+                for (; e + 3 * NT < tl.end; e += 4 * NT) {
+                    float av[4], bv[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ga[e + u * NT] = g * bv[u];
-                    gb[e + u * NT] = g * av[u];
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = a[e + u * NT];
+                        bv[u] = b[e + u * NT];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ga[e + u * NT] = g * bv[u];
+                        gb[e + u * NT] = g * av[u];
+                    }
                 }
             }
             for (; e < tl.end; e += NT) {
@@ -164,30 +237,73 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             const float *x = B + tk.b_off, *g = gout + tk.out_off;
             const float *a = A + tk.a_off;
             float *ga = gA + tk.a_off;
-            for (int64_t j = threadIdx.x; j < c; j += NT) {
-                const float xj = x[j];
-                float acc = 0.f;
-                int64_t r = tl.begin;
-                for (; r + 3 < tl.end; r += 4) {
-                    float av[4], gv[4];
+            if (vec && ((tk.a_off | tk.b_off | c) & 3) == 0) {
+                // four consecutive columns per thread
+                const int64_t c4 = c >> 2;
+                const float4 *a4 = reinterpret_cast<const float4 *>(a), *x4 = reinterpret_cast<const float4 *>(x);
+                float4 *ga4 = reinterpret_cast<float4 *>(ga);
+                for (int64_t j = threadIdx.x; j < c4; j += NT) {
+                    const float4 xj = x4[j];
+                    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                    int64_t r = tl.begin;
+                    for (; r + 3 < tl.end; r += 4) {
+                        float4 av[4];
+                        float gv[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        av[u] = a[(r + u) * c + j];
-                        gv[u] = g[r + u];
-                    }
+                        for (int u = 0; u < 4; ++u) {
+                            av[u] = a4[(r + u) * c4 + j];
+                            gv[u] = g[r + u];
+                        }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        acc += av[u] * gv[u];
-                        ga[(r + u) * c + j] = gv[u] * xj;
+                        for (int u = 0; u < 4; ++u) {
+                            acc.x += av[u].x * gv[u];
+                            acc.y += av[u].y * gv[u];
+                            acc.z += av[u].z * gv[u];
+                            acc.w += av[u].w * gv[u];
+                            ga4[(r + u) * c4 + j] = make_float4(gv[u] * xj.x, gv[u] * xj.y, gv[u] * xj.z, gv[u] * xj.w);
+                        }
                     }
+                    for (; r < tl.end; ++r) {
+                        const float gr = g[r];
+                        const float4 av = a4[r * c4 + j];
+                        acc.x += av.x * gr;
+                        acc.y += av.y * gr;
+                        acc.z += av.z * gr;
+                        acc.w += av.w * gr;
+                        ga4[r * c4 + j] = make_float4(gr * xj.x, gr * xj.y, gr * xj.z, gr * xj.w);
+                    }
+                    float *dst = tl.part >= 0 ? part + tl.part + 4 * j : gB + tk.b_off + 4 * j;
+                    dst[0] = acc.x;
+                    dst[1] = acc.y;
+                    dst[2] = acc.z;
+                    dst[3] = acc.w;
                 }
-                for (; r < tl.end; ++r) {
-                    const float gr = g[r];
-                    acc += a[r * c + j] * gr;
-                    ga[r * c + j] = gr * xj;
+            } else {
+                for (int64_t j = threadIdx.x; j < c; j += NT) {
+                    const float xj = x[j];
+                    float acc = 0.f;
+                    int64_t r = tl.begin;
+                    for (; r + 3 < tl.end; r += 4) {
+                        float av[4], gv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            av[u] = a[(r + u) * c + j];
+                            gv[u] = g[r + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            acc += av[u] * gv[u];
+                            ga[(r + u) * c + j] = gv[u] * xj;
+                        }
+                    }
+                    for (; r < tl.end; ++r) {
+                        const float gr = g[r];
+                        acc += a[r * c + j] * gr;
+                        ga[r * c + j] = gr * xj;
+                    }
+                    if (tl.part >= 0) part[tl.part + j] = acc;
+                    else gB[tk.b_off + j] = acc;
                 }
-                if (tl.part >= 0) part[tl.part + j] = acc;
-                else gB[tk.b_off + j] = acc;
             }
         }
     }
@@ -422,8 +538,9 @@ int grid_of(const mx_batch_plan *p, int64_t ntiles) {
 mx_status fwd_impl(const mx_batch_plan *p, const float *A, const float *B, float *out, void *ws, hipStream_t s) {
     unsigned *ticket = (unsigned *)ws;
     float *part = fwd_part_ptr(p, ws);
+    const int vec = aligned16(A) && aligned16(B);
     hipLaunchKernelGGL(k_batch_fwd, dim3(grid_of(p, p->n_fwd)), dim3(NT), 0, s, p->d_tasks, p->d_fwd, p->n_fwd, A, B,
-                       out, part, ticket);
+                       out, part, ticket, vec);
     hipLaunchKernelGGL(k_batch_combine_fwd, dim3((unsigned)std::max<int64_t>(1, ceil_div(p->n_fwd_list, NT))),
                        dim3(NT), 0, s, p->d_tasks, p->d_fwd_list, p->n_fwd_list, part, out, ticket);
     return last_launch("mx_batch_forward");
@@ -433,8 +550,9 @@ mx_status bwd_impl(const mx_batch_plan *p, const float *A, const float *B, const
                    void *ws, hipStream_t s) {
     unsigned *ticket = (unsigned *)ws + 1;
     float *part = bwd_part_ptr(p, ws);
+    const int vec = aligned16(A) && aligned16(B) && aligned16(gA) && aligned16(gB);
     hipLaunchKernelGGL(k_batch_bwd, dim3(grid_of(p, p->n_bwd)), dim3(NT), 0, s, p->d_tasks, p->d_bwd, p->n_bwd, A, B,
-                       gout, gA, gB, part, ticket);
+                       gout, gA, gB, part, ticket, vec);
     hipLaunchKernelGGL(k_batch_combine_bwd, dim3((unsigned)std::max<int64_t>(1, p->n_bwd_list)), dim3(NT), 0, s,
                        p->d_tasks, p->d_bwd_list, p->n_bwd_list, part, gB, ticket);
     return last_launch("mx_batch_backward");

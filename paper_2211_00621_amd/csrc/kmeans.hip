@@ -18,11 +18,20 @@
 // oracle's operation order -- subtract, square, add, no fused multiply-add --
 // and takes the lexicographic minimum, so labels are bit-exact in all cases.
 //
-// Reduce-by-key without float atomics: each wave adds its points, one point at
-// a time with lanes = dimensions, into wave-private LDS sums in point order;
-// the block adds its waves in wave order and writes one partial per block; a
-// finish kernel adds the block partials in block order in binary64, divides
-// and writes the new centroids and the int64 counts.
+// Persistent waves: a fixed grid of at most kMaxBlocks blocks, each wave
+// walking its own sequence of 64-point chunks and loading the next chunk's
+// points while it works on the current one, so the stream of X from HBM
+// overlaps the matrix-core work.
+//
+// Reduce-by-key from the registers that already hold the chunk: lane
+// (g, l16) holds dimensions 8g..8g+7 of points mi*16 + l16 and adds them to
+// wave-private LDS sums.  Lanes whose points share a label are separated into
+// passes by their rank among equal labels, so no instruction has two lanes on
+// one address; a wave's LDS operations execute in issue order, so the sums
+// are the same on every run.  The block adds its waves in wave order and
+// writes one partial per block; a finish kernel adds the block partials in
+// block order in binary64, divides and writes the new centroids and the int64
+// counts.  The grid does not depend on the device, so neither do the results.
 #include <algorithm>
 #include <atomic>
 #include <cfloat>
@@ -34,10 +43,8 @@ namespace {
 
 constexpr int NT = 256;       // 4 waves
 constexpr int kWaves = NT / kWave;
-constexpr int kPtsWave = 64;  // points per wave per tile
-constexpr int kTile = kWaves * kPtsWave;
-constexpr int kTilesPerBlock = 4;
-constexpr int kPtsBlock = kTile * kTilesPerBlock;
+constexpr int kPtsWave = 64;  // points per wave chunk
+constexpr int kMaxBlocks = 512; // persistent grid (two blocks per CU on 256 CUs)
 constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -101,34 +108,63 @@ struct KmArgs {
     unsigned long long *fallbacks;  // optional counter of binary64 recomputations
 };
 
+// Orders this wave's LDS writes before its later LDS reads (a wave's LDS
+// operations execute in order; this only keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// X fragments of chunk c: point c*64 + mi*16 + l16, dims kc*32 + 8g .. +7
+template <int DP>
+__device__ __forceinline__ void load_chunk(float4 (&xa)[4][DP / 32][2], const KmArgs &a, int64_t c, int l16, int g,
+                                           bool vec_x) {
+    const int d = a.d;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+        const int64_t p = c * kPtsWave + mi * 16 + l16;
+#pragma unroll
+        for (int kc = 0; kc < DP / 32; ++kc) {
+            const int t0 = kc * 32 + 8 * g;
+            if (vec_x && p < a.n) {
+                const float4 *q = reinterpret_cast<const float4 *>(a.X + p * d + t0);
+                xa[mi][kc][0] = q[0];
+                xa[mi][kc][1] = q[1];
+            } else {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (p < a.n && t0 + e < d) ? a.X[p * d + t0 + e] : 0.f;
+                xa[mi][kc][0] = make_float4(v[0], v[1], v[2], v[3]);
+                xa[mi][kc][1] = make_float4(v[4], v[5], v[6], v[7]);
+            }
+        }
+    }
+}
+
 // DP: d padded to a multiple of 32; KP: k padded to a multiple of 64.
 template <int DP, int KP>
-__global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
+__global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_fused(KmArgs a) {
     constexpr int LDC = DP + 4;
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    float *Cs = smem;                            // [KP][LDC]
-    float *cnorm = Cs + KP * LDC;                // [KP]
-    float *sums = cnorm + KP;                    // [kWaves][k*d]
-    const int kd = a.k * a.d;
-    int *counts = (int *)(sums + kWaves * kd);   // [kWaves][k]
-    float *xnorm = (float *)(counts + kWaves * a.k);  // [kWaves][64]
-    float *best1 = xnorm + kWaves * kPtsWave;
-    float *best2 = best1 + kWaves * kPtsWave;
-    int *bidx = (int *)(best2 + kWaves * kPtsWave);
-    int *lab = bidx + kWaves * kPtsWave;         // [kWaves][64]
+    const int d = a.d, k = a.k, ldd = d + 1;  // odd row stride: labels spread over banks
+    float *Cs = smem;                                  // [KP][LDC]
+    float *cnorm = Cs + KP * LDC;                      // [KP]
+    float *sums_all = cnorm + KP;                      // [kWaves][k][ldd]
+    int *counts_all = (int *)(sums_all + kWaves * k * ldd);  // [kWaves][k]
+    float *scr = (float *)(counts_all + kWaves * k);   // [kWaves][5][64]
     __shared__ float cmax_s;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, g = lane >> 4;
-    const int d = a.d, k = a.k;
 
     // centroids into LDS (zero padded), their squared norms, the largest norm
     for (int e = tid; e < KP * LDC; e += NT) {
         const int j = e / LDC, t = e - j * LDC;
         Cs[e] = (j < k && t < d) ? a.C[(int64_t)j * d + t] : 0.f;
     }
-    for (int e = tid; e < kWaves * kd; e += NT) sums[e] = 0.f;
-    for (int e = tid; e < kWaves * k; e += NT) counts[e] = 0;
+    for (int e = tid; e < kWaves * k * ldd; e += NT) sums_all[e] = 0.f;
+    for (int e = tid; e < kWaves * k; e += NT) counts_all[e] = 0;
     __syncthreads();
     if (tid < KP) {
         float s = 0.f;
@@ -136,56 +172,50 @@ __global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
         cnorm[tid] = tid < k ? s : INFINITY;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {
         float m = 0.f;
-        for (int j = 0; j < k; ++j) m = fmaxf(m, cnorm[j]);
-        cmax_s = sqrtf(m);
+        for (int j = lane; j < k; j += kWave) m = fmaxf(m, cnorm[j]);
+        m = wave_reduce<Red<MX_MAX, float>>(m);
+        if (lane == 0) cmax_s = sqrtf(m);
     }
     __syncthreads();
     const float cmax = cmax_s;
     const float eps_factor = 2.0f * (float)(d + 8) * 5.9604645e-8f;  // 2 (d + 8) 2^-24
 
+    float *ws = sums_all + wave * k * ldd;
+    int *wc = counts_all + wave * k;
+    float *xnorm = scr + wave * 5 * kPtsWave;
+    float *best1 = xnorm + kPtsWave;
+    float *best2 = best1 + kPtsWave;
+    int *bidx = (int *)(best2 + kPtsWave);
+    int *lab = bidx + kPtsWave;
+
     const bool vec_x = (d == DP) && ((uintptr_t)a.X % 16 == 0);
-    for (int tile = 0; tile < kTilesPerBlock; ++tile) {
-        // the exit test is block-uniform: every wave reaches the same barriers
-        if ((int64_t)blockIdx.x * kPtsBlock + (int64_t)tile * kTile >= a.n) break;
-        const int64_t p0 = (int64_t)blockIdx.x * kPtsBlock + (int64_t)tile * kTile + wave * kPtsWave;
-        // ---- A fragments: point p0 + mi*16 + l16, dims kc*32 + 8g .. +7
-        float4 xa[4][DP / 32][2];
-        float xs[4];
+    const int64_t nchunks = (a.n + kPtsWave - 1) / kPtsWave;
+    const int64_t wstride = (int64_t)gridDim.x * kWaves;
+    int64_t c = (int64_t)blockIdx.x * kWaves + wave;  // wave-uniform
+    float4 xa[4][DP / 32][2];
+    if (c < nchunks) load_chunk<DP>(xa, a, c, l16, g, vec_x);
+    for (; c < nchunks; c += wstride) {
+        const int64_t p0 = c * kPtsWave;
+        // next chunk's points, in flight while this one is processed
+        float4 xn[4][DP / 32][2];
+        if (c + wstride < nchunks) load_chunk<DP>(xn, a, c + wstride, l16, g, vec_x);
+
+        // |x|^2: add the four lane groups g (lanes l16, l16+16, l16+32, l16+48)
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi) {
-            const int64_t p = p0 + mi * 16 + l16;
             float s = 0.f;
 #pragma unroll
-            for (int kc = 0; kc < DP / 32; ++kc) {
-                const int t0 = kc * 32 + 8 * g;
-                if (vec_x && p < a.n) {
-                    const float4 *q = reinterpret_cast<const float4 *>(a.X + p * d + t0);
-                    xa[mi][kc][0] = q[0];
-                    xa[mi][kc][1] = q[1];
-                } else {
-                    float v[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = (p < a.n && t0 + q < d) ? a.X[p * d + t0 + q] : 0.f;
-                    xa[mi][kc][0] = make_float4(v[0], v[1], v[2], v[3]);
-                    xa[mi][kc][1] = make_float4(v[4], v[5], v[6], v[7]);
-                }
+            for (int kc = 0; kc < DP / 32; ++kc)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const float4 u = xa[mi][kc][h];
                     s += u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w;
                 }
-            }
-            xs[mi] = s;
-        }
-        // |x|^2: add the four lane groups g (lanes l16, l16+16, l16+32, l16+48)
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-            float s = xs[mi];
             s += __shfl_xor(s, 16, 64);
             s += __shfl_xor(s, 32, 64);
-            if (g == 0) xnorm[wave * kPtsWave + mi * 16 + l16] = s;
+            if (g == 0) xnorm[mi * 16 + l16] = s;
         }
 
         // ---- f = |c|^2 - 2 x.c over column chunks of 64 centroids
@@ -243,25 +273,24 @@ __global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
             for (int r = 0; r < 4; ++r) {
                 const Best b = row_merge(bt[mi][r]);
                 if (l16 == 0) {
-                    const int pt = wave * kPtsWave + mi * 16 + 4 * g + r;
+                    const int pt = mi * 16 + 4 * g + r;
                     best1[pt] = b.b1;
                     best2[pt] = b.b2;
                     bidx[pt] = b.i1;
                 }
             }
-        __syncthreads();
-        // ---- certify each label; uncertified points are recomputed in binary64
-        //      by the whole wave, one point at a time, lanes over centroids
+        wave_sync();
+        // ---- certify each label (lane = point); uncertified points are
+        //      recomputed in binary64 by the whole wave, lanes over centroids
         {
             const int64_t p = p0 + lane;
-            const int pt = wave * kPtsWave + lane;
             int label = -1;
             bool certified = true;
             if (p < a.n) {
-                const float xn = sqrtf(xnorm[pt]) + cmax;
-                const float E = eps_factor * xn * xn;
-                certified = best2[pt] - best1[pt] > 2.0f * E;
-                label = bidx[pt];
+                const float xn_ = sqrtf(xnorm[lane]) + cmax;
+                const float E = eps_factor * xn_ * xn_;
+                certified = best2[lane] - best1[lane] > 2.0f * E;
+                label = bidx[lane];
             }
             uint64_t todo = __ballot(!certified);
             if (todo && a.fallbacks && lane == 0) atomicAdd(a.fallbacks, (unsigned long long)__popcll(todo));
@@ -284,45 +313,64 @@ __global__ void __launch_bounds__(NT) k_kmeans_fused(KmArgs a) {
                 if (lane == q) label = bj;
             }
             if (p < a.n) a.labels[p] = label;
-            lab[pt] = label;
+            lab[lane] = label;
+            if (label >= 0) atomicAdd(&wc[label], 1);  // integer: order-free
         }
-        __syncthreads();
-        // ---- reduce-by-key into wave-private sums, point order, lanes = dims
-        float *ws = sums + wave * kd;
-        int *wc = counts + wave * k;
-        for (int q0 = 0; q0 < kPtsWave; q0 += 16) {
-            float xv[16];
+        wave_sync();
+        // ---- reduce-by-key from registers: passes by rank among equal labels
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int64_t p = p0 + q0 + q;
-                xv[q] = (p < a.n && lane < d) ? a.X[p * d + lane] : 0.f;
+        for (int mi = 0; mi < 4; ++mi) {
+            const int L = lab[mi * 16 + l16];
+            int rank = 0;
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int4 lq = *reinterpret_cast<const int4 *>(lab + mi * 16 + 4 * q4);
+                rank += (4 * q4 + 0 < l16 && lq.x == L) + (4 * q4 + 1 < l16 && lq.y == L) +
+                        (4 * q4 + 2 < l16 && lq.z == L) + (4 * q4 + 3 < l16 && lq.w == L);
             }
+            for (int m = 0; __ballot(L >= 0 && rank >= m); ++m) {
+                if (L >= 0 && rank == m) {
+                    float *dst = ws + L * ldd;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int l = lab[wave * kPtsWave + q0 + q];
-                if (l >= 0) {
-                    if (lane < d) ws[l * d + lane] += xv[q];
-                    if (lane == 0) wc[l] += 1;
+                    for (int kc = 0; kc < DP / 32; ++kc)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int t = kc * 32 + 8 * g + 4 * h + e;
+                                if (t < d)
+                                    __hip_atomic_fetch_add(dst + t, vget<float4, float>(xa[mi][kc][h], e),
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int kc = 0; kc < DP / 32; ++kc) {
+                xa[mi][kc][0] = xn[mi][kc][0];
+                xa[mi][kc][1] = xn[mi][kc][1];
+            }
     }
     __syncthreads();
     // ---- block partial: waves added in wave order
+    const int kd = k * d;
     float *ps = a.part_sums + (int64_t)blockIdx.x * kd;
     for (int e = tid; e < kd; e += NT) {
-        float s = sums[e];
+        const int j = e / d, t = e - j * d;
+        float s = sums_all[j * ldd + t];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += sums[w * kd + e];
+        for (int w = 1; w < kWaves; ++w) s += sums_all[(w * k + j) * ldd + t];
         ps[e] = s;
     }
     int *pc = a.part_counts + (int64_t)blockIdx.x * k;
     for (int j = tid; j < k; j += NT) {
-        int c = counts[j];
+        int cn = counts_all[j];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) c += counts[w * k + j];
-        pc[j] = c;
+        for (int w = 1; w < kWaves; ++w) cn += counts_all[w * k + j];
+        pc[j] = cn;
     }
 }
 
@@ -492,10 +540,13 @@ __global__ void __launch_bounds__(NT) k_sse_grad(const float *__restrict__ X, in
 }
 
 // ---------------------------------------------------------------- sizes and dispatch
-int64_t fused_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kPtsBlock); }
+int64_t fused_blocks(int64_t n) {
+    const int64_t b = ceil_div(n > 0 ? n : 1, (int64_t)kWaves * kPtsWave);
+    return b < kMaxBlocks ? b : kMaxBlocks;
+}
 
 size_t fused_lds_bytes(int DP, int KP, int k, int d) {
-    return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * d * 4 + (size_t)kWaves * k * 4 +
+    return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * (d + 1) * 4 + (size_t)kWaves * k * 4 +
            (size_t)kWaves * kPtsWave * 4 * 5;
 }
 

@@ -76,23 +76,34 @@ mx_status validate_lengths(const char *who, const int64_t *len, int64_t n, hipSt
 
 // ---------------------------------------------------------------- block-span reduce
 // A block takes `rb` consecutive rows, whose values form one contiguous span
-// [offsets[r0], offsets[r0 + rb]).  Its threads stream the whole span in
-// 16-byte vectors (thread t takes vectors t, t + NT, ...; eight in flight),
-// so a block keeps about 32 KB of loads in flight whatever the row lengths,
-// and the offsets cost one round trip per rb rows instead of one per row.
+// [offsets[r0], offsets[r0 + rb]).  The span's 16-byte vectors are cut into
+// four contiguous quarters, one per wave; inside its quarter a wave's lanes
+// interleave (coalesced), eight vectors per lane in flight.  So a block keeps
+// up to 32 KB of loads in flight whatever the row lengths, and the offsets
+// cost one round trip per rb rows instead of one per row.
 //
 // Row attribution: the positions a thread visits increase, so the row they
 // fall in never decreases.  A thread keeps one accumulator for its current
 // row; on crossing a row end it parks that value in its own LDS slot
-// (row, thread) and starts afresh.  Afterwards each row's NT slots are folded
-// in a fixed order (four slots per lane, then the DPP wave tree), so the
-// result depends only on the offsets, never on timing.
+// (row, thread) and starts afresh.  A wave finds the row of its quarter's
+// first position with one ballot, so a lane crosses only the row ends inside
+// its quarter.  Afterwards each row's NT slots are folded in a fixed order
+// (four per lane, then the DPP wave tree), so the result depends only on the
+// offsets, never on timing.
 constexpr int kMaxRowsPerBlock = 16;
 
 // LDS: rb + 1 offsets (padded to 16 bytes), then rb x NT accumulator slots
 __host__ __device__ constexpr size_t span_off_bytes(int rb) { return ((size_t)(rb + 1) * 8 + 15) & ~(size_t)15; }
 template <mx_dtype D> constexpr size_t span_lds_bytes(int rb) {
     return span_off_bytes(rb) + (size_t)rb * NT * sizeof(typename DT<D>::Acc);
+}
+
+// row (0-based within the block) holding position p: the number of row ends
+// soff[1..nrows] at or before p, counted by one ballot (nrows < 64)
+__device__ __forceinline__ int row_of(const int64_t *soff, int nrows, int64_t p) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool past = lane < nrows && soff[lane + 1] <= p;
+    return __popcll(__ballot(past));
 }
 
 template <mx_dtype D, int OP>
@@ -106,10 +117,11 @@ __global__ void __launch_bounds__(NT) k_seg_span(const typename DT<D>::In *__res
     using R = Red<OP, Acc>;
     constexpr int V = DT<D>::kVec;
     constexpr int U = 8;
+    constexpr int NW = NT / kWave;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     int64_t *soff = reinterpret_cast<int64_t *>(lds);
     Acc *slot = reinterpret_cast<Acc *>(lds + span_off_bytes(rb));
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * rb;
     const int nrows = (int)(nseg - r0 < rb ? nseg - r0 : rb);  // >= 1: the grid covers nseg exactly
     if (t <= nrows) soff[t] = offsets[r0 + t];
@@ -131,19 +143,27 @@ __global__ void __launch_bounds__(NT) k_seg_span(const typename DT<D>::In *__res
         a = R::ap(a, x);
     };
     if (vec) {
-        const int64_t vs = (S + V - 1) / V, ve = E / V;  // whole vectors inside [S, E)
+        const int64_t vs = (S + V - 1) / V, ve = E / V > vs ? E / V : vs;  // whole vectors inside [S, E)
         const int64_t head_end = vs * V < E ? vs * V : E;
-        if (S + t < head_end) take(S + t, Acc(values[S + t]));
+        const int64_t q = (ve - vs + NW - 1) / NW;                          // vectors per wave
+        const int64_t cs = vs + w * q < ve ? vs + w * q : ve;
+        const int64_t ce = cs + q < ve ? cs + q : ve;
+        if (w == 0) {
+            if (S + lane < head_end) take(S + lane, Acc(values[S + lane]));
+        } else if (cs < ce) {
+            cur = row_of(soff, nrows, cs * V);
+            end = soff[cur + 1];
+        }
         const Vec *vv = reinterpret_cast<const Vec *>(values);
-        for (int64_t i = vs + t; i < ve; i += U * NT) {
+        for (int64_t i = cs + lane; i < ce; i += U * kWave) {
             Vec x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (i + u * NT < ve) x[u] = vv[i + u * NT];
+                if (i + u * kWave < ce) x[u] = vv[i + u * kWave];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (i + u * NT < ve) {
-                    const int64_t p0 = (i + u * NT) * V;
+                if (i + u * kWave < ce) {
+                    const int64_t p0 = (i + u * kWave) * V;
                     if (p0 + V - 1 < end) {
 #pragma unroll
                         for (int j = 0; j < V; ++j) a = R::ap(a, Acc(vget<Vec, In>(x[u], j)));
@@ -154,19 +174,24 @@ __global__ void __launch_bounds__(NT) k_seg_span(const typename DT<D>::In *__res
                 }
             }
         }
-        const int64_t tail_start = ve * V > head_end ? ve * V : head_end;
-        if (tail_start + t < E) take(tail_start + t, Acc(values[tail_start + t]));
+        if (w == NW - 1) {
+            const int64_t tail_start = ve * V > head_end ? ve * V : head_end;
+            if (cs >= ce && tail_start < E) {  // wave-uniform: no vectors, only the tail
+                cur = row_of(soff, nrows, tail_start);
+                end = soff[cur + 1];
+            }
+            if (tail_start + lane < E) take(tail_start + lane, Acc(values[tail_start + lane]));
+        }
     } else {
         for (int64_t i = S + t; i < E; i += NT) take(i, Acc(values[i]));
     }
     slot[cur * NT + t] = a;
     __syncthreads();
 
-    const int lane = t & (kWave - 1), w = t / kWave;
-    for (int k = w; k < nrows; k += NT / kWave) {
+    for (int k = w; k < nrows; k += NW) {
         Acc v = slot[k * NT + lane];
 #pragma unroll
-        for (int q = 1; q < NT / kWave; ++q) v = R::ap(v, slot[k * NT + q * kWave + lane]);
+        for (int qq = 1; qq < NW; ++qq) v = R::ap(v, slot[k * NT + qq * kWave + lane]);
         v = wave_reduce<R>(v);
         if (lane == 0) out[r0 + k] = R::ap(ne, v);
     }
@@ -321,23 +346,36 @@ __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ l
     }
     int64_t total;
     const int64_t ex = block_excl_scan(s, wsum, &total);
-    if (threadIdx.x == 0) {
-        int64_t prefix = 0;
-        if (LOOKBACK) {
-            if (t == 0) {
-                status_store(&status[0], kStatPre | ((uint64_t)total & kStatVal));
-            } else {
-                status_store(&status[t], kStatAgg | ((uint64_t)total & kStatVal));
-                for (int p = t - 1;; --p) {
-                    uint64_t w;
-                    while (((w = status_load(&status[p])) >> 62) == 0) __builtin_amdgcn_s_sleep(1);
-                    prefix += (int64_t)(w & kStatVal);
-                    if ((w >> 62) == 2 || p == 0) break;
+    if (LOOKBACK) {
+        if (threadIdx.x == 0)
+            status_store(&status[t], (t == 0 ? kStatPre : kStatAgg) | ((uint64_t)total & kStatVal));
+        if (threadIdx.x < kWave) {
+            // wave 0 looks back over 64 predecessors at a time: once every one of
+            // them has published, add the totals down to the nearest published
+            // inclusive prefix (positions before tile 0 count as a prefix of 0)
+            const int lane = threadIdx.x;
+            int64_t prefix = 0;
+            for (int hi = t - 1; hi >= 0; hi -= kWave) {
+                const int p = hi - lane;
+                uint64_t w;
+                for (;;) {
+                    w = p >= 0 ? status_load(&status[p]) : kStatPre;
+                    if (__ballot((w >> 62) == 0) == 0) break;
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                status_store(&status[t], kStatPre | ((uint64_t)(prefix + total) & kStatVal));
+                const uint64_t pre = __ballot((w >> 62) == 2);
+                const int stop = pre ? __builtin_ctzll(pre) : kWave;  // nearest prefix in this window
+                const int64_t v = lane <= stop ? (int64_t)(w & kStatVal) : 0;
+                prefix += wave_reduce<Red<MX_ADD, int64_t>>(v);
+                if (pre) break;
+            }
+            if (lane == 0) {
+                if (t > 0) status_store(&status[t], kStatPre | ((uint64_t)(prefix + total) & kStatVal));
+                sh_prefix = prefix;
             }
         }
-        sh_prefix = prefix;
+    } else if (threadIdx.x == 0) {
+        sh_prefix = 0;
     }
     __syncthreads();
     const int64_t prefix = sh_prefix;

@@ -346,7 +346,7 @@ def test_segmented_shapes(lengths, dt):
             assert np.array_equal(got, R), shift
         else:
             check_vector(got, R, O.segmented_reduce(O.ADD, 0.0, np.abs(v), off), L, what=f"shift {shift}")
-    if dt == np.float32:
+    if dt == np.float32 and off[-1] > 0:
         g = rng.uniform(-1, 1, len(L)).astype(np.float32)
         gv = torch.full((int(off[-1]) + 1,), 5.0, device=DEV)
         abi.mx_segmented_sum_adjoint_f32(dev(g), dev(off), gv[1:])

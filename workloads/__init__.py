@@ -178,17 +178,21 @@ def batched_tasks(ntasks: int, seed: int = 0, smin: float = 1e2, smax: float = 1
     a_len = rows * cols
     b_len = cols.copy()
     o_len = np.where(mv, rows, 1).astype(np.int64)
+    # operands start on 16-byte boundaries (lengths padded to multiples of 4
+    # floats; the padding belongs to no task)
+    a_pad = (a_len + 3) // 4 * 4
+    b_pad = (b_len + 3) // 4 * 4
     a_off = np.zeros(ntasks, dtype=np.int64)
     b_off = np.zeros(ntasks, dtype=np.int64)
     out_off = np.zeros(ntasks, dtype=np.int64)
-    a_off[1:] = np.cumsum(a_len)[:-1]
-    b_off[1:] = np.cumsum(b_len)[:-1]
+    a_off[1:] = np.cumsum(a_pad)[:-1]
+    b_off[1:] = np.cumsum(b_pad)[:-1]
     out_off[1:] = np.cumsum(o_len)[:-1]
-    a_total = int(a_len.sum())
+    a_total = int(a_pad.sum())
     if max_total is not None:
         assert a_total <= max_total, (a_total, max_total)
     A = _uniform_f32(rng, -1.0, 1.0, a_total)
-    B = _uniform_f32(rng, -1.0, 1.0, int(b_len.sum()))
+    B = _uniform_f32(rng, -1.0, 1.0, int(b_pad.sum()))
     out_len = int(o_len.sum())
     gout = _uniform_f32(rng, -1.0, 1.0, out_len)
     for t in np.nonzero(~mv)[0]:
