@@ -63,55 +63,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-class PartTimer:
-    """HIP events recorded on the launch stream around each part of a step."""
-
-    def __init__(self, names, steps):
-        import torch
-        self.names = names
-        self.ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-                   for _ in range(steps)]
-        self.step = 0
-        self.i = 0
-
-    def mark(self):
-        if self.step < len(self.ev):
-            self.ev[self.step][self.i].record()
-            self.i += 1
-
-    def next_step(self):
-        self.step += 1
-        self.i = 0
-
-    def averages_ms(self):
-        out = {}
-        for k, n in enumerate(self.names):
-            ts = [e[k].elapsed_time(e[k + 1]) for e in self.ev]
-            out[n] = sum(ts) / len(ts)
-        return out
-
-
-def timed(step, steps, warmup, names):
-    """Run warmup steps, then time `steps` steps; returns (ms_per_step, part ms)."""
-    import torch
-    for _ in range(warmup):
-        step(None)
-    torch.cuda.synchronize()
-    pt = PartTimer(names, steps)
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(steps):
-        step(pt)
-        pt.next_step()
-    end.record()
-    torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps, pt.averages_ms()
-
-
 def gbs(nbytes, ms):
     return nbytes / (ms * 1e-3) / 1e9
+
+
+def timed_on(stream, fn, steps, warmup):
+    """Run `warmup` untimed calls, then time exactly `steps` calls of fn on
+    `stream` between two HIP events, synchronising before and after; returns
+    ms per call."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def per_launch_ms(fn, reps=20, warmup=3):
+    """Average duration of one launch: `reps` back-to-back launches of fn on
+    the current stream between two events (no marker between launches)."""
+    import torch
+    return timed_on(torch.cuda.current_stream(), fn, reps, warmup)
+
+
+def capture(stream, fn):
+    """fn() once eagerly on `stream`, then captured into a HIP graph."""
+    import torch
+    from paper_2211_00621_amd import abi
+    with torch.cuda.stream(stream):
+        fn()
+        stream.synchronize()
+        abi.mx_graph_begin(stream)
+        fn()
+        g = abi.mx_graph_end(stream)
+    stream.synchronize()
+    return g
 
 
 def cpu_threads():
@@ -153,26 +145,38 @@ def bench_nested(args):
     ws = api.workspace(abi.MX_WS_SCAN, nseg, device=dev)
     names = ["offsets", "row_sums", "mmr_fwd", "row_sums_adjoint", "mmr_adjoint_A", "mmr_adjoint_B"]
 
-    def make_step(plain):
+    def make_parts(plain):
         seg = abi.mx_segmented_reduce_plain if plain else abi.mx_segmented_reduce
         mmr = abi.mx_map_map_reduce_plain_f32 if plain else abi.mx_map_map_reduce_f32
+        return [
+            lambda: abi.mx_lengths_to_offsets(d["tL"], offsets, ws),
+            lambda: seg(abi.MX_ADD, d["tv"], offsets, 0.0, rows),
+            lambda: mmr(0, 0, d["tA"], d["tB"], C),
+            lambda: abi.mx_segmented_sum_adjoint_f32(d["tg"], offsets, gvals),
+            lambda: mmr(0, 1, d["tG"], d["tB"], gA),
+            lambda: mmr(1, 0, d["tA"], d["tG"], gB),
+        ]
 
-        def step(pt):
-            m = pt.mark if pt else (lambda: None)
-            m(); abi.mx_lengths_to_offsets(d["tL"], offsets, ws)
-            m(); seg(abi.MX_ADD, d["tv"], offsets, 0.0, rows)
-            m(); mmr(0, 0, d["tA"], d["tB"], C)
-            m(); abi.mx_segmented_sum_adjoint_f32(d["tg"], offsets, gvals)
-            m(); mmr(0, 1, d["tG"], d["tB"], gA)
-            m(); mmr(1, 0, d["tA"], d["tG"], gB)
-            m()
-        return step
+    fused_parts, plain_parts = make_parts(False), make_parts(True)
 
-    log("nested: fused steps")
-    ms, parts = timed(make_step(False), args.steps, args.warmup, names)
-    log(f"nested: fused {ms:.3f} ms/step")
+    def step():
+        for f in fused_parts:
+            f()
+
+    def plain_step():
+        for f in plain_parts:
+            f()
+
+    log("nested: fused steps (HIP graph of one step)")
+    side = torch.cuda.Stream()
+    graph = capture(side, step)
+    ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
+    eager_ms = timed_on(torch.cuda.current_stream(), step, args.steps, args.warmup)
+    log(f"nested: fused {ms:.3f} ms/step (graph), {eager_ms:.3f} ms/step (eager)")
+    parts = {nm: per_launch_ms(f, reps=max(args.steps, 10)) for nm, f in zip(names, fused_parts)}
     psteps = max(1, min(args.steps, 3))
-    pms, pparts = timed(make_step(True), psteps, 1, names)
+    pms = timed_on(torch.cuda.current_stream(), plain_step, psteps, 1)
+    pparts = {nm: per_launch_ms(f, reps=1, warmup=0) for nm, f in zip(names, plain_parts)}
     log(f"nested: plain {pms:.3f} ms/step")
 
     elems = 2 * nval + 3 * M * N * K
@@ -213,9 +217,13 @@ def bench_nested(args):
         "parts": detail,
         "plain": {"ms_per_step": pms, "value": elems / (pms * 1e-3),
                   "fused_speedup": round(pms / ms, 2)},
+        "eager_ms_per_step": eager_ms,
+        "timing": "value and ms_per_step: K replays of a HIP graph of one step; parts: K back-to-back launches "
+                  "of each part between two events",
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_nested(d, rows, C, gA, gB, gvals, offsets)
+    del graph
     return line
 
 
@@ -271,30 +279,25 @@ def bench_dot(args):
     outi = torch.empty((), dtype=torch.int64, device=dev)
     tmp = torch.empty(n, dtype=torch.float32, device=dev)
     ws = api.workspace(abi.MX_WS_REDUCE, n, device=dev)
-    names = ["fused_f32", "fused_i32", "plain_map2", "plain_reduce"]
-
-    def step(pt):
-        m = pt.mark if pt else (lambda: None)
-        m(); abi.mx_map2_reduce(abi.MX_B_MUL, abi.MX_ADD, ta, tb, 0.0, out, ws)
-        m(); abi.mx_map2_reduce(abi.MX_B_MUL, abi.MX_ADD, tai, tbi, 0, outi, ws)
-        m(); abi.mx_map2(abi.MX_B_MUL, ta, tb, tmp)
-        m(); abi.mx_reduce(abi.MX_ADD, tmp, 0.0, out, ws)
-        m()
-
-    ms, parts = timed(step, args.steps, args.warmup, names)
+    parts = {
+        "fused_f32": per_launch_ms(lambda: abi.mx_map2_reduce(abi.MX_B_MUL, abi.MX_ADD, ta, tb, 0.0, out, ws),
+                                   reps=args.steps, warmup=args.warmup),
+        "fused_i32": per_launch_ms(lambda: abi.mx_map2_reduce(abi.MX_B_MUL, abi.MX_ADD, tai, tbi, 0, outi, ws),
+                                   reps=args.steps, warmup=args.warmup),
+        "plain_map2": per_launch_ms(lambda: abi.mx_map2(abi.MX_B_MUL, ta, tb, tmp), reps=args.steps,
+                                    warmup=args.warmup),
+        "plain_reduce": per_launch_ms(lambda: abi.mx_reduce(abi.MX_ADD, tmp, 0.0, out, ws), reps=args.steps,
+                                      warmup=args.warmup),
+    }
+    ms = parts["fused_f32"]
     sweep = {}
     for k in (24, 26):
         nn = 1 << k
         x = torch.rand(nn, device=dev)
         y = torch.rand(nn, device=dev)
-
-        def s2(pt, x=x, y=y):
-            m = pt.mark if pt else (lambda: None)
-            m(); abi.mx_map2_reduce(abi.MX_B_MUL, abi.MX_ADD, x, y, 0.0, out, ws)
-            m()
-        _, p2 = timed(s2, 20, 3, ["fused"])
-        sweep[f"2^{k}"] = {"us": round(p2["fused"] * 1e3, 2), "GB/s": round(gbs(8 * nn, p2["fused"]), 1),
-                           "frac_hbm": round(gbs(8 * nn, p2["fused"]) / HBM_PEAK_GBS, 4)}
+        us = per_launch_ms(lambda: abi.mx_map2_reduce(abi.MX_B_MUL, abi.MX_ADD, x, y, 0.0, out, ws)) * 1e3
+        sweep[f"2^{k}"] = {"us": round(us, 2), "GB/s": round(gbs(8 * nn, us * 1e-3), 1),
+                           "frac_hbm": round(gbs(8 * nn, us * 1e-3) / HBM_PEAK_GBS, 4)}
     fused = parts["fused_f32"]
     plain = parts["plain_map2"] + parts["plain_reduce"]
     return {
@@ -384,12 +387,9 @@ def bench_nbody(args):
     log(f"nbody: fwd+bwd {ms:.3f} ms, fwd {ms_fwd:.3f} ms")
 
     # per-launch durations of the pair kernels (eager, events on the launch stream)
-    def one_step(pt):
-        m_ = pt.mark if pt else (lambda: None)
-        m_(); abi.mx_nbody_step_f32(p4, v4, eps2, G, dt, xa, va, pws)
-        m_(); abi.mx_nbody_adjoint_step_f32(p4, xb, va, eps2, G, dt, gx, gv, pws)
-        m_()
-    _, parts = timed(one_step, 10, 2, ["step", "adjoint_step"])
+    parts = {"step": per_launch_ms(lambda: abi.mx_nbody_step_f32(p4, v4, eps2, G, dt, xa, va, pws), reps=10),
+             "adjoint_step": per_launch_ms(
+                 lambda: abi.mx_nbody_adjoint_step_f32(p4, xb, va, eps2, G, dt, gx, gv, pws), reps=10)}
 
     # plain: eager untiled pair loop + separate update, forward only
     def plain_fwd(pt):
@@ -470,29 +470,12 @@ def bench_kmeans(args):
         graph = abi.mx_graph_end(side)
     side.synchronize()
 
-    def timed_on(stream, fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        stream.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(steps):
-            fn()
-        b.record(stream)
-        stream.synchronize()
-        return a.elapsed_time(b) / steps
-
     ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
     cur = torch.cuda.current_stream()
     pms = timed_on(cur, lambda: body(abi.mx_kmeans_step_plain_f32, None), max(1, min(args.steps, 5)), 1)
 
-    def parts_step(pt):
-        m_ = pt.mark if pt else (lambda: None)
-        m_(); abi.mx_kmeans_step_f32(Xt, Cs[0], labels, counts, Cs[1], ws)
-        m_(); abi.mx_kmeans_sse_grad_f32(Xt, Cs[1], labels, one, G)
-        m_()
-    _, parts = timed(parts_step, 10, 2, ["kmeans_step", "sse_grad"])
+    parts = {"kmeans_step": per_launch_ms(lambda: abi.mx_kmeans_step_f32(Xt, Cs[0], labels, counts, Cs[1], ws)),
+             "sse_grad": per_launch_ms(lambda: abi.mx_kmeans_sse_grad_f32(Xt, Cs[1], labels, one, G))}
     log(f"kmeans: fused {ms:.3f} ms, plain {pms:.3f} ms")
     flops_step = 2.0 * n * k * d
     ach = flops_step / (parts["kmeans_step"] * 1e-3) / 1e12
@@ -559,19 +542,6 @@ def bench_batched(args):
         graph = abi.mx_graph_end(side)
     side.synchronize()
 
-    def timed_on(stream, fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        stream.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(steps):
-            fn()
-        b.record(stream)
-        stream.synchronize()
-        return a.elapsed_time(b) / steps
-
     ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
     cur = torch.cuda.current_stream()
 
@@ -580,12 +550,8 @@ def bench_batched(args):
         batch.backward(A, B, g, gA, gB, plain=True)
     pms = timed_on(cur, plain, max(1, min(args.steps, 5)), 1)
 
-    def parts_step(pt):
-        m_ = pt.mark if pt else (lambda: None)
-        m_(); batch.forward(A, B, out)
-        m_(); batch.backward(A, B, g, gA, gB)
-        m_()
-    _, parts = timed(parts_step, 10, 2, ["forward", "backward"])
+    parts = {"forward": per_launch_ms(lambda: batch.forward(A, B, out)),
+             "backward": per_launch_ms(lambda: batch.backward(A, B, g, gA, gB))}
     log(f"batched: graph {ms:.3f} ms, plain {pms:.3f} ms")
 
     rows, cols, kind = bt.rows, bt.cols, bt.kind

@@ -309,6 +309,21 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
     }
 }
 
+// sum of q = 0 .. nq-1 of p[q * stride], in q order, eight loads in flight
+__device__ __forceinline__ float sum_strided(const float *__restrict__ p, int64_t nq, int64_t stride) {
+    float s = 0.f;
+    int64_t q = 0;
+    for (; q + 8 <= nq; q += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(q + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < nq; ++q) s += p[q * stride];
+    return s;
+}
+
 // Adds the tile partials of each multi-tile task in tile order; resets the ticket.
 __global__ void __launch_bounds__(NT) k_batch_combine_fwd(const TaskDev *__restrict__ tasks,
                                                           const int32_t *__restrict__ list, int64_t nlist,
@@ -318,24 +333,21 @@ __global__ void __launch_bounds__(NT) k_batch_combine_fwd(const TaskDev *__restr
     const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (i >= nlist) return;
     const TaskDev tk = tasks[list[i]];
-    float s = 0.f;
-    for (int64_t q = 0; q < tk.fwd_ntiles; ++q) s += part[tk.fwd_part + q];
-    out[tk.out_off] = s;
+    out[tk.out_off] = sum_strided(part + tk.fwd_part, tk.fwd_ntiles, 1);
 }
 
+// grid (tasks in the list, column chunks of NT): column j of task gets the sum
+// of its per-tile partial column sums in tile order
 __global__ void __launch_bounds__(NT) k_batch_combine_bwd(const TaskDev *__restrict__ tasks,
                                                           const int32_t *__restrict__ list, int64_t nlist,
                                                           const float *__restrict__ part, float *__restrict__ gB,
                                                           unsigned *ticket) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0u;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ticket = 0u;
     if ((int64_t)blockIdx.x >= nlist) return;
     const TaskDev tk = tasks[list[blockIdx.x]];
     const int64_t c = tk.cols;
-    for (int64_t j = threadIdx.x; j < c; j += NT) {
-        float s = 0.f;
-        for (int64_t q = 0; q < tk.bwd_ntiles; ++q) s += part[tk.bwd_part + q * c + j];
-        gB[tk.b_off + j] = s;
-    }
+    for (int64_t j = (int64_t)blockIdx.y * NT + threadIdx.x; j < c; j += (int64_t)gridDim.y * NT)
+        gB[tk.b_off + j] = sum_strided(part + tk.bwd_part + j, tk.bwd_ntiles, c);
 }
 
 // ---------------------------------------------------------------- plain: one launch per task
@@ -395,6 +407,7 @@ struct mx_batch_plan {
     TileDev *d_fwd = nullptr, *d_bwd = nullptr;
     int32_t *d_fwd_list = nullptr, *d_bwd_list = nullptr;
     int64_t n_fwd = 0, n_bwd = 0, n_fwd_list = 0, n_bwd_list = 0;
+    int64_t bwd_list_max_cols = 1;
     int64_t fwd_part_floats = 0, bwd_part_floats = 0;
     size_t ws_need = 0;
 };
@@ -434,7 +447,7 @@ mx_status build_tiles(mx_batch_plan *p) {
     std::vector<TaskDev> tasks((size_t)p->ntasks);
     std::vector<TileDev> fwd, bwd;
     std::vector<int32_t> fwd_list, bwd_list;
-    int64_t fpart = 0, bpart = 0;
+    int64_t fpart = 0, bpart = 0, max_cols = 1;
     for (int64_t t = 0; t < p->ntasks; ++t) {
         const int64_t *r = &p->table[(size_t)(6 * t)];
         TaskDev &tk = tasks[(size_t)t];
@@ -475,6 +488,7 @@ mx_status build_tiles(mx_batch_plan *p) {
             if (nt > 1) {
                 bwd_list.push_back((int32_t)t);
                 bpart += nt * tk.cols;
+                max_cols = std::max(max_cols, tk.cols);
             }
         }
     }
@@ -504,6 +518,7 @@ mx_status build_tiles(mx_batch_plan *p) {
     p->n_bwd = (int64_t)bwd.size();
     p->n_fwd_list = (int64_t)fwd_list.size();
     p->n_bwd_list = (int64_t)bwd_list.size();
+    p->bwd_list_max_cols = max_cols;
     p->fwd_part_floats = fpart;
     p->bwd_part_floats = bpart;
     return MX_OK;
@@ -553,7 +568,9 @@ mx_status bwd_impl(const mx_batch_plan *p, const float *A, const float *B, const
     const int vec = aligned16(A) && aligned16(B) && aligned16(gA) && aligned16(gB);
     hipLaunchKernelGGL(k_batch_bwd, dim3(grid_of(p, p->n_bwd)), dim3(NT), 0, s, p->d_tasks, p->d_bwd, p->n_bwd, A, B,
                        gout, gA, gB, part, ticket, vec);
-    hipLaunchKernelGGL(k_batch_combine_bwd, dim3((unsigned)std::max<int64_t>(1, p->n_bwd_list)), dim3(NT), 0, s,
+    const dim3 cgrid((unsigned)std::max<int64_t>(1, p->n_bwd_list),
+                     (unsigned)std::min<int64_t>(1024, ceil_div(p->bwd_list_max_cols, NT)));
+    hipLaunchKernelGGL(k_batch_combine_bwd, cgrid, dim3(NT), 0, s,
                        p->d_tasks, p->d_bwd_list, p->n_bwd_list, part, gB, ticket);
     return last_launch("mx_batch_backward");
 }

@@ -294,10 +294,16 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             }
             uint64_t todo = __ballot(!certified);
             if (todo && a.fallbacks && lane == 0) atomicAdd(a.fallbacks, (unsigned long long)__popcll(todo));
+            // the point is staged in this wave's best1 slots (read above): one
+            // coalesced load, then LDS broadcasts for every centroid lane
+            float *xs = best1;
             while (todo) {
                 const int q = __builtin_ctzll(todo);  // wave-uniform
                 todo &= todo - 1;
-                const float *x = a.X + (p0 + q) * d;
+                wave_sync();
+                if (lane < d) xs[lane] = a.X[(p0 + q) * d + lane];
+                wave_sync();
+                const float *x = xs;
                 double bd = INFINITY;
                 int bj = 0x7fffffff;
                 for (int j = lane; j < k; j += kWave) {
