@@ -44,7 +44,18 @@ FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 # `source` is the SHA-256 of the kernel's source file when the counters were
 # taken: once that file changes the figure no longer describes the kernel and
 # the bench reports null.
-TRAFFIC = {}
+TRAFFIC = {
+    # k_gemm_mfma<128,64,4,2,0,0>, 2048^3: 100.74 MB fetched (A and B panels re-read once per XCD that
+    # needs them; 33.6 MB is the algorithmic minimum) + 16.78 MB written (C)
+    "gemm_nn": {"file": "gemm.hip", "bytes": 117514427,
+                "source": "46c407011de154c0da4502fa5d9c9c1f8c426e3c73b33d97fd2f6088cf11ebc2"},
+    # k_seg_span, 65536 rows / 32.1 M values: 130.46 MB fetched + 0.26 MB written (1.01x algorithmic)
+    "seg_span": {"file": "segmented.hip", "bytes": 130721777,
+                 "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},
+    # k_seg_broadcast: 1.61 MB fetched (offsets, gradients) + 128.83 MB written
+    "seg_broadcast": {"file": "segmented.hip", "bytes": 130438732,
+                      "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},
+}
 
 
 def traffic_of(key):
@@ -186,9 +197,12 @@ def bench_nested(args):
         "row_sums": 4 * nval + 8 * (nseg + 1) + 4 * nseg,
         "row_sums_adjoint": 4 * nval + 8 * (nseg + 1) + 4 * nseg,
     }
+    counted = {"row_sums": traffic_of("seg_span"), "row_sums_adjoint": traffic_of("seg_broadcast")}
     detail = {}
     for n in names:
         e = {"us": round(parts[n] * 1e3, 2), "plain_us": round(pparts[n] * 1e3, 2)}
+        if counted.get(n):
+            e["traffic_bytes"] = counted[n]
         if n in bytes_:
             e["GB/s"] = round(gbs(bytes_[n], parts[n]), 1)
             e["frac_hbm"] = round(gbs(bytes_[n], parts[n]) / HBM_PEAK_GBS, 4)
