@@ -121,6 +121,55 @@ __device__ __forceinline__ void tile_of(int b, int tiles_m, int tiles_n, int &tm
     tn = in / gm;
 }
 
+// MFMA work of one K slice held in LDS: the wave's MI x NI blocks of 16 x 16
+template <int BM, int BN, int WM, int WN, bool RA, bool RB>
+__device__ __forceinline__ void mma_slice(v4f (&acc)[BM / WM / 16][BN / WN / 16], const float *__restrict__ as,
+                                          const float *__restrict__ bs, int wrow0, int wcol0, int l16, int g) {
+    constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
+    using OA = Operand<BM, RA>;
+    using OB = Operand<BN, RB>;
+    float a8[RA ? MI : 1][8], b8[RB ? NI : 1][8];
+    if constexpr (RA) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+            const float *q = as + (wrow0 + 16 * i + l16) * OA::LD + 8 * g;
+            float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
+            a8[i][0] = lo.x; a8[i][1] = lo.y; a8[i][2] = lo.z; a8[i][3] = lo.w;
+            a8[i][4] = hi.x; a8[i][5] = hi.y; a8[i][6] = hi.z; a8[i][7] = hi.w;
+        }
+    }
+    if constexpr (RB) {
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            const float *q = bs + (wcol0 + 16 * j + l16) * OB::LD + 8 * g;
+            float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
+            b8[j][0] = lo.x; b8[j][1] = lo.y; b8[j][2] = lo.z; b8[j][3] = lo.w;
+            b8[j][4] = hi.x; b8[j][5] = hi.y; b8[j][6] = hi.z; b8[j][7] = hi.w;
+        }
+    }
+#pragma unroll
+    for (int step = 0; step < 8; ++step) {
+        float av[MI], bv[NI];
+        if constexpr (RA) {
+#pragma unroll
+            for (int i = 0; i < MI; ++i) av[i] = a8[i][step];
+        } else {
+            lds_read<MI>(av, as + (8 * g + step) * OA::LD + wrow0 + MI * l16);
+        }
+        if constexpr (RB) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) bv[j] = b8[j][step];
+        } else {
+            lds_read<NI>(bv, bs + (8 * g + step) * OB::LD + wcol0 + NI * l16);
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+}
+
 template <int BM, int BN, int WM, int WN, int TA, int TB>
 __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restrict__ A, const float *__restrict__ B,
                                                             float *__restrict__ C, int64_t M, int64_t N, int64_t K,
@@ -154,73 +203,67 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
 #pragma unroll
         for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    float4 ra[BM * BK / 4 / NT], rb[BN * BK / 4 / NT];
-    {
-        const bool fast = interior && (BK <= K);
-        load_slice<BM, RA, NT>(ra, A, lda, m0, 0, M, K, fast);
-        load_slice<BN, RB, NT>(rb, B, ldb, n0, 0, N, K, fast);
-        store_slice<BM, RA, NT>(As[0], ra);
-        store_slice<BN, RB, NT>(Bs[0], rb);
-    }
-    __syncthreads();
-
     const int wrow0 = wm * (BM / WM), wcol0 = wn * (BN / WN);
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) {
-            const int64_t k0 = (int64_t)(kt + 1) * BK;
-            const bool fast = interior && (k0 + BK <= K);
-            load_slice<BM, RA, NT>(ra, A, lda, m0, k0, M, K, fast);
-            load_slice<BN, RB, NT>(rb, B, ldb, n0, k0, N, K, fast);
+    constexpr int NA = BM * BK / 4 / NT, NB = BN * BK / 4 / NT;
+    if (interior && K % (2 * BK) == 0) {
+        // Interior tile, whole slice pairs: a branch-free pipeline.  Slice
+        // kt + 2 is loaded while slice kt is multiplied and stored to LDS only
+        // after slice kt + 1 has been, so every load has two slices of MFMA
+        // work to land; past the end the slice index is clamped (the extra
+        // loads are never read) rather than branched around, which would make
+        // the compiler wait for every load in flight.
+        float4 ra0[NA], rb0[NB], ra1[NA], rb1[NB];
+        load_slice<BM, RA, NT>(ra0, A, lda, m0, 0, M, K, true);
+        load_slice<BN, RB, NT>(rb0, B, ldb, n0, 0, N, K, true);
+        store_slice<BM, RA, NT>(As[0], ra0);
+        store_slice<BN, RB, NT>(Bs[0], rb0);
+        load_slice<BM, RA, NT>(ra1, A, lda, m0, BK, M, K, true);
+        load_slice<BN, RB, NT>(rb1, B, ldb, n0, BK, N, K, true);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            const int64_t k2 = (int64_t)min(kt + 2, nk - 1) * BK, k3 = (int64_t)min(kt + 3, nk - 1) * BK;
+            load_slice<BM, RA, NT>(ra0, A, lda, m0, k2, M, K, true);
+            load_slice<BN, RB, NT>(rb0, B, ldb, n0, k2, N, K, true);
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As[0], Bs[0], wrow0, wcol0, l16, g);
+            store_slice<BM, RA, NT>(As[1], ra1);
+            store_slice<BN, RB, NT>(Bs[1], rb1);
+            __syncthreads();
+            load_slice<BM, RA, NT>(ra1, A, lda, m0, k3, M, K, true);
+            load_slice<BN, RB, NT>(rb1, B, ldb, n0, k3, N, K, true);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As[1], Bs[1], wrow0, wcol0, l16, g);
+            store_slice<BM, RA, NT>(As[0], ra0);
+            store_slice<BN, RB, NT>(Bs[0], rb0);
+            __syncthreads();
         }
-        const float *as = As[buf];
-        const float *bs = Bs[buf];
-        float a8[RA ? MI : 1][8], b8[RB ? NI : 1][8];
-        if constexpr (RA) {
-#pragma unroll
-            for (int i = 0; i < MI; ++i) {
-                const float *q = as + (wrow0 + 16 * i + l16) * OA::LD + 8 * g;
-                float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
-                a8[i][0] = lo.x; a8[i][1] = lo.y; a8[i][2] = lo.z; a8[i][3] = lo.w;
-                a8[i][4] = hi.x; a8[i][5] = hi.y; a8[i][6] = hi.z; a8[i][7] = hi.w;
-            }
-        }
-        if constexpr (RB) {
-#pragma unroll
-            for (int j = 0; j < NI; ++j) {
-                const float *q = bs + (wcol0 + 16 * j + l16) * OB::LD + 8 * g;
-                float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
-                b8[j][0] = lo.x; b8[j][1] = lo.y; b8[j][2] = lo.z; b8[j][3] = lo.w;
-                b8[j][4] = hi.x; b8[j][5] = hi.y; b8[j][6] = hi.z; b8[j][7] = hi.w;
-            }
-        }
-#pragma unroll
-        for (int step = 0; step < 8; ++step) {
-            float av[MI], bv[NI];
-            if constexpr (RA) {
-#pragma unroll
-                for (int i = 0; i < MI; ++i) av[i] = a8[i][step];
-            } else {
-                lds_read<MI>(av, as + (8 * g + step) * OA::LD + wrow0 + MI * l16);
-            }
-            if constexpr (RB) {
-#pragma unroll
-                for (int j = 0; j < NI; ++j) bv[j] = b8[j][step];
-            } else {
-                lds_read<NI>(bv, bs + (8 * g + step) * OB::LD + wcol0 + NI * l16);
-            }
-#pragma unroll
-            for (int i = 0; i < MI; ++i)
-#pragma unroll
-                for (int j = 0; j < NI; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-        }
-        if (more) {
-            store_slice<BM, RA, NT>(As[buf ^ 1], ra);
-            store_slice<BN, RB, NT>(Bs[buf ^ 1], rb);
+    } else {
+        // edge tiles and ragged K: bounds-checked loads, one slice ahead
+        float4 ra[NA], rb[NB];
+        {
+            const bool fast = interior && (BK <= K);
+            load_slice<BM, RA, NT>(ra, A, lda, m0, 0, M, K, fast);
+            load_slice<BN, RB, NT>(rb, B, ldb, n0, 0, N, K, fast);
+            store_slice<BM, RA, NT>(As[0], ra);
+            store_slice<BN, RB, NT>(Bs[0], rb);
         }
         __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) {
+                const int64_t k0 = (int64_t)(kt + 1) * BK;
+                const bool fast = interior && (k0 + BK <= K);
+                load_slice<BM, RA, NT>(ra, A, lda, m0, k0, M, K, fast);
+                load_slice<BN, RB, NT>(rb, B, ldb, n0, k0, N, K, fast);
+            }
+            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As[buf], Bs[buf], wrow0, wcol0, l16, g);
+            if (more) {
+                store_slice<BM, RA, NT>(As[buf ^ 1], ra);
+                store_slice<BN, RB, NT>(Bs[buf ^ 1], rb);
+            }
+            __syncthreads();
+        }
     }
 
     // D block (i, j): lane holds block rows rho = 4g .. 4g+3 of block column

@@ -108,6 +108,14 @@ struct KmArgs {
     unsigned long long *fallbacks;  // optional counter of binary64 recomputations
 };
 
+// Row stride of the LDS sums: d rounded up to 16 bytes, plus 16 bytes when
+// that is a multiple of 32 floats, so consecutive labels start on different
+// banks.
+__host__ __device__ inline int sums_ld(int d) {
+    const int r4 = (d + 3) & ~3;
+    return (r4 & 31) == 0 ? r4 + 4 : r4;
+}
+
 // Orders this wave's LDS writes before its later LDS reads (a wave's LDS
 // operations execute in order; this only keeps the compiler from moving them).
 __device__ __forceinline__ void wave_sync() {
@@ -116,25 +124,31 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// X fragments of chunk c: point c*64 + mi*16 + l16, dims kc*32 + 8g .. +7
-template <int DP>
-__device__ __forceinline__ void load_chunk(float4 (&xa)[4][DP / 32][2], const KmArgs &a, int64_t c, int l16, int g,
-                                           bool vec_x) {
+// X fragments of chunk c: point c*64 + mi*16 + l16, dims kc*32 + 8g .. +7.
+// Branch-free, so the loads stay in flight while the current chunk is
+// processed: points past n are read from the last point (their labels are
+// never used) and dimensions past d from dimension d - 1 (the centroids are
+// zero there, so only |x|^2 needs them zeroed, which mask_chunk does when the
+// chunk is consumed).  VX: d == DP and X 16-byte aligned (two 16-byte loads).
+template <int DP, bool VX>
+__device__ __forceinline__ void load_chunk(float4 (&xa)[4][DP / 32][2], const KmArgs &a, int64_t c, int l16,
+                                           int g) {
     const int d = a.d;
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
         const int64_t p = c * kPtsWave + mi * 16 + l16;
+        const int64_t pc = p < a.n ? p : a.n - 1;
 #pragma unroll
         for (int kc = 0; kc < DP / 32; ++kc) {
             const int t0 = kc * 32 + 8 * g;
-            if (vec_x && p < a.n) {
-                const float4 *q = reinterpret_cast<const float4 *>(a.X + p * d + t0);
+            if constexpr (VX) {
+                const float4 *q = reinterpret_cast<const float4 *>(a.X + pc * d + t0);
                 xa[mi][kc][0] = q[0];
                 xa[mi][kc][1] = q[1];
             } else {
                 float v[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (p < a.n && t0 + e < d) ? a.X[p * d + t0 + e] : 0.f;
+                for (int e = 0; e < 8; ++e) v[e] = a.X[pc * d + (t0 + e < d ? t0 + e : d - 1)];
                 xa[mi][kc][0] = make_float4(v[0], v[1], v[2], v[3]);
                 xa[mi][kc][1] = make_float4(v[4], v[5], v[6], v[7]);
             }
@@ -142,12 +156,32 @@ __device__ __forceinline__ void load_chunk(float4 (&xa)[4][DP / 32][2], const Km
     }
 }
 
+// zeroes the dimensions past d (nothing to do when d == DP)
+template <int DP, bool VX>
+__device__ __forceinline__ void mask_chunk(float4 (&xa)[4][DP / 32][2], int d, int g) {
+    if constexpr (!VX) {
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int kc = 0; kc < DP / 32; ++kc)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int t = kc * 32 + 8 * g + 4 * h;
+                    float4 &u = xa[mi][kc][h];
+                    u.x = t + 0 < d ? u.x : 0.f;
+                    u.y = t + 1 < d ? u.y : 0.f;
+                    u.z = t + 2 < d ? u.z : 0.f;
+                    u.w = t + 3 < d ? u.w : 0.f;
+                }
+    }
+}
+
 // DP: d padded to a multiple of 32; KP: k padded to a multiple of 64.
-template <int DP, int KP>
+template <int DP, int KP, bool VX>
 __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_fused(KmArgs a) {
     constexpr int LDC = DP + 4;
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    const int d = a.d, k = a.k, ldd = d + 1;  // odd row stride: labels spread over banks
+    const int d = a.d, k = a.k, ldd = sums_ld(d);
     float *Cs = smem;                                  // [KP][LDC]
     float *cnorm = Cs + KP * LDC;                      // [KP]
     float *sums_all = cnorm + KP;                      // [kWaves][k][ldd]
@@ -190,17 +224,18 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     int *bidx = (int *)(best2 + kPtsWave);
     int *lab = bidx + kPtsWave;
 
-    const bool vec_x = (d == DP) && ((uintptr_t)a.X % 16 == 0);
     const int64_t nchunks = (a.n + kPtsWave - 1) / kPtsWave;
     const int64_t wstride = (int64_t)gridDim.x * kWaves;
     int64_t c = (int64_t)blockIdx.x * kWaves + wave;  // wave-uniform
     float4 xa[4][DP / 32][2];
-    if (c < nchunks) load_chunk<DP>(xa, a, c, l16, g, vec_x);
+    if (c < nchunks) load_chunk<DP, VX>(xa, a, c, l16, g);
     for (; c < nchunks; c += wstride) {
         const int64_t p0 = c * kPtsWave;
-        // next chunk's points, in flight while this one is processed
+        mask_chunk<DP, VX>(xa, d, g);
+        // next chunk's points, in flight while this one is processed (the
+        // last chunk reloads itself rather than branch around the loads)
         float4 xn[4][DP / 32][2];
-        if (c + wstride < nchunks) load_chunk<DP>(xn, a, c + wstride, l16, g, vec_x);
+        load_chunk<DP, VX>(xn, a, c + wstride < nchunks ? c + wstride : c, l16, g);
 
         // |x|^2: add the four lane groups g (lanes l16, l16+16, l16+32, l16+48)
 #pragma unroll
@@ -334,20 +369,31 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 rank += (4 * q4 + 0 < l16 && lq.x == L) + (4 * q4 + 1 < l16 && lq.y == L) +
                         (4 * q4 + 2 < l16 && lq.z == L) + (4 * q4 + 3 < l16 && lq.w == L);
             }
+            // within a pass every active lane owns distinct addresses, so a
+            // plain read-add-write is exact (LDS float atomics run about one
+            // lane per clock); 16-byte accesses where all 8 dims exist
             for (int m = 0; __ballot(L >= 0 && rank >= m); ++m) {
                 if (L >= 0 && rank == m) {
                     float *dst = ws + L * ldd;
 #pragma unroll
-                    for (int kc = 0; kc < DP / 32; ++kc)
+                    for (int kc = 0; kc < DP / 32; ++kc) {
+                        const int t0 = kc * 32 + 8 * g;
+                        if (t0 + 8 <= d) {
+                            float4 *q = reinterpret_cast<float4 *>(dst + t0);
+                            float4 s0 = q[0], s1 = q[1];
+                            const float4 x0 = xa[mi][kc][0], x1 = xa[mi][kc][1];
+                            s0.x += x0.x; s0.y += x0.y; s0.z += x0.z; s0.w += x0.w;
+                            s1.x += x1.x; s1.y += x1.y; s1.z += x1.z; s1.w += x1.w;
+                            q[0] = s0;
+                            q[1] = s1;
+                        } else {
 #pragma unroll
-                        for (int h = 0; h < 2; ++h)
+                            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const int t = kc * 32 + 8 * g + 4 * h + e;
-                                if (t < d)
-                                    __hip_atomic_fetch_add(dst + t, vget<float4, float>(xa[mi][kc][h], e),
-                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            }
+                                for (int e = 0; e < 4; ++e)
+                                    if (t0 + 4 * h + e < d) dst[t0 + 4 * h + e] += vget<float4, float>(xa[mi][kc][h], e);
+                        }
+                    }
                 }
             }
         }
@@ -552,7 +598,7 @@ int64_t fused_blocks(int64_t n) {
 }
 
 size_t fused_lds_bytes(int DP, int KP, int k, int d) {
-    return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * (d + 1) * 4 + (size_t)kWaves * k * 4 +
+    return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * sums_ld(d) * 4 + (size_t)kWaves * k * 4 +
            (size_t)kWaves * kPtsWave * 4 * 5;
 }
 
@@ -583,7 +629,10 @@ unsigned long long *g_fb_counter[64] = {};
 
 template <int DP, int KP>
 void launch_fused(const KmArgs &a, int64_t nb, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_kmeans_fused<DP, KP>), dim3((unsigned)nb), dim3(NT), lds, s, a);
+    if (a.d == DP && (uintptr_t)a.X % 16 == 0)
+        hipLaunchKernelGGL((k_kmeans_fused<DP, KP, true>), dim3((unsigned)nb), dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_kmeans_fused<DP, KP, false>), dim3((unsigned)nb), dim3(NT), lds, s, a);
 }
 
 }  // namespace
