@@ -69,23 +69,22 @@ __device__ __forceinline__ Best merge(Best a, Best b) {
     return r;
 }
 
-template <int CTRL>
-__device__ __forceinline__ Best dpp_best(Best v) {
-    Best o;
-    o.b1 = dpp_move<CTRL, 0xF>(v.b1, v.b1);
-    o.i1 = dpp_move<CTRL, 0xF>(v.i1, v.i1);
-    o.b2 = dpp_move<CTRL, 0xF>(v.b2, v.b2);
-    return o;
-}
-
-// Merge over the 16 lanes of a DPP row; every lane of the row ends with the result.
-__device__ __forceinline__ Best row_merge(Best v) {
-    v = merge(v, dpp_best<0xB1>(v));   // quad_perm [1,0,3,2]
-    v = merge(v, dpp_best<0x4E>(v));   // quad_perm [2,3,0,1]
-    v = merge(v, dpp_best<0x141>(v));  // row_half_mirror
-    v = merge(v, dpp_best<0x140>(v));  // row_mirror
+// Minimum over the 16 lanes of a DPP row; every lane of the row gets it.
+__device__ __forceinline__ float row_min(float v) {
+    v = fminf(v, dpp_move<0xB1, 0xF>(v, v));   // quad_perm [1,0,3,2]
+    v = fminf(v, dpp_move<0x4E, 0xF>(v, v));   // quad_perm [2,3,0,1]
+    v = fminf(v, dpp_move<0x141, 0xF>(v, v));  // row_half_mirror
+    v = fminf(v, dpp_move<0x140, 0xF>(v, v));  // row_mirror
     return v;
 }
+__device__ __forceinline__ int row_min(int v) {
+    v = min(v, dpp_move<0xB1, 0xF>(v, v));
+    v = min(v, dpp_move<0x4E, 0xF>(v, v));
+    v = min(v, dpp_move<0x141, 0xF>(v, v));
+    v = min(v, dpp_move<0x140, 0xF>(v, v));
+    return v;
+}
+
 
 // binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
 __device__ __forceinline__ double dist64(const float *__restrict__ x, const float *c, int d) {
@@ -287,31 +286,46 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                         }
                     }
             }
-            // lane holds rows 4g + r of column l16 of each (mi, ni) block
+            // Lane holds rows 4g + r of column l16 of each (mi, ni) block: per
+            // point (mi, r) four candidates per lane, 64 per DPP row.  Three
+            // row minimums give the lexicographic (value, index) minimum and
+            // the smallest value among the other candidates.
+            float cn[4];
+            int jn[4];
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni) {
-                const int j = cc * 64 + ni * 16 + l16;
-                const float cn = cnorm[j];
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float f = cn - 2.0f * acc[mi][ni][r];
-                        bt[mi][r] = merge(bt[mi][r], Best{f, j, INFINITY});
-                    }
+                jn[ni] = cc * 64 + ni * 16 + l16;
+                cn[ni] = cnorm[jn[ni]];
             }
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float f[4];
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) f[ni] = cn[ni] - 2.0f * acc[mi][ni][r];
+                    const float m1 = row_min(fminf(fminf(f[0], f[1]), fminf(f[2], f[3])));
+                    int jj = 0x7fffffff;
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) jj = min(jj, f[ni] == m1 ? jn[ni] : 0x7fffffff);
+                    jj = row_min(jj);
+                    float m2 = INFINITY;
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) m2 = fminf(m2, jn[ni] == jj ? INFINITY : f[ni]);
+                    m2 = row_min(m2);
+                    bt[mi][r] = merge(bt[mi][r], Best{m1, jj, m2});
+                }
         }
-        // merge over the 16 columns held by one DPP row; lane l16 == 0 publishes
+        // lane l16 == 0 of each row publishes its four points
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const Best b = row_merge(bt[mi][r]);
                 if (l16 == 0) {
                     const int pt = mi * 16 + 4 * g + r;
-                    best1[pt] = b.b1;
-                    best2[pt] = b.b2;
-                    bidx[pt] = b.i1;
+                    best1[pt] = bt[mi][r].b1;
+                    best2[pt] = bt[mi][r].b2;
+                    bidx[pt] = bt[mi][r].i1;
                 }
             }
         wave_sync();
