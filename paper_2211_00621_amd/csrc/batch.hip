@@ -173,12 +173,51 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
     }
 }
 
+// Column quad j of a matvec tile's adjoint: gA rows r = r0, r0 + step, ...
+// below r1 get g[r] x, and the function returns the sum over those rows of
+// g[r] A[r][4j..4j+3] (in row order, four rows per round).
+__device__ __forceinline__ float4 matvec_adj_cols(const float4 *__restrict__ a4, const float4 *__restrict__ x4,
+                                                  const float *__restrict__ g, float4 *__restrict__ ga4, int64_t c4,
+                                                  int64_t j, int64_t r0, int64_t r1, int step) {
+    const float4 xj = x4[j];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int64_t r = r0;
+    for (; r + 3 * step < r1; r += 4 * step) {
+        float4 av[4];
+        float gv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            av[u] = a4[(r + u * step) * c4 + j];
+            gv[u] = g[r + u * step];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc.x += av[u].x * gv[u];
+            acc.y += av[u].y * gv[u];
+            acc.z += av[u].z * gv[u];
+            acc.w += av[u].w * gv[u];
+            ga4[(r + u * step) * c4 + j] = make_float4(gv[u] * xj.x, gv[u] * xj.y, gv[u] * xj.z, gv[u] * xj.w);
+        }
+    }
+    for (; r < r1; r += step) {
+        const float gr = g[r];
+        const float4 av = a4[r * c4 + j];
+        acc.x += av.x * gr;
+        acc.y += av.y * gr;
+        acc.z += av.z * gr;
+        acc.w += av.w * gr;
+        ga4[r * c4 + j] = make_float4(gr * xj.x, gr * xj.y, gr * xj.z, gr * xj.w);
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ tasks, const TileDev *__restrict__ tiles,
                                                   int64_t ntiles, const float *__restrict__ A,
                                                   const float *__restrict__ B, const float *__restrict__ gout,
                                                   float *__restrict__ gA, float *__restrict__ gB,
                                                   float *__restrict__ part, unsigned *ticket, int vec) {
     __shared__ int64_t slot;
+    __shared__ float4 red4[NT];
     for (;;) {
         const int64_t t = next_tile(ticket, &slot);
         if (t >= ntiles) break;
@@ -238,45 +277,40 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             const float *a = A + tk.a_off;
             float *ga = gA + tk.a_off;
             if (vec && ((tk.a_off | tk.b_off | c) & 3) == 0) {
-                // four consecutive columns per thread
+                // four consecutive columns per thread; when there are fewer
+                // than NT column quads, the threads split the rows into P
+                // phases (rows ph, ph + P, ...) and the phase partial column
+                // sums are added in phase order through LDS
                 const int64_t c4 = c >> 2;
+                const int P = c4 >= NT ? 1 : (int)(NT / c4);
                 const float4 *a4 = reinterpret_cast<const float4 *>(a), *x4 = reinterpret_cast<const float4 *>(x);
                 float4 *ga4 = reinterpret_cast<float4 *>(ga);
-                for (int64_t j = threadIdx.x; j < c4; j += NT) {
-                    const float4 xj = x4[j];
-                    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-                    int64_t r = tl.begin;
-                    for (; r + 3 < tl.end; r += 4) {
-                        float4 av[4];
-                        float gv[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            av[u] = a4[(r + u) * c4 + j];
-                            gv[u] = g[r + u];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            acc.x += av[u].x * gv[u];
-                            acc.y += av[u].y * gv[u];
-                            acc.z += av[u].z * gv[u];
-                            acc.w += av[u].w * gv[u];
-                            ga4[(r + u) * c4 + j] = make_float4(gv[u] * xj.x, gv[u] * xj.y, gv[u] * xj.z, gv[u] * xj.w);
-                        }
+                float *dst = tl.part >= 0 ? part + tl.part : gB + tk.b_off;
+                if (P == 1) {
+                    for (int64_t j = threadIdx.x; j < c4; j += NT) {
+                        const float4 s4 = matvec_adj_cols(a4, x4, g, ga4, c4, j, tl.begin, tl.end, 1);
+                        dst[4 * j + 0] = s4.x;
+                        dst[4 * j + 1] = s4.y;
+                        dst[4 * j + 2] = s4.z;
+                        dst[4 * j + 3] = s4.w;
                     }
-                    for (; r < tl.end; ++r) {
-                        const float gr = g[r];
-                        const float4 av = a4[r * c4 + j];
-                        acc.x += av.x * gr;
-                        acc.y += av.y * gr;
-                        acc.z += av.z * gr;
-                        acc.w += av.w * gr;
-                        ga4[r * c4 + j] = make_float4(gr * xj.x, gr * xj.y, gr * xj.z, gr * xj.w);
+                } else {
+                    const int j = (int)(threadIdx.x % c4), ph = (int)(threadIdx.x / c4);
+                    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (ph < P) s4 = matvec_adj_cols(a4, x4, g, ga4, c4, j, tl.begin + ph, tl.end, P);
+                    red4[threadIdx.x] = s4;
+                    __syncthreads();
+                    if (threadIdx.x < c4) {
+                        float4 t4 = red4[threadIdx.x];
+                        for (int q = 1; q < P; ++q) {
+                            const float4 u = red4[q * c4 + threadIdx.x];
+                            t4.x += u.x; t4.y += u.y; t4.z += u.z; t4.w += u.w;
+                        }
+                        dst[4 * threadIdx.x + 0] = t4.x;
+                        dst[4 * threadIdx.x + 1] = t4.y;
+                        dst[4 * threadIdx.x + 2] = t4.z;
+                        dst[4 * threadIdx.x + 3] = t4.w;
                     }
-                    float *dst = tl.part >= 0 ? part + tl.part + 4 * j : gB + tk.b_off + 4 * j;
-                    dst[0] = acc.x;
-                    dst[1] = acc.y;
-                    dst[2] = acc.z;
-                    dst[3] = acc.w;
                 }
             } else {
                 for (int64_t j = threadIdx.x; j < c; j += NT) {
