@@ -45,10 +45,11 @@ FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 # taken: once that file changes the figure no longer describes the kernel and
 # the bench reports null.
 TRAFFIC = {
-    # k_gemm_mfma<128,64,4,2,0,0>, 2048^3: 100.74 MB fetched (A and B panels re-read once per XCD that
-    # needs them; 33.6 MB is the algorithmic minimum) + 16.78 MB written (C)
-    "gemm_nn": {"file": "gemm.hip", "bytes": 117514427,
-                "source": "46c407011de154c0da4502fa5d9c9c1f8c426e3c73b33d97fd2f6088cf11ebc2"},
+    # k_gemm_mfma<128,64,4,2,0,0>, 2048^3: 119.88 MB fetched (A and B panels re-read by each XCD that
+    # needs them, plus two clamped slices past the end per tile; 33.6 MB is the algorithmic minimum)
+    # + 16.78 MB written (C)
+    "gemm_nn": {"file": "gemm.hip", "bytes": 136651622,
+                "source": "91603e2bfccc3b24cd6b6b4b4cc4b4183203ec50f4a1d0604ffe40d2be7f85e5"},
     # k_seg_span, 65536 rows / 32.1 M values: 130.46 MB fetched + 0.26 MB written (1.01x algorithmic)
     "seg_span": {"file": "segmented.hip", "bytes": 130721777,
                  "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},

@@ -559,16 +559,32 @@ __global__ void __launch_bounds__(NT) k_kmeans_divide_plain(const float *__restr
 }
 
 // ---------------------------------------------------------------- SSE and its gradient
+// Partial sums of (x - c_label)^2, one per block.  VEC: d % 4 == 0 and X, C
+// 16-byte aligned (16-byte loads, the vector index split by 32-bit division
+// when n*d/4 < 2^32, which it is for any X below 16 GiB).
+template <bool VEC>
 __global__ void __launch_bounds__(NT) k_sse_partial(const float *__restrict__ X, int64_t n, int d,
                                                     const float *__restrict__ C,
                                                     const int32_t *__restrict__ labels, float *__restrict__ part) {
     __shared__ float red[NT / kWave];
     float acc = 0.f;
-    const int64_t total = n * d;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        const int64_t p = e / d;
-        const float diff = X[e] - C[(int64_t)labels[p] * d + (e - p * d)];
-        acc += diff * diff;
+    if constexpr (VEC) {
+        const uint32_t dv = (uint32_t)d / 4, nv = (uint32_t)(n * d / 4);
+        const float4 *X4 = reinterpret_cast<const float4 *>(X), *C4 = reinterpret_cast<const float4 *>(C);
+        for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nv; i += gridDim.x * NT) {
+            const uint32_t p = i / dv, q = i - p * dv;
+            const float4 x = X4[i];
+            const float4 c = C4[(uint32_t)labels[p] * dv + q];
+            const float a = x.x - c.x, b = x.y - c.y, e = x.z - c.z, f = x.w - c.w;
+            acc += (a * a + b * b) + (e * e + f * f);
+        }
+    } else {
+        const int64_t total = n * d;
+        for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+            const int64_t p = e / d;
+            const float diff = X[e] - C[(int64_t)labels[p] * d + (e - p * d)];
+            acc += diff * diff;
+        }
     }
     acc = block_reduce<Red<MX_ADD, float>, NT>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -756,7 +772,11 @@ mx_status mx_kmeans_sse_f32(const float *X_dev, int64_t n, int d, const float *C
                "%s: workspace needs %zu bytes, 256-byte aligned", who, need);
     float *part = (float *)((char *)ws + kCounterBytes);
     int nb = (int)std::min<int64_t>(1024, ceil_div(n * d > 0 ? n * d : 1, NT * 4));
-    hipLaunchKernelGGL(k_sse_partial, dim3(nb), dim3(NT), 0, stream, X_dev, n, d, C_dev, labels_dev, part);
+    const bool vec = d % 4 == 0 && (uintptr_t)X_dev % 16 == 0 && (uintptr_t)C_dev % 16 == 0 && n * d / 4 < (1LL << 32);
+    if (vec)
+        hipLaunchKernelGGL(k_sse_partial<true>, dim3(nb), dim3(NT), 0, stream, X_dev, n, d, C_dev, labels_dev, part);
+    else
+        hipLaunchKernelGGL(k_sse_partial<false>, dim3(nb), dim3(NT), 0, stream, X_dev, n, d, C_dev, labels_dev, part);
     hipLaunchKernelGGL(k_sse_final, dim3(1), dim3(NT), 0, stream, part, nb, sse_dev);
     return last_launch(who);
 }

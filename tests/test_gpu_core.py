@@ -389,7 +389,9 @@ def _abs_prod_sum(A, B):
 
 
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (128, 128, 32), (200, 130, 70), (257, 511, 33),
-                                   (64, 300, 1000), (129, 127, 129), (3, 1025, 5)])
+                                   (64, 300, 1000), (129, 127, 129), (3, 1025, 5),
+                                   # K a multiple of 64: interior tiles take the pipelined loop
+                                   (256, 192, 128), (300, 200, 64), (513, 257, 320)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_mmr_shapes_vs_oracle(M, N, K, ta, tb):
     say("mmr", M, N, K, ta, tb)
