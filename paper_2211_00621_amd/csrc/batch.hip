@@ -34,6 +34,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int kDot = 0, kMatvec = 1;
 constexpr int kMinTile = 4096;
+constexpr int kXLds = 2048;  // matvec x staged in LDS up to this many columns
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
@@ -72,6 +73,7 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
                                                   float *__restrict__ part, unsigned *ticket, int vec) {
     __shared__ int64_t slot;
     __shared__ float red[NT / kWave];
+    __shared__ float xs[kXLds];
     using R = Red<MX_ADD, float>;
     for (;;) {
         const int64_t t = next_tile(ticket, &slot);
@@ -121,36 +123,48 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
                 else out[tk.out_off] = acc;
             }
         } else {
-            // 16 lanes per row, 16 rows at a time, four loads per lane in flight
+            // 16 lanes per row, 16 rows at a time.  x is staged in LDS once
+            // per tile (when it fits), so every row can be read with 16-byte
+            // loads whatever its alignment: a scalar head up to the next
+            // 16-byte boundary of A, the vector body (eight loads per lane in
+            // flight), a scalar tail; x values come from LDS.
             const int grp = threadIdx.x >> 4, l = threadIdx.x & 15;
             const int64_t c = tk.cols;
             const float *x = B + tk.b_off;
-            const bool v4 = vec && ((tk.a_off | tk.b_off | c) & 3) == 0;
+            const bool stage = vec && c <= kXLds;
+            if (stage) {
+                for (int64_t q = threadIdx.x; q < c; q += NT) xs[q] = x[q];
+                __syncthreads();
+            }
             for (int64_t r0 = tl.begin; r0 < tl.end; r0 += NT / 16) {
                 const int64_t r = r0 + grp;
                 float ac[4] = {0.f, 0.f, 0.f, 0.f};
                 if (r < tl.end) {
-                    const float *row = A + tk.a_off + r * c;
-                    if (v4) {
-                        const float4 *row4 = reinterpret_cast<const float4 *>(row);
-                        const float4 *x4 = reinterpret_cast<const float4 *>(x);
-                        const int64_t c4 = c >> 2;
-                        int64_t j = l;
-                        for (; j + 48 < c4; j += 64) {
-                            float4 av[4], xv[4];
+                    const int64_t e0 = tk.a_off + r * c;  // row start in A
+                    const float *row = A + e0;
+                    if (stage) {
+                        const int64_t head = ((4 - (e0 & 3)) & 3) < c ? ((4 - (e0 & 3)) & 3) : c;
+                        const int64_t nb4 = (c - head) >> 2;
+                        const float4 *row4 = reinterpret_cast<const float4 *>(row + head);
+                        if (l < head) ac[1] += row[l] * xs[l];
+                        int64_t v = l;
+                        for (; v + 112 < nb4; v += 128) {
+                            float4 av[8];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                av[u] = row4[j + 16 * u];
-                                xv[u] = x4[j + 16 * u];
+                            for (int u = 0; u < 8; ++u) av[u] = row4[v + 16 * u];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const float *xq = xs + head + 4 * (v + 16 * u);
+                                ac[u & 3] += av[u].x * xq[0] + av[u].y * xq[1] + av[u].z * xq[2] + av[u].w * xq[3];
                             }
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)
-                                ac[u] += av[u].x * xv[u].x + av[u].y * xv[u].y + av[u].z * xv[u].z + av[u].w * xv[u].w;
                         }
-                        for (; j < c4; j += 16) {
-                            const float4 av = row4[j], xv = x4[j];
-                            ac[0] += av.x * xv.x + av.y * xv.y + av.z * xv.z + av.w * xv.w;
+                        for (; v < nb4; v += 16) {
+                            const float4 av = row4[v];
+                            const float *xq = xs + head + 4 * v;
+                            ac[0] += av.x * xq[0] + av.y * xq[1] + av.z * xq[2] + av.w * xq[3];
                         }
+                        const int64_t t0 = head + 4 * nb4;
+                        if (t0 + l < c) ac[2] += row[t0 + l] * xs[t0 + l];
                     } else {
                         int64_t j = l;
                         for (; j + 48 < c; j += 64) {
@@ -173,42 +187,90 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
     }
 }
 
-// Column quad j of a matvec tile's adjoint: gA rows r = r0, r0 + step, ...
-// below r1 get g[r] x, and the function returns the sum over those rows of
-// g[r] A[r][4j..4j+3] (in row order, four rows per round).
-__device__ __forceinline__ float4 matvec_adj_cols(const float4 *__restrict__ a4, const float4 *__restrict__ x4,
-                                                  const float *__restrict__ g, float4 *__restrict__ ga4, int64_t c4,
-                                                  int64_t j, int64_t r0, int64_t r1, int step) {
-    const float4 xj = x4[j];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+// Column group j of a matvec tile's adjoint, V = float4 (4 columns, rows
+// 16-byte aligned) or float (1 column): gA rows r = r0, r0 + step, ... below
+// r1 get g[r] x, and the function returns the sum over those rows of
+// g[r] A[r][cols of j] in row order, U rows per round in flight.
+template <class V> struct Lanes;
+template <> struct Lanes<float> {
+    static __device__ __forceinline__ float scale(float v, float s) { return v * s; }
+    static __device__ __forceinline__ void fma(float &acc, float a, float s) { acc += a * s; }
+};
+template <> struct Lanes<float4> {
+    static __device__ __forceinline__ float4 scale(float4 v, float s) { return make_float4(v.x * s, v.y * s, v.z * s, v.w * s); }
+    static __device__ __forceinline__ void fma(float4 &acc, float4 a, float s) {
+        acc.x += a.x * s;
+        acc.y += a.y * s;
+        acc.z += a.z * s;
+        acc.w += a.w * s;
+    }
+};
+
+template <class V, int U>
+__device__ __forceinline__ V matvec_adj_cols(const V *__restrict__ a, const V *__restrict__ x,
+                                             const float *__restrict__ g, V *__restrict__ ga, int64_t cv,
+                                             int64_t j, int64_t r0, int64_t r1, int step) {
+    using Ln = Lanes<V>;
+    const V xj = x[j];
+    V acc;
+    __builtin_memset(&acc, 0, sizeof acc);
     int64_t r = r0;
-    for (; r + 3 * step < r1; r += 4 * step) {
-        float4 av[4];
-        float gv[4];
+    for (; r + (U - 1) * step < r1; r += U * step) {
+        V av[U];
+        float gv[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            av[u] = a4[(r + u * step) * c4 + j];
+        for (int u = 0; u < U; ++u) {
+            av[u] = a[(r + u * step) * cv + j];
             gv[u] = g[r + u * step];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            acc.x += av[u].x * gv[u];
-            acc.y += av[u].y * gv[u];
-            acc.z += av[u].z * gv[u];
-            acc.w += av[u].w * gv[u];
-            ga4[(r + u * step) * c4 + j] = make_float4(gv[u] * xj.x, gv[u] * xj.y, gv[u] * xj.z, gv[u] * xj.w);
+        for (int u = 0; u < U; ++u) {
+            Ln::fma(acc, av[u], gv[u]);
+            ga[(r + u * step) * cv + j] = Ln::scale(xj, gv[u]);
         }
     }
     for (; r < r1; r += step) {
         const float gr = g[r];
-        const float4 av = a4[r * c4 + j];
-        acc.x += av.x * gr;
-        acc.y += av.y * gr;
-        acc.z += av.z * gr;
-        acc.w += av.w * gr;
-        ga4[r * c4 + j] = make_float4(gr * xj.x, gr * xj.y, gr * xj.z, gr * xj.w);
+        Ln::fma(acc, a[r * cv + j], gr);
+        ga[r * cv + j] = Ln::scale(xj, gr);
     }
     return acc;
+}
+
+// One matvec tile's backward with column groups of V: one thread per column
+// group; when there are fewer groups than threads the threads split the rows
+// into P phases (rows ph, ph + P, ...) and the phase partials are added in
+// phase order through LDS.  dst: the tile's partial column sums or gB.
+template <class V, int U>
+__device__ __forceinline__ void matvec_adj_tile(const V *__restrict__ a, const V *__restrict__ x,
+                                                const float *__restrict__ g, V *__restrict__ ga, int64_t cv,
+                                                int64_t rb, int64_t re, float *__restrict__ dst, V *red) {
+    constexpr int W = sizeof(V) / sizeof(float);
+    const int P = cv >= NT ? 1 : (int)(NT / cv);
+    if (P == 1) {
+        for (int64_t j = threadIdx.x; j < cv; j += NT) {
+            const V s = matvec_adj_cols<V, U>(a, x, g, ga, cv, j, rb, re, 1);
+            __builtin_memcpy(dst + W * j, &s, sizeof s);
+        }
+    } else {
+        const int j = (int)(threadIdx.x % cv), ph = (int)(threadIdx.x / cv);
+        V s;
+        __builtin_memset(&s, 0, sizeof s);
+        if (ph < P) s = matvec_adj_cols<V, U>(a, x, g, ga, cv, j, rb + ph, re, P);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < cv) {
+            float t[W];
+            __builtin_memcpy(t, &red[threadIdx.x], sizeof t);
+            for (int q = 1; q < P; ++q) {
+                float u[W];
+                __builtin_memcpy(u, &red[q * cv + threadIdx.x], sizeof u);
+#pragma unroll
+                for (int e = 0; e < W; ++e) t[e] += u[e];
+            }
+            __builtin_memcpy(dst + W * threadIdx.x, t, sizeof t);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ tasks, const TileDev *__restrict__ tiles,
@@ -218,6 +280,7 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
                                                   float *__restrict__ part, unsigned *ticket, int vec) {
     __shared__ int64_t slot;
     __shared__ float4 red4[NT];
+    __shared__ float red1[NT];
     for (;;) {
         const int64_t t = next_tile(ticket, &slot);
         if (t >= ntiles) break;
@@ -276,69 +339,12 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             const float *x = B + tk.b_off, *g = gout + tk.out_off;
             const float *a = A + tk.a_off;
             float *ga = gA + tk.a_off;
-            if (vec && ((tk.a_off | tk.b_off | c) & 3) == 0) {
-                // four consecutive columns per thread; when there are fewer
-                // than NT column quads, the threads split the rows into P
-                // phases (rows ph, ph + P, ...) and the phase partial column
-                // sums are added in phase order through LDS
-                const int64_t c4 = c >> 2;
-                const int P = c4 >= NT ? 1 : (int)(NT / c4);
-                const float4 *a4 = reinterpret_cast<const float4 *>(a), *x4 = reinterpret_cast<const float4 *>(x);
-                float4 *ga4 = reinterpret_cast<float4 *>(ga);
-                float *dst = tl.part >= 0 ? part + tl.part : gB + tk.b_off;
-                if (P == 1) {
-                    for (int64_t j = threadIdx.x; j < c4; j += NT) {
-                        const float4 s4 = matvec_adj_cols(a4, x4, g, ga4, c4, j, tl.begin, tl.end, 1);
-                        dst[4 * j + 0] = s4.x;
-                        dst[4 * j + 1] = s4.y;
-                        dst[4 * j + 2] = s4.z;
-                        dst[4 * j + 3] = s4.w;
-                    }
-                } else {
-                    const int j = (int)(threadIdx.x % c4), ph = (int)(threadIdx.x / c4);
-                    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (ph < P) s4 = matvec_adj_cols(a4, x4, g, ga4, c4, j, tl.begin + ph, tl.end, P);
-                    red4[threadIdx.x] = s4;
-                    __syncthreads();
-                    if (threadIdx.x < c4) {
-                        float4 t4 = red4[threadIdx.x];
-                        for (int q = 1; q < P; ++q) {
-                            const float4 u = red4[q * c4 + threadIdx.x];
-                            t4.x += u.x; t4.y += u.y; t4.z += u.z; t4.w += u.w;
-                        }
-                        dst[4 * threadIdx.x + 0] = t4.x;
-                        dst[4 * threadIdx.x + 1] = t4.y;
-                        dst[4 * threadIdx.x + 2] = t4.z;
-                        dst[4 * threadIdx.x + 3] = t4.w;
-                    }
-                }
-            } else {
-                for (int64_t j = threadIdx.x; j < c; j += NT) {
-                    const float xj = x[j];
-                    float acc = 0.f;
-                    int64_t r = tl.begin;
-                    for (; r + 3 < tl.end; r += 4) {
-                        float av[4], gv[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            av[u] = a[(r + u) * c + j];
-                            gv[u] = g[r + u];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            acc += av[u] * gv[u];
-                            ga[(r + u) * c + j] = gv[u] * xj;
-                        }
-                    }
-                    for (; r < tl.end; ++r) {
-                        const float gr = g[r];
-                        acc += a[r * c + j] * gr;
-                        ga[r * c + j] = gr * xj;
-                    }
-                    if (tl.part >= 0) part[tl.part + j] = acc;
-                    else gB[tk.b_off + j] = acc;
-                }
-            }
+            float *dst = tl.part >= 0 ? part + tl.part : gB + tk.b_off;
+            if (vec && ((tk.a_off | tk.b_off | c) & 3) == 0)
+                matvec_adj_tile<float4, 8>(reinterpret_cast<const float4 *>(a), reinterpret_cast<const float4 *>(x),
+                                           g, reinterpret_cast<float4 *>(ga), c >> 2, tl.begin, tl.end, dst, red4);
+            else
+                matvec_adj_tile<float, 16>(a, x, g, ga, c, tl.begin, tl.end, dst, red1);
         }
     }
 }

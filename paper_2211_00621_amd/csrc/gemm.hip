@@ -328,11 +328,12 @@ mx_status check(const char *who, int ta, int tb, int64_t M, int64_t N, int64_t K
     return MX_OK;
 }
 
-// Tile shape: 128 x 64 with 8 waves (2 x 2 blocks of 16 x 16 per wave), the
-// fastest of the configurations below for every transpose case at 2048^3 on
-// MI355X (its 512 threads hide each other's LDS and barrier waits better
-// than 4 waves with twice the work each); MX_GEMM_TILE in the environment
-// forces one of them (for tuning).
+// Tile shapes, 8 waves each (512 threads hide each other's LDS and barrier
+// waits better than 4 waves with twice the work): 128 x 128 (2 x 4 blocks of
+// 16 x 16 per wave) when there are enough tiles for every CU, 128 x 64
+// (2 x 2 per wave) otherwise and for A B^T, where it measured faster at
+// 2048^3; MX_GEMM_TILE in the environment forces one of the configurations
+// below (for tuning).
 template <int BM, int BN, int WM, int WN>
 mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A, const float *B, float *C,
                       int vec_ok, hipStream_t s) {
@@ -354,7 +355,7 @@ mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const flo
 // Tile configurations: BM x BN block tile, WM x WN waves.
 enum GemmTile { kT128x64 = 1, kT128x128, kT128x64w8, kT128x128w8, kT64x64 };
 
-int gemm_tile_choice(int64_t M, int64_t N, const DeviceInfo *d) {
+int gemm_tile_choice(int ta, int tb, int64_t M, int64_t N, const DeviceInfo *d) {
     static int forced = -1;
     if (forced < 0) {
         forced = 0;
@@ -367,7 +368,10 @@ int gemm_tile_choice(int64_t M, int64_t N, const DeviceInfo *d) {
         }
     }
     if (forced) return forced;
-    (void)M, (void)N, (void)d;
+    // 128 x 128 when it still gives every CU a tile, except for A B^T (both
+    // operands [row][k]), where the 128 x 64 tile measured faster
+    const int64_t big = ceil_div(M, 128) * ceil_div(N, 128);
+    if (big >= d->num_cus && !(ta == 0 && tb == 1)) return kT128x128w8;
     return kT128x64w8;
 }
 
@@ -387,7 +391,7 @@ mx_status mx_map_map_reduce_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
     const int64_t lda = ta ? M : K, ldb = tb ? K : N;
     const int vec_ok = ((uintptr_t)A_dev % 16 == 0) && ((uintptr_t)B_dev % 16 == 0) && (lda % 4 == 0) &&
                        (ldb % 4 == 0);
-    switch (gemm_tile_choice(M, N, d)) {
+    switch (gemm_tile_choice(ta, tb, M, N, d)) {
     case kT128x64: return launch_gemm<128, 64, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
     case kT128x64w8: return launch_gemm<128, 64, 4, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
     case kT128x128w8: return launch_gemm<128, 128, 4, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
