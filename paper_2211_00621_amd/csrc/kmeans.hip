@@ -69,23 +69,6 @@ __device__ __forceinline__ Best merge(Best a, Best b) {
     return r;
 }
 
-// Minimum over the 16 lanes of a DPP row; every lane of the row gets it.
-__device__ __forceinline__ float row_min(float v) {
-    v = fminf(v, dpp_move<0xB1, 0xF>(v, v));   // quad_perm [1,0,3,2]
-    v = fminf(v, dpp_move<0x4E, 0xF>(v, v));   // quad_perm [2,3,0,1]
-    v = fminf(v, dpp_move<0x141, 0xF>(v, v));  // row_half_mirror
-    v = fminf(v, dpp_move<0x140, 0xF>(v, v));  // row_mirror
-    return v;
-}
-__device__ __forceinline__ int row_min(int v) {
-    v = min(v, dpp_move<0xB1, 0xF>(v, v));
-    v = min(v, dpp_move<0x4E, 0xF>(v, v));
-    v = min(v, dpp_move<0x141, 0xF>(v, v));
-    v = min(v, dpp_move<0x140, 0xF>(v, v));
-    return v;
-}
-
-
 // binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
 __device__ __forceinline__ double dist64(const float *__restrict__ x, const float *c, int d) {
     double acc = 0.0;
@@ -252,82 +235,81 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             if (g == 0) xnorm[mi * 16 + l16] = s;
         }
 
-        // ---- f = |c|^2 - 2 x.c over column chunks of 64 centroids
-        Best bt[4][4];
+        // ---- f = |c|^2 - 2 c.x over chunks of 64 centroids.  Centroids are the
+        //      MFMA's A operand and points its B operand, so lane (g, l16) ends
+        //      with rows 4g + r (centroids) of column l16 (point) of each
+        //      (centroid block ci, point block pi): 16 candidates per point in
+        //      one lane, 64 over the four lanes l16 + 16g.
+        Best bt[4];
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bt[mi][r] = Best{INFINITY, 0x7fffffff, INFINITY};
+        for (int pi = 0; pi < 4; ++pi) bt[pi] = Best{INFINITY, 0x7fffffff, INFINITY};
 #pragma unroll
         for (int cc = 0; cc < KP / 64; ++cc) {
-            v4f acc[4][4];
+            v4f acc[4][4];  // [ci][pi]
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
+            for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int pi = 0; pi < 4; ++pi) acc[ci][pi] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kc = 0; kc < DP / 32; ++kc) {
                 float4 cb[4][2];
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni) {
-                    const float *q = Cs + (cc * 64 + ni * 16 + l16) * LDC + kc * 32 + 8 * g;
-                    cb[ni][0] = *reinterpret_cast<const float4 *>(q);
-                    cb[ni][1] = *reinterpret_cast<const float4 *>(q + 4);
+                for (int ci = 0; ci < 4; ++ci) {
+                    const float *q = Cs + (cc * 64 + ci * 16 + l16) * LDC + kc * 32 + 8 * g;
+                    cb[ci][0] = *reinterpret_cast<const float4 *>(q);
+                    cb[ci][1] = *reinterpret_cast<const float4 *>(q + 4);
                 }
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
-                    for (int mi = 0; mi < 4; ++mi) {
-                        const float av = vget<float4, float>(xa[mi][kc][kk >> 2], kk & 3);
+                    for (int ci = 0; ci < 4; ++ci) {
+                        const float av = vget<float4, float>(cb[ci][kk >> 2], kk & 3);
 #pragma unroll
-                        for (int ni = 0; ni < 4; ++ni) {
-                            const float bv = vget<float4, float>(cb[ni][kk >> 2], kk & 3);
-                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[mi][ni], 0, 0, 0);
+                        for (int pi = 0; pi < 4; ++pi) {
+                            const float bv = vget<float4, float>(xa[pi][kc][kk >> 2], kk & 3);
+                            acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ci][pi], 0, 0, 0);
                         }
                     }
             }
-            // Lane holds rows 4g + r of column l16 of each (mi, ni) block: per
-            // point (mi, r) four candidates per lane, 64 per DPP row.  Three
-            // row minimums give the lexicographic (value, index) minimum and
-            // the smallest value among the other candidates.
-            float cn[4];
-            int jn[4];
+            float cn[4][4];
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni) {
-                jn[ni] = cc * 64 + ni * 16 + l16;
-                cn[ni] = cnorm[jn[ni]];
+            for (int ci = 0; ci < 4; ++ci) {
+                const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + cc * 64 + ci * 16 + 4 * g);
+                cn[ci][0] = c4.x; cn[ci][1] = c4.y; cn[ci][2] = c4.z; cn[ci][3] = c4.w;
             }
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
+            for (int pi = 0; pi < 4; ++pi) {
+                // in-lane scan in increasing centroid index: (value, index) minimum
+                // and the smallest value among the others
+                float b1 = INFINITY, b2 = INFINITY;
+                int i1 = 0x7fffffff;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float f[4];
+                for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
-                    for (int ni = 0; ni < 4; ++ni) f[ni] = cn[ni] - 2.0f * acc[mi][ni][r];
-                    const float m1 = row_min(fminf(fminf(f[0], f[1]), fminf(f[2], f[3])));
-                    int jj = 0x7fffffff;
-#pragma unroll
-                    for (int ni = 0; ni < 4; ++ni) jj = min(jj, f[ni] == m1 ? jn[ni] : 0x7fffffff);
-                    jj = row_min(jj);
-                    float m2 = INFINITY;
-#pragma unroll
-                    for (int ni = 0; ni < 4; ++ni) m2 = fminf(m2, jn[ni] == jj ? INFINITY : f[ni]);
-                    m2 = row_min(m2);
-                    bt[mi][r] = merge(bt[mi][r], Best{m1, jj, m2});
-                }
+                    for (int r = 0; r < 4; ++r) {
+                        const float f = cn[ci][r] - 2.0f * acc[ci][pi][r];
+                        const int jj = cc * 64 + ci * 16 + 4 * g + r;
+                        b2 = fminf(b2, fmaxf(b1, f));
+                        i1 = f < b1 ? jj : i1;
+                        b1 = fminf(b1, f);
+                    }
+                Best b{b1, i1, b2};
+                // merge over the four lanes holding this point
+                b = merge(b, Best{__shfl_xor(b.b1, 16, kWave), __shfl_xor(b.i1, 16, kWave), __shfl_xor(b.b2, 16, kWave)});
+                b = merge(b, Best{__shfl_xor(b.b1, 32, kWave), __shfl_xor(b.i1, 32, kWave), __shfl_xor(b.b2, 32, kWave)});
+                bt[pi] = merge(bt[pi], b);
+            }
         }
-        // lane l16 == 0 of each row publishes its four points
+        // lanes g == 0 publish their four points
+        if (g == 0) {
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (l16 == 0) {
-                    const int pt = mi * 16 + 4 * g + r;
-                    best1[pt] = bt[mi][r].b1;
-                    best2[pt] = bt[mi][r].b2;
-                    bidx[pt] = bt[mi][r].i1;
-                }
+            for (int pi = 0; pi < 4; ++pi) {
+                const int pt = pi * 16 + l16;
+                best1[pt] = bt[pi].b1;
+                best2[pt] = bt[pi].b2;
+                bidx[pt] = bt[pi].i1;
             }
+        }
         wave_sync();
         // ---- certify each label (lane = point); uncertified points are
         //      recomputed in binary64 by the whole wave, lanes over centroids
