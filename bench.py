@@ -236,10 +236,61 @@ def bench_nested(args):
         "timing": "value and ms_per_step: K eager steps between two events (graph_ms_per_step: the same step "
                   "replayed from a HIP graph); parts: K back-to-back launches of each part between two events",
     }
+    line["marshal"] = marshal_rates(d, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_nested(d, rows, C, gA, gB, gvals, offsets)
     del graph
     return line
+
+
+def marshal_rates(d, dev):
+    """Host-side marshaling of the 65 536 ragged rows through the C ABI:
+    mx_marshal_rows (gather into pinned staging on host threads, one
+    host-to-device copy, device lengths -> offsets scan) and mx_unmarshal_rows
+    (one device-to-host copy, scatter into the host rows).  PCIe-inclusive
+    rates, not part of `value`."""
+    import ctypes
+    import torch
+    from paper_2211_00621_amd import abi, api
+    L, v = d["L"], d["v"]
+    off = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    nseg, total = len(L), int(off[-1])
+    rows_in = [v[off[i]:off[i + 1]] for i in range(nseg)]
+    rows_out = [np.empty(int(L[i]), dtype=np.float32) for i in range(nseg)]
+    ptr_in = (ctypes.c_void_p * nseg)(*[r.ctypes.data if r.size else None for r in rows_in])
+    ptr_out = (ctypes.c_void_p * nseg)(*[r.ctypes.data if r.size else None for r in rows_out])
+    lengths = np.ascontiguousarray(L, dtype=np.int64)
+    staging = torch.empty(((total * 4 + 255) // 256) * 256 + 8 * nseg, dtype=torch.uint8, pin_memory=True)
+    values = torch.empty(total, dtype=torch.float32, device=dev)
+    lens_dev = torch.empty(nseg, dtype=torch.int64, device=dev)
+    offs_dev = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+    ws = api.workspace(abi.MX_WS_SCAN, nseg, device=dev)
+    lib = abi._L()
+    st = torch.cuda.current_stream().cuda_stream
+
+    def h2d():
+        abi._check(lib.mx_marshal_rows(ptr_in, lengths.ctypes.data, nseg, 4, staging.data_ptr(),
+                                       staging.numel(), values.data_ptr(), lens_dev.data_ptr(),
+                                       offs_dev.data_ptr(), ws.data_ptr(), ws.numel(), st), "mx_marshal_rows")
+        torch.cuda.synchronize()
+
+    def d2h():
+        abi._check(lib.mx_unmarshal_rows(values.data_ptr(), off.ctypes.data, nseg, 4, staging.data_ptr(),
+                                         staging.numel(), ptr_out, st), "mx_unmarshal_rows")
+
+    out = {}
+    for name, fn in (("host_to_device", h2d), ("device_to_host", d2h)):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            fn()
+        secs = (time.perf_counter() - t0) / 3
+        nbytes = total * 4 + (nseg + 1) * 8
+        out[name] = {"ms": round(secs * 1e3, 2), "GB/s": round(nbytes / secs / 1e9, 1)}
+    assert np.array_equal(offs_dev.cpu().numpy(), off) and all(
+        np.array_equal(a, b) for a, b in zip(rows_out[:64], rows_in[:64])), "marshal round trip"
+    out["note"] = "65 536 host rows (128 MB) through the C ABI, PCIe-inclusive; not part of value"
+    return out
 
 
 def cpu_baseline_nested(d, rows, C, gA, gB, gvals, offsets):

@@ -403,7 +403,9 @@ mx_status mx_kmeans_sse_grad_f32(const float *X_dev, int64_t n, int d, const flo
  *   dot:    gA[a_off + i] = g * B[b_off + i], gB[b_off + i] = g * A[a_off + i]
  *   matvec: gA[a_off + r*cols + c] = g[r] * B[b_off + c],
  *           gB[b_off + c] = sum_r A[a_off + r*cols + c] * g[r].
- * A plan cuts tasks into tiles of about tile_elems elements, longest first;
+ * A plan cuts tasks into tiles of equal bytes, longest first: dots into
+ * ranges of tile_elems elements, matvecs into whole-row ranges of about
+ * 2 * tile_elems elements (one streamed operand instead of two);
  * forward and backward each run as one persistent launch (blocks_per_cu blocks
  * per compute unit pulling tiles with an atomic ticket) plus one combine
  * launch that adds multi-tile partials in tile order.  Results are

@@ -6,9 +6,10 @@
 // expressions -- dot products reduce (+) 0 (map2 (*) a b) and matrix-vector
 // products map (reduce (+) 0 . map2 (*) x) over rows -- as one launch.
 //
-// Plan (host, once): every task is cut into tiles of about `tile_elems`
-// elements -- element ranges for a dot, whole-row ranges for a matvec -- and
-// the tiles are ordered longest first.  Forward: a persistent grid pulls tiles
+// Plan (host, once): every task is cut into tiles of equal bytes -- element
+// ranges of `tile_elems` for a dot (two streamed operands), whole-row ranges
+// of about 2 * `tile_elems` elements for a matvec (one) -- and the tiles are
+// ordered longest first.  Forward: a persistent grid pulls tiles
 // with an atomic ticket; a single-tile task writes its result, a multi-tile dot
 // writes one partial per tile.  A combine launch adds each task's partials in
 // tile order (deterministic for a given plan) and resets the ticket.  Backward
@@ -475,7 +476,7 @@ void partial_floats(const std::vector<int64_t> &tb, int64_t ntasks, int64_t tile
             const int64_t nt = ceil_div(cols > 0 ? cols : 1, tile);
             if (nt > 1) *fwd += nt;
         } else {
-            const int64_t rpt = std::max<int64_t>(1, tile / std::max<int64_t>(cols, 1));
+            const int64_t rpt = std::max<int64_t>(1, 2 * tile / std::max<int64_t>(cols, 1));
             const int64_t nt = ceil_div(rows > 0 ? rows : 1, rpt);
             if (nt > 1) *bwd += nt * cols;
         }
@@ -514,7 +515,9 @@ mx_status build_tiles(mx_batch_plan *p) {
             tk.bwd_part = -1;
         } else {
             const int64_t c = std::max<int64_t>(tk.cols, 1);
-            const int64_t rpt = std::max<int64_t>(1, T / c);
+            // a matvec streams one operand (4 bytes per element) where a dot
+            // streams two: twice the elements give tiles of equal bytes
+            const int64_t rpt = std::max<int64_t>(1, 2 * T / c);
             const int64_t nt = std::max<int64_t>(1, ceil_div(tk.rows, rpt));
             tk.fwd_ntiles = nt;
             tk.fwd_part = -1;
