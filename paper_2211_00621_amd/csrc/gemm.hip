@@ -4,9 +4,9 @@
 // A block owns a BM x BN tile of C and walks K in slices of 32; its waves form
 // a WM x WN grid, each owning a (BM/WM) x (BN/WN) sub-tile of 16 x 16 MFMA
 // blocks.  Each operand slice is staged in LDS in the orientation it has in
-// memory -- [row][k] (row stride 36 floats) when k is contiguous, [k][row]
-// (row stride BM + 16) when rows are contiguous -- so every global load is a
-// 16-byte vector and every LDS store a 16-byte store.  Two LDS buffers, one
+// memory -- [row][k] (32-float rows, 16-byte quads swizzled by row) when k is
+// contiguous, [k][row] (row stride BM + 4) when rows are contiguous -- so
+// every global load is a 16-byte vector and every LDS store a 16-byte store.  Two LDS buffers, one
 // barrier per slice; the next slice's global loads are issued before the
 // current slice's MFMAs.
 //
@@ -31,7 +31,11 @@ namespace mx {
 namespace {
 
 constexpr int BK = 32;
-constexpr int LDK = BK + 4;  // [row][k] stride in floats
+// [row][k] slices: rows of BK = 32 floats (eight 16-byte quads) with the quad
+// position swizzled by the row, quad q of row r at q ^ ((r >> 1) & 7): the
+// 16-byte stores of two consecutive rows and the reads of quads 2g, 2g + 1 by
+// 16 consecutive rows then fall on distinct banks.
+__device__ __forceinline__ int swz(int row, int quad) { return row * BK + 4 * (quad ^ ((row >> 1) & 7)); }
 constexpr int kGroupM = 4;   // tile rows per scheduling group
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -53,8 +57,10 @@ __device__ __forceinline__ float4 ld4(const float *__restrict__ p, int64_t ld, i
 }
 
 template <int ROWS, bool ROWK> struct Operand {
-    static constexpr int LD = ROWK ? LDK : ROWS + 16;             // LDS stride in floats
-    static constexpr int FLOATS = ROWK ? ROWS * LDK : BK * (ROWS + 16);
+    // [k][row] stride: ROWS + 4 floats, so the k rows 8 apart read by the four
+    // lane groups start 32 banks apart
+    static constexpr int LD = ROWK ? BK : ROWS + 4;               // LDS stride in floats
+    static constexpr int FLOATS = ROWK ? ROWS * BK : BK * (ROWS + 4);
 };
 
 // One K-slice of an operand (ROWS rows) into registers, NT threads.
@@ -84,7 +90,7 @@ __device__ __forceinline__ void store_slice(float *__restrict__ s, const float4 
         const int idx = threadIdx.x + NT * i;
         if constexpr (ROWK) {
             const int row = idx >> 3, kq = idx & 7;
-            *reinterpret_cast<float4 *>(s + row * Op::LD + 4 * kq) = r[i];
+            *reinterpret_cast<float4 *>(s + swz(row, kq)) = r[i];
         } else {
             constexpr int Q = ROWS / 4;
             const int k = idx / Q, rq = idx % Q;
@@ -132,8 +138,9 @@ __device__ __forceinline__ void mma_slice(v4f (&acc)[BM / WM / 16][BN / WN / 16]
     if constexpr (RA) {
 #pragma unroll
         for (int i = 0; i < MI; ++i) {
-            const float *q = as + (wrow0 + 16 * i + l16) * OA::LD + 8 * g;
-            float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
+            const int row = wrow0 + 16 * i + l16;
+            const float4 lo = *reinterpret_cast<const float4 *>(as + swz(row, 2 * g));
+            const float4 hi = *reinterpret_cast<const float4 *>(as + swz(row, 2 * g + 1));
             a8[i][0] = lo.x; a8[i][1] = lo.y; a8[i][2] = lo.z; a8[i][3] = lo.w;
             a8[i][4] = hi.x; a8[i][5] = hi.y; a8[i][6] = hi.z; a8[i][7] = hi.w;
         }
@@ -141,8 +148,9 @@ __device__ __forceinline__ void mma_slice(v4f (&acc)[BM / WM / 16][BN / WN / 16]
     if constexpr (RB) {
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
-            const float *q = bs + (wcol0 + 16 * j + l16) * OB::LD + 8 * g;
-            float4 lo = *reinterpret_cast<const float4 *>(q), hi = *reinterpret_cast<const float4 *>(q + 4);
+            const int row = wcol0 + 16 * j + l16;
+            const float4 lo = *reinterpret_cast<const float4 *>(bs + swz(row, 2 * g));
+            const float4 hi = *reinterpret_cast<const float4 *>(bs + swz(row, 2 * g + 1));
             b8[j][0] = lo.x; b8[j][1] = lo.y; b8[j][2] = lo.z; b8[j][3] = lo.w;
             b8[j][4] = hi.x; b8[j][5] = hi.y; b8[j][6] = hi.z; b8[j][7] = hi.w;
         }
