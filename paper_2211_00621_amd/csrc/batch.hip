@@ -45,10 +45,13 @@ struct TaskDev {
     int64_t fwd_part, fwd_ntiles, bwd_part, bwd_ntiles;
 };
 
+// One tile, carrying the task fields its kernels need so that taking a tile
+// costs one descriptor load.
 struct TileDev {
-    int32_t task, pad;
+    int32_t task, kind;
     int64_t begin, end;  // dot: elements; matvec: rows
     int64_t part;        // partial slot (float offset) or -1 to write the result directly
+    int64_t cols, a_off, b_off, out_off;
 };
 
 // sum over the 16 lanes of a DPP row, result in every lane of the row
@@ -61,26 +64,31 @@ __device__ __forceinline__ float row16_sum(float v) {
     return v;
 }
 
-__device__ __forceinline__ int64_t next_tile(unsigned *ticket, int64_t *slot) {
-    __syncthreads();  // everyone has read the previous slot
-    if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(ticket, 1u);
-    __syncthreads();
-    return *slot;
-}
+// Tile loop of the persistent kernels: thread 0 takes a ticket, the block
+// reads it after a barrier and loads the tile descriptor.  (Taking the next
+// ticket while the current tile streams was measured slower: a busy block
+// then holds a tile an idle block could already be working on.)
+#define MX_TILE_LOOP_BEGIN                                                         \
+    __shared__ int64_t slot;                                                     \
+    for (;;) {                                                                   \
+        __syncthreads();                                                         \
+        if (threadIdx.x == 0) slot = (int64_t)atomicAdd(ticket, 1u);             \
+        __syncthreads();                                                         \
+        const int64_t t = slot;                                                  \
+        if (t >= ntiles) break;                                                  \
+        const TileDev tl = tiles[t];                                             \
+        const TileDev &tk = tl;
+
+#define MX_TILE_LOOP_END }
 
 __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ tasks, const TileDev *__restrict__ tiles,
                                                   int64_t ntiles, const float *__restrict__ A,
                                                   const float *__restrict__ B, float *__restrict__ out,
                                                   float *__restrict__ part, unsigned *ticket, int vec) {
-    __shared__ int64_t slot;
     __shared__ float red[NT / kWave];
     __shared__ float xs[kXLds];
     using R = Red<MX_ADD, float>;
-    for (;;) {
-        const int64_t t = next_tile(ticket, &slot);
-        if (t >= ntiles) break;
-        const TileDev tl = tiles[t];
-        const TaskDev tk = tasks[tl.task];
+    MX_TILE_LOOP_BEGIN
         if (tk.kind == kDot) {
             const float *a = A + tk.a_off, *b = B + tk.b_off;
             float ac[4] = {0.f, 0.f, 0.f, 0.f};
@@ -185,7 +193,7 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
                 if (l == 0 && r < tl.end) out[tk.out_off + r] = acc;
             }
         }
-    }
+    MX_TILE_LOOP_END
 }
 
 // Column group j of a matvec tile's adjoint, V = float4 (4 columns, rows
@@ -279,14 +287,9 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
                                                   const float *__restrict__ B, const float *__restrict__ gout,
                                                   float *__restrict__ gA, float *__restrict__ gB,
                                                   float *__restrict__ part, unsigned *ticket, int vec) {
-    __shared__ int64_t slot;
     __shared__ float4 red4[NT];
     __shared__ float red1[NT];
-    for (;;) {
-        const int64_t t = next_tile(ticket, &slot);
-        if (t >= ntiles) break;
-        const TileDev tl = tiles[t];
-        const TaskDev tk = tasks[tl.task];
+    MX_TILE_LOOP_BEGIN
         if (tk.kind == kDot) {
             const float g = gout[tk.out_off];
             const float *a = A + tk.a_off, *b = B + tk.b_off;
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(NT) k_batch_bwd(const TaskDev *__restrict__ ta
             else
                 matvec_adj_tile<float, 16>(a, x, g, ga, c, tl.begin, tl.end, dst, red1);
         }
-    }
+    MX_TILE_LOOP_END
 }
 
 // sum of q = 0 .. nq-1 of p[q * stride], in q order, eight loads in flight
@@ -483,6 +486,10 @@ void partial_floats(const std::vector<int64_t> &tb, int64_t ntasks, int64_t tile
     }
 }
 
+TileDev make_tile(int64_t t, const TaskDev &tk, int64_t begin, int64_t end, int64_t part) {
+    return TileDev{(int32_t)t, tk.kind, begin, end, part, tk.cols, tk.a_off, tk.b_off, tk.out_off};
+}
+
 mx_status build_tiles(mx_batch_plan *p) {
     const int64_t T = p->cfg.tile_elems;
     std::vector<TaskDev> tasks((size_t)p->ntasks);
@@ -504,13 +511,13 @@ mx_status build_tiles(mx_batch_plan *p) {
             tk.fwd_ntiles = nt;
             tk.fwd_part = nt > 1 ? fpart : -1;
             for (int64_t q = 0; q < nt; ++q)
-                fwd.push_back(TileDev{(int32_t)t, 0, q * T, std::min(n, (q + 1) * T), nt > 1 ? fpart + q : -1});
+                fwd.push_back(make_tile(t, tk, q * T, std::min(n, (q + 1) * T), nt > 1 ? fpart + q : -1));
             if (nt > 1) {
                 fwd_list.push_back((int32_t)t);
                 fpart += nt;
             }
             for (int64_t q = 0; q < nt; ++q)
-                bwd.push_back(TileDev{(int32_t)t, 0, q * T, std::min(n, (q + 1) * T), -1});
+                bwd.push_back(make_tile(t, tk, q * T, std::min(n, (q + 1) * T), -1));
             tk.bwd_ntiles = nt;
             tk.bwd_part = -1;
         } else {
@@ -525,8 +532,8 @@ mx_status build_tiles(mx_batch_plan *p) {
             tk.bwd_part = nt > 1 ? bpart : -1;
             for (int64_t q = 0; q < nt; ++q) {
                 const int64_t b = q * rpt, e = std::min(tk.rows, (q + 1) * rpt);
-                fwd.push_back(TileDev{(int32_t)t, 0, b, e, -1});
-                bwd.push_back(TileDev{(int32_t)t, 0, b, e, nt > 1 ? bpart + q * tk.cols : -1});
+                fwd.push_back(make_tile(t, tk, b, e, -1));
+                bwd.push_back(make_tile(t, tk, b, e, nt > 1 ? bpart + q * tk.cols : -1));
             }
             if (nt > 1) {
                 bwd_list.push_back((int32_t)t);
