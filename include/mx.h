@@ -354,9 +354,10 @@ mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int
  *                certified per point, binary64 recomputation otherwise)
  *   counts[j]  = #{i : labels[i] = j}                      (int64, exact)
  *   C_out[j]   = mean of the points labelled j, or C[j] when count is 0
- * Supported sizes: 1 <= d <= 64, 1 <= k <= 256, k * d <= 4096 (and LDS needs
- * at most 64 KiB, which holds for the configurations used here), else
- * MX_ERR_UNSUPPORTED.  Deterministic: no float atomics.  C_out must not alias
+ * Supported sizes: 1 <= d <= 64, 1 <= k <= 256, k * d <= 4096, else
+ * MX_ERR_UNSUPPORTED.  The step's workgroups need up to 133 KiB of LDS (at
+ * d = 17, k = 240), within the 160 KiB a gfx950 workgroup may use; a device
+ * that allows less rejects the larger shapes with MX_ERR_UNSUPPORTED.  Deterministic: no float atomics.  C_out must not alias
  * C.  Workspace: mx_kmeans_workspace_bytes(n, d, k), zero-filled once. */
 size_t mx_kmeans_workspace_bytes(int64_t n, int d, int k);
 mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *C_dev, int k,

@@ -7,16 +7,20 @@
 //   c'_j = sum_j / count_j, or c_j when count_j = 0
 //
 // Assignment on the matrix cores: argmin_j dist(x, c_j) = argmin_j f_j with
-// f_j = |c_j|^2 - 2 x.c_j, the x.c_j products of 64 points x 64 centroids per
-// wave on v_mfma_f32_16x16x4_f32 (X straight from HBM into registers, C in
-// LDS).  The FP32 values f~_j satisfy |f~_j - f_j| <= E = (d + 8) u (|x| +
-// max_j |c_j|)^2 with u = 2^-24 (d products, two rounded additions per MFMA
-// step of four, the norm and the final subtraction), so when the two smallest
-// f~ differ by more than 2E the smallest is the exact, unique minimiser and
-// also the binary64 oracle's.  Otherwise (about one point in a million on
-// Gaussian blobs) the lane recomputes every distance in binary64 in the
-// oracle's operation order -- subtract, square, add, no fused multiply-add --
-// and takes the lexicographic minimum, so labels are bit-exact in all cases.
+// f_j = |c_j|^2 - 2 x.c_j, 64 points x 64 centroids per wave on
+// v_mfma_f32_16x16x4_f32 (X straight from HBM into registers, -2C in LDS, the
+// accumulators starting at the FP32 |c_j|^2).  The FP32 f~_j carry their
+// candidate's slot in the four low mantissa bits (a change of at most 15 ulp,
+// under 2^-19 |f~_j|).  With u = 2^-24 these values p_j satisfy |p_j - f_j| <=
+// E = (2d + 40) u (|x| + max_j |c_j|)^2: the norm (d roundings on |c_j|^2),
+// the d products and d additions of the accumulation (each term at most
+// (|x| + |c_j|)^2 in total), and 32 u for the slot bits.  When the two
+// smallest p differ by more than 2E the smallest is the exact, unique
+// minimiser and also the binary64 oracle's.  Otherwise (a few points in a
+// million on Gaussian blobs) the lane recomputes every distance in binary64 in
+// the oracle's operation order -- subtract, square, add, no fused
+// multiply-add -- and takes the lexicographic minimum, so labels are
+// bit-exact in all cases.
 //
 // Persistent waves: a fixed grid of at most kMaxBlocks blocks, each wave
 // walking its own sequence of 64-point chunks and loading the next chunk's
@@ -46,28 +50,9 @@ constexpr int kWaves = NT / kWave;
 constexpr int kPtsWave = 64;  // points per wave chunk
 constexpr int kMaxBlocks = 512; // persistent grid (two blocks per CU on 256 CUs)
 constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
+constexpr int kScrFloats = kPtsWave * 4 * 4 + kPtsWave;  // per wave: publication slots, label and rank
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-struct Best {
-    float b1;
-    int i1;
-    float b2;
-};
-
-__device__ __forceinline__ Best merge(Best a, Best b) {
-    // lexicographic (value, index) minimum, and the smallest remaining value
-    const bool take_b = (b.b1 < a.b1) || (b.b1 == a.b1 && b.i1 < a.i1);
-    Best r;
-    if (take_b) {
-        r.b1 = b.b1; r.i1 = b.i1;
-        r.b2 = fminf(a.b1, b.b2);
-    } else {
-        r.b1 = a.b1; r.i1 = a.i1;
-        r.b2 = fminf(b.b1, a.b2);
-    }
-    return r;
-}
 
 // binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
 __device__ __forceinline__ double dist64(const float *__restrict__ x, const float *c, int d) {
@@ -75,6 +60,24 @@ __device__ __forceinline__ double dist64(const float *__restrict__ x, const floa
     for (int t = 0; t < d; ++t) {
         const double diff = sub_rn((double)x[t], (double)c[t]);
         acc = add_rn(acc, mul_rn(diff, diff));
+    }
+    return acc;
+}
+
+// The same over the DP padded dimensions of an LDS row holding -2c (c = -m2 / 2
+// exactly in binary64); past d both rows hold zeros, which add exact zeros.
+template <int DP>
+__device__ __forceinline__ double dist64_m2(const float *x, const float *m2) {
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < DP; t += 4) {
+        const float4 xv = *reinterpret_cast<const float4 *>(x + t);
+        const float4 cv = *reinterpret_cast<const float4 *>(m2 + t);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double diff = sub_rn((double)vget<float4, float>(xv, e), -0.5 * (double)vget<float4, float>(cv, e));
+            acc = add_rn(acc, mul_rn(diff, diff));
+        }
     }
     return acc;
 }
@@ -162,30 +165,36 @@ __device__ __forceinline__ void mask_chunk(float4 (&xa)[4][DP / 32][2], int d, i
 template <int DP, int KP, bool VX>
 __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_fused(KmArgs a) {
     constexpr int LDC = DP + 4;
+    constexpr int LBITS = KP <= 64 ? 6 : KP <= 128 ? 7 : 8;  // bits of a label
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int d = a.d, k = a.k, ldd = sums_ld(d);
     float *Cs = smem;                                  // [KP][LDC]
     float *cnorm = Cs + KP * LDC;                      // [KP]
     float *sums_all = cnorm + KP;                      // [kWaves][k][ldd]
     int *counts_all = (int *)(sums_all + kWaves * k * ldd);  // [kWaves][k]
-    float *scr = (float *)(counts_all + kWaves * k);   // [kWaves][5][64]
+    float *scr = (float *)(counts_all + kWaves * k);   // [kWaves][kScrFloats]
     __shared__ float cmax_s;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, g = lane >> 4;
 
-    // centroids into LDS (zero padded), their squared norms, the largest norm
+    // -2 c into LDS (zero padded; the scaling is exact), |c|^2 (padding
+    // centroids get FLT_MAX, finite so that index packing keeps them
+    // ordered, and never below a real centroid's value), the largest norm
     for (int e = tid; e < KP * LDC; e += NT) {
         const int j = e / LDC, t = e - j * LDC;
-        Cs[e] = (j < k && t < d) ? a.C[(int64_t)j * d + t] : 0.f;
+        Cs[e] = (j < k && t < d) ? -2.0f * a.C[(int64_t)j * d + t] : 0.f;
     }
     for (int e = tid; e < kWaves * k * ldd; e += NT) sums_all[e] = 0.f;
     for (int e = tid; e < kWaves * k; e += NT) counts_all[e] = 0;
-    __syncthreads();
     if (tid < KP) {
         float s = 0.f;
-        for (int t = 0; t < d; ++t) s += Cs[tid * LDC + t] * Cs[tid * LDC + t];
-        cnorm[tid] = tid < k ? s : INFINITY;
+        if (tid < k)
+            for (int t = 0; t < d; ++t) {
+                const float v = a.C[(int64_t)tid * d + t];
+                s += v * v;
+            }
+        cnorm[tid] = tid < k ? s : FLT_MAX;
     }
     __syncthreads();
     if (wave == 0) {
@@ -196,15 +205,12 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     }
     __syncthreads();
     const float cmax = cmax_s;
-    const float eps_factor = 2.0f * (float)(d + 8) * 5.9604645e-8f;  // 2 (d + 8) 2^-24
+    const float eps_factor = 2.0f * (float)(2 * d + 40) * 5.9604645e-8f;  // 2 (2d + 40) 2^-24
 
     float *ws = sums_all + wave * k * ldd;
     int *wc = counts_all + wave * k;
-    float *xnorm = scr + wave * 5 * kPtsWave;
-    float *best1 = xnorm + kPtsWave;
-    float *best2 = best1 + kPtsWave;
-    int *bidx = (int *)(best2 + kPtsWave);
-    int *lab = bidx + kPtsWave;
+    float4 *pub = reinterpret_cast<float4 *>(scr + wave * kScrFloats);  // [64 points][4 lane groups]
+    int *lr = reinterpret_cast<int *>(pub + 4 * kPtsWave);  // [64 points] rank << 16 | label, or -1
 
     const int64_t nchunks = (a.n + kPtsWave - 1) / kPtsWave;
     const int64_t wstride = (int64_t)gridDim.x * kWaves;
@@ -219,7 +225,8 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
         float4 xn[4][DP / 32][2];
         load_chunk<DP, VX>(xn, a, c + wstride < nchunks ? c + wstride : c, l16, g);
 
-        // |x|^2: add the four lane groups g (lanes l16, l16+16, l16+32, l16+48)
+        // this lane's part of |x|^2 (its eight or sixteen dimensions)
+        float xpart[4];
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi) {
             float s = 0.f;
@@ -230,26 +237,28 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                     const float4 u = xa[mi][kc][h];
                     s += u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w;
                 }
-            s += __shfl_xor(s, 16, 64);
-            s += __shfl_xor(s, 32, 64);
-            if (g == 0) xnorm[mi * 16 + l16] = s;
+            xpart[mi] = s;
         }
 
-        // ---- f = |c|^2 - 2 c.x over chunks of 64 centroids.  Centroids are the
-        //      MFMA's A operand and points its B operand, so lane (g, l16) ends
-        //      with rows 4g + r (centroids) of column l16 (point) of each
-        //      (centroid block ci, point block pi): 16 candidates per point in
-        //      one lane, 64 over the four lanes l16 + 16g.
-        Best bt[4];
-#pragma unroll
-        for (int pi = 0; pi < 4; ++pi) bt[pi] = Best{INFINITY, 0x7fffffff, INFINITY};
+        // ---- f = |c|^2 - 2 c.x over chunks of 64 centroids.  The MFMA's A
+        //      operand is -2c (centroid rows), its B operand the points and its
+        //      accumulator starts at |c|^2, so lane (g, l16) ends with f for
+        //      rows 4g + r (centroids) of column l16 (point) of each (centroid
+        //      block ci, point block pi): 16 candidates per point in one lane.
+        //      Each f carries its candidate's slot ci*4 + r in its four low
+        //      mantissa bits, so one minimum gives value and index, and one
+        //      median of three keeps the second smallest value.
+        float r1[4], r2[4];
+        int ri[4];
 #pragma unroll
         for (int cc = 0; cc < KP / 64; ++cc) {
             v4f acc[4][4];  // [ci][pi]
 #pragma unroll
-            for (int ci = 0; ci < 4; ++ci)
+            for (int ci = 0; ci < 4; ++ci) {
+                const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + cc * 64 + ci * 16 + 4 * g);
 #pragma unroll
-                for (int pi = 0; pi < 4; ++pi) acc[ci][pi] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int pi = 0; pi < 4; ++pi) acc[ci][pi] = v4f{c4.x, c4.y, c4.z, c4.w};
+            }
 #pragma unroll
             for (int kc = 0; kc < DP / 32; ++kc) {
                 float4 cb[4][2];
@@ -271,74 +280,78 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                         }
                     }
             }
-            float cn[4][4];
-#pragma unroll
-            for (int ci = 0; ci < 4; ++ci) {
-                const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + cc * 64 + ci * 16 + 4 * g);
-                cn[ci][0] = c4.x; cn[ci][1] = c4.y; cn[ci][2] = c4.z; cn[ci][3] = c4.w;
-            }
 #pragma unroll
             for (int pi = 0; pi < 4; ++pi) {
-                // in-lane scan in increasing centroid index: (value, index) minimum
-                // and the smallest value among the others
                 float b1 = INFINITY, b2 = INFINITY;
-                int i1 = 0x7fffffff;
 #pragma unroll
                 for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float f = cn[ci][r] - 2.0f * acc[ci][pi][r];
-                        const int jj = cc * 64 + ci * 16 + 4 * g + r;
-                        b2 = fminf(b2, fmaxf(b1, f));
-                        i1 = f < b1 ? jj : i1;
-                        b1 = fminf(b1, f);
+                        const float f = __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~15u) |
+                                                        (unsigned)(ci * 4 + r));
+                        // median forms: no canonicalising of the bit-built f
+                        b2 = __builtin_amdgcn_fmed3f(b1, b2, f);
+                        b1 = __builtin_amdgcn_fmed3f(b1, f, -FLT_MAX);
                     }
-                Best b{b1, i1, b2};
-                // merge over the four lanes holding this point
-                b = merge(b, Best{__shfl_xor(b.b1, 16, kWave), __shfl_xor(b.i1, 16, kWave), __shfl_xor(b.b2, 16, kWave)});
-                b = merge(b, Best{__shfl_xor(b.b1, 32, kWave), __shfl_xor(b.i1, 32, kWave), __shfl_xor(b.b2, 32, kWave)});
-                bt[pi] = merge(bt[pi], b);
+                const int slot = (int)(__float_as_uint(b1) & 15u);
+                const int j1 = cc * 64 + (slot >> 2) * 16 + 4 * g + (slot & 3);
+                if (cc == 0) {
+                    r1[pi] = b1; ri[pi] = j1; r2[pi] = b2;
+                } else {  // later centroid chunks have larger indices: ties keep the earlier
+                    r2[pi] = fminf(fmaxf(r1[pi], b1), fminf(r2[pi], b2));
+                    ri[pi] = b1 < r1[pi] ? j1 : ri[pi];
+                    r1[pi] = fminf(r1[pi], b1);
+                }
             }
         }
-        // lanes g == 0 publish their four points
-        if (g == 0) {
+        // every lane publishes (best, index, second, |x|^2 part) per point
 #pragma unroll
-            for (int pi = 0; pi < 4; ++pi) {
-                const int pt = pi * 16 + l16;
-                best1[pt] = bt[pi].b1;
-                best2[pt] = bt[pi].b2;
-                bidx[pt] = bt[pi].i1;
-            }
-        }
+        for (int pi = 0; pi < 4; ++pi)
+            pub[(pi * 16 + l16) * 4 + g] = make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
         wave_sync();
         // ---- certify each label (lane = point); uncertified points are
         //      recomputed in binary64 by the whole wave, lanes over centroids
         {
             const int64_t p = p0 + lane;
+            // merge the four lane groups in index order (lexicographic minimum)
+            float4 q = pub[lane * 4];
+            float m1 = q.x, m2 = q.z, xx = q.w;
+            int mj = __float_as_int(q.y);
+#pragma unroll
+            for (int gg = 1; gg < 4; ++gg) {
+                q = pub[lane * 4 + gg];
+                const int qj = __float_as_int(q.y);
+                const bool take = q.x < m1 || (q.x == m1 && qj < mj);
+                m2 = fminf(fmaxf(m1, q.x), fminf(m2, q.z));
+                mj = take ? qj : mj;
+                m1 = fminf(m1, q.x);
+                xx += q.w;
+            }
             int label = -1;
             bool certified = true;
             if (p < a.n) {
-                const float xn_ = sqrtf(xnorm[lane]) + cmax;
-                const float E = eps_factor * xn_ * xn_;
-                certified = best2[lane] - best1[lane] > 2.0f * E;
-                label = bidx[lane];
+                const float xn_ = sqrtf(xx) + cmax;
+                certified = m2 - m1 > eps_factor * xn_ * xn_;
+                label = mj;
             }
             uint64_t todo = __ballot(!certified);
             if (todo && a.fallbacks && lane == 0) atomicAdd(a.fallbacks, (unsigned long long)__popcll(todo));
-            // the point is staged in this wave's best1 slots (read above): one
-            // coalesced load, then LDS broadcasts for every centroid lane
-            float *xs = best1;
+            // the point is staged in this wave's publication slots (read
+            // above): one coalesced load, then LDS broadcasts for every
+            // centroid lane
+            float *xs = reinterpret_cast<float *>(pub);
             while (todo) {
                 const int q = __builtin_ctzll(todo);  // wave-uniform
                 todo &= todo - 1;
                 wave_sync();
-                if (lane < d) xs[lane] = a.X[(p0 + q) * d + lane];
+                if (lane < DP) xs[lane] = lane < d ? a.X[(p0 + q) * d + lane] : 0.f;
                 wave_sync();
                 const float *x = xs;
                 double bd = INFINITY;
                 int bj = 0x7fffffff;
                 for (int j = lane; j < k; j += kWave) {
-                    const double dj = dist64(x, Cs + j * LDC, d);
+                    // -2c overflows only where |c|^2 does, which makes cmax infinite
+                    const double dj = cmax < INFINITY ? dist64_m2<DP>(x, Cs + j * LDC) : dist64(x, a.C + (int64_t)j * d, d);
                     if (dj < bd || (dj == bd && j < bj)) { bd = dj; bj = j; }
                 }
 #pragma unroll
@@ -350,47 +363,77 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 if (lane == q) label = bj;
             }
             if (p < a.n) a.labels[p] = label;
-            lab[lane] = label;
             if (label >= 0) atomicAdd(&wc[label], 1);  // integer: order-free
+            // rank among the chunk's earlier points with the same label: the
+            // lanes with an equal label, found one label bit at a time
+            uint64_t same = __ballot(label >= 0);
+#pragma unroll
+            for (int b = 0; b < LBITS; ++b) {
+                const bool bit = (label >> b) & 1;
+                const uint64_t mb = __ballot(bit);
+                same &= bit ? mb : ~mb;
+            }
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+            lr[lane] = label >= 0 ? (rank << 16) | label : -1;
         }
         wave_sync();
-        // ---- reduce-by-key from registers: passes by rank among equal labels
+        // ---- reduce-by-key from registers.  Pass m adds every point whose
+        //      rank among equal labels is m, so the lanes of one pass own
+        //      distinct rows and a plain read-add-write is exact (LDS float
+        //      atomics run about one lane per clock); each row receives its
+        //      points in increasing index order.  A pass issues all its reads
+        //      before its writes; lanes with nothing to add in it read and
+        //      write their own slots in the (consumed) publication area.
+        //      Dimensions past d hold zeros in xa, so a 16-byte group that
+        //      ends within round4(d) (inside the row) is added whole; groups
+        //      past it are skipped.
+        {
+            int Lm[4], Rm[4];
+            int rmax = -1;
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-            const int L = lab[mi * 16 + l16];
-            int rank = 0;
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const int4 lq = *reinterpret_cast<const int4 *>(lab + mi * 16 + 4 * q4);
-                rank += (4 * q4 + 0 < l16 && lq.x == L) + (4 * q4 + 1 < l16 && lq.y == L) +
-                        (4 * q4 + 2 < l16 && lq.z == L) + (4 * q4 + 3 < l16 && lq.w == L);
+            for (int mi = 0; mi < 4; ++mi) {
+                const int v = lr[mi * 16 + l16];
+                Lm[mi] = v & 0xffff;
+                Rm[mi] = v >> 16;  // -1 for points past n
+                rmax = max(rmax, Rm[mi]);
             }
-            // within a pass every active lane owns distinct addresses, so a
-            // plain read-add-write is exact (LDS float atomics run about one
-            // lane per clock); 16-byte accesses where all 8 dims exist
-            for (int m = 0; __ballot(L >= 0 && rank >= m); ++m) {
-                if (L >= 0 && rank == m) {
-                    float *dst = ws + L * ldd;
+            const int d4 = (d + 3) & ~3;
+            float4 *junk = pub + lane * 4;
+            for (int m = 0; __ballot(rmax >= m); ++m) {
+                // point blocks with nothing to add in this pass are skipped
+                bool act[4];
 #pragma unroll
-                    for (int kc = 0; kc < DP / 32; ++kc) {
-                        const int t0 = kc * 32 + 8 * g;
-                        if (t0 + 8 <= d) {
-                            float4 *q = reinterpret_cast<float4 *>(dst + t0);
-                            float4 s0 = q[0], s1 = q[1];
-                            const float4 x0 = xa[mi][kc][0], x1 = xa[mi][kc][1];
-                            s0.x += x0.x; s0.y += x0.y; s0.z += x0.z; s0.w += x0.w;
-                            s1.x += x1.x; s1.y += x1.y; s1.z += x1.z; s1.w += x1.w;
-                            q[0] = s0;
-                            q[1] = s1;
-                        } else {
+                for (int mi = 0; mi < 4; ++mi) act[mi] = __ballot(Rm[mi] == m) != 0;
+                float4 *dst[4][DP / 32][2];
+                float4 sm[4][DP / 32][2];
 #pragma unroll
-                            for (int h = 0; h < 2; ++h)
+                for (int mi = 0; mi < 4; ++mi)
+                    if (act[mi]) {
 #pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    if (t0 + 4 * h + e < d) dst[t0 + 4 * h + e] += vget<float4, float>(xa[mi][kc][h], e);
-                        }
+                        for (int kc = 0; kc < DP / 32; ++kc)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int t = kc * 32 + 8 * g + 4 * h;
+                                const bool live = Rm[mi] == m && (VX || t + 4 <= d4);
+                                dst[mi][kc][h] = live ? reinterpret_cast<float4 *>(ws + Lm[mi] * ldd + t)
+                                                      : junk + kc * 2 + h;
+                                sm[mi][kc][h] = *dst[mi][kc][h];
+                            }
                     }
-                }
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+                    if (act[mi]) {
+#pragma unroll
+                        for (int kc = 0; kc < DP / 32; ++kc)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                float4 v = sm[mi][kc][h];
+                                const float4 x = xa[mi][kc][h];
+                                v.x += x.x; v.y += x.y; v.z += x.z; v.w += x.w;
+                                *dst[mi][kc][h] = v;
+                            }
+                    }
             }
         }
         wave_sync();
@@ -611,7 +654,7 @@ int64_t fused_blocks(int64_t n) {
 
 size_t fused_lds_bytes(int DP, int KP, int k, int d) {
     return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * sums_ld(d) * 4 + (size_t)kWaves * k * 4 +
-           (size_t)kWaves * kPtsWave * 4 * 5;
+           (size_t)kWaves * kScrFloats * 4;
 }
 
 size_t ws_layout(int64_t n, int d, int k, size_t *sums_off, size_t *counts_off, size_t *plain_off) {
@@ -676,13 +719,13 @@ mx_status mx_kmeans_step_f32(const float *X_dev, int64_t n, int d, const float *
     const int DP = d <= 32 ? 32 : 64;
     const int KP = (int)ceil_div(k, 64) * 64;
     const size_t lds = fused_lds_bytes(DP, KP, k, d);
-    MX_REQUIRE(lds <= 65536, MX_ERR_UNSUPPORTED, "%s: k = %d, d = %d needs %zu bytes of LDS (limit 65536)", who, k,
-               d, lds);
+    const DeviceInfo *dv;
+    if (mx_status st = device_info(&dv)) return st;
+    MX_REQUIRE(lds <= (size_t)dv->lds_bytes, MX_ERR_UNSUPPORTED,
+               "%s: k = %d, d = %d needs %zu bytes of LDS (the device allows %d)", who, k, d, lds, dv->lds_bytes);
     KmArgs a{X_dev, n, d, k, C_dev, labels_dev, (float *)((char *)ws + so), (int *)((char *)ws + co), nullptr};
     const bool dbg = debug_mode();
     if (dbg) {
-        const DeviceInfo *dv;
-        if (mx_status st = device_info(&dv)) return st;
         if (!g_fb_counter[dv->device]) MX_TRY_HIP(hipMalloc(&g_fb_counter[dv->device], sizeof(unsigned long long)));
         MX_TRY_HIP(hipMemsetAsync(g_fb_counter[dv->device], 0, sizeof(unsigned long long), stream));
         a.fallbacks = g_fb_counter[dv->device];

@@ -73,7 +73,8 @@ def test_kmeans_ten_iterations_lockstep(plain):
 
 
 @pytest.mark.parametrize("n,d,k", [(1, 32, 64), (1000, 32, 64), (4097, 5, 3), (3001, 64, 32), (2500, 16, 100),
-                                   (5000, 8, 192), (777, 1, 1)])
+                                   (5000, 8, 192), (777, 1, 1),
+                                   (2000, 17, 240), (1500, 64, 64), (3000, 16, 256)])
 def test_kmeans_shapes(n, d, k):
     say("kmeans shape", n, d, k)
     X, _, _ = W.kmeans_blobs(n, d, max(k // 2, 1), seed=n + d)
@@ -165,6 +166,10 @@ def test_kmeans_unsupported_sizes():
         api.kmeans_step(X, torch.zeros((4, 65), device=DEV))
     assert e.value.status == abi.MX_ERR_UNSUPPORTED
     X = torch.zeros((10, 64), device=DEV)
-    with pytest.raises(abi.MxError) as e:  # k * d = 4096 at d = 64: LDS beyond 64 KiB
-        api.kmeans_step(X, torch.zeros((64, 64), device=DEV))
+    with pytest.raises(abi.MxError) as e:  # k * d = 4160 > 4096
+        api.kmeans_step(X, torch.zeros((65, 64), device=DEV))
+    assert e.value.status == abi.MX_ERR_UNSUPPORTED
+    X = torch.zeros((10, 1), device=DEV)
+    with pytest.raises(abi.MxError) as e:  # k > 256
+        api.kmeans_step(X, torch.zeros((257, 1), device=DEV))
     assert e.value.status == abi.MX_ERR_UNSUPPORTED
