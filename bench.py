@@ -48,8 +48,8 @@ TRAFFIC = {
     # k_gemm_mfma<128,128,4,2,0,0>, 2048^3: 100.78 MB fetched (A and B panels re-read by each XCD that
     # needs them, plus two clamped slices past the end of K per tile; 33.6 MB is the algorithmic
     # minimum) + 16.78 MB written (C)
-    "gemm_nn": {"file": "gemm.hip", "bytes": 117551367,
-                "source": "ddb0e9c7225bc12b5978382d0c83487c2adf95ad157739008d76eb72203293e6"},
+    "gemm_nn": {"file": "gemm.hip", "bytes": 117551940,
+                "source": "e3de6e32d73e713b7af21202564fbc60d4736cd93458aa1021a82736a18a937c"},
     # k_seg_span, 65536 rows / 32.1 M values: 130.46 MB fetched + 0.26 MB written (1.01x algorithmic)
     "seg_span": {"file": "segmented.hip", "bytes": 130721777,
                  "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},

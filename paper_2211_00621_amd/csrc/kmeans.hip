@@ -401,7 +401,8 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             const int d4 = (d + 3) & ~3;
             float4 *junk = pub + lane * 4;
             for (int m = 0; __ballot(rmax >= m); ++m) {
-                // point blocks with nothing to add in this pass are skipped
+                // point blocks with nothing to add in this pass read one
+                // broadcast slot and write nothing
                 bool act[4];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi) act[mi] = __ballot(Rm[mi] == m) != 0;
@@ -409,18 +410,16 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 float4 sm[4][DP / 32][2];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
-                    if (act[mi]) {
 #pragma unroll
-                        for (int kc = 0; kc < DP / 32; ++kc)
+                    for (int kc = 0; kc < DP / 32; ++kc)
 #pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                const int t = kc * 32 + 8 * g + 4 * h;
-                                const bool live = Rm[mi] == m && (VX || t + 4 <= d4);
-                                dst[mi][kc][h] = live ? reinterpret_cast<float4 *>(ws + Lm[mi] * ldd + t)
-                                                      : junk + kc * 2 + h;
-                                sm[mi][kc][h] = *dst[mi][kc][h];
-                            }
-                    }
+                        for (int h = 0; h < 2; ++h) {
+                            const int t = kc * 32 + 8 * g + 4 * h;
+                            const bool live = Rm[mi] == m && (VX || t + 4 <= d4);
+                            dst[mi][kc][h] = live ? reinterpret_cast<float4 *>(ws + Lm[mi] * ldd + t)
+                                                  : junk + kc * 2 + h;
+                            sm[mi][kc][h] = *(act[mi] ? dst[mi][kc][h] : pub);
+                        }
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi)
                     if (act[mi]) {
