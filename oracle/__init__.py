@@ -27,6 +27,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 ADD, MUL, MIN, MAX = 0, 1, 2, 3
 U_ID, U_NEG, U_ABS, U_SQ, U_AFFINE, U_EXP, U_LOG, U_SQRT, U_RSQRT = range(9)
 B_ADD, B_SUB, B_MUL, B_DIV, B_MIN, B_MAX = range(6)
+(X_IN, X_CONST, X_ADD, X_SUB, X_MUL, X_DIV, X_MIN, X_MAX, X_NEG, X_ABS, X_SQ, X_EXP, X_LOG, X_SQRT,
+ X_RSQRT) = range(15)
 
 
 def build(force: bool = False) -> str:
@@ -85,6 +87,9 @@ def _declare(lib):
         "or_kmeans_sse_grad": (None, [_p, _i64, _i64, _p, _p, _d, _p]),
         "or_batch_forward": (None, [_p, _i64, _p, _p, _p]),
         "or_batch_backward": (None, [_p, _i64, _p, _p, _p, _p, _p]),
+        "or_expr_map_f64": (None, [_p, _p, _int, _int, _p, _i64, _p]),
+        "or_expr_map_foldl_f64": (_d, [_int, _d, _p, _p, _int, _int, _p, _i64]),
+        "or_expr_vjp_f64": (None, [_p, _p, _int, _int, _int, _p, _i64, _p, _p, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -395,3 +400,45 @@ def batch_backward(table, A, B, gout):
     gB = np.zeros_like(b)
     _L().or_batch_backward(_ptr(tb), tb.shape[0], _ptr(a), _ptr(b), _ptr(g), _ptr(gA), _ptr(gB))
     return gA, gB
+
+
+# ---------------------------------------------------------------- user-defined map bodies
+def _prog(prog):
+    """prog: sequence of (op, dst, a, b, imm) -> int32 code [ninsn x 4], float64 imm [ninsn]."""
+    code = np.ascontiguousarray(np.array([[int(p[0]), int(p[1]), int(p[2]), int(p[3])] for p in prog],
+                                         dtype=np.int32).reshape(-1, 4))
+    imm = np.ascontiguousarray(np.array([float(p[4]) for p in prog], dtype=np.float64))
+    return code, imm
+
+
+def _inputs(inputs):
+    X = np.ascontiguousarray(np.stack([_f64(x).ravel() for x in inputs]))
+    return X, X.shape[1]
+
+
+def expr_map(prog, out_reg: int, *inputs) -> np.ndarray:
+    """map of the straight-line body `prog` over the inputs (binary64)."""
+    code, imm = _prog(prog)
+    X, n = _inputs(inputs)
+    out = np.zeros(n, dtype=np.float64)
+    _L().or_expr_map_f64(_ptr(code), _ptr(imm), code.shape[0], out_reg, _ptr(X), n, _ptr(out))
+    return out
+
+
+def expr_map_reduce(op: int, ne, prog, out_reg: int, *inputs) -> float:
+    """foldl op ne (map body inputs) (binary64)."""
+    code, imm = _prog(prog)
+    X, n = _inputs(inputs)
+    return _L().or_expr_map_foldl_f64(op, float(ne), _ptr(code), _ptr(imm), code.shape[0], out_reg, _ptr(X), n)
+
+
+def expr_vjp(prog, out_reg: int, inputs, gout=None, gscale=None):
+    """Per-element reverse mode of the body: list of d body / d input_k times the seed."""
+    code, imm = _prog(prog)
+    X, n = _inputs(inputs)
+    G = np.zeros_like(X)
+    g = _f64(gout).ravel() if gout is not None else None
+    s = np.array([float(gscale)], dtype=np.float64) if gscale is not None else None
+    _L().or_expr_vjp_f64(_ptr(code), _ptr(imm), code.shape[0], X.shape[0], out_reg, _ptr(X), n,
+                         _ptr(g) if g is not None else None, _ptr(s) if s is not None else None, _ptr(G))
+    return [G[k] for k in range(X.shape[0])]

@@ -550,3 +550,141 @@ void or_batch_backward(const int64_t *table, int64_t ntasks, const double *A, co
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* User-defined map bodies.  The source language's map and map2 take any    */
+/* first-order function built from the language's arithmetic (Appendix A;   */
+/* Section 4.2).  A body is a straight-line program over registers          */
+/* r0..r15: each instruction (op, dst, a, b, imm) writes r[dst].  The       */
+/* interpreter runs it once per element, in binary64.                       */
+/* ------------------------------------------------------------------------ */
+enum { OR_X_IN = 0, OR_X_CONST = 1, OR_X_ADD = 2, OR_X_SUB = 3, OR_X_MUL = 4, OR_X_DIV = 5,
+       OR_X_MIN = 6, OR_X_MAX = 7, OR_X_NEG = 8, OR_X_ABS = 9, OR_X_SQ = 10, OR_X_EXP = 11,
+       OR_X_LOG = 12, OR_X_SQRT = 13, OR_X_RSQRT = 14 };
+#define OR_X_REGS 16
+#define OR_X_MAXINSN 64
+
+/* one instruction on values already read from the registers */
+static double x_apply(int op, double va, double vb, double imm, double in)
+{
+    switch (op) {
+    case OR_X_IN: return in;
+    case OR_X_CONST: return imm;
+    case OR_X_ADD: return va + vb;
+    case OR_X_SUB: return va - vb;
+    case OR_X_MUL: return va * vb;
+    case OR_X_DIV: return va / vb;
+    case OR_X_MIN: return vb < va ? vb : va;
+    case OR_X_MAX: return vb > va ? vb : va;
+    case OR_X_NEG: return -va;
+    case OR_X_ABS: return va < 0.0 ? -va : va;
+    case OR_X_SQ: return va * va;
+    case OR_X_EXP: return exp(va);
+    case OR_X_LOG: return log(va);
+    case OR_X_SQRT: return sqrt(va);
+    case OR_X_RSQRT: return 1.0 / sqrt(va);
+    }
+    return NAN;
+}
+
+/* Evaluates the body at element i of the inputs X[k*n + i] (k < nin); the
+ * value of every instruction goes to val[] (indexed by instruction), and the
+ * instruction that produced each operand to src_a[] / src_b[]. */
+static double x_eval(const int32_t *code, const double *imm, int ninsn, int out_reg, const double *X,
+                     int64_t n, int64_t i, double *val, int *src_a, int *src_b, int *out_src)
+{
+    double r[OR_X_REGS];
+    int last[OR_X_REGS];
+    for (int q = 0; q < OR_X_REGS; ++q) { r[q] = 0.0; last[q] = -1; }
+    for (int k = 0; k < ninsn; ++k) {
+        const int op = code[4 * k], dst = code[4 * k + 1], a = code[4 * k + 2], b = code[4 * k + 3];
+        const int reads_a = op >= OR_X_ADD, reads_b = op >= OR_X_ADD && op <= OR_X_MAX;
+        const double va = reads_a ? r[a] : 0.0, vb = reads_b ? r[b] : 0.0;
+        const double in = op == OR_X_IN ? X[(int64_t)a * n + i] : 0.0;
+        src_a[k] = reads_a ? last[a] : -1;
+        src_b[k] = reads_b ? last[b] : -1;
+        val[k] = x_apply(op, va, vb, imm[k], in);
+        r[dst] = val[k];
+        last[dst] = k;
+    }
+    *out_src = last[out_reg];
+    return r[out_reg];
+}
+
+void or_expr_map_f64(const int32_t *code, const double *imm, int ninsn, int out_reg, const double *X, int64_t n,
+                     double *out)
+{
+    double val[OR_X_MAXINSN];
+    int sa[OR_X_MAXINSN], sb[OR_X_MAXINSN], os;
+    for (int64_t i = 0; i < n; ++i) out[i] = x_eval(code, imm, ninsn, out_reg, X, n, i, val, sa, sb, &os);
+}
+
+/* reduce op ne (map body s): the sequential left fold of the body's values */
+double or_expr_map_foldl_f64(int op, double ne, const int32_t *code, const double *imm, int ninsn, int out_reg,
+                             const double *X, int64_t n)
+{
+    double val[OR_X_MAXINSN];
+    int sa[OR_X_MAXINSN], sb[OR_X_MAXINSN], os;
+    double acc = ne;
+    for (int64_t i = 0; i < n; ++i)
+        acc = red_f64(op, acc, x_eval(code, imm, ninsn, out_reg, X, n, i, val, sa, sb, &os));
+    return acc;
+}
+
+/* Reverse mode of the body at every element: G[k*n + i] = s_i * d body / d
+ * input k, with s_i = (gout ? gout[i] : 1) * (gscale ? *gscale : 1).  Adjoints
+ * flow from the output back through the instructions in reverse order; an
+ * operand receives the chain-rule term of the instruction that read it,
+ * terms added in that reverse order.  min / max pass the adjoint to the
+ * operand they returned, abs to x with the sign of the branch taken.
+ * Instructions the output does not depend on pass nothing. */
+void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin, int out_reg, const double *X,
+                     int64_t n, const double *gout, const double *gscale, double *G)
+{
+    double val[OR_X_MAXINSN], adj[OR_X_MAXINSN];
+    int sa[OR_X_MAXINSN], sb[OR_X_MAXINSN], reached[OR_X_MAXINSN], os;
+    for (int64_t i = 0; i < n; ++i) {
+        x_eval(code, imm, ninsn, out_reg, X, n, i, val, sa, sb, &os);
+        for (int k = 0; k < ninsn; ++k) { adj[k] = 0.0; reached[k] = 0; }
+        double seed = gout ? gout[i] : 1.0;
+        if (gscale) seed = gout ? seed * gscale[0] : gscale[0];
+        double gin[4] = {0.0, 0.0, 0.0, 0.0};
+        int gin_set[4] = {0, 0, 0, 0};
+        if (os >= 0) { adj[os] = seed; reached[os] = 1; }
+        for (int k = ninsn - 1; k >= 0; --k) {
+            if (!reached[k]) continue;
+            const int op = code[4 * k];
+            const double g = adj[k], vk = val[k];
+            const int ja = sa[k], jb = sb[k];
+            const double va = ja >= 0 ? val[ja] : 0.0, vb = jb >= 0 ? val[jb] : 0.0;
+            double ca = 0.0, cb = 0.0;  /* terms for operands a and b */
+            int ta = 0, tb = 0;         /* which operands receive a term */
+            switch (op) {
+            case OR_X_IN: {
+                const int a = code[4 * k + 2];
+                gin[a] = gin_set[a] ? gin[a] + g : g;
+                gin_set[a] = 1;
+                break;
+            }
+            case OR_X_CONST: break;
+            case OR_X_ADD: ca = g; cb = g; ta = tb = 1; break;
+            case OR_X_SUB: ca = g; cb = -g; ta = tb = 1; break;
+            case OR_X_MUL: ca = g * vb; cb = g * va; ta = tb = 1; break;
+            case OR_X_DIV: ca = g / vb; cb = -(g * vk / vb); ta = tb = 1; break;
+            case OR_X_MIN: if (vb < va) { cb = g; tb = 1; } else { ca = g; ta = 1; } break;
+            case OR_X_MAX: if (vb > va) { cb = g; tb = 1; } else { ca = g; ta = 1; } break;
+            case OR_X_NEG: ca = -g; ta = 1; break;
+            case OR_X_ABS: ca = va < 0.0 ? -g : g; ta = 1; break;
+            case OR_X_SQ: ca = g * (va + va); ta = 1; break;
+            case OR_X_EXP: ca = g * vk; ta = 1; break;
+            case OR_X_LOG: ca = g / va; ta = 1; break;
+            case OR_X_SQRT: ca = g / (vk + vk); ta = 1; break;
+            case OR_X_RSQRT: ca = -(g * vk * vk * vk) * 0.5; ta = 1; break;
+            }
+            /* operand a's term first, then b's (a MUL of a value by itself adds both) */
+            if (ta && ja >= 0) { adj[ja] = reached[ja] ? adj[ja] + ca : ca; reached[ja] = 1; }
+            if (tb && jb >= 0) { adj[jb] = reached[jb] ? adj[jb] + cb : cb; reached[jb] = 1; }
+        }
+        for (int a = 0; a < nin; ++a) G[(int64_t)a * n + i] = gin[a];
+    }
+}
