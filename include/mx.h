@@ -452,6 +452,80 @@ mx_status mx_batch_autotune(mx_batch_plan *plan, const float *A_dev, const float
                             const char *cache_path, hipStream_t stream, mx_batch_config *chosen);
 
 /* ======================================================================= */
+/* User-defined map bodies                                                   */
+/* ======================================================================= */
+/* The source language's map and map2 take any first-order function built
+ * from its arithmetic (Appendix A; the compilable subset of Section 4.2),
+ * not only the fixed bodies above.  A body here is a straight-line program
+ * over registers r0..r15 of the element type, one instruction
+ *   { op, dst, a, b, imm }   writing r[dst]:
+ *   MX_X_IN      r[dst] = element i of input array a        (0 <= a < nin)
+ *   MX_X_CONST   r[dst] = imm, rounded to the element type
+ *   MX_X_ADD .. MX_X_MAX       r[dst] = r[a] op r[b]
+ *                (MIN: r[b] < r[a] ? r[b] : r[a]; MAX likewise with >)
+ *   MX_X_NEG .. MX_X_RSQRT     r[dst] = f(r[a])
+ *                (NEG -x; ABS x < 0 ? -x : x; SQ x*x; RSQRT 1/sqrt(x))
+ * Every operation is rounded on its own (no fused multiply-add), as in the
+ * map bodies above.  The body's value is r[out_reg] after the last
+ * instruction.
+ *
+ * mx_expr_create checks the program (1..64 instructions, registers read only
+ * after being written, out_reg written, 1 <= nin <= 4, dtype MX_F32 or
+ * MX_F64; else MX_ERR_INVALID / MX_ERR_DTYPE) and generates HIP source in
+ * which the body is inlined code: a map kernel, a fused map + reduce (one
+ * partial pass over a grid that depends only on n, a finish kernel in block
+ * order: deterministic), and the reverse mode.  The source is compiled with
+ * hipRTC for the current device's architecture on first use and cached for
+ * the life of the process (per source text and device), so a chain of
+ * operations costs one pass over HBM.  The handle owns host memory only;
+ * compiled modules stay loaded until the process ends.  Input and output
+ * arrays are device arrays of n elements of the program's dtype; outputs
+ * must not overlap inputs. */
+typedef enum {
+    MX_X_IN = 0, MX_X_CONST = 1,
+    MX_X_ADD = 2, MX_X_SUB = 3, MX_X_MUL = 4, MX_X_DIV = 5, MX_X_MIN = 6, MX_X_MAX = 7,
+    MX_X_NEG = 8, MX_X_ABS = 9, MX_X_SQ = 10, MX_X_EXP = 11, MX_X_LOG = 12, MX_X_SQRT = 13, MX_X_RSQRT = 14
+} mx_xop;
+typedef struct {
+    int32_t op, dst, a, b;
+    double imm;
+} mx_xinsn;
+typedef struct mx_expr mx_expr;
+
+mx_status mx_expr_create(const mx_xinsn *prog, int ninsn, int nin, int out_reg, mx_dtype dtype, mx_expr **out);
+mx_status mx_expr_destroy(mx_expr *e);
+/* Compiles the kernels for the current device now (otherwise the first call
+ * that needs them does), so that later calls only launch; call it before
+ * capturing the expression's launches into a graph. */
+mx_status mx_expr_prepare(mx_expr *e);
+/* The generated HIP source (owned by the handle; valid until it is destroyed). */
+const char *mx_expr_source(const mx_expr *e);
+
+/* out[i] = body(in[0][i], .., in[nin-1][i]).  in_dev: host array of nin
+ * device pointers. */
+mx_status mx_expr_map(mx_expr *e, const void *const *in_dev, int64_t n, void *out_dev, hipStream_t stream);
+
+/* *out_dev = ne op body(x_0) op body(x_1) ... (reduce of the map, fused; ne
+ * from host memory, of the element type).  n = 0 gives ne.  Workspace:
+ * mx_expr_workspace_bytes(e, n), 256-byte aligned. */
+size_t mx_expr_workspace_bytes(const mx_expr *e, int64_t n);
+mx_status mx_expr_map_reduce(mx_expr *e, mx_redop op, const void *const *in_dev, int64_t n, const void *ne_host,
+                             void *out_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Reverse mode: gin[k][i] = s_i * d body / d input k at element i, with
+ * s_i = (gout ? gout[i] : 1) * (gscale ? *gscale : 1) (gout a device array of
+ * n, gscale a device scalar; either may be NULL).  The adjoint flows back
+ * through the instructions in reverse order; min / max pass it to the
+ * operand they returned and a zero term to the other, abs to x with the sign
+ * of the branch taken;
+ * instructions the output does not depend on pass nothing.  gin_dev: host
+ * array of nin device pointers, NULL entries skipped.  With gout = NULL and
+ * gscale the upstream gradient of a map + reduce (+) this is that reduce's
+ * adjoint. */
+mx_status mx_expr_vjp(mx_expr *e, const void *const *in_dev, int64_t n, const void *gout_dev,
+                      const void *gscale_dev, void *const *gin_dev, hipStream_t stream);
+
+/* ======================================================================= */
 /* HIP graphs of launch sequences (loop bodies, forward + backward passes)  */
 /* ======================================================================= */
 /* Any sequence of this library's launches on one stream can be captured once

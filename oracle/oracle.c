@@ -636,8 +636,9 @@ double or_expr_map_foldl_f64(int op, double ne, const int32_t *code, const doubl
  * flow from the output back through the instructions in reverse order; an
  * operand receives the chain-rule term of the instruction that read it,
  * terms added in that reverse order.  min / max pass the adjoint to the
- * operand they returned, abs to x with the sign of the branch taken.
- * Instructions the output does not depend on pass nothing. */
+ * operand they returned and a zero term to the other (which operands take
+ * part does not depend on the data), abs to x with the sign of the branch
+ * taken.  Instructions the output does not depend on pass nothing. */
 void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin, int out_reg, const double *X,
                      int64_t n, const double *gout, const double *gscale, double *G)
 {
@@ -671,8 +672,8 @@ void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin,
             case OR_X_SUB: ca = g; cb = -g; ta = tb = 1; break;
             case OR_X_MUL: ca = g * vb; cb = g * va; ta = tb = 1; break;
             case OR_X_DIV: ca = g / vb; cb = -(g * vk / vb); ta = tb = 1; break;
-            case OR_X_MIN: if (vb < va) { cb = g; tb = 1; } else { ca = g; ta = 1; } break;
-            case OR_X_MAX: if (vb > va) { cb = g; tb = 1; } else { ca = g; ta = 1; } break;
+            case OR_X_MIN: ca = vb < va ? 0.0 : g; cb = vb < va ? g : 0.0; ta = tb = 1; break;
+            case OR_X_MAX: ca = vb > va ? 0.0 : g; cb = vb > va ? g : 0.0; ta = tb = 1; break;
             case OR_X_NEG: ca = -g; ta = 1; break;
             case OR_X_ABS: ca = va < 0.0 ? -g : g; ta = 1; break;
             case OR_X_SQ: ca = g * (va + va); ta = 1; break;

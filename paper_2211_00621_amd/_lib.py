@@ -72,6 +72,14 @@ SIGNATURES = {
     "mx_batch_forward_plain": (c_status, [c_p, c_p, c_p, c_p, c_p]),
     "mx_batch_backward_plain": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "mx_batch_autotune": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_size, ctypes.c_char_p, c_p, c_p]),
+    "mx_expr_create": (c_status, [c_p, c_int, c_int, c_int, c_enum, c_pp]),
+    "mx_expr_destroy": (c_status, [c_p]),
+    "mx_expr_prepare": (c_status, [c_p]),
+    "mx_expr_source": (ctypes.c_char_p, [c_p]),
+    "mx_expr_map": (c_status, [c_p, c_pp, c_i64, c_p, c_p]),
+    "mx_expr_workspace_bytes": (c_size, [c_p, c_i64]),
+    "mx_expr_map_reduce": (c_status, [c_p, c_enum, c_pp, c_i64, c_p, c_p, c_p, c_size, c_p]),
+    "mx_expr_vjp": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_pp, c_p]),
     "mx_graph_begin": (c_status, [c_p]),
     "mx_graph_end": (c_status, [c_p, c_pp]),
     "mx_graph_launch": (c_status, [c_p, c_p]),

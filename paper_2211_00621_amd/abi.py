@@ -23,6 +23,8 @@ MX_ADD, MX_MUL, MX_MIN, MX_MAX = 0, 1, 2, 3
  MX_U_RSQRT) = range(9)
 MX_B_ADD, MX_B_SUB, MX_B_MUL, MX_B_DIV, MX_B_MIN, MX_B_MAX = range(6)
 MX_WS_REDUCE, MX_WS_SCAN = 0, 1
+(MX_X_IN, MX_X_CONST, MX_X_ADD, MX_X_SUB, MX_X_MUL, MX_X_DIV, MX_X_MIN, MX_X_MAX, MX_X_NEG, MX_X_ABS, MX_X_SQ,
+ MX_X_EXP, MX_X_LOG, MX_X_SQRT, MX_X_RSQRT) = range(15)
 
 DTYPE_OF = {torch.float32: MX_F32, torch.float64: MX_F64, torch.int32: MX_I32, torch.int64: MX_I64}
 ACC_OF = {torch.float32: torch.float32, torch.float64: torch.float64, torch.int32: torch.int64,
@@ -426,6 +428,78 @@ def mx_batch_autotune(plan: BatchPlan, A, B, out, gout, gA, gB, ws, cache_path: 
 
 
 # ---------------------------------------------------------------- graphs
+# ---------------------------------------------------------------- user-defined map bodies
+class XInsn(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("dst", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("imm", ctypes.c_double)]
+
+
+class Expr:
+    """Owning handle of an mx_expr (destroyed with the object)."""
+
+    def __init__(self, handle: int, nin: int, dtype: int):
+        self.handle, self.nin, self.dtype = handle, nin, dtype
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                _L().mx_expr_destroy(self.handle)
+            except Exception:  # interpreter shutdown: the library may already be gone
+                pass
+            self.handle = None
+
+
+def _ptr_list(ts):
+    arr = (ctypes.c_void_p * max(1, len(ts)))()
+    for i, t in enumerate(ts):
+        arr[i] = _dptr(t)
+    return arr
+
+
+def mx_expr_create(prog, nin: int, out_reg: int, dtype: int) -> Expr:
+    """prog: sequence of (op, dst, a, b, imm)."""
+    ins = (XInsn * max(1, len(prog)))()
+    for i, (op, dst, a, b, imm) in enumerate(prog):
+        ins[i] = XInsn(int(op), int(dst), int(a), int(b), float(imm))
+    h = ctypes.c_void_p()
+    _check(_L().mx_expr_create(ins, len(prog), int(nin), int(out_reg), int(dtype), ctypes.byref(h)),
+           "mx_expr_create")
+    return Expr(h.value, nin, dtype)
+
+
+def mx_expr_destroy(e: Expr) -> None:
+    if e.handle:
+        _check(_L().mx_expr_destroy(e.handle), "mx_expr_destroy")
+        e.handle = None
+
+
+def mx_expr_prepare(e: Expr) -> None:
+    _check(_L().mx_expr_prepare(e.handle), "mx_expr_prepare")
+
+
+def mx_expr_source(e: Expr) -> str:
+    return _L().mx_expr_source(e.handle).decode()
+
+
+def mx_expr_map(e: Expr, inputs, out, stream=None) -> None:
+    _check(_L().mx_expr_map(e.handle, _ptr_list(inputs), out.numel(), _dptr(out), _stream(stream)), "mx_expr_map")
+
+
+def mx_expr_workspace_bytes(e: Expr, n: int) -> int:
+    return int(_L().mx_expr_workspace_bytes(e.handle, int(n)))
+
+
+def mx_expr_map_reduce(e: Expr, op: int, inputs, n: int, ne, out, ws, stream=None) -> None:
+    nb = ctypes.c_float(ne) if e.dtype == MX_F32 else ctypes.c_double(ne)
+    _check(_L().mx_expr_map_reduce(e.handle, int(op), _ptr_list(inputs), int(n), ctypes.byref(nb), _dptr(out),
+                                   _dptr(ws), _nbytes(ws), _stream(stream)), "mx_expr_map_reduce")
+
+
+def mx_expr_vjp(e: Expr, inputs, n: int, gout, gscale, grads, stream=None) -> None:
+    _check(_L().mx_expr_vjp(e.handle, _ptr_list(inputs), int(n), _dptr(gout), _dptr(gscale), _ptr_list(grads),
+                            _stream(stream)), "mx_expr_vjp")
+
+
 class Graph:
     """An instantiated capture of library launches (opaque mx_graph handle)."""
 

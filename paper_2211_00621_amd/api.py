@@ -361,3 +361,148 @@ class Batch:
 
     def autotune(self, A, B, out, gout, gA, gB, cache_path=None, stream=None):
         return abi.mx_batch_autotune(self.plan, A, B, out, gout, gA, gB, self.ws, cache_path, stream)
+
+
+# ---------------------------------------------------------------- user-defined map bodies
+class Var:
+    """A value of a map body under construction: the body is written with the
+    usual operators on the results of ``body_inputs`` and lowered to the C
+    ABI's straight-line register program by ``Body``."""
+
+    def __init__(self, op: int, args=(), imm: float = 0.0, index: int = 0):
+        self.op, self.args, self.imm, self.index = op, tuple(args), float(imm), index
+
+    @staticmethod
+    def of(x) -> "Var":
+        return x if isinstance(x, Var) else Var(abi.MX_X_CONST, imm=float(x))
+
+    def _bin(self, op, other, swap=False):
+        a, b = (Var.of(other), self) if swap else (self, Var.of(other))
+        return Var(op, (a, b))
+
+    def __add__(self, o): return self._bin(abi.MX_X_ADD, o)
+    def __radd__(self, o): return self._bin(abi.MX_X_ADD, o, True)
+    def __sub__(self, o): return self._bin(abi.MX_X_SUB, o)
+    def __rsub__(self, o): return self._bin(abi.MX_X_SUB, o, True)
+    def __mul__(self, o): return self._bin(abi.MX_X_MUL, o)
+    def __rmul__(self, o): return self._bin(abi.MX_X_MUL, o, True)
+    def __truediv__(self, o): return self._bin(abi.MX_X_DIV, o)
+    def __rtruediv__(self, o): return self._bin(abi.MX_X_DIV, o, True)
+    def __neg__(self): return Var(abi.MX_X_NEG, (self,))
+    def __abs__(self): return Var(abi.MX_X_ABS, (self,))
+
+    def __pow__(self, p):
+        if p != 2:
+            raise ValueError("only x ** 2 is a body operation")
+        return Var(abi.MX_X_SQ, (self,))
+
+
+def body_inputs(n: int):
+    return tuple(Var(abi.MX_X_IN, index=k) for k in range(n))
+
+
+def exp(x): return Var(abi.MX_X_EXP, (Var.of(x),))
+def log(x): return Var(abi.MX_X_LOG, (Var.of(x),))
+def sqrt(x): return Var(abi.MX_X_SQRT, (Var.of(x),))
+def rsqrt(x): return Var(abi.MX_X_RSQRT, (Var.of(x),))
+def minimum(a, b): return Var(abi.MX_X_MIN, (Var.of(a), Var.of(b)))
+def maximum(a, b): return Var(abi.MX_X_MAX, (Var.of(a), Var.of(b)))
+
+
+def lower_body(out: Var, nregs: int = 16):
+    """Straight-line program (op, dst, a, b, imm) and output register for the
+    expression `out`: nodes in post order (shared nodes once), a register
+    freed after the last read of its value."""
+    order, seen = [], {}
+
+    def visit(v):
+        if id(v) in seen:
+            return
+        for a in v.args:
+            visit(a)
+        seen[id(v)] = len(order)
+        order.append(v)
+
+    visit(out)
+    last_use = {}
+    for pos, v in enumerate(order):
+        for a in v.args:
+            last_use[id(a)] = pos
+    free, reg, prog = list(range(nregs - 1, -1, -1)), {}, []
+    for pos, v in enumerate(order):
+        srcs = [reg[id(a)] for a in v.args]
+        # operands read for the last time give their registers back (the
+        # instruction reads them before it writes its result)
+        for a in {id(a): a for a in v.args}.values():
+            if last_use.get(id(a)) == pos and id(a) != id(out):
+                free.append(reg[id(a)])
+        if not free:
+            raise ValueError(f"the body needs more than {nregs} live values")
+        dst = free.pop()
+        reg[id(v)] = dst
+        a = srcs[0] if srcs else (v.index if v.op == abi.MX_X_IN else 0)
+        b = srcs[1] if len(srcs) > 1 else 0
+        prog.append((v.op, dst, a, b, v.imm))
+    return prog, reg[id(out)]
+
+
+class Body:
+    """A user-defined map body compiled by the library (hipRTC) into fused
+    map, map + reduce and reverse-mode kernels."""
+
+    def __init__(self, out: Var, nin: int, dtype=torch.float32):
+        self.prog, self.out_reg = lower_body(out)
+        self.nin, self.torch_dtype = nin, dtype
+        self.e = abi.mx_expr_create(self.prog, nin, self.out_reg, abi.DTYPE_OF[dtype])
+        self._ws = {}
+
+    def _args(self, xs):
+        if len(xs) != self.nin:
+            raise ValueError(f"the body takes {self.nin} inputs")
+        xs = [x.contiguous().view(-1) for x in xs]
+        n = xs[0].numel()
+        if any(x.numel() != n or x.dtype != self.torch_dtype for x in xs):
+            raise abi.MxError(abi.MX_ERR_SHAPE, "inputs differ in length or dtype")
+        return xs, n
+
+    def map(self, *xs) -> torch.Tensor:
+        xs, n = self._args(xs)
+        out = torch.empty(n, dtype=self.torch_dtype, device=xs[0].device)
+        abi.mx_expr_map(self.e, xs, out)
+        return out
+
+    def map_reduce(self, op: int, *xs, ne=0.0) -> torch.Tensor:
+        xs, n = self._args(xs)
+        out = torch.empty((), dtype=self.torch_dtype, device=xs[0].device)
+        key = xs[0].device.index
+        ws = self._ws.get(key)
+        need = abi.mx_expr_workspace_bytes(self.e, n)
+        if ws is None or ws.numel() < need:
+            ws = self._ws[key] = torch.zeros(need, dtype=torch.uint8, device=xs[0].device)
+        abi.mx_expr_map_reduce(self.e, op, xs, n, ne, out, ws)
+        return out
+
+    def vjp(self, *xs, gout=None, gscale=None):
+        xs, n = self._args(xs)
+        grads = [torch.empty_like(x) for x in xs]
+        abi.mx_expr_vjp(self.e, xs, n, None if gout is None else gout.contiguous().view(-1),
+                        None if gscale is None else gscale.contiguous().view(1), grads)
+        return grads
+
+    def sum(self, *xs) -> torch.Tensor:
+        """reduce (+) 0 (map body xs), differentiable."""
+        return _BodySum.apply(self, *xs)
+
+
+class _BodySum(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, body, *xs):
+        ctx.body = body
+        ctx.save_for_backward(*xs)
+        return body.map_reduce(MX_ADD, *xs, ne=0.0)
+
+    @staticmethod
+    def backward(ctx, g):
+        xs = ctx.saved_tensors
+        grads = ctx.body.vjp(*xs, gscale=g.contiguous().to(ctx.body.torch_dtype))
+        return (None, *[gr.view(x.shape) for gr, x in zip(grads, xs)])

@@ -1,0 +1,313 @@
+"""GPU parity of user-defined map bodies (hipRTC-generated kernels) against
+the oracle's interpreter: map, fused map + reduce for the four reduce
+operators, reverse mode with every seed form, the differentiable sum, graph
+replay, alignment / tail / empty cases and the full-size sampled check.
+
+Tolerance of a map value: a first-order running error bound of the body in
+the element type, computed here from the oracle's binary64 values: each
+basic operation adds one rounding (u |v|, u = 2^-24 or 2^-53), exp / log /
+1/sqrt three (their library implementations are within 2 ulp, 1/sqrt is two
+roundings), and an operation passes its operands' bounds on with its partial
+derivatives.  The GPU value must lie within 4x that bound.  Reductions add the
+reduce rule of tests/parity.py; the reverse mode (twice the program's length,
+terms O(1) on these inputs) is held to 2e-5 relative for float32 and 1e-13 for
+float64, over the gradient's norm.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from parity import check_scalar, say
+
+import paper_2211_00621_amd as mx  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+abi, api = mx.abi, mx.api
+X = abi
+DEV = "cuda"
+TD = {abi.MX_F32: torch.float32, abi.MX_F64: torch.float64}
+ND = {abi.MX_F32: np.float32, abi.MX_F64: np.float64}
+U = {abi.MX_F32: 2.0 ** -24, abi.MX_F64: 2.0 ** -53}
+
+
+def IN(d, k): return (X.MX_X_IN, d, k, 0, 0.0)
+def CONST(d, v): return (X.MX_X_CONST, d, 0, 0, v)
+def OP(op, d, a, b=0): return (op, d, a, b, 0.0)
+
+
+GAUSS_DOT = ([IN(0, 0), IN(1, 1), OP(X.MX_X_SUB, 2, 0, 1), OP(X.MX_X_SQ, 2, 2), OP(X.MX_X_NEG, 2, 2),
+              OP(X.MX_X_EXP, 2, 2), CONST(3, 0.5), OP(X.MX_X_MUL, 2, 2, 3), OP(X.MX_X_MUL, 4, 0, 1),
+              OP(X.MX_X_ADD, 2, 2, 4)], 2, 2)
+ALL_OPS = ([IN(0, 0), IN(1, 1), IN(2, 2), OP(X.MX_X_SUB, 3, 0, 1), OP(X.MX_X_SQ, 3, 3), OP(X.MX_X_NEG, 3, 3),
+            OP(X.MX_X_EXP, 3, 3), CONST(4, 0.5), OP(X.MX_X_MUL, 3, 3, 4), OP(X.MX_X_DIV, 5, 0, 2),
+            OP(X.MX_X_SQRT, 6, 2), OP(X.MX_X_RSQRT, 7, 2), OP(X.MX_X_LOG, 8, 2), OP(X.MX_X_ABS, 9, 5),
+            OP(X.MX_X_MIN, 10, 9, 6), OP(X.MX_X_MAX, 10, 10, 7), OP(X.MX_X_ADD, 3, 3, 10),
+            OP(X.MX_X_ADD, 3, 3, 8)], 3, 3)
+HORNER = ([IN(0, 0), CONST(1, 0.75), OP(X.MX_X_MUL, 1, 1, 0), CONST(2, -1.5), OP(X.MX_X_ADD, 1, 1, 2),
+           OP(X.MX_X_MUL, 1, 1, 0), CONST(2, 2.0), OP(X.MX_X_ADD, 1, 1, 2)], 1, 1)
+PROGRAMS = {"gauss_dot": GAUSS_DOT, "all_ops": ALL_OPS, "horner": HORNER}
+
+
+def inputs(nin, n, dtype, seed):
+    rng = np.random.default_rng(seed)
+    xs = [rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(0.5, 2.0, n)][:nin]
+    return [x.astype(ND[dtype]) for x in xs]
+
+
+def error_bound(prog, out_reg, xs, u):
+    """First-order running error bound of the body evaluated in precision u."""
+    val, err = {}, {}
+    for op, dst, a, b, imm in prog:
+        if op == X.MX_X_IN:
+            v, e = np.asarray(xs[a], np.float64), np.zeros(len(xs[0]))
+        elif op == X.MX_X_CONST:
+            v, e = np.full(len(xs[0]), imm), np.zeros(len(xs[0]))
+        else:
+            va, ea = val[a], err[a]
+            vb, eb = (val[b], err[b]) if op <= X.MX_X_MAX else (None, None)
+            if op in (X.MX_X_ADD, X.MX_X_SUB):
+                v = va + vb if op == X.MX_X_ADD else va - vb
+                e = ea + eb + u * np.abs(v)
+            elif op == X.MX_X_MUL:
+                v = va * vb
+                e = np.abs(vb) * ea + np.abs(va) * eb + ea * eb + u * np.abs(v)
+            elif op == X.MX_X_DIV:
+                v = va / vb
+                e = (ea + np.abs(v) * eb) / np.maximum(np.abs(vb) - eb, 1e-300) + u * np.abs(v)
+            elif op in (X.MX_X_MIN, X.MX_X_MAX):
+                v = np.where(vb < va, vb, va) if op == X.MX_X_MIN else np.where(vb > va, vb, va)
+                e = np.maximum(ea, eb)
+            elif op in (X.MX_X_NEG, X.MX_X_ABS):
+                v = -va if op == X.MX_X_NEG else np.abs(va)
+                e = ea
+            elif op == X.MX_X_SQ:
+                v = va * va
+                e = 2 * np.abs(va) * ea + ea * ea + u * np.abs(v)
+            elif op == X.MX_X_EXP:
+                v = np.exp(va)
+                e = np.abs(v) * ea * (1 + ea) + 3 * u * np.abs(v)
+            elif op == X.MX_X_LOG:
+                v = np.log(va)
+                e = ea / np.maximum(np.abs(va) - ea, 1e-300) + 3 * u * np.abs(v)
+            elif op == X.MX_X_SQRT:
+                v = np.sqrt(va)
+                e = ea / np.maximum(2 * np.sqrt(np.maximum(va - ea, 1e-300)), 1e-300) + u * np.abs(v)
+            else:  # RSQRT
+                v = 1 / np.sqrt(va)
+                e = 0.5 * np.abs(v) * ea / np.maximum(np.abs(va) - ea, 1e-300) + 3 * u * np.abs(v)
+        val[dst], err[dst] = v, e
+    return err[out_reg]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def check_map(got, prog, out, xs, dtype, what):
+    ref = O.expr_map(prog, out, *xs)
+    bound = 4 * error_bound(prog, out, xs, U[dtype]) + 1e-300
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    bad = np.nonzero(err > bound)[0]
+    assert len(bad) == 0, f"{what}: {len(bad)} of {len(ref)} out of bound, first {bad[:3]}, " \
+                          f"err {err[bad[:3]]}, bound {bound[bad[:3]]}"
+
+
+@pytest.mark.parametrize("dtype", [abi.MX_F32, abi.MX_F64])
+@pytest.mark.parametrize("name", list(PROGRAMS))
+@pytest.mark.parametrize("n", [1, 3, 1000, (1 << 20) + 3])
+def test_map(dtype, name, n):
+    prog, nin, out = PROGRAMS[name]
+    say("expr map", name, dtype, n)
+    xs = inputs(nin, n, dtype, n + nin)
+    e = abi.mx_expr_create(prog, nin, out, dtype)
+    o = torch.empty(n, dtype=TD[dtype], device=DEV)
+    abi.mx_expr_map(e, [dev(x) for x in xs], o)
+    check_map(host(o), prog, out, xs, dtype, f"{name} n={n}")
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_map_misaligned_views_and_empty(shift):
+    prog, nin, out = GAUSS_DOT
+    say("expr map misaligned", shift)
+    n = 4099
+    xs = inputs(nin, n + shift, abi.MX_F32, 7)
+    big = [dev(x) for x in xs]
+    views = [t[shift:] for t in big]
+    o_big = torch.empty(n + shift, dtype=torch.float32, device=DEV)
+    o = o_big[shift:]
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    abi.mx_expr_map(e, views, o)
+    check_map(host(o), prog, out, [x[shift:] for x in xs], abi.MX_F32, "misaligned")
+    abi.mx_expr_map(e, views, o[:0])  # n = 0: nothing to do
+
+
+@pytest.mark.parametrize("dtype", [abi.MX_F32, abi.MX_F64])
+@pytest.mark.parametrize("op", [abi.MX_ADD, abi.MX_MUL, abi.MX_MIN, abi.MX_MAX])
+@pytest.mark.parametrize("n", [0, 5, 4096 * 16 + 13, (1 << 22) + 1])
+def test_map_reduce(dtype, op, n):
+    say("expr map_reduce", dtype, op, n)
+    if op == abi.MX_MUL:
+        # product of values near 1: x -> 1 + x * 2^-12, n capped so the product stays finite
+        prog, nin, out = [IN(0, 0), CONST(1, 2.0 ** -12), OP(X.MX_X_MUL, 0, 0, 1), CONST(1, 1.0),
+                          OP(X.MX_X_ADD, 0, 0, 1)], 1, 0
+        n = min(n, 20000)
+    else:
+        prog, nin, out = GAUSS_DOT
+    xs = inputs(nin, n, dtype, 3 + n)
+    ne = {abi.MX_ADD: 0.25, abi.MX_MUL: 1.0, abi.MX_MIN: 10.0, abi.MX_MAX: -10.0}[op]
+    e = abi.mx_expr_create(prog, nin, out, dtype)
+    ws = torch.zeros(abi.mx_expr_workspace_bytes(e, n), dtype=torch.uint8, device=DEV)
+    r = torch.empty((), dtype=TD[dtype], device=DEV)
+    abi.mx_expr_map_reduce(e, op, [dev(x) for x in xs], n, ne, r, ws)
+    got = float(host(r))
+    R = O.expr_map_reduce(op, ne, prog, out, *xs) if n else ne
+    if n == 0:
+        assert got == np.asarray(ne, ND[dtype])
+        return
+    vals = O.expr_map(prog, out, *xs)
+    bnd = 4 * error_bound(prog, out, xs, U[dtype])
+    if op in (abi.MX_MIN, abi.MX_MAX):
+        assert abs(got - R) <= bnd.max(), (got, R)
+    elif op == abi.MX_ADD:
+        S = np.abs(vals).sum() + abs(ne)
+        check_scalar(got, R, S, n + 1, rtol=1e-4 if dtype == abi.MX_F32 else 1e-12, what="sum")
+        assert abs(got - R) <= bnd.sum() + 1e-4 * max(abs(R), S / np.sqrt(n)), (got, R)
+    else:
+        rel = (bnd / np.abs(vals)).sum() + 4 * n * U[dtype]
+        assert abs(got - R) <= rel * abs(R), (got, R)
+    # same inputs, same bits
+    r2 = torch.empty_like(r)
+    abi.mx_expr_map_reduce(e, op, [dev(x) for x in xs], n, ne, r2, ws)
+    assert host(r2).tobytes() == host(r).tobytes()
+
+
+def _vjp_tol(dtype):
+    return 2e-5 if dtype == abi.MX_F32 else 1e-13
+
+
+@pytest.mark.parametrize("dtype", [abi.MX_F32, abi.MX_F64])
+@pytest.mark.parametrize("seed", ["none", "gout", "gscale", "both"])
+@pytest.mark.parametrize("name", ["gauss_dot", "all_ops"])
+def test_vjp(dtype, seed, name):
+    prog, nin, out = PROGRAMS[name]
+    n = 10007
+    say("expr vjp", name, dtype, seed)
+    xs = inputs(nin, n, dtype, 21)
+    rng = np.random.default_rng(5)
+    gout = rng.uniform(-1, 1, n).astype(ND[dtype]) if seed in ("gout", "both") else None
+    gscale = np.array([0.375], dtype=ND[dtype]) if seed in ("gscale", "both") else None
+    e = abi.mx_expr_create(prog, nin, out, dtype)
+    grads = [torch.full((n,), np.nan, dtype=TD[dtype], device=DEV) for _ in range(nin)]
+    abi.mx_expr_vjp(e, [dev(x) for x in xs], n, None if gout is None else dev(gout),
+                    None if gscale is None else dev(gscale), grads)
+    ref = O.expr_vjp(prog, out, xs, gout=gout, gscale=None if gscale is None else float(gscale[0]))
+    for k in range(nin):
+        g = host(grads[k]).astype(np.float64)
+        scale = np.linalg.norm(ref[k]) / np.sqrt(n) + 1e-300
+        assert np.all(np.abs(g - ref[k]) <= _vjp_tol(dtype) * (np.abs(ref[k]) + scale)), (k, seed)
+
+
+def test_vjp_skips_null_gradients_and_unused_inputs():
+    say("expr vjp null outputs")
+    prog = [IN(0, 0), IN(1, 1), IN(2, 2), OP(X.MX_X_MUL, 3, 0, 0)]  # inputs 1 and 2 unused
+    n = 999
+    xs = inputs(3, n, abi.MX_F32, 4)
+    e = abi.mx_expr_create(prog, 3, 3, abi.MX_F32)
+    g0 = torch.full((n,), 7.0, device=DEV)
+    g2 = torch.full((n,), 7.0, device=DEV)
+    abi.mx_expr_vjp(e, [dev(x) for x in xs], n, None, None, [g0, None, g2])
+    assert np.allclose(host(g0), 2 * xs[0], rtol=1e-6, atol=0)
+    assert np.all(host(g2) == 0.0)
+
+
+def test_body_sum_autograd_matches_vjp():
+    say("expr autograd")
+    a, b, c = api.body_inputs(3)
+    body = api.Body(api.exp(-(a - b) ** 2) * 0.5 + a * b / c, 3)
+    xs = inputs(3, 50001, abi.MX_F32, 9)
+    ts = [dev(x).requires_grad_(True) for x in xs]
+    s = body.sum(*ts)
+    (2.5 * s).backward()
+    prog, out = body.prog, body.out_reg
+    R = O.expr_map_reduce(O.ADD, 0.0, prog, out, *xs)
+    vals = O.expr_map(prog, out, *xs)
+    check_scalar(float(host(s.detach())), R, np.abs(vals).sum(), len(vals), what="body sum")
+    ref = O.expr_vjp(prog, out, xs, gscale=2.5)
+    for t, r in zip(ts, ref):
+        g = host(t.grad).astype(np.float64)
+        assert np.all(np.abs(g - r) <= 2e-5 * (np.abs(r) + np.linalg.norm(r) / np.sqrt(len(r))))
+
+
+def test_graph_replay_of_map_reduce():
+    say("expr graph")
+    prog, nin, out = GAUSS_DOT
+    n = 1 << 20
+    xs = inputs(nin, n, abi.MX_F32, 13)
+    ins = [dev(x) for x in xs]
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    abi.mx_expr_prepare(e)
+    ws = torch.zeros(abi.mx_expr_workspace_bytes(e, n), dtype=torch.uint8, device=DEV)
+    r = torch.empty((), dtype=torch.float32, device=DEV)
+    o = torch.empty(n, dtype=torch.float32, device=DEV)
+    abi.mx_expr_map_reduce(e, abi.MX_ADD, ins, n, 0.0, r, ws)
+    abi.mx_expr_map(e, ins, o)
+    eager_r, eager_o = host(r).copy(), host(o).copy()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        abi.mx_graph_begin(s)
+        abi.mx_expr_map_reduce(e, abi.MX_ADD, ins, n, 0.0, r, ws, stream=s)
+        abi.mx_expr_map(e, ins, o, stream=s)
+        g = abi.mx_graph_end(s)
+    for rep in range(3):
+        r.zero_()
+        o.zero_()
+        torch.cuda.synchronize()
+        abi.mx_graph_launch(g, s)
+        s.synchronize()
+        assert host(r).tobytes() == eager_r.tobytes() and np.array_equal(host(o), eager_o), rep
+    abi.mx_graph_destroy(g)
+
+
+def test_argument_errors():
+    say("expr errors")
+    prog, nin, out = GAUSS_DOT
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    x = torch.zeros(16, device=DEV)
+    r = torch.empty((), device=DEV)
+    with pytest.raises(abi.MxError) as err:
+        abi.mx_expr_map(e, [x, None], torch.empty(16, device=DEV))
+    assert err.value.status == abi.MX_ERR_INVALID
+    with pytest.raises(abi.MxError) as err:
+        abi.mx_expr_map_reduce(e, abi.MX_ADD, [x, x], 16, 0.0, r, torch.zeros(16, dtype=torch.uint8, device=DEV))
+    assert err.value.status == abi.MX_ERR_WORKSPACE
+    with pytest.raises(abi.MxError) as err:
+        abi.mx_expr_map_reduce(e, 7, [x, x], 16, 0.0, r, torch.zeros(1 << 14, dtype=torch.uint8, device=DEV))
+    assert err.value.status == abi.MX_ERR_INVALID
+
+
+def test_full_size_sampled():
+    """2^26 elements in the launch configuration the bench times, checked on a
+    sample of positions (elementwise, so each sampled value is the oracle's)."""
+    prog, nin, out = GAUSS_DOT
+    n = 1 << 26
+    say("expr full size", n)
+    gen = torch.Generator(device=DEV).manual_seed(0)
+    ins = [torch.rand(n, device=DEV, generator=gen) * 2 - 1 for _ in range(nin)]
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    o = torch.empty(n, device=DEV)
+    abi.mx_expr_map(e, ins, o)
+    idx = torch.cat([torch.arange(0, 4096, device=DEV), torch.randint(0, n, (1 << 16,), device=DEV, generator=gen),
+                     torch.arange(n - 4096, n, device=DEV)])
+    xs = [host(t[idx]) for t in ins]
+    check_map(host(o[idx]), prog, out, xs, abi.MX_F32, "full size")
+    ws = torch.zeros(abi.mx_expr_workspace_bytes(e, n), dtype=torch.uint8, device=DEV)
+    r = torch.empty((), device=DEV)
+    abi.mx_expr_map_reduce(e, abi.MX_ADD, ins, n, 0.0, r, ws)
+    total = float(host(o).astype(np.float64).sum())   # the sum of the checked map values
+    assert abs(float(host(r)) - total) <= 1e-4 * max(abs(total), float(np.abs(host(o)).sum()) / np.sqrt(n))
