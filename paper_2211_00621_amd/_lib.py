@@ -94,6 +94,9 @@ def load() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch brings its own HIP runtime; loading it first makes libmx.so bind to
+    # that same runtime (by soname) instead of starting a second one
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2211_00621_amd/build.py` "
                           "(the primitives have no CPU fallback)")
