@@ -55,6 +55,10 @@ TRAFFIC = {
     # k_seg_span, 65536 rows / 32.1 M values: 130.46 MB fetched + 0.26 MB written (1.01x algorithmic)
     "seg_span": {"file": "segmented.hip", "bytes": 130721777,
                  "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},
+    # mx_xvjp (generated from expr.hip) for exp(-(a-b)^2)*0.5 + a*b over 2^26 float32 pairs:
+    # 536.87 MB fetched + 536.80 MB written (1.00x algorithmic)
+    "expr_vjp": {"file": "expr.hip", "bytes": 1073666406,
+                 "source": "d8fca25dfc5c6fd5b82c0000ec071f7961c30db0f15bb0ea9343b8be7378e3e5"},
     # k_seg_broadcast: 1.61 MB fetched (offsets, gradients) + 128.83 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 130438732,
                       "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},
@@ -302,7 +306,7 @@ def cpu_baseline_nested(d, rows, C, gA, gB, gvals, offsets):
     torch.cuda.synchronize()
     log("nested: cpu baseline (oracle)")
     L, v, A, B, G, g = d["L"], d["v"], d["A"], d["B"], d["G"], d["g_rows"]
-    sample_rows = 24
+    sample_rows = 128
     t0 = time.perf_counter()
     off = O.offsets_from_lengths(L)
     R = O.segmented_reduce(O.ADD, 0.0, v, off)
@@ -368,7 +372,7 @@ def bench_dot(args):
                            "frac_hbm": round(gbs(8 * nn, us * 1e-3) / HBM_PEAK_GBS, 4)}
     fused = parts["fused_f32"]
     plain = parts["plain_map2"] + parts["plain_reduce"]
-    return {
+    line = {
         "metric": METRIC, "value": n / (fused * 1e-3), "unit": "elem/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -381,6 +385,18 @@ def bench_dot(args):
         "plain": {"us": round(plain * 1e3, 2), "fused_speedup": round(plain / fused, 2)},
         "sweep": sweep,
     }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("dot: cpu baseline (oracle)")
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            O.dot(a, b)
+            reps += 1
+        secs = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": reps * n / secs, "unit": "elem/s", "cores": cpu_threads(),
+                                "kind": "oracle", "seconds": round(secs, 2),
+                                "sample": f"the float32 dot over 2^20, {reps} times"}
+    return line
 
 
 # ============================================================ N-body loop
@@ -566,14 +582,16 @@ def bench_kmeans(args):
     if not args.no_cpu_baseline:
         import oracle as O
         log("kmeans: cpu baseline (oracle)")
-        sample = 1 << 16
+        Co = X[:k].astype(np.float64)
         t0 = time.perf_counter()
-        lab = O.kmeans_assign(X[:sample], X[:k])
-        O.kmeans_update(X[:sample], lab, X[:k])
+        for _ in range(iters):
+            lab = O.kmeans_assign(X, Co)
+            _, _, Co = O.kmeans_update(X, lab, Co)
         secs = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": sample * k / secs, "unit": "point-centroid evals/s", "cores": cpu_threads(),
-                                "kind": "oracle", "seconds": round(secs, 2),
-                                "sample": "one assignment + update step over the first 2^16 of the 2^20 points"}
+        line["cpu_baseline"] = {"value": iters * n * k / secs, "unit": "point-centroid evals/s",
+                                "cores": cpu_threads(), "kind": "oracle", "seconds": round(secs, 2),
+                                "sample": f"the whole workload: {iters} assignment + update steps over all "
+                                          f"2^20 points (no SSE / gradient)"}
     del graph
     return line
 
@@ -646,7 +664,7 @@ def bench_batched(args):
     if not args.no_cpu_baseline:
         import oracle as O
         log("batched: cpu baseline (oracle)")
-        sample = 512
+        sample = 2048
         t0 = time.perf_counter()
         O.batch_forward(tb[:sample], bt.A, bt.B, bt.out_len)
         O.batch_backward(tb[:sample], bt.A, bt.B, bt.gout)
@@ -719,7 +737,7 @@ def bench_expr(args):
         "config": {"workload": "user-defined map body exp(-(a-b)^2)*0.5 + a*b over two float32 vectors of 2^26: "
                                "fused map+reduce(+) and its reverse mode (runtime-compiled kernels)", "n": n},
         "roofline": {"bound": "hbm", "kernel": "mx_xvjp", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_of("expr_vjp")},
         "parts": {"map_reduce_us": round(parts["map_reduce"] * 1e3, 1),
                   "map_reduce_GB/s": round(gbs(fwd_bytes, parts["map_reduce"]), 1),
                   "vjp_us": round(parts["vjp"] * 1e3, 1), "vjp_GB/s": round(ach, 1)},
@@ -729,7 +747,7 @@ def bench_expr(args):
         import numpy as np
         import oracle as O
         log("expr: cpu baseline (oracle)")
-        sample = 1 << 24
+        sample = n
         an, bn = a[:sample].cpu().numpy(), b[:sample].cpu().numpy()
         t0 = time.perf_counter()
         O.expr_map_reduce(O.ADD, 0.0, prog, out_reg, an, bn)
@@ -737,7 +755,7 @@ def bench_expr(args):
         secs = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": 2 * sample / secs, "unit": "elem/s", "cores": cpu_threads(),
                                 "kind": "oracle", "seconds": round(secs, 2),
-                                "sample": f"map+reduce and reverse mode over the first 2^24 of the 2^26 elements"}
+                                "sample": "map+reduce and reverse mode over all 2^26 elements"}
     return line
 
 
