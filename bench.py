@@ -192,6 +192,27 @@ def bench_nested(args):
     graph_ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
     log(f"nested: fused {ms:.3f} ms/step (eager), {graph_ms:.3f} ms/step (HIP graph replay)")
     parts = {nm: per_launch_ms(f, reps=max(args.steps, 10)) for nm, f in zip(names, fused_parts)}
+    # the same ragged kernels over three copies of their streamed array in turn
+    # (3 x 129 MB, more than the 256 MB last-level cache): every launch reads
+    # or writes its values from HBM, not from a cache warmed by the previous one
+    vcopies = [d["tv"]] + [d["tv"].clone() for _ in range(2)]
+    gcopies = [gvals] + [torch.empty_like(gvals) for _ in range(2)]
+    turn = [0]
+
+    def rotating(fn):
+        def f():
+            turn[0] = (turn[0] + 1) % 3
+            fn(turn[0])
+        return f
+
+    cold = {
+        "row_sums": per_launch_ms(rotating(lambda i: abi.mx_segmented_reduce(abi.MX_ADD, vcopies[i], offsets, 0.0,
+                                                                              rows)), reps=max(args.steps, 12)),
+        "row_sums_adjoint": per_launch_ms(rotating(lambda i: abi.mx_segmented_sum_adjoint_f32(d["tg"], offsets,
+                                                                                               gcopies[i])),
+                                          reps=max(args.steps, 12)),
+    }
+    del vcopies, gcopies
     psteps = max(1, min(args.steps, 3))
     pms = timed_on(torch.cuda.current_stream(), plain_step, psteps, 1)
     pparts = {nm: per_launch_ms(f, reps=1, warmup=0) for nm, f in zip(names, plain_parts)}
@@ -213,6 +234,9 @@ def bench_nested(args):
         if n in bytes_:
             e["GB/s"] = round(gbs(bytes_[n], parts[n]), 1)
             e["frac_hbm"] = round(gbs(bytes_[n], parts[n]) / HBM_PEAK_GBS, 4)
+        if n in cold:
+            e["cold_us"] = round(cold[n] * 1e3, 2)
+            e["cold_GB/s"] = round(gbs(bytes_[n], cold[n]), 1)
         else:
             tf = flops / (parts[n] * 1e-3) / 1e12
             e["TFLOP/s"] = round(tf, 2)
@@ -723,6 +747,26 @@ def bench_expr(args):
 
     parts = {"map_reduce": per_launch_ms(fwd, reps=args.steps, warmup=args.warmup),
              "vjp": per_launch_ms(bwd, reps=args.steps, warmup=args.warmup)}
+    # the body inside the nested map(reduce) over the ragged rows of the nested
+    # step (65 536 rows, lengths log-uniform [1, 4096]), two value arrays
+    import workloads as W
+    L = W.ragged_lengths(NESTED["nseg"], NESTED["seed"], NESTED["lmax"])
+    off = torch.from_numpy(np.concatenate([[0], np.cumsum(L)]).astype(np.int64)).to(dev)
+    nv = int(L.sum())
+    va, vb = a[:nv], b[:nv]
+    rows = torch.empty(len(L), device=dev)
+    tmpv = torch.empty(nv, device=dev)
+
+    def seg():
+        abi.mx_expr_segmented_reduce(e, abi.MX_ADD, [va, vb], off, 0.0, rows)
+
+    def seg_plain():  # body into a temporary, then the fixed ragged row sums
+        abi.mx_expr_map(e, [va, vb], tmpv)
+        abi.mx_segmented_reduce(abi.MX_ADD, tmpv, off, 0.0, rows)
+
+    parts["segmented"] = per_launch_ms(seg, reps=args.steps, warmup=args.warmup)
+    parts["segmented_plain"] = per_launch_ms(seg_plain, reps=args.steps, warmup=args.warmup)
+    seg_bytes = 8 * nv + 8 * (len(L) + 1) + 4 * len(L)
     cur = torch.cuda.current_stream()
     ms = timed_on(cur, lambda: (fwd(), bwd()), args.steps, args.warmup)
     pms = timed_on(cur, plain_fwd, max(1, min(args.steps, 10)), 1)
@@ -740,7 +784,11 @@ def bench_expr(args):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_of("expr_vjp")},
         "parts": {"map_reduce_us": round(parts["map_reduce"] * 1e3, 1),
                   "map_reduce_GB/s": round(gbs(fwd_bytes, parts["map_reduce"]), 1),
-                  "vjp_us": round(parts["vjp"] * 1e3, 1), "vjp_GB/s": round(ach, 1)},
+                  "vjp_us": round(parts["vjp"] * 1e3, 1), "vjp_GB/s": round(ach, 1),
+                  "segmented_rows": len(L), "segmented_values": nv,
+                  "segmented_us": round(parts["segmented"] * 1e3, 1),
+                  "segmented_GB/s": round(gbs(seg_bytes, parts["segmented"]), 1),
+                  "segmented_via_temporary_us": round(parts["segmented_plain"] * 1e3, 1)},
         "plain": {"forward_us": round(pms * 1e3, 1), "fused_speedup": round(pms / parts["map_reduce"], 2)},
     }
     if not args.no_cpu_baseline:

@@ -512,6 +512,20 @@ size_t mx_expr_workspace_bytes(const mx_expr *e, int64_t n);
 mx_status mx_expr_map_reduce(mx_expr *e, mx_redop op, const void *const *in_dev, int64_t n, const void *ne_host,
                              void *out_dev, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Nested map (reduce op ne . map body) over ragged rows (Listing 2's shape
+ * with any body): out[r] = ne op body(x_i) op ... over the elements i of row
+ * r, i in [offsets[r], offsets[r+1]); every input is a device array (not
+ * NULL, even when all rows are empty) of offsets[nseg] elements laid out by
+ * the same int64 device offsets (nseg + 1 entries,
+ * offsets[0] = 0, non-decreasing; checked on the device in debug mode).  An
+ * empty row gives ne.  Same block-span schedule as mx_segmented_reduce, with
+ * the body applied as each element is loaded (no temporary); deterministic.
+ * The reverse of a row sum with a body is mx_segmented_sum_adjoint_f32 (the
+ * row gradients broadcast over the elements) then mx_expr_vjp with that as
+ * gout. */
+mx_status mx_expr_segmented_reduce(mx_expr *e, mx_redop op, const void *const *in_dev, const int64_t *offsets_dev,
+                                   int64_t nseg, const void *ne_host, void *out_dev, hipStream_t stream);
+
 /* Reverse mode: gin[k][i] = s_i * d body / d input k at element i, with
  * s_i = (gout ? gout[i] : 1) * (gscale ? *gscale : 1) (gout a device array of
  * n, gscale a device scalar; either may be NULL).  The adjoint flows back

@@ -495,6 +495,12 @@ def mx_expr_map_reduce(e: Expr, op: int, inputs, n: int, ne, out, ws, stream=Non
                                    _dptr(ws), _nbytes(ws), _stream(stream)), "mx_expr_map_reduce")
 
 
+def mx_expr_segmented_reduce(e: Expr, op: int, inputs, offsets, ne, out, stream=None) -> None:
+    nb = ctypes.c_float(ne) if e.dtype == MX_F32 else ctypes.c_double(ne)
+    _check(_L().mx_expr_segmented_reduce(e.handle, int(op), _ptr_list(inputs), _dptr(offsets), offsets.numel() - 1,
+                                         ctypes.byref(nb), _dptr(out), _stream(stream)), "mx_expr_segmented_reduce")
+
+
 def mx_expr_vjp(e: Expr, inputs, n: int, gout, gscale, grads, stream=None) -> None:
     _check(_L().mx_expr_vjp(e.handle, _ptr_list(inputs), int(n), _dptr(gout), _dptr(gscale), _ptr_list(grads),
                             _stream(stream)), "mx_expr_vjp")

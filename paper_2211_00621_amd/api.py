@@ -482,6 +482,13 @@ class Body:
         abi.mx_expr_map_reduce(self.e, op, xs, n, ne, out, ws)
         return out
 
+    def segmented_reduce(self, op: int, offsets: torch.Tensor, *xs, ne=0.0) -> torch.Tensor:
+        """out[r] = ne op body(x_i) ... over the elements i of ragged row r."""
+        xs, n = self._args(xs)
+        out = torch.empty(offsets.numel() - 1, dtype=self.torch_dtype, device=xs[0].device)
+        abi.mx_expr_segmented_reduce(self.e, op, xs, offsets, ne, out)
+        return out
+
     def vjp(self, *xs, gout=None, gscale=None):
         xs, n = self._args(xs)
         grads = [torch.empty_like(x) for x in xs]

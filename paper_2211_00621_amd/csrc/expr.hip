@@ -167,6 +167,7 @@ std::string gen_source(const mx_expr &e) {
     s += f32 ? "typedef float T;\ntypedef float4 VT;\n#define VW 4\n" : "typedef double T;\ntypedef double2 VT;\n#define VW 2\n";
     s += "#define NT " + std::to_string(NT) + "\n#define GPI " + std::to_string(kGroupsPerIt) + "\n";
     s += "#define NIN " + std::to_string(e.nin) + "\n";
+    s += "#define SU (NIN >= 4 ? 2 : NIN >= 2 ? 4 : 8)\n";  // 16-byte groups per input in flight per lane
     s += "__device__ __forceinline__ T mx_body(" + in_params + ") {\n#pragma clang fp contract(off)\n" + fwd +
          "    return v" + std::to_string(os) + ";\n}\n";
     s += "__device__ __forceinline__ void mx_body_vjp(" + in_params +
@@ -333,6 +334,95 @@ extern "C" __global__ void __launch_bounds__(NT) mx_xfin_)" + nm + R"((const T *
     const T r = mx_block_)" + nm + R"((acc, sh);
     if (threadIdx.x == 0) *out = mx_op_)" + nm + R"((ne, r);
 }
+// Nested map (reduce op ne . map body) over ragged rows sharing `offsets`: a
+// block takes rb consecutive rows (one contiguous span of elements), its four
+// waves take contiguous quarters of the span's 16-byte groups, lanes
+// interleaved; a thread folds the body values it visits into its current row
+// (positions only increase, so rows never go back) and parks finished rows in
+// its own LDS slot; each row's NT slots are then folded in a fixed order.
+extern "C" __global__ void __launch_bounds__(NT) mx_xseg_)" + nm + R"((MX_PTRS, const long long *__restrict__ offsets,
+                                                              long long nseg, int rb, T ne, T *__restrict__ out,
+                                                              int vec) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char mx_lds[];
+    long long *soff = (long long *)mx_lds;
+    T *slot = (T *)(mx_lds + (((long long)(rb + 1) * 8 + 15) & ~15LL));
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const long long r0 = (long long)blockIdx.x * rb;
+    const int nrows = (int)(nseg - r0 < rb ? nseg - r0 : rb);
+    if (t <= nrows) soff[t] = offsets[r0 + t];
+    for (int k = 0; k < nrows; ++k) slot[k * NT + t] = )" + id + R"(;
+    __syncthreads();
+    const long long S = soff[0], E = soff[nrows];
+    int cur = 0;
+    long long end = soff[1];
+    T a = )" + id + R"(;
+    auto take = [&](long long p, T x) {
+        while (p >= end) {
+            slot[cur * NT + t] = a;
+            a = )" + id + R"(;
+            ++cur;
+            end = soff[cur + 1];
+        }
+        a = mx_op_)" + nm + R"((a, x);
+    };
+    // row (within the block) holding position p: row ends at or before p, one ballot
+    auto row_of = [&](long long p) {
+        const bool past = lane < nrows && soff[lane + 1] <= p;
+        return __popcll(__ballot(past));
+    };
+    if (vec) {
+        const long long vs = (S + VW - 1) / VW, ve = E / VW > vs ? E / VW : vs;
+        const long long head_end = vs * VW < E ? vs * VW : E;
+        const long long q = (ve - vs + 3) / 4;
+        const long long cs = vs + w * q < ve ? vs + w * q : ve;
+        const long long ce = cs + q < ve ? cs + q : ve;
+        if (w == 0) {
+            if (S + lane < head_end) take(S + lane, mx_body_i(p0, p1, p2, p3, S + lane));
+        } else if (cs < ce) {
+            cur = row_of(cs * VW);
+            end = soff[cur + 1];
+        }
+        for (long long i = cs + lane; i < ce; i += SU * 64) {
+            VT x[SU][4];
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                if (i + u * 64 < ce) mx_load_group(p0, p1, p2, p3, i + u * 64, x[u]);
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                if (i + u * 64 < ce) {
+                    const long long q0 = (i + u * 64) * VW;
+                    if (q0 + VW - 1 < end) {
+#pragma unroll
+                        for (int j = 0; j < VW; ++j) a = mx_op_)" + nm + R"((a, mx_body_at(x[u], j));
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < VW; ++j) take(q0 + j, mx_body_at(x[u], j));
+                    }
+                }
+            }
+        }
+        if (w == 3) {
+            const long long tail_start = ve * VW > head_end ? ve * VW : head_end;
+            if (cs >= ce && tail_start < E) {
+                cur = row_of(tail_start);
+                end = soff[cur + 1];
+            }
+            if (tail_start + lane < E) take(tail_start + lane, mx_body_i(p0, p1, p2, p3, tail_start + lane));
+        }
+    } else {
+        for (long long i = S + t; i < E; i += NT) take(i, mx_body_i(p0, p1, p2, p3, i));
+    }
+    slot[cur * NT + t] = a;
+    __syncthreads();
+    for (int k = w; k < nrows; k += NT / 64) {
+        T v = slot[k * NT + lane];
+#pragma unroll
+        for (int qq = 1; qq < NT / 64; ++qq) v = mx_op_)" + nm + R"((v, slot[k * NT + qq * 64 + lane]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v = mx_op_)" + nm + R"((v, __shfl_xor(v, o, 64));
+        if (lane == 0) out[r0 + k] = mx_op_)" + nm + R"((ne, v);
+    }
+}
 )";
     }
     return s;
@@ -341,7 +431,7 @@ extern "C" __global__ void __launch_bounds__(NT) mx_xfin_)" + nm + R"((const T *
 // ---------------------------------------------------------------- compiled modules
 struct Compiled {
     hipModule_t mod = nullptr;
-    hipFunction_t map = nullptr, vjp = nullptr, red[4] = {}, fin[4] = {};
+    hipFunction_t map = nullptr, vjp = nullptr, red[4] = {}, fin[4] = {}, seg[4] = {};
 };
 
 std::mutex g_mu;
@@ -388,14 +478,16 @@ mx_status compile(const mx_expr &e, const Compiled **out) {
     for (int o = 0; o < 4; ++o) {
         MX_TRY_HIP(hipModuleGetFunction(&c->red[o], c->mod, (std::string("mx_xred_") + nm[o]).c_str()));
         MX_TRY_HIP(hipModuleGetFunction(&c->fin[o], c->mod, (std::string("mx_xfin_") + nm[o]).c_str()));
+        MX_TRY_HIP(hipModuleGetFunction(&c->seg[o], c->mod, (std::string("mx_xseg_") + nm[o]).c_str()));
     }
     *out = c.get();
     g_cache.emplace(key, std::move(c));
     return MX_OK;
 }
 
-mx_status launch(hipFunction_t f, int64_t blocks, hipStream_t s, void **args, const char *what) {
-    MX_TRY_HIP(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, NT, 1, 1, 0, s, args, nullptr));
+mx_status launch(hipFunction_t f, int64_t blocks, hipStream_t s, void **args, const char *what,
+                 unsigned lds = 0) {
+    MX_TRY_HIP(hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, NT, 1, 1, lds, s, args, nullptr));
     (void)what;
     return MX_OK;
 }
@@ -544,6 +636,44 @@ mx_status mx_expr_map_reduce(mx_expr *e, mx_redop op, const void *const *in_dev,
     double ne = *(const double *)ne_host;
     void *args[] = {&partial, &nbi, &ne, &out_dev};
     return launch(c->fin[op], 1, stream, args, who);
+}
+
+mx_status mx_expr_segmented_reduce(mx_expr *e, mx_redop op, const void *const *in_dev, const int64_t *offsets_dev,
+                                   int64_t nseg, const void *ne_host, void *out_dev, hipStream_t stream) {
+    const char *who = "mx_expr_segmented_reduce";
+    MX_REQUIRE(e, MX_ERR_INVALID, "%s: null expression", who);
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "%s: nseg < 0", who);
+    MX_REQUIRE(op >= MX_ADD && op <= MX_MAX, MX_ERR_INVALID, "%s: bad reduce operator %d", who, (int)op);
+    if (nseg == 0) return MX_OK;
+    MX_REQUIRE(in_dev && offsets_dev && ne_host && out_dev, MX_ERR_INVALID, "%s: null pointer", who);
+    for (int k = 0; k < e->nin; ++k) MX_REQUIRE(in_dev[k], MX_ERR_INVALID, "%s: input %d is null", who, k);
+    if (debug_mode())
+        if (mx_status st = check_offsets_debug(who, offsets_dev, nseg, stream)) return st;
+    const Compiled *c;
+    if (mx_status st = compile(*e, &c)) return st;
+    const DeviceInfo *dv;
+    if (mx_status st = device_info(&dv)) return st;
+    const void *p[kMaxIn] = {};
+    bool al = true;
+    for (int k = 0; k < e->nin; ++k) {
+        p[k] = in_dev[k];
+        al = al && aligned16(p[k]);
+    }
+    const int rb = segmented_rows_per_block(nseg, dv);
+    const int64_t grid = ceil_div(nseg, rb);
+    MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "%s: too many rows", who);
+    const unsigned lds = (unsigned)((((size_t)rb + 1) * 8 + 15) / 16 * 16 + (size_t)rb * NT * dtype_size(e->dtype));
+    int vec = al ? 1 : 0, rbi = rb;
+    long long ns = nseg;
+    const void *off = offsets_dev;
+    if (e->dtype == MX_F32) {
+        float ne = *(const float *)ne_host;
+        void *args[] = {&p[0], &p[1], &p[2], &p[3], &off, &ns, &rbi, &ne, &out_dev, &vec};
+        return launch(c->seg[op], grid, stream, args, who, lds);
+    }
+    double ne = *(const double *)ne_host;
+    void *args[] = {&p[0], &p[1], &p[2], &p[3], &off, &ns, &rbi, &ne, &out_dev, &vec};
+    return launch(c->seg[op], grid, stream, args, who, lds);
 }
 
 mx_status mx_expr_vjp(mx_expr *e, const void *const *in_dev, int64_t n, const void *gout_dev,

@@ -39,6 +39,9 @@ struct DeviceInfo {
 };
 mx_status device_info(const DeviceInfo **out);  // current device, cached
 bool debug_mode();
+// block-span segmented reduce: rows per block; debug-mode check of offsets
+int segmented_rows_per_block(int64_t nseg, const DeviceInfo *d);
+mx_status check_offsets_debug(const char *who, const int64_t *off, int64_t nseg, hipStream_t s);
 
 constexpr int kWave = 64;
 

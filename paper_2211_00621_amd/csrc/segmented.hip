@@ -473,6 +473,16 @@ mx_status segmented(const char *who, bool plain, int op, mx_dtype dtype, const v
 
 }  // namespace
 
+// Shared with the generated map-body kernels: rows per block of a block-span
+// reduce, and the debug-mode check of an offsets array.
+int segmented_rows_per_block(int64_t nseg, const DeviceInfo *d) { return rows_per_block(nseg, d); }
+
+mx_status check_offsets_debug(const char *who, const int64_t *off, int64_t nseg, hipStream_t s) {
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    return validate_offsets(who, off, nseg, s, d);
+}
+
 // Also used by marshaling.
 mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, void *ws,
                              size_t ws_bytes, hipStream_t s) {

@@ -84,7 +84,7 @@ def test_generated_source_compiles_for_gfx950(dtype):
     rtc = _hiprtc()
     e = abi.mx_expr_create(ALL_OPS, 3, 3, dtype)
     src = abi.mx_expr_source(e).encode()
-    assert b"mx_xmap" in src and b"mx_xvjp" in src and b"mx_xred_max" in src
+    assert b"mx_xmap" in src and b"mx_xvjp" in src and b"mx_xred_max" in src and b"mx_xseg_min" in src
     prog = ctypes.c_void_p()
     assert rtc.hiprtcCreateProgram(ctypes.byref(prog), src, b"mx_expr.hip", 0, None, None) == 0
     opts = [b"--offload-arch=gfx950", b"-O3", b"-ffp-contract=off", b"-Xclang", b"-target-feature", b"-Xclang",

@@ -1,7 +1,8 @@
 """GPU parity of user-defined map bodies (hipRTC-generated kernels) against
 the oracle's interpreter: map, fused map + reduce for the four reduce
-operators, reverse mode with every seed form, the differentiable sum, graph
-replay, alignment / tail / empty cases and the full-size sampled check.
+operators, the nested map(reduce) over ragged rows, reverse mode with every
+seed form, the differentiable sum, graph replay, alignment / tail / empty
+cases and the full-size sampled checks.
 
 Tolerance of a map value: a first-order running error bound of the body in
 the element type, computed here from the oracle's binary64 values: each
@@ -311,3 +312,108 @@ def test_full_size_sampled():
     abi.mx_expr_map_reduce(e, abi.MX_ADD, ins, n, 0.0, r, ws)
     total = float(host(o).astype(np.float64).sum())   # the sum of the checked map values
     assert abs(float(host(r)) - total) <= 1e-4 * max(abs(total), float(np.abs(host(o)).sum()) / np.sqrt(n))
+
+
+# ---------------------------------------------------------------- nested map(reduce) over ragged rows
+def ragged_lengths(kind, rng):
+    if kind == "mixed_empty":
+        return np.array([0, 0, 5, 0, 1000, 3, 0, 1, 64, 65, 4096, 0])
+    if kind == "one_long":
+        return np.array([100003])
+    if kind == "log_uniform":
+        return np.floor(np.exp(rng.uniform(0, np.log(4097), 3000))).astype(np.int64)
+    if kind == "all_empty":
+        return np.zeros(7, dtype=np.int64)
+    if kind == "short_many":
+        return rng.integers(0, 9, 20000)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("dtype", [abi.MX_F32, abi.MX_F64])
+@pytest.mark.parametrize("op", [abi.MX_ADD, abi.MX_MUL, abi.MX_MIN, abi.MX_MAX])
+@pytest.mark.parametrize("kind", ["mixed_empty", "one_long", "log_uniform", "all_empty", "short_many"])
+@pytest.mark.parametrize("shift", [0, 1])
+def test_segmented_reduce(dtype, op, kind, shift):
+    say("expr segmented", dtype, op, kind, shift)
+    rng = np.random.default_rng(17)
+    L = ragged_lengths(kind, rng)
+    off = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    n = int(off[-1])
+    if op == abi.MX_MUL:
+        prog, nin, out = [IN(0, 0), CONST(1, 2.0 ** -12), OP(X.MX_X_MUL, 0, 0, 1), CONST(1, 1.0),
+                          OP(X.MX_X_ADD, 0, 0, 1)], 1, 0
+    else:
+        prog, nin, out = GAUSS_DOT
+    xs = inputs(nin, n + shift + 4, dtype, 5)   # a few spare elements: views are never empty allocations
+    ne = {abi.MX_ADD: 0.25, abi.MX_MUL: 1.0, abi.MX_MIN: 10.0, abi.MX_MAX: -10.0}[op]
+    e = abi.mx_expr_create(prog, nin, out, dtype)
+    # inputs must be real device arrays even when every row is empty
+    ins = [dev(x)[shift:shift + n] if n else dev(x) for x in xs]
+    xs = [x[shift:shift + n] for x in xs]
+    o = torch.full((len(L),), np.nan, dtype=TD[dtype], device=DEV)
+    abi.mx_expr_segmented_reduce(e, op, ins, dev(off), ne, o)
+    got = host(o).astype(np.float64)
+    vals = O.expr_map(prog, out, *xs) if n else np.zeros(0)
+    R = O.segmented_reduce(op, ne, vals, off)
+    bnd = 4 * error_bound(prog, out, xs, U[dtype]) if n else np.zeros(0)
+    for r in range(len(L)):
+        a, b = off[r], off[r + 1]
+        if a == b:
+            assert got[r] == np.asarray(ne, ND[dtype]), r
+            continue
+        if op in (abi.MX_MIN, abi.MX_MAX):
+            assert abs(got[r] - R[r]) <= bnd[a:b].max(), r
+        elif op == abi.MX_ADD:
+            S = np.abs(vals[a:b]).sum() + abs(ne)
+            tol = (1e-4 if dtype == abi.MX_F32 else 1e-12) * max(abs(R[r]), S / np.sqrt(b - a + 1))
+            assert abs(got[r] - R[r]) <= bnd[a:b].sum() + tol, (r, got[r], R[r])
+        else:
+            rel = (bnd[a:b] / np.abs(vals[a:b])).sum() + 4 * (b - a + 1) * U[dtype]
+            assert abs(got[r] - R[r]) <= rel * abs(R[r]), r
+    o2 = torch.empty_like(o)
+    abi.mx_expr_segmented_reduce(e, op, ins, dev(off), ne, o2)
+    assert host(o2).tobytes() == host(o).tobytes()
+
+
+def test_segmented_reduce_debug_mode_rejects_bad_offsets():
+    say("expr segmented debug")
+    prog, nin, out = GAUSS_DOT
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    x = torch.zeros(16, device=DEV)
+    o = torch.empty(2, device=DEV)
+    abi.mx_set_debug(True)
+    try:
+        for bad in ([0, 9, 4], [1, 2, 3]):
+            with pytest.raises(abi.MxError) as err:
+                abi.mx_expr_segmented_reduce(e, abi.MX_ADD, [x, x], dev(np.array(bad, dtype=np.int64)), 0.0, o)
+            assert err.value.status == abi.MX_ERR_SHAPE
+    finally:
+        abi.mx_set_debug(False)
+
+
+def test_segmented_reduce_full_size_sampled():
+    """The nested-step rows (65 536 rows, lengths log-uniform [1, 4096]) with the
+    body over two value arrays, checked on a sample of rows."""
+    prog, nin, out = GAUSS_DOT
+    say("expr segmented full size")
+    import workloads as W
+    rng = np.random.default_rng(0)
+    L = W.ragged_lengths(65536, 0, 4096)
+    off = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    n = int(off[-1])
+    gen = torch.Generator(device=DEV).manual_seed(1)
+    ins = [torch.rand(n, device=DEV, generator=gen) * 2 - 1 for _ in range(nin)]
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    o = torch.empty(len(L), device=DEV)
+    abi.mx_expr_segmented_reduce(e, abi.MX_ADD, ins, dev(off), 0.0, o)
+    got = host(o).astype(np.float64)
+    rows = np.concatenate([np.arange(64), rng.integers(0, len(L), 512), np.arange(len(L) - 64, len(L))])
+    host_in = [host(t) for t in ins]
+    for r in rows:
+        a, b = off[r], off[r + 1]
+        xs = [h[a:b] for h in host_in]
+        vals = O.expr_map(prog, out, *xs)
+        R = O.reduce(O.ADD, 0.0, vals)
+        S = np.abs(vals).sum()
+        tol = 4 * error_bound(prog, out, xs, U[abi.MX_F32]).sum() + 1e-4 * max(abs(R), S / np.sqrt(b - a))
+        assert abs(got[r] - R) <= tol, (r, got[r], R)
