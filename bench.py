@@ -53,15 +53,19 @@ TRAFFIC = {
     "gemm_nn": {"file": "gemm.hip", "bytes": 117551940,
                 "source": "e3de6e32d73e713b7af21202564fbc60d4736cd93458aa1021a82736a18a937c"},
     # k_seg_span, 65536 rows / 32.1 M values: 130.46 MB fetched + 0.26 MB written (1.01x algorithmic)
-    "seg_span": {"file": "segmented.hip", "bytes": 130721777,
-                 "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},
+    "seg_span": {"file": "segmented.hip", "bytes": 130706799,
+                 "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
     # mx_xvjp (generated from expr.hip) for exp(-(a-b)^2)*0.5 + a*b over 2^26 float32 pairs:
     # 536.87 MB fetched + 536.80 MB written (1.00x algorithmic)
-    "expr_vjp": {"file": "expr.hip", "bytes": 1073666406,
-                 "source": "d8fca25dfc5c6fd5b82c0000ec071f7961c30db0f15bb0ea9343b8be7378e3e5"},
+    "expr_vjp": {"file": "expr.hip", "bytes": 1073660327,
+                 "source": "3c4193914692d926aa8a723f32c8381bc8d66eab67fc9745764d8118e13838e2"},
+    # mx_xseg_add, same body over the nested step's 65 536 ragged rows (2 x 32.1 M values):
+    # 261.19 MB fetched + 0.26 MB written (1.01x algorithmic)
+    "expr_seg": {"file": "expr.hip", "bytes": 261456154,
+                 "source": "3c4193914692d926aa8a723f32c8381bc8d66eab67fc9745764d8118e13838e2"},
     # k_seg_broadcast: 1.61 MB fetched (offsets, gradients) + 128.83 MB written
-    "seg_broadcast": {"file": "segmented.hip", "bytes": 130438732,
-                      "source": "1ca012c13bcb31a45e51ee57c588c49fdf09536b18ece38c3a8d47394e14af3e"},
+    "seg_broadcast": {"file": "segmented.hip", "bytes": 130405516,
+                      "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
 }
 
 
@@ -234,9 +238,10 @@ def bench_nested(args):
         if n in bytes_:
             e["GB/s"] = round(gbs(bytes_[n], parts[n]), 1)
             e["frac_hbm"] = round(gbs(bytes_[n], parts[n]) / HBM_PEAK_GBS, 4)
-        if n in cold:
-            e["cold_us"] = round(cold[n] * 1e3, 2)
-            e["cold_GB/s"] = round(gbs(bytes_[n], cold[n]), 1)
+            if n in cold:
+                e["cold_us"] = round(cold[n] * 1e3, 2)
+                e["cold_GB/s"] = round(gbs(bytes_[n], cold[n]), 1)
+                e["cold_frac_hbm"] = round(gbs(bytes_[n], cold[n]) / HBM_PEAK_GBS, 4)
         else:
             tf = flops / (parts[n] * 1e-3) / 1e12
             e["TFLOP/s"] = round(tf, 2)
@@ -788,11 +793,11 @@ def bench_expr(args):
                   "segmented_rows": len(L), "segmented_values": nv,
                   "segmented_us": round(parts["segmented"] * 1e3, 1),
                   "segmented_GB/s": round(gbs(seg_bytes, parts["segmented"]), 1),
+                  "segmented_traffic_bytes": traffic_of("expr_seg"),
                   "segmented_via_temporary_us": round(parts["segmented_plain"] * 1e3, 1)},
         "plain": {"forward_us": round(pms * 1e3, 1), "fused_speedup": round(pms / parts["map_reduce"], 2)},
     }
     if not args.no_cpu_baseline:
-        import numpy as np
         import oracle as O
         log("expr: cpu baseline (oracle)")
         sample = n
