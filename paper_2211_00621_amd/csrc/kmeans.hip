@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
 
     float *ws = sums_all + wave * k * ldd;
     int *wc = counts_all + wave * k;
-    float4 *pub = reinterpret_cast<float4 *>(scr + wave * kScrFloats);  // [64 points][4 lane groups]
+    float4 *pub = reinterpret_cast<float4 *>(scr + wave * kScrFloats);  // [4 lane groups][64 points]
     int *lr = reinterpret_cast<int *>(pub + 4 * kPtsWave);  // [64 points] rank << 16 | label, or -1
 
     const int64_t nchunks = (a.n + kPtsWave - 1) / kPtsWave;
@@ -307,19 +307,19 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
         // every lane publishes (best, index, second, |x|^2 part) per point
 #pragma unroll
         for (int pi = 0; pi < 4; ++pi)
-            pub[(pi * 16 + l16) * 4 + g] = make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
+            pub[g * kPtsWave + pi * 16 + l16] = make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
         wave_sync();
         // ---- certify each label (lane = point); uncertified points are
         //      recomputed in binary64 by the whole wave, lanes over centroids
         {
             const int64_t p = p0 + lane;
             // merge the four lane groups in index order (lexicographic minimum)
-            float4 q = pub[lane * 4];
+            float4 q = pub[lane];
             float m1 = q.x, m2 = q.z, xx = q.w;
             int mj = __float_as_int(q.y);
 #pragma unroll
             for (int gg = 1; gg < 4; ++gg) {
-                q = pub[lane * 4 + gg];
+                q = pub[gg * kPtsWave + lane];
                 const int qj = __float_as_int(q.y);
                 const bool take = q.x < m1 || (q.x == m1 && qj < mj);
                 m2 = fminf(fmaxf(m1, q.x), fminf(m2, q.z));
@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 rmax = max(rmax, Rm[mi]);
             }
             const int d4 = (d + 3) & ~3;
-            float4 *junk = pub + lane * 4;
+            float4 *junk = pub + lane;  // slot (kc, h) of this lane: junk[(kc * 2 + h) * 64]
             for (int m = 0; __ballot(rmax >= m); ++m) {
                 // point blocks with nothing to add in this pass read one
                 // broadcast slot and write nothing
@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                             const int t = kc * 32 + 8 * g + 4 * h;
                             const bool live = Rm[mi] == m && (VX || t + 4 <= d4);
                             dst[mi][kc][h] = live ? reinterpret_cast<float4 *>(ws + Lm[mi] * ldd + t)
-                                                  : junk + kc * 2 + h;
+                                                  : junk + (kc * 2 + h) * kPtsWave;
                             sm[mi][kc][h] = *(act[mi] ? dst[mi][kc][h] : pub);
                         }
 #pragma unroll
