@@ -187,6 +187,16 @@ mx_status mx_fields_to_records(const void *const *soa_fields_host, int64_t n, in
 mx_status mx_compose_offsets(const int64_t *outer_dev, int64_t nouter, const int64_t *inner_dev,
                              int64_t *out_dev, hipStream_t stream);
 
+/* Regularity of one nesting level: succeeds when every row of the offsets
+ * array (device, nseg + 1 entries) has the same length, returned in
+ * *row_len_host (0 for nseg = 0); MX_ERR_SHAPE when the rows are ragged or the
+ * offsets decrease.  Tensors (rank <= 3) are nested sequences whose levels
+ * are all regular (the paper's Futhark backend accepts only those, Section
+ * 4.3); this is the check that turns a marshalled nesting into a tensor
+ * shape.  Synchronous: waits for the stream.  Keeps one 16-byte device
+ * buffer per device for the process. */
+mx_status mx_offsets_regular(const int64_t *offsets_dev, int64_t nseg, int64_t *row_len_host, hipStream_t stream);
+
 /* ======================================================================= */
 /* map / map2 (Appendix A)                                                  */
 /* ======================================================================= */

@@ -35,6 +35,7 @@ SIGNATURES = {
     "mx_records_to_fields": (c_status, [c_p, c_i64, c_int, c_size, c_pp, c_p]),
     "mx_fields_to_records": (c_status, [c_pp, c_i64, c_int, c_size, c_p, c_p]),
     "mx_compose_offsets": (c_status, [c_p, c_i64, c_p, c_p, c_p]),
+    "mx_offsets_regular": (c_status, [c_p, c_i64, c_p, c_p]),
     "mx_map": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_p, c_p]),
     "mx_map2": (c_status, [c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p]),
     "mx_reduce": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_p, c_p, c_size, c_p]),

@@ -171,6 +171,14 @@ def mx_compose_offsets(outer, inner, out, stream=None) -> None:
                                    _stream(stream)), "mx_compose_offsets")
 
 
+def mx_offsets_regular(offsets, stream=None) -> int:
+    """Common row length of a regular nesting level (MxError MX_ERR_SHAPE if ragged)."""
+    r = ctypes.c_int64()
+    _check(_L().mx_offsets_regular(_dptr(offsets), offsets.numel() - 1, ctypes.byref(r), _stream(stream)),
+           "mx_offsets_regular")
+    return r.value
+
+
 # ---------------------------------------------------------------- map / map2
 def mx_map(f: int, x, params, out, stream=None) -> None:
     dt = x.dtype

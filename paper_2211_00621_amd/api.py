@@ -138,6 +138,98 @@ def unmarshal_rows(r: Ragged):
     return rows
 
 
+@dataclass
+class Nested:
+    """A marshalled nested sequence of depth len(offsets) + 1: flat values in
+    depth-first order and one int64 offsets array per level, outermost first
+    (level l counts the sequences of level l + 1; the last level counts
+    values), all on the device."""
+    values: torch.Tensor
+    offsets: list
+
+    @property
+    def depth(self) -> int:
+        return len(self.offsets) + 1
+
+
+def marshal_nested(seq, depth: int, dtype=np.float32, device="cuda") -> Nested:
+    """Marshal a nested Python sequence (depth 1..4; depth 1 = [T]) of scalars:
+    the innermost sequences go through mx_marshal_rows (host gather, one copy,
+    device scan), the upper levels' lengths through mx_lengths_to_offsets."""
+    if depth < 1 or depth > 4:
+        raise ValueError("depth must be 1..4")
+    if depth == 1:
+        rows = [np.asarray(seq, dtype=dtype)]
+        return Nested(marshal_rows(rows, device).values, [])
+    lengths = [[] for _ in range(depth - 2)]   # per upper level, children counts
+    leaves = []
+
+    def walk(node, lvl):
+        if lvl == depth - 2:
+            leaves.append(np.asarray(node, dtype=dtype).ravel())
+        else:
+            lengths[lvl].append(len(node))
+            for child in node:
+                walk(child, lvl + 1)
+
+    top = list(seq)
+    for node in top:
+        walk(node, 0)
+    inner = marshal_rows(leaves, device) if leaves else Ragged(
+        torch.empty(0, dtype=torch.from_numpy(np.zeros(0, dtype)).dtype, device=device),
+        torch.zeros(1, dtype=torch.int64, device=device))
+    offsets = []
+    for lvl in range(depth - 2):
+        L = torch.from_numpy(np.asarray(lengths[lvl], dtype=np.int64)).to(device)
+        offsets.append(offsets_from_lengths(L) if L.numel() else torch.zeros(1, dtype=torch.int64,
+                                                                               device=device))
+    return Nested(inner.values, offsets + [inner.offsets])
+
+
+def unmarshal_nested(nd: Nested):
+    """Inverse of marshal_nested: nested lists whose innermost sequences are
+    numpy arrays (mx_unmarshal_rows copies the values back row by row)."""
+    if not nd.offsets:
+        return unmarshal_rows(Ragged(nd.values, torch.tensor([0, nd.values.numel()], dtype=torch.int64,
+                                                               device=nd.values.device)))[0]
+    rows = unmarshal_rows(Ragged(nd.values, nd.offsets[-1]))
+    levels = [o.cpu().numpy() for o in nd.offsets[:-1]]
+
+    def build(level, i):
+        lo, hi = int(levels[level][i]), int(levels[level][i + 1])
+        if level == len(levels) - 1:
+            return rows[lo:hi]
+        return [build(level + 1, j) for j in range(lo, hi)]
+
+    if not levels:
+        return rows
+    return [build(0, i) for i in range(len(levels[0]) - 1)]
+
+
+def flatten(nd: Nested, level: int = 0) -> Nested:
+    """flatten at nesting level `level` (0 = outermost): the sequences of that
+    level are concatenated, so level and level + 1 merge (mx_compose_offsets)."""
+    if level < 0 or level >= len(nd.offsets):
+        raise ValueError("no such level to flatten")
+    if level == 0:
+        return Nested(nd.values, nd.offsets[1:])
+    outer, inner = nd.offsets[level - 1], nd.offsets[level]
+    merged = torch.empty_like(outer)
+    abi.mx_compose_offsets(outer, inner, merged)
+    return Nested(nd.values, nd.offsets[:level - 1] + [merged] + nd.offsets[level + 1:])
+
+
+def to_tensor(nd: Nested) -> torch.Tensor:
+    """A regular nesting as a dense tensor of rank depth (the rows of every
+    level must have equal lengths: mx_offsets_regular)."""
+    shape = [nd.offsets[0].numel() - 1] if nd.offsets else []
+    for o in nd.offsets:
+        shape.append(abi.mx_offsets_regular(o))
+    if not nd.offsets:
+        shape = [nd.values.numel()]
+    return nd.values.view(*shape)
+
+
 def records_to_fields(aos: torch.Tensor):
     fields = [torch.empty(aos.shape[0], dtype=aos.dtype, device=aos.device) for _ in range(aos.shape[1])]
     abi.mx_records_to_fields(aos.contiguous(), fields)

@@ -10,6 +10,9 @@
 #include <thread>
 #include <vector>
 
+#include <climits>
+#include <mutex>
+
 #include "mx_internal.h"
 
 namespace mx {
@@ -63,6 +66,38 @@ __global__ void __launch_bounds__(NT) k_soa_to_aos4(FieldPtrs soa, int64_t n, fl
         aos[i] = make_float4(reinterpret_cast<const float *>(soa.p[0])[i], reinterpret_cast<const float *>(soa.p[1])[i],
                              reinterpret_cast<const float *>(soa.p[2])[i], reinterpret_cast<const float *>(soa.p[3])[i]);
 }
+
+// smallest and largest row length of an offsets array (integer atomics: the
+// result does not depend on the order)
+__global__ void __launch_bounds__(NT) k_row_len_range(const int64_t *__restrict__ off, int64_t nseg,
+                                                      long long *__restrict__ mm) {
+    long long lo = LLONG_MAX, hi = LLONG_MIN;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nseg; i += stride) {
+        const long long len = (long long)(off[i + 1] - off[i]);
+        lo = len < lo ? len : lo;
+        hi = len > hi ? len : hi;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const long long a = __shfl_xor(lo, o, kWave), b = __shfl_xor(hi, o, kWave);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicMin(&mm[0], lo);
+        atomicMax(&mm[1], hi);
+    }
+}
+
+__global__ void k_range_init(long long *mm) {
+    mm[0] = LLONG_MAX;
+    mm[1] = LLONG_MIN;
+}
+
+// one two-word device buffer per device for the range, kept for the process
+long long *g_range[64] = {};
+std::mutex g_range_mu;
 
 int grid_for(int64_t n, const DeviceInfo *d) {
     int64_t g = ceil_div(n > 0 ? n : 1, NT);
@@ -191,6 +226,34 @@ mx_status mx_records_to_fields(const void *aos_dev, int64_t n, int nfields, size
         hipLaunchKernelGGL(k_aos_to_soa<uint64_t>, dim3(grid), dim3(NT), 0, stream, (const uint64_t *)aos_dev, n,
                            nfields, fp);
     return last_launch("mx_records_to_fields");
+}
+
+mx_status mx_offsets_regular(const int64_t *offsets_dev, int64_t nseg, int64_t *row_len_host, hipStream_t stream) {
+    const char *who = "mx_offsets_regular";
+    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "%s: nseg < 0", who);
+    MX_REQUIRE(row_len_host, MX_ERR_INVALID, "%s: null output", who);
+    *row_len_host = 0;
+    if (nseg == 0) return MX_OK;
+    MX_REQUIRE(offsets_dev, MX_ERR_INVALID, "%s: null offsets", who);
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    long long *mm;
+    {
+        std::lock_guard<std::mutex> lk(g_range_mu);
+        if (!g_range[d->device]) MX_TRY_HIP(hipMalloc(&g_range[d->device], 2 * sizeof(long long)));
+        mm = g_range[d->device];
+    }
+    hipLaunchKernelGGL(k_range_init, dim3(1), dim3(1), 0, stream, mm);
+    if (mx_status st = last_launch(who)) return st;
+    hipLaunchKernelGGL(k_row_len_range, dim3(grid_for(nseg, d)), dim3(NT), 0, stream, offsets_dev, nseg, mm);
+    if (mx_status st = last_launch(who)) return st;
+    long long h[2];
+    MX_TRY_HIP(hipMemcpyAsync(h, mm, sizeof h, hipMemcpyDeviceToHost, stream));
+    MX_TRY_HIP(hipStreamSynchronize(stream));
+    MX_REQUIRE(h[0] >= 0, MX_ERR_SHAPE, "%s: offsets decrease (a row of length %lld)", who, h[0]);
+    MX_REQUIRE(h[0] == h[1], MX_ERR_SHAPE, "%s: irregular rows (lengths %lld .. %lld)", who, h[0], h[1]);
+    *row_len_host = h[0];
+    return MX_OK;
 }
 
 mx_status mx_fields_to_records(const void *const *soa_fields_host, int64_t n, int nfields,
