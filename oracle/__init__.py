@@ -90,6 +90,7 @@ def _declare(lib):
         "or_expr_map_f64": (None, [_p, _p, _int, _int, _p, _i64, _p]),
         "or_expr_map_foldl_f64": (_d, [_int, _d, _p, _p, _int, _int, _p, _i64]),
         "or_expr_vjp_f64": (None, [_p, _p, _int, _int, _int, _p, _i64, _p, _p, _p]),
+        "or_expr_loop_scatter_f64": (None, [_p, _p, _int, _int, _p, _i64, _p, _p, _i64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -442,3 +443,15 @@ def expr_vjp(prog, out_reg: int, inputs, gout=None, gscale=None):
     _L().or_expr_vjp_f64(_ptr(code), _ptr(imm), code.shape[0], X.shape[0], out_reg, _ptr(X), n,
                          _ptr(g) if g is not None else None, _ptr(s) if s is not None else None, _ptr(G))
     return [G[k] for k in range(X.shape[0])]
+
+
+def expr_loop_scatter(prog, out_reg: int, inputs, idx, out_init):
+    """loop over i ascending: out[idx[i]] = body(inputs at i) (binary64); out
+    starts as a copy of out_init; indices outside the output are skipped."""
+    code, imm = _prog(prog)
+    X, n = _inputs(inputs)
+    ix = _i64a(idx)
+    out = _f64(out_init).copy()
+    _L().or_expr_loop_scatter_f64(_ptr(code), _ptr(imm), code.shape[0], out_reg, _ptr(X), n, _ptr(ix), _ptr(out),
+                                  out.size)
+    return out

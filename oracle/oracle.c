@@ -689,3 +689,18 @@ void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin,
         for (int a = 0; a < nin; ++a) G[(int64_t)a * n + i] = gin[a];
     }
 }
+
+/* loop n (\i -> tensorSet out idx[i] (body x_i)): the CUDA backend's parallel
+ * loop over i (Section 4.1, `loop`), here run sequentially in ascending i.
+ * Slots outside [0, out_len) are not written. */
+void or_expr_loop_scatter_f64(const int32_t *code, const double *imm, int ninsn, int out_reg, const double *X,
+                              int64_t n, const int64_t *idx, double *out, int64_t out_len)
+{
+    double val[OR_X_MAXINSN];
+    int sa[OR_X_MAXINSN], sb[OR_X_MAXINSN], os;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = idx[i];
+        const double v = x_eval(code, imm, ninsn, out_reg, X, n, i, val, sa, sb, &os);
+        if (j >= 0 && j < out_len) out[j] = v;
+    }
+}

@@ -142,3 +142,18 @@ def test_vjp_matches_central_differences(seeded):
         dn[k] -= h
         fd = (O.expr_map(prog, 13, *up) - O.expr_map(prog, 13, *dn)) / (2 * h) * seed
         assert np.allclose(grads[k], fd, rtol=2e-6, atol=2e-7), k
+
+
+def test_loop_scatter_identity_and_permutation_and_skips():
+    a, b = RNG.uniform(-1, 1, 77), RNG.uniform(-1, 1, 77)
+    vals = O.expr_map(GAUSS_DOT, 2, a, b)
+    ident = np.arange(77)
+    assert np.array_equal(O.expr_loop_scatter(GAUSS_DOT, 2, [a, b], ident, np.zeros(77)), vals)
+    perm = RNG.permutation(100)[:77]
+    ref = np.full(100, -5.0)
+    ref[perm] = vals                          # numpy fancy-index assignment
+    assert np.array_equal(O.expr_loop_scatter(GAUSS_DOT, 2, [a, b], perm, np.full(100, -5.0)), ref)
+    idx = ident.copy()
+    idx[3], idx[5] = -1, 77                   # outside the output: not written
+    got = O.expr_loop_scatter(GAUSS_DOT, 2, [a, b], idx, np.full(77, 9.0))
+    assert got[3] == 9.0 and got[5] == 9.0 and np.array_equal(np.delete(got, [3, 5]), np.delete(vals, [3, 5]))
