@@ -536,6 +536,20 @@ mx_status mx_expr_map_reduce(mx_expr *e, mx_redop op, const void *const *in_dev,
 mx_status mx_expr_segmented_reduce(mx_expr *e, mx_redop op, const void *const *in_dev, const int64_t *offsets_dev,
                                    int64_t nseg, const void *ne_host, void *out_dev, hipStream_t stream);
 
+/* The parallel loop of the CUDA backend (Section 4.1, `loop n f` with f
+ * writing tensor slots): for every i < n, out[index[i]] = body(x_i).
+ * Iterations run in parallel in no particular order, so the result is defined
+ * when the indices are distinct -- the user's guarantee, as in the paper.
+ * index: n int64 device entries; out: out_len device elements, slots no index
+ * names keep their values; indices outside [0, out_len) are never written.
+ * In debug mode the library first checks, on the device, that every index is
+ * in range and no slot is written twice (MX_ERR_SHAPE otherwise; nothing is
+ * written then), using ws of mx_expr_loop_workspace_bytes(out_len) bytes
+ * (256-byte aligned; may be NULL outside debug mode), and synchronises. */
+size_t mx_expr_loop_workspace_bytes(int64_t out_len);
+mx_status mx_expr_loop_scatter(mx_expr *e, const void *const *in_dev, int64_t n, const int64_t *index_dev,
+                               void *out_dev, int64_t out_len, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Reverse mode: gin[k][i] = s_i * d body / d input k at element i, with
  * s_i = (gout ? gout[i] : 1) * (gscale ? *gscale : 1) (gout a device array of
  * n, gscale a device scalar; either may be NULL).  The adjoint flows back

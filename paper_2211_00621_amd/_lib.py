@@ -81,6 +81,8 @@ SIGNATURES = {
     "mx_expr_workspace_bytes": (c_size, [c_p, c_i64]),
     "mx_expr_map_reduce": (c_status, [c_p, c_enum, c_pp, c_i64, c_p, c_p, c_p, c_size, c_p]),
     "mx_expr_segmented_reduce": (c_status, [c_p, c_enum, c_pp, c_p, c_i64, c_p, c_p, c_p]),
+    "mx_expr_loop_workspace_bytes": (c_size, [c_i64]),
+    "mx_expr_loop_scatter": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_i64, c_p, c_size, c_p]),
     "mx_expr_vjp": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_pp, c_p]),
     "mx_graph_begin": (c_status, [c_p]),
     "mx_graph_end": (c_status, [c_p, c_pp]),

@@ -509,6 +509,15 @@ def mx_expr_segmented_reduce(e: Expr, op: int, inputs, offsets, ne, out, stream=
                                          ctypes.byref(nb), _dptr(out), _stream(stream)), "mx_expr_segmented_reduce")
 
 
+def mx_expr_loop_workspace_bytes(out_len: int) -> int:
+    return int(_L().mx_expr_loop_workspace_bytes(int(out_len)))
+
+
+def mx_expr_loop_scatter(e: Expr, inputs, index, out, ws=None, stream=None) -> None:
+    _check(_L().mx_expr_loop_scatter(e.handle, _ptr_list(inputs), index.numel(), _dptr(index), _dptr(out),
+                                     out.numel(), _dptr(ws), _nbytes(ws), _stream(stream)), "mx_expr_loop_scatter")
+
+
 def mx_expr_vjp(e: Expr, inputs, n: int, gout, gscale, grads, stream=None) -> None:
     _check(_L().mx_expr_vjp(e.handle, _ptr_list(inputs), int(n), _dptr(gout), _dptr(gscale), _ptr_list(grads),
                             _stream(stream)), "mx_expr_vjp")

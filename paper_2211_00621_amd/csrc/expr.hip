@@ -275,6 +275,18 @@ extern "C" __global__ void __launch_bounds__(NT) mx_xvjp(MX_PTRS, const T *__res
         if (g3) g3[i] = d3;
     }
 }
+
+// loop n (\i -> out[idx[i]] = body(x_i)): one slot per iteration, slots
+// outside [0, out_len) never written
+extern "C" __global__ void __launch_bounds__(NT) mx_xscatter(MX_PTRS, const long long *__restrict__ idx,
+                                                               T *__restrict__ out, long long n, long long out_len) {
+    const long long tid = (long long)blockIdx.x * NT + threadIdx.x, nt = (long long)gridDim.x * NT;
+    for (long long i = tid; i < n; i += nt) {
+        const long long j = idx[i];
+        const T v = mx_body_i(p0, p1, p2, p3, i);
+        if (j >= 0 && j < out_len) out[j] = v;
+    }
+}
 )";
     // fused map + reduce, one pair of kernels per operator
     const char *ops[4][3] = {{"add", "a + b", "(T)0"},
@@ -431,7 +443,7 @@ extern "C" __global__ void __launch_bounds__(NT) mx_xseg_)" + nm + R"((MX_PTRS, 
 // ---------------------------------------------------------------- compiled modules
 struct Compiled {
     hipModule_t mod = nullptr;
-    hipFunction_t map = nullptr, vjp = nullptr, red[4] = {}, fin[4] = {}, seg[4] = {};
+    hipFunction_t map = nullptr, vjp = nullptr, scatter = nullptr, red[4] = {}, fin[4] = {}, seg[4] = {};
 };
 
 std::mutex g_mu;
@@ -474,6 +486,7 @@ mx_status compile(const mx_expr &e, const Compiled **out) {
     MX_TRY_HIP(hipModuleLoadData(&c->mod, code.data()));
     MX_TRY_HIP(hipModuleGetFunction(&c->map, c->mod, "mx_xmap"));
     MX_TRY_HIP(hipModuleGetFunction(&c->vjp, c->mod, "mx_xvjp"));
+    MX_TRY_HIP(hipModuleGetFunction(&c->scatter, c->mod, "mx_xscatter"));
     const char *nm[4] = {"add", "mul", "min", "max"};
     for (int o = 0; o < 4; ++o) {
         MX_TRY_HIP(hipModuleGetFunction(&c->red[o], c->mod, (std::string("mx_xred_") + nm[o]).c_str()));
@@ -504,6 +517,22 @@ int64_t stream_blocks(int64_t n, int vw, int num_cus) {
 int64_t reduce_blocks(int64_t n, int vw) {
     const int64_t b = ceil_div(n > 0 ? n : 1, (int64_t)NT * vw * kGroupsPerIt);
     return b > kMaxRedBlocks ? kMaxRedBlocks : b;
+}
+
+// Debug mode of the indexed-write loop: every index in range and no slot hit
+// twice.  counts[j] = number of iterations writing slot j (integer atomics).
+__global__ void __launch_bounds__(NT) k_zero_u32(uint32_t *__restrict__ p, int64_t m) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += stride) p[i] = 0u;
+}
+__global__ void __launch_bounds__(NT) k_scatter_check(const long long *__restrict__ idx, int64_t n, int64_t out_len,
+                                                      uint32_t *__restrict__ counts, uint32_t *__restrict__ flag) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        const long long j = idx[i];
+        if (j < 0 || j >= out_len) atomicOr(flag, 1u);
+        else if (atomicAdd(&counts[j], 1u) != 0u) atomicOr(flag, 2u);
+    }
 }
 
 mx_status check_inputs(const mx_expr *e, const void *const *in_dev, int64_t n, const char *who) {
@@ -674,6 +703,49 @@ mx_status mx_expr_segmented_reduce(mx_expr *e, mx_redop op, const void *const *i
     double ne = *(const double *)ne_host;
     void *args[] = {&p[0], &p[1], &p[2], &p[3], &off, &ns, &rbi, &ne, &out_dev, &vec};
     return launch(c->seg[op], grid, stream, args, who, lds);
+}
+
+size_t mx_expr_loop_workspace_bytes(int64_t out_len) {
+    if (out_len < 0) return 0;
+    return align256(kCounterBytes + (size_t)out_len * sizeof(uint32_t));
+}
+
+mx_status mx_expr_loop_scatter(mx_expr *e, const void *const *in_dev, int64_t n, const int64_t *index_dev,
+                               void *out_dev, int64_t out_len, void *ws, size_t ws_bytes, hipStream_t stream) {
+    const char *who = "mx_expr_loop_scatter";
+    if (mx_status st = check_inputs(e, in_dev, n, who)) return st;
+    MX_REQUIRE(out_len >= 0, MX_ERR_SHAPE, "%s: out_len < 0", who);
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(index_dev && (out_dev || out_len == 0), MX_ERR_INVALID, "%s: null index or output", who);
+    const DeviceInfo *dv;
+    if (mx_status st = device_info(&dv)) return st;
+    const int grid = (int)stream_blocks(n, 1, dv->num_cus);
+    if (debug_mode()) {
+        const size_t need = mx_expr_loop_workspace_bytes(out_len);
+        MX_REQUIRE(ws && ws_bytes >= need && ((uintptr_t)ws & 255) == 0, MX_ERR_WORKSPACE,
+                   "%s: debug mode needs a workspace of %zu bytes, 256-byte aligned", who, need);
+        uint32_t *flag = (uint32_t *)ws, *counts = (uint32_t *)((char *)ws + kCounterBytes);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(NT), 0, stream, flag, (int64_t)1);
+        if (out_len > 0)
+            hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)stream_blocks(out_len, 1, dv->num_cus)), dim3(NT), 0,
+                               stream, counts, out_len);
+        hipLaunchKernelGGL(k_scatter_check, dim3(grid), dim3(NT), 0, stream, (const long long *)index_dev, n,
+                           out_len, counts, flag);
+        if (mx_status st = last_launch(who)) return st;
+        uint32_t h = 0;
+        MX_TRY_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, stream));
+        MX_TRY_HIP(hipStreamSynchronize(stream));
+        MX_REQUIRE(!(h & 1u), MX_ERR_SHAPE, "%s: an index is outside [0, %lld)", who, (long long)out_len);
+        MX_REQUIRE(!(h & 2u), MX_ERR_SHAPE, "%s: two iterations write the same slot", who);
+    }
+    const Compiled *c;
+    if (mx_status st = compile(*e, &c)) return st;
+    const void *p[kMaxIn] = {};
+    for (int k = 0; k < e->nin; ++k) p[k] = in_dev[k];
+    long long nn = n, ol = out_len;
+    const void *ix = index_dev;
+    void *args[] = {&p[0], &p[1], &p[2], &p[3], &ix, &out_dev, &nn, &ol};
+    return launch(c->scatter, grid, stream, args, who);
 }
 
 mx_status mx_expr_vjp(mx_expr *e, const void *const *in_dev, int64_t n, const void *gout_dev,

@@ -417,3 +417,61 @@ def test_segmented_reduce_full_size_sampled():
         S = np.abs(vals).sum()
         tol = 4 * error_bound(prog, out, xs, U[abi.MX_F32]).sum() + 1e-4 * max(abs(R), S / np.sqrt(b - a))
         assert abs(got[r] - R) <= tol, (r, got[r], R)
+
+
+# ---------------------------------------------------------------- parallel loop writing indexed slots
+@pytest.mark.parametrize("dtype", [abi.MX_F32, abi.MX_F64])
+@pytest.mark.parametrize("n,out_len", [(1, 1), (1000, 1000), (100003, 120011)])
+def test_loop_scatter_permutation(dtype, n, out_len):
+    say("expr loop scatter", dtype, n, out_len)
+    prog, nin, out = GAUSS_DOT
+    rng = np.random.default_rng(n)
+    xs = inputs(nin, n, dtype, 31)
+    idx = rng.permutation(out_len)[:n].astype(np.int64)
+    init = rng.uniform(-3, 3, out_len).astype(ND[dtype])
+    e = abi.mx_expr_create(prog, nin, out, dtype)
+    o = dev(init)
+    abi.mx_expr_loop_scatter(e, [dev(x) for x in xs], dev(idx), o)
+    got = host(o).astype(np.float64)
+    ref = O.expr_loop_scatter(prog, out, xs, idx, init)
+    untouched = np.ones(out_len, bool)
+    untouched[idx] = False
+    assert np.array_equal(got[untouched], init[untouched].astype(np.float64))
+    bound = 4 * error_bound(prog, out, xs, U[dtype])
+    assert np.all(np.abs(got[idx] - ref[idx]) <= bound)
+
+
+def test_loop_scatter_skips_out_of_range_and_debug_checks():
+    say("expr loop scatter checks")
+    prog, nin, out = GAUSS_DOT
+    n, out_len = 5000, 6000
+    xs = inputs(nin, n, abi.MX_F32, 8)
+    e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
+    ins = [dev(x) for x in xs]
+    idx = np.random.default_rng(2).permutation(out_len)[:n].astype(np.int64)
+    bad = idx.copy()
+    bad[[7, 99]] = [-4, out_len + 10]
+    init = np.full(out_len, 0.5, np.float32)
+    o = dev(init)
+    abi.mx_expr_loop_scatter(e, ins, dev(bad), o)     # accelerate mode: out-of-range iterations write nothing
+    ref = O.expr_loop_scatter(prog, out, xs, bad, init)
+    assert np.allclose(host(o), ref, rtol=1e-5, atol=1e-6)
+    ws = torch.zeros(abi.mx_expr_loop_workspace_bytes(out_len), dtype=torch.uint8, device=DEV)
+    dup = idx.copy()
+    dup[10] = dup[11]
+    abi.mx_set_debug(True)
+    try:
+        for wrong in (bad, dup):
+            o2 = dev(init)
+            with pytest.raises(abi.MxError) as err:
+                abi.mx_expr_loop_scatter(e, ins, dev(wrong), o2, ws)
+            assert err.value.status == abi.MX_ERR_SHAPE
+            assert np.array_equal(host(o2), init)          # nothing written
+        o3 = dev(init)
+        abi.mx_expr_loop_scatter(e, ins, dev(idx), o3, ws)  # disjoint and in range: runs
+        assert np.allclose(host(o3), O.expr_loop_scatter(prog, out, xs, idx, init), rtol=1e-5, atol=1e-6)
+        with pytest.raises(abi.MxError) as err:                # debug mode needs the workspace
+            abi.mx_expr_loop_scatter(e, ins, dev(idx), o3, None)
+        assert err.value.status == abi.MX_ERR_WORKSPACE
+    finally:
+        abi.mx_set_debug(False)
