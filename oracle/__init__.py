@@ -91,6 +91,9 @@ def _declare(lib):
         "or_expr_map_foldl_f64": (_d, [_int, _d, _p, _p, _int, _int, _p, _i64]),
         "or_expr_vjp_f64": (None, [_p, _p, _int, _int, _int, _p, _i64, _p, _p, _p]),
         "or_expr_loop_scatter_f64": (None, [_p, _p, _int, _int, _p, _i64, _p, _p, _i64]),
+        "or_histogram_u32": (None, [_p, _i64, _i64, _p]),
+        "or_stencil7": (None, [_p, _i64, _i64, _i64, _d, _d, _p]),
+        "or_mriq": (None, [_p, _p, _p, _p, _i64, _p, _p, _p, _i64, _p, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -455,3 +458,32 @@ def expr_loop_scatter(prog, out_reg: int, inputs, idx, out_init):
     _L().or_expr_loop_scatter_f64(_ptr(code), _ptr(imm), code.shape[0], out_reg, _ptr(X), n, _ptr(ix), _ptr(out),
                                   out.size)
     return out
+
+
+# ---------------------------------------------------------------- Parboil-shaped kernels (Table 1)
+def histogram(keys, nbins: int) -> np.ndarray:
+    """counts[k] = #{i : keys[i] = k} (int64); keys >= nbins fall in no bin."""
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint32))
+    counts = np.zeros(int(nbins), dtype=np.int64)
+    _L().or_histogram_u32(_ptr(k), k.size, int(nbins), _ptr(counts))
+    return counts
+
+
+def stencil7(grid, c0: float, c1: float) -> np.ndarray:
+    """One 7-point Jacobi sweep of a (nz, ny, nx) grid (binary64); boundary copied."""
+    g = _f64(grid)
+    nz, ny, nx = g.shape
+    out = np.empty_like(g)
+    _L().or_stencil7(_ptr(g), nx, ny, nz, float(c0), float(c1), _ptr(out))
+    return out
+
+
+def mriq(kx, ky, kz, phi, x, y, z):
+    """(Qr, Qi) of the mri-q computation (binary64)."""
+    kx, ky, kz, phi = _f64(kx), _f64(ky), _f64(kz), _f64(phi)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    qr = np.empty(x.size)
+    qi = np.empty(x.size)
+    _L().or_mriq(_ptr(kx), _ptr(ky), _ptr(kz), _ptr(phi), kx.size, _ptr(x), _ptr(y), _ptr(z), x.size, _ptr(qr),
+                 _ptr(qi))
+    return qr, qi

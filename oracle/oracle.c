@@ -704,3 +704,58 @@ void or_expr_loop_scatter_f64(const int32_t *code, const double *imm, int ninsn,
         if (j >= 0 && j < out_len) out[j] = v;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Kernels of the shapes in the paper's Parboil comparison (Table 1), on     */
+/* synthetic inputs (the datasets are not available).                        */
+/* ------------------------------------------------------------------------ */
+
+/* histo: reduce-by-key of keys into bins, counts[k] = #{i : keys[i] = k};
+ * keys >= nbins fall in no bin. */
+void or_histogram_u32(const uint32_t *keys, int64_t n, int64_t nbins, int64_t *counts)
+{
+    for (int64_t k = 0; k < nbins; ++k) counts[k] = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if ((int64_t)keys[i] < nbins) counts[keys[i]] = counts[keys[i]] + 1;
+}
+
+/* stencil: one Jacobi sweep of the 7-point stencil on an nx x ny x nz grid
+ * (x fastest): at interior points out = c1 * (sum of the six neighbours,
+ * added x-, x+, y-, y+, z-, z+) - c0 * centre; boundary points are copied. */
+void or_stencil7(const double *in, int64_t nx, int64_t ny, int64_t nz, double c0, double c1, double *out)
+{
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t i = (z * ny + y) * nx + x;
+                if (x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1) {
+                    out[i] = in[i];
+                    continue;
+                }
+                double s = in[i - 1];
+                s = s + in[i + 1];
+                s = s + in[i - nx];
+                s = s + in[i + nx];
+                s = s + in[i - nx * ny];
+                s = s + in[i + nx * ny];
+                out[i] = c1 * s - c0 * in[i];
+            }
+}
+
+/* mri-q: for every voxel x_i, with arg = 2 pi (kx_k x + ky_k y + kz_k z),
+ * Qr_i = sum_k phi_k cos(arg), Qi_i = sum_k phi_k sin(arg), k ascending. */
+void or_mriq(const double *kx, const double *ky, const double *kz, const double *phi, int64_t nk,
+             const double *x, const double *y, const double *z, int64_t nx, double *qr, double *qi)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t i = 0; i < nx; ++i) {
+        double ar = 0.0, ai = 0.0;
+        for (int64_t k = 0; k < nk; ++k) {
+            const double arg = two_pi * (kx[k] * x[i] + ky[k] * y[i] + kz[k] * z[i]);
+            ar = ar + phi[k] * cos(arg);
+            ai = ai + phi[k] * sin(arg);
+        }
+        qr[i] = ar;
+        qi[i] = ai;
+    }
+}

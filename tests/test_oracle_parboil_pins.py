@@ -1,0 +1,61 @@
+"""Pins for the oracle's Parboil-shaped kernels (histogram, 7-point stencil,
+mri-q): library routines on the same data (numpy.bincount, scipy.ndimage
+convolution, a numpy matrix formulation of mri-q), closed forms on constant
+and affine grids, and symmetry invariants."""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle as O
+
+RNG = np.random.default_rng(23)
+
+
+@pytest.mark.parametrize("nbins", [1, 7, 4096])
+def test_histogram_is_bincount(nbins):
+    keys = RNG.integers(0, nbins + 5, 20000).astype(np.uint32)   # some keys past the last bin
+    got = O.histogram(keys, nbins)
+    ref = np.bincount(keys[keys < nbins], minlength=nbins)
+    assert np.array_equal(got, ref)
+    assert got.sum() == int((keys < nbins).sum())
+    assert np.array_equal(O.histogram(keys[:0], nbins), np.zeros(nbins, np.int64))
+
+
+def test_stencil_constant_and_affine_grids_and_boundary():
+    c0, c1 = 0.5, 0.25
+    g = np.full((5, 6, 7), 3.0)
+    out = O.stencil7(g, c0, c1)
+    assert np.all(out[1:-1, 1:-1, 1:-1] == (6 * c1 - c0) * 3.0)
+    z, y, x = np.meshgrid(np.arange(5.0), np.arange(6.0), np.arange(7.0), indexing="ij")
+    f = 2 * x - 3 * y + 5 * z + 1
+    out = O.stencil7(f, c0, c1)
+    assert np.array_equal(out[1:-1, 1:-1, 1:-1], ((6 * c1 - c0) * f)[1:-1, 1:-1, 1:-1])
+    for sl in (np.s_[0], np.s_[-1], np.s_[:, 0], np.s_[:, -1], np.s_[:, :, 0], np.s_[:, :, -1]):
+        assert np.array_equal(out[sl], f[sl])
+
+
+def test_stencil_is_a_convolution():
+    g = RNG.uniform(-1, 1, (6, 9, 11))
+    c0, c1 = 0.7, 0.15
+    kern = np.zeros((3, 3, 3))
+    kern[1, 1, 1] = -c0
+    for d in ((0, 1, 1), (2, 1, 1), (1, 0, 1), (1, 2, 1), (1, 1, 0), (1, 1, 2)):
+        kern[d] = c1
+    ref = ndimage.convolve(g, kern, mode="constant")
+    out = O.stencil7(g, c0, c1)
+    assert np.allclose(out[1:-1, 1:-1, 1:-1], ref[1:-1, 1:-1, 1:-1], rtol=1e-14, atol=1e-14)
+
+
+def test_mriq_matches_matrix_form_and_symmetries():
+    nk, nx = 64, 50
+    kx, ky, kz = (RNG.uniform(-0.5, 0.5, nk) for _ in range(3))
+    phi = RNG.uniform(0, 1, nk)
+    x, y, z = (RNG.uniform(-1, 1, nx) for _ in range(3))
+    qr, qi = O.mriq(kx, ky, kz, phi, x, y, z)
+    arg = 2 * np.pi * (np.outer(x, kx) + np.outer(y, ky) + np.outer(z, kz))
+    assert np.allclose(qr, np.cos(arg) @ phi, rtol=1e-12, atol=1e-12)
+    assert np.allclose(qi, np.sin(arg) @ phi, rtol=1e-12, atol=1e-12)
+    qr2, qi2 = O.mriq(kx, ky, kz, phi, -x, -y, -z)
+    assert np.allclose(qr2, qr, rtol=1e-12, atol=1e-12) and np.allclose(qi2, -qi, rtol=1e-12, atol=1e-12)
+    qr0, qi0 = O.mriq(np.zeros(nk), np.zeros(nk), np.zeros(nk), phi, x, y, z)
+    assert np.allclose(qr0, phi.sum(), rtol=1e-14) and np.all(qi0 == 0)
