@@ -16,7 +16,7 @@ ragged value (forward), one write per value (reverse), one multiply-add per
 
 Other workloads (--workload): dot (fused map2+reduce vs plain), nbody, kmeans,
 batched, expr (a user-defined map body, fused map+reduce and reverse mode vs
-the same body from the fixed operators).  Prints one JSON line on stdout;
+the same body from the fixed operators), parboil (histogram, stencil, mri-q).  Prints one JSON line on stdout;
 progress goes to stderr.
 """
 from __future__ import annotations
@@ -812,6 +812,106 @@ def bench_expr(args):
     return line
 
 
+# ============================================================ Parboil-shaped kernels
+# VALU issue slots per (voxel, sample) pair in the inner loop of k_mriq
+# (gfx950 ISA: 89 per sample for the thread's two voxels; sincospi is a
+# polynomial on the VALU, no transcendental unit).
+MRIQ_VALU_PER_PAIR = 44.5
+
+
+def bench_parboil(args):
+    import torch
+    from paper_2211_00621_amd import abi
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(0)
+    # histo: 2^24 keys of an image-like (concentrated) distribution
+    nkeys = 1 << 24
+    keys_np = {nb: np.clip(np.rint(rng.normal(nb * 0.4, nb / 20, nkeys)), 0, nb - 1).astype(np.uint32)
+               for nb in (4096, 1 << 20)}
+    keys = {nb: torch.from_numpy(k).to(dev).view(torch.int32) for nb, k in keys_np.items()}
+    counts = {nb: torch.empty(nb, dtype=torch.int32, device=dev) for nb in keys}
+    # stencil: 64 planes of 512 x 512
+    nz, ny, nx = 64, 512, 512
+    g0 = torch.rand((nz, ny, nx), device=dev) * 2 - 1
+    g1 = torch.empty_like(g0)
+    # mri-q: 2048 samples, 2^18 voxels
+    nk, nv = 2048, 1 << 18
+    kxyz = [torch.rand(nk, device=dev) * 32 - 16 for _ in range(3)]
+    phi = torch.rand(nk, device=dev)
+    xyz = [torch.rand(nv, device=dev) - 0.5 for _ in range(3)]
+    qr, qi = torch.empty(nv, device=dev), torch.empty(nv, device=dev)
+
+    def histo_small():
+        abi.mx_histogram_u32(keys[4096], 4096, counts[4096])
+
+    def histo_large():
+        abi.mx_histogram_u32(keys[1 << 20], 1 << 20, counts[1 << 20])
+
+    def stencil():
+        abi.mx_stencil7_f32(g0, g1, 1.0 / 6.0, 0.125)
+
+    def mriq():
+        abi.mx_mriq_f32(*kxyz, phi, *xyz, qr, qi)
+
+    def step():
+        histo_small()
+        histo_large()
+        stencil()
+        mriq()
+
+    parts = {nm: per_launch_ms(f, reps=max(args.steps, 5), warmup=args.warmup)
+             for nm, f in (("histo_4096_bins", histo_small), ("histo_2^20_bins", histo_large),
+                           ("stencil", stencil), ("mriq", mriq))}
+    ms = timed_on(torch.cuda.current_stream(), step, args.steps, args.warmup)
+    pts = nx * ny * nz
+    pairs = nk * nv
+    elems = 2 * nkeys + pts + pairs
+    mriq_peak = LANE_OPS_PER_S / MRIQ_VALU_PER_PAIR
+    mriq_rate = pairs / (parts["mriq"] * 1e-3)
+    log(f"parboil: step {ms:.3f} ms; " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in parts.items()))
+    line = {
+        "metric": METRIC, "value": elems / (ms * 1e-3), "unit": "elem/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Parboil-shaped kernels on synthetic data: histogram of 2^24 concentrated keys into "
+                               "4096 and 2^20 bins, one 7-point stencil sweep of 512x512x64 float32, mri-q with "
+                               "2048 samples x 2^18 voxels", "keys": nkeys, "grid": [nz, ny, nx],
+                   "mriq": [nk, nv], "elements_per_step": elems},
+        "roofline": {"bound": "alu", "kernel": "k_mriq", "achieved": round(mriq_rate / 1e9, 1),
+                     "peak": round(mriq_peak / 1e9, 1), "unit": "Gpair/s", "frac": round(mriq_rate / mriq_peak, 4),
+                     "traffic": None,
+                     "peak_basis": f"256 CU x 64 lanes x 2.4 GHz / {MRIQ_VALU_PER_PAIR} VALU issues per pair"},
+        "parts": {
+            "histo_4096_bins": {"us": round(parts["histo_4096_bins"] * 1e3, 1),
+                                "GB/s": round(gbs(4 * nkeys, parts["histo_4096_bins"]), 1)},
+            "histo_2^20_bins": {"us": round(parts["histo_2^20_bins"] * 1e3, 1),
+                                "GB/s": round(gbs(4 * nkeys, parts["histo_2^20_bins"]), 1)},
+            "stencil": {"us": round(parts["stencil"] * 1e3, 1), "GB/s": round(gbs(8 * pts, parts["stencil"]), 1),
+                        "frac_hbm": round(gbs(8 * pts, parts["stencil"]) / HBM_PEAK_GBS, 4)},
+            "mriq": {"us": round(parts["mriq"] * 1e3, 1), "Gpair/s": round(mriq_rate / 1e9, 1)},
+        },
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("parboil: cpu baseline (oracle)")
+        sample_v = 2048
+        g0n = g0.cpu().numpy()
+        kn = [t.cpu().numpy() for t in kxyz]
+        xn = [t[:sample_v].cpu().numpy() for t in xyz]
+        t0 = time.perf_counter()
+        for nb, k in keys_np.items():
+            O.histogram(k, nb)
+        O.stencil7(g0n, 1.0 / 6.0, 0.125)
+        O.mriq(*kn, phi.cpu().numpy(), *xn)
+        secs = time.perf_counter() - t0
+        n_done = 2 * nkeys + pts + nk * sample_v
+        line["cpu_baseline"] = {"value": n_done / secs, "unit": "elem/s", "cores": cpu_threads(), "kind": "oracle",
+                                "seconds": round(secs, 2),
+                                "sample": f"both histograms and the stencil sweep in full, mri-q for the first "
+                                          f"{sample_v} of the 2^18 voxels"}
+    return line
+
+
 def copy_calibration(mib):
     import torch
     from paper_2211_00621_amd import abi
@@ -825,7 +925,7 @@ def copy_calibration(mib):
 
 
 WORKLOADS = {"nested": bench_nested, "dot": bench_dot, "nbody": bench_nbody, "kmeans": bench_kmeans,
-             "batched": bench_batched, "expr": bench_expr}
+             "batched": bench_batched, "expr": bench_expr, "parboil": bench_parboil}
 
 
 def main(argv=None):

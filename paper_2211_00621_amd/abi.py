@@ -436,6 +436,23 @@ def mx_batch_autotune(plan: BatchPlan, A, B, out, gout, gA, gB, ws, cache_path: 
 
 
 # ---------------------------------------------------------------- graphs
+# ---------------------------------------------------------------- Parboil-shaped kernels
+def mx_histogram_u32(keys, nbins: int, counts, stream=None) -> None:
+    _check(_L().mx_histogram_u32(_dptr(keys), keys.numel(), int(nbins), _dptr(counts), _stream(stream)),
+           "mx_histogram_u32")
+
+
+def mx_stencil7_f32(grid_in, grid_out, c0: float, c1: float, stream=None) -> None:
+    nz, ny, nx = grid_in.shape
+    _check(_L().mx_stencil7_f32(_dptr(grid_in), _dptr(grid_out), nx, ny, nz, float(c0), float(c1), _stream(stream)),
+           "mx_stencil7_f32")
+
+
+def mx_mriq_f32(kx, ky, kz, phi, x, y, z, qr, qi, stream=None) -> None:
+    _check(_L().mx_mriq_f32(_dptr(kx), _dptr(ky), _dptr(kz), _dptr(phi), kx.numel(), _dptr(x), _dptr(y), _dptr(z),
+                            x.numel(), _dptr(qr), _dptr(qi), _stream(stream)), "mx_mriq_f32")
+
+
 # ---------------------------------------------------------------- user-defined map bodies
 class XInsn(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("dst", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),

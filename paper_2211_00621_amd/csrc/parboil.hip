@@ -1,0 +1,229 @@
+// Kernels of the shapes in the paper's Parboil comparison (Table 1): the
+// histogram reduce-by-key (histo), the neighbour-access map of a 7-point
+// stencil sweep (stencil), and the trigonometric per-output reduction over
+// samples (mri-q).  The paper's Futhark programs for these are compiled
+// whole; here each is one gfx950 kernel family behind the C ABI.
+#include <algorithm>
+#include <cmath>
+
+#include "mx_internal.h"
+
+namespace mx {
+namespace {
+
+constexpr int NT = 256;
+constexpr int64_t kHistLdsBins = 32768;  // 128 KiB of LDS counters per block
+
+__global__ void __launch_bounds__(NT) k_zero32(uint32_t *__restrict__ p, int64_t m) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += stride) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- histo
+// Few bins: each block counts its keys into a private LDS histogram (LDS
+// integer atomics), then adds its non-zero bins to the global counts.
+// Integer additions commute, so the counts do not depend on the order.
+__global__ void __launch_bounds__(NT) k_hist_lds(const uint32_t *__restrict__ keys, int64_t n, int nbins,
+                                                 uint32_t *__restrict__ counts, int vec) {
+    extern __shared__ uint32_t hist[];
+    for (int b = threadIdx.x; b < nbins; b += NT) hist[b] = 0u;
+    __syncthreads();
+    const int64_t tid = (int64_t)blockIdx.x * NT + threadIdx.x, nt = (int64_t)gridDim.x * NT;
+    const uint32_t nb = (uint32_t)nbins;
+    int64_t done = 0;
+    if (vec) {
+        const int64_t nv = n / 4;
+        const uint4 *kv = reinterpret_cast<const uint4 *>(keys);
+        for (int64_t j = tid; j < nv; j += nt) {
+            const uint4 k = kv[j];
+            if (k.x < nb) atomicAdd(&hist[k.x], 1u);
+            if (k.y < nb) atomicAdd(&hist[k.y], 1u);
+            if (k.z < nb) atomicAdd(&hist[k.z], 1u);
+            if (k.w < nb) atomicAdd(&hist[k.w], 1u);
+        }
+        done = nv * 4;
+    }
+    for (int64_t i = done + tid; i < n; i += nt) {
+        const uint32_t k = keys[i];
+        if (k < nb) atomicAdd(&hist[k], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += NT)
+        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
+// Many bins: integer atomics on the global counts.
+__global__ void __launch_bounds__(NT) k_hist_global(const uint32_t *__restrict__ keys, int64_t n, int64_t nbins,
+                                                    uint32_t *__restrict__ counts, int vec) {
+    const int64_t tid = (int64_t)blockIdx.x * NT + threadIdx.x, nt = (int64_t)gridDim.x * NT;
+    int64_t done = 0;
+    if (vec) {
+        const int64_t nv = n / 4;
+        const uint4 *kv = reinterpret_cast<const uint4 *>(keys);
+        for (int64_t j = tid; j < nv; j += nt) {
+            const uint4 k = kv[j];
+            if ((int64_t)k.x < nbins) atomicAdd(&counts[k.x], 1u);
+            if ((int64_t)k.y < nbins) atomicAdd(&counts[k.y], 1u);
+            if ((int64_t)k.z < nbins) atomicAdd(&counts[k.z], 1u);
+            if ((int64_t)k.w < nbins) atomicAdd(&counts[k.w], 1u);
+        }
+        done = nv * 4;
+    }
+    for (int64_t i = done + tid; i < n; i += nt) {
+        const uint32_t k = keys[i];
+        if ((int64_t)k < nbins) atomicAdd(&counts[k], 1u);
+    }
+}
+
+// ---------------------------------------------------------------- stencil
+// One Jacobi sweep of the 7-point stencil.  A thread owns one (x, y) column
+// and marches up a slab of kSlab planes keeping the z - 1, z and z + 1 values
+// in registers, so each input value is read from HBM about once; the four
+// in-plane neighbours are cache hits of the neighbouring lanes' loads.  The
+// six neighbours are added x-, x+, y-, y+, z-, z+ and every operation is
+// rounded on its own.  Boundary points are copied.
+constexpr int kSlab = 16;
+
+__global__ void __launch_bounds__(NT) k_stencil7(const float *__restrict__ in, float *__restrict__ out, int64_t nx,
+                                                 int64_t ny, int64_t nz, float c0, float c1) {
+#pragma clang fp contract(off)
+    const int64_t col = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (col >= nx * ny) return;
+    const int64_t y = col / nx, x = col - y * nx;
+    const int64_t z0 = (int64_t)blockIdx.y * kSlab;
+    const int64_t z1 = z0 + kSlab < nz ? z0 + kSlab : nz;
+    const int64_t plane = nx * ny;
+    const bool edge = x == 0 || y == 0 || x == nx - 1 || y == ny - 1;
+    const float *p = in + col;
+    float below = z0 > 0 ? p[(z0 - 1) * plane] : 0.f;
+    float cur = p[z0 * plane];
+    for (int64_t z = z0; z < z1; ++z) {
+        const float above = z + 1 < nz ? p[(z + 1) * plane] : 0.f;
+        const int64_t i = z * plane + col;
+        float r;
+        if (edge || z == 0 || z == nz - 1) {
+            r = cur;
+        } else {
+            float s = in[i - 1];
+            s = s + in[i + 1];
+            s = s + in[i - nx];
+            s = s + in[i + nx];
+            s = s + below;
+            s = s + above;
+            r = c1 * s - c0 * cur;
+        }
+        out[i] = r;
+        below = cur;
+        cur = above;
+    }
+}
+
+// ---------------------------------------------------------------- mri-q
+// Qr_i = sum_k phi_k cos(2 pi t_ik), Qi_i = sum_k phi_k sin(2 pi t_ik) with
+// t_ik = kx_k x_i + ky_k y_i + kz_k z_i.  The samples go through LDS in tiles
+// (every lane reads the same sample: a broadcast); each thread owns two
+// voxels; sin and cos of 2 pi t come from sincospi(2t) (2t is exact), so the
+// angle is never rounded after the multiplication by pi.
+constexpr int kMriTile = 1024;
+
+__global__ void __launch_bounds__(NT) k_mriq(const float *__restrict__ kx, const float *__restrict__ ky,
+                                             const float *__restrict__ kz, const float *__restrict__ phi,
+                                             int64_t nk, const float *__restrict__ x, const float *__restrict__ y,
+                                             const float *__restrict__ z, int64_t nv, float *__restrict__ qr,
+                                             float *__restrict__ qi) {
+    __shared__ float4 ks[kMriTile];
+    const int64_t v0 = (int64_t)blockIdx.x * NT * 2 + threadIdx.x, v1 = v0 + NT;
+    const bool h0 = v0 < nv, h1 = v1 < nv;
+    const float x0 = h0 ? x[v0] : 0.f, y0 = h0 ? y[v0] : 0.f, z0 = h0 ? z[v0] : 0.f;
+    const float x1 = h1 ? x[v1] : 0.f, y1 = h1 ? y[v1] : 0.f, z1 = h1 ? z[v1] : 0.f;
+    float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
+    for (int64_t k0 = 0; k0 < nk; k0 += kMriTile) {
+        const int cnt = (int)(nk - k0 < kMriTile ? nk - k0 : kMriTile);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT)
+            ks[j] = make_float4(kx[k0 + j], ky[k0 + j], kz[k0 + j], phi[k0 + j]);
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const float4 s = ks[j];
+            const float t0 = s.x * x0 + s.y * y0 + s.z * z0;
+            const float t1 = s.x * x1 + s.y * y1 + s.z * z1;
+            float sn0, cs0, sn1, cs1;
+            sincospif(t0 + t0, &sn0, &cs0);
+            sincospif(t1 + t1, &sn1, &cs1);
+            r0 += s.w * cs0;
+            i0 += s.w * sn0;
+            r1 += s.w * cs1;
+            i1 += s.w * sn1;
+        }
+    }
+    if (h0) { qr[v0] = r0; qi[v0] = i0; }
+    if (h1) { qr[v1] = r1; qi[v1] = i1; }
+}
+
+}  // namespace
+}  // namespace mx
+
+using namespace mx;
+
+extern "C" {
+
+mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, uint32_t *counts_dev,
+                           hipStream_t stream) {
+    const char *who = "mx_histogram_u32";
+    MX_REQUIRE(n >= 0 && n < (int64_t)0xffffffff, MX_ERR_SHAPE, "%s: need 0 <= n < 2^32 - 1", who);
+    MX_REQUIRE(nbins >= 1 && nbins <= ((int64_t)1 << 32), MX_ERR_SHAPE, "%s: need 1 <= nbins <= 2^32", who);
+    MX_REQUIRE(counts_dev && (keys_dev || n == 0), MX_ERR_INVALID, "%s: null pointer", who);
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    const int64_t zb = ceil_div(nbins, NT);
+    hipLaunchKernelGGL(k_zero32, dim3((unsigned)(zb < d->num_cus * 8 ? zb : d->num_cus * 8)), dim3(NT), 0, stream,
+                       counts_dev, nbins);
+    if (mx_status st = last_launch(who)) return st;
+    if (n == 0) return MX_OK;
+    const int vec = ((uintptr_t)keys_dev & 15) == 0;
+    if (nbins <= kHistLdsBins && (size_t)nbins * 4 <= (size_t)d->lds_bytes) {
+        // as many blocks as fit the CUs' LDS (at most eight per CU); each
+        // block's flush adds at most nbins global atomics
+        const int64_t per_cu = std::min<int64_t>(8, std::max<int64_t>(1, (int64_t)d->lds_bytes / (nbins * 4)));
+        int64_t grid = ceil_div(n, (int64_t)NT * 64);
+        if (grid > d->num_cus * per_cu) grid = d->num_cus * per_cu;
+        hipLaunchKernelGGL(k_hist_lds, dim3((unsigned)grid), dim3(NT), (size_t)nbins * 4, stream, keys_dev, n,
+                           (int)nbins, counts_dev, vec);
+    } else {
+        int64_t grid = ceil_div(n, (int64_t)NT * 16);
+        if (grid > d->num_cus * 8) grid = d->num_cus * 8;
+        hipLaunchKernelGGL(k_hist_global, dim3((unsigned)grid), dim3(NT), 0, stream, keys_dev, n, nbins,
+                           counts_dev, vec);
+    }
+    return last_launch(who);
+}
+
+mx_status mx_stencil7_f32(const float *in_dev, float *out_dev, int64_t nx, int64_t ny, int64_t nz, float c0,
+                          float c1, hipStream_t stream) {
+    const char *who = "mx_stencil7_f32";
+    MX_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, MX_ERR_SHAPE, "%s: empty grid", who);
+    MX_REQUIRE(nx * ny <= ((int64_t)0x7fffffff) * NT, MX_ERR_SHAPE, "%s: plane too large", who);
+    MX_REQUIRE(in_dev && out_dev && in_dev != out_dev, MX_ERR_INVALID, "%s: null or aliased grids", who);
+    const int64_t gx = ceil_div(nx * ny, NT), gz = ceil_div(nz, kSlab);
+    MX_REQUIRE(gz <= 65535, MX_ERR_SHAPE, "%s: nz too large", who);
+    hipLaunchKernelGGL(k_stencil7, dim3((unsigned)gx, (unsigned)gz), dim3(NT), 0, stream, in_dev, out_dev, nx, ny,
+                       nz, c0, c1);
+    return last_launch(who);
+}
+
+mx_status mx_mriq_f32(const float *kx_dev, const float *ky_dev, const float *kz_dev, const float *phi_dev,
+                      int64_t nk, const float *x_dev, const float *y_dev, const float *z_dev, int64_t nv,
+                      float *qr_dev, float *qi_dev, hipStream_t stream) {
+    const char *who = "mx_mriq_f32";
+    MX_REQUIRE(nk >= 0 && nv >= 0, MX_ERR_SHAPE, "%s: negative size", who);
+    if (nv == 0) return MX_OK;
+    MX_REQUIRE(x_dev && y_dev && z_dev && qr_dev && qi_dev, MX_ERR_INVALID, "%s: null voxel array", who);
+    MX_REQUIRE(nk == 0 || (kx_dev && ky_dev && kz_dev && phi_dev), MX_ERR_INVALID, "%s: null sample array", who);
+    const int64_t grid = ceil_div(nv, (int64_t)NT * 2);
+    MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "%s: too many voxels", who);
+    hipLaunchKernelGGL(k_mriq, dim3((unsigned)grid), dim3(NT), 0, stream, kx_dev, ky_dev, kz_dev, phi_dev, nk, x_dev,
+                       y_dev, z_dev, nv, qr_dev, qi_dev);
+    return last_launch(who);
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+"""GPU parity of the Parboil-shaped kernels against the oracle: histogram
+counts bit-exact (LDS and global paths, skewed and uniform keys, keys past the
+last bin, misaligned and empty inputs, 2^24 keys); one 7-point stencil sweep
+within a bound derived from its six additions and three roundings; mri-q
+within a bound from the rounding of t, the sin / cos error (2 ulp) and the
+FP32 sums.  Inputs are seeded synthetic stand-ins for the Parboil datasets."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from parity import say
+
+import paper_2211_00621_amd as mx  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+abi, api = mx.abi, mx.api
+DEV = "cuda"
+U32 = 2.0 ** -24
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def keys_for(kind, n, nbins, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        k = rng.integers(0, nbins + max(1, nbins // 50), n)        # about 2 % past the last bin
+    else:                                                           # image-like: concentrated
+        k = np.clip(np.rint(rng.normal(nbins * 0.4, max(1.0, nbins / 20), n)), 0, 2 ** 32 - 1)
+    return k.astype(np.uint32)
+
+
+@pytest.mark.parametrize("nbins", [1, 7, 4096, 32768, 32769, 1 << 20])
+@pytest.mark.parametrize("kind", ["uniform", "skewed"])
+@pytest.mark.parametrize("n", [0, 3, 100001])
+def test_histogram(nbins, kind, n):
+    say("histogram", nbins, kind, n)
+    keys = keys_for(kind, n, nbins, nbins + n)
+    counts = torch.full((nbins,), 7, dtype=torch.int32, device=DEV)   # overwritten, not added to
+    abi.mx_histogram_u32(dev(keys).view(torch.int32), nbins, counts)
+    assert np.array_equal(host(counts).astype(np.int64), O.histogram(keys, nbins))
+
+
+@pytest.mark.parametrize("nbins", [256, 1 << 20])
+def test_histogram_misaligned_and_large(nbins):
+    say("histogram large", nbins)
+    n = (1 << 24) + 3
+    keys = keys_for("skewed", n + 1, nbins, 5)
+    counts = torch.empty(nbins, dtype=torch.int32, device=DEV)
+    abi.mx_histogram_u32(dev(keys).view(torch.int32)[1:], nbins, counts)
+    assert np.array_equal(host(counts).astype(np.int64), O.histogram(keys[1:], nbins))
+
+
+def stencil_bound(g, c0, c1):
+    """8 u (|c1| sum|neighbours| + |c0| |centre|) at interior points."""
+    return 8 * U32 * O.stencil7(np.abs(g.astype(np.float64)), -abs(c0), abs(c1))
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (7, 9, 11), (40, 64, 64), (17, 1, 5), (64, 512, 512)])
+def test_stencil(shape):
+    say("stencil", shape)
+    rng = np.random.default_rng(sum(shape))
+    g = rng.uniform(-1, 1, shape).astype(np.float32)
+    c0, c1 = np.float32(1.0 / 6.0), np.float32(0.125)
+    out = torch.full(shape, np.nan, device=DEV)
+    abi.mx_stencil7_f32(dev(g), out, float(c0), float(c1))
+    got = host(out).astype(np.float64)
+    ref = O.stencil7(g, float(c0), float(c1))
+    interior = np.zeros(shape, bool)
+    if min(shape) >= 3:
+        interior[1:-1, 1:-1, 1:-1] = True
+    assert np.array_equal(got[~interior], g.astype(np.float64)[~interior])
+    bound = stencil_bound(g, float(c0), float(c1))
+    assert np.all(np.abs(got - ref)[interior] <= bound[interior])
+
+
+def mriq_inputs(nk, nv, seed):
+    rng = np.random.default_rng(seed)
+    k = [rng.uniform(-16, 16, nk).astype(np.float32) for _ in range(3)]
+    phi = rng.uniform(0, 1, nk).astype(np.float32)
+    x = [rng.uniform(-0.5, 0.5, nv).astype(np.float32) for _ in range(3)]
+    return k, phi, x
+
+
+def mriq_bound(k, phi, x, idx):
+    """sum_k phi_k (2 pi 3u T_ik + 4u) + nk u sum_k phi_k, T_ik = sum |k_c x_c|."""
+    T = sum(np.abs(np.outer(xc[idx].astype(np.float64), kc.astype(np.float64))) for kc, xc in zip(k, x))
+    phi64 = phi.astype(np.float64)
+    return (2 * np.pi * 3 * U32 * T + 4 * U32) @ phi64 + len(phi) * U32 * phi64.sum()
+
+
+@pytest.mark.parametrize("nk,nv", [(1, 1), (100, 513), (2048, 4096), (3000, 1000)])
+def test_mriq(nk, nv):
+    say("mriq", nk, nv)
+    k, phi, x = mriq_inputs(nk, nv, nk + nv)
+    qr, qi = torch.empty(nv, device=DEV), torch.empty(nv, device=DEV)
+    abi.mx_mriq_f32(*[dev(a) for a in k], dev(phi), *[dev(a) for a in x], qr, qi)
+    rr, ri = O.mriq(*k, phi, *x)
+    b = mriq_bound(k, phi, x, np.arange(nv))
+    assert np.all(np.abs(host(qr) - rr) <= b) and np.all(np.abs(host(qi) - ri) <= b)
+
+
+def test_mriq_full_size_sampled():
+    nk, nv = 2048, 1 << 18
+    say("mriq full size", nk, nv)
+    k, phi, x = mriq_inputs(nk, nv, 0)
+    qr, qi = torch.empty(nv, device=DEV), torch.empty(nv, device=DEV)
+    abi.mx_mriq_f32(*[dev(a) for a in k], dev(phi), *[dev(a) for a in x], qr, qi)
+    idx = np.concatenate([np.arange(256), np.random.default_rng(1).integers(0, nv, 512), np.arange(nv - 256, nv)])
+    rr, ri = O.mriq(*k, phi, *[xc[idx] for xc in x])
+    b = mriq_bound(k, phi, x, idx)
+    assert np.all(np.abs(host(qr)[idx] - rr) <= b) and np.all(np.abs(host(qi)[idx] - ri) <= b)
