@@ -63,6 +63,10 @@ TRAFFIC = {
     # 261.19 MB fetched + 0.26 MB written (1.01x algorithmic)
     "expr_seg": {"file": "expr.hip", "bytes": 261456154,
                  "source": "3c4193914692d926aa8a723f32c8381bc8d66eab67fc9745764d8118e13838e2"},
+    # k_stencil7, 512 x 512 x 64 float32: 73.15 MB fetched (1.09x: a 16-plane slab re-reads the planes
+    # below and above it) + 67.10 MB written
+    "stencil": {"file": "parboil.hip", "bytes": 140252752,
+                "source": "92db0ba9f847ddac06f507185de962b8c200090e969a807ea4b93ca37851d2dc"},
     # k_seg_broadcast: 1.61 MB fetched (offsets, gradients) + 128.83 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 130405516,
                       "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
@@ -429,14 +433,19 @@ def bench_dot(args):
 
 
 # ============================================================ N-body loop
-# VALU issue slots per pair interaction in the inner loop of the fused forward
+# VALU instructions per pair interaction in the inner loop of the fused forward
 # pair kernel (gfx950 ISA of k_pairs<STEP>): 3 sub, 3 mul/fma for |d|^2 plus
-# eps2, 2 mul for the cube, 1 mul by the mass, 3 fma into the sums = 12; the
-# v_rsq_f32 goes to the transcendental unit, which issues alongside the VALU
-# (the measured pair rate is above what 13 slots per pair would allow).
+# eps2, 2 mul for the cube, 1 mul by the mass, 3 fma into the sums = 12, plus
+# the v_rsq_f32 on the transcendental unit.
 NBODY_VALU_PER_PAIR = 12
-# 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz (no packed FP32).
-LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# The ALU peak in lane operations per second: the chip's FP32 vector peak,
+# 157.3 TFLOP/s = 256 CUs x 4 SIMDs x 32 FMA lanes per clock x 2 flops x
+# 2.4 GHz, counts 32 lane operations per clock per SIMD.  (Sixteen, the width
+# of one SIMD's non-packed FP32 lanes, is not the limit: the SQ counters of
+# k_mriq show 20.1 VALU lane operations per clock per SIMD, 373.5 M wave
+# instructions x 64 lanes in 1.163 M cycles of the 2.2 GHz clock over 1024
+# SIMDs.)
+LANE_OPS_PER_S = 256 * 4 * 32 * 2.4e9
 
 
 def nbody_peak_pairs_per_s(valu):
@@ -527,8 +536,9 @@ def bench_nbody(args):
         "roofline": {"bound": "alu", "kernel": "k_pairs<STEP> (+ slice finish)",
                      "achieved": round(ach / 1e9, 1), "peak": round(peak / 1e9, 1), "unit": "Gpair/s",
                      "frac": round(ach / peak, 4), "traffic": None,
-                     "peak_basis": f"256 CU x 64 lanes x 2.4 GHz / {NBODY_VALU_PER_PAIR} VALU issues per pair "
-                                   "(reciprocal square root on the transcendental unit)"},
+                     "peak_basis": f"FP32 vector peak as lane operations (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) / "
+                                   f"{NBODY_VALU_PER_PAIR} VALU instructions per pair (reciprocal square root on "
+                                   "the transcendental unit)"},
         "parts": {"fwd_20_steps_ms": round(ms_fwd, 3), "reverse_ms": round(ms - ms_fwd, 3),
                   "step_launch_us": round(parts["step"] * 1e3, 1),
                   "adjoint_step_launch_us": round(parts["adjoint_step"] * 1e3, 1)},
@@ -813,7 +823,7 @@ def bench_expr(args):
 
 
 # ============================================================ Parboil-shaped kernels
-# VALU issue slots per (voxel, sample) pair in the inner loop of k_mriq
+# VALU instructions per (voxel, sample) pair in the inner loop of k_mriq
 # (gfx950 ISA: 89 per sample for the thread's two voxels; sincospi is a
 # polynomial on the VALU, no transcendental unit).
 MRIQ_VALU_PER_PAIR = 44.5
@@ -880,14 +890,16 @@ def bench_parboil(args):
         "roofline": {"bound": "alu", "kernel": "k_mriq", "achieved": round(mriq_rate / 1e9, 1),
                      "peak": round(mriq_peak / 1e9, 1), "unit": "Gpair/s", "frac": round(mriq_rate / mriq_peak, 4),
                      "traffic": None,
-                     "peak_basis": f"256 CU x 64 lanes x 2.4 GHz / {MRIQ_VALU_PER_PAIR} VALU issues per pair"},
+                     "peak_basis": f"FP32 vector peak as lane operations (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) / "
+                                   f"{MRIQ_VALU_PER_PAIR} VALU instructions per pair"},
         "parts": {
             "histo_4096_bins": {"us": round(parts["histo_4096_bins"] * 1e3, 1),
                                 "GB/s": round(gbs(4 * nkeys, parts["histo_4096_bins"]), 1)},
             "histo_2^20_bins": {"us": round(parts["histo_2^20_bins"] * 1e3, 1),
                                 "GB/s": round(gbs(4 * nkeys, parts["histo_2^20_bins"]), 1)},
             "stencil": {"us": round(parts["stencil"] * 1e3, 1), "GB/s": round(gbs(8 * pts, parts["stencil"]), 1),
-                        "frac_hbm": round(gbs(8 * pts, parts["stencil"]) / HBM_PEAK_GBS, 4)},
+                        "frac_hbm": round(gbs(8 * pts, parts["stencil"]) / HBM_PEAK_GBS, 4),
+                        "traffic_bytes": traffic_of("stencil")},
             "mriq": {"us": round(parts["mriq"] * 1e3, 1), "Gpair/s": round(mriq_rate / 1e9, 1)},
         },
     }

@@ -20,14 +20,19 @@ __global__ void __launch_bounds__(NT) k_zero32(uint32_t *__restrict__ p, int64_t
 }
 
 // ---------------------------------------------------------------- histo
-// Few bins: each block counts its keys into a private LDS histogram (LDS
-// integer atomics), then adds its non-zero bins to the global counts.
-// Integer additions commute, so the counts do not depend on the order.
+// Few bins: each block counts its keys into private LDS histograms (LDS
+// integer atomics), then adds its non-zero bins to the global counts.  With
+// `copies` > 1 lane l counts into copy l % copies (copies nbins + 1 words
+// apart, so equal bins of different copies sit in different banks): lanes of
+// one instruction that hit the same bin wait for each other `copies` times
+// less.  Integer additions commute, so the counts do not depend on the order.
 __global__ void __launch_bounds__(NT) k_hist_lds(const uint32_t *__restrict__ keys, int64_t n, int nbins,
-                                                 uint32_t *__restrict__ counts, int vec) {
-    extern __shared__ uint32_t hist[];
-    for (int b = threadIdx.x; b < nbins; b += NT) hist[b] = 0u;
+                                                 int copies, uint32_t *__restrict__ counts, int vec) {
+    extern __shared__ uint32_t hist_all[];
+    const int stride = nbins + 1;
+    for (int b = threadIdx.x; b < stride * copies; b += NT) hist_all[b] = 0u;
     __syncthreads();
+    uint32_t *hist = hist_all + (threadIdx.x % copies) * stride;
     const int64_t tid = (int64_t)blockIdx.x * NT + threadIdx.x, nt = (int64_t)gridDim.x * NT;
     const uint32_t nb = (uint32_t)nbins;
     int64_t done = 0;
@@ -48,8 +53,11 @@ __global__ void __launch_bounds__(NT) k_hist_lds(const uint32_t *__restrict__ ke
         if (k < nb) atomicAdd(&hist[k], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += NT)
-        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+    for (int b = threadIdx.x; b < nbins; b += NT) {
+        uint32_t c = 0u;
+        for (int q = 0; q < copies; ++q) c += hist_all[q * stride + b];
+        if (c) atomicAdd(&counts[b], c);
+    }
 }
 
 // Many bins: integer atomics on the global counts.
@@ -84,10 +92,16 @@ __global__ void __launch_bounds__(NT) k_hist_global(const uint32_t *__restrict__
 // rounded on its own.  Boundary points are copied.
 constexpr int kSlab = 16;
 
+// Blocks are dealt to the 8 XCDs in turn, each XCD with its own L2; the
+// column tiles are renumbered so that XCD k takes one contiguous band of
+// rows, and the rows above and below a tile are mostly in the same L2.
 __global__ void __launch_bounds__(NT) k_stencil7(const float *__restrict__ in, float *__restrict__ out, int64_t nx,
                                                  int64_t ny, int64_t nz, float c0, float c1) {
 #pragma clang fp contract(off)
-    const int64_t col = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t ntiles = gridDim.x, per = ntiles / 8;
+    int64_t tile = blockIdx.x;
+    if (tile < per * 8) tile = (tile % 8) * per + tile / 8;
+    const int64_t col = tile * NT + threadIdx.x;
     if (col >= nx * ny) return;
     const int64_t y = col / nx, x = col - y * nx;
     const int64_t z0 = (int64_t)blockIdx.y * kSlab;
@@ -181,14 +195,19 @@ mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, u
     if (mx_status st = last_launch(who)) return st;
     if (n == 0) return MX_OK;
     const int vec = ((uintptr_t)keys_dev & 15) == 0;
-    if (nbins <= kHistLdsBins && (size_t)nbins * 4 <= (size_t)d->lds_bytes) {
+    if (nbins <= kHistLdsBins && (size_t)(nbins + 1) * 4 <= (size_t)d->lds_bytes) {
         // as many blocks as fit the CUs' LDS (at most eight per CU); each
         // block's flush adds at most nbins global atomics
-        const int64_t per_cu = std::min<int64_t>(8, std::max<int64_t>(1, (int64_t)d->lds_bytes / (nbins * 4)));
+        // up to four copies within 64 KiB; as many blocks as fit the CUs'
+        // LDS (at most eight per CU); each block's flush adds at most nbins
+        // global atomics
+        const int copies = (int)std::max<int64_t>(1, std::min<int64_t>(4, 16383 / (nbins + 1)));
+        const size_t lds = (size_t)(nbins + 1) * copies * 4;
+        const int64_t per_cu = std::min<int64_t>(8, std::max<int64_t>(1, (int64_t)d->lds_bytes / (int64_t)lds));
         int64_t grid = ceil_div(n, (int64_t)NT * 64);
         if (grid > d->num_cus * per_cu) grid = d->num_cus * per_cu;
-        hipLaunchKernelGGL(k_hist_lds, dim3((unsigned)grid), dim3(NT), (size_t)nbins * 4, stream, keys_dev, n,
-                           (int)nbins, counts_dev, vec);
+        hipLaunchKernelGGL(k_hist_lds, dim3((unsigned)grid), dim3(NT), lds, stream, keys_dev, n, (int)nbins, copies,
+                           counts_dev, vec);
     } else {
         int64_t grid = ceil_div(n, (int64_t)NT * 16);
         if (grid > d->num_cus * 8) grid = d->num_cus * 8;
