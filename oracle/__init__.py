@@ -94,6 +94,7 @@ def _declare(lib):
         "or_histogram_u32": (None, [_p, _i64, _i64, _p]),
         "or_stencil7": (None, [_p, _i64, _i64, _i64, _d, _d, _p]),
         "or_mriq": (None, [_p, _p, _p, _p, _i64, _p, _p, _p, _i64, _p, _p]),
+        "or_tpacf": (None, [_p, _p, _p, _i64, _p, _p, _p, _i64, _int, _p, _int, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -487,3 +488,16 @@ def mriq(kx, ky, kz, phi, x, y, z):
     _L().or_mriq(_ptr(kx), _ptr(ky), _ptr(kz), _ptr(phi), kx.size, _ptr(x), _ptr(y), _ptr(z), x.size, _ptr(qr),
                  _ptr(qi))
     return qr, qi
+
+
+def tpacf(p1, p2, edges, self_pairs: bool) -> np.ndarray:
+    """Angular pair counts (int64, len(edges) + 1 bins); points (3, n) binary32
+    unit vectors; the dot product and the comparisons in binary32."""
+    f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))  # noqa: E731
+    x1, y1, z1 = (f(c) for c in p1)
+    x2, y2, z2 = (f(c) for c in (p1 if self_pairs else p2))
+    e = f(edges)
+    counts = np.zeros(e.size + 1, dtype=np.int64)
+    _L().or_tpacf(_ptr(x1), _ptr(y1), _ptr(z1), x1.size, _ptr(x2), _ptr(y2), _ptr(z2), x2.size, int(self_pairs),
+                  _ptr(e), e.size, _ptr(counts))
+    return counts

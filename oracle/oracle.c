@@ -759,3 +759,28 @@ void or_mriq(const double *kx, const double *ky, const double *kz, const double 
         qi[i] = ai;
     }
 }
+
+/* tpacf: angular pair counts.  Points are unit vectors (x, y, z) in
+ * binary32; a pair's similarity is the binary32 dot product x1 x2 + y1 y2 +
+ * z1 z2 (three products and two additions, each rounded to binary32 -- the
+ * precision the kernel decides in).  With the decreasing binary32 bin edges
+ * e_0 > ... > e_{m-1} (cosines of increasing angles), a pair falls in bin
+ * #{b : d < e_b}, one of m + 1 bins.  self != 0: pairs i < j of set 1 only;
+ * else all pairs of set 1 x set 2. */
+void or_tpacf(const float *x1, const float *y1, const float *z1, int64_t n1, const float *x2, const float *y2,
+              const float *z2, int64_t n2, int self, const float *edges, int m, int64_t *counts)
+{
+    for (int b = 0; b <= m; ++b) counts[b] = 0;
+    for (int64_t i = 0; i < n1; ++i) {
+        const int64_t j0 = self ? i + 1 : 0, jn = self ? n1 : n2;
+        for (int64_t j = j0; j < jn; ++j) {
+            const float xj = self ? x1[j] : x2[j], yj = self ? y1[j] : y2[j], zj = self ? z1[j] : z2[j];
+            float d = x1[i] * xj;
+            d = d + y1[i] * yj;
+            d = d + z1[i] * zj;
+            int bin = 0;
+            for (int b = 0; b < m; ++b) bin += d < edges[b];
+            counts[bin] = counts[bin] + 1;
+        }
+    }
+}

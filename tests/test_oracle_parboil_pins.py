@@ -59,3 +59,26 @@ def test_mriq_matches_matrix_form_and_symmetries():
     assert np.allclose(qr2, qr, rtol=1e-12, atol=1e-12) and np.allclose(qi2, -qi, rtol=1e-12, atol=1e-12)
     qr0, qi0 = O.mriq(np.zeros(nk), np.zeros(nk), np.zeros(nk), phi, x, y, z)
     assert np.allclose(qr0, phi.sum(), rtol=1e-14) and np.all(qi0 == 0)
+
+
+
+def _sphere(n, seed):
+    r = np.random.default_rng(seed)
+    v = r.normal(size=(3, n))
+    return (v / np.linalg.norm(v, axis=0)).astype(np.float32)
+
+
+def test_tpacf_is_binary32_dot_and_searchsorted():
+    p1, p2 = _sphere(120, 1), _sphere(90, 2)
+    edges = np.cos(np.radians(np.logspace(-1, 2, 12))).astype(np.float32)   # decreasing cosines
+    d = (p1[0][:, None] * p2[0][None, :]).astype(np.float32)                # numpy float32: each op rounded
+    d = (d + (p1[1][:, None] * p2[1][None, :]).astype(np.float32)).astype(np.float32)
+    d = (d + (p1[2][:, None] * p2[2][None, :]).astype(np.float32)).astype(np.float32)
+    bins = np.searchsorted(-edges, -d.ravel(), side="right")   # #{b : d < e_b} via the ascending -e
+    ref = np.bincount(bins, minlength=edges.size + 1)
+    assert np.array_equal(O.tpacf(p1, p2, edges, False), ref)
+    got_self = O.tpacf(p1, None, edges, True)
+    assert got_self.sum() == 120 * 119 // 2
+    full = O.tpacf(p1, p1, edges, False)                       # all ordered pairs incl. i == j
+    diag = O.tpacf(p1[:, :1], p1[:, :1], edges, False)         # a single self pair lands in bin 0 or 1
+    assert full.sum() == 120 * 120 and diag.sum() == 1
