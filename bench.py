@@ -850,6 +850,18 @@ def bench_parboil(args):
     phi = torch.rand(nk, device=dev)
     xyz = [torch.rand(nv, device=dev) - 0.5 for _ in range(3)]
     qr, qi = torch.empty(nv, device=dev), torch.empty(nv, device=dev)
+    # tpacf: 2^15 data and 2^15 random points on the sphere, 20 log-spaced angular edges (0.1 .. 158 deg)
+    npt, nedge = 1 << 15, 20
+    sph = []
+    for sd in (1, 2):
+        v = torch.randn((3, npt), device=dev, generator=torch.Generator(device=dev).manual_seed(sd))
+        sph.append((v / v.norm(dim=0)).contiguous())
+    tp_edges = torch.from_numpy(np.cos(np.radians(np.logspace(-1, 2.2, nedge))).astype(np.float32)).to(dev)
+    tp_counts = torch.empty(nedge + 1, dtype=torch.int64, device=dev)
+
+    def tpacf():  # DD (pairs i < j) then DR (all pairs)
+        abi.mx_tpacf_f32(sph[0], sph[0], tp_edges, tp_counts, True)
+        abi.mx_tpacf_f32(sph[0], sph[1], tp_edges, tp_counts, False)
 
     def histo_small():
         abi.mx_histogram_u32(keys[4096], 4096, counts[4096])
@@ -868,14 +880,16 @@ def bench_parboil(args):
         histo_large()
         stencil()
         mriq()
+        tpacf()
 
     parts = {nm: per_launch_ms(f, reps=max(args.steps, 5), warmup=args.warmup)
              for nm, f in (("histo_4096_bins", histo_small), ("histo_2^20_bins", histo_large),
-                           ("stencil", stencil), ("mriq", mriq))}
+                           ("stencil", stencil), ("mriq", mriq), ("tpacf", tpacf))}
     ms = timed_on(torch.cuda.current_stream(), step, args.steps, args.warmup)
     pts = nx * ny * nz
     pairs = nk * nv
-    elems = 2 * nkeys + pts + pairs
+    tp_pairs = npt * (npt - 1) // 2 + npt * npt
+    elems = 2 * nkeys + pts + pairs + tp_pairs
     mriq_peak = LANE_OPS_PER_S / MRIQ_VALU_PER_PAIR
     mriq_rate = pairs / (parts["mriq"] * 1e-3)
     log(f"parboil: step {ms:.3f} ms; " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in parts.items()))
@@ -885,8 +899,9 @@ def bench_parboil(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "Parboil-shaped kernels on synthetic data: histogram of 2^24 concentrated keys into "
                                "4096 and 2^20 bins, one 7-point stencil sweep of 512x512x64 float32, mri-q with "
-                               "2048 samples x 2^18 voxels", "keys": nkeys, "grid": [nz, ny, nx],
-                   "mriq": [nk, nv], "elements_per_step": elems},
+                               "2048 samples x 2^18 voxels, tpacf DD + DR pair counts of 2^15 + 2^15 points on "
+                               "the sphere in 21 angular bins", "keys": nkeys, "grid": [nz, ny, nx],
+                   "mriq": [nk, nv], "tpacf_points": npt, "elements_per_step": elems},
         "roofline": {"bound": "alu", "kernel": "k_mriq", "achieved": round(mriq_rate / 1e9, 1),
                      "peak": round(mriq_peak / 1e9, 1), "unit": "Gpair/s", "frac": round(mriq_rate / mriq_peak, 4),
                      "traffic": None,
@@ -901,6 +916,8 @@ def bench_parboil(args):
                         "frac_hbm": round(gbs(8 * pts, parts["stencil"]) / HBM_PEAK_GBS, 4),
                         "traffic_bytes": traffic_of("stencil")},
             "mriq": {"us": round(parts["mriq"] * 1e3, 1), "Gpair/s": round(mriq_rate / 1e9, 1)},
+            "tpacf": {"us": round(parts["tpacf"] * 1e3, 1), "pairs": tp_pairs,
+                      "Gpair/s": round(tp_pairs / (parts["tpacf"] * 1e-3) / 1e9, 1)},
         },
     }
     if not args.no_cpu_baseline:

@@ -488,6 +488,19 @@ mx_status mx_mriq_f32(const float *kx_dev, const float *ky_dev, const float *kz_
                       int64_t nk, const float *x_dev, const float *y_dev, const float *z_dev, int64_t nv,
                       float *qr_dev, float *qi_dev, hipStream_t stream);
 
+/* tpacf: angular pair counts of unit vectors (x, y, z) in float32.  A pair's
+ * similarity is the float32 dot product x1 x2 + y1 y2 + z1 z2 (each product
+ * and addition rounded on its own); with the decreasing float32 edges
+ * e_0 > ... > e_{m-1} (cosines of increasing angles, device array, m <= 32)
+ * the pair falls in bin #{b : d < e_b}, one of m + 1 bins; counts: m + 1
+ * int64 device entries, overwritten.  self_pairs != 0: the pairs i < j of set
+ * 1 (set 2 ignored); else all pairs of set 1 x set 2.  Integer counts,
+ * bit-exact and order-free.  Errors: MX_ERR_SHAPE, MX_ERR_UNSUPPORTED (m >
+ * 32), MX_ERR_INVALID. */
+mx_status mx_tpacf_f32(const float *x1_dev, const float *y1_dev, const float *z1_dev, int64_t n1,
+                       const float *x2_dev, const float *y2_dev, const float *z2_dev, int64_t n2, int self_pairs,
+                       const float *edges_dev, int nedges, int64_t *counts_dev, hipStream_t stream);
+
 /* ======================================================================= */
 /* User-defined map bodies                                                   */
 /* ======================================================================= */

@@ -76,6 +76,7 @@ SIGNATURES = {
     "mx_histogram_u32": (c_status, [c_p, c_i64, c_i64, c_p, c_p]),
     "mx_stencil7_f32": (c_status, [c_p, c_p, c_i64, c_i64, c_i64, c_f32, c_f32, c_p]),
     "mx_mriq_f32": (c_status, [c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p]),
+    "mx_tpacf_f32": (c_status, [c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_i64, c_int, c_p, c_int, c_p, c_p]),
     "mx_expr_create": (c_status, [c_p, c_int, c_int, c_int, c_enum, c_pp]),
     "mx_expr_destroy": (c_status, [c_p]),
     "mx_expr_prepare": (c_status, [c_p]),

@@ -453,6 +453,14 @@ def mx_mriq_f32(kx, ky, kz, phi, x, y, z, qr, qi, stream=None) -> None:
                             x.numel(), _dptr(qr), _dptr(qi), _stream(stream)), "mx_mriq_f32")
 
 
+def mx_tpacf_f32(p1, p2, edges, counts, self_pairs: bool = False, stream=None) -> None:
+    """p1, p2: (3, n) float32 device tensors of unit vectors (p2 ignored for self pairs)."""
+    q = p1 if self_pairs else p2
+    _check(_L().mx_tpacf_f32(_dptr(p1[0]), _dptr(p1[1]), _dptr(p1[2]), p1.shape[1], _dptr(q[0]), _dptr(q[1]),
+                             _dptr(q[2]), q.shape[1], int(bool(self_pairs)), _dptr(edges), edges.numel(),
+                             _dptr(counts), _stream(stream)), "mx_tpacf_f32")
+
+
 # ---------------------------------------------------------------- user-defined map bodies
 class XInsn(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("dst", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),

@@ -174,6 +174,84 @@ __global__ void __launch_bounds__(NT) k_mriq(const float *__restrict__ kx, const
     if (h1) { qr[v1] = r1; qi[v1] = i1; }
 }
 
+// ---------------------------------------------------------------- tpacf
+// Angular pair counts: a thread owns one point of set 1 and walks set 2 in
+// LDS tiles (broadcast reads); per pair the binary32 dot product (three
+// products, two additions, each rounded) and, for every edge e_b, whether
+// d < e_b -- kept as running counts below[b] in registers, so no atomics and
+// no indexed register writes.  Bin k holds below[k-1] - below[k] pairs.  The
+// block adds its threads' counts and each bin goes to the global int64
+// counts with one atomic add; integer sums, so the result does not depend on
+// the order.
+constexpr int kTpTile = 512;
+constexpr int kTpMaxEdges = 32;
+
+template <int ME>  // edges handled, >= m (registers for the running counts)
+__global__ void __launch_bounds__(NT) k_tpacf(const float *__restrict__ x1, const float *__restrict__ y1,
+                                              const float *__restrict__ z1, int64_t n1,
+                                              const float *__restrict__ x2, const float *__restrict__ y2,
+                                              const float *__restrict__ z2, int64_t n2, int self,
+                                              const float *__restrict__ edges, int m,
+                                              unsigned long long *__restrict__ counts) {
+#pragma clang fp contract(off)
+    __shared__ float4 tile[kTpTile];
+    __shared__ unsigned long long red[kTpMaxEdges + 1];
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const bool has = i < n1;
+    const float xi = has ? x1[i] : 0.f, yi = has ? y1[i] : 0.f, zi = has ? z1[i] : 0.f;
+    float e[ME];
+    unsigned below[ME];
+#pragma unroll
+    for (int b = 0; b < ME; ++b) {
+        e[b] = b < m ? edges[b] : -INFINITY;  // past m: never counted
+        below[b] = 0u;
+    }
+    unsigned long long total = 0;
+    if (threadIdx.x <= kTpMaxEdges) red[threadIdx.x] = 0ull;
+    // self pairs: only j > i; the block's smallest i bounds the tiles it needs
+    const int64_t jstart = self ? (int64_t)blockIdx.x * NT + 1 : 0;
+    for (int64_t t0 = jstart; t0 < n2; t0 += kTpTile) {
+        const int cnt = (int)(n2 - t0 < kTpTile ? n2 - t0 : kTpTile);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT) tile[j] = make_float4(x2[t0 + j], y2[t0 + j], z2[t0 + j], 0.f);
+        __syncthreads();
+        if (!has) continue;
+        const int jlo = self ? (int)(i + 1 - t0 > 0 ? (i + 1 - t0 < cnt ? i + 1 - t0 : cnt) : 0) : 0;
+        unsigned run[ME];
+#pragma unroll
+        for (int b = 0; b < ME; ++b) run[b] = 0u;
+        for (int j = jlo; j < cnt; ++j) {
+            const float4 q = tile[j];
+            float d = xi * q.x;
+            d = d + yi * q.y;
+            d = d + zi * q.z;
+#pragma unroll
+            for (int b = 0; b < ME; ++b) run[b] += d < e[b] ? 1u : 0u;
+        }
+        total += (unsigned long long)(cnt - jlo);
+#pragma unroll
+        for (int b = 0; b < ME; ++b) below[b] += run[b];
+    }
+    // bins from the running counts, block sums, one atomic per bin
+    __syncthreads();
+    for (int k = 0; k <= m; ++k) {
+        unsigned long long c;
+        if (k == 0) c = total - (m > 0 ? below[0] : 0u);
+        else if (k == m) c = below[m - 1];
+        else c = (unsigned long long)(below[k - 1] - below[k]);
+        if (!has) c = 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd(&red[k], c);
+    }
+    __syncthreads();
+    if (threadIdx.x <= m && red[threadIdx.x]) atomicAdd(&counts[threadIdx.x], red[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(NT) k_zero64(unsigned long long *__restrict__ p, int m) {
+    if ((int)threadIdx.x < m) p[threadIdx.x] = 0ull;
+}
+
 }  // namespace
 }  // namespace mx
 
@@ -227,6 +305,37 @@ mx_status mx_stencil7_f32(const float *in_dev, float *out_dev, int64_t nx, int64
     MX_REQUIRE(gz <= 65535, MX_ERR_SHAPE, "%s: nz too large", who);
     hipLaunchKernelGGL(k_stencil7, dim3((unsigned)gx, (unsigned)gz), dim3(NT), 0, stream, in_dev, out_dev, nx, ny,
                        nz, c0, c1);
+    return last_launch(who);
+}
+
+mx_status mx_tpacf_f32(const float *x1_dev, const float *y1_dev, const float *z1_dev, int64_t n1,
+                       const float *x2_dev, const float *y2_dev, const float *z2_dev, int64_t n2, int self_pairs,
+                       const float *edges_dev, int nedges, int64_t *counts_dev, hipStream_t stream) {
+    const char *who = "mx_tpacf_f32";
+    MX_REQUIRE(n1 >= 0 && n2 >= 0, MX_ERR_SHAPE, "%s: negative size", who);
+    MX_REQUIRE(nedges >= 0 && nedges <= kTpMaxEdges, MX_ERR_UNSUPPORTED, "%s: at most %d edges", who, kTpMaxEdges);
+    MX_REQUIRE(counts_dev && (nedges == 0 || edges_dev), MX_ERR_INVALID, "%s: null counts or edges", who);
+    if (self_pairs) {
+        x2_dev = x1_dev;
+        y2_dev = y1_dev;
+        z2_dev = z1_dev;
+        n2 = n1;
+    }
+    MX_REQUIRE((n1 == 0 || (x1_dev && y1_dev && z1_dev)) && (n2 == 0 || (x2_dev && y2_dev && z2_dev)),
+               MX_ERR_INVALID, "%s: null point array", who);
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, stream, (unsigned long long *)counts_dev, nedges + 1);
+    if (mx_status st = last_launch(who)) return st;
+    if (n1 == 0 || n2 == 0) return MX_OK;
+    const int64_t grid = ceil_div(n1, (int64_t)NT);
+    MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "%s: too many points", who);
+#define MX_TPACF(ME)                                                                                               \
+    hipLaunchKernelGGL(k_tpacf<ME>, dim3((unsigned)grid), dim3(NT), 0, stream, x1_dev, y1_dev, z1_dev, n1, x2_dev, \
+                       y2_dev, z2_dev, n2, self_pairs ? 1 : 0, edges_dev, nedges, (unsigned long long *)counts_dev)
+    if (nedges <= 8) MX_TPACF(8);
+    else if (nedges <= 16) MX_TPACF(16);
+    else if (nedges <= 24) MX_TPACF(24);
+    else MX_TPACF(32);
+#undef MX_TPACF
     return last_launch(who);
 }
 

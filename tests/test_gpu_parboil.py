@@ -117,3 +117,34 @@ def test_mriq_full_size_sampled():
     rr, ri = O.mriq(*k, phi, *[xc[idx] for xc in x])
     b = mriq_bound(k, phi, x, idx)
     assert np.all(np.abs(host(qr)[idx] - rr) <= b) and np.all(np.abs(host(qi)[idx] - ri) <= b)
+
+
+# ---------------------------------------------------------------- tpacf
+def sphere(n, seed):
+    v = np.random.default_rng(seed).normal(size=(3, n))
+    return (v / np.linalg.norm(v, axis=0)).astype(np.float32)
+
+
+def edges_of(m):
+    return np.cos(np.radians(np.logspace(-1, 2.2, m))).astype(np.float32) if m else np.zeros(0, np.float32)
+
+
+@pytest.mark.parametrize("n1,n2", [(1, 1), (300, 700), (4096, 4096), (1000, 0), (5000, 257)])
+@pytest.mark.parametrize("self_pairs", [False, True])
+@pytest.mark.parametrize("m", [0, 1, 20, 32])
+def test_tpacf_counts_bit_exact(n1, n2, self_pairs, m):
+    say("tpacf", n1, n2, self_pairs, m)
+    p1, p2 = sphere(n1, n1 + 7), sphere(n2, n2 + 11)
+    e = edges_of(m)
+    counts = torch.full((m + 1,), -1, dtype=torch.int64, device=DEV)
+    abi.mx_tpacf_f32(dev(p1), dev(p2), dev(e) if m else torch.empty(0, device=DEV), counts, self_pairs)
+    ref = O.tpacf(p1, p2, e, self_pairs)
+    assert np.array_equal(host(counts), ref)
+    assert ref.sum() == (n1 * (n1 - 1) // 2 if self_pairs else n1 * n2)
+
+
+def test_tpacf_rejects_too_many_edges():
+    p = dev(sphere(4, 0))
+    with pytest.raises(abi.MxError) as err:
+        abi.mx_tpacf_f32(p, p, dev(edges_of(33)), torch.empty(34, dtype=torch.int64, device=DEV))
+    assert err.value.status == abi.MX_ERR_UNSUPPORTED
