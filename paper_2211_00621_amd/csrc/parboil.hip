@@ -178,71 +178,168 @@ __global__ void __launch_bounds__(NT) k_mriq(const float *__restrict__ kx, const
 // Angular pair counts: a thread owns one point of set 1 and walks set 2 in
 // LDS tiles (broadcast reads); per pair the binary32 dot product (three
 // products, two additions, each rounded) and, for every edge e_b, whether
-// d < e_b -- kept as running counts below[b] in registers, so no atomics and
-// no indexed register writes.  Bin k holds below[k-1] - below[k] pairs.  The
-// block adds its threads' counts and each bin goes to the global int64
+// d < e_b.  Only block totals are wanted, so these running counts below[b]
+// are kept two ways and the vector and scalar units share the work: for the
+// first NS edges the wave counts its lanes at once (a 64-bit compare mask,
+// popcount and add on the scalar unit), for the rest every lane keeps its own
+// count in a register (compare, add with carry).  No atomics and no indexed
+// register writes in the loop.  Bin k holds below[k-1] - below[k] pairs.  The
+// grid is two-dimensional: blockIdx.x picks 256 points of set 1, blockIdx.y a
+// chunk of set 2, so a few thousand blocks fill the chip even when set 1 is
+// small.  Each wave's bins go to LDS and each block bin to the global int64
 // counts with one atomic add; integer sums, so the result does not depend on
 // the order.
-constexpr int kTpTile = 512;
+constexpr int kTpTile = 256;
 constexpr int kTpMaxEdges = 32;
+
+// edges counted per wave on the scalar unit: a vector-counted edge costs two
+// vector instructions per pair, a wave-counted one a vector compare plus 1.75
+// scalar instructions per 64 pairs (four columns share one add).  The time
+// follows the total instruction count more than the split (measured nearly
+// flat from a half to seven eighths); half was the fastest.
+constexpr int tp_wave_edges(int me) { return me / 2; }
+
+// One tile: pairs (i, j) for j in [j0, cnt).  MASKED: some lanes have no point
+// or need j >= jlo (self pairs); their d becomes +inf, below no edge.
+template <int ME, bool MASKED>
+__device__ __forceinline__ void tp_tile(const float4 *__restrict__ tile, int j0, int cnt, int jlo, bool has,
+                                        float xi, float yi, float zi, const float (&e)[ME],
+                                        unsigned (&ws)[tp_wave_edges(ME)],
+                                        unsigned (&run)[ME - tp_wave_edges(ME)]) {
+#pragma clang fp contract(off)
+    constexpr int NS = tp_wave_edges(ME);
+    int j = j0;
+    if (!MASKED) {
+        // four pairs columns at a time: the wave-counted edges add four
+        // popcounts on the scalar unit before one add into their running count
+        for (; j + 4 <= cnt; j += 4) {
+            float d[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 q = tile[j + u];
+                d[u] = xi * q.x;
+                d[u] = d[u] + yi * q.y;
+                d[u] = d[u] + zi * q.z;
+            }
+#pragma unroll
+            for (int b = 0; b < NS; ++b) {
+                unsigned c = 0u;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) c += (unsigned)__popcll(__ballot(d[u] < e[b]));
+                ws[b] += c;
+                // one edge's four masks live at a time (scalar registers)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int b = NS; b < ME; ++b) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) run[b - NS] += d[u] < e[b] ? 1u : 0u;
+            }
+        }
+    }
+    for (; j < cnt; ++j) {
+        const float4 q = tile[j];
+        float d = xi * q.x;
+        d = d + yi * q.y;
+        d = d + zi * q.z;
+        if (MASKED) d = has && j >= jlo ? d : INFINITY;
+#pragma unroll
+        for (int b = 0; b < NS; ++b) ws[b] += (unsigned)__popcll(__ballot(d < e[b]));
+#pragma unroll
+        for (int b = NS; b < ME; ++b) run[b - NS] += d < e[b] ? 1u : 0u;
+    }
+}
 
 template <int ME>  // edges handled, >= m (registers for the running counts)
 __global__ void __launch_bounds__(NT) k_tpacf(const float *__restrict__ x1, const float *__restrict__ y1,
                                               const float *__restrict__ z1, int64_t n1,
                                               const float *__restrict__ x2, const float *__restrict__ y2,
-                                              const float *__restrict__ z2, int64_t n2, int self,
-                                              const float *__restrict__ edges, int m,
+                                              const float *__restrict__ z2, int64_t n2, int64_t chunk,
+                                              int self, const float *__restrict__ edges, int m,
                                               unsigned long long *__restrict__ counts) {
-#pragma clang fp contract(off)
+    constexpr int NS = tp_wave_edges(ME), NV = ME - NS;
     __shared__ float4 tile[kTpTile];
     __shared__ unsigned long long red[kTpMaxEdges + 1];
     const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    // this block's part of set 2; self pairs need only j > i, and the block's
+    // smallest i bounds the part it needs (whole-block exit, before any barrier)
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t jend = c0 + chunk < n2 ? c0 + chunk : n2;
+    const int64_t jstart = self && (int64_t)blockIdx.x * NT + 1 > c0 ? (int64_t)blockIdx.x * NT + 1 : c0;
+    if (jstart >= jend) return;
+    // the wave's first point (wave-uniform)
+    const int64_t w0 = (int64_t)blockIdx.x * NT + __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
     const bool has = i < n1;
     const float xi = has ? x1[i] : 0.f, yi = has ? y1[i] : 0.f, zi = has ? z1[i] : 0.f;
     float e[ME];
-    unsigned below[ME];
 #pragma unroll
     for (int b = 0; b < ME; ++b) {
         e[b] = b < m ? edges[b] : -INFINITY;  // past m: never counted
-        below[b] = 0u;
+        // keep the edges in vector registers: the scalar ones hold the wave counts
+        asm volatile("" : "+v"(e[b]));
     }
+    // wave counts: edge b's in lane b of one 64-bit register (scalar
+    // registers would not hold them all); lane counts in below[] (a chunk
+    // holds fewer than 2^32 points)
+    unsigned long long wbelow = 0ull;
+    unsigned below[NV > 0 ? NV : 1];
+    const int lane = (int)threadIdx.x & 63;
+#pragma unroll
+    for (int b = 0; b < NV; ++b) below[b] = 0u;
     unsigned long long total = 0;
     if (threadIdx.x <= kTpMaxEdges) red[threadIdx.x] = 0ull;
-    // self pairs: only j > i; the block's smallest i bounds the tiles it needs
-    const int64_t jstart = self ? (int64_t)blockIdx.x * NT + 1 : 0;
-    for (int64_t t0 = jstart; t0 < n2; t0 += kTpTile) {
-        const int cnt = (int)(n2 - t0 < kTpTile ? n2 - t0 : kTpTile);
+    for (int64_t t0 = jstart; t0 < jend; t0 += kTpTile) {
+        const int cnt = (int)(jend - t0 < kTpTile ? jend - t0 : kTpTile);
         __syncthreads();
         for (int j = threadIdx.x; j < cnt; j += NT) tile[j] = make_float4(x2[t0 + j], y2[t0 + j], z2[t0 + j], 0.f);
         __syncthreads();
-        if (!has) continue;
+        if (w0 >= n1) continue;  // the whole wave is past set 1
         const int jlo = self ? (int)(i + 1 - t0 > 0 ? (i + 1 - t0 < cnt ? i + 1 - t0 : cnt) : 0) : 0;
-        unsigned run[ME];
+        unsigned ws[NS > 0 ? NS : 1], run[NV > 0 ? NV : 1];
 #pragma unroll
-        for (int b = 0; b < ME; ++b) run[b] = 0u;
-        for (int j = jlo; j < cnt; ++j) {
-            const float4 q = tile[j];
-            float d = xi * q.x;
-            d = d + yi * q.y;
-            d = d + zi * q.z;
+        for (int b = 0; b < NS; ++b) ws[b] = 0u;
 #pragma unroll
-            for (int b = 0; b < ME; ++b) run[b] += d < e[b] ? 1u : 0u;
+        for (int b = 0; b < NV; ++b) run[b] = 0u;
+        if (w0 + 64 <= n1 && (!self || t0 >= w0 + 64)) {
+            tp_tile<ME, false>(tile, 0, cnt, 0, true, xi, yi, zi, e, ws, run);
+        } else {
+            // first j any lane of the wave needs
+            const int jw = self ? (int)(w0 + 1 - t0 > 0 ? (w0 + 1 - t0 < cnt ? w0 + 1 - t0 : cnt) : 0) : 0;
+            tp_tile<ME, true>(tile, jw, cnt, jlo, has, xi, yi, zi, e, ws, run);
         }
-        total += (unsigned long long)(cnt - jlo);
+        if (has) total += (unsigned long long)(cnt - jlo);
 #pragma unroll
-        for (int b = 0; b < ME; ++b) below[b] += run[b];
+        for (int b = 0; b < NS; ++b) wbelow += lane == b ? (unsigned long long)ws[b] : 0ull;
+#pragma unroll
+        for (int b = 0; b < NV; ++b) below[b] += run[b];
     }
-    // bins from the running counts, block sums, one atomic per bin
+    // wave sums of the lane counts, bins per wave into LDS, one atomic per bin
     __syncthreads();
-    for (int k = 0; k <= m; ++k) {
-        unsigned long long c;
-        if (k == 0) c = total - (m > 0 ? below[0] : 0u);
-        else if (k == m) c = below[m - 1];
-        else c = (unsigned long long)(below[k - 1] - below[k]);
-        if (!has) c = 0;
+    unsigned long long wv[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int b = 0; b < NV; ++b) {
+        unsigned long long c = below[b];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-        if ((threadIdx.x & 63) == 0 && c) atomicAdd(&red[k], c);
+        wv[b] = c;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o, 64);
+    if ((threadIdx.x & 63) == 0 && w0 < n1) {
+        // static register indices: fully unrolled over the ME + 1 bins
+        unsigned long long prev = total;
+#pragma unroll
+        for (int k = 0; k <= ME; ++k) {
+            if (k > m) break;
+            const unsigned long long wk =
+                (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)wbelow, k < NS ? k : 0) |
+                (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(wbelow >> 32), k < NS ? k : 0)
+                    << 32;
+            const unsigned long long next = k == m ? 0ull : k < NS ? wk : wv[k >= NS && k - NS < NV ? k - NS : 0];
+            const unsigned long long c = prev - next;
+            if (c) atomicAdd(&red[k], c);
+            prev = next;
+        }
     }
     __syncthreads();
     if (threadIdx.x <= m && red[threadIdx.x]) atomicAdd(&counts[threadIdx.x], red[threadIdx.x]);
@@ -326,15 +423,38 @@ mx_status mx_tpacf_f32(const float *x1_dev, const float *y1_dev, const float *z1
     hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, stream, (unsigned long long *)counts_dev, nedges + 1);
     if (mx_status st = last_launch(who)) return st;
     if (n1 == 0 || n2 == 0) return MX_OK;
-    const int64_t grid = ceil_div(n1, (int64_t)NT);
-    MX_REQUIRE(grid <= 0x7fffffff, MX_ERR_SHAPE, "%s: too many points", who);
-#define MX_TPACF(ME)                                                                                               \
-    hipLaunchKernelGGL(k_tpacf<ME>, dim3((unsigned)grid), dim3(NT), 0, stream, x1_dev, y1_dev, z1_dev, n1, x2_dev, \
-                       y2_dev, z2_dev, n2, self_pairs ? 1 : 0, edges_dev, nedges, (unsigned long long *)counts_dev)
-    if (nedges <= 8) MX_TPACF(8);
-    else if (nedges <= 16) MX_TPACF(16);
-    else if (nedges <= 24) MX_TPACF(24);
-    else MX_TPACF(32);
+    const DeviceInfo *d;
+    if (mx_status st = device_info(&d)) return st;
+    const int64_t gx = ceil_div(n1, (int64_t)NT);
+    MX_REQUIRE(gx <= 0x7fffffff, MX_ERR_SHAPE, "%s: too many points", who);
+    // split set 2 into whole tiles so that about 32 blocks per CU exist
+    // (several rounds of resident blocks, a short tail; self pairs skip the
+    // blocks below the diagonal)
+    const int64_t tiles = ceil_div(n2, (int64_t)kTpTile);
+    int64_t gy = ceil_div((int64_t)d->num_cus * 32, gx);
+    if (gy > tiles) gy = tiles;
+    if (gy > 65535) gy = 65535;
+    if (gy < 1) gy = 1;
+    int64_t chunk = ceil_div(tiles, gy) * kTpTile;
+    if (chunk > ((int64_t)1 << 31)) chunk = (int64_t)1 << 31;  // per-lane counts stay below 2^32
+    gy = ceil_div(n2, chunk);
+    MX_REQUIRE(gy <= 65535, MX_ERR_SHAPE, "%s: set 2 too large", who);
+#define MX_TPACF(ME)                                                                                                \
+    hipLaunchKernelGGL(k_tpacf<ME>, dim3((unsigned)gx, (unsigned)gy), dim3(NT), 0, stream, x1_dev, y1_dev, z1_dev, \
+                       n1, x2_dev, y2_dev, z2_dev, n2, chunk, self_pairs ? 1 : 0, edges_dev, nedges,               \
+                       (unsigned long long *)counts_dev)
+    // register counts for the edges rounded up to a multiple of four
+    switch ((nedges + 3) / 4) {
+    case 0:
+    case 1: MX_TPACF(4); break;
+    case 2: MX_TPACF(8); break;
+    case 3: MX_TPACF(12); break;
+    case 4: MX_TPACF(16); break;
+    case 5: MX_TPACF(20); break;
+    case 6: MX_TPACF(24); break;
+    case 7: MX_TPACF(28); break;
+    default: MX_TPACF(32); break;
+    }
 #undef MX_TPACF
     return last_launch(who);
 }

@@ -143,6 +143,37 @@ def test_tpacf_counts_bit_exact(n1, n2, self_pairs, m):
     assert ref.sum() == (n1 * (n1 - 1) // 2 if self_pairs else n1 * n2)
 
 
+@pytest.mark.parametrize("n1,n2", [(300, 701), (4096, 4093)])
+@pytest.mark.parametrize("self_pairs", [False, True])
+@pytest.mark.parametrize("m", [3, 5, 9, 13, 17, 24, 27])
+def test_tpacf_every_edge_count_class(n1, n2, self_pairs, m):
+    say("tpacf edge class", n1, n2, self_pairs, m)
+    p1, p2 = sphere(n1, n1 + 3), sphere(n2, n2 + 5)
+    e = edges_of(m)
+    counts = torch.full((m + 1,), -1, dtype=torch.int64, device=DEV)
+    abi.mx_tpacf_f32(dev(p1), dev(p2), dev(e), counts, self_pairs)
+    assert np.array_equal(host(counts), O.tpacf(p1, p2, e, self_pairs))
+
+
+@pytest.mark.parametrize("self_pairs", [False, True])
+def test_tpacf_edges_equal_to_pair_dots(self_pairs):
+    # edges taken from binary32 dot products of actual pairs: those pairs sit
+    # exactly on an edge, which does not count them below it
+    n1, n2 = 2000, 1500
+    say("tpacf ties", n1, n2, self_pairs)
+    p1, p2 = sphere(n1, 41), sphere(n2, 43)
+    q = p1 if self_pairs else p2
+    rng = np.random.default_rng(5)
+    i, j = rng.integers(0, n1, 64), rng.integers(0, q.shape[1], 64)
+    d = (p1[0, i] * q[0, j] + p1[1, i] * q[1, j]) + p1[2, i] * q[2, j]
+    assert d.dtype == np.float32
+    u = np.unique(d)[::-1]  # decreasing edges
+    e = u[:: max(1, len(u) // 24)][:24].astype(np.float32)
+    counts = torch.full((len(e) + 1,), -1, dtype=torch.int64, device=DEV)
+    abi.mx_tpacf_f32(dev(p1), dev(p2), dev(e), counts, self_pairs)
+    assert np.array_equal(host(counts), O.tpacf(p1, p2, e, self_pairs))
+
+
 def test_tpacf_rejects_too_many_edges():
     p = dev(sphere(4, 0))
     with pytest.raises(abi.MxError) as err:
