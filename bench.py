@@ -890,7 +890,12 @@ def bench_parboil(args):
     def histo_small():
         abi.mx_histogram_u32(keys[4096], 4096, counts[4096])
 
-    def histo_large():
+    hws = torch.zeros(abi.mx_workspace_bytes(abi.MX_WS_HISTOGRAM, nkeys, 1 << 20), dtype=torch.uint8, device=dev)
+
+    def histo_large():  # bucketed: group keys by bucket of 2^11 bins, then LDS counts per bucket
+        abi.mx_histogram_u32(keys[1 << 20], 1 << 20, counts[1 << 20], hws)
+
+    def histo_large_atomics():  # the same without a workspace: one global atomic per key
         abi.mx_histogram_u32(keys[1 << 20], 1 << 20, counts[1 << 20])
 
     def stencil():
@@ -908,7 +913,11 @@ def bench_parboil(args):
 
     parts = {nm: per_launch_ms(f, reps=max(args.steps, 5), warmup=args.warmup)
              for nm, f in (("histo_4096_bins", histo_small), ("histo_2^20_bins", histo_large),
+                           ("histo_2^20_bins_global_atomics", histo_large_atomics),
                            ("stencil", stencil), ("mriq", mriq), ("tpacf", tpacf))}
+    histo_large()
+    assert np.array_equal(counts[1 << 20].cpu().numpy().astype(np.int64),
+                          np.bincount(keys_np[1 << 20], minlength=1 << 20)), "bucketed histogram"
     ms = timed_on(torch.cuda.current_stream(), step, args.steps, args.warmup)
     pts = nx * ny * nz
     pairs = nk * nv
@@ -936,6 +945,9 @@ def bench_parboil(args):
                                 "GB/s": round(gbs(4 * nkeys, parts["histo_4096_bins"]), 1)},
             "histo_2^20_bins": {"us": round(parts["histo_2^20_bins"] * 1e3, 1),
                                 "GB/s": round(gbs(4 * nkeys, parts["histo_2^20_bins"]), 1)},
+            "histo_2^20_bins_global_atomics": {"us": round(parts["histo_2^20_bins_global_atomics"] * 1e3, 1),
+                                               "GB/s": round(gbs(4 * nkeys, parts["histo_2^20_bins_global_atomics"]),
+                                                             1)},
             "stencil": {"us": round(parts["stencil"] * 1e3, 1), "GB/s": round(gbs(8 * pts, parts["stencil"]), 1),
                         "frac_hbm": round(gbs(8 * pts, parts["stencil"]) / HBM_PEAK_GBS, 4),
                         "traffic_bytes": traffic_of("stencil")},

@@ -90,8 +90,9 @@ typedef enum mx_binop {
 /* Workspace kinds for mx_workspace_bytes (other entry points have their own
  * size queries next to them). */
 typedef enum mx_ws_kind {
-    MX_WS_REDUCE = 0, /* mx_reduce, mx_map2_reduce: n = sequence length */
-    MX_WS_SCAN = 1    /* mx_lengths_to_offsets, mx_marshal_rows: n = number of rows */
+    MX_WS_REDUCE = 0,   /* mx_reduce, mx_map2_reduce: n = sequence length */
+    MX_WS_SCAN = 1,     /* mx_lengths_to_offsets, mx_marshal_rows: n = number of rows */
+    MX_WS_HISTOGRAM = 2 /* mx_histogram_u32: n = number of keys, aux = nbins; 0 = none used */
 } mx_ws_kind;
 
 /* ======================================================================= */
@@ -467,11 +468,17 @@ mx_status mx_batch_autotune(mx_batch_plan *plan, const float *A_dev, const float
 /* histo: counts[k] = #{i : keys[i] = k} for k < nbins (keys >= nbins fall in
  * no bin), a reduce-by-key with integer counts.  counts: nbins uint32 device
  * entries, overwritten.  0 <= n < 2^32 - 1.  Few bins (<= 32768) are counted
- * in per-block LDS histograms and flushed; more bins by global atomics.
- * Integer additions commute: the result does not depend on the order.
- * Errors: MX_ERR_SHAPE, MX_ERR_INVALID. */
-mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, uint32_t *counts_dev,
-                           hipStream_t stream);
+ * in per-block LDS histograms and flushed.  More bins, up to 2^27: with a
+ * workspace of mx_workspace_bytes(MX_WS_HISTOGRAM, n, nbins) bytes (zero-
+ * filled before first use, 256-byte aligned; the call leaves its counters at
+ * zero) the keys are first grouped by bucket of 2^11..2^15 bins and each
+ * bucket is counted in LDS by one block; with ws = NULL, or past 2^27 bins,
+ * by global atomics (slow: every key is a memory-side atomic).  ws is unused
+ * when the size query returns 0.  Integer additions commute: the result does
+ * not depend on the order.  Errors: MX_ERR_SHAPE, MX_ERR_INVALID,
+ * MX_ERR_WORKSPACE. */
+mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, uint32_t *counts_dev, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
 
 /* stencil: one Jacobi sweep of the 7-point stencil on an nx x ny x nz float32
  * grid (x fastest): out = c1 * (x- + x+ + y- + y+ + z- + z+, added in that

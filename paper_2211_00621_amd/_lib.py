@@ -73,7 +73,7 @@ SIGNATURES = {
     "mx_batch_forward_plain": (c_status, [c_p, c_p, c_p, c_p, c_p]),
     "mx_batch_backward_plain": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     "mx_batch_autotune": (c_status, [c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_size, ctypes.c_char_p, c_p, c_p]),
-    "mx_histogram_u32": (c_status, [c_p, c_i64, c_i64, c_p, c_p]),
+    "mx_histogram_u32": (c_status, [c_p, c_i64, c_i64, c_p, c_p, c_size, c_p]),
     "mx_stencil7_f32": (c_status, [c_p, c_p, c_i64, c_i64, c_i64, c_f32, c_f32, c_p]),
     "mx_mriq_f32": (c_status, [c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_i64, c_p, c_p, c_p]),
     "mx_tpacf_f32": (c_status, [c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_i64, c_int, c_p, c_int, c_p, c_p]),

@@ -22,7 +22,7 @@ MX_ADD, MX_MUL, MX_MIN, MX_MAX = 0, 1, 2, 3
 (MX_U_ID, MX_U_NEG, MX_U_ABS, MX_U_SQ, MX_U_AFFINE, MX_U_EXP, MX_U_LOG, MX_U_SQRT,
  MX_U_RSQRT) = range(9)
 MX_B_ADD, MX_B_SUB, MX_B_MUL, MX_B_DIV, MX_B_MIN, MX_B_MAX = range(6)
-MX_WS_REDUCE, MX_WS_SCAN = 0, 1
+MX_WS_REDUCE, MX_WS_SCAN, MX_WS_HISTOGRAM = 0, 1, 2
 (MX_X_IN, MX_X_CONST, MX_X_ADD, MX_X_SUB, MX_X_MUL, MX_X_DIV, MX_X_MIN, MX_X_MAX, MX_X_NEG, MX_X_ABS, MX_X_SQ,
  MX_X_EXP, MX_X_LOG, MX_X_SQRT, MX_X_RSQRT) = range(15)
 
@@ -437,9 +437,10 @@ def mx_batch_autotune(plan: BatchPlan, A, B, out, gout, gA, gB, ws, cache_path: 
 
 # ---------------------------------------------------------------- graphs
 # ---------------------------------------------------------------- Parboil-shaped kernels
-def mx_histogram_u32(keys, nbins: int, counts, stream=None) -> None:
-    _check(_L().mx_histogram_u32(_dptr(keys), keys.numel(), int(nbins), _dptr(counts), _stream(stream)),
-           "mx_histogram_u32")
+def mx_histogram_u32(keys, nbins: int, counts, ws=None, stream=None) -> None:
+    _check(_L().mx_histogram_u32(_dptr(keys), keys.numel(), int(nbins), _dptr(counts),
+                                 None if ws is None else _dptr(ws), 0 if ws is None else ws.numel(),
+                                 _stream(stream)), "mx_histogram_u32")
 
 
 def mx_stencil7_f32(grid_in, grid_out, c0: float, c1: float, stream=None) -> None:

@@ -16,9 +16,6 @@
 #include "mx_internal.h"
 
 namespace mx {
-mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, void *ws,
-                             size_t ws_bytes, hipStream_t s);
-
 namespace {
 
 constexpr int NT = 256;

@@ -42,6 +42,11 @@ bool debug_mode();
 // block-span segmented reduce: rows per block; debug-mode check of offsets
 int segmented_rows_per_block(int64_t nseg, const DeviceInfo *d);
 mx_status check_offsets_debug(const char *who, const int64_t *off, int64_t nseg, hipStream_t s);
+// exclusive scan of int64 lengths into nseg + 1 offsets (workspace kind MX_WS_SCAN)
+mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, void *ws, size_t ws_bytes,
+                             hipStream_t s);
+// bytes of the bucketed histogram's workspace (0: the call takes none)
+size_t histogram_ws_bytes(int64_t n, int64_t nbins);
 
 constexpr int kWave = 64;
 

@@ -1,7 +1,7 @@
 // Kernels of the shapes in the paper's Parboil comparison (Table 1): the
 // histogram reduce-by-key (histo), the neighbour-access map of a 7-point
-// stencil sweep (stencil), and the trigonometric per-output reduction over
-// samples (mri-q).  The paper's Futhark programs for these are compiled
+// stencil sweep (stencil), the trigonometric per-output reduction over
+// samples (mri-q) and the pairwise angular histogram (tpacf).  The paper's Futhark programs for these are compiled
 // whole; here each is one gfx950 kernel family behind the C ABI.
 #include <algorithm>
 #include <cmath>
@@ -81,6 +81,199 @@ __global__ void __launch_bounds__(NT) k_hist_global(const uint32_t *__restrict__
         const uint32_t k = keys[i];
         if ((int64_t)k < nbins) atomicAdd(&counts[k], 1u);
     }
+}
+
+// Many bins with a workspace: bucket the keys first.  Bucket b holds the
+// bins [b 2^w, (b + 1) 2^w), at most 4096 buckets of 2048..32768 bins.
+// (1) every block counts its chunk of keys per bucket in LDS and writes one
+// column of the bucket-major count matrix; (2) an exclusive scan of the
+// matrix gives every (bucket, block) its place; (3) every block re-reads its
+// chunk and writes each key's bin-within-bucket (16 bits) to its bucket's
+// range, places taken with LDS atomics; (4) one block per bucket counts its
+// range in an LDS histogram and writes the bucket's bins.  Every bin is
+// written once, by one block: no global atomics and no zero-fill of the
+// counts.  Global atomics on 2^20 counters cost a 32-byte memory-side write
+// each on this GPU; the four passes move about 12 bytes per key.
+constexpr int64_t kHbChunk = 16384;   // keys per block in passes 1 and 3 (at least)
+constexpr int64_t kHbMaxBlocks = 2048;
+constexpr int64_t kHbMaxBuckets = 4096;
+constexpr int kHbMinShift = 11, kHbMaxShift = 15;
+constexpr int NTB = 1024;  // threads per bucket block in pass 4
+
+struct HbPlan {
+    bool ok;            // the bucketed passes apply
+    int w;              // log2 of the bins per bucket
+    int64_t nb, g;      // buckets, blocks of passes 1 and 3
+    int64_t chunk;      // keys per block (a multiple of 4)
+    size_t scan_bytes, cnt_off, off_off, sorted_off, bytes;
+};
+
+HbPlan hb_plan(int64_t n, int64_t nbins) {
+    HbPlan p{};
+    int w = kHbMinShift;
+    while (w < kHbMaxShift && ((int64_t)512 << w) < nbins) ++w;  // about 512 buckets where possible
+    p.w = w;
+    p.nb = ceil_div(nbins, (int64_t)1 << w);
+    p.ok = nbins > kHistLdsBins && p.nb <= kHbMaxBuckets;
+    p.g = std::min<int64_t>(kHbMaxBlocks, std::max<int64_t>(1, ceil_div(n, kHbChunk)));
+    p.chunk = ceil_div(ceil_div(std::max<int64_t>(n, 1), p.g), (int64_t)4) * 4;
+    const int64_t m = p.g * p.nb;
+    p.scan_bytes = mx_workspace_bytes(MX_WS_SCAN, m, 0);
+    p.cnt_off = align256(p.scan_bytes);
+    p.off_off = p.cnt_off + align256((size_t)m * 8);
+    p.sorted_off = p.off_off + align256((size_t)(m + 1) * 8);
+    p.bytes = p.sorted_off + align256((size_t)std::max<int64_t>(n, 1) * 2);
+    return p;
+}
+
+// Passes 1 and 3 walk their block's keys in pieces of kHbPiece, every thread
+// loading its kHbPiece / NTS keys of the piece before it uses any (all loads
+// in flight at once; keys past the end read as ~0, which no bin takes).
+constexpr int kHbPiece = 16384;
+constexpr int NTS = 1024;  // threads per block of passes 1 and 3
+constexpr int kHbKpt = kHbPiece / NTS;
+
+__device__ __forceinline__ void hb_load_piece(const uint32_t *__restrict__ keys, int64_t p0, int cnt,
+                                              uint32_t (&kk)[kHbKpt]) {
+#pragma unroll
+    for (int u = 0; u < kHbKpt; ++u) {
+        const int i = (int)threadIdx.x + u * NTS;
+        kk[u] = i < cnt ? keys[p0 + i] : ~0u;
+    }
+}
+
+__global__ void __launch_bounds__(NTS) k_hb_count(const uint32_t *__restrict__ keys, int64_t n, int64_t nbins,
+                                                  int64_t chunk, int w, int nb, int64_t g,
+                                                  int64_t *__restrict__ cnt) {
+    extern __shared__ uint32_t bc[];
+    for (int b = threadIdx.x; b < nb; b += NTS) bc[b] = 0u;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t p0 = lo; p0 < hi; p0 += kHbPiece) {
+        uint32_t kk[kHbKpt];
+        hb_load_piece(keys, p0, (int)(hi - p0 < kHbPiece ? hi - p0 : kHbPiece), kk);
+#pragma unroll
+        for (int u = 0; u < kHbKpt; ++u)
+            if ((int64_t)kk[u] < nbins) atomicAdd(&bc[kk[u] >> w], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += NTS) cnt[(int64_t)b * g + blockIdx.x] = bc[b];
+}
+
+// In-place exclusive scan of a[0..m) in LDS by the whole block of BS
+// threads; returns the total.  Thread t owns the entries [t per, (t + 1) per).
+template <int BS> __device__ __forceinline__ uint32_t hb_block_scan(uint32_t *a, int m) {
+    __shared__ uint32_t wsum[BS / 64];
+    const int per = (m + BS - 1) / BS;
+    const int b0 = threadIdx.x * per, b1 = b0 + per < m ? b0 + per : m;
+    uint32_t s = 0u;
+    for (int i = b0; i < b1; ++i) s += a[i];
+    uint32_t x = s;  // inclusive scan over the wave
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint32_t base = 0u, total = 0u;
+#pragma unroll
+    for (int q = 0; q < BS / 64; ++q) {
+        if (q < (int)(threadIdx.x >> 6)) base += wsum[q];
+        total += wsum[q];
+    }
+    uint32_t run = base + x - s;
+    for (int i = b0; i < b1; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Pass 3, per piece: rank each key within its bucket (LDS atomics, ranks kept
+// in registers), scan the piece's bucket counts, stage the keys in LDS in
+// bucket order, then write each bucket's run to its place: consecutive lanes
+// write consecutive 16-bit entries.  LDS: 2 nb words + 2 kHbPiece half-words.
+__global__ void __launch_bounds__(NTS) k_hb_scatter(const uint32_t *__restrict__ keys, int64_t n, int64_t nbins,
+                                                    int64_t chunk, int w, int nb, int64_t g,
+                                                    const int64_t *__restrict__ off,
+                                                    uint16_t *__restrict__ sorted) {
+    extern __shared__ uint32_t sm[];
+    uint32_t *lc = sm, *cur = sm + nb;
+    uint16_t *sbin = reinterpret_cast<uint16_t *>(sm + 2 * nb), *sbkt = sbin + kHbPiece;
+    for (int b = threadIdx.x; b < nb; b += NTS) cur[b] = (uint32_t)off[(int64_t)b * g + blockIdx.x];
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const uint32_t mask = (1u << w) - 1u;
+    for (int64_t p0 = lo; p0 < hi; p0 += kHbPiece) {
+        uint32_t kk[kHbKpt], rk[kHbKpt];
+        hb_load_piece(keys, p0, (int)(hi - p0 < kHbPiece ? hi - p0 : kHbPiece), kk);
+        for (int b = threadIdx.x; b < nb; b += NTS) lc[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kHbKpt; ++u) rk[u] = (int64_t)kk[u] < nbins ? atomicAdd(&lc[kk[u] >> w], 1u) : 0u;
+        __syncthreads();
+        const uint32_t tot = hb_block_scan<NTS>(lc, nb);
+#pragma unroll
+        for (int u = 0; u < kHbKpt; ++u) {
+            if ((int64_t)kk[u] < nbins) {
+                const uint32_t pos = lc[kk[u] >> w] + rk[u];
+                sbin[pos] = (uint16_t)(kk[u] & mask);
+                sbkt[pos] = (uint16_t)(kk[u] >> w);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < (int)tot; i += NTS) {
+            const int b = sbkt[i];
+            sorted[cur[b] + ((uint32_t)i - lc[b])] = sbin[i];
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += NTS) cur[b] += (b + 1 < nb ? lc[b + 1] : tot) - lc[b];
+        __syncthreads();
+    }
+}
+
+// Pass 4: one block per bucket; 16-byte loads of eight entries, four in
+// flight per thread, between an unaligned head and tail.
+__global__ void __launch_bounds__(NTB) k_hb_bins(const uint16_t *__restrict__ sorted, const int64_t *__restrict__ off,
+                                                 int64_t g, int w, int64_t nbins, uint32_t *__restrict__ counts) {
+    extern __shared__ uint32_t h[];
+    const int nbb = 1 << w;
+    for (int i = threadIdx.x; i < nbb; i += NTB) h[i] = 0u;
+    __syncthreads();
+    const int64_t b = blockIdx.x;
+    const int64_t s = off[b * g], e = off[(b + 1) * g];
+    int64_t a0 = (s + 7) & ~(int64_t)7;
+    if (a0 > e) a0 = e;
+    for (int64_t i = s + threadIdx.x; i < a0; i += NTB) atomicAdd(&h[sorted[i]], 1u);
+    const int64_t nv = (e - a0) / 8, a1 = a0 + nv * 8;
+    const uint4 *v = reinterpret_cast<const uint4 *>(sorted + a0);
+    auto count8 = [&](uint4 q) {
+        atomicAdd(&h[q.x & 0xffffu], 1u);
+        atomicAdd(&h[q.x >> 16], 1u);
+        atomicAdd(&h[q.y & 0xffffu], 1u);
+        atomicAdd(&h[q.y >> 16], 1u);
+        atomicAdd(&h[q.z & 0xffffu], 1u);
+        atomicAdd(&h[q.z >> 16], 1u);
+        atomicAdd(&h[q.w & 0xffffu], 1u);
+        atomicAdd(&h[q.w >> 16], 1u);
+    };
+    int64_t j = threadIdx.x;
+    for (; j + 3 * NTB < nv; j += 4 * NTB) {
+        const uint4 q0 = v[j], q1 = v[j + NTB], q2 = v[j + 2 * NTB], q3 = v[j + 3 * NTB];
+        count8(q0);
+        count8(q1);
+        count8(q2);
+        count8(q3);
+    }
+    for (; j < nv; j += NTB) count8(v[j]);
+    for (int64_t i = a1 + threadIdx.x; i < e; i += NTB) atomicAdd(&h[sorted[i]], 1u);
+    __syncthreads();
+    const int64_t base = b << w;
+    const int64_t m = nbins - base < nbb ? nbins - base : nbb;
+    for (int64_t i = threadIdx.x; i < m; i += NTB) counts[base + i] = h[i];
 }
 
 // ---------------------------------------------------------------- stencil
@@ -350,26 +543,53 @@ __global__ void __launch_bounds__(NT) k_zero64(unsigned long long *__restrict__ 
 }
 
 }  // namespace
+
+size_t histogram_ws_bytes(int64_t n, int64_t nbins) {
+    if (n < 0 || nbins < 1) return 0;
+    const HbPlan p = hb_plan(n, nbins);
+    return p.ok ? p.bytes : 0;
+}
+
 }  // namespace mx
 
 using namespace mx;
 
 extern "C" {
 
-mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, uint32_t *counts_dev,
-                           hipStream_t stream) {
+mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, uint32_t *counts_dev, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
     const char *who = "mx_histogram_u32";
     MX_REQUIRE(n >= 0 && n < (int64_t)0xffffffff, MX_ERR_SHAPE, "%s: need 0 <= n < 2^32 - 1", who);
     MX_REQUIRE(nbins >= 1 && nbins <= ((int64_t)1 << 32), MX_ERR_SHAPE, "%s: need 1 <= nbins <= 2^32", who);
     MX_REQUIRE(counts_dev && (keys_dev || n == 0), MX_ERR_INVALID, "%s: null pointer", who);
     const DeviceInfo *d;
     if (mx_status st = device_info(&d)) return st;
+    const int vec = ((uintptr_t)keys_dev & 15) == 0;
+    const HbPlan p = hb_plan(n, nbins);
+    if (ws && p.ok && n > 0) {
+        MX_REQUIRE(ws_bytes >= p.bytes, MX_ERR_WORKSPACE, "%s: workspace needs %zu bytes", who, p.bytes);
+        MX_REQUIRE(((uintptr_t)ws & 255) == 0, MX_ERR_INVALID, "%s: workspace must be 256-byte aligned", who);
+        MX_REQUIRE(((int64_t)4 << p.w) <= (int64_t)d->lds_bytes, MX_ERR_UNSUPPORTED, "%s: LDS too small", who);
+        char *base = (char *)ws;
+        int64_t *cnt = (int64_t *)(base + p.cnt_off), *off = (int64_t *)(base + p.off_off);
+        uint16_t *sorted = (uint16_t *)(base + p.sorted_off);
+        const size_t lds_nb = (size_t)p.nb * 4;
+        hipLaunchKernelGGL(k_hb_count, dim3((unsigned)p.g), dim3(NTS), lds_nb, stream, keys_dev, n, nbins, p.chunk,
+                           p.w, (int)p.nb, p.g, cnt);
+        if (mx_status st = last_launch(who)) return st;
+        if (mx_status st = lengths_to_offsets(cnt, p.g * p.nb, off, ws, p.scan_bytes, stream)) return st;
+        hipLaunchKernelGGL(k_hb_scatter, dim3((unsigned)p.g), dim3(NTS), 2 * lds_nb + 2 * kHbPiece * 2, stream,
+                           keys_dev, n, nbins, p.chunk, p.w, (int)p.nb, p.g, (const int64_t *)off, sorted);
+        if (mx_status st = last_launch(who)) return st;
+        hipLaunchKernelGGL(k_hb_bins, dim3((unsigned)p.nb), dim3(NTB), (size_t)4 << p.w, stream,
+                           (const uint16_t *)sorted, (const int64_t *)off, p.g, p.w, nbins, counts_dev);
+        return last_launch(who);
+    }
     const int64_t zb = ceil_div(nbins, NT);
     hipLaunchKernelGGL(k_zero32, dim3((unsigned)(zb < d->num_cus * 8 ? zb : d->num_cus * 8)), dim3(NT), 0, stream,
                        counts_dev, nbins);
     if (mx_status st = last_launch(who)) return st;
     if (n == 0) return MX_OK;
-    const int vec = ((uintptr_t)keys_dev & 15) == 0;
     if (nbins <= kHistLdsBins && (size_t)(nbins + 1) * 4 <= (size_t)d->lds_bytes) {
         // as many blocks as fit the CUs' LDS (at most eight per CU); each
         // block's flush adds at most nbins global atomics

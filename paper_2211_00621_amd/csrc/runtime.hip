@@ -110,6 +110,7 @@ size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux) {
         int64_t tiles = (n + 4095) / 4096 + 1;
         return kCounterBytes + align256((size_t)tiles * 8);
     }
+    case MX_WS_HISTOGRAM: return histogram_ws_bytes(n, aux);
     }
     return 0;
 }

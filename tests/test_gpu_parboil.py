@@ -1,6 +1,7 @@
 """GPU parity of the Parboil-shaped kernels against the oracle: histogram
-counts bit-exact (LDS and global paths, skewed and uniform keys, keys past the
-last bin, misaligned and empty inputs, 2^24 keys); one 7-point stencil sweep
+counts bit-exact (LDS, bucketed and global paths, skewed and uniform keys,
+keys past the last bin, one repeated key, misaligned and empty inputs, 2^24
+keys, up to 2^27 bins); one 7-point stencil sweep
 within a bound derived from its six additions and three roundings; mri-q
 within a bound from the rounding of t, the sin / cos error (2 ulp) and the
 FP32 sums.  Inputs are seeded synthetic stand-ins for the Parboil datasets."""
@@ -37,25 +38,75 @@ def keys_for(kind, n, nbins, seed):
     return k.astype(np.uint32)
 
 
+def hist_ws(n, nbins):
+    nbytes = abi.mx_workspace_bytes(abi.MX_WS_HISTOGRAM, n, nbins)
+    return torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=DEV) if nbytes else None
+
+
 @pytest.mark.parametrize("nbins", [1, 7, 4096, 32768, 32769, 1 << 20])
 @pytest.mark.parametrize("kind", ["uniform", "skewed"])
 @pytest.mark.parametrize("n", [0, 3, 100001])
-def test_histogram(nbins, kind, n):
-    say("histogram", nbins, kind, n)
+@pytest.mark.parametrize("with_ws", [False, True])
+def test_histogram(nbins, kind, n, with_ws):
+    say("histogram", nbins, kind, n, with_ws)
     keys = keys_for(kind, n, nbins, nbins + n)
     counts = torch.full((nbins,), 7, dtype=torch.int32, device=DEV)   # overwritten, not added to
-    abi.mx_histogram_u32(dev(keys).view(torch.int32), nbins, counts)
+    abi.mx_histogram_u32(dev(keys).view(torch.int32), nbins, counts, hist_ws(n, nbins) if with_ws else None)
     assert np.array_equal(host(counts).astype(np.int64), O.histogram(keys, nbins))
 
 
 @pytest.mark.parametrize("nbins", [256, 1 << 20])
-def test_histogram_misaligned_and_large(nbins):
-    say("histogram large", nbins)
+@pytest.mark.parametrize("with_ws", [False, True])
+def test_histogram_misaligned_and_large(nbins, with_ws):
+    say("histogram large", nbins, with_ws)
     n = (1 << 24) + 3
     keys = keys_for("skewed", n + 1, nbins, 5)
     counts = torch.empty(nbins, dtype=torch.int32, device=DEV)
-    abi.mx_histogram_u32(dev(keys).view(torch.int32)[1:], nbins, counts)
+    abi.mx_histogram_u32(dev(keys).view(torch.int32)[1:], nbins, counts, hist_ws(n, nbins) if with_ws else None)
     assert np.array_equal(host(counts).astype(np.int64), O.histogram(keys[1:], nbins))
+
+
+@pytest.mark.parametrize("nbins", [32769, 65543, 3_000_001, 1 << 24, 1 << 27])
+@pytest.mark.parametrize("kind", ["uniform", "skewed", "one_key", "past_end"])
+def test_histogram_bucketed(nbins, kind):
+    # bucket widths 2^11 .. 2^15 and up to 4096 buckets; one key repeated
+    # (every key in one bucket and one bin); keys mostly past the last bin
+    n = 300_007
+    say("histogram bucketed", nbins, kind, n)
+    if kind == "one_key":
+        keys = np.full(n, nbins - 1, np.uint32)
+    elif kind == "past_end":
+        keys = np.random.default_rng(3).integers(nbins - 50, nbins + 50, n).astype(np.uint32)
+    else:
+        keys = keys_for(kind, n, nbins, 11)
+    ws = hist_ws(n, nbins)
+    assert ws is not None
+    counts = torch.full((nbins,), 7, dtype=torch.int32, device=DEV)
+    abi.mx_histogram_u32(dev(keys).view(torch.int32), nbins, counts, ws)
+    got = host(counts).astype(np.int64)
+    ref = O.histogram(keys, nbins)
+    assert np.array_equal(got, ref)
+
+
+def test_histogram_bucketed_reuses_workspace():
+    # the same workspace for a large call then a smaller one: its scan
+    # counters are back at zero after each call
+    nbins = 1 << 20
+    ws = hist_ws(1 << 22, nbins)
+    for n, seed in ((1 << 22, 1), (70_001, 2), (1 << 22, 3)):
+        keys = keys_for("skewed", n, nbins, seed)
+        counts = torch.empty(nbins, dtype=torch.int32, device=DEV)
+        abi.mx_histogram_u32(dev(keys).view(torch.int32), nbins, counts, ws)
+        assert np.array_equal(host(counts).astype(np.int64), O.histogram(keys, nbins)), n
+
+
+def test_histogram_rejects_small_workspace():
+    nbins, n = 1 << 20, 4096
+    ws = torch.zeros(abi.mx_workspace_bytes(abi.MX_WS_HISTOGRAM, n, nbins) - 256, dtype=torch.uint8, device=DEV)
+    keys = dev(np.zeros(n, np.uint32)).view(torch.int32)
+    with pytest.raises(abi.MxError) as err:
+        abi.mx_histogram_u32(keys, nbins, torch.empty(nbins, dtype=torch.int32, device=DEV), ws)
+    assert err.value.status == abi.MX_ERR_WORKSPACE
 
 
 def stencil_bound(g, c0, c1):
