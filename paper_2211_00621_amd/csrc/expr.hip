@@ -39,7 +39,7 @@ namespace {
 constexpr int kRegs = 16, kMaxInsn = 64, kMaxIn = 4;
 constexpr int NT = 256;          // threads per block of every generated kernel
 constexpr int kGroupsPerIt = 4;  // vector groups per thread and loop iteration
-constexpr int kMaxRedBlocks = 4096;
+constexpr int kMaxRedBlocks = 2048;  // eight per CU resident at once: one round, longer-lived threads
 
 bool reads_a(int op) { return op >= MX_X_ADD; }
 bool reads_b(int op) { return op >= MX_X_ADD && op <= MX_X_MAX; }

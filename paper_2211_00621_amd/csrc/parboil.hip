@@ -523,19 +523,22 @@ __global__ void __launch_bounds__(NT) k_tpacf(const float *__restrict__ x1, cons
         unsigned long long prev = total;
 #pragma unroll
         for (int k = 0; k <= ME; ++k) {
-            if (k > m) break;
-            const unsigned long long wk =
-                (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)wbelow, k < NS ? k : 0) |
-                (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(wbelow >> 32), k < NS ? k : 0)
-                    << 32;
-            const unsigned long long next = k == m ? 0ull : k < NS ? wk : wv[k >= NS && k - NS < NV ? k - NS : 0];
-            const unsigned long long c = prev - next;
-            if (c) atomicAdd(&red[k], c);
-            prev = next;
+            if (k <= m) {
+                const unsigned long long wk =
+                    (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)wbelow, k < NS ? k : 0) |
+                    (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(wbelow >> 32),
+                                                                            k < NS ? k : 0)
+                        << 32;
+                const unsigned long long next =
+                    k == m ? 0ull : k < NS ? wk : wv[k >= NS && k - NS < NV ? k - NS : 0];
+                const unsigned long long c = prev - next;
+                if (c) atomicAdd(&red[k], c);
+                prev = next;
+            }
         }
     }
     __syncthreads();
-    if (threadIdx.x <= m && red[threadIdx.x]) atomicAdd(&counts[threadIdx.x], red[threadIdx.x]);
+    if ((int)threadIdx.x <= m && red[threadIdx.x]) atomicAdd(&counts[threadIdx.x], red[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(NT) k_zero64(unsigned long long *__restrict__ p, int m) {
