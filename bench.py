@@ -848,9 +848,14 @@ def bench_expr(args):
 
 # ============================================================ Parboil-shaped kernels
 # VALU instructions per (voxel, sample) pair in the inner loop of k_mriq
-# (gfx950 ISA: 89 per sample for the thread's two voxels; sincospi is a
-# polynomial on the VALU, no transcendental unit).
-MRIQ_VALU_PER_PAIR = 44.5
+# (gfx950 ISA: 73 per four samples for the thread's two voxels, of which 16
+# are v_sin / v_cos on the transcendental unit).
+MRIQ_VALU_PER_PAIR = 9.125
+# VALU instructions per pair in the inner loop of k_tpacf<20> (gfx950 ISA:
+# 141 per four columns of 64 pairs, i.e. per lane and column: the dot product,
+# 20 compares, 10 per-lane count updates with their selects); the scalar
+# unit adds 87 instructions per four columns alongside.
+TPACF_VALU_PER_PAIR = 35.25
 
 
 def bench_parboil(args):
@@ -924,6 +929,8 @@ def bench_parboil(args):
     tp_pairs = npt * (npt - 1) // 2 + npt * npt
     elems = 2 * nkeys + pts + pairs + tp_pairs
     mriq_peak = LANE_OPS_PER_S / MRIQ_VALU_PER_PAIR
+    tp_peak = LANE_OPS_PER_S / TPACF_VALU_PER_PAIR
+    tp_rate = tp_pairs / (parts["tpacf"] * 1e-3)
     mriq_rate = pairs / (parts["mriq"] * 1e-3)
     log(f"parboil: step {ms:.3f} ms; " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in parts.items()))
     line = {
@@ -935,11 +942,11 @@ def bench_parboil(args):
                                "2048 samples x 2^18 voxels, tpacf DD + DR pair counts of 2^15 + 2^15 points on "
                                "the sphere in 21 angular bins", "keys": nkeys, "grid": [nz, ny, nx],
                    "mriq": [nk, nv], "tpacf_points": npt, "elements_per_step": elems},
-        "roofline": {"bound": "alu", "kernel": "k_mriq", "achieved": round(mriq_rate / 1e9, 1),
-                     "peak": round(mriq_peak / 1e9, 1), "unit": "Gpair/s", "frac": round(mriq_rate / mriq_peak, 4),
+        "roofline": {"bound": "alu", "kernel": "k_tpacf<20>", "achieved": round(tp_rate / 1e9, 1),
+                     "peak": round(tp_peak / 1e9, 1), "unit": "Gpair/s", "frac": round(tp_rate / tp_peak, 4),
                      "traffic": None,
                      "peak_basis": f"FP32 vector peak as lane operations (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) / "
-                                   f"{MRIQ_VALU_PER_PAIR} VALU instructions per pair"},
+                                   f"{TPACF_VALU_PER_PAIR} VALU instructions per pair"},
         "parts": {
             "histo_4096_bins": {"us": round(parts["histo_4096_bins"] * 1e3, 1),
                                 "GB/s": round(gbs(4 * nkeys, parts["histo_4096_bins"]), 1)},
@@ -951,9 +958,11 @@ def bench_parboil(args):
             "stencil": {"us": round(parts["stencil"] * 1e3, 1), "GB/s": round(gbs(8 * pts, parts["stencil"]), 1),
                         "frac_hbm": round(gbs(8 * pts, parts["stencil"]) / HBM_PEAK_GBS, 4),
                         "traffic_bytes": traffic_of("stencil")},
-            "mriq": {"us": round(parts["mriq"] * 1e3, 1), "Gpair/s": round(mriq_rate / 1e9, 1)},
+            "mriq": {"us": round(parts["mriq"] * 1e3, 1), "Gpair/s": round(mriq_rate / 1e9, 1),
+                     "frac_alu": round(mriq_rate / mriq_peak, 4),
+                     "alu_basis": f"{MRIQ_VALU_PER_PAIR} VALU instructions per pair"},
             "tpacf": {"us": round(parts["tpacf"] * 1e3, 1), "pairs": tp_pairs,
-                      "Gpair/s": round(tp_pairs / (parts["tpacf"] * 1e-3) / 1e9, 1)},
+                      "Gpair/s": round(tp_rate / 1e9, 1), "frac_alu": round(tp_rate / tp_peak, 4)},
         },
     }
     if not args.no_cpu_baseline:
