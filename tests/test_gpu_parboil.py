@@ -3,8 +3,8 @@ counts bit-exact (LDS, bucketed and global paths, skewed and uniform keys,
 keys past the last bin, one repeated key, misaligned and empty inputs, 2^24
 keys, up to 2^27 bins); one 7-point stencil sweep
 within a bound derived from its six additions and three roundings; mri-q
-within a bound from the rounding of t, the sin / cos error (2 ulp) and the
-FP32 sums.  Inputs are seeded synthetic stand-ins for the Parboil datasets."""
+within a bound from the rounding of t, the sin / cos error (4 units of 2^-24
+per sample, checked on its own) and the FP32 sums.  Inputs are seeded synthetic stand-ins for the Parboil datasets."""
 import numpy as np
 import pytest
 import torch
@@ -156,6 +156,25 @@ def test_mriq(nk, nv):
     rr, ri = O.mriq(*k, phi, *x)
     b = mriq_bound(k, phi, x, np.arange(nv))
     assert np.all(np.abs(host(qr) - rr) <= b) and np.all(np.abs(host(qi) - ri) <= b)
+
+
+def test_mriq_trig_error_per_sample():
+    # one sample k = (1, 0, 0), phi = 1: t = x exactly, so Qr, Qi are the
+    # kernel's cos(2 pi x), sin(2 pi x) alone; each within the 4 units of
+    # 2^-24 per sample that mriq_bound allows, over |x| <= 24 and near the
+    # multiples of 1/4 where one of them passes through zero
+    rng = np.random.default_rng(9)
+    near = (np.arange(-96, 97) / 4.0)[:, None] + rng.uniform(-1e-3, 1e-3, (193, 256))
+    xs = np.concatenate([rng.uniform(-24, 24, 1 << 20), near.ravel()]).astype(np.float32)
+    nv = xs.size
+    say("mriq trig", nv)
+    one, zero = np.ones(1, np.float32), np.zeros(1, np.float32)
+    zv = np.zeros(nv, np.float32)
+    qr, qi = torch.empty(nv, device=DEV), torch.empty(nv, device=DEV)
+    abi.mx_mriq_f32(dev(one), dev(zero), dev(zero), dev(one), dev(xs), dev(zv), dev(zv), qr, qi)
+    ang = 2 * np.pi * xs.astype(np.float64)
+    assert np.max(np.abs(host(qr) - np.cos(ang))) <= 4 * U32
+    assert np.max(np.abs(host(qi) - np.sin(ang))) <= 4 * U32
 
 
 def test_mriq_full_size_sampled():
