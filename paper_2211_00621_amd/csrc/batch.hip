@@ -156,21 +156,20 @@ __global__ void __launch_bounds__(NT) k_batch_fwd(const TaskDev *__restrict__ ta
                         const int64_t nb4 = (c - head) >> 2;
                         const float4 *row4 = reinterpret_cast<const float4 *>(row + head);
                         if (l < head) ac[1] += row[l] * xs[l];
-                        int64_t v = l;
-                        for (; v + 112 < nb4; v += 128) {
+                        // eight loads per lane in flight, the last round
+                        // predicated (a row's remainder is not a latency chain)
+                        for (int64_t v = l; v < nb4; v += 128) {
                             float4 av[8];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) av[u] = row4[v + 16 * u];
+                            for (int u = 0; u < 8; ++u)
+                                av[u] = v + 16 * u < nb4 ? row4[v + 16 * u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
-                                const float *xq = xs + head + 4 * (v + 16 * u);
-                                ac[u & 3] += av[u].x * xq[0] + av[u].y * xq[1] + av[u].z * xq[2] + av[u].w * xq[3];
+                                if (v + 16 * u < nb4) {
+                                    const float *xq = xs + head + 4 * (v + 16 * u);
+                                    ac[u & 3] += av[u].x * xq[0] + av[u].y * xq[1] + av[u].z * xq[2] + av[u].w * xq[3];
+                                }
                             }
-                        }
-                        for (; v < nb4; v += 16) {
-                            const float4 av = row4[v];
-                            const float *xq = xs + head + 4 * v;
-                            ac[0] += av.x * xq[0] + av.y * xq[1] + av.z * xq[2] + av.w * xq[3];
                         }
                         const int64_t t0 = head + 4 * nb4;
                         if (t0 + l < c) ac[2] += row[t0 + l] * xs[t0 + l];
