@@ -57,16 +57,16 @@ TRAFFIC = {
                  "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
     # mx_xvjp (generated from expr.hip) for exp(-(a-b)^2)*0.5 + a*b over 2^26 float32 pairs:
     # 536.88 MB fetched + 536.80 MB written (1.00x algorithmic)
-    "expr_vjp": {"file": "expr.hip", "bytes": 1073676274,
-                 "source": "da65ca9cb0b18a684c21ff5f0ca0f47be33a71041a9b97dc929f5df378312b14"},
+    "expr_vjp": {"file": "expr.hip", "bytes": 1073676893,
+                 "source": "69c512abf2ff185acf077b11dc4aa21aa7cc9d06465aee3d177aeccebbfac52c"},
     # mx_xseg_add, same body over the nested step's 65 536 ragged rows (2 x 32.1 M values):
-    # 261.11 MB fetched + 0.26 MB written (1.01x algorithmic)
-    "expr_seg": {"file": "expr.hip", "bytes": 261376808,
-                 "source": "da65ca9cb0b18a684c21ff5f0ca0f47be33a71041a9b97dc929f5df378312b14"},
+    # 261.06 MB fetched + 0.26 MB written (1.01x algorithmic)
+    "expr_seg": {"file": "expr.hip", "bytes": 261321064,
+                 "source": "69c512abf2ff185acf077b11dc4aa21aa7cc9d06465aee3d177aeccebbfac52c"},
     # k_stencil7, 512 x 512 x 64 float32: 73.15 MB fetched (1.09x: a 16-plane slab re-reads the planes
     # below and above it) + 67.10 MB written
-    "stencil": {"file": "parboil.hip", "bytes": 140248657,
-                "source": "a85c233f0f2efcbe1ea708769446e4797e6404877700e6c64a64e8d486b480b7"},
+    "stencil": {"file": "parboil.hip", "bytes": 140253326,
+                "source": "616fad6f5a4c32f9c06d15eeaea3a06add9e913267c81ae25e8cdb82a823a13f"},
     # k_seg_broadcast: 1.61 MB fetched (offsets, gradients) + 128.83 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 130405516,
                       "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
@@ -339,7 +339,7 @@ def cpu_baseline_nested(d, rows, C, gA, gB, gvals, offsets):
     torch.cuda.synchronize()
     log("nested: cpu baseline (oracle)")
     L, v, A, B, G, g = d["L"], d["v"], d["A"], d["B"], d["G"], d["g_rows"]
-    sample_rows = 128
+    sample_rows = 256
     t0 = time.perf_counter()
     off = O.offsets_from_lengths(L)
     R = O.segmented_reduce(O.ADD, 0.0, v, off)
@@ -968,21 +968,25 @@ def bench_parboil(args):
     if not args.no_cpu_baseline:
         import oracle as O
         log("parboil: cpu baseline (oracle)")
-        sample_v = 2048
+        sample_v, sample_p = 1 << 16, 8192
         g0n = g0.cpu().numpy()
         kn = [t.cpu().numpy() for t in kxyz]
         xn = [t[:sample_v].cpu().numpy() for t in xyz]
+        s0, s1 = sph[0].cpu().numpy(), sph[1].cpu().numpy()
+        e_np = tp_edges.cpu().numpy()
         t0 = time.perf_counter()
         for nb, k in keys_np.items():
             O.histogram(k, nb)
         O.stencil7(g0n, 1.0 / 6.0, 0.125)
         O.mriq(*kn, phi.cpu().numpy(), *xn)
+        O.tpacf(s0[:, :sample_p], s1, e_np, False)
         secs = time.perf_counter() - t0
-        n_done = 2 * nkeys + pts + nk * sample_v
+        n_done = 2 * nkeys + pts + nk * sample_v + sample_p * npt
         line["cpu_baseline"] = {"value": n_done / secs, "unit": "elem/s", "cores": cpu_threads(), "kind": "oracle",
                                 "seconds": round(secs, 2),
                                 "sample": f"both histograms and the stencil sweep in full, mri-q for the first "
-                                          f"{sample_v} of the 2^18 voxels"}
+                                          f"{sample_v} of the 2^18 voxels, tpacf cross pairs of the first {sample_p} "
+                                          f"data points with all 2^15 random points"}
     return line
 
 

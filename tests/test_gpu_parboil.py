@@ -100,6 +100,35 @@ def test_histogram_bucketed_reuses_workspace():
         assert np.array_equal(host(counts).astype(np.int64), O.histogram(keys, nbins)), n
 
 
+def test_histogram_bucketed_graph_replay():
+    # the four bucketed passes captured in one HIP graph: every replay, with
+    # eager work between them, gives the eager counts (the scan's counters
+    # and status words are back at zero after each call, no memset nodes)
+    nbins, n = 1 << 20, 1 << 21
+    say("histogram graph", nbins, n)
+    keys_np = keys_for("skewed", n, nbins, 21)
+    keys = dev(keys_np).view(torch.int32)
+    ws = hist_ws(n, nbins)
+    counts = torch.empty(nbins, dtype=torch.int32, device=DEV)
+    abi.mx_histogram_u32(keys, nbins, counts, ws)
+    eager = host(counts).copy()
+    assert np.array_equal(eager.astype(np.int64), O.histogram(keys_np, nbins))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        abi.mx_graph_begin(s)
+        abi.mx_histogram_u32(keys, nbins, counts, ws, stream=s)
+        g = abi.mx_graph_end(s)
+    other = torch.empty(nbins, dtype=torch.int32, device=DEV)
+    for rep in range(3):
+        counts.fill_(-1)
+        abi.mx_histogram_u32(keys[: n // 2], nbins, other, ws)   # eager use of the same workspace
+        torch.cuda.synchronize()
+        abi.mx_graph_launch(g, s)
+        s.synchronize()
+        assert np.array_equal(host(counts), eager), rep
+    abi.mx_graph_destroy(g)
+
+
 def test_histogram_rejects_small_workspace():
     nbins, n = 1 << 20, 4096
     ws = torch.zeros(abi.mx_workspace_bytes(abi.MX_WS_HISTOGRAM, n, nbins) - 256, dtype=torch.uint8, device=DEV)
