@@ -73,3 +73,16 @@ def test_argument_errors_before_any_device_work(lib):
     assert lib.mx_map_map_reduce_f32(2, 0, 4, 4, 4, fake, fake, fake, None) == abi.MX_ERR_INVALID
     assert lib.mx_records_to_fields(fake, 4, 17, 4, None, None) == abi.MX_ERR_INVALID
     assert "mx_records_to_fields" in lib.mx_last_error().decode()
+
+
+def test_histogram_workspace_sizes(lib):
+    # the bucketed histogram needs a workspace only past the LDS histogram's
+    # 32 768 bins and up to 2^27 bins; it grows with the keys (16 bits each)
+    from paper_2211_00621_amd import abi
+    ws = lambda n, nbins: lib.mx_workspace_bytes(abi.MX_WS_HISTOGRAM, n, nbins)  # noqa: E731
+    assert ws(1 << 24, 4096) == 0 and ws(1 << 24, 32768) == 0
+    assert ws(1 << 24, (1 << 27) + 1) == 0 and ws(1 << 24, 0) == 0
+    big, small = ws(1 << 24, 1 << 20), ws(1 << 20, 1 << 20)
+    assert big % 256 == 0 and small % 256 == 0
+    assert big - small >= 2 * ((1 << 24) - (1 << 20))
+    assert ws(100, 1 << 27) > 0 and ws(0, 1 << 20) > 0
