@@ -25,26 +25,36 @@ __global__ void __launch_bounds__(NT) k_zero32(uint32_t *__restrict__ p, int64_t
 // `copies` > 1 lane l counts into copy l % copies (copies nbins + 1 words
 // apart, so equal bins of different copies sit in different banks): lanes of
 // one instruction that hit the same bin wait for each other `copies` times
-// less.  Integer additions commute, so the counts do not depend on the order.
-__global__ void __launch_bounds__(NT) k_hist_lds(const uint32_t *__restrict__ keys, int64_t n, int nbins,
+// less.  Blocks of 1024 threads: the copies fill 64 KiB at 4096 bins, so two
+// blocks fit a CU, and 32 waves keep the key loads and atomics in flight.
+// Integer additions commute, so the counts do not depend on the order.
+constexpr int NTH = 1024;
+__global__ void __launch_bounds__(NTH) k_hist_lds(const uint32_t *__restrict__ keys, int64_t n, int nbins,
                                                  int copies, uint32_t *__restrict__ counts, int vec) {
     extern __shared__ uint32_t hist_all[];
     const int stride = nbins + 1;
-    for (int b = threadIdx.x; b < stride * copies; b += NT) hist_all[b] = 0u;
+    for (int b = threadIdx.x; b < stride * copies; b += NTH) hist_all[b] = 0u;
     __syncthreads();
     uint32_t *hist = hist_all + (threadIdx.x % copies) * stride;
-    const int64_t tid = (int64_t)blockIdx.x * NT + threadIdx.x, nt = (int64_t)gridDim.x * NT;
+    const int64_t tid = (int64_t)blockIdx.x * NTH + threadIdx.x, nt = (int64_t)gridDim.x * NTH;
     const uint32_t nb = (uint32_t)nbins;
     int64_t done = 0;
     if (vec) {
         const int64_t nv = n / 4;
         const uint4 *kv = reinterpret_cast<const uint4 *>(keys);
-        for (int64_t j = tid; j < nv; j += nt) {
-            const uint4 k = kv[j];
-            if (k.x < nb) atomicAdd(&hist[k.x], 1u);
-            if (k.y < nb) atomicAdd(&hist[k.y], 1u);
-            if (k.z < nb) atomicAdd(&hist[k.z], 1u);
-            if (k.w < nb) atomicAdd(&hist[k.w], 1u);
+        // four 16-byte loads in flight before their atomics (keys past the
+        // end read as ~0, which no bin takes)
+        for (int64_t j = tid; j < nv; j += 4 * nt) {
+            uint4 k[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) k[u] = j + u * nt < nv ? kv[j + u * nt] : make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k[u].x < nb) atomicAdd(&hist[k[u].x], 1u);
+                if (k[u].y < nb) atomicAdd(&hist[k[u].y], 1u);
+                if (k[u].z < nb) atomicAdd(&hist[k[u].z], 1u);
+                if (k[u].w < nb) atomicAdd(&hist[k[u].w], 1u);
+            }
         }
         done = nv * 4;
     }
@@ -53,7 +63,7 @@ __global__ void __launch_bounds__(NT) k_hist_lds(const uint32_t *__restrict__ ke
         if (k < nb) atomicAdd(&hist[k], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += NT) {
+    for (int b = threadIdx.x; b < nbins; b += NTH) {
         uint32_t c = 0u;
         for (int q = 0; q < copies; ++q) c += hist_all[q * stride + b];
         if (c) atomicAdd(&counts[b], c);
@@ -607,9 +617,9 @@ mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, u
         const int copies = (int)std::max<int64_t>(1, std::min<int64_t>(4, 16383 / (nbins + 1)));
         const size_t lds = (size_t)(nbins + 1) * copies * 4;
         const int64_t per_cu = std::min<int64_t>(8, std::max<int64_t>(1, (int64_t)d->lds_bytes / (int64_t)lds));
-        int64_t grid = ceil_div(n, (int64_t)NT * 64);
+        int64_t grid = ceil_div(n, (int64_t)NTH * 64);
         if (grid > d->num_cus * per_cu) grid = d->num_cus * per_cu;
-        hipLaunchKernelGGL(k_hist_lds, dim3((unsigned)grid), dim3(NT), lds, stream, keys_dev, n, (int)nbins, copies,
+        hipLaunchKernelGGL(k_hist_lds, dim3((unsigned)grid), dim3(NTH), lds, stream, keys_dev, n, (int)nbins, copies,
                            counts_dev, vec);
     } else {
         int64_t grid = ceil_div(n, (int64_t)NT * 16);
