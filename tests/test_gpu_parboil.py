@@ -273,6 +273,26 @@ def test_tpacf_edges_equal_to_pair_dots(self_pairs):
     assert np.array_equal(host(counts), O.tpacf(p1, p2, e, self_pairs))
 
 
+def test_tpacf_full_size():
+    # the bench's launch: 2^15 + 2^15 points, 20 edges.  The full counts hold
+    # n (n - 1) / 2 and n^2 pairs; the cross counts of the first 2048 data
+    # points against all 2^15 random points (the same two-dimensional grid
+    # over set 2) match the oracle bit for bit
+    n, m = 1 << 15, 20
+    say("tpacf full size", n, m)
+    d, r = sphere(n, 101), sphere(n, 102)
+    e = edges_of(m)
+    dd = torch.empty(m + 1, dtype=torch.int64, device=DEV)
+    dr = torch.empty(m + 1, dtype=torch.int64, device=DEV)
+    abi.mx_tpacf_f32(dev(d), dev(d), dev(e), dd, True)
+    abi.mx_tpacf_f32(dev(d), dev(r), dev(e), dr, False)
+    assert host(dd).sum() == n * (n - 1) // 2 and host(dr).sum() == n * n
+    assert np.all(host(dd) >= 0) and np.all(host(dr) >= 0)
+    part = torch.empty(m + 1, dtype=torch.int64, device=DEV)
+    abi.mx_tpacf_f32(dev(d[:, :2048]), dev(r), dev(e), part, False)
+    assert np.array_equal(host(part), O.tpacf(d[:, :2048], r, e, False))
+
+
 def test_tpacf_rejects_too_many_edges():
     p = dev(sphere(4, 0))
     with pytest.raises(abi.MxError) as err:
