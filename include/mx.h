@@ -483,14 +483,18 @@ mx_status mx_histogram_u32(const uint32_t *keys_dev, int64_t n, int64_t nbins, u
 /* stencil: one Jacobi sweep of the 7-point stencil on an nx x ny x nz float32
  * grid (x fastest): out = c1 * (x- + x+ + y- + y+ + z- + z+, added in that
  * order) - c0 * centre at interior points, every operation rounded on its
- * own; boundary points are copied.  in and out must not overlap. */
+ * own; boundary points are copied.  in and out must not overlap.
+ * Errors: MX_ERR_SHAPE (an empty grid, a plane or nz beyond the launch
+ * limits), MX_ERR_INVALID (null or identical grids). */
 mx_status mx_stencil7_f32(const float *in_dev, float *out_dev, int64_t nx, int64_t ny, int64_t nz, float c0,
                           float c1, hipStream_t stream);
 
 /* mri-q: for voxels (x_i, y_i, z_i) and samples (kx_k, ky_k, kz_k, phi_k),
  * Qr_i = sum_k phi_k cos(2 pi t_ik), Qi_i = sum_k phi_k sin(2 pi t_ik),
  * t_ik = kx_k x_i + ky_k y_i + kz_k z_i (FP32, samples in order; sin and cos
- * of 2 pi t computed as sinpi / cospi of the exact 2t). */
+ * of 2 pi t from the hardware sine and cosine of the exactly reduced
+ * revolution t - rint(t), absolute error at most 1.26e-7 as measured against
+ * binary64).  Errors: MX_ERR_SHAPE, MX_ERR_INVALID. */
 mx_status mx_mriq_f32(const float *kx_dev, const float *ky_dev, const float *kz_dev, const float *phi_dev,
                       int64_t nk, const float *x_dev, const float *y_dev, const float *z_dev, int64_t nv,
                       float *qr_dev, float *qi_dev, hipStream_t stream);
