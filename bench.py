@@ -851,11 +851,11 @@ def bench_expr(args):
 # (gfx950 ISA: 73 per four samples for the thread's two voxels, of which 16
 # are v_sin / v_cos on the transcendental unit).
 MRIQ_VALU_PER_PAIR = 9.125
-# VALU instructions per pair in the inner loop of k_tpacf<20> (gfx950 ISA:
-# 141 per four columns of 64 pairs, i.e. per lane and column: the dot product,
-# 20 compares, 10 per-lane count updates with their selects); the scalar
-# unit adds 87 instructions per four columns alongside.
-TPACF_VALU_PER_PAIR = 35.25
+# VALU instructions per pair in the inner loop of k_tpacf<32> (gfx950 ISA:
+# 89 per four pairs: the dot product, a five-level binary search over the
+# edges, two levels from registers and three LDS probes, and the counter
+# address); 12 LDS reads and 4 LDS adds per four pairs alongside.
+TPACF_VALU_PER_PAIR = 22.25
 
 
 def bench_parboil(args):
@@ -942,7 +942,7 @@ def bench_parboil(args):
                                "2048 samples x 2^18 voxels, tpacf DD + DR pair counts of 2^15 + 2^15 points on "
                                "the sphere in 21 angular bins", "keys": nkeys, "grid": [nz, ny, nx],
                    "mriq": [nk, nv], "tpacf_points": npt, "elements_per_step": elems},
-        "roofline": {"bound": "alu", "kernel": "k_tpacf<20>", "achieved": round(tp_rate / 1e9, 1),
+        "roofline": {"bound": "alu", "kernel": "k_tpacf<32>", "achieved": round(tp_rate / 1e9, 1),
                      "peak": round(tp_peak / 1e9, 1), "unit": "Gpair/s", "frac": round(tp_rate / tp_peak, 4),
                      "traffic": None,
                      "peak_basis": f"FP32 vector peak as lane operations (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) / "

@@ -385,89 +385,38 @@ __global__ void __launch_bounds__(NT) k_mriq(const float *__restrict__ kx, const
 // ---------------------------------------------------------------- tpacf
 // Angular pair counts: a thread owns one point of set 1 and walks set 2 in
 // LDS tiles (broadcast reads); per pair the binary32 dot product (three
-// products, two additions, each rounded) and, for every edge e_b, whether
-// d < e_b.  Only block totals are wanted, so these running counts below[b]
-// are kept two ways and the vector and scalar units share the work: for the
-// first NS edges the wave counts its lanes at once (a 64-bit compare mask,
-// popcount and add on the scalar unit), for the rest every lane keeps its own
-// count in a register (compare, add with carry).  No atomics and no indexed
-// register writes in the loop.  Bin k holds below[k-1] - below[k] pairs.  The
-// grid is two-dimensional: blockIdx.x picks 256 points of set 1, blockIdx.y a
-// chunk of set 2, so a few thousand blocks fill the chip even when set 1 is
-// small.  Each wave's bins go to LDS and each block bin to the global int64
-// counts with one atomic add; integer sums, so the result does not depend on
-// the order.
+// products, two additions, each rounded) and its bin k = #{b : d < e_b}.  The
+// edges decrease, so {b : d < e_b} is a prefix and k is found by a binary
+// search over a table of TB = 32 (or 64, for 32 edges) edges padded with -inf
+// (d < -inf never holds, so the search never passes the m real edges), each
+// probe one float compare of d with an edge as the definition has it; the
+// first two levels' three pivots sit in registers, the rest are LDS reads
+// (a chain of dependent reads: four pairs are searched side by side, and the
+// counters take only m + 1 bins of LDS so more blocks share a CU).  Each thread then
+// adds one to its own counter of bin k: counter (k, t) sits at word
+// k * NT + t, so the 64 lanes of a wave always hit 64 different banks and the
+// add needs no ordering.  The grid is two-dimensional: blockIdx.x picks 256
+// points of set 1, blockIdx.y a chunk of set 2, so a few thousand blocks fill
+// the chip even when set 1 is small.  The block's counters are summed per bin
+// (wave trees, then one LDS atomic per wave) and each bin goes to the global
+// int64 counts with one atomic add; integer sums, so the result does not
+// depend on the order.
 constexpr int kTpTile = 256;
 constexpr int kTpMaxEdges = 32;
+constexpr int kTpBins = kTpMaxEdges + 1;
 
-// edges counted per wave on the scalar unit: a vector-counted edge costs two
-// vector instructions per pair, a wave-counted one a vector compare plus 1.75
-// scalar instructions per 64 pairs (four columns share one add).  The time
-// follows the total instruction count more than the split (measured nearly
-// flat from a half to seven eighths); half was the fastest.
-constexpr int tp_wave_edges(int me) { return me / 2; }
-
-// One tile: pairs (i, j) for j in [j0, cnt).  MASKED: some lanes have no point
-// or need j >= jlo (self pairs); their d becomes +inf, below no edge.
-template <int ME, bool MASKED>
-__device__ __forceinline__ void tp_tile(const float4 *__restrict__ tile, int j0, int cnt, int jlo, bool has,
-                                        float xi, float yi, float zi, const float (&e)[ME],
-                                        unsigned (&ws)[tp_wave_edges(ME)],
-                                        unsigned (&run)[ME - tp_wave_edges(ME)]) {
-#pragma clang fp contract(off)
-    constexpr int NS = tp_wave_edges(ME);
-    int j = j0;
-    if (!MASKED) {
-        // four pairs columns at a time: the wave-counted edges add four
-        // popcounts on the scalar unit before one add into their running count
-        for (; j + 4 <= cnt; j += 4) {
-            float d[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const float4 q = tile[j + u];
-                d[u] = xi * q.x;
-                d[u] = d[u] + yi * q.y;
-                d[u] = d[u] + zi * q.z;
-            }
-#pragma unroll
-            for (int b = 0; b < NS; ++b) {
-                unsigned c = 0u;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) c += (unsigned)__popcll(__ballot(d[u] < e[b]));
-                ws[b] += c;
-                // one edge's four masks live at a time (scalar registers)
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int b = NS; b < ME; ++b) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) run[b - NS] += d[u] < e[b] ? 1u : 0u;
-            }
-        }
-    }
-    for (; j < cnt; ++j) {
-        const float4 q = tile[j];
-        float d = xi * q.x;
-        d = d + yi * q.y;
-        d = d + zi * q.z;
-        if (MASKED) d = has && j >= jlo ? d : INFINITY;
-#pragma unroll
-        for (int b = 0; b < NS; ++b) ws[b] += (unsigned)__popcll(__ballot(d < e[b]));
-#pragma unroll
-        for (int b = NS; b < ME; ++b) run[b - NS] += d < e[b] ? 1u : 0u;
-    }
-}
-
-template <int ME>  // edges handled, >= m (registers for the running counts)
+template <int TB>  // probe table size: edges, then -inf
 __global__ void __launch_bounds__(NT) k_tpacf(const float *__restrict__ x1, const float *__restrict__ y1,
                                               const float *__restrict__ z1, int64_t n1,
                                               const float *__restrict__ x2, const float *__restrict__ y2,
                                               const float *__restrict__ z2, int64_t n2, int64_t chunk,
                                               int self, const float *__restrict__ edges, int m,
                                               unsigned long long *__restrict__ counts) {
-    constexpr int NS = tp_wave_edges(ME), NV = ME - NS;
+#pragma clang fp contract(off)
     __shared__ float4 tile[kTpTile];
-    __shared__ unsigned long long red[kTpMaxEdges + 1];
+    __shared__ float et[TB];
+    __shared__ unsigned long long red[kTpBins];
+    extern __shared__ uint32_t cnt[];  // [m + 1][NT]
     const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
     // this block's part of set 2; self pairs need only j > i, and the block's
     // smallest i bounds the part it needs (whole-block exit, before any barrier)
@@ -475,82 +424,67 @@ __global__ void __launch_bounds__(NT) k_tpacf(const float *__restrict__ x1, cons
     const int64_t jend = c0 + chunk < n2 ? c0 + chunk : n2;
     const int64_t jstart = self && (int64_t)blockIdx.x * NT + 1 > c0 ? (int64_t)blockIdx.x * NT + 1 : c0;
     if (jstart >= jend) return;
-    // the wave's first point (wave-uniform)
-    const int64_t w0 = (int64_t)blockIdx.x * NT + __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
+    for (int b = threadIdx.x; b < TB; b += NT) et[b] = b < m ? edges[b] : -INFINITY;
+    for (int b = threadIdx.x; b < (m + 1) * NT; b += NT) cnt[b] = 0u;
+    if (threadIdx.x < kTpBins) red[threadIdx.x] = 0ull;
     const bool has = i < n1;
     const float xi = has ? x1[i] : 0.f, yi = has ? y1[i] : 0.f, zi = has ? z1[i] : 0.f;
-    float e[ME];
-#pragma unroll
-    for (int b = 0; b < ME; ++b) {
-        e[b] = b < m ? edges[b] : -INFINITY;  // past m: never counted
-        // keep the edges in vector registers: the scalar ones hold the wave counts
-        asm volatile("" : "+v"(e[b]));
-    }
-    // wave counts: edge b's in lane b of one 64-bit register (scalar
-    // registers would not hold them all); lane counts in below[] (a chunk
-    // holds fewer than 2^32 points)
-    unsigned long long wbelow = 0ull;
-    unsigned below[NV > 0 ? NV : 1];
-    const int lane = (int)threadIdx.x & 63;
-#pragma unroll
-    for (int b = 0; b < NV; ++b) below[b] = 0u;
-    unsigned long long total = 0;
-    if (threadIdx.x <= kTpMaxEdges) red[threadIdx.x] = 0ull;
+    uint32_t *mine = cnt + threadIdx.x;  // bin k of this thread at mine[k * NT]
     for (int64_t t0 = jstart; t0 < jend; t0 += kTpTile) {
-        const int cnt = (int)(jend - t0 < kTpTile ? jend - t0 : kTpTile);
+        const int ct = (int)(jend - t0 < kTpTile ? jend - t0 : kTpTile);
         __syncthreads();
-        for (int j = threadIdx.x; j < cnt; j += NT) tile[j] = make_float4(x2[t0 + j], y2[t0 + j], z2[t0 + j], 0.f);
+        for (int j = threadIdx.x; j < ct; j += NT) tile[j] = make_float4(x2[t0 + j], y2[t0 + j], z2[t0 + j], 0.f);
         __syncthreads();
-        if (w0 >= n1) continue;  // the whole wave is past set 1
-        const int jlo = self ? (int)(i + 1 - t0 > 0 ? (i + 1 - t0 < cnt ? i + 1 - t0 : cnt) : 0) : 0;
-        unsigned ws[NS > 0 ? NS : 1], run[NV > 0 ? NV : 1];
+        if (!has) continue;
+        const float p1 = et[TB / 2 - 1], p2lo = et[TB / 4 - 1], p2hi = et[3 * TB / 4 - 1];
+        const int jlo = self ? (int)(i + 1 - t0 > 0 ? (i + 1 - t0 < ct ? i + 1 - t0 : ct) : 0) : 0;
+        // four pairs at a time: their searches interleave (the counter adds,
+        // LDS writes, come after all four); byte offsets k4 = 4 k into the
+        // table, so each probe is one LDS read at k4 plus a constant
+        const char *etb = reinterpret_cast<const char *>(et);
+        char *mb = reinterpret_cast<char *>(mine);
+        int j = jlo;
+        for (; j + 4 <= ct; j += 4) {
+            float d[4];
+            uint32_t k4[4];
 #pragma unroll
-        for (int b = 0; b < NS; ++b) ws[b] = 0u;
+            for (int u = 0; u < 4; ++u) {
+                const float4 q = tile[j + u];
+                d[u] = xi * q.x;
+                d[u] = d[u] + yi * q.y;
+                d[u] = d[u] + zi * q.z;
+                k4[u] = d[u] < p1 ? 4u * (TB / 2) : 0u;
+                k4[u] += d[u] < (k4[u] ? p2hi : p2lo) ? 4u * (TB / 4) : 0u;
+            }
 #pragma unroll
-        for (int b = 0; b < NV; ++b) run[b] = 0u;
-        if (w0 + 64 <= n1 && (!self || t0 >= w0 + 64)) {
-            tp_tile<ME, false>(tile, 0, cnt, 0, true, xi, yi, zi, e, ws, run);
-        } else {
-            // first j any lane of the wave needs
-            const int jw = self ? (int)(w0 + 1 - t0 > 0 ? (w0 + 1 - t0 < cnt ? w0 + 1 - t0 : cnt) : 0) : 0;
-            tp_tile<ME, true>(tile, jw, cnt, jlo, has, xi, yi, zi, e, ws, run);
+            for (int s = TB / 8; s >= 1; s >>= 1)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    k4[u] += d[u] < *reinterpret_cast<const float *>(etb + k4[u] + 4 * (s - 1)) ? 4u * s : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)  // this thread's own counters: no other lane adds to them
+                atomicAdd(reinterpret_cast<uint32_t *>(mb + (size_t)k4[u] * NT), 1u);
         }
-        if (has) total += (unsigned long long)(cnt - jlo);
+        for (; j < ct; ++j) {
+            const float4 q = tile[j];
+            float d = xi * q.x;
+            d = d + yi * q.y;
+            d = d + zi * q.z;
+            int k = d < p1 ? TB / 2 : 0;
+            k += d < (k ? p2hi : p2lo) ? TB / 4 : 0;
 #pragma unroll
-        for (int b = 0; b < NS; ++b) wbelow += lane == b ? (unsigned long long)ws[b] : 0ull;
-#pragma unroll
-        for (int b = 0; b < NV; ++b) below[b] += run[b];
+            for (int s = TB / 8; s >= 1; s >>= 1) k += d < et[k + s - 1] ? s : 0;
+            atomicAdd(&mine[k * NT], 1u);
+        }
     }
-    // wave sums of the lane counts, bins per wave into LDS, one atomic per bin
+    // per bin: the block's 256 counters, a wave tree each, one LDS atomic per
+    // wave, one global atomic per bin
     __syncthreads();
-    unsigned long long wv[NV > 0 ? NV : 1];
-#pragma unroll
-    for (int b = 0; b < NV; ++b) {
-        unsigned long long c = below[b];
+    for (int k = 0; k <= m; ++k) {
+        unsigned long long c = cnt[k * NT + threadIdx.x];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-        wv[b] = c;
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o, 64);
-    if ((threadIdx.x & 63) == 0 && w0 < n1) {
-        // static register indices: fully unrolled over the ME + 1 bins
-        unsigned long long prev = total;
-#pragma unroll
-        for (int k = 0; k <= ME; ++k) {
-            if (k <= m) {
-                const unsigned long long wk =
-                    (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)wbelow, k < NS ? k : 0) |
-                    (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(wbelow >> 32),
-                                                                            k < NS ? k : 0)
-                        << 32;
-                const unsigned long long next =
-                    k == m ? 0ull : k < NS ? wk : wv[k >= NS && k - NS < NV ? k - NS : 0];
-                const unsigned long long c = prev - next;
-                if (c) atomicAdd(&red[k], c);
-                prev = next;
-            }
-        }
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd(&red[k], c);
     }
     __syncthreads();
     if ((int)threadIdx.x <= m && red[threadIdx.x]) atomicAdd(&counts[threadIdx.x], red[threadIdx.x]);
@@ -674,26 +608,18 @@ mx_status mx_tpacf_f32(const float *x1_dev, const float *y1_dev, const float *z1
     if (gy > 65535) gy = 65535;
     if (gy < 1) gy = 1;
     int64_t chunk = ceil_div(tiles, gy) * kTpTile;
-    if (chunk > ((int64_t)1 << 31)) chunk = (int64_t)1 << 31;  // per-lane counts stay below 2^32
+    if (chunk > ((int64_t)1 << 31)) chunk = (int64_t)1 << 31;  // per-thread counts stay below 2^32
     gy = ceil_div(n2, chunk);
     MX_REQUIRE(gy <= 65535, MX_ERR_SHAPE, "%s: set 2 too large", who);
-#define MX_TPACF(ME)                                                                                                \
-    hipLaunchKernelGGL(k_tpacf<ME>, dim3((unsigned)gx, (unsigned)gy), dim3(NT), 0, stream, x1_dev, y1_dev, z1_dev, \
-                       n1, x2_dev, y2_dev, z2_dev, n2, chunk, self_pairs ? 1 : 0, edges_dev, nedges,               \
-                       (unsigned long long *)counts_dev)
-    // register counts for the edges rounded up to a multiple of four
-    switch ((nedges + 3) / 4) {
-    case 0:
-    case 1: MX_TPACF(4); break;
-    case 2: MX_TPACF(8); break;
-    case 3: MX_TPACF(12); break;
-    case 4: MX_TPACF(16); break;
-    case 5: MX_TPACF(20); break;
-    case 6: MX_TPACF(24); break;
-    case 7: MX_TPACF(28); break;
-    default: MX_TPACF(32); break;
-    }
-#undef MX_TPACF
+const size_t lds = (size_t)(nedges + 1) * NT * 4;
+    if (nedges < 32)
+        hipLaunchKernelGGL(k_tpacf<32>, dim3((unsigned)gx, (unsigned)gy), dim3(NT), lds, stream, x1_dev, y1_dev,
+                           z1_dev, n1, x2_dev, y2_dev, z2_dev, n2, chunk, self_pairs ? 1 : 0, edges_dev, nedges,
+                           (unsigned long long *)counts_dev);
+    else
+        hipLaunchKernelGGL(k_tpacf<64>, dim3((unsigned)gx, (unsigned)gy), dim3(NT), lds, stream, x1_dev, y1_dev,
+                           z1_dev, n1, x2_dev, y2_dev, z2_dev, n2, chunk, self_pairs ? 1 : 0, edges_dev, nedges,
+                           (unsigned long long *)counts_dev);
     return last_launch(who);
 }
 
