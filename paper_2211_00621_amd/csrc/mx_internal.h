@@ -246,11 +246,4 @@ template <class Op, int NT, class T> __device__ __forceinline__ T block_reduce(T
     return r;
 }
 
-// ---------------------------------------------------------------- cross-block tickets
-// Release the block's prior global writes at device scope and take a ticket.
-__device__ __forceinline__ unsigned take_ticket(unsigned *counter) {
-    __threadfence();
-    return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 }  // namespace mx
