@@ -503,7 +503,8 @@ mx_status mx_mriq_f32(const float *kx_dev, const float *ky_dev, const float *kz_
  * similarity is the float32 dot product x1 x2 + y1 y2 + z1 z2 (each product
  * and addition rounded on its own); with the decreasing float32 edges
  * e_0 > ... > e_{m-1} (cosines of increasing angles, device array, m <= 32)
- * the pair falls in bin #{b : d < e_b}, one of m + 1 bins; counts: m + 1
+ * the pair falls in bin #{b : d < e_b}, one of m + 1 bins (found by binary
+ * search, so edges that increase anywhere give undefined bins); counts: m + 1
  * int64 device entries, overwritten.  self_pairs != 0: the pairs i < j of set
  * 1 (set 2 ignored); else all pairs of set 1 x set 2.  Integer counts,
  * bit-exact and order-free.  Errors: MX_ERR_SHAPE, MX_ERR_UNSUPPORTED (m >
