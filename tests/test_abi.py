@@ -86,3 +86,25 @@ def test_histogram_workspace_sizes(lib):
     assert big % 256 == 0 and small % 256 == 0
     assert big - small >= 2 * ((1 << 24) - (1 << 20))
     assert ws(100, 1 << 27) > 0 and ws(0, 1 << 20) > 0
+
+
+def test_parboil_argument_errors_before_any_device_work(lib):
+    # size, operand and workspace checks of the Parboil-shaped entry points
+    # happen on the host, before any launch
+    from paper_2211_00621_amd import abi
+    fake = ctypes.c_void_p(4096)
+    other = ctypes.c_void_p(8192)
+    assert lib.mx_histogram_u32(fake, -1, 16, fake, None, 0, None) == abi.MX_ERR_SHAPE
+    assert lib.mx_histogram_u32(fake, 16, 0, fake, None, 0, None) == abi.MX_ERR_SHAPE
+    assert lib.mx_histogram_u32(fake, 16, 16, None, None, 0, None) == abi.MX_ERR_INVALID
+    assert lib.mx_stencil7_f32(fake, fake, 8, 8, 8, ctypes.c_float(0.5), ctypes.c_float(0.1), None) == \
+        abi.MX_ERR_INVALID
+    assert lib.mx_stencil7_f32(fake, other, 0, 8, 8, ctypes.c_float(0.5), ctypes.c_float(0.1), None) == \
+        abi.MX_ERR_SHAPE
+    assert lib.mx_mriq_f32(fake, fake, fake, fake, -1, fake, fake, fake, 4, fake, fake, None) == abi.MX_ERR_SHAPE
+    assert lib.mx_mriq_f32(fake, fake, fake, fake, 4, None, fake, fake, 4, fake, fake, None) == abi.MX_ERR_INVALID
+    assert lib.mx_tpacf_f32(fake, fake, fake, 4, fake, fake, fake, 4, 0, fake, 33, fake, None) == \
+        abi.MX_ERR_UNSUPPORTED
+    assert lib.mx_tpacf_f32(fake, fake, fake, -1, fake, fake, fake, 4, 0, fake, 20, fake, None) == abi.MX_ERR_SHAPE
+    assert lib.mx_tpacf_f32(fake, fake, fake, 4, fake, fake, fake, 4, 0, fake, 20, None, None) == abi.MX_ERR_INVALID
+    assert "mx_tpacf_f32" in lib.mx_last_error().decode()
