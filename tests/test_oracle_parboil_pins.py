@@ -74,7 +74,7 @@ def test_tpacf_is_binary32_dot_and_searchsorted():
     d = (p1[0][:, None] * p2[0][None, :]).astype(np.float32)                # numpy float32: each op rounded
     d = (d + (p1[1][:, None] * p2[1][None, :]).astype(np.float32)).astype(np.float32)
     d = (d + (p1[2][:, None] * p2[2][None, :]).astype(np.float32)).astype(np.float32)
-    bins = np.searchsorted(-edges, -d.ravel(), side="right")   # #{b : d < e_b} via the ascending -e
+    bins = np.searchsorted(-edges, -d.ravel(), side="left")    # #{b : -e_b < -d} = #{b : d < e_b}
     ref = np.bincount(bins, minlength=edges.size + 1)
     assert np.array_equal(O.tpacf(p1, p2, edges, False), ref)
     got_self = O.tpacf(p1, None, edges, True)
@@ -82,3 +82,18 @@ def test_tpacf_is_binary32_dot_and_searchsorted():
     full = O.tpacf(p1, p1, edges, False)                       # all ordered pairs incl. i == j
     diag = O.tpacf(p1[:, :1], p1[:, :1], edges, False)         # a single self pair lands in bin 0 or 1
     assert full.sum() == 120 * 120 and diag.sum() == 1
+
+
+def test_tpacf_pair_on_an_edge_is_not_below_it():
+    # edges equal to binary32 dot products of actual pairs: d < e_b is strict,
+    # so such a pair counts in the bin after the edge, not before it
+    p1, p2 = _sphere(40, 5), _sphere(30, 6)
+    d = (p1[0][:, None] * p2[0][None, :]).astype(np.float32)
+    d = (d + (p1[1][:, None] * p2[1][None, :]).astype(np.float32)).astype(np.float32)
+    d = (d + (p1[2][:, None] * p2[2][None, :]).astype(np.float32)).astype(np.float32)
+    edges = np.unique(d.ravel())[::-1][::97][:12].astype(np.float32)   # decreasing, every one a pair's d
+    strict = np.bincount(np.searchsorted(-edges, -d.ravel(), side="left"), minlength=edges.size + 1)
+    loose = np.bincount(np.searchsorted(-edges, -d.ravel(), side="right"), minlength=edges.size + 1)
+    got = O.tpacf(p1, p2, edges, False)
+    assert np.array_equal(got, strict) and not np.array_equal(got, loose)
+
