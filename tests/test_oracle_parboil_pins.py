@@ -96,4 +96,12 @@ def test_tpacf_pair_on_an_edge_is_not_below_it():
     loose = np.bincount(np.searchsorted(-edges, -d.ravel(), side="right"), minlength=edges.size + 1)
     got = O.tpacf(p1, p2, edges, False)
     assert np.array_equal(got, strict) and not np.array_equal(got, loose)
+    # edges one ulp above pairs' dot products: those pairs are below them, so
+    # a dot product rounded differently (a fused multiply-add, another order)
+    # moves a pair across an edge in one of the two cases
+    for e in (np.unique(d.ravel())[::-1][::37][:32],
+              np.unique(np.nextafter(d.ravel(), np.float32(np.inf)))[::-1][::37][:32]):
+        e = e.astype(np.float32)
+        ref = np.bincount(np.searchsorted(-e, -d.ravel(), side="left"), minlength=e.size + 1)
+        assert np.array_equal(O.tpacf(p1, p2, e, False), ref)
 
