@@ -157,3 +157,13 @@ def test_loop_scatter_identity_and_permutation_and_skips():
     idx[3], idx[5] = -1, 77                   # outside the output: not written
     got = O.expr_loop_scatter(GAUSS_DOT, 2, [a, b], idx, np.full(77, 9.0))
     assert got[3] == 9.0 and got[5] == 9.0 and np.array_equal(np.delete(got, [3, 5]), np.delete(vals, [3, 5]))
+
+
+def test_min_max_return_the_first_operand_on_ties():
+    # min a b = (b < a ? b : a) and max a b = (b > a ? b : a): on equal
+    # values (here +0 and -0) the first operand comes back, sign included
+    a = np.array([0.0, -0.0, 1.0], dtype=np.float64)
+    b = np.array([-0.0, 0.0, 1.0], dtype=np.float64)
+    for xop in (O.X_MIN, O.X_MAX):
+        got = O.expr_map([IN(0, 0), IN(1, 1), OP(xop, 2, 0, 1)], 2, a, b)
+        assert np.array_equal(np.signbit(got), np.signbit(a)) and np.array_equal(got, a)
