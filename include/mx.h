@@ -588,8 +588,8 @@ mx_status mx_expr_map_reduce(mx_expr *e, mx_redop op, const void *const *in_dev,
 mx_status mx_expr_segmented_reduce(mx_expr *e, mx_redop op, const void *const *in_dev, const int64_t *offsets_dev,
                                    int64_t nseg, const void *ne_host, void *out_dev, hipStream_t stream);
 
-/* The parallel loop of the CUDA backend (Section 4.1, `loop n f` with f
- * writing tensor slots): for every i < n, out[index[i]] = body(x_i).
+/* The parallel loop of the CUDA backend (Appendix A, Source Language: `loop n f`
+ * calls f i for every i in [0, n) in an undefined order; here f writes tensor slots): for every i < n, out[index[i]] = body(x_i).
  * Iterations run in parallel in no particular order, so the result is defined
  * when the indices are distinct -- the user's guarantee, as in the paper.
  * index: n int64 device entries; out: out_len device elements, slots no index

@@ -635,10 +635,13 @@ double or_expr_map_foldl_f64(int op, double ne, const int32_t *code, const doubl
  * input k, with s_i = (gout ? gout[i] : 1) * (gscale ? *gscale : 1).  Adjoints
  * flow from the output back through the instructions in reverse order; an
  * operand receives the chain-rule term of the instruction that read it,
- * terms added in that reverse order.  min / max pass the adjoint to the
- * operand they returned and a zero term to the other (which operands take
- * part does not depend on the data), abs to x with the sign of the branch
- * taken.  Instructions the output does not depend on pass nothing. */
+ * terms added in that reverse order.  min / max are locally one of their
+ * operands, so their derivative is that of the operand they returned: it
+ * alone receives the adjoint and the other operand receives nothing (its
+ * subtree is not reached from this use, so a non-finite partial inside it,
+ * such as 1/c or log c at c = 0, leaves the gradient untouched).  abs passes
+ * the adjoint to x with the sign of the branch taken.  Instructions the
+ * output does not depend on pass nothing. */
 void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin, int out_reg, const double *X,
                      int64_t n, const double *gout, const double *gscale, double *G)
 {
@@ -672,8 +675,8 @@ void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin,
             case OR_X_SUB: ca = g; cb = -g; ta = tb = 1; break;
             case OR_X_MUL: ca = g * vb; cb = g * va; ta = tb = 1; break;
             case OR_X_DIV: ca = g / vb; cb = -(g * vk / vb); ta = tb = 1; break;
-            case OR_X_MIN: ca = vb < va ? 0.0 : g; cb = vb < va ? g : 0.0; ta = tb = 1; break;
-            case OR_X_MAX: ca = vb > va ? 0.0 : g; cb = vb > va ? g : 0.0; ta = tb = 1; break;
+            case OR_X_MIN: if (vb < va) { cb = g; tb = 1; } else { ca = g; ta = 1; } break;
+            case OR_X_MAX: if (vb > va) { cb = g; tb = 1; } else { ca = g; ta = 1; } break;
             case OR_X_NEG: ca = -g; ta = 1; break;
             case OR_X_ABS: ca = va < 0.0 ? -g : g; ta = 1; break;
             case OR_X_SQ: ca = g * (va + va); ta = 1; break;
@@ -691,7 +694,8 @@ void or_expr_vjp_f64(const int32_t *code, const double *imm, int ninsn, int nin,
 }
 
 /* loop n (\i -> tensorSet out idx[i] (body x_i)): the CUDA backend's parallel
- * loop over i (Section 4.1, `loop`), here run sequentially in ascending i.
+ * loop over i (Appendix A, Source Language: `loop n f` calls f i for every i
+ * in [0, n) in an undefined order), here run sequentially in ascending i.
  * Slots outside [0, out_len) are not written. */
 void or_expr_loop_scatter_f64(const int32_t *code, const double *imm, int ninsn, int out_reg, const double *X,
                               int64_t n, const int64_t *idx, double *out, int64_t out_len)

@@ -102,60 +102,75 @@ std::string gen_source(const mx_expr &e) {
     const std::string fwd = forward_lines(e.prog, e.dtype, sa, sb, os, e.out_reg);
     const int n = (int)e.prog.size();
 
-    // reverse sweep
+    // Reverse sweep.  Every SSA value k that the output can reach carries an
+    // adjoint g<k> and a predicate r<k>: whether the output reaches it at
+    // this element.  min / max pass their adjoint to the operand they
+    // returned only, so which values are reached depends on the data; a term
+    // is selected into an adjoint under its predicate rather than multiplied
+    // by zero, so a subtree that is not reached (a log or a quotient at a
+    // pole behind the branch not taken) contributes nothing, not 0 * inf.
+    // Where no min / max lies on the way, the predicates are constants and
+    // fold away.
     std::string rev;
     std::vector<char> declared(n, 0);
-    bool gin_set[kMaxIn] = {false, false, false, false};
     auto g = [](int k) { return "g" + std::to_string(k); };
+    auto r = [](int k) { return "r" + std::to_string(k); };
     auto v = [](int k) { return "v" + std::to_string(k); };
-    auto add_term = [&](int j, const std::string &term) {
+    // adjoint j gains term under predicate cond
+    auto add_term = [&](int j, const std::string &cond, const std::string &term) {
         if (j < 0) return;
-        if (declared[j]) {
-            rev += "    " + g(j) + " = " + g(j) + " + " + term + ";\n";
-        } else {
-            rev += "    T " + g(j) + " = " + term + ";\n";
+        if (!declared[j]) {
+            rev += "    T " + g(j) + " = (T)0;\n    bool " + r(j) + " = false;\n";
             declared[j] = 1;
         }
+        rev += "    if (" + cond + ") { " + g(j) + " = " + r(j) + " ? " + g(j) + " + " + term + " : " + term + "; " +
+               r(j) + " = true; }\n";
     };
-    rev += "    T " + g(os) + " = seed;\n";
+    rev += "    T " + g(os) + " = seed;\n    bool " + r(os) + " = true;\n";
     declared[os] = 1;
+    bool gin_decl[kMaxIn] = {false, false, false, false};
     for (int k = n - 1; k >= 0; --k) {
         if (!declared[k]) continue;
         const mx_xinsn &q = e.prog[k];
-        const std::string gk = g(k), vk = v(k);
+        const std::string gk = g(k), vk = v(k), rk = r(k);
         const std::string va = sa[k] >= 0 ? v(sa[k]) : "", vb = sb[k] >= 0 ? v(sb[k]) : "";
         switch (q.op) {
-        case MX_X_IN:
-            if (gin_set[q.a]) {
-                rev += "    gi" + std::to_string(q.a) + " = gi" + std::to_string(q.a) + " + " + gk + ";\n";
-            } else {
-                rev += "    gi" + std::to_string(q.a) + " = " + gk + ";\n";
-                gin_set[q.a] = true;
+        case MX_X_IN: {
+            const std::string gi = "gi" + std::to_string(q.a), ri = "ri" + std::to_string(q.a);
+            if (!gin_decl[q.a]) {
+                rev += "    bool " + ri + " = false;\n";
+                gin_decl[q.a] = true;
             }
+            rev += "    if (" + rk + ") { " + gi + " = " + ri + " ? " + gi + " + " + gk + " : " + gk + "; " + ri +
+                   " = true; }\n";
             break;
+        }
         case MX_X_CONST: break;
-        case MX_X_ADD: add_term(sa[k], gk); add_term(sb[k], gk); break;
-        case MX_X_SUB: add_term(sa[k], gk); add_term(sb[k], "(-" + gk + ")"); break;
-        case MX_X_MUL: add_term(sa[k], "(" + gk + " * " + vb + ")"); add_term(sb[k], "(" + gk + " * " + va + ")"); break;
+        case MX_X_ADD: add_term(sa[k], rk, gk); add_term(sb[k], rk, gk); break;
+        case MX_X_SUB: add_term(sa[k], rk, gk); add_term(sb[k], rk, "(-" + gk + ")"); break;
+        case MX_X_MUL:
+            add_term(sa[k], rk, "(" + gk + " * " + vb + ")");
+            add_term(sb[k], rk, "(" + gk + " * " + va + ")");
+            break;
         case MX_X_DIV:
-            add_term(sa[k], "(" + gk + " / " + vb + ")");
-            add_term(sb[k], "(-(" + gk + " * " + vk + " / " + vb + "))");
+            add_term(sa[k], rk, "(" + gk + " / " + vb + ")");
+            add_term(sb[k], rk, "(-(" + gk + " * " + vk + " / " + vb + "))");
             break;
         case MX_X_MIN:
-            add_term(sa[k], "(" + vb + " < " + va + " ? (T)0 : " + gk + ")");
-            add_term(sb[k], "(" + vb + " < " + va + " ? " + gk + " : (T)0)");
+            add_term(sa[k], rk + " && !(" + vb + " < " + va + ")", gk);
+            add_term(sb[k], rk + " && (" + vb + " < " + va + ")", gk);
             break;
         case MX_X_MAX:
-            add_term(sa[k], "(" + vb + " > " + va + " ? (T)0 : " + gk + ")");
-            add_term(sb[k], "(" + vb + " > " + va + " ? " + gk + " : (T)0)");
+            add_term(sa[k], rk + " && !(" + vb + " > " + va + ")", gk);
+            add_term(sb[k], rk + " && (" + vb + " > " + va + ")", gk);
             break;
-        case MX_X_NEG: add_term(sa[k], "(-" + gk + ")"); break;
-        case MX_X_ABS: add_term(sa[k], "(" + va + " < (T)0 ? -" + gk + " : " + gk + ")"); break;
-        case MX_X_SQ: add_term(sa[k], "(" + gk + " * (" + va + " + " + va + "))"); break;
-        case MX_X_EXP: add_term(sa[k], "(" + gk + " * " + vk + ")"); break;
-        case MX_X_LOG: add_term(sa[k], "(" + gk + " / " + va + ")"); break;
-        case MX_X_SQRT: add_term(sa[k], "(" + gk + " / (" + vk + " + " + vk + "))"); break;
-        case MX_X_RSQRT: add_term(sa[k], "(-(" + gk + " * " + vk + " * " + vk + " * " + vk + ") * (T)0.5)"); break;
+        case MX_X_NEG: add_term(sa[k], rk, "(-" + gk + ")"); break;
+        case MX_X_ABS: add_term(sa[k], rk, "(" + va + " < (T)0 ? -" + gk + " : " + gk + ")"); break;
+        case MX_X_SQ: add_term(sa[k], rk, "(" + gk + " * (" + va + " + " + va + "))"); break;
+        case MX_X_EXP: add_term(sa[k], rk, "(" + gk + " * " + vk + ")"); break;
+        case MX_X_LOG: add_term(sa[k], rk, "(" + gk + " / " + va + ")"); break;
+        case MX_X_SQRT: add_term(sa[k], rk, "(" + gk + " / (" + vk + " + " + vk + "))"); break;
+        case MX_X_RSQRT: add_term(sa[k], rk, "(-(" + gk + " * " + vk + " * " + vk + " * " + vk + ") * (T)0.5)"); break;
         }
     }
 

@@ -214,6 +214,40 @@ def test_vjp(dtype, seed, name):
         assert np.all(np.abs(g - ref[k]) <= _vjp_tol(dtype) * (np.abs(ref[k]) + scale)), (k, seed)
 
 
+# bodies whose min / max leave a branch with non-finite partials untaken at
+# the points below: the reverse mode must not reach it (d/dc = 0, not NaN)
+BRANCH_BODIES = {
+    "max_x_log_c": ([IN(0, 0), IN(1, 1), OP(X.MX_X_LOG, 2, 1), OP(X.MX_X_MAX, 3, 0, 2)], 3),
+    "min_x_inv_c": ([IN(0, 0), IN(1, 1), CONST(2, 1.0), OP(X.MX_X_DIV, 2, 2, 1), OP(X.MX_X_MIN, 3, 0, 2)], 3),
+    "min_1_x_over_c": ([IN(0, 0), IN(1, 1), CONST(2, 1.0), OP(X.MX_X_DIV, 3, 0, 1), OP(X.MX_X_MIN, 4, 2, 3)], 4),
+    "max_x_log_c_plus_c": ([IN(0, 0), IN(1, 1), OP(X.MX_X_LOG, 2, 1), OP(X.MX_X_MAX, 3, 0, 2),
+                            OP(X.MX_X_ADD, 3, 3, 1)], 3),
+}
+
+
+@pytest.mark.parametrize("dtype", [abi.MX_F32, abi.MX_F64])
+@pytest.mark.parametrize("name", sorted(BRANCH_BODIES))
+def test_vjp_does_not_reach_the_branch_not_taken(dtype, name):
+    prog, out = BRANCH_BODIES[name]
+    n = 4099
+    say("expr vjp branch", name, dtype)
+    rng = np.random.default_rng(17)
+    x = rng.uniform(0.25, 1.0, n)
+    c = rng.uniform(0.5, 2.0, n)
+    c[::3] = 0.0                       # every third element sits at the pole of the untaken branch
+    xs = [x.astype(ND[dtype]), c.astype(ND[dtype])]
+    e = abi.mx_expr_create(prog, 2, out, dtype)
+    grads = [torch.full((n,), np.nan, dtype=TD[dtype], device=DEV) for _ in range(2)]
+    abi.mx_expr_vjp(e, [dev(v) for v in xs], n, None, None, grads)
+    ref = O.expr_vjp(prog, out, xs)
+    for k in range(2):
+        g = host(grads[k]).astype(np.float64)
+        assert np.all(np.isfinite(ref[k])), (name, k)
+        assert np.all(np.isfinite(g)), (name, k)
+        assert np.array_equal(g[::3], ref[k][::3]), (name, k)   # 0 or 1 exactly at the poles
+        assert np.all(np.abs(g - ref[k]) <= _vjp_tol(dtype) * (np.abs(ref[k]) + 1.0)), (name, k)
+
+
 def test_vjp_skips_null_gradients_and_unused_inputs():
     say("expr vjp null outputs")
     prog = [IN(0, 0), IN(1, 1), IN(2, 2), OP(X.MX_X_MUL, 3, 0, 0)]  # inputs 1 and 2 unused

@@ -114,6 +114,43 @@ def test_vjp_min_max_abs_pass_to_the_branch_taken():
     assert g.tolist() == [1, 1, 1, -1, 1]
 
 
+def test_vjp_min_max_do_not_reach_the_operand_not_returned():
+    # min / max equal the operand they return on a neighbourhood of any point
+    # where the operands differ, so the derivative is that operand's alone;
+    # the other subtree is not reached even where its own partials are not
+    # finite (log c and 1 / c at c = 0 -- a zero term pushed through them
+    # would give 0 * inf = NaN).
+    x = np.array([-0.75, 0.0, 0.5, 1.0])
+    c = np.zeros(4)
+    # max(x, log c): log 0 = -inf < x, so d/dx = 1 and d/dc = 0
+    gx, gc = O.expr_vjp([IN(0, 0), IN(1, 1), OP(O.X_LOG, 2, 1), OP(O.X_MAX, 3, 0, 2)], 3, [x, c])
+    assert gx.tolist() == [1, 1, 1, 1] and gc.tolist() == [0, 0, 0, 0]
+    # min(x, 1 / c): 1 / +0 = +inf > x
+    gx, gc = O.expr_vjp([IN(0, 0), IN(1, 1), CONST(2, 1.0), OP(O.X_DIV, 2, 2, 1), OP(O.X_MIN, 3, 0, 2)], 3,
+                        [x, c])
+    assert gx.tolist() == [1, 1, 1, 1] and gc.tolist() == [0, 0, 0, 0]
+    # max(x, sqrt c): the branch taken is x where x > 0 = sqrt 0; at x <= 0 it
+    # is sqrt c (ties go to the first operand only when equal: x = 0 here)
+    x2, c2 = np.array([0.5, 2.0]), np.zeros(2)
+    gx, gc = O.expr_vjp([IN(0, 0), IN(1, 1), OP(O.X_SQRT, 2, 1), OP(O.X_MAX, 3, 0, 2)], 3, [x2, c2])
+    assert gx.tolist() == [1, 1] and gc.tolist() == [0, 0]
+    # the safe-division clamp min(1, x / y) at y = 0 (x > 0): constant 1 there
+    xs, ys = np.array([0.5, 3.0]), np.zeros(2)
+    gx, gy = O.expr_vjp([IN(0, 0), IN(1, 1), CONST(2, 1.0), OP(O.X_DIV, 3, 0, 1), OP(O.X_MIN, 4, 2, 3)], 4,
+                        [xs, ys])
+    assert gx.tolist() == [0, 0] and gy.tolist() == [0, 0]
+    # an operand not returned here but used elsewhere still gets that use's
+    # term: max(x, log c) + c at c = 0 has d/dc = 1
+    gx, gc = O.expr_vjp([IN(0, 0), IN(1, 1), OP(O.X_LOG, 2, 1), OP(O.X_MAX, 3, 0, 2), OP(O.X_ADD, 3, 3, 1)], 3,
+                        [x, c])
+    assert gx.tolist() == [1, 1, 1, 1] and gc.tolist() == [1, 1, 1, 1]
+    # and where the branch flips, the gradient follows it: max(x, log c) at
+    # c = e^2 > e^x for x < 2 gives d/dc = 1 / c
+    ce = np.full(4, np.exp(2.0))
+    gx, gc = O.expr_vjp([IN(0, 0), IN(1, 1), OP(O.X_LOG, 2, 1), OP(O.X_MAX, 3, 0, 2)], 3, [x, ce])
+    assert gx.tolist() == [0, 0, 0, 0] and np.array_equal(gc, 1.0 / ce)
+
+
 def test_vjp_of_a_value_used_twice_adds_both_terms():
     x = RNG.uniform(-2, 2, 60)
     (g,) = O.expr_vjp([IN(0, 0), OP(O.X_MUL, 1, 0, 0), IN(2, 0), OP(O.X_ADD, 1, 1, 2)], 1, [x])
