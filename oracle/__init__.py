@@ -72,6 +72,8 @@ def _declare(lib):
         "or_segmented_foldl_f64": (None, [_int, _d, _p, _p, _i64, _p]),
         "or_segmented_foldl_i64": (None, [_int, _i64, _p, _p, _i64, _p]),
         "or_segmented_sum_adjoint_f64": (None, [_p, _p, _i64, _p]),
+        "or_reduce_adjoint_f64": (_int, [_int, _d, _p, _i64, _d, _p]),
+        "or_segmented_reduce_adjoint_f64": (_int, [_int, _d, _p, _p, _i64, _p, _p]),
         "or_matmul_f64": (None, [_p, _p, _p, _i64, _i64, _i64, _int, _int]),
         "or_nbody_accel": (None, [_p, _p, _i64, _d, _d, _p]),
         "or_nbody_step": (None, [_p, _p, _p, _i64, _d, _d, _d, _p, _p]),
@@ -274,6 +276,29 @@ def segmented_sum_adjoint(gout, offsets) -> np.ndarray:
     g = _f64(gout)
     out = np.empty(int(off[-1]), dtype=np.float64)
     _L().or_segmented_sum_adjoint_f64(_ptr(g), _ptr(off), off.size - 1, _ptr(out))
+    return out
+
+
+def reduce_adjoint(op: int, ne, s, g) -> np.ndarray:
+    """Gradient of foldl op ne s with respect to s, times g (op = ADD, MIN, MAX):
+    a broadcast of g for ADD; g at the element the fold ends on (the lowest
+    index attaining the extreme, none when ne is not improved upon) for MIN /
+    MAX."""
+    x = _f64(s).ravel()
+    out = np.empty_like(x)
+    if _L().or_reduce_adjoint_f64(op, float(ne), _ptr(x), x.size, float(g), _ptr(out)):
+        raise ValueError("no reverse mode for this operator")
+    return out
+
+
+def segmented_reduce_adjoint(op: int, ne, values, offsets, gout) -> np.ndarray:
+    """Row by row reduce_adjoint of map (reduce op ne) over a ragged sequence."""
+    off = _i64a(offsets)
+    v = _f64(values).ravel()
+    g = _f64(gout).ravel()
+    out = np.empty_like(v)
+    if _L().or_segmented_reduce_adjoint_f64(op, float(ne), _ptr(v), _ptr(off), off.size - 1, _ptr(g), _ptr(out)):
+        raise ValueError("no reverse mode for this operator")
     return out
 
 

@@ -215,6 +215,53 @@ void or_segmented_sum_adjoint_f64(const double *gout, const int64_t *offsets, in
         for (int64_t e = offsets[r]; e < offsets[r + 1]; ++e) gvalues[e] = gout[r];
 }
 
+/* Reverse of reduce op ne s (derived; the paper has no reverse mode): the
+ * gradient of y = foldl op ne s with respect to every element of s, times
+ * the upstream gradient g.
+ *   op = +        every element receives g (the adjoint of a sum is a
+ *                 broadcast).
+ *   op = min/max  the fold replaces its accumulator only when an element is
+ *                 strictly below (above) it, so y is the element at which the
+ *                 last replacement happened -- the lowest index attaining the
+ *                 extreme -- or ne itself when no element improves on it.
+ *                 That element receives g, every other element 0 (y does not
+ *                 depend on them where the values differ).
+ *   op = *        not defined here (returns -1). */
+int or_reduce_adjoint_f64(int op, double ne, const double *s, int64_t n, double g, double *gs)
+{
+    if (op == OR_ADD) {
+        for (int64_t i = 0; i < n; ++i) gs[i] = g;
+        return 0;
+    }
+    if (op != OR_MIN && op != OR_MAX) return -1;
+    double acc = ne;
+    int64_t arg = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const int better = op == OR_MIN ? s[i] < acc : s[i] > acc;
+        if (better) {
+            acc = s[i];
+            arg = i;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) gs[i] = 0.0;
+    if (arg >= 0) gs[arg] = g;
+    return 0;
+}
+
+/* ... and of map (reduce op ne) over the rows of a marshalled ragged
+ * sequence: row r's elements receive the reverse of its reduce with the
+ * upstream gradient gout[r]. */
+int or_segmented_reduce_adjoint_f64(int op, double ne, const double *values, const int64_t *offsets, int64_t nseg,
+                                    const double *gout, double *gvalues)
+{
+    for (int64_t r = 0; r < nseg; ++r) {
+        const int rc = or_reduce_adjoint_f64(op, ne, values + offsets[r], offsets[r + 1] - offsets[r], gout[r],
+                                             gvalues + offsets[r]);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Dense nested map-map-reduce (the sgemm pattern of Table 1):               */
 /*   C[i][j] = reduce (+) 0 (map2 (*) (row i of op(A)) (column j of op(B)))  */

@@ -20,6 +20,7 @@ import oracle as O
 import workloads as W
 
 U64 = 2 ** 64
+RNG_ADJ = np.random.default_rng(2211)
 EPS64 = 2.0 ** -53
 
 
@@ -341,6 +342,79 @@ def test_segmented_sum_adjoint_by_finite_differences():
 
 
 # ------------------------------------------------------------------ dense
+# ------------------------------------------------------------------ reverse of reduce (min / max / +)
+def test_reduce_min_max_adjoint_is_the_library_argmin():
+    # values distinct: the fold ends on numpy's argmin / argmax
+    x = RNG_ADJ.permutation(1000).astype(np.float64) * 0.5 - 100
+    for op, arg in ((O.MIN, np.argmin(x)), (O.MAX, np.argmax(x))):
+        ne = np.inf if op == O.MIN else -np.inf
+        g = O.reduce_adjoint(op, ne, x, 3.0)
+        ref = np.zeros_like(x)
+        ref[arg] = 3.0
+        assert np.array_equal(g, ref)
+
+
+def test_reduce_min_max_adjoint_by_finite_differences():
+    # on distinct values min / max are locally one of the elements: the central
+    # difference of the oracle's own fold is 1 there and 0 elsewhere
+    x = RNG_ADJ.uniform(-1, 1, 40)
+    for op in (O.MIN, O.MAX):
+        ne = np.inf if op == O.MIN else -np.inf
+        g = O.reduce_adjoint(op, ne, x, 1.0)
+        fd = np.empty_like(x)
+        for i in range(x.size):
+            h = 1e-7
+            up, dn = x.copy(), x.copy()
+            up[i] += h
+            dn[i] -= h
+            fd[i] = (O.reduce(op, ne, up) - O.reduce(op, ne, dn)) / (2 * h)
+        assert np.allclose(g, fd, rtol=1e-8, atol=1e-8), op
+
+
+def test_reduce_min_max_adjoint_ties_and_neutral_element():
+    # equal values: the lowest index (numpy's argmin also returns the first)
+    x = np.array([3.0, 1.0, 2.0, 1.0, 1.0])
+    assert O.reduce_adjoint(O.MIN, np.inf, x, 1.0).tolist() == [0, 1, 0, 0, 0]
+    assert O.reduce_adjoint(O.MAX, -np.inf, -x, 1.0).tolist() == [0, 1, 0, 0, 0]
+    # +0 and -0 compare equal: the first of them
+    z = np.array([1.0, 0.0, -0.0])
+    assert O.reduce_adjoint(O.MIN, np.inf, z, 1.0).tolist() == [0, 1, 0]
+    # ne at or beyond the extreme: y = ne does not depend on the elements
+    assert O.reduce_adjoint(O.MIN, 1.0, x, 1.0).tolist() == [0] * 5
+    assert O.reduce_adjoint(O.MIN, 0.5, x, 1.0).tolist() == [0] * 5
+    assert O.reduce_adjoint(O.MAX, 3.0, x, 1.0).tolist() == [0] * 5
+    # a finite ne that the elements improve on: the arg as before
+    assert O.reduce_adjoint(O.MAX, 2.5, x, 2.0).tolist() == [2, 0, 0, 0, 0]
+    assert O.reduce_adjoint(O.MIN, 7.0, np.zeros(0), 1.0).size == 0
+    # NaN elements never replace the accumulator of the fold
+    y = np.array([np.nan, 2.0, np.nan, 1.5])
+    assert O.reduce_adjoint(O.MIN, np.inf, y, 1.0).tolist() == [0, 0, 0, 1]
+    with pytest.raises(ValueError):
+        O.reduce_adjoint(O.MUL, 1.0, x, 1.0)
+
+
+def test_reduce_add_adjoint_is_a_broadcast():
+    x = RNG_ADJ.uniform(-1, 1, 17)
+    assert np.array_equal(O.reduce_adjoint(O.ADD, 0.0, x, -1.25), np.full(17, -1.25))
+
+
+def test_segmented_reduce_adjoint_row_by_row():
+    L = np.array([0, 3, 1, 0, 5, 2])
+    off = O.offsets_from_lengths(L)
+    v = RNG_ADJ.permutation(int(off[-1])).astype(np.float64)
+    g = np.arange(1, len(L) + 1, dtype=np.float64)
+    for op in (O.MIN, O.MAX):
+        ne = np.inf if op == O.MIN else -np.inf
+        got = O.segmented_reduce_adjoint(op, ne, v, off, g)
+        ref = np.zeros_like(v)
+        for r in range(len(L)):
+            row = v[off[r]:off[r + 1]]
+            if row.size:
+                ref[off[r] + (np.argmin(row) if op == O.MIN else np.argmax(row))] = g[r]
+        assert np.array_equal(got, ref)
+    assert np.array_equal(O.segmented_reduce_adjoint(O.ADD, 0.0, v, off, g), O.segmented_sum_adjoint(g, off))
+
+
 def test_matmul_rank_one_closed_form():
     M, N, K = 7, 5, 33
     u = np.arange(1, M + 1) * 0.25
