@@ -245,9 +245,35 @@ mx_status mx_dot_adjoint_f32(const float *a_dev, const float *b_dev, int64_t n,
                              const float *gout_dev, float *ga_dev, float *gb_dev,
                              hipStream_t stream);
 
+/* Reverse of y = reduce op ne x (F32; derived, the paper has no reverse
+ * mode) with upstream gradient g = *gout_dev (a device float):
+ *   MX_ADD            gx[i] = g for every i (a broadcast).
+ *   MX_MIN / MX_MAX   the left fold replaces its accumulator only when an
+ *                     element is strictly below (above) it, so y is the element
+ *                     at the lowest index attaining the extreme, or ne when no
+ *                     element improves on ne (ties with ne included, and a NaN
+ *                     ne); that element gets g, all others 0.  NaN elements
+ *                     are never chosen.  The index is exact and deterministic.
+ *   MX_MUL            MX_ERR_UNSUPPORTED.
+ * ne_host: one host float (the forward call's ne).  gx must not alias x.
+ * Workspace (MIN / MAX only; may be NULL for ADD): kind MX_WS_REDUCE with n.
+ * Two launches for MIN / MAX (per-block arg pairs with gx zero-filled, then
+ * one block writes g at the arg).  Errors: MX_ERR_INVALID, MX_ERR_SHAPE,
+ * MX_ERR_WORKSPACE, MX_ERR_UNSUPPORTED. */
+mx_status mx_reduce_adjoint_f32(mx_redop op, const float *x_dev, int64_t n, const float *ne_host,
+                                const float *gout_dev, float *gx_dev, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* ======================================================================= */
 /* Nested map (reduce) over a ragged sequence                               */
 /* ======================================================================= */
+/* The parallel keywords nest (Appendix A, Source Language: map applies a
+ * function to every element of a sequence, reduce folds a sequence with an
+ * associative operator and its neutral element), so map (reduce op ne) over a
+ * sequence of sequences reduces every inner sequence; marshaling (Section
+ * 4.3) lays the rows out as one flat value array plus offsets.  The rows may
+ * differ in length: the dynamic assumptions that make Futhark's nested arrays
+ * regular (Appendix, Dynamic Assumptions) are not needed here. */
 
 /* out[r] = reduce op ne (row r) for r < nseg, where row r is
  * values[offsets[r] .. offsets[r+1]) of the flat layout made by marshaling.
@@ -270,9 +296,26 @@ mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *val
 mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *offsets_dev,
                                        int64_t nseg, float *gvalues_dev, hipStream_t stream);
 
+/* Reverse of out[r] = reduce op ne (row r) (F32): row r receives the reverse
+ * of its reduce (as mx_reduce_adjoint_f32) with upstream gradient gout[r]:
+ * MX_ADD broadcasts gout[r] over the row (mx_segmented_sum_adjoint_f32;
+ * values may then be NULL), MX_MIN / MX_MAX put gout[r] at the row's arg
+ * element and 0 elsewhere (one wave per row).  gout: device float[nseg];
+ * gvalues: device float[offsets[nseg]], must not alias values.  Errors:
+ * MX_ERR_INVALID, MX_ERR_SHAPE (debug mode), MX_ERR_UNSUPPORTED (MX_MUL). */
+mx_status mx_segmented_reduce_adjoint_f32(mx_redop op, const float *values_dev, const int64_t *offsets_dev,
+                                          int64_t nseg, const float *ne_host, const float *gout_dev,
+                                          float *gvalues_dev, hipStream_t stream);
+
 /* ======================================================================= */
 /* Dense nested map (map (reduce (+) 0 (map2 (*) row col))) -- FP32 on MFMA */
 /* ======================================================================= */
+/* The same keywords nested twice over regular data (Appendix A, Source
+ * Language): map over the rows of A of map over the columns of B of
+ * reduce (+) 0 (map2 (*) row col) -- the matrix product the paper's sgemm
+ * benchmarks compute (Section 5.1, Table 1).  Regular nesting is what the
+ * Futhark backend requires of nested sequences (Appendix, Dynamic
+ * Assumptions); here it is a dense contraction and runs on the matrix cores. */
 
 /* C[i][j] = sum_k op(A)[i][k] * op(B)[k][j], i < M, j < N, k < K, FP32 inputs
  * and FP32 accumulation on the matrix cores.  Row-major, densely packed:
@@ -353,6 +396,22 @@ size_t mx_nbody_workspace_bytes(int64_t n, int nsteps, int ckpt_every);
 mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
                                float dt, int nsteps, int ckpt_every, float *ke_dev, float *gx4_dev,
                                float *gv4_dev, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The same loop split at the kinetic energy, for callers that want the
+ * gradient later or not at all (an autograd forward and backward):
+ * mx_nbody_ke_f32 runs the forward loop, leaves the checkpoints and the final
+ * state in ws and writes KE; mx_nbody_ke_vjp_f32, given the same inputs and
+ * the ws that call left untouched, runs the checkpointed reverse sweep seeded
+ * with g m v_T, g = *gscale_dev (a device float; NULL means 1), and writes
+ * g dKE/dx0 and g dKE/dv0.  With gscale_dev NULL the two calls give the
+ * gradients of mx_nbody_ke_grad_f32 bit for bit.  Same arguments, workspace
+ * size and errors as mx_nbody_ke_grad_f32; n = 0 writes KE = 0. */
+mx_status mx_nbody_ke_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G, float dt,
+                          int nsteps, int ckpt_every, float *ke_dev, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
+mx_status mx_nbody_ke_vjp_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
+                              float dt, int nsteps, int ckpt_every, const float *gscale_dev, float *gx4_dev,
+                              float *gv4_dev, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ======================================================================= */
 /* k-means step: map (argmin-reduce) + reduce-by-key (the histo pattern of  */

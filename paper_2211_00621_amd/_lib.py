@@ -44,6 +44,8 @@ SIGNATURES = {
     "mx_segmented_reduce": (c_status, [c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p, c_p]),
     "mx_segmented_reduce_plain": (c_status, [c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p, c_p]),
     "mx_segmented_sum_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_p]),
+    "mx_reduce_adjoint_f32": (c_status, [c_enum, c_p, c_i64, c_p, c_p, c_p, c_p, c_size, c_p]),
+    "mx_segmented_reduce_adjoint_f32": (c_status, [c_enum, c_p, c_p, c_i64, c_p, c_p, c_p, c_p]),
     "mx_map_map_reduce_f32": (c_status, [c_int, c_int, c_i64, c_i64, c_i64, c_p, c_p, c_p, c_p]),
     "mx_map_map_reduce_plain_f32": (c_status, [c_int, c_int, c_i64, c_i64, c_i64, c_p, c_p, c_p, c_p]),
     "mx_nbody_pair_workspace_bytes": (c_size, [c_i64]),
@@ -57,6 +59,9 @@ SIGNATURES = {
     "mx_nbody_workspace_bytes": (c_size, [c_i64, c_int, c_int]),
     "mx_nbody_ke_grad_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_int, c_int, c_p, c_p, c_p, c_p,
                                         c_size, c_p]),
+    "mx_nbody_ke_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_int, c_int, c_p, c_p, c_size, c_p]),
+    "mx_nbody_ke_vjp_f32": (c_status, [c_p, c_p, c_i64, c_f32, c_f32, c_f32, c_int, c_int, c_p, c_p, c_p, c_p,
+                                       c_size, c_p]),
     "mx_kmeans_workspace_bytes": (c_size, [c_i64, c_int, c_int]),
     "mx_kmeans_step_f32": (c_status, [c_p, c_i64, c_int, c_p, c_int, c_p, c_p, c_p, c_p, c_size, c_p]),
     "mx_kmeans_debug_fallbacks": (c_i64, []),

@@ -242,6 +242,21 @@ def mx_segmented_sum_adjoint_f32(gout, offsets, gvalues, stream=None) -> None:
            "mx_segmented_sum_adjoint_f32")
 
 
+def mx_reduce_adjoint_f32(op: int, x, ne, gout, gx, ws=None, stream=None) -> None:
+    """Reverse of reduce op ne x (ADD, MIN, MAX); gout: one device float."""
+    nb = ctypes.c_float(float(ne))
+    _check(_L().mx_reduce_adjoint_f32(int(op), _dptr(x), x.numel(), ctypes.byref(nb), _dptr(gout), _dptr(gx),
+                                      _dptr(ws), _nbytes(ws), _stream(stream)), "mx_reduce_adjoint_f32")
+
+
+def mx_segmented_reduce_adjoint_f32(op: int, values, offsets, ne, gout, gvalues, stream=None) -> None:
+    """Reverse of map (reduce op ne) over ragged rows; gout: device float[nseg]."""
+    nb = ctypes.c_float(float(ne))
+    _check(_L().mx_segmented_reduce_adjoint_f32(int(op), _dptr(values), _dptr(offsets), offsets.numel() - 1,
+                                                ctypes.byref(nb), _dptr(gout), _dptr(gvalues), _stream(stream)),
+           "mx_segmented_reduce_adjoint_f32")
+
+
 # ---------------------------------------------------------------- dense
 def _mmr_dims(ta, tb, A, B):
     M, K = (A.shape[1], A.shape[0]) if ta else (A.shape[0], A.shape[1])
@@ -315,6 +330,17 @@ def mx_nbody_ke_grad_f32(pos4, vel4, eps2, G, dt, nsteps, ckpt_every, ke, gx4, g
     _check(_L().mx_nbody_ke_grad_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), eps2, G, dt, int(nsteps),
                                      int(ckpt_every), _dptr(ke), _dptr(gx4), _dptr(gv4), _dptr(ws), _nbytes(ws),
                                      _stream(stream)), "mx_nbody_ke_grad_f32")
+
+
+def mx_nbody_ke_f32(pos4, vel4, eps2, G, dt, nsteps, ckpt_every, ke, ws, stream=None) -> None:
+    _check(_L().mx_nbody_ke_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), eps2, G, dt, int(nsteps), int(ckpt_every),
+                                _dptr(ke), _dptr(ws), _nbytes(ws), _stream(stream)), "mx_nbody_ke_f32")
+
+
+def mx_nbody_ke_vjp_f32(pos4, vel4, eps2, G, dt, nsteps, ckpt_every, gscale, gx4, gv4, ws, stream=None) -> None:
+    _check(_L().mx_nbody_ke_vjp_f32(_dptr(pos4), _dptr(vel4), _n4(pos4), eps2, G, dt, int(nsteps),
+                                    int(ckpt_every), _dptr(gscale), _dptr(gx4), _dptr(gv4), _dptr(ws),
+                                    _nbytes(ws), _stream(stream)), "mx_nbody_ke_vjp_f32")
 
 
 # ---------------------------------------------------------------- k-means

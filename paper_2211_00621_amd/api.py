@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import abi
-from .abi import (MX_ADD, MX_B_MUL, MX_WS_REDUCE, MX_WS_SCAN, ACC_OF)
+from .abi import (MX_ADD, MX_MIN, MX_MAX, MX_B_MUL, MX_WS_REDUCE, MX_WS_SCAN, ACC_OF)
 
 # ---------------------------------------------------------------- workspaces
 _WS: dict = {}
@@ -47,11 +47,37 @@ def map2(f: int, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = No
     return out
 
 
-def reduce(op: int, x: torch.Tensor, ne) -> torch.Tensor:
-    x = x.contiguous().view(-1)
+def _reduce(op: int, x: torch.Tensor, ne) -> torch.Tensor:
     out = torch.empty((), dtype=ACC_OF[x.dtype], device=x.device)
     abi.mx_reduce(op, x, ne, out, workspace(MX_WS_REDUCE, x.numel(), device=x.device))
     return out
+
+
+class _Reduce(torch.autograd.Function):
+    """reduce op ne x for float32 x and op in (+, min, max); backward is the
+    library's reverse of reduce (a broadcast, or the arg element's scatter)."""
+
+    @staticmethod
+    def forward(ctx, x, op, ne):
+        ctx.save_for_backward(x)
+        ctx.op, ctx.ne = op, ne
+        return _reduce(op, x, ne)
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        gx = torch.empty_like(x)
+        abi.mx_reduce_adjoint_f32(ctx.op, x, ctx.ne, g.contiguous().view(1), gx,
+                                  workspace(MX_WS_REDUCE, x.numel(), device=x.device))
+        return gx, None, None
+
+
+def reduce(op: int, x: torch.Tensor, ne) -> torch.Tensor:
+    """reduce op ne x; differentiable for float32 x with op in (+, min, max)."""
+    x = x.contiguous().view(-1)
+    if x.dtype == torch.float32 and x.requires_grad and op in (MX_ADD, MX_MIN, MX_MAX):
+        return _Reduce.apply(x, op, ne)
+    return _reduce(op, x, ne)
 
 
 def map2_reduce(f: int, op: int, a: torch.Tensor, b: torch.Tensor, ne) -> torch.Tensor:
@@ -242,11 +268,35 @@ def fields_to_records(fields) -> torch.Tensor:
     return aos
 
 
-def segmented_reduce(op: int, r: Ragged, ne, plain: bool = False) -> torch.Tensor:
+def _segmented_reduce(op: int, r: Ragged, ne, plain: bool = False) -> torch.Tensor:
     out = torch.empty(r.nseg, dtype=ACC_OF[r.values.dtype], device=r.values.device)
     fn = abi.mx_segmented_reduce_plain if plain else abi.mx_segmented_reduce
     fn(op, r.values, r.offsets, ne, out)
     return out
+
+
+class _SegReduce(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, values, offsets, op, ne):
+        ctx.save_for_backward(values, offsets)
+        ctx.op, ctx.ne = op, ne
+        return _segmented_reduce(op, Ragged(values, offsets), ne)
+
+    @staticmethod
+    def backward(ctx, g):
+        values, offsets = ctx.saved_tensors
+        gv = torch.empty_like(values)
+        abi.mx_segmented_reduce_adjoint_f32(ctx.op, values, offsets, ctx.ne, g.contiguous(), gv)
+        return gv, None, None, None
+
+
+def segmented_reduce(op: int, r: Ragged, ne, plain: bool = False) -> torch.Tensor:
+    """map (reduce op ne) over the rows; differentiable for float32 values with
+    op in (+, min, max)."""
+    if (not plain and r.values.dtype == torch.float32 and r.values.requires_grad
+            and op in (MX_ADD, MX_MIN, MX_MAX)):
+        return _SegReduce.apply(r.values, r.offsets, op, ne)
+    return _segmented_reduce(op, r, ne, plain)
 
 
 class _SegSum(torch.autograd.Function):
@@ -270,7 +320,7 @@ def segmented_sum(r: Ragged) -> torch.Tensor:
     """map (reduce (+) 0) over the rows; differentiable for float32 values."""
     if r.values.dtype == torch.float32 and r.values.requires_grad:
         return _SegSum.apply(r.values, r.offsets)
-    return segmented_reduce(MX_ADD, r, 0)
+    return _segmented_reduce(MX_ADD, r, 0)
 
 
 # ---------------------------------------------------------------- dense
@@ -369,20 +419,33 @@ def nbody_ke_grad(pos4, vel4, eps2, G, dt, nsteps, ckpt_every):
 
 
 class _NBodyKE(torch.autograd.Function):
-    """KE after an Euler loop as a differentiable function of (x0, v0)."""
+    """KE after an Euler loop as a differentiable function of (x0, v0).
+
+    forward runs the loop and keeps its checkpoints in a workspace of its own;
+    backward runs the checkpointed reverse sweep from them, seeded on the
+    device with the upstream gradient."""
 
     @staticmethod
     def forward(ctx, pos, vel, mass, eps2, G, dt, nsteps, ckpt_every):
         p4 = bodies(pos, mass)
         v4 = vec4(vel)
-        ke, gx, gv = nbody_ke_grad(p4, v4, eps2, G, dt, nsteps, ckpt_every)
-        ctx.save_for_backward(gx, gv)
+        n = p4.shape[0]
+        ke = torch.empty((), dtype=torch.float32, device=p4.device)
+        ws = torch.zeros(max(abi.mx_nbody_workspace_bytes(n, nsteps, ckpt_every), 256), dtype=torch.uint8,
+                         device=p4.device)
+        abi.mx_nbody_ke_f32(p4, v4, eps2, G, dt, nsteps, ckpt_every, ke, ws)
+        ctx.save_for_backward(p4, v4, ws)
+        ctx.args = (eps2, G, dt, nsteps, ckpt_every)
         return ke
 
     @staticmethod
     def backward(ctx, g):
-        gx, gv = ctx.saved_tensors
-        return (g * gx[:, :3], g * gv[:, :3], None, None, None, None, None, None)
+        p4, v4, ws = ctx.saved_tensors
+        eps2, G, dt, nsteps, ckpt_every = ctx.args
+        gx, gv = torch.empty_like(p4), torch.empty_like(p4)
+        gs = g.detach().to(torch.float32).contiguous().view(1)
+        abi.mx_nbody_ke_vjp_f32(p4, v4, eps2, G, dt, nsteps, ckpt_every, gs, gx, gv, ws)
+        return (gx[:, :3], gv[:, :3], None, None, None, None, None, None)
 
 
 def nbody_kinetic_energy(pos, vel, mass, eps2, G, dt, nsteps, ckpt_every=5):
@@ -557,13 +620,28 @@ class Body:
             raise abi.MxError(abi.MX_ERR_SHAPE, "inputs differ in length or dtype")
         return xs, n
 
-    def map(self, *xs) -> torch.Tensor:
+    def _map(self, *xs) -> torch.Tensor:
         xs, n = self._args(xs)
         out = torch.empty(n, dtype=self.torch_dtype, device=xs[0].device)
         abi.mx_expr_map(self.e, xs, out)
         return out
 
+    def _grad(self, xs) -> bool:
+        return self.torch_dtype == torch.float32 and torch.is_grad_enabled() and any(x.requires_grad for x in xs)
+
+    def map(self, *xs) -> torch.Tensor:
+        """map body xs (flat); differentiable for float32 (reverse mode of the body)."""
+        if self._grad(xs):
+            return _BodyMap.apply(self, *xs)
+        return self._map(*xs)
+
     def map_reduce(self, op: int, *xs, ne=0.0) -> torch.Tensor:
+        """reduce op ne (map body xs); differentiable for float32 with op in (+, min, max)."""
+        if self._grad(xs) and op in (MX_ADD, MX_MIN, MX_MAX):
+            return _BodyMapReduce.apply(self, op, ne, *xs)
+        return self._map_reduce(op, *xs, ne=ne)
+
+    def _map_reduce(self, op: int, *xs, ne=0.0) -> torch.Tensor:
         xs, n = self._args(xs)
         out = torch.empty((), dtype=self.torch_dtype, device=xs[0].device)
         key = xs[0].device.index
@@ -575,7 +653,13 @@ class Body:
         return out
 
     def segmented_reduce(self, op: int, offsets: torch.Tensor, *xs, ne=0.0) -> torch.Tensor:
-        """out[r] = ne op body(x_i) ... over the elements i of ragged row r."""
+        """out[r] = ne op body(x_i) ... over the elements i of ragged row r;
+        differentiable for float32 with op in (+, min, max)."""
+        if self._grad(xs) and op in (MX_ADD, MX_MIN, MX_MAX):
+            return _BodySegReduce.apply(self, op, ne, offsets, *xs)
+        return self._segmented_reduce(op, offsets, *xs, ne=ne)
+
+    def _segmented_reduce(self, op: int, offsets: torch.Tensor, *xs, ne=0.0) -> torch.Tensor:
         xs, n = self._args(xs)
         out = torch.empty(offsets.numel() - 1, dtype=self.torch_dtype, device=xs[0].device)
         abi.mx_expr_segmented_reduce(self.e, op, xs, offsets, ne, out)
@@ -598,10 +682,78 @@ class _BodySum(torch.autograd.Function):
     def forward(ctx, body, *xs):
         ctx.body = body
         ctx.save_for_backward(*xs)
-        return body.map_reduce(MX_ADD, *xs, ne=0.0)
+        return body._map_reduce(MX_ADD, *xs, ne=0.0)
 
     @staticmethod
     def backward(ctx, g):
         xs = ctx.saved_tensors
         grads = ctx.body.vjp(*xs, gscale=g.contiguous().to(ctx.body.torch_dtype))
         return (None, *[gr.view(x.shape) for gr, x in zip(grads, xs)])
+
+
+def _shaped(grads, xs):
+    return [gr.view(x.shape) for gr, x in zip(grads, xs)]
+
+
+class _BodyMap(torch.autograd.Function):
+    """map body xs; backward: the body's reverse mode seeded with the
+    upstream gradient of every element."""
+
+    @staticmethod
+    def forward(ctx, body, *xs):
+        ctx.body = body
+        ctx.save_for_backward(*xs)
+        return body._map(*xs)
+
+    @staticmethod
+    def backward(ctx, g):
+        xs = ctx.saved_tensors
+        return (None, *_shaped(ctx.body.vjp(*xs, gout=g.contiguous()), xs))
+
+
+class _BodyMapReduce(torch.autograd.Function):
+    """reduce op ne (map body xs): the reverse of the reduce (broadcast for +,
+    the arg element for min / max) over the body's values, then the body's
+    reverse mode with that as the per-element seed."""
+
+    @staticmethod
+    def forward(ctx, body, op, ne, *xs):
+        ctx.body, ctx.op, ctx.ne = body, op, ne
+        ctx.save_for_backward(*xs)
+        return body._map_reduce(op, *xs, ne=ne)
+
+    @staticmethod
+    def backward(ctx, g):
+        xs = ctx.saved_tensors
+        body = ctx.body
+        g = g.contiguous().view(1)
+        if ctx.op == MX_ADD:
+            grads = body.vjp(*xs, gscale=g)
+        else:
+            vals = body._map(*xs)
+            seed = torch.empty_like(vals)
+            abi.mx_reduce_adjoint_f32(ctx.op, vals, ctx.ne, g, seed,
+                                      workspace(MX_WS_REDUCE, vals.numel(), device=vals.device))
+            grads = body.vjp(*xs, gout=seed)
+        return (None, None, None, *_shaped(grads, xs))
+
+
+class _BodySegReduce(torch.autograd.Function):
+    """map (reduce op ne . map body) over ragged rows: the reverse of each
+    row's reduce over the body's values, then the body's reverse mode."""
+
+    @staticmethod
+    def forward(ctx, body, op, ne, offsets, *xs):
+        ctx.body, ctx.op, ctx.ne = body, op, ne
+        ctx.save_for_backward(offsets, *xs)
+        return body._segmented_reduce(op, offsets, *xs, ne=ne)
+
+    @staticmethod
+    def backward(ctx, g):
+        offsets, *xs = ctx.saved_tensors
+        body = ctx.body
+        n = xs[0].numel()
+        seed = torch.empty(n, dtype=torch.float32, device=g.device)
+        vals = body._map(*xs) if ctx.op != MX_ADD else None
+        abi.mx_segmented_reduce_adjoint_f32(ctx.op, vals, offsets, ctx.ne, g.contiguous(), seed)
+        return (None, None, None, None, *_shaped(body.vjp(*xs, gout=seed), xs))

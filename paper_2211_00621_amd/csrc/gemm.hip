@@ -341,7 +341,7 @@ mx_status check(const char *who, int ta, int tb, int64_t M, int64_t N, int64_t K
 // 16 x 16 per wave) when there are enough tiles for every CU, 128 x 64
 // (2 x 2 per wave) otherwise and for A B^T, where it measured faster at
 // 2048^3; MX_GEMM_TILE in the environment forces one of the configurations
-// below (for tuning).
+// below (for tuning and for testing every tile at small shapes).
 template <int BM, int BN, int WM, int WN>
 mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A, const float *B, float *C,
                       int vec_ok, hipStream_t s) {
@@ -364,18 +364,15 @@ mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const flo
 enum GemmTile { kT128x64 = 1, kT128x128, kT128x64w8, kT128x128w8, kT64x64 };
 
 int gemm_tile_choice(int ta, int tb, int64_t M, int64_t N, const DeviceInfo *d) {
-    static int forced = -1;
-    if (forced < 0) {
-        forced = 0;
-        if (const char *e = getenv("MX_GEMM_TILE")) {
-            static const struct { const char *name; int tile; } names[] = {
-                {"128x64", kT128x64}, {"128x128", kT128x128}, {"128x64w8", kT128x64w8},
-                {"128x128w8", kT128x128w8}, {"64x64", kT64x64}};
-            for (const auto &n : names)
-                if (!strcmp(e, n.name)) forced = n.tile;
-        }
+    // read on every call (a getenv is cheap next to a launch), so one process
+    // can run every configuration
+    if (const char *e = getenv("MX_GEMM_TILE")) {
+        static const struct { const char *name; int tile; } names[] = {
+            {"128x64", kT128x64}, {"128x128", kT128x128}, {"128x64w8", kT128x64w8},
+            {"128x128w8", kT128x128w8}, {"64x64", kT64x64}};
+        for (const auto &n : names)
+            if (!strcmp(e, n.name)) return n.tile;
     }
-    if (forced) return forced;
     // 128 x 128 when it still gives every CU a tile, except for A B^T (both
     // operands [row][k]), where the 128 x 64 tile measured faster
     const int64_t big = ceil_div(M, 128) * ceil_div(N, 128);

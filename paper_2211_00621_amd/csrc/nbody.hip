@@ -183,6 +183,21 @@ __global__ void __launch_bounds__(NT) k_kinetic(const float4 *__restrict__ pos, 
     if (threadIdx.x == 0) ke[0] = acc;
 }
 
+// Start of the reverse sweep for an upstream gradient g of KE (a device
+// scalar; null means 1): vbar = g m v, xbar = 0.  With g = 1 the products
+// equal k_kinetic's m v bit for bit.
+__global__ void __launch_bounds__(NT) k_adjoint_seed(const float4 *__restrict__ pos, const float4 *__restrict__ vel,
+                                                     int64_t n, const float *__restrict__ gscale,
+                                                     float4 *__restrict__ vbar, float4 *__restrict__ xbar) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    const float g = gscale ? gscale[0] : 1.f;
+    const float4 v = vel[i];
+    const float m = pos[i].w;
+    vbar[i] = make_float4(m * v.x * g, m * v.y * g, m * v.z * g, 0.f);
+    xbar[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // ---------------------------------------------------------------- launch helpers
 // The j range is cut into S slices so that about kTargetBlocks blocks run
 // (8 per CU on 256 CUs); S depends only on n, so results are the same on
@@ -376,25 +391,25 @@ mx_status mx_nbody_kinetic_f32(const float *pos4_dev, const float *vel4_dev, int
     return kinetic_impl((const float4 *)pos4_dev, (const float4 *)vel4_dev, n, ke_dev, nullptr, nullptr, stream);
 }
 
-mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
-                               float dt, int nsteps, int ckpt_every, float *ke_dev, float *gx4_dev,
-                               float *gv4_dev, void *ws, size_t ws_bytes, hipStream_t stream) {
-    const char *who = "mx_nbody_ke_grad_f32";
+namespace {
+mx_status ke_check(const char *who, const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2,
+                   int nsteps, int ckpt_every, void *ws, size_t ws_bytes) {
     MX_REQUIRE(nsteps >= 1 && ckpt_every >= 1 && ckpt_every <= kMaxCkptEvery, MX_ERR_INVALID,
                "%s: need nsteps >= 1 and 1 <= ckpt_every <= %d", who, kMaxCkptEvery);
     if (mx_status st = check_common(who, n, eps2, ws, ws_bytes, mx_nbody_workspace_bytes(n, nsteps, ckpt_every)))
         return st;
-    if (n == 0) return MX_OK;
-    MX_REQUIRE(pos4_dev && vel4_dev && ke_dev && gx4_dev && gv4_dev, MX_ERR_INVALID, "%s: null pointer", who);
-    MX_REQUIRE(a16(pos4_dev) && a16(vel4_dev) && a16(gx4_dev) && a16(gv4_dev), MX_ERR_INVALID,
-               "%s: pointers must be 16-byte aligned", who);
-    const int k = ckpt_every < nsteps ? ckpt_every : nsteps;
-    NbodyWs w = nbody_ws_layout((char *)ws, n, nsteps, k);
-    const int64_t st4 = (int64_t)(align256((size_t)n * 16) / 16);  // float4 stride between states
-    const int nck = (nsteps + k - 1) / k;
-    const float4 *x0 = (const float4 *)pos4_dev, *v0 = (const float4 *)vel4_dev;
+    if (n > 0)
+        MX_REQUIRE(pos4_dev && vel4_dev && a16(pos4_dev) && a16(vel4_dev), MX_ERR_INVALID,
+                   "%s: null or unaligned state pointer", who);
+    return MX_OK;
+}
 
-    // forward loop: checkpoint c holds the state at t = c k (checkpoint 0 is the input)
+// Forward loop: checkpoint c (c >= 1) holds the state at t = c k in the
+// workspace (checkpoint 0 is the input itself), the final state goes to
+// fin_x / fin_v; then KE of the final state.
+mx_status ke_forward(const float4 *x0, const float4 *v0, int64_t n, float eps2, float G, float dt, int nsteps,
+                     int k, float *ke_dev, const NbodyWs &w, hipStream_t stream) {
+    const int64_t st4 = (int64_t)(align256((size_t)n * 16) / 16);  // float4 stride between states
     const float4 *x = x0, *v = v0;
     for (int t = 0; t < nsteps; ++t) {
         float4 *xo, *vo;
@@ -409,9 +424,21 @@ mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int
         x = xo;
         v = vo;
     }
-    // KE of the final state; the reverse sweep starts from vbar = m v_T, xbar = 0
+    return kinetic_impl(w.fin_x, w.fin_v, n, ke_dev, nullptr, nullptr, stream);
+}
+
+// Reverse sweep from the checkpoints ke_forward left: vbar = g m v_T,
+// xbar = 0, then segment by segment (last first) the states recomputed
+// forward from the segment's checkpoint onto the tape and the adjoint steps
+// walked back over them.
+mx_status ke_reverse(const float4 *x0, const float4 *v0, int64_t n, float eps2, float G, float dt, int nsteps,
+                     int k, const float *gscale, float4 *gx, float4 *gv, const NbodyWs &w, hipStream_t stream) {
+    const int64_t st4 = (int64_t)(align256((size_t)n * 16) / 16);
+    const int nck = (nsteps + k - 1) / k;
     int cur = 0;
-    if (mx_status st = kinetic_impl(w.fin_x, w.fin_v, n, ke_dev, w.vb[0], w.xb[0], stream)) return st;
+    hipLaunchKernelGGL(k_adjoint_seed, dim3((unsigned)ceil_div(n, NT)), dim3(NT), 0, stream, w.fin_x, w.fin_v, n,
+                       gscale, w.vb[0], w.xb[0]);
+    if (mx_status st = last_launch("nbody adjoint seed")) return st;
     for (int c = nck - 1; c >= 0; --c) {
         const int t0 = c * k, t1 = (t0 + k < nsteps) ? t0 + k : nsteps;
         // recompute x_t for t0 <= t < t1 from the checkpoint (tape entry 0 is the checkpoint itself)
@@ -427,8 +454,8 @@ mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int
             tape[t - t0 + 1] = xo;
         }
         for (int t = t1 - 1; t >= t0; --t) {
-            float4 *xbo = (t == 0) ? (float4 *)gx4_dev : w.xb[cur ^ 1];
-            float4 *vbo = (t == 0) ? (float4 *)gv4_dev : w.vb[cur ^ 1];
+            float4 *xbo = (t == 0) ? gx : w.xb[cur ^ 1];
+            float4 *vbo = (t == 0) ? gv : w.vb[cur ^ 1];
             if (mx_status st = adjstep_impl(tape[t - t0], w.xb[cur], w.vb[cur], n, eps2, G, dt, xbo, vbo, w.pair,
                                             stream))
                 return st;
@@ -436,6 +463,49 @@ mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int
         }
     }
     return MX_OK;
+}
+}  // namespace
+
+mx_status mx_nbody_ke_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G, float dt,
+                          int nsteps, int ckpt_every, float *ke_dev, void *ws, size_t ws_bytes,
+                          hipStream_t stream) {
+    const char *who = "mx_nbody_ke_f32";
+    if (mx_status st = ke_check(who, pos4_dev, vel4_dev, n, eps2, nsteps, ckpt_every, ws, ws_bytes)) return st;
+    MX_REQUIRE(ke_dev, MX_ERR_INVALID, "%s: null ke pointer", who);
+    if (n == 0) return kinetic_impl(nullptr, nullptr, 0, ke_dev, nullptr, nullptr, stream);
+    const int k = ckpt_every < nsteps ? ckpt_every : nsteps;
+    NbodyWs w = nbody_ws_layout((char *)ws, n, nsteps, k);
+    return ke_forward((const float4 *)pos4_dev, (const float4 *)vel4_dev, n, eps2, G, dt, nsteps, k, ke_dev, w,
+                      stream);
+}
+
+mx_status mx_nbody_ke_vjp_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
+                              float dt, int nsteps, int ckpt_every, const float *gscale_dev, float *gx4_dev,
+                              float *gv4_dev, void *ws, size_t ws_bytes, hipStream_t stream) {
+    const char *who = "mx_nbody_ke_vjp_f32";
+    if (mx_status st = ke_check(who, pos4_dev, vel4_dev, n, eps2, nsteps, ckpt_every, ws, ws_bytes)) return st;
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(gx4_dev && gv4_dev && a16(gx4_dev) && a16(gv4_dev), MX_ERR_INVALID,
+               "%s: null or unaligned gradient pointer", who);
+    const int k = ckpt_every < nsteps ? ckpt_every : nsteps;
+    NbodyWs w = nbody_ws_layout((char *)ws, n, nsteps, k);
+    return ke_reverse((const float4 *)pos4_dev, (const float4 *)vel4_dev, n, eps2, G, dt, nsteps, k, gscale_dev,
+                      (float4 *)gx4_dev, (float4 *)gv4_dev, w, stream);
+}
+
+mx_status mx_nbody_ke_grad_f32(const float *pos4_dev, const float *vel4_dev, int64_t n, float eps2, float G,
+                               float dt, int nsteps, int ckpt_every, float *ke_dev, float *gx4_dev,
+                               float *gv4_dev, void *ws, size_t ws_bytes, hipStream_t stream) {
+    const char *who = "mx_nbody_ke_grad_f32";
+    if (mx_status st = ke_check(who, pos4_dev, vel4_dev, n, eps2, nsteps, ckpt_every, ws, ws_bytes)) return st;
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(ke_dev && gx4_dev && gv4_dev && a16(gx4_dev) && a16(gv4_dev), MX_ERR_INVALID,
+               "%s: null or unaligned pointer", who);
+    const int k = ckpt_every < nsteps ? ckpt_every : nsteps;
+    NbodyWs w = nbody_ws_layout((char *)ws, n, nsteps, k);
+    const float4 *x0 = (const float4 *)pos4_dev, *v0 = (const float4 *)vel4_dev;
+    if (mx_status st = ke_forward(x0, v0, n, eps2, G, dt, nsteps, k, ke_dev, w, stream)) return st;
+    return ke_reverse(x0, v0, n, eps2, G, dt, nsteps, k, nullptr, (float4 *)gx4_dev, (float4 *)gv4_dev, w, stream);
 }
 
 }  // extern "C"

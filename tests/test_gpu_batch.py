@@ -86,6 +86,17 @@ def test_batch_config_persistent(config_case):
     config_case.check(*run(config_case, b), "persistent")
 
 
+def test_batch_config_unpadded_pools():
+    """The full 2048-task configuration with operands packed back to back (odd
+    offsets, so most tasks start off any 16-byte boundary): forward and
+    backward in the persistent launch against the oracle."""
+    say("batch config unpadded pools")
+    case = Case(W.batched_tasks(2048, seed=1, pad=1))
+    assert np.any(case.bt.a_off % 4 != 0) and np.any(case.bt.b_off % 2 == 1)
+    b = api.Batch(case.tb)
+    case.check(*run(case, b), "unpadded")
+
+
 def test_batch_config_plain(config_case):
     say("batch plain")
     b = api.Batch(config_case.tb)

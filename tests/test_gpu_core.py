@@ -436,6 +436,74 @@ def test_mmr_config_2048_sampled(seed):
         check_scalar(C[i, j], R, S, K, what=f"C[{i},{j}]")
 
 
+TILES = ["128x64", "128x128", "128x64w8", "128x128w8", "64x64"]
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_mmr_every_tile_vs_oracle(tile, ta, tb, monkeypatch):
+    """Every tile configuration (forced through MX_GEMM_TILE, read per call) on
+    shapes with edge tiles, ragged K and K a multiple of 64 (interior tiles on
+    the pipelined loop): the whole C against the oracle."""
+    monkeypatch.setenv("MX_GEMM_TILE", tile)
+    for M, N, K in [(300, 200, 128), (257, 385, 100), (512, 256, 192)]:
+        say("mmr tile", tile, ta, tb, M, N, K)
+        A, B = W.dense_f32(M, N, K, seed=M + K + 7 * ta + 3 * tb)
+        As = A.T.copy() if ta else A
+        Bs = B.T.copy() if tb else B
+        C = torch.empty((M, N), device=DEV)
+        abi.mx_map_map_reduce_f32(ta, tb, dev(As), dev(Bs), C)
+        check_vector(host(C).ravel(), O.matmul(A, B).ravel(), _abs_prod_sum(A, B).ravel(), K,
+                     what=f"C {tile} {ta}{tb}")
+
+
+def _rows_cols_check(C, A, B, seed, what):
+    """64 whole rows and 64 whole columns of C = A B against the oracle
+    (including the first and last of each)."""
+    M, K = A.shape
+    N = B.shape[1]
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([[0, M - 1], rng.choice(M, 62, replace=False)]))
+    cols = np.unique(np.concatenate([[0, N - 1], rng.choice(N, 62, replace=False)]))
+    Bt = B.T.copy()  # the oracle reads B^T row by row: same fold, contiguous access
+    R = O.matmul(A[rows], Bt, tb=True)
+    S = O.matmul(np.abs(A[rows]), np.abs(Bt), tb=True)
+    check_vector(C[rows].ravel(), R.ravel(), S.ravel(), K, what=f"{what} rows")
+    Bc = B[:, cols].copy()
+    R = O.matmul(A, Bc)
+    S = O.matmul(np.abs(A), np.abs(Bc))
+    check_vector(C[:, cols].ravel(), R.ravel(), S.ravel(), K, what=f"{what} cols")
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_mmr_config_2048_every_transpose_rows_and_cols(ta, tb):
+    """2048^3 with the default tile choice (256 tiles of 128 x 128 for three of
+    the cases, 128 x 64 for A B^T): 64 whole rows and 64 whole columns."""
+    say("mmr 2048 transposes", ta, tb)
+    M = N = K = 2048
+    A, B = W.dense_f32(M, N, K, seed=10 + 2 * ta + tb)
+    As = A.T.copy() if ta else A
+    Bs = B.T.copy() if tb else B
+    C = torch.empty((M, N), device=DEV)
+    abi.mx_map_map_reduce_f32(ta, tb, dev(As), dev(Bs), C)
+    _rows_cols_check(host(C), A, B, seed=ta * 2 + tb, what=f"C {ta}{tb}")
+
+
+def test_mmr_config_2048_backward_rows_and_cols():
+    """The benchmark's products through autograd: C = A B, then dA = dC B^T
+    (128 x 64 tiles) and dB = A^T dC (128 x 128 tiles), at 2048^3."""
+    say("mmr 2048 backward")
+    M = N = K = 2048
+    A, B = W.dense_f32(M, N, K, seed=0)
+    G = np.random.default_rng(42).uniform(-1, 1, (M, N)).astype(np.float32)
+    tA, tB = dev(A).requires_grad_(), dev(B).requires_grad_()
+    C = api.matmul(tA, tB)
+    C.backward(dev(G))
+    _rows_cols_check(host(C.detach()), A, B, seed=1, what="C")
+    _rows_cols_check(host(tA.grad), G, B.T.copy(), seed=2, what="dA")
+    _rows_cols_check(host(tB.grad), A.T.copy(), G, seed=3, what="dB")
+
+
 def test_mmr_deterministic_and_gradients():
     say("mmr grad")
     M, N, K = 192, 160, 96

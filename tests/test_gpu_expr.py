@@ -327,25 +327,27 @@ def test_argument_errors():
 
 
 def test_full_size_sampled():
-    """2^26 elements in the launch configuration the bench times, checked on a
-    sample of positions (elementwise, so each sampled value is the oracle's)."""
+    """2^26 elements in the launch configuration the bench times: the map
+    checked on a sample of positions (elementwise, so each sampled value is
+    the oracle's), the fused map + reduce against the oracle's left fold of
+    the body over all 2^26 elements of the same inputs."""
     prog, nin, out = GAUSS_DOT
     n = 1 << 26
     say("expr full size", n)
-    gen = torch.Generator(device=DEV).manual_seed(0)
-    ins = [torch.rand(n, device=DEV, generator=gen) * 2 - 1 for _ in range(nin)]
+    xs = inputs(nin, n, abi.MX_F32, 26)
+    ins = [dev(x) for x in xs]
     e = abi.mx_expr_create(prog, nin, out, abi.MX_F32)
     o = torch.empty(n, device=DEV)
     abi.mx_expr_map(e, ins, o)
-    idx = torch.cat([torch.arange(0, 4096, device=DEV), torch.randint(0, n, (1 << 16,), device=DEV, generator=gen),
-                     torch.arange(n - 4096, n, device=DEV)])
-    xs = [host(t[idx]) for t in ins]
-    check_map(host(o[idx]), prog, out, xs, abi.MX_F32, "full size")
+    rng = np.random.default_rng(26)
+    idx = np.concatenate([np.arange(0, 4096), rng.integers(0, n, 1 << 16), np.arange(n - 4096, n)])
+    check_map(host(o)[idx], prog, out, [x[idx] for x in xs], abi.MX_F32, "full size")
     ws = torch.zeros(abi.mx_expr_workspace_bytes(e, n), dtype=torch.uint8, device=DEV)
     r = torch.empty((), device=DEV)
     abi.mx_expr_map_reduce(e, abi.MX_ADD, ins, n, 0.0, r, ws)
-    total = float(host(o).astype(np.float64).sum())   # the sum of the checked map values
-    assert abs(float(host(r)) - total) <= 1e-4 * max(abs(total), float(np.abs(host(o)).sum()) / np.sqrt(n))
+    R = O.expr_map_reduce(O.ADD, 0.0, prog, out, *xs)
+    S = float(np.abs(O.expr_map(prog, out, *xs)).sum())
+    check_scalar(float(host(r)), R, S, n, what="map + reduce 2^26")
 
 
 # ---------------------------------------------------------------- nested map(reduce) over ragged rows

@@ -5,9 +5,11 @@ The full loop is chaotic at the configured size (close pairs at ~eps): a
 1-ulp binary32 perturbation of the initial positions changes the binary64
 gradient by ~5e-3 at N = 1024 and ~2e-1 at N = 2048 (test_nbody_conditioning
 in test_nbody_host.py).  End-to-end loop parity is therefore checked where the
-problem is well conditioned (N = 256), and at the full size N = 16384 every
-single forward and reverse step is checked against the oracle from the same
-state, together with the bit-identity of checkpointed and full-tape reverses.
+problem is well conditioned (N = 256).  At the full size N = 16384 the first,
+middle and last forward steps and reverse steps are checked against the
+oracle from the GPU's own states on 2048 sampled bodies, and the checkpointed
+gradient entry point is shown equal, bit for bit, to that chain of steps;
+checkpointed and full-tape reverses are bit-identical at N = 4096.
 """
 import numpy as np
 import pytest
@@ -212,9 +214,19 @@ def test_loop_graph_replay_matches_eager():
     abi.mx_graph_destroy(graph)
 
 
-def test_config_16384_every_step_vs_oracle_sampled():
-    """Full size: the GPU's own loop, with its first and last forward steps and
-    its last reverse step checked against the oracle from the same state."""
+def test_config_16384_steps_vs_oracle_sampled():
+    """Full size, the launches the benchmark times.  The GPU's own forward loop
+    (mx_nbody_step_f32), its reverse sweep by mx_nbody_adjoint_step_f32 from
+    the GPU's own states and adjoints, and mx_nbody_ke_grad_f32:
+
+    * forward steps t = 0, 10, 19: positions and velocities of the sampled
+      bodies against the oracle's step from the same state;
+    * reverse steps t = 19, 10, 0: xbar_t and vbar_t of the sampled bodies
+      against the oracle's adjoint step from the same (x_t, xbar_{t+1},
+      vbar_{t+1});
+    * mx_nbody_ke_grad_f32 (checkpoints every 5 steps, recomputed segments)
+      equals that chain of checked steps bit for bit, and its KE the final
+      state's kinetic energy."""
     n = 16384
     say("nbody 16384 steps")
     pos, m, vel = W.nbody(n, seed=0)
@@ -222,20 +234,77 @@ def test_config_16384_every_step_vs_oracle_sampled():
     states = [(p4, vv)]
     for t in range(T):
         states.append(api.nbody_step(*states[-1], EPS2, G, DT))
-    for t in (0, T - 1):
+    for t in (0, T // 2, T - 1):
         x_t = host(states[t][0])
         v_t = host(states[t][1])
-        v_next = host(states[t + 1][1])[:, :3]
+        x_next, v_next = host(states[t + 1][0]), host(states[t + 1][1])
         ref_x, ref_v = O.nbody_step(x_t[:, :3], v_t[:, :3], x_t[:, 3], EPS2, G, DT)
+        assert np.array_equal(x_next[:, 3], m), t
+        # x' = x + dt v: one FMA or two roundings of binary32
+        assert np.allclose(x_next[SAMPLE, :3], ref_x[SAMPLE], rtol=2e-7, atol=1e-9), f"x_{t + 1}"
         S = DT * accel_magnitude(x_t[:, :3], x_t[:, 3], EPS2, rows=SAMPLE) + np.abs(v_t[SAMPLE, :3])
-        check_bodies(v_next[SAMPLE], ref_v[SAMPLE], S, n, what=f"v_{t + 1}")
-    # last reverse step from the final state: vbar = m v_T, xbar = 0
-    xT = host(states[T - 1][0])
-    vbar = xT[:, 3:4] * host(states[T][1])[:, :3]
-    out = host(api.nbody_accel_vjp(states[T - 1][0], dev(v4(vbar)), EPS2, G))[:, :3]
-    ref = O.nbody_accel_vjp(xT[:, :3], xT[:, 3], vbar, EPS2, G)
-    check_bodies(out[SAMPLE], ref[SAMPLE], vjp_magnitude(xT[:, :3], xT[:, 3], vbar, EPS2, rows=SAMPLE), n,
-                 what="vjp at t=19")
+        check_bodies(v_next[SAMPLE, :3], ref_v[SAMPLE], S, n, what=f"v_{t + 1}")
+    # reverse sweep: vbar_T = m v_T (binary32 products, as the library forms them), xbar_T = 0
+    vT = host(states[T][1])
+    xb = dev(np.zeros((n, 4), dtype=np.float32))
+    vb = dev(v4(m[:, None] * vT[:, :3]))
+    ws = api.bytes_workspace(abi.mx_nbody_pair_workspace_bytes(n), "nbody_pair")
+    for t in range(T - 1, -1, -1):
+        xbo = torch.empty((n, 4), device=DEV)
+        vbo = torch.empty((n, 4), device=DEV)
+        abi.mx_nbody_adjoint_step_f32(states[t][0], xb, vb, EPS2, G, DT, xbo, vbo, ws)
+        if t in (T - 1, T // 2, 0):
+            x_t = host(states[t][0])
+            xb_in, vb_in = host(xb)[:, :3], host(vb)[:, :3]
+            vjp = O.nbody_accel_vjp(x_t[:, :3], x_t[:, 3], vb_in, EPS2, G)
+            xb_ref = xb_in.astype(np.float64) + DT * vjp
+            vb_ref = vb_in.astype(np.float64) + DT * xb_in.astype(np.float64)
+            S = DT * vjp_magnitude(x_t[:, :3], x_t[:, 3], vb_in, EPS2, rows=SAMPLE) + np.abs(xb_in[SAMPLE])
+            check_bodies(host(xbo)[SAMPLE, :3], xb_ref[SAMPLE], S, n, what=f"xbar_{t}")
+            assert np.allclose(host(vbo)[SAMPLE, :3], vb_ref[SAMPLE], rtol=2e-7, atol=1e-9), f"vbar_{t}"
+        xb, vb = xbo, vbo
+    ke, gx, gv = api.nbody_ke_grad(p4, vv, EPS2, G, DT, T, K)
+    assert host(gx).tobytes() == host(xb).tobytes() and host(gv).tobytes() == host(vb).tobytes()
+    kin = torch.empty((), device=DEV)
+    abi.mx_nbody_kinetic_f32(states[T][0], states[T][1], kin)
+    assert host(ke).tobytes() == host(kin).tobytes()
+    ke_ref = O.nbody_kinetic(vT[:, :3], m)
+    assert abs(float(host(ke)) - ke_ref) <= 1e-4 * ke_ref
+
+
+def test_ke_forward_and_vjp_split_equals_fused_grad():
+    """mx_nbody_ke_f32 + mx_nbody_ke_vjp_f32 (no gscale) give mx_nbody_ke_grad_f32
+    bit for bit; a device gscale g scales the seed: g = 2 exactly doubles the
+    gradients (every rounding is scaled by a power of two), g = 0.3 agrees
+    with 0.3 times them within binary32 rounding of the seed."""
+    n = 1500
+    say("nbody ke split")
+    pos, m, vel = W.nbody(n, seed=6)
+    vel = np.random.default_rng(6).normal(scale=0.1, size=(n, 3)).astype(np.float32)
+    p4, vv = dev(to4(pos, m)), dev(v4(vel))
+    ke0, gx0, gv0 = [host(t) for t in api.nbody_ke_grad(p4, vv, EPS2, G, DT, T, K)]
+    ws = torch.zeros(abi.mx_nbody_workspace_bytes(n, T, K), dtype=torch.uint8, device=DEV)
+    ke = torch.empty((), device=DEV)
+    abi.mx_nbody_ke_f32(p4, vv, EPS2, G, DT, T, K, ke, ws)
+    assert host(ke).tobytes() == ke0.tobytes()
+    for g in (None, 2.0, 0.3):
+        gx, gv = torch.empty((n, 4), device=DEV), torch.empty((n, 4), device=DEV)
+        gs = None if g is None else torch.tensor([g], dtype=torch.float32, device=DEV)
+        abi.mx_nbody_ke_vjp_f32(p4, vv, EPS2, G, DT, T, K, gs, gx, gv, ws)
+        gx, gv = host(gx), host(gv)
+        if g is None:
+            assert gx.tobytes() == gx0.tobytes() and gv.tobytes() == gv0.tobytes()
+        elif g == 2.0:
+            assert np.array_equal(gx, 2 * gx0) and np.array_equal(gv, 2 * gv0)
+        else:
+            for a, b in ((gx, gx0), (gv, gv0)):
+                ref = np.float64(np.float32(g)) * b.astype(np.float64)
+                assert np.linalg.norm(a - ref) <= 1e-5 * np.linalg.norm(ref)
+    # n = 0: KE = 0, nothing else written
+    e = torch.zeros((0, 4), device=DEV)
+    k0 = torch.full((), 5.0, device=DEV)
+    abi.mx_nbody_ke_f32(e, e, EPS2, G, DT, T, K, k0, torch.zeros(256, dtype=torch.uint8, device=DEV))
+    assert float(host(k0)) == 0.0
 
 
 def test_autograd_wrapper_matches_entry_point():

@@ -155,7 +155,7 @@ class BatchedTasks:
 
 
 def batched_tasks(ntasks: int, seed: int = 0, smin: float = 1e2, smax: float = 1e6,
-                  max_total: int | None = None) -> BatchedTasks:
+                  max_total: int | None = None, pad: int = 4) -> BatchedTasks:
     """Uneven batch: even task index = dot, odd = matvec.
 
     Sizes s = floor(exp(U[ln smin, ln smax))).  A dot has s elements per operand;
@@ -163,6 +163,9 @@ def batched_tasks(ntasks: int, seed: int = 0, smin: float = 1e2, smax: float = 1
     uniform in [-1, 1]; the upstream gradient is 1.0 for every dot output and
     uniform in [-1, 1] for matvec outputs.  ``max_total`` (optional) rescales
     nothing: it only asserts that the A pool stays below that many elements.
+    ``pad``: operand lengths are rounded up to a multiple of ``pad`` floats in
+    the pools (4: every operand starts on a 16-byte boundary; 1: operands are
+    packed back to back at arbitrary offsets).
     """
     rng = _rng(seed)
     s = np.floor(np.exp(rng.uniform(math.log(smin), math.log(smax), ntasks))).astype(np.int64)
@@ -178,10 +181,10 @@ def batched_tasks(ntasks: int, seed: int = 0, smin: float = 1e2, smax: float = 1
     a_len = rows * cols
     b_len = cols.copy()
     o_len = np.where(mv, rows, 1).astype(np.int64)
-    # operands start on 16-byte boundaries (lengths padded to multiples of 4
-    # floats; the padding belongs to no task)
-    a_pad = (a_len + 3) // 4 * 4
-    b_pad = (b_len + 3) // 4 * 4
+    # with pad = 4, operands start on 16-byte boundaries (lengths padded to
+    # multiples of 4 floats; the padding belongs to no task)
+    a_pad = (a_len + pad - 1) // pad * pad
+    b_pad = (b_len + pad - 1) // pad * pad
     a_off = np.zeros(ntasks, dtype=np.int64)
     b_off = np.zeros(ntasks, dtype=np.int64)
     out_off = np.zeros(ntasks, dtype=np.int64)
