@@ -665,14 +665,95 @@ mx_status mx_expr_loop_scatter(mx_expr *e, const void *const *in_dev, int64_t n,
  * s_i = (gout ? gout[i] : 1) * (gscale ? *gscale : 1) (gout a device array of
  * n, gscale a device scalar; either may be NULL).  The adjoint flows back
  * through the instructions in reverse order; min / max pass it to the
- * operand they returned and a zero term to the other, abs to x with the sign
- * of the branch taken;
+ * operand they returned only (the other operand, and the values behind it
+ * that nothing else uses, receive nothing: a pole on the branch not taken
+ * leaves the gradient finite), abs to x with the sign of the branch taken;
  * instructions the output does not depend on pass nothing.  gin_dev: host
  * array of nin device pointers, NULL entries skipped.  With gout = NULL and
  * gscale the upstream gradient of a map + reduce (+) this is that reduce's
  * adjoint. */
 mx_status mx_expr_vjp(mx_expr *e, const void *const *in_dev, int64_t n, const void *gout_dev,
                       const void *gscale_dev, void *const *gin_dev, hipStream_t stream);
+
+/* ======================================================================= */
+/* The general parallel loop (Appendix A, Source Language: `loop n f` runs  */
+/* f i for every i in [0, n) in an undefined order; f reads and writes      */
+/* tensors through tensorGet / tensorSet -- Listing 1's in-place axpy)      */
+/* ======================================================================= */
+/* A loop body is a straight-line program over two register files: 64 integer
+ * registers (int64, two's-complement wrap-around) and 64 float registers of
+ * the loop's float type T (F32 or F64), all starting at 0 in every
+ * iteration.  Tensors (the paper's Tensor[Int] / Tensor[Float], rank 1 to 3
+ * -- the default maximum rank of Appendix "Dynamic Assumptions") are numbered
+ * 0..ntensors-1 (at most 8), each with an element type (F32, F64, I32, I64)
+ * and a rank fixed when the loop is created; their data and dimensions are
+ * given per run, row-major (the last index fastest).
+ *
+ *   MX_L_ITER           i[dst] = the iteration number i
+ *   MX_L_ICONST         i[dst] = iimm
+ *   MX_L_IADD .. IMAX   i[dst] = i[a] op i[b]; IDIV truncates toward zero and
+ *                       IMOD is the remainder of that division (a - (a/b) b);
+ *                       a zero divisor gives 0 for both; INT64_MIN / -1
+ *                       wraps to INT64_MIN
+ *   MX_L_INEG           i[dst] = -i[a]
+ *   MX_L_I2F            f[dst] = i[a] rounded to T
+ *   the map-body codes MX_X_CONST .. MX_X_RSQRT act on the float registers:
+ *                       f[dst] = fimm (rounded to T), f[a] op f[b], f(f[a])
+ *   MX_L_FGET / IGET    f[dst] / i[dst] = tensor[t][i[a]] (rank 1),
+ *                       [i[a], i[b]] (rank 2), [i[a], i[b], i[c]] (rank 3);
+ *                       a float tensor for FGET, an integer one for IGET
+ *   MX_L_FSET / ISET    tensor[t][index as above] = f[src] / i[src], rounded
+ *                       (F32) or wrapped (I32) to the element type
+ *
+ * Within an iteration the instructions take effect in program order (a get
+ * after a set of the same slot sees the stored value).  Iterations run in
+ * parallel in no particular order: the result is defined when no slot that
+ * one iteration writes is written or read by another -- the user's
+ * guarantee, as in the paper.  An index outside its dimension makes a get
+ * yield 0 and a set write nothing (never a fault).  Debug mode
+ * (mx_set_debug) first traces every iteration without writing anything --
+ * the indices as the iteration computes them, its own earlier sets
+ * included -- and fails with MX_ERR_SHAPE, before anything is written, when
+ * an index is out of range, two iterations set one slot, or an iteration
+ * reads a slot another one sets; it uses the workspace of
+ * mx_loop_workspace_bytes (one int64 per element of every tensor the body
+ * sets, 256-byte aligned; NULL is fine outside debug mode) and synchronises.
+ * The body is compiled (hipRTC) into HIP source on first use per device. */
+typedef enum {
+    MX_L_ITER = 32, MX_L_ICONST = 33,
+    MX_L_IADD = 34, MX_L_ISUB = 35, MX_L_IMUL = 36, MX_L_IDIV = 37, MX_L_IMOD = 38, MX_L_IMIN = 39, MX_L_IMAX = 40,
+    MX_L_INEG = 41, MX_L_I2F = 42,
+    MX_L_FGET = 48, MX_L_IGET = 49, MX_L_FSET = 50, MX_L_ISET = 51
+} mx_lop;
+typedef struct {
+    int32_t op, dst, a, b, c, src, tensor, reserved;  /* reserved: 0 */
+    int64_t iimm;
+    double fimm;
+} mx_linsn;
+typedef struct {
+    mx_dtype dtype;
+    int32_t rank;  /* 1..3 */
+} mx_ltype;
+typedef struct {
+    void *data;       /* device, dims[0] * .. * dims[rank-1] elements */
+    int64_t dims[3];  /* entries past the rank are ignored */
+} mx_ltensor;
+typedef struct mx_loop mx_loop;
+
+/* At most 256 instructions, 8 tensors, registers 0..63.  Checks operands,
+ * register files, tensor numbers and element kinds.  Errors: MX_ERR_INVALID,
+ * MX_ERR_DTYPE. */
+mx_status mx_loop_create(const mx_linsn *prog, int ninsn, const mx_ltype *tensors, int ntensors, mx_dtype float_type,
+                         mx_loop **out);
+mx_status mx_loop_destroy(mx_loop *l);
+mx_status mx_loop_prepare(mx_loop *l);
+const char *mx_loop_source(const mx_loop *l);
+size_t mx_loop_workspace_bytes(const mx_loop *l, const mx_ltensor *tensors);
+/* Runs loop n f with tensors (host array of ntensors descriptors).  Errors:
+ * MX_ERR_INVALID, MX_ERR_SHAPE (negative sizes; debug-mode findings),
+ * MX_ERR_WORKSPACE (debug mode), MX_ERR_HIP. */
+mx_status mx_loop_run(mx_loop *l, int64_t n, const mx_ltensor *tensors, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
 
 /* ======================================================================= */
 /* HIP graphs of launch sequences (loop bodies, forward + backward passes)  */

@@ -73,6 +73,8 @@ def _declare(lib):
         "or_segmented_foldl_i64": (None, [_int, _i64, _p, _p, _i64, _p]),
         "or_segmented_sum_adjoint_f64": (None, [_p, _p, _i64, _p]),
         "or_reduce_adjoint_f64": (_int, [_int, _d, _p, _i64, _d, _p]),
+        "or_loop_run": (_int, [_p, _p, _p, _int, _int, _p, _p, _p, _p, _p, _i64, _p]),
+        "or_loop_check": (_int, [_p, _p, _p, _int, _int, _p, _p, _p, _p, _p, _i64]),
         "or_segmented_reduce_adjoint_f64": (_int, [_int, _d, _p, _p, _i64, _p, _p]),
         "or_matmul_f64": (None, [_p, _p, _p, _i64, _i64, _i64, _int, _int]),
         "or_nbody_accel": (None, [_p, _p, _i64, _d, _d, _p]),
@@ -484,6 +486,64 @@ def expr_loop_scatter(prog, out_reg: int, inputs, idx, out_init):
     _L().or_expr_loop_scatter_f64(_ptr(code), _ptr(imm), code.shape[0], out_reg, _ptr(X), n, _ptr(ix), _ptr(out),
                                   out.size)
     return out
+
+
+# ---------------------------------------------------------------- the general parallel loop
+(L_ITER, L_ICONST, L_IADD, L_ISUB, L_IMUL, L_IDIV, L_IMOD, L_IMIN, L_IMAX, L_INEG, L_I2F) = range(32, 43)
+L_FGET, L_IGET, L_FSET, L_ISET = 48, 49, 50, 51
+
+
+def _loop_prog(prog):
+    """prog: tuples (op, dst, a, b, c, src, tensor, iimm, fimm)."""
+    m = len(prog)
+    code = np.zeros((max(m, 1), 8), dtype=np.int32)
+    iimm = np.zeros(max(m, 1), dtype=np.int64)
+    fimm = np.zeros(max(m, 1), dtype=np.float64)
+    for k, q in enumerate(prog):
+        code[k, :7] = q[:7]
+        iimm[k] = int(q[7])
+        fimm[k] = float(q[8])
+    return code, iimm, fimm, m
+
+
+def _loop_tensors(tensors):
+    """Working copies: float tensors as float64, integer tensors as int64."""
+    arrs, is_int, is32, rank, dims = [], [], [], [], []
+    for t in tensors:
+        t = np.asarray(t)
+        if t.ndim < 1 or t.ndim > 3:
+            raise ValueError("tensors have rank 1..3")
+        integer = np.issubdtype(t.dtype, np.integer)
+        arrs.append(np.ascontiguousarray(t, dtype=np.int64 if integer else np.float64).copy())
+        is_int.append(int(integer))
+        is32.append(int(t.dtype == np.int32))
+        rank.append(t.ndim)
+        dims.extend(list(t.shape) + [1] * (3 - t.ndim))
+    k = len(arrs)
+    ptrs = (ctypes.c_void_p * max(k, 1))(*[a.ctypes.data for a in arrs])
+    return (arrs, np.array(is_int or [0], np.int32), np.array(is32 or [0], np.int32), np.array(rank or [1], np.int32),
+            np.array(dims or [0, 0, 0], np.int64), ptrs)
+
+
+def loop_run(prog, tensors, n: int, order=None):
+    """loop n f over copies of the tensors, iterations in `order` (default
+    ascending).  Returns (tensors after the loop, flags; bit 0: an index was
+    out of range)."""
+    code, iimm, fimm, m = _loop_prog(prog)
+    arrs, is_int, is32, rank, dims, ptrs = _loop_tensors(tensors)
+    o = None if order is None else _i64a(order)
+    flags = _L().or_loop_run(_ptr(code), _ptr(iimm), _ptr(fimm), m, len(arrs), _ptr(is_int), _ptr(is32), _ptr(rank),
+                             _ptr(dims), ptrs, int(n), _ptr(o) if o is not None else None)
+    return arrs, int(flags)
+
+
+def loop_check(prog, tensors, n: int) -> int:
+    """The debug-mode verdict: bit 0 an index out of range, bit 1 a slot set by
+    two iterations, bit 2 a slot set by one iteration and read by another."""
+    code, iimm, fimm, m = _loop_prog(prog)
+    arrs, is_int, is32, rank, dims, ptrs = _loop_tensors(tensors)
+    return int(_L().or_loop_check(_ptr(code), _ptr(iimm), _ptr(fimm), m, len(arrs), _ptr(is_int), _ptr(is32),
+                                  _ptr(rank), _ptr(dims), ptrs, int(n)))
 
 
 # ---------------------------------------------------------------- Parboil-shaped kernels (Table 1)

@@ -757,6 +757,177 @@ void or_expr_loop_scatter_f64(const int32_t *code, const double *imm, int ninsn,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The general parallel loop (Appendix A, Source Language: `loop n f` calls  */
+/* f i for every i in [0, n) in an undefined order; f reads and writes       */
+/* tensors with tensorGet / tensorSet, as in Listing 1's in-place axpy).     */
+/* The body is a straight-line program over 64 int64 registers and 64       */
+/* binary64 registers; tensors (rank 1..3, row-major) hold binary64 (float   */
+/* element types) or int64 (integer element types, an I32 tensor keeping    */
+/* its stores wrapped to 32 bits) values.                                   */
+/* ------------------------------------------------------------------------ */
+enum { OR_L_ITER = 32, OR_L_ICONST = 33, OR_L_IADD = 34, OR_L_ISUB = 35, OR_L_IMUL = 36, OR_L_IDIV = 37,
+       OR_L_IMOD = 38, OR_L_IMIN = 39, OR_L_IMAX = 40, OR_L_INEG = 41, OR_L_I2F = 42,
+       OR_L_FGET = 48, OR_L_IGET = 49, OR_L_FSET = 50, OR_L_ISET = 51 };
+#define OR_L_REGS 64
+#define OR_L_MAXSET 256
+
+typedef struct {
+    int ntensors;
+    const int *is_int, *is32, *rank;
+    const int64_t *dims;   /* 3 per tensor */
+    void *const *data;     /* double * or int64_t * */
+} or_tensors;
+
+/* integer division truncating toward zero, 0 for a zero divisor, wrapping
+ * INT64_MIN / -1 */
+static int64_t l_idiv(int64_t a, int64_t b)
+{
+    if (b == 0) return 0;
+    if (b == -1) return (int64_t)(0 - (uint64_t)a);
+    return a / b;
+}
+
+static int64_t l_imod(int64_t a, int64_t b)
+{
+    if (b == 0 || b == -1) return 0;
+    return a % b;
+}
+
+/* slot of tensor t at the index registers, -1 when out of range */
+static int64_t l_slot(const or_tensors *T, int t, int64_t i0, int64_t i1, int64_t i2)
+{
+    const int64_t *d = T->dims + 3 * t;
+    const int r = T->rank[t];
+    if (i0 < 0 || i0 >= d[0]) return -1;
+    if (r == 1) return i0;
+    if (i1 < 0 || i1 >= d[1]) return -1;
+    if (r == 2) return i0 * d[1] + i1;
+    if (i2 < 0 || i2 >= d[2]) return -1;
+    return (i0 * d[1] + i1) * d[2] + i2;
+}
+
+static int64_t l_numel(const or_tensors *T, int t)
+{
+    int64_t m = 1;
+    for (int k = 0; k < T->rank[t]; ++k) m *= T->dims[3 * t + k];
+    return m;
+}
+
+/* One iteration.  mode 0: run (gets and sets on the tensors).  mode 1 and 2
+ * trace it without writing: sets go to a private log that later gets of the
+ * same iteration read first.  mode 1 claims every set slot for iteration
+ * it in owner[t] (0 = free, it + 1 = taken) and flags 2 when another
+ * iteration holds it; mode 2 flags 4 for a get of a slot another iteration
+ * owns.  Returns the flags, bit 0 for an index out of range. */
+static int l_exec(const int32_t *code, const int64_t *iimm, const double *fimm, int ninsn, const or_tensors *T,
+                  int64_t it, int mode, int64_t *const *owner)
+{
+    int64_t ir[OR_L_REGS];
+    double fr[OR_L_REGS];
+    int logt[OR_L_MAXSET];
+    int64_t logs[OR_L_MAXSET], logi[OR_L_MAXSET];
+    double logf[OR_L_MAXSET];
+    int nlog = 0, flags = 0;
+    for (int q = 0; q < OR_L_REGS; ++q) { ir[q] = 0; fr[q] = 0.0; }
+    for (int k = 0; k < ninsn; ++k) {
+        const int32_t *c = code + 8 * k;
+        const int op = c[0], dst = c[1], a = c[2], b = c[3], cc = c[4], src = c[5], t = c[6];
+        switch (op) {
+        case OR_L_ITER: ir[dst] = it; break;
+        case OR_L_ICONST: ir[dst] = iimm[k]; break;
+        case OR_L_IADD: ir[dst] = (int64_t)((uint64_t)ir[a] + (uint64_t)ir[b]); break;
+        case OR_L_ISUB: ir[dst] = (int64_t)((uint64_t)ir[a] - (uint64_t)ir[b]); break;
+        case OR_L_IMUL: ir[dst] = (int64_t)((uint64_t)ir[a] * (uint64_t)ir[b]); break;
+        case OR_L_IDIV: ir[dst] = l_idiv(ir[a], ir[b]); break;
+        case OR_L_IMOD: ir[dst] = l_imod(ir[a], ir[b]); break;
+        case OR_L_IMIN: ir[dst] = ir[b] < ir[a] ? ir[b] : ir[a]; break;
+        case OR_L_IMAX: ir[dst] = ir[b] > ir[a] ? ir[b] : ir[a]; break;
+        case OR_L_INEG: ir[dst] = (int64_t)(0 - (uint64_t)ir[a]); break;
+        case OR_L_I2F: fr[dst] = (double)ir[a]; break;
+        case OR_L_FGET:
+        case OR_L_IGET: {
+            const int64_t sl = l_slot(T, t, ir[a], ir[b], ir[cc]);
+            double fv = 0.0;
+            int64_t iv = 0;
+            if (sl < 0) {
+                flags |= 1;
+            } else {
+                int hit = 0;
+                for (int e = nlog - 1; e >= 0 && !hit; --e)
+                    if (logt[e] == t && logs[e] == sl) { fv = logf[e]; iv = logi[e]; hit = 1; }
+                if (!hit) {
+                    if (T->is_int[t]) iv = ((const int64_t *)T->data[t])[sl];
+                    else fv = ((const double *)T->data[t])[sl];
+                }
+                if (mode == 2 && owner[t] && owner[t][sl] != 0 && owner[t][sl] != it + 1) flags |= 4;
+            }
+            if (op == OR_L_FGET) fr[dst] = fv;
+            else ir[dst] = iv;
+            break;
+        }
+        case OR_L_FSET:
+        case OR_L_ISET: {
+            const int64_t sl = l_slot(T, t, ir[a], ir[b], ir[cc]);
+            if (sl < 0) { flags |= 1; break; }
+            int64_t iv = op == OR_L_ISET ? ir[src] : 0;
+            if (op == OR_L_ISET && T->is32[t]) iv = (int64_t)(int32_t)(uint32_t)(uint64_t)iv;
+            const double fv = op == OR_L_FSET ? fr[src] : 0.0;
+            if (mode == 0) {
+                if (T->is_int[t]) ((int64_t *)T->data[t])[sl] = iv;
+                else ((double *)T->data[t])[sl] = fv;
+            } else {
+                if (nlog < OR_L_MAXSET) { logt[nlog] = t; logs[nlog] = sl; logi[nlog] = iv; logf[nlog] = fv; ++nlog; }
+                if (mode == 1) {
+                    if (owner[t][sl] == 0) owner[t][sl] = it + 1;
+                    else if (owner[t][sl] != it + 1) flags |= 2;
+                }
+            }
+            break;
+        }
+        default:  /* float arithmetic: the map-body operators on float registers */
+            if (op == OR_X_CONST) fr[dst] = fimm[k];
+            else fr[dst] = x_apply(op, fr[a], op >= OR_X_ADD && op <= OR_X_MAX ? fr[b] : 0.0, 0.0, 0.0);
+            break;
+        }
+    }
+    return flags;
+}
+
+/* loop n f: iterations in the order given (NULL: ascending).  Returns bit 0
+ * when an index was out of range (that get gave 0, that set wrote nothing). */
+int or_loop_run(const int32_t *code, const int64_t *iimm, const double *fimm, int ninsn, int ntensors,
+                const int *is_int, const int *is32, const int *rank, const int64_t *dims, void *const *data,
+                int64_t n, const int64_t *order)
+{
+    const or_tensors T = {ntensors, is_int, is32, rank, dims, data};
+    int flags = 0;
+    for (int64_t j = 0; j < n; ++j) flags |= l_exec(code, iimm, fimm, ninsn, &T, order ? order[j] : j, 0, NULL);
+    return flags;
+}
+
+/* The debug-mode check: every iteration traced from the tensors as they are
+ * before the loop (its own earlier sets visible to its own gets), nothing
+ * written.  Flags: 1 an index out of range, 2 a slot set by two iterations,
+ * 4 a slot one iteration sets and another reads. */
+int or_loop_check(const int32_t *code, const int64_t *iimm, const double *fimm, int ninsn, int ntensors,
+                  const int *is_int, const int *is32, const int *rank, const int64_t *dims, void *const *data,
+                  int64_t n)
+{
+    const or_tensors T = {ntensors, is_int, is32, rank, dims, data};
+    int64_t *owner[8] = {0};
+    int flags = 0;
+    for (int k = 0; k < ninsn; ++k) {
+        const int op = code[8 * k], t = code[8 * k + 6];
+        if ((op == OR_L_FSET || op == OR_L_ISET) && !owner[t])
+            owner[t] = (int64_t *)calloc((size_t)(l_numel(&T, t) > 0 ? l_numel(&T, t) : 1), sizeof(int64_t));
+    }
+    for (int64_t i = 0; i < n; ++i) flags |= l_exec(code, iimm, fimm, ninsn, &T, i, 1, owner);
+    for (int64_t i = 0; i < n; ++i) flags |= l_exec(code, iimm, fimm, ninsn, &T, i, 2, owner);
+    for (int t = 0; t < 8; ++t) free(owner[t]);
+    return flags;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Kernels of the shapes in the paper's Parboil comparison (Table 1), on     */
 /* synthetic inputs (the datasets are not available).                        */
 /* ------------------------------------------------------------------------ */
