@@ -93,6 +93,12 @@ SIGNATURES = {
     "mx_expr_loop_workspace_bytes": (c_size, [c_i64]),
     "mx_expr_loop_scatter": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_i64, c_p, c_size, c_p]),
     "mx_expr_vjp": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_pp, c_p]),
+    "mx_loop_create": (c_status, [c_p, c_int, c_p, c_int, c_enum, c_pp]),
+    "mx_loop_destroy": (c_status, [c_p]),
+    "mx_loop_prepare": (c_status, [c_p]),
+    "mx_loop_source": (ctypes.c_char_p, [c_p]),
+    "mx_loop_workspace_bytes": (c_size, [c_p, c_p]),
+    "mx_loop_run": (c_status, [c_p, c_i64, c_p, c_p, c_size, c_p]),
     "mx_graph_begin": (c_status, [c_p]),
     "mx_graph_end": (c_status, [c_p, c_pp]),
     "mx_graph_launch": (c_status, [c_p, c_p]),

@@ -608,3 +608,83 @@ def mx_graph_destroy(graph: Graph) -> None:
     if graph.handle:
         _check(_L().mx_graph_destroy(graph.handle), "mx_graph_destroy")
         graph.handle = None
+
+
+# ---------------------------------------------------------------- the general parallel loop
+(MX_L_ITER, MX_L_ICONST, MX_L_IADD, MX_L_ISUB, MX_L_IMUL, MX_L_IDIV, MX_L_IMOD, MX_L_IMIN, MX_L_IMAX, MX_L_INEG,
+ MX_L_I2F) = range(32, 43)
+MX_L_FGET, MX_L_IGET, MX_L_FSET, MX_L_ISET = 48, 49, 50, 51
+
+
+class LInsn(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("dst", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("c", ctypes.c_int32), ("src", ctypes.c_int32), ("tensor", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("iimm", ctypes.c_int64), ("fimm", ctypes.c_double)]
+
+
+class LType(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("rank", ctypes.c_int32)]
+
+
+class LTensor(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dims", ctypes.c_int64 * 3)]
+
+
+class Loop:
+    """Owning handle of an mx_loop (destroyed with the object)."""
+
+    def __init__(self, handle: int, types):
+        self.handle, self.types = handle, list(types)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                _L().mx_loop_destroy(self.handle)
+            except Exception:  # interpreter shutdown: the library may already be gone
+                pass
+            self.handle = None
+
+
+def mx_loop_create(prog, types, float_dtype: int) -> Loop:
+    """prog: tuples (op, dst, a, b, c, src, tensor, iimm, fimm); types: (dtype, rank) per tensor."""
+    ins = (LInsn * max(1, len(prog)))()
+    for i, q in enumerate(prog):
+        op, dst, a, b, c, src, tensor, iimm, fimm = q
+        ins[i] = LInsn(int(op), int(dst), int(a), int(b), int(c), int(src), int(tensor), 0, int(iimm), float(fimm))
+    tt = (LType * max(1, len(types)))()
+    for i, (dt, rank) in enumerate(types):
+        tt[i] = LType(int(dt), int(rank))
+    h = ctypes.c_void_p()
+    _check(_L().mx_loop_create(ins, len(prog), tt, len(types), int(float_dtype), ctypes.byref(h)), "mx_loop_create")
+    return Loop(h.value, types)
+
+
+def _ltensors(tensors):
+    arr = (LTensor * max(1, len(tensors)))()
+    for i, t in enumerate(tensors):
+        dims = list(t.shape) + [1] * (3 - t.dim())
+        arr[i] = LTensor(_dptr(t), (ctypes.c_int64 * 3)(*dims))
+    return arr
+
+
+def mx_loop_prepare(lp: Loop) -> None:
+    _check(_L().mx_loop_prepare(lp.handle), "mx_loop_prepare")
+
+
+def mx_loop_source(lp: Loop) -> str:
+    return _L().mx_loop_source(lp.handle).decode()
+
+
+def mx_loop_workspace_bytes(lp: Loop, tensors) -> int:
+    return int(_L().mx_loop_workspace_bytes(lp.handle, _ltensors(tensors)))
+
+
+def mx_loop_run(lp: Loop, n: int, tensors, ws=None, stream=None) -> None:
+    """tensors: contiguous device tensors of rank 1..3, in the loop's order."""
+    if len(tensors) != len(lp.types):
+        raise MxError(MX_ERR_INVALID, "mx_loop_run: wrong number of tensors")
+    for t, (dt, rank) in zip(tensors, lp.types):
+        if t.dim() != rank or _dtype(t) != dt:
+            raise MxError(MX_ERR_SHAPE, "mx_loop_run: tensor rank or dtype differs from the loop's")
+    _check(_L().mx_loop_run(lp.handle, int(n), _ltensors(tensors), _dptr(ws), _nbytes(ws), _stream(stream)),
+           "mx_loop_run")

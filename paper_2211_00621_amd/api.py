@@ -757,3 +757,152 @@ class _BodySegReduce(torch.autograd.Function):
         vals = body._map(*xs) if ctx.op != MX_ADD else None
         abi.mx_segmented_reduce_adjoint_f32(ctx.op, vals, offsets, ctx.ne, g.contiguous(), seed)
         return (None, None, None, None, *_shaped(body.vjp(*xs, gout=seed), xs))
+
+
+# ---------------------------------------------------------------- the general parallel loop
+class _LVal:
+    """A value of a loop body under construction (integer or float register)."""
+
+    def __init__(self, lp: "ParallelLoop", reg: int, is_int: bool):
+        self.lp, self.reg, self.is_int = lp, reg, is_int
+
+    def _other(self, o):
+        if isinstance(o, _LVal):
+            if o.is_int != self.is_int:
+                raise TypeError("integer and float values do not mix; use .to_float()")
+            return o
+        return self.lp.const(o, self.is_int)
+
+    def _bin(self, iop, fop, o, swap=False):
+        o = self._other(o)
+        a, b = (o, self) if swap else (self, o)
+        return self.lp._emit(iop if self.is_int else fop, self.is_int, a=a.reg, b=b.reg)
+
+    def __add__(self, o): return self._bin(abi.MX_L_IADD, abi.MX_X_ADD, o)
+    def __radd__(self, o): return self._bin(abi.MX_L_IADD, abi.MX_X_ADD, o, True)
+    def __sub__(self, o): return self._bin(abi.MX_L_ISUB, abi.MX_X_SUB, o)
+    def __rsub__(self, o): return self._bin(abi.MX_L_ISUB, abi.MX_X_SUB, o, True)
+    def __mul__(self, o): return self._bin(abi.MX_L_IMUL, abi.MX_X_MUL, o)
+    def __rmul__(self, o): return self._bin(abi.MX_L_IMUL, abi.MX_X_MUL, o, True)
+
+    def __truediv__(self, o):
+        if self.is_int:
+            raise TypeError("integer division is //")
+        return self._bin(None, abi.MX_X_DIV, o)
+
+    def __floordiv__(self, o):
+        """Integer division truncating toward zero (C semantics; 0 for a zero divisor)."""
+        if not self.is_int:
+            raise TypeError("// is integer division")
+        return self._bin(abi.MX_L_IDIV, None, o)
+
+    def __mod__(self, o):
+        if not self.is_int:
+            raise TypeError("% is the integer remainder")
+        return self._bin(abi.MX_L_IMOD, None, o)
+
+    def __neg__(self):
+        return self.lp._emit(abi.MX_L_INEG if self.is_int else abi.MX_X_NEG, self.is_int, a=self.reg)
+
+    def to_float(self):
+        if not self.is_int:
+            return self
+        return self.lp._emit(abi.MX_L_I2F, False, a=self.reg)
+
+
+class ParallelLoop:
+    """`loop n f` with tensorGet / tensorSet: the body is written imperatively
+    against an iteration value, compiled by the library (hipRTC) on first run.
+
+        lp = ParallelLoop([(torch.float32, 1), (torch.float32, 1)])
+        i = lp.iteration
+        lp.set(0, i, lp.get(0, i) + 2.0 * lp.get(1, i))     # Listing 1's axpy
+        lp.run(n, t1, t2)
+    """
+
+    def __init__(self, types, float_dtype=torch.float32):
+        self.types = [(abi.DTYPE_OF[dt], int(rank)) for dt, rank in types]
+        self.float_dtype = abi.DTYPE_OF[float_dtype]
+        self.prog = []
+        self._next = [0, 0]  # float, int registers
+        self._handle = None
+        self.iteration = self._emit(abi.MX_L_ITER, True)
+
+    def _reg(self, is_int):
+        r = self._next[is_int]
+        if r >= 64:
+            raise ValueError("the loop body needs more than 64 registers of one kind")
+        self._next[is_int] += 1
+        return r
+
+    def _emit(self, op, is_int, a=0, b=0, iimm=0, fimm=0.0):
+        dst = self._reg(is_int)
+        self.prog.append((op, dst, a, b, 0, 0, 0, iimm, fimm))
+        self._handle = None
+        return _LVal(self, dst, is_int)
+
+    def const(self, v, is_int=None):
+        if is_int is None:
+            is_int = isinstance(v, (int, np.integer))
+        if is_int:
+            return self._emit(abi.MX_L_ICONST, True, iimm=int(v))
+        return self._emit(abi.MX_X_CONST, False, fimm=float(v))
+
+    def _index(self, t, idx):
+        rank = self.types[t][1]
+        idx = list(idx)
+        if len(idx) != rank:
+            raise ValueError(f"tensor {t} has rank {rank}")
+        regs = [(x if isinstance(x, _LVal) else self.const(int(x), True)) for x in idx]
+        if any(not r.is_int for r in regs):
+            raise TypeError("indices are integer values")
+        regs = [r.reg for r in regs] + [0] * (3 - rank)
+        return regs
+
+    def get(self, t: int, *idx) -> _LVal:
+        a, b, c = self._index(t, idx)
+        is_int = self.types[t][0] in (abi.MX_I32, abi.MX_I64)
+        dst = self._reg(is_int)
+        self.prog.append((abi.MX_L_IGET if is_int else abi.MX_L_FGET, dst, a, b, c, 0, t, 0, 0.0))
+        self._handle = None
+        return _LVal(self, dst, is_int)
+
+    def set(self, t: int, idx, value) -> None:
+        if not isinstance(idx, (tuple, list)):
+            idx = (idx,)
+        a, b, c = self._index(t, idx)
+        is_int = self.types[t][0] in (abi.MX_I32, abi.MX_I64)
+        if not isinstance(value, _LVal):
+            value = self.const(value, is_int)
+        if value.is_int != is_int:
+            raise TypeError("the value's kind differs from the tensor's element kind")
+        self.prog.append((abi.MX_L_ISET if is_int else abi.MX_L_FSET, 0, a, b, c, value.reg, t, 0, 0.0))
+        self._handle = None
+
+    def unary(self, xop: int, x: _LVal) -> _LVal:
+        """f(x) for a float map-body operator (MX_X_NEG .. MX_X_RSQRT)."""
+        return self._emit(xop, False, a=x.reg)
+
+    def binary(self, op: int, x: _LVal, y) -> _LVal:
+        """min / max (MX_X_MIN / MX_X_MAX, or MX_L_IMIN / MX_L_IMAX) and the other binary codes."""
+        y = x._other(y)
+        return self._emit(op, x.is_int, a=x.reg, b=y.reg)
+
+    @property
+    def handle(self):
+        if self._handle is None:
+            self._handle = abi.mx_loop_create(self.prog, self.types, self.float_dtype)
+        return self._handle
+
+    def source(self) -> str:
+        return abi.mx_loop_source(self.handle)
+
+    def run(self, n: int, *tensors, stream=None) -> None:
+        ts = [t if t.is_contiguous() else t.contiguous() for t in tensors]
+        if any(a is not b for a, b in zip(ts, tensors)):
+            raise ValueError("loop tensors must be contiguous (they are written in place)")
+        ws = None
+        if abi.mx_get_debug():
+            ws = torch.zeros(max(abi.mx_loop_workspace_bytes(self.handle, ts), 256), dtype=torch.uint8,
+                             device=ts[0].device if ts else None)
+        abi.mx_loop_run(self.handle, n, ts, ws, stream)

@@ -34,6 +34,51 @@ struct mx_expr {
 };
 
 namespace mx {
+
+// hipRTC: source -> code object for the current device -> module, cached per
+// (device, source) for the life of the process.
+mx_status rtc_module(const std::string &src, const char *name, hipModule_t *out) {
+    static std::mutex mu;
+    static std::unordered_map<std::string, hipModule_t> cache;
+    int dev = 0;
+    MX_TRY_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    MX_TRY_HIP(hipGetDeviceProperties(&prop, dev));
+    const std::string key = std::to_string(dev) + "\n" + src;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return MX_OK;
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), name, 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return set_error(MX_ERR_HIP, "hiprtcCreateProgram failed");
+    const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+    // no packed FP32 instructions in generated code either
+    const char *opts[] = {arch.c_str(), "-O3", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return set_error(MX_ERR_HIP, "hipRTC failed to compile %s: %s", name, log.c_str());
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    hipModule_t mod = nullptr;
+    MX_TRY_HIP(hipModuleLoadData(&mod, code.data()));
+    cache.emplace(key, mod);
+    *out = mod;
+    return MX_OK;
+}
+
 namespace {
 
 constexpr int kRegs = 16, kMaxInsn = 64, kMaxIn = 4;
@@ -467,8 +512,6 @@ std::unordered_map<std::string, std::unique_ptr<Compiled>> g_cache;  // key: dev
 mx_status compile(const mx_expr &e, const Compiled **out) {
     int dev = 0;
     MX_TRY_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    MX_TRY_HIP(hipGetDeviceProperties(&prop, dev));
     const std::string key = std::to_string(dev) + "\n" + e.src;
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);
@@ -476,29 +519,10 @@ mx_status compile(const mx_expr &e, const Compiled **out) {
         *out = it->second.get();
         return MX_OK;
     }
-    hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, e.src.c_str(), "mx_expr.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
-        return set_error(MX_ERR_HIP, "hiprtcCreateProgram failed");
-    const std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
-    // no packed FP32 instructions in generated code either
-    const char *opts[] = {arch.c_str(), "-O3", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
-                          "-packed-fp32-ops"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
-    if (rc != HIPRTC_SUCCESS) {
-        size_t ls = 0;
-        hiprtcGetProgramLogSize(prog, &ls);
-        std::string log(ls, '\0');
-        if (ls) hiprtcGetProgramLog(prog, &log[0]);
-        hiprtcDestroyProgram(&prog);
-        return set_error(MX_ERR_HIP, "hipRTC failed to compile a map body: %s", log.c_str());
-    }
-    size_t cs = 0;
-    hiprtcGetCodeSize(prog, &cs);
-    std::vector<char> code(cs);
-    hiprtcGetCode(prog, code.data());
-    hiprtcDestroyProgram(&prog);
+    hipModule_t mod = nullptr;
+    if (mx_status st = rtc_module(e.src, "mx_expr.hip", &mod)) return st;
     auto c = std::make_unique<Compiled>();
-    MX_TRY_HIP(hipModuleLoadData(&c->mod, code.data()));
+    c->mod = mod;
     MX_TRY_HIP(hipModuleGetFunction(&c->map, c->mod, "mx_xmap"));
     MX_TRY_HIP(hipModuleGetFunction(&c->vjp, c->mod, "mx_xvjp"));
     MX_TRY_HIP(hipModuleGetFunction(&c->scatter, c->mod, "mx_xscatter"));

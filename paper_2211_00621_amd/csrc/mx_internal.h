@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <string>
 #include <type_traits>
 
 #include "mx.h"
@@ -47,6 +48,9 @@ mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, voi
                              hipStream_t s);
 // bytes of the bucketed histogram's workspace (0: the call takes none)
 size_t histogram_ws_bytes(int64_t n, int64_t nbins);
+// hipRTC: compiles HIP source for the current device and loads it; modules
+// are cached per (device, source) for the life of the process
+mx_status rtc_module(const std::string &src, const char *name, hipModule_t *out);
 
 constexpr int kWave = 64;
 
