@@ -659,6 +659,12 @@ def mx_loop_create(prog, types, float_dtype: int) -> Loop:
     return Loop(h.value, types)
 
 
+def mx_loop_destroy(lp: Loop) -> None:
+    if lp.handle:
+        _check(_L().mx_loop_destroy(lp.handle), "mx_loop_destroy")
+        lp.handle = None
+
+
 def _ltensors(tensors):
     arr = (LTensor * max(1, len(tensors)))()
     for i, t in enumerate(tensors):
