@@ -179,6 +179,57 @@ mx_status mx_records_to_fields(const void *aos_dev, int64_t n, int nfields, size
 mx_status mx_fields_to_records(const void *const *soa_fields_host, int64_t n, int nfields,
                                size_t field_bytes, void *aos_dev, hipStream_t stream);
 
+/* Sequences of records whose fields are scalars or sequences (the record
+ * types {l_1 : T_1, ..., l_f : T_f} of Appendix A allow T_i = [T]; Section
+ * 4.3 marshals accelerated bindings by their types).  The host records are
+ * nrec structs of rec_bytes each; field f sits at byte offset fields[f].offset
+ * of a record: a scalar of elem_bytes, or an mx_hseq (pointer and length of
+ * the record's sequence).  Field-wise device layout: a scalar field is one
+ * array of nrec values (values_dev); a sequence field is the concatenation of
+ * every record's sequence in record order (values_dev), their lengths
+ * (lengths_dev, int64[nrec]) and offsets (offsets_dev, int64[nrec + 1], the
+ * exclusive scan of the lengths, computed on the device). */
+typedef struct {
+    const void *data;  /* host: len elements of the field's elem_bytes */
+    int64_t len;
+} mx_hseq;
+typedef enum { MX_FIELD_SCALAR = 0, MX_FIELD_SEQ = 1 } mx_field_kind;
+typedef struct {
+    int32_t kind;          /* mx_field_kind */
+    int32_t elem_bytes;    /* 1, 2, 4 or 8 */
+    int64_t offset;        /* byte offset of the field in a host record */
+    void *values_dev;      /* device: nrec values, or the sum of the lengths */
+    int64_t *lengths_dev;  /* sequence fields: device int64[nrec]; else NULL */
+    int64_t *offsets_dev;  /* sequence fields: device int64[nrec + 1]; else NULL */
+} mx_field;
+
+/* For every field its element count (nrec for a scalar field, the sum of the
+ * records' lengths for a sequence field) into counts_host[f], and the bytes of
+ * pinned host staging that mx_marshal_records and mx_unmarshal_records need.
+ * Errors: MX_ERR_INVALID (bad field description, null sequence data with a
+ * positive length), MX_ERR_SHAPE (negative length). */
+mx_status mx_records_layout(const void *recs_host, int64_t nrec, size_t rec_bytes, const mx_field *fields,
+                            int nfields, int64_t *counts_host, size_t *staging_bytes_host);
+
+/* Marshals the records field by field: host threads gather every field into
+ * the pinned staging buffer, one host-to-device copy per field (and per
+ * sequence field one for its lengths), then the offsets of each sequence field
+ * by the device scan (mx_lengths_to_offsets; workspace kind MX_WS_SCAN with
+ * n = nrec, reused field after field).  Waits for earlier work on the stream
+ * before it refills the staging buffer, which must then stay untouched until
+ * the stream has passed this call.  1 <= nfields <= 16. */
+mx_status mx_marshal_records(const void *recs_host, int64_t nrec, size_t rec_bytes, const mx_field *fields,
+                             int nfields, void *staging_host, size_t staging_bytes, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* The inverse: copies every field back and writes the host records -- scalar
+ * fields into the records, sequence fields into the host memory each record's
+ * mx_hseq points to, whose len must equal the device length of that record's
+ * sequence (MX_ERR_SHAPE otherwise; checked before any record is written).
+ * Synchronous.  Staging: the bytes mx_records_layout gives for the records. */
+mx_status mx_unmarshal_records(const mx_field *fields, int nfields, int64_t nrec, void *recs_host, size_t rec_bytes,
+                               void *staging_host, size_t staging_bytes, hipStream_t stream);
+
 /* `map flatten` over a depth-3 ragged sequence [[[T]]] given by outer offsets
  * (nouter+1 entries, counting middle rows) and inner offsets (counting values):
  * the flattened inner rows of outer element i span values

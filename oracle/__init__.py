@@ -250,6 +250,45 @@ def unmarshal_records(soa, fields):
     return [{f: soa[f][i].item() for f in fields} for i in range(n)]
 
 
+def marshal_record_seqs(records, schema):
+    """A sequence of records whose fields are scalars or sequences (Appendix
+    A: record types {l_i : T_i} with T_i possibly [T]; Section 4.3) -> one
+    flat layout per field: a scalar field becomes one array of len(records)
+    values; a sequence field becomes (values, offsets), its values the
+    records' sequences concatenated in record order and offsets[r] ..
+    offsets[r + 1] delimiting record r's.  schema: (name, "scalar" | "seq",
+    numpy dtype) triples.  Pure Python loops, for small cases."""
+    out = {}
+    for name, kind, dt in schema:
+        if kind == "scalar":
+            out[name] = np.array([rec[name] for rec in records], dtype=dt)
+            continue
+        values, offsets = [], [0]
+        for rec in records:
+            for x in rec[name]:
+                values.append(x)
+            offsets.append(len(values))
+        out[name] = (np.array(values, dtype=dt), np.array(offsets, dtype=np.int64))
+    return out
+
+
+def unmarshal_record_seqs(layout, schema):
+    """Inverse of marshal_record_seqs: a list of dicts, sequence fields as lists."""
+    n = None
+    for name, kind, _ in schema:
+        m = len(layout[name]) if kind == "scalar" else len(layout[name][1]) - 1
+        n = m if n is None else n
+    recs = [dict() for _ in range(n or 0)]
+    for name, kind, _ in schema:
+        for r in range(n or 0):
+            if kind == "scalar":
+                recs[r][name] = layout[name][r].item()
+            else:
+                vals, off = layout[name]
+                recs[r][name] = [v.item() for v in vals[off[r]:off[r + 1]]]
+    return recs
+
+
 def flatten(values, offsets_levels):
     """flatten [[T]] -> [T] on a marshalled value: drop the outermost offsets.
 

@@ -93,6 +93,9 @@ SIGNATURES = {
     "mx_expr_loop_workspace_bytes": (c_size, [c_i64]),
     "mx_expr_loop_scatter": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_i64, c_p, c_size, c_p]),
     "mx_expr_vjp": (c_status, [c_p, c_pp, c_i64, c_p, c_p, c_pp, c_p]),
+    "mx_records_layout": (c_status, [c_p, c_i64, c_size, c_p, c_int, c_p, c_p]),
+    "mx_marshal_records": (c_status, [c_p, c_i64, c_size, c_p, c_int, c_p, c_size, c_p, c_size, c_p]),
+    "mx_unmarshal_records": (c_status, [c_p, c_int, c_i64, c_p, c_size, c_p, c_size, c_p]),
     "mx_loop_create": (c_status, [c_p, c_int, c_p, c_int, c_enum, c_pp]),
     "mx_loop_destroy": (c_status, [c_p]),
     "mx_loop_prepare": (c_status, [c_p]),

@@ -694,3 +694,46 @@ def mx_loop_run(lp: Loop, n: int, tensors, ws=None, stream=None) -> None:
             raise MxError(MX_ERR_SHAPE, "mx_loop_run: tensor rank or dtype differs from the loop's")
     _check(_L().mx_loop_run(lp.handle, int(n), _ltensors(tensors), _dptr(ws), _nbytes(ws), _stream(stream)),
            "mx_loop_run")
+
+
+# ---------------------------------------------------------------- records whose fields are sequences
+MX_FIELD_SCALAR, MX_FIELD_SEQ = 0, 1
+
+
+class HSeq(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("len", ctypes.c_int64)]
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("elem_bytes", ctypes.c_int32), ("offset", ctypes.c_int64),
+                ("values_dev", ctypes.c_void_p), ("lengths_dev", ctypes.c_void_p), ("offsets_dev", ctypes.c_void_p)]
+
+
+def _fields(desc):
+    """desc: (kind, elem_bytes, offset, values, lengths, offsets) with device tensors or None."""
+    arr = (Field * max(1, len(desc)))()
+    for i, (kind, eb, off, vals, lens, offs) in enumerate(desc):
+        arr[i] = Field(int(kind), int(eb), int(off), _dptr(vals), _dptr(lens), _dptr(offs))
+    return arr
+
+
+def mx_records_layout(recs: np.ndarray, desc):
+    """(element counts per field, staging bytes) for host records `recs` (a numpy structured array)."""
+    counts = np.zeros(max(1, len(desc)), dtype=np.int64)
+    staging = ctypes.c_size_t()
+    _check(_L().mx_records_layout(recs.ctypes.data if recs.size else None, recs.size, recs.dtype.itemsize,
+                                  _fields(desc), len(desc), counts.ctypes.data, ctypes.byref(staging)),
+           "mx_records_layout")
+    return counts[:len(desc)], staging.value
+
+
+def mx_marshal_records(recs: np.ndarray, desc, staging, ws, stream=None) -> None:
+    _check(_L().mx_marshal_records(recs.ctypes.data if recs.size else None, recs.size, recs.dtype.itemsize,
+                                   _fields(desc), len(desc), staging.data_ptr() if staging is not None else None,
+                                   _nbytes(staging), _dptr(ws), _nbytes(ws), _stream(stream)), "mx_marshal_records")
+
+
+def mx_unmarshal_records(desc, recs: np.ndarray, staging, stream=None) -> None:
+    _check(_L().mx_unmarshal_records(_fields(desc), len(desc), recs.size, recs.ctypes.data if recs.size else None,
+                                     recs.dtype.itemsize, staging.data_ptr() if staging is not None else None,
+                                     _nbytes(staging), _stream(stream)), "mx_unmarshal_records")

@@ -256,6 +256,100 @@ def to_tensor(nd: Nested) -> torch.Tensor:
     return nd.values.view(*shape)
 
 
+@dataclass
+class RecordSeqs:
+    """A marshalled sequence of records whose fields are scalars or sequences:
+    scalar fields as one device tensor each, sequence fields as Ragged."""
+    fields: dict
+    nrec: int
+    schema: list
+
+
+def _record_dtype(schema):
+    """C layout of a host record: scalar fields in their dtype, sequence fields
+    as the C ABI's mx_hseq (data pointer, int64 length)."""
+    hseq = np.dtype([("data", np.uint64), ("len", np.int64)], align=True)
+    return np.dtype({"names": [n for n, _, _ in schema],
+                     "formats": [np.dtype(dt) if kind == "scalar" else hseq for _, kind, dt in schema]}, align=True)
+
+
+def _field_desc(schema, rdt, tensors=None):
+    desc = []
+    for name, kind, dt in schema:
+        k = abi.MX_FIELD_SCALAR if kind == "scalar" else abi.MX_FIELD_SEQ
+        vals, lens, offs = tensors[name] if tensors else (None, None, None)
+        desc.append((k, np.dtype(dt).itemsize, rdt.fields[name][1], vals, lens, offs))
+    return desc
+
+
+def marshal_record_seqs(records, schema, device="cuda") -> RecordSeqs:
+    """Marshal a list of dict records through the C ABI (mx_marshal_records).
+    schema: (name, "scalar" | "seq", numpy dtype) triples."""
+    rdt = _record_dtype(schema)
+    n = len(records)
+    recs = np.zeros(n, dtype=rdt)
+    keep = []
+    for name, kind, dt in schema:
+        if kind == "scalar":
+            recs[name] = np.array([r[name] for r in records], dtype=dt) if n else np.zeros(0, dt)
+            continue
+        for i, r in enumerate(records):
+            a = np.ascontiguousarray(np.asarray(r[name], dtype=dt))
+            keep.append(a)
+            recs[name]["data"][i] = a.ctypes.data if a.size else 0
+            recs[name]["len"][i] = a.size
+    counts, staging_bytes = abi.mx_records_layout(recs, _field_desc(schema, rdt))
+    tensors, out = {}, {}
+    for (name, kind, dt), cnt in zip(schema, counts):
+        tdt = torch.from_numpy(np.zeros(0, dt)).dtype
+        vals = torch.empty(int(cnt), dtype=tdt, device=device)
+        if kind == "scalar":
+            tensors[name] = (vals, None, None)
+            out[name] = vals
+        else:
+            lens = torch.empty(n, dtype=torch.int64, device=device)
+            offs = torch.empty(n + 1, dtype=torch.int64, device=device)
+            tensors[name] = (vals, lens, offs)
+            out[name] = Ragged(vals, offs)
+    staging = torch.empty(max(staging_bytes, 256), dtype=torch.uint8, pin_memory=True)
+    abi.mx_marshal_records(recs, _field_desc(schema, rdt, tensors), staging,
+                           workspace(MX_WS_SCAN, n, device=device))
+    torch.cuda.current_stream().synchronize()  # staging and the host sequences are local to this call
+    del keep
+    return RecordSeqs(out, n, list(schema))
+
+
+def unmarshal_record_seqs(rs: RecordSeqs):
+    """Back to a list of dict records (mx_unmarshal_records): scalar fields as
+    Python scalars, sequence fields as numpy arrays."""
+    rdt = _record_dtype(rs.schema)
+    n = rs.nrec
+    recs = np.zeros(n, dtype=rdt)
+    tensors, seqs = {}, {}
+    for name, kind, dt in rs.schema:
+        f = rs.fields[name]
+        if kind == "scalar":
+            tensors[name] = (f, None, None)
+            continue
+        off = f.offsets.cpu().numpy()
+        arrs = [np.empty(int(off[i + 1] - off[i]), dtype=dt) for i in range(n)]
+        seqs[name] = arrs
+        for i, a in enumerate(arrs):
+            recs[name]["data"][i] = a.ctypes.data if a.size else 0
+            recs[name]["len"][i] = a.size
+        tensors[name] = (f.values, None, f.offsets)
+    _, staging_bytes = abi.mx_records_layout(recs, _field_desc(rs.schema, rdt))
+    staging = torch.empty(max(staging_bytes, 256), dtype=torch.uint8, pin_memory=True)
+    abi.mx_unmarshal_records(_field_desc(rs.schema, rdt, tensors), recs, staging)
+    out = []
+    for i in range(n):
+        rec = {}
+        for name, kind, _ in rs.schema:
+            rec[name] = recs[name][i].item() if kind == "scalar" else seqs[name][i]
+        out.append(rec)
+    return out
+
+
 def records_to_fields(aos: torch.Tensor):
     fields = [torch.empty(aos.shape[0], dtype=aos.dtype, device=aos.device) for _ in range(aos.shape[1])]
     abi.mx_records_to_fields(aos.contiguous(), fields)

@@ -129,6 +129,77 @@ void gather_rows(const void *const *rows, const int64_t *lengths, const int64_t 
     for (auto &x : th) x.join();
 }
 
+// Field-wise layout of records whose fields are scalars or sequences: where
+// each field's values (and a sequence field's lengths / offsets) sit in the
+// staging buffer.
+struct FieldPlan {
+    int64_t count = 0;   // values of the field
+    size_t vpos = 0, vbytes = 0, lpos = 0;
+};
+
+mx_hseq seq_at(const void *recs, size_t rec_bytes, int64_t r, int64_t offset) {
+    mx_hseq h;
+    std::memcpy(&h, (const char *)recs + (size_t)r * rec_bytes + (size_t)offset, sizeof h);
+    return h;
+}
+
+mx_status plan_records(const char *who, const void *recs, int64_t nrec, size_t rec_bytes, const mx_field *fields,
+                       int nf, std::vector<FieldPlan> &plan, size_t *staging) {
+    MX_REQUIRE(nrec >= 0, MX_ERR_SHAPE, "%s: nrec < 0", who);
+    MX_REQUIRE(fields && nf >= 1 && nf <= kMaxFields, MX_ERR_INVALID, "%s: 1..%d fields", who, kMaxFields);
+    MX_REQUIRE(nrec == 0 || (recs && rec_bytes > 0), MX_ERR_INVALID, "%s: null records", who);
+    plan.assign((size_t)nf, FieldPlan{});
+    size_t pos = 0;
+    for (int f = 0; f < nf; ++f) {
+        const mx_field &fd = fields[f];
+        const int eb = fd.elem_bytes;
+        MX_REQUIRE(fd.kind == MX_FIELD_SCALAR || fd.kind == MX_FIELD_SEQ, MX_ERR_INVALID, "%s: field %d: bad kind", who, f);
+        MX_REQUIRE(eb == 1 || eb == 2 || eb == 4 || eb == 8, MX_ERR_INVALID, "%s: field %d: elem_bytes 1, 2, 4 or 8",
+                   who, f);
+        const size_t width = fd.kind == MX_FIELD_SCALAR ? (size_t)eb : sizeof(mx_hseq);
+        MX_REQUIRE(fd.offset >= 0 && (size_t)fd.offset + width <= rec_bytes, MX_ERR_INVALID,
+                   "%s: field %d lies outside the record", who, f);
+        FieldPlan &p = plan[(size_t)f];
+        if (fd.kind == MX_FIELD_SCALAR) {
+            p.count = nrec;
+        } else {
+            for (int64_t r = 0; r < nrec; ++r) {
+                const mx_hseq h = seq_at(recs, rec_bytes, r, fd.offset);
+                MX_REQUIRE(h.len >= 0, MX_ERR_SHAPE, "%s: field %d, record %lld: negative length", who, f, (long long)r);
+                MX_REQUIRE(h.len == 0 || h.data, MX_ERR_INVALID, "%s: field %d, record %lld: null data", who, f,
+                           (long long)r);
+                p.count += h.len;
+            }
+        }
+        p.vpos = pos;
+        p.vbytes = (size_t)p.count * (size_t)eb;
+        pos += align256(p.vbytes);
+        if (fd.kind == MX_FIELD_SEQ) {
+            p.lpos = pos;
+            pos += align256((size_t)(nrec + 1) * 8);
+        }
+    }
+    *staging = pos;
+    return MX_OK;
+}
+
+// Runs fn(r0, r1) over record ranges on up to 16 host threads (one when the
+// work is small).
+template <class Fn> void parallel_records(int64_t nrec, int64_t bytes, Fn fn) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int nth = (int)std::min<int64_t>(std::max(1u, std::min(hw, 16u)), std::max<int64_t>(1, bytes / (4 << 20)));
+    if (nth <= 1 || nrec < 2) {
+        fn((int64_t)0, nrec);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) {
+        const int64_t r0 = nrec * t / nth, r1 = nrec * (t + 1) / nth;
+        if (r1 > r0) th.emplace_back(fn, r0, r1);
+    }
+    for (auto &x : th) x.join();
+}
+
 }  // namespace
 }  // namespace mx
 
@@ -277,6 +348,124 @@ mx_status mx_fields_to_records(const void *const *soa_fields_host, int64_t n, in
         hipLaunchKernelGGL(k_soa_to_aos<uint64_t>, dim3(grid), dim3(NT), 0, stream, fp, n, nfields,
                            (uint64_t *)aos_dev);
     return last_launch("mx_fields_to_records");
+}
+
+
+mx_status mx_records_layout(const void *recs_host, int64_t nrec, size_t rec_bytes, const mx_field *fields,
+                            int nfields, int64_t *counts_host, size_t *staging_bytes_host) {
+    std::vector<FieldPlan> plan;
+    size_t staging = 0;
+    if (mx_status st = plan_records("mx_records_layout", recs_host, nrec, rec_bytes, fields, nfields, plan, &staging))
+        return st;
+    if (counts_host)
+        for (int f = 0; f < nfields; ++f) counts_host[f] = plan[(size_t)f].count;
+    if (staging_bytes_host) *staging_bytes_host = staging;
+    return MX_OK;
+}
+
+mx_status mx_marshal_records(const void *recs_host, int64_t nrec, size_t rec_bytes, const mx_field *fields,
+                             int nfields, void *staging_host, size_t staging_bytes, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
+    const char *who = "mx_marshal_records";
+    std::vector<FieldPlan> plan;
+    size_t need = 0;
+    if (mx_status st = plan_records(who, recs_host, nrec, rec_bytes, fields, nfields, plan, &need)) return st;
+    MX_REQUIRE(staging_host || need == 0, MX_ERR_INVALID, "%s: null staging", who);
+    MX_REQUIRE(staging_bytes >= need, MX_ERR_INVALID, "%s: staging needs %zu bytes", who, need);
+    for (int f = 0; f < nfields; ++f) {
+        const mx_field &fd = fields[f];
+        MX_REQUIRE(plan[(size_t)f].count == 0 || fd.values_dev, MX_ERR_INVALID, "%s: field %d: null values", who, f);
+        if (fd.kind == MX_FIELD_SEQ)
+            MX_REQUIRE(fd.offsets_dev && (nrec == 0 || fd.lengths_dev), MX_ERR_INVALID,
+                       "%s: field %d: null lengths or offsets", who, f);
+    }
+    // the previous use of the staging buffer on this stream must be finished
+    MX_TRY_HIP(hipStreamSynchronize(stream));
+    char *st = (char *)staging_host;
+    const char *recs = (const char *)recs_host;
+    for (int f = 0; f < nfields; ++f) {
+        const mx_field &fd = fields[f];
+        const FieldPlan &p = plan[(size_t)f];
+        const size_t eb = (size_t)fd.elem_bytes;
+        if (fd.kind == MX_FIELD_SCALAR) {
+            parallel_records(nrec, (int64_t)p.vbytes, [&](int64_t r0, int64_t r1) {
+                for (int64_t r = r0; r < r1; ++r)
+                    std::memcpy(st + p.vpos + (size_t)r * eb, recs + (size_t)r * rec_bytes + (size_t)fd.offset, eb);
+            });
+        } else {
+            std::vector<const void *> rows((size_t)nrec);
+            std::vector<int64_t> lens((size_t)nrec), starts((size_t)nrec + 1, 0);
+            for (int64_t r = 0; r < nrec; ++r) {
+                const mx_hseq h = seq_at(recs_host, rec_bytes, r, fd.offset);
+                rows[(size_t)r] = h.data;
+                lens[(size_t)r] = h.len;
+                starts[(size_t)r + 1] = starts[(size_t)r] + h.len;
+            }
+            gather_rows(rows.data(), lens.data(), starts.data(), nrec, eb, st + p.vpos, p.count);
+            if (nrec) std::memcpy(st + p.lpos, lens.data(), (size_t)nrec * 8);
+        }
+        if (p.vbytes) MX_TRY_HIP(hipMemcpyAsync(fd.values_dev, st + p.vpos, p.vbytes, hipMemcpyHostToDevice, stream));
+        if (fd.kind == MX_FIELD_SEQ) {
+            if (nrec)
+                MX_TRY_HIP(hipMemcpyAsync(fd.lengths_dev, st + p.lpos, (size_t)nrec * 8, hipMemcpyHostToDevice, stream));
+            if (mx_status s2 = lengths_to_offsets(fd.lengths_dev, nrec, fd.offsets_dev, ws, ws_bytes, stream)) return s2;
+        }
+    }
+    return MX_OK;
+}
+
+mx_status mx_unmarshal_records(const mx_field *fields, int nfields, int64_t nrec, void *recs_host, size_t rec_bytes,
+                               void *staging_host, size_t staging_bytes, hipStream_t stream) {
+    const char *who = "mx_unmarshal_records";
+    std::vector<FieldPlan> plan;
+    size_t need = 0;
+    if (mx_status st = plan_records(who, recs_host, nrec, rec_bytes, fields, nfields, plan, &need)) return st;
+    MX_REQUIRE(staging_host || need == 0, MX_ERR_INVALID, "%s: null staging", who);
+    MX_REQUIRE(staging_bytes >= need, MX_ERR_INVALID, "%s: staging needs %zu bytes", who, need);
+    char *st = (char *)staging_host;
+    for (int f = 0; f < nfields; ++f) {
+        const mx_field &fd = fields[f];
+        const FieldPlan &p = plan[(size_t)f];
+        MX_REQUIRE(p.count == 0 || fd.values_dev, MX_ERR_INVALID, "%s: field %d: null values", who, f);
+        if (p.vbytes) MX_TRY_HIP(hipMemcpyAsync(st + p.vpos, fd.values_dev, p.vbytes, hipMemcpyDeviceToHost, stream));
+        if (fd.kind == MX_FIELD_SEQ) {
+            MX_REQUIRE(fd.offsets_dev, MX_ERR_INVALID, "%s: field %d: null offsets", who, f);
+            MX_TRY_HIP(hipMemcpyAsync(st + p.lpos, fd.offsets_dev, (size_t)(nrec + 1) * 8, hipMemcpyDeviceToHost,
+                                      stream));
+        }
+    }
+    MX_TRY_HIP(hipStreamSynchronize(stream));
+    char *recs = (char *)recs_host;
+    // every sequence's device length against the host record's, before any write
+    for (int f = 0; f < nfields; ++f) {
+        if (fields[f].kind != MX_FIELD_SEQ) continue;
+        const int64_t *off = (const int64_t *)(st + plan[(size_t)f].lpos);
+        MX_REQUIRE(off[0] == 0, MX_ERR_SHAPE, "%s: field %d: offsets[0] != 0", who, f);
+        for (int64_t r = 0; r < nrec; ++r)
+            MX_REQUIRE(off[r + 1] - off[r] == seq_at(recs_host, rec_bytes, r, fields[f].offset).len, MX_ERR_SHAPE,
+                       "%s: field %d, record %lld: the host sequence's length differs from the device's", who, f,
+                       (long long)r);
+    }
+    for (int f = 0; f < nfields; ++f) {
+        const mx_field &fd = fields[f];
+        const FieldPlan &p = plan[(size_t)f];
+        const size_t eb = (size_t)fd.elem_bytes;
+        if (fd.kind == MX_FIELD_SCALAR) {
+            parallel_records(nrec, (int64_t)p.vbytes, [&](int64_t r0, int64_t r1) {
+                for (int64_t r = r0; r < r1; ++r)
+                    std::memcpy(recs + (size_t)r * rec_bytes + (size_t)fd.offset, st + p.vpos + (size_t)r * eb, eb);
+            });
+        } else {
+            const int64_t *off = (const int64_t *)(st + p.lpos);
+            parallel_records(nrec, (int64_t)p.vbytes, [&](int64_t r0, int64_t r1) {
+                for (int64_t r = r0; r < r1; ++r) {
+                    const mx_hseq h = seq_at(recs_host, rec_bytes, r, fd.offset);
+                    if (h.len > 0) std::memcpy((void *)h.data, st + p.vpos + (size_t)off[r] * eb, (size_t)h.len * eb);
+                }
+            });
+        }
+    }
+    return MX_OK;
 }
 
 }  // extern "C"

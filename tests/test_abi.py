@@ -108,3 +108,26 @@ def test_parboil_argument_errors_before_any_device_work(lib):
     assert lib.mx_tpacf_f32(fake, fake, fake, -1, fake, fake, fake, 4, 0, fake, 20, fake, None) == abi.MX_ERR_SHAPE
     assert lib.mx_tpacf_f32(fake, fake, fake, 4, fake, fake, fake, 4, 0, fake, 20, None, None) == abi.MX_ERR_INVALID
     assert "mx_tpacf_f32" in lib.mx_last_error().decode()
+
+
+def test_records_layout_on_the_host():
+    """mx_records_layout reads host records only: element counts and staging size."""
+    import numpy as np
+    from paper_2211_00621_amd import abi, api
+    schema = [("id", "scalar", np.int64), ("xs", "seq", np.float32), ("k", "scalar", np.int16)]
+    rdt = api._record_dtype(schema)
+    recs = np.zeros(3, dtype=rdt)
+    data = [np.zeros(m, np.float32) for m in (2, 0, 5)]
+    for i, a in enumerate(data):
+        recs["xs"]["data"][i] = a.ctypes.data if a.size else 0
+        recs["xs"]["len"][i] = a.size
+    desc = api._field_desc(schema, rdt)
+    counts, nbytes = abi.mx_records_layout(recs, desc)
+    assert counts.tolist() == [3, 7, 3]
+    assert nbytes == 256 + 256 + 256 + 256   # id values, xs values, xs offsets, k values (each 256-aligned)
+    recs["xs"]["len"][1] = -1
+    with pytest.raises(abi.MxError):
+        abi.mx_records_layout(recs, desc)
+    recs["xs"]["len"][1] = 4                 # a positive length with null data
+    with pytest.raises(abi.MxError):
+        abi.mx_records_layout(recs, desc)

@@ -281,6 +281,46 @@ def test_marshal_rows_and_records():
     assert O.unmarshal_records(soa, ["x", "y", "m"]) == recs
 
 
+RECORD_SCHEMA = [("id", "scalar", np.int64), ("xs", "seq", np.float32), ("w", "scalar", np.float64),
+                 ("tags", "seq", np.int32), ("k", "scalar", np.int16)]
+
+
+def _records(n, seed):
+    rng = np.random.default_rng(seed)
+    recs = []
+    for r in range(n):
+        lx, lt = int(rng.integers(0, 7)), int(rng.integers(0, 4))
+        recs.append({"id": int(rng.integers(-2 ** 40, 2 ** 40)), "xs": rng.uniform(-1, 1, lx).astype(np.float32).tolist(),
+                     "w": float(rng.normal()), "tags": rng.integers(-100, 100, lt).tolist(),
+                     "k": int(rng.integers(-300, 300))})
+    return recs
+
+
+def test_marshal_record_seqs_fieldwise_layout():
+    recs = _records(40, 3)
+    lay = O.marshal_record_seqs(recs, RECORD_SCHEMA)
+    # scalar fields: the column in record order (numpy's own array of the column)
+    assert np.array_equal(lay["id"], np.array([r["id"] for r in recs]))
+    assert lay["k"].dtype == np.int16 and lay["k"].tolist() == [r["k"] for r in recs]
+    for name in ("xs", "tags"):
+        vals, off = lay[name]
+        # offsets: the running sum of the sequence lengths (numpy cumsum); values: numpy concatenate
+        assert np.array_equal(off, np.concatenate([[0], np.cumsum([len(r[name]) for r in recs])]))
+        parts = [np.asarray(r[name]) for r in recs]
+        assert np.array_equal(vals, np.concatenate(parts).astype(vals.dtype))
+    assert O.unmarshal_record_seqs(lay, RECORD_SCHEMA) == [
+        {k: (v if not isinstance(v, list) else [type(x)(x) for x in v]) for k, v in r.items()} for r in recs]
+
+
+def test_marshal_record_seqs_empty_cases():
+    lay = O.marshal_record_seqs([], RECORD_SCHEMA)
+    assert lay["id"].size == 0 and lay["xs"][1].tolist() == [0]
+    recs = [{"id": 1, "xs": [], "w": 0.5, "tags": [], "k": 0}] * 3
+    lay = O.marshal_record_seqs(recs, RECORD_SCHEMA)
+    assert lay["xs"][1].tolist() == [0, 0, 0, 0] and lay["tags"][0].size == 0
+    assert O.unmarshal_record_seqs(lay, RECORD_SCHEMA) == recs
+
+
 def test_ragged_lengths_distribution():
     L = W.ragged_lengths(65536, seed=0)
     assert L.min() >= 1 and L.max() <= 4096
