@@ -205,6 +205,7 @@ __global__ void __launch_bounds__(NT) k_adjoint_seed(const float4 *__restrict__ 
 constexpr int64_t kTargetBlocks = 2048;
 
 int slices_for(int64_t n) {
+    if (n <= 0) return 1;  // no bodies: one (empty) slice
     const int64_t tiles = ceil_div(n, NT);
     int64_t s = ceil_div(kTargetBlocks, tiles > 0 ? tiles : 1);
     if (s > tiles) s = tiles;

@@ -240,8 +240,11 @@ def test_config_16384_steps_vs_oracle_sampled():
         x_next, v_next = host(states[t + 1][0]), host(states[t + 1][1])
         ref_x, ref_v = O.nbody_step(x_t[:, :3], v_t[:, :3], x_t[:, 3], EPS2, G, DT)
         assert np.array_equal(x_next[:, 3], m), t
-        # x' = x + dt v: one FMA or two roundings of binary32
-        assert np.allclose(x_next[SAMPLE, :3], ref_x[SAMPLE], rtol=2e-7, atol=1e-9), f"x_{t + 1}"
+        # x' = x + dt v: one FMA or two roundings of binary32 (and dt itself
+        # rounded to binary32), so within 2^-22 of the operands' magnitudes
+        xs, vs = x_t[SAMPLE, :3].astype(np.float64), v_t[SAMPLE, :3].astype(np.float64)
+        assert np.all(np.abs(x_next[SAMPLE, :3] - ref_x[SAMPLE]) <= 2.0 ** -22 * (np.abs(xs) + DT * np.abs(vs))), \
+            f"x_{t + 1}"
         S = DT * accel_magnitude(x_t[:, :3], x_t[:, 3], EPS2, rows=SAMPLE) + np.abs(v_t[SAMPLE, :3])
         check_bodies(v_next[SAMPLE, :3], ref_v[SAMPLE], S, n, what=f"v_{t + 1}")
     # reverse sweep: vbar_T = m v_T (binary32 products, as the library forms them), xbar_T = 0
@@ -261,7 +264,10 @@ def test_config_16384_steps_vs_oracle_sampled():
             vb_ref = vb_in.astype(np.float64) + DT * xb_in.astype(np.float64)
             S = DT * vjp_magnitude(x_t[:, :3], x_t[:, 3], vb_in, EPS2, rows=SAMPLE) + np.abs(xb_in[SAMPLE])
             check_bodies(host(xbo)[SAMPLE, :3], xb_ref[SAMPLE], S, n, what=f"xbar_{t}")
-            assert np.allclose(host(vbo)[SAMPLE, :3], vb_ref[SAMPLE], rtol=2e-7, atol=1e-9), f"vbar_{t}"
+            # vbar_t = vbar_{t+1} + dt xbar_{t+1}: the same two-operand bound;
+            # the terms can cancel, so it is relative to the operands, not the sum
+            bnd = 2.0 ** -22 * (np.abs(vb_in[SAMPLE]).astype(np.float64) + DT * np.abs(xb_in[SAMPLE]))
+            assert np.all(np.abs(host(vbo)[SAMPLE, :3] - vb_ref[SAMPLE]) <= bnd), f"vbar_{t}"
         xb, vb = xbo, vbo
     ke, gx, gv = api.nbody_ke_grad(p4, vv, EPS2, G, DT, T, K)
     assert host(gx).tobytes() == host(xb).tobytes() and host(gv).tobytes() == host(vb).tobytes()
