@@ -14,10 +14,16 @@ element is one application of the innermost map2 / reduce body: one add per
 ragged value (forward), one write per value (reverse), one multiply-add per
 (i, j, k) of each of the three matrix products.
 
+The default line also carries `hbm` (the ragged half of the step alone, cold,
+against 8 TB/s and against the measured read-only ceiling) and `suite`: the
+fused dot, the N-body loop, k-means and the batched expressions, each with its
+plain comparison and the roofline of its dominant kernel (--no-suite skips
+them).
+
 Other workloads (--workload): dot (fused map2+reduce vs plain), nbody, kmeans,
 batched, expr (a user-defined map body, fused map+reduce and reverse mode vs
-the same body from the fixed operators), parboil (histogram, stencil, mri-q).  Prints one JSON line on stdout;
-progress goes to stderr.
+the same body from the fixed operators), parboil (histogram, stencil, mri-q).
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -118,6 +124,60 @@ def per_launch_ms(fn, reps=20, warmup=3):
     return timed_on(torch.cuda.current_stream(), fn, reps, warmup)
 
 
+def launch_stats(fn, reps=50, warmup=3, stream=None):
+    """Per-launch durations in ms: each of `reps` launches of fn between its
+    own pair of events on `stream` (the current stream by default).  Returns
+    the numpy array of durations."""
+    import torch
+    stream = torch.cuda.current_stream() if stream is None else stream
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def summary_us(t):
+    """mean / median / p10 / p90 of per-launch durations (ms in, us out)."""
+    t = np.asarray(t) * 1e3
+    return {"mean_us": round(float(t.mean()), 2), "median_us": round(float(np.median(t)), 2),
+            "p10_us": round(float(np.percentile(t, 10)), 2), "p90_us": round(float(np.percentile(t, 90)), 2),
+            "reps": int(t.size)}
+
+
+def rotating(copies, fn):
+    """A launcher that calls fn(copy) over `copies` in turn (more bytes than
+    the last-level cache holds, so each launch streams from HBM)."""
+    turn = [0]
+
+    def f():
+        turn[0] = (turn[0] + 1) % len(copies)
+        fn(copies[turn[0]])
+    return f
+
+
+def hbm_read_ceiling(dev, nbytes, reps=50):
+    """What the chip streams read-only: mx_stream_read (one contiguous 16 KB
+    chunk per block, 16-byte loads) over four rotating buffers of nbytes
+    (cold: 4 x nbytes exceeds the 256 MB last-level cache when nbytes is
+    ~129 MB).  Per-launch durations, events around each launch."""
+    import torch
+    from paper_2211_00621_amd import abi
+    n = nbytes // 16 * 4
+    bufs = [torch.full((n,), i + 1, dtype=torch.int32, device=dev) for i in range(4)]
+    x = torch.zeros(abi.MX_STREAM_READ_SLOTS, dtype=torch.int32, device=dev)
+    t = launch_stats(rotating(bufs, lambda b: abi.mx_stream_read(b, x)), reps=reps)
+    med = float(np.median(t))
+    del bufs
+    return {"kernel": "k_stream_read", "bytes": 4 * n, **summary_us(t), "GB/s": round(gbs(4 * n, med), 1),
+            "frac_hbm": round(gbs(4 * n, med) / HBM_PEAK_GBS, 4)}
+
+
 def capture(stream, fn):
     """fn() once eagerly on `stream`, then captured into a HIP graph."""
     import torch
@@ -133,7 +193,34 @@ def capture(stream, fn):
 
 
 def cpu_threads():
-    return 1  # the oracle is single-threaded
+    """Host threads for the oracle's parallel leg: the cores this process may
+    run on, at most OMP_NUM_THREADS when that is set (the GPU host's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def split_ranges(n, parts):
+    """`parts` contiguous [lo, hi) ranges covering range(n)."""
+    b = np.linspace(0, n, parts + 1).astype(np.int64)
+    return [(int(b[i]), int(b[i + 1])) for i in range(parts) if b[i + 1] > b[i]]
 
 
 # ============================================================ nested map(reduce)
@@ -169,14 +256,18 @@ def bench_nested(args):
     gA = torch.empty((M, K), dtype=torch.float32, device=dev)
     gB = torch.empty((K, N), dtype=torch.float32, device=dev)
     ws = api.workspace(abi.MX_WS_SCAN, nseg, device=dev)
+    wseg = api.workspace(abi.MX_WS_SEGMENTED, nval, device=dev)
     names = ["offsets", "row_sums", "mmr_fwd", "row_sums_adjoint", "mmr_adjoint_A", "mmr_adjoint_B"]
 
     def make_parts(plain):
-        seg = abi.mx_segmented_reduce_plain if plain else abi.mx_segmented_reduce
+        if plain:
+            seg = lambda: abi.mx_segmented_reduce_plain(abi.MX_ADD, d["tv"], offsets, 0.0, rows)  # noqa: E731
+        else:
+            seg = lambda: abi.mx_segmented_reduce(abi.MX_ADD, d["tv"], offsets, 0.0, rows, wseg)  # noqa: E731
         mmr = abi.mx_map_map_reduce_plain_f32 if plain else abi.mx_map_map_reduce_f32
         return [
             lambda: abi.mx_lengths_to_offsets(d["tL"], offsets, ws),
-            lambda: seg(abi.MX_ADD, d["tv"], offsets, 0.0, rows),
+            seg,
             lambda: mmr(0, 0, d["tA"], d["tB"], C),
             lambda: abi.mx_segmented_sum_adjoint_f32(d["tg"], offsets, gvals),
             lambda: mmr(0, 1, d["tG"], d["tB"], gA),
@@ -199,28 +290,25 @@ def bench_nested(args):
     graph = capture(side, step)
     graph_ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
     log(f"nested: fused {ms:.3f} ms/step (eager), {graph_ms:.3f} ms/step (HIP graph replay)")
-    parts = {nm: per_launch_ms(f, reps=max(args.steps, 10)) for nm, f in zip(names, fused_parts)}
-    # the same ragged kernels over three copies of their streamed array in turn
-    # (3 x 129 MB, more than the 256 MB last-level cache): every launch reads
-    # or writes its values from HBM, not from a cache warmed by the previous one
-    vcopies = [d["tv"]] + [d["tv"].clone() for _ in range(2)]
-    gcopies = [gvals] + [torch.empty_like(gvals) for _ in range(2)]
-    turn = [0]
-
-    def rotating(fn):
-        def f():
-            turn[0] = (turn[0] + 1) % 3
-            fn(turn[0])
-        return f
-
+    reps = max(50, args.steps)
+    # every part: per-launch durations (events around each launch), and the
+    # average over back-to-back launches (no marker between them)
+    stats = {nm: launch_stats(f, reps=reps) for nm, f in zip(names, fused_parts)}
+    b2b = {nm: per_launch_ms(f, reps=reps) for nm, f in zip(names, fused_parts)}
+    # cold: the ragged kernels over four copies of their streamed array in turn
+    # (4 x 129 MB, more than the 256 MB last-level cache), so every launch
+    # reads or writes its values from HBM
+    vcopies = [d["tv"]] + [d["tv"].clone() for _ in range(3)]
+    gcopies = [gvals] + [torch.empty_like(gvals) for _ in range(3)]
     cold = {
-        "row_sums": per_launch_ms(rotating(lambda i: abi.mx_segmented_reduce(abi.MX_ADD, vcopies[i], offsets, 0.0,
-                                                                              rows)), reps=max(args.steps, 12)),
-        "row_sums_adjoint": per_launch_ms(rotating(lambda i: abi.mx_segmented_sum_adjoint_f32(d["tg"], offsets,
-                                                                                               gcopies[i])),
-                                          reps=max(args.steps, 12)),
+        "row_sums": launch_stats(rotating(vcopies, lambda v: abi.mx_segmented_reduce(abi.MX_ADD, v, offsets, 0.0,
+                                                                                      rows, wseg)), reps=reps),
+        "row_sums_adjoint": launch_stats(rotating(gcopies, lambda gv: abi.mx_segmented_sum_adjoint_f32(
+            d["tg"], offsets, gv)), reps=reps),
     }
     del vcopies, gcopies
+    ceiling = hbm_read_ceiling(dev, 4 * nval, reps=reps)
+    log(f"nested: read-only ceiling {ceiling['GB/s']} GB/s over {ceiling['bytes'] / 1e6:.1f} MB")
     psteps = max(1, min(args.steps, 3))
     pms = timed_on(torch.cuda.current_stream(), plain_step, psteps, 1)
     pparts = {nm: per_launch_ms(f, reps=1, warmup=0) for nm, f in zip(names, plain_parts)}
@@ -236,23 +324,28 @@ def bench_nested(args):
     counted = {"row_sums": traffic_of("seg_span"), "row_sums_adjoint": traffic_of("seg_broadcast")}
     detail = {}
     for n in names:
-        e = {"us": round(parts[n] * 1e3, 2), "plain_us": round(pparts[n] * 1e3, 2)}
+        mean = float(stats[n].mean())
+        e = {**summary_us(stats[n]), "b2b_us": round(b2b[n] * 1e3, 2), "plain_us": round(pparts[n] * 1e3, 2)}
         if counted.get(n):
             e["traffic_bytes"] = counted[n]
         if n in bytes_:
-            e["GB/s"] = round(gbs(bytes_[n], parts[n]), 1)
-            e["frac_hbm"] = round(gbs(bytes_[n], parts[n]) / HBM_PEAK_GBS, 4)
+            med = float(np.median(stats[n]))
+            e["GB/s"] = round(gbs(bytes_[n], med), 1)
+            e["frac_hbm"] = round(gbs(bytes_[n], med) / HBM_PEAK_GBS, 4)
             if n in cold:
-                e["cold_us"] = round(cold[n] * 1e3, 2)
-                e["cold_GB/s"] = round(gbs(bytes_[n], cold[n]), 1)
-                e["cold_frac_hbm"] = round(gbs(bytes_[n], cold[n]) / HBM_PEAK_GBS, 4)
+                cmed = float(np.median(cold[n]))
+                e["cold"] = summary_us(cold[n])
+                e["cold_GB/s"] = round(gbs(bytes_[n], cmed), 1)
+                e["cold_frac_hbm"] = round(gbs(bytes_[n], cmed) / HBM_PEAK_GBS, 4)
+                e["cold_frac_ceiling"] = round(gbs(bytes_[n], cmed) / ceiling["GB/s"], 4)
         else:
-            tf = flops / (parts[n] * 1e-3) / 1e12
+            tf = flops / (mean * 1e-3) / 1e12
             e["TFLOP/s"] = round(tf, 2)
             e["frac_mfma"] = round(tf / FP32_MFMA_PEAK_TFLOPS, 4)
         detail[n] = e
     dom = "mmr_fwd"
-    ach = flops / (parts[dom] * 1e-3) / 1e12
+    ach = flops / (float(stats[dom].mean()) * 1e-3) / 1e12
+    hbm_ms = float(np.median(cold["row_sums"]) + np.median(cold["row_sums_adjoint"]))
     line = {
         "metric": METRIC,
         "value": elems / (ms * 1e-3),
@@ -267,13 +360,23 @@ def bench_nested(args):
                    "elements_per_step": elems},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_mfma<128,128,4,2,0,0> (dense map-map-reduce forward)",
                      "achieved": round(ach, 2), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": traffic_of("gemm_nn")},
+                     "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": traffic_of("gemm_nn"),
+                     "duration": "mean of per-launch event pairs"},
+        # the ragged (HBM) half of the step on its own: values read forward and
+        # written backward, from HBM (cold), against 8 TB/s and the read ceiling
+        "hbm": {"elements": 2 * nval, "cold_ms": round(hbm_ms, 4),
+                "elem/s": 2 * nval / (hbm_ms * 1e-3),
+                "GB/s": round(gbs(bytes_["row_sums"] + bytes_["row_sums_adjoint"], hbm_ms), 1),
+                "frac_hbm": round(gbs(bytes_["row_sums"] + bytes_["row_sums_adjoint"], hbm_ms) / HBM_PEAK_GBS, 4),
+                "read_ceiling": ceiling},
         "parts": detail,
         "plain": {"ms_per_step": pms, "value": elems / (pms * 1e-3),
                   "fused_speedup": round(pms / ms, 2)},
         "graph_ms_per_step": graph_ms,
         "timing": "value and ms_per_step: K eager steps between two events (graph_ms_per_step: the same step "
-                  "replayed from a HIP graph); parts: K back-to-back launches of each part between two events",
+                  "replayed from a HIP graph); parts: per-launch event pairs over >= 50 launches (mean, median, "
+                  "p10, p90) and the back-to-back average (b2b_us); cold: the ragged kernels over four 129 MB "
+                  "copies in turn",
     }
     line["marshal"] = marshal_rates(d, dev)
     if not args.no_cpu_baseline:
@@ -333,39 +436,69 @@ def marshal_rates(d, dev):
 
 
 def cpu_baseline_nested(d, rows, C, gA, gB, gvals, offsets):
-    """The oracle on a bounded sample of the same workload, timed on the host."""
+    """The oracle on a bounded sample of the same workload, timed on the host
+    twice: on one thread (the sequential column of the paper's tables), and on
+    all the host threads this process may use, splitting only the outer maps
+    (row ranges of the ragged rows, row blocks of the products) -- every fold
+    stays a sequential left fold, so both legs give the same values."""
+    import concurrent.futures as cf
     import torch
     import oracle as O
     torch.cuda.synchronize()
     log("nested: cpu baseline (oracle)")
     L, v, A, B, G, g = d["L"], d["v"], d["A"], d["B"], d["G"], d["g_rows"]
     sample_rows = 256
-    t0 = time.perf_counter()
     off = O.offsets_from_lengths(L)
-    R = O.segmented_reduce(O.ADD, 0.0, v, off)
-    gv = O.segmented_sum_adjoint(g, off)
-    Cs = O.matmul(A[:sample_rows], B)
-    gAs = O.matmul(G[:sample_rows], B, tb=True)
-    gBs = O.matmul(A[:, :sample_rows].copy(), G, ta=True)
-    secs = time.perf_counter() - t0
     n = len(L) + 2 * int(L.sum()) + 3 * sample_rows * d["B"].shape[1] * A.shape[1]
+    At = A[:, :sample_rows].T.copy()  # rows of A^T: the sample of dB = A^T dC
+
+    def rows_part(lo, hi):
+        o = off[lo:hi + 1] - off[lo]
+        vv = v[off[lo]:off[hi]]
+        return O.segmented_reduce(O.ADD, 0.0, vv, o), O.segmented_sum_adjoint(g[lo:hi], o)
+
+    def prod_part(lo, hi):
+        return O.matmul(A[lo:hi], B), O.matmul(G[lo:hi], B, tb=True), O.matmul(At[lo:hi], G)
+
+    def run(threads):
+        t0 = time.perf_counter()
+        if threads == 1:
+            parts_r = [rows_part(0, len(L))]
+            parts_p = [prod_part(0, sample_rows)]
+        else:
+            with cf.ThreadPoolExecutor(threads) as ex:
+                fr = [ex.submit(rows_part, lo, hi) for lo, hi in split_ranges(len(L), 4 * threads)]
+                fp = [ex.submit(prod_part, lo, hi) for lo, hi in split_ranges(sample_rows, threads)]
+                parts_r = [f.result() for f in fr]
+                parts_p = [f.result() for f in fp]
+        secs = time.perf_counter() - t0
+        R = np.concatenate([p[0] for p in parts_r])
+        gv = np.concatenate([p[1] for p in parts_r])
+        Cs, gAs, gBs = (np.concatenate([p[k] for p in parts_p]) for k in range(3))
+        return secs, R, gv, Cs, gAs, gBs
+
+    secs1, R, gv, Cs, gAs, gBs = run(1)
+    nt = cpu_threads()
+    secsN, RN, gvN, CN, gAN, gBN = run(nt)
+    same = all(np.array_equal(x, y) for x, y in ((R, RN), (gv, gvN), (Cs, CN), (gAs, gAN), (gBs, gBN)))
     # sample parity: the GPU results of the timed run against the oracle's
-    ok = bool(np.array_equal(offsets.cpu().numpy(), off))
+    ok = bool(np.array_equal(offsets.cpu().numpy(), off)) and same
     S = O.segmented_reduce(O.ADD, 0.0, np.abs(v), off)
     rg = rows.cpu().numpy().astype(np.float64)
     ok &= bool(np.all(np.abs(rg - R) <= 1e-4 * np.maximum(np.abs(R), S / np.sqrt(np.maximum(L, 1)))))
     ok &= bool(np.array_equal(gvals.cpu().numpy(), gv.astype(np.float32)))
     worst = 0.0
-    for got, ref, absref in ((C.cpu().numpy()[:sample_rows], Cs, None),
-                             (gA.cpu().numpy()[:sample_rows], gAs, None),
-                             (gB.cpu().numpy()[:sample_rows], gBs, None)):
+    for got, ref in ((C.cpu().numpy()[:sample_rows], Cs), (gA.cpu().numpy()[:sample_rows], gAs),
+                     (gB.cpu().numpy()[:sample_rows], gBs)):
         err = np.abs(got - ref) / np.maximum(np.abs(ref), math.sqrt(A.shape[1]) / 4)
         worst = max(worst, float(err.max()))
     ok &= worst <= 1e-4
-    return {"value": n / secs, "unit": "elem/s", "cores": cpu_threads(), "kind": "oracle",
-            "seconds": round(secs, 2),
-            "sample": f"all 65536 row sums and their adjoint, plus {sample_rows} rows of C, dA and dB "
-                      f"(2048-long folds) of the 2048^3 products",
+    sample = (f"all 65536 row sums and their adjoint, plus {sample_rows} rows of C, dA and dB "
+              f"(2048-long folds) of the 2048^3 products")
+    return {"value": n / secsN, "unit": "elem/s", "cores": nt, "kind": "oracle", "seconds": round(secsN, 2),
+            "sample": sample, "cpu": cpu_model(),
+            "split": "outer maps only (row ranges, product row blocks); folds sequential",
+            "single_thread": {"value": n / secs1, "cores": 1, "seconds": round(secs1, 2)},
             "sample_parity": "ok" if ok else "MISMATCH", "max_rel_err_products": worst}
 
 
@@ -450,7 +583,7 @@ def bench_dot(args):
             O.dot(a, b)
             reps += 1
         secs = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": reps * n / secs, "unit": "elem/s", "cores": cpu_threads(),
+        line["cpu_baseline"] = {"value": reps * n / secs, "unit": "elem/s", "cores": 1,
                                 "kind": "oracle", "seconds": round(secs, 2),
                                 "sample": f"the float32 dot over 2^20, {reps} times"}
     return line
@@ -576,7 +709,7 @@ def bench_nbody(args):
         O.nbody_step(x0, vel, m, eps2, G, dt)
         O.nbody_accel_vjp(x0, m, np.ones_like(x0), eps2, G)
         secs = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": 2 * n * n / secs, "unit": "pair-interactions/s", "cores": cpu_threads(),
+        line["cpu_baseline"] = {"value": 2 * n * n / secs, "unit": "pair-interactions/s", "cores": 1,
                                 "kind": "oracle", "seconds": round(secs, 2),
                                 "sample": "one forward Euler step and one transposed-Jacobian product at N=16384"}
     del g_full, g_fwd
@@ -652,7 +785,7 @@ def bench_kmeans(args):
             _, _, Co = O.kmeans_update(X, lab, Co)
         secs = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": iters * n * k / secs, "unit": "point-centroid evals/s",
-                                "cores": cpu_threads(), "kind": "oracle", "seconds": round(secs, 2),
+                                "cores": 1, "kind": "oracle", "seconds": round(secs, 2),
                                 "sample": f"the whole workload: {iters} assignment + update steps over all "
                                           f"2^20 points (no SSE / gradient)"}
     del graph
@@ -733,7 +866,7 @@ def bench_batched(args):
         O.batch_backward(tb[:sample], bt.A, bt.B, bt.gout)
         secs = time.perf_counter() - t0
         se = int((rows[:sample] * cols[:sample]).sum())
-        line["cpu_baseline"] = {"value": 2 * se / secs, "unit": "elem/s", "cores": cpu_threads(), "kind": "oracle",
+        line["cpu_baseline"] = {"value": 2 * se / secs, "unit": "elem/s", "cores": 1, "kind": "oracle",
                                 "seconds": round(secs, 2),
                                 "sample": "forward + backward of all 2048 tasks"}
     del graph
@@ -752,7 +885,7 @@ def gauss_dot_body(abi):
 
 def bench_expr(args):
     import torch
-    from paper_2211_00621_amd import abi
+    from paper_2211_00621_amd import abi, api
     dev = torch.device("cuda:0")
     n = 1 << 26
     gen = torch.Generator(device=dev).manual_seed(0)
@@ -795,13 +928,14 @@ def bench_expr(args):
     va, vb = a[:nv], b[:nv]
     rows = torch.empty(len(L), device=dev)
     tmpv = torch.empty(nv, device=dev)
+    wseg = api.workspace(abi.MX_WS_SEGMENTED, nv, device=dev)
 
     def seg():
         abi.mx_expr_segmented_reduce(e, abi.MX_ADD, [va, vb], off, 0.0, rows)
 
     def seg_plain():  # body into a temporary, then the fixed ragged row sums
         abi.mx_expr_map(e, [va, vb], tmpv)
-        abi.mx_segmented_reduce(abi.MX_ADD, tmpv, off, 0.0, rows)
+        abi.mx_segmented_reduce(abi.MX_ADD, tmpv, off, 0.0, rows, wseg)
 
     parts["segmented"] = per_launch_ms(seg, reps=args.steps, warmup=args.warmup)
     parts["segmented_plain"] = per_launch_ms(seg_plain, reps=args.steps, warmup=args.warmup)
@@ -840,7 +974,7 @@ def bench_expr(args):
         O.expr_map_reduce(O.ADD, 0.0, prog, out_reg, an, bn)
         O.expr_vjp(prog, out_reg, [an, bn], gscale=1.0)
         secs = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": 2 * sample / secs, "unit": "elem/s", "cores": cpu_threads(),
+        line["cpu_baseline"] = {"value": 2 * sample / secs, "unit": "elem/s", "cores": 1,
                                 "kind": "oracle", "seconds": round(secs, 2),
                                 "sample": "map+reduce and reverse mode over all 2^26 elements"}
     return line
@@ -982,7 +1116,7 @@ def bench_parboil(args):
         O.tpacf(s0[:, :sample_p], s1, e_np, False)
         secs = time.perf_counter() - t0
         n_done = 2 * nkeys + pts + nk * sample_v + sample_p * npt
-        line["cpu_baseline"] = {"value": n_done / secs, "unit": "elem/s", "cores": cpu_threads(), "kind": "oracle",
+        line["cpu_baseline"] = {"value": n_done / secs, "unit": "elem/s", "cores": 1, "kind": "oracle",
                                 "seconds": round(secs, 2),
                                 "sample": f"both histograms and the stencil sweep in full, mri-q for the first "
                                           f"{sample_v} of the 2^18 voxels, tpacf cross pairs of the first {sample_p} "
@@ -1002,6 +1136,32 @@ def copy_calibration(mib):
     return {"copy_calibration": {"kernel": "k_copy32", "launches": 5, "read_bytes": n, "write_bytes": n}}
 
 
+def suite_results(args):
+    """The other configurations measured inside the default run, each with its
+    own fused and plain forms (fewer timed steps, no CPU baseline): the
+    fused dot (2^20), the N-body loop with its checkpointed reverse (16 384
+    bodies, 20 steps), k-means (2^20 x 32, k = 64, 10 steps) and the 2048
+    batched uneven expressions.  Per workload: value, step time, the roofline
+    of its dominant kernel and the plain comparison."""
+    import torch
+    sub = argparse.Namespace(steps=max(3, min(args.steps, 10)), warmup=2, no_cpu_baseline=True)
+    out = {}
+    for name, fn in (("dot", bench_dot), ("nbody", bench_nbody), ("kmeans", bench_kmeans),
+                     ("batched", bench_batched)):
+        t0 = time.perf_counter()
+        log(f"suite: {name}")
+        ln = fn(sub)
+        rf = ln["roofline"]
+        out[name] = {"workload": ln["config"]["workload"], "value": ln["value"], "unit": ln["unit"],
+                     "ms_per_step": round(ln["ms_per_step"], 4),
+                     "roofline": {k: rf[k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac")},
+                     "plain": ln.get("plain"), "parts": ln.get("parts"), "steps": sub.steps,
+                     "seconds": round(time.perf_counter() - t0, 1)}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 WORKLOADS = {"nested": bench_nested, "dot": bench_dot, "nbody": bench_nbody, "kmeans": bench_kmeans,
              "batched": bench_batched, "expr": bench_expr, "parboil": bench_parboil}
 
@@ -1013,6 +1173,8 @@ def main(argv=None):
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", choices=sorted(WORKLOADS), default="nested")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-suite", action="store_true",
+                   help="default workload only: skip the dot / nbody / kmeans / batched sub-results")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run mx_copy32 over MIB MiB five times (the reference kernel that scales the "
                         "FETCH_SIZE / WRITE_SIZE counters to bytes) and print its size")
@@ -1028,6 +1190,9 @@ def main(argv=None):
         line = copy_calibration(args.copy_calibration)
     else:
         line = WORKLOADS[args.workload](args)
+        if args.workload == "nested" and not args.no_suite:
+            torch.cuda.empty_cache()
+            line["suite"] = suite_results(args)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -92,7 +92,8 @@ typedef enum mx_binop {
 typedef enum mx_ws_kind {
     MX_WS_REDUCE = 0,   /* mx_reduce, mx_map2_reduce: n = sequence length */
     MX_WS_SCAN = 1,     /* mx_lengths_to_offsets, mx_marshal_rows: n = number of rows */
-    MX_WS_HISTOGRAM = 2 /* mx_histogram_u32: n = number of keys, aux = nbins; 0 = none used */
+    MX_WS_HISTOGRAM = 2, /* mx_histogram_u32: n = number of keys, aux = nbins; 0 = none used */
+    MX_WS_SEGMENTED = 3  /* mx_segmented_reduce: n = number of values (any dtype) */
 } mx_ws_kind;
 
 /* ======================================================================= */
@@ -123,6 +124,16 @@ size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux);
  * streaming kernel (the reference kernel used to calibrate hardware byte
  * counters).  dst and src must not overlap.  Errors: MX_ERR_INVALID. */
 mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t stream);
+
+/* Read-only streaming pass over n 32-bit words (the measured ceiling that
+ * the memory-bound kernels are compared with): each block reads one
+ * contiguous 16 KB chunk in 16-byte loads and XORs the XOR of its words into
+ * xor_dev[block % MX_STREAM_READ_SLOTS]; xor_dev is a device array of
+ * MX_STREAM_READ_SLOTS uint32 the caller zero-fills first, and the XOR of all
+ * slots is the XOR of all n words (independent of block order).  src must be
+ * 16-byte aligned.  Errors: MX_ERR_INVALID, MX_ERR_SHAPE. */
+#define MX_STREAM_READ_SLOTS 1024
+mx_status mx_stream_read(const void *src_dev, int64_t n, uint32_t *xor_dev, hipStream_t stream);
 
 /* ======================================================================= */
 /* Marshaling (Section 4.3): nested sequences -> flat values + offsets      */
@@ -328,35 +339,50 @@ mx_status mx_reduce_adjoint_f32(mx_redop op, const float *x_dev, int64_t n, cons
 
 /* out[r] = reduce op ne (row r) for r < nseg, where row r is
  * values[offsets[r] .. offsets[r+1]) of the flat layout made by marshaling.
- * offsets: device int64[nseg+1], non-decreasing, offsets[0] = 0 (validated in
- * debug mode).  Empty rows give ne.  out: device, accumulator type, nseg
- * values.  Errors: MX_ERR_INVALID, MX_ERR_DTYPE, MX_ERR_SHAPE (debug mode). */
-mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_dev,
-                              const int64_t *offsets_dev, int64_t nseg, const void *ne_host,
-                              void *out_dev, hipStream_t stream);
+ * values: device, nvalues elements of dtype.  offsets: device int64[nseg+1],
+ * non-decreasing, offsets[0] = 0, offsets[nseg] = nvalues (all three
+ * validated in debug mode).  Empty rows give ne.  out: device, accumulator
+ * type, nseg values.
+ * Work is split by value count: the values are cut into 16 KB chunks, one
+ * block each, so the time does not depend on how the lengths are spread.  A
+ * row that spans chunks is folded per chunk and the chunk parts are combined
+ * in chunk order, so results are deterministic (for floating point they may
+ * differ in the last bits from mx_segmented_reduce_plain's left fold).
+ * Workspace: mx_workspace_bytes(MX_WS_SEGMENTED, nvalues, 0) bytes, 256-byte
+ * aligned, zero-filled before first use (the call leaves it zero again); NULL
+ * is accepted when nvalues <= 2048.  Calls that share a workspace must not
+ * overlap.  Errors: MX_ERR_INVALID, MX_ERR_DTYPE, MX_ERR_WORKSPACE,
+ * MX_ERR_SHAPE (nvalues < 0; bad offsets in debug mode). */
+mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_dev, int64_t nvalues,
+                              const int64_t *offsets_dev, int64_t nseg, const void *ne_host, void *out_dev,
+                              void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Reference "plain" form of mx_segmented_reduce: one thread folds one row
- * sequentially (no load balancing, uncoalesced).  Same contract. */
-mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *values_dev,
+ * sequentially, left to right from ne (no load balancing, uncoalesced, no
+ * workspace).  Same contract otherwise. */
+mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *values_dev, int64_t nvalues,
                                     const int64_t *offsets_dev, int64_t nseg, const void *ne_host,
                                     void *out_dev, hipStream_t stream);
 
 /* Reverse of the row sums out[r] = sum(row r) (F32): every element of row r
  * receives gout[r]: gvalues[e] = gout[r] for offsets[r] <= e < offsets[r+1].
- * Errors: MX_ERR_INVALID, MX_ERR_SHAPE (debug mode). */
-mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *offsets_dev,
-                                       int64_t nseg, float *gvalues_dev, hipStream_t stream);
+ * gvalues: device float[nvalues], offsets[nseg] = nvalues (debug mode checks
+ * it).  Written in 16 KB chunks, one block each, like mx_segmented_reduce.
+ * Errors: MX_ERR_INVALID, MX_ERR_SHAPE. */
+mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *offsets_dev, int64_t nseg,
+                                       float *gvalues_dev, int64_t nvalues, hipStream_t stream);
 
 /* Reverse of out[r] = reduce op ne (row r) (F32): row r receives the reverse
  * of its reduce (as mx_reduce_adjoint_f32) with upstream gradient gout[r]:
  * MX_ADD broadcasts gout[r] over the row (mx_segmented_sum_adjoint_f32;
  * values may then be NULL), MX_MIN / MX_MAX put gout[r] at the row's arg
  * element and 0 elsewhere (one wave per row).  gout: device float[nseg];
- * gvalues: device float[offsets[nseg]], must not alias values.  Errors:
+ * values and gvalues: device float[nvalues] with nvalues = offsets[nseg];
+ * gvalues must not alias values.  Errors:
  * MX_ERR_INVALID, MX_ERR_SHAPE (debug mode), MX_ERR_UNSUPPORTED (MX_MUL). */
-mx_status mx_segmented_reduce_adjoint_f32(mx_redop op, const float *values_dev, const int64_t *offsets_dev,
-                                          int64_t nseg, const float *ne_host, const float *gout_dev,
-                                          float *gvalues_dev, hipStream_t stream);
+mx_status mx_segmented_reduce_adjoint_f32(mx_redop op, const float *values_dev, int64_t nvalues,
+                                          const int64_t *offsets_dev, int64_t nseg, const float *ne_host,
+                                          const float *gout_dev, float *gvalues_dev, hipStream_t stream);
 
 /* ======================================================================= */
 /* Dense nested map (map (reduce (+) 0 (map2 (*) row col))) -- FP32 on MFMA */

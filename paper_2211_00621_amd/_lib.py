@@ -29,6 +29,7 @@ SIGNATURES = {
     "mx_get_debug": (c_int, []),
     "mx_workspace_bytes": (c_size, [c_enum, c_i64, c_i64]),
     "mx_copy32": (c_status, [c_p, c_p, c_i64, c_p]),
+    "mx_stream_read": (c_status, [c_p, c_i64, c_p, c_p]),
     "mx_lengths_to_offsets": (c_status, [c_p, c_i64, c_p, c_p, c_size, c_p]),
     "mx_marshal_rows": (c_status, [c_pp, c_p, c_i64, c_size, c_p, c_size, c_p, c_p, c_p, c_p, c_size, c_p]),
     "mx_unmarshal_rows": (c_status, [c_p, c_p, c_i64, c_size, c_p, c_size, c_pp, c_p]),
@@ -41,11 +42,11 @@ SIGNATURES = {
     "mx_reduce": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_p, c_p, c_size, c_p]),
     "mx_map2_reduce": (c_status, [c_enum, c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p, c_p, c_size, c_p]),
     "mx_dot_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_p, c_p, c_p]),
-    "mx_segmented_reduce": (c_status, [c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p, c_p]),
-    "mx_segmented_reduce_plain": (c_status, [c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p, c_p]),
-    "mx_segmented_sum_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_p]),
+    "mx_segmented_reduce": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_size, c_p]),
+    "mx_segmented_reduce_plain": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_i64, c_p, c_p, c_p]),
+    "mx_segmented_sum_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_i64, c_p]),
     "mx_reduce_adjoint_f32": (c_status, [c_enum, c_p, c_i64, c_p, c_p, c_p, c_p, c_size, c_p]),
-    "mx_segmented_reduce_adjoint_f32": (c_status, [c_enum, c_p, c_p, c_i64, c_p, c_p, c_p, c_p]),
+    "mx_segmented_reduce_adjoint_f32": (c_status, [c_enum, c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p]),
     "mx_map_map_reduce_f32": (c_status, [c_int, c_int, c_i64, c_i64, c_i64, c_p, c_p, c_p, c_p]),
     "mx_map_map_reduce_plain_f32": (c_status, [c_int, c_int, c_i64, c_i64, c_i64, c_p, c_p, c_p, c_p]),
     "mx_nbody_pair_workspace_bytes": (c_size, [c_i64]),

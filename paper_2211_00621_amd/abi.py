@@ -22,7 +22,7 @@ MX_ADD, MX_MUL, MX_MIN, MX_MAX = 0, 1, 2, 3
 (MX_U_ID, MX_U_NEG, MX_U_ABS, MX_U_SQ, MX_U_AFFINE, MX_U_EXP, MX_U_LOG, MX_U_SQRT,
  MX_U_RSQRT) = range(9)
 MX_B_ADD, MX_B_SUB, MX_B_MUL, MX_B_DIV, MX_B_MIN, MX_B_MAX = range(6)
-MX_WS_REDUCE, MX_WS_SCAN, MX_WS_HISTOGRAM = 0, 1, 2
+MX_WS_REDUCE, MX_WS_SCAN, MX_WS_HISTOGRAM, MX_WS_SEGMENTED = 0, 1, 2, 3
 (MX_X_IN, MX_X_CONST, MX_X_ADD, MX_X_SUB, MX_X_MUL, MX_X_DIV, MX_X_MIN, MX_X_MAX, MX_X_NEG, MX_X_ABS, MX_X_SQ,
  MX_X_EXP, MX_X_LOG, MX_X_SQRT, MX_X_RSQRT) = range(15)
 
@@ -117,6 +117,19 @@ def mx_workspace_bytes(kind: int, n: int, aux: int = 0) -> int:
 def mx_copy32(src, dst, stream=None) -> None:
     n = src.numel() * src.element_size() // 4
     _check(_L().mx_copy32(_dptr(src), _dptr(dst), n, _stream(stream)), "mx_copy32")
+
+
+MX_STREAM_READ_SLOTS = 1024
+
+
+def mx_stream_read(src, xor_slots, stream=None) -> None:
+    """Read-only pass over src (16-byte aligned, 4-byte elements); the XOR of its words is XORed, block by
+    block, into the MX_STREAM_READ_SLOTS words of xor_slots (the XOR of the slots is the XOR of src)."""
+    if src.element_size() != 4:
+        raise MxError(MX_ERR_INVALID, "mx_stream_read: 4-byte elements expected")
+    if xor_slots.numel() * xor_slots.element_size() < 4 * MX_STREAM_READ_SLOTS:
+        raise MxError(MX_ERR_INVALID, "mx_stream_read: xor_slots needs MX_STREAM_READ_SLOTS words")
+    _check(_L().mx_stream_read(_dptr(src), src.numel(), _dptr(xor_slots), _stream(stream)), "mx_stream_read")
 
 
 # ---------------------------------------------------------------- marshaling
@@ -222,23 +235,25 @@ def mx_dot_adjoint_f32(a, b, gout, ga, gb, stream=None) -> None:
 
 
 # ---------------------------------------------------------------- ragged
-def mx_segmented_reduce(op: int, values, offsets, ne, out, stream=None) -> None:
+def mx_segmented_reduce(op: int, values, offsets, ne, out, ws, stream=None) -> None:
+    """ws: a zero-filled workspace of mx_workspace_bytes(MX_WS_SEGMENTED, values.numel()) bytes (None when
+    values has at most 2048 elements)."""
     nb = _acc_scalar(ne, values.dtype)
-    _check(_L().mx_segmented_reduce(int(op), _dtype(values), _dptr(values), _dptr(offsets),
-                                    offsets.numel() - 1, ctypes.byref(nb), _dptr(out), _stream(stream)),
-           "mx_segmented_reduce")
+    _check(_L().mx_segmented_reduce(int(op), _dtype(values), _dptr(values), values.numel(), _dptr(offsets),
+                                    offsets.numel() - 1, ctypes.byref(nb), _dptr(out), _dptr(ws), _nbytes(ws),
+                                    _stream(stream)), "mx_segmented_reduce")
 
 
 def mx_segmented_reduce_plain(op: int, values, offsets, ne, out, stream=None) -> None:
     nb = _acc_scalar(ne, values.dtype)
-    _check(_L().mx_segmented_reduce_plain(int(op), _dtype(values), _dptr(values), _dptr(offsets),
+    _check(_L().mx_segmented_reduce_plain(int(op), _dtype(values), _dptr(values), values.numel(), _dptr(offsets),
                                           offsets.numel() - 1, ctypes.byref(nb), _dptr(out),
                                           _stream(stream)), "mx_segmented_reduce_plain")
 
 
 def mx_segmented_sum_adjoint_f32(gout, offsets, gvalues, stream=None) -> None:
     _check(_L().mx_segmented_sum_adjoint_f32(_dptr(gout), _dptr(offsets), offsets.numel() - 1,
-                                             _dptr(gvalues), _stream(stream)),
+                                             _dptr(gvalues), gvalues.numel(), _stream(stream)),
            "mx_segmented_sum_adjoint_f32")
 
 
@@ -252,8 +267,9 @@ def mx_reduce_adjoint_f32(op: int, x, ne, gout, gx, ws=None, stream=None) -> Non
 def mx_segmented_reduce_adjoint_f32(op: int, values, offsets, ne, gout, gvalues, stream=None) -> None:
     """Reverse of map (reduce op ne) over ragged rows; gout: device float[nseg]."""
     nb = ctypes.c_float(float(ne))
-    _check(_L().mx_segmented_reduce_adjoint_f32(int(op), _dptr(values), _dptr(offsets), offsets.numel() - 1,
-                                                ctypes.byref(nb), _dptr(gout), _dptr(gvalues), _stream(stream)),
+    _check(_L().mx_segmented_reduce_adjoint_f32(int(op), _dptr(values), gvalues.numel(), _dptr(offsets),
+                                                offsets.numel() - 1, ctypes.byref(nb), _dptr(gout), _dptr(gvalues),
+                                                _stream(stream)),
            "mx_segmented_reduce_adjoint_f32")
 
 

@@ -364,8 +364,11 @@ def fields_to_records(fields) -> torch.Tensor:
 
 def _segmented_reduce(op: int, r: Ragged, ne, plain: bool = False) -> torch.Tensor:
     out = torch.empty(r.nseg, dtype=ACC_OF[r.values.dtype], device=r.values.device)
-    fn = abi.mx_segmented_reduce_plain if plain else abi.mx_segmented_reduce
-    fn(op, r.values, r.offsets, ne, out)
+    if plain:
+        abi.mx_segmented_reduce_plain(op, r.values, r.offsets, ne, out)
+    else:
+        ws = workspace(abi.MX_WS_SEGMENTED, r.values.numel(), device=r.values.device)
+        abi.mx_segmented_reduce(op, r.values, r.offsets, ne, out, ws)
     return out
 
 
@@ -399,7 +402,8 @@ class _SegSum(torch.autograd.Function):
         ctx.save_for_backward(offsets)
         ctx.n = values.numel()
         out = torch.empty(offsets.numel() - 1, dtype=values.dtype, device=values.device)
-        abi.mx_segmented_reduce(MX_ADD, values, offsets, 0.0, out)
+        ws = workspace(abi.MX_WS_SEGMENTED, values.numel(), device=values.device)
+        abi.mx_segmented_reduce(MX_ADD, values, offsets, 0.0, out, ws)
         return out
 
     @staticmethod

@@ -196,18 +196,18 @@ mx_status mx_reduce_adjoint_f32(mx_redop op, const float *x_dev, int64_t n, cons
     return last_launch(who);
 }
 
-mx_status mx_segmented_reduce_adjoint_f32(mx_redop op, const float *values_dev, const int64_t *offsets_dev,
-                                          int64_t nseg, const float *ne_host, const float *gout_dev,
-                                          float *gvalues_dev, hipStream_t stream) {
+mx_status mx_segmented_reduce_adjoint_f32(mx_redop op, const float *values_dev, int64_t nvalues,
+                                          const int64_t *offsets_dev, int64_t nseg, const float *ne_host,
+                                          const float *gout_dev, float *gvalues_dev, hipStream_t stream) {
     const char *who = "mx_segmented_reduce_adjoint_f32";
-    MX_REQUIRE(nseg >= 0, MX_ERR_SHAPE, "%s: nseg < 0", who);
+    MX_REQUIRE(nseg >= 0 && nvalues >= 0, MX_ERR_SHAPE, "%s: nseg < 0 or nvalues < 0", who);
     MX_REQUIRE(op == MX_ADD || op == MX_MIN || op == MX_MAX,
                op == MX_MUL ? MX_ERR_UNSUPPORTED : MX_ERR_INVALID, "%s: operator %d has no reverse here", who,
                (int)op);
     MX_REQUIRE(ne_host, MX_ERR_INVALID, "%s: null ne", who);
     if (nseg == 0) return MX_OK;
-    MX_REQUIRE(offsets_dev && gout_dev && gvalues_dev, MX_ERR_INVALID, "%s: null pointer", who);
-    if (op == MX_ADD) return mx_segmented_sum_adjoint_f32(gout_dev, offsets_dev, nseg, gvalues_dev, stream);
+    MX_REQUIRE(offsets_dev && gout_dev && (gvalues_dev || nvalues == 0), MX_ERR_INVALID, "%s: null pointer", who);
+    if (op == MX_ADD) return mx_segmented_sum_adjoint_f32(gout_dev, offsets_dev, nseg, gvalues_dev, nvalues, stream);
     MX_REQUIRE(values_dev, MX_ERR_INVALID, "%s: null values", who);
     MX_REQUIRE(gvalues_dev != values_dev, MX_ERR_INVALID, "%s: gvalues must not alias values", who);
     if (mx_status st = check_offsets_debug(who, offsets_dev, nseg, stream)) return st;

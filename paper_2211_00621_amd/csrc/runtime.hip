@@ -1,5 +1,6 @@
 // Runtime: error text, per-device property cache, debug flag, workspace
 // sizing and the plain streaming copy kernel.
+#include <algorithm>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -76,6 +77,33 @@ __global__ void __launch_bounds__(256) k_copy32(const uint32_t *__restrict__ src
     if (blockIdx.x == 0 && threadIdx.x < (n & 3)) dst[nv * 4 + threadIdx.x] = src[nv * 4 + threadIdx.x];
 }
 
+// Read-only stream: block b reads the contiguous 16 KB chunk b (1024 16-byte
+// vectors, four per thread, all in flight together) and folds it by XOR.
+constexpr int kReadChunkVec = 1024;
+constexpr int kReadSlots = MX_STREAM_READ_SLOTS;
+__global__ void __launch_bounds__(256) k_stream_read(const u32x4 *__restrict__ src, int64_t nv,
+                                                     const uint32_t *__restrict__ tail, int ntail,
+                                                     uint32_t *xor_out) {
+    __shared__ uint32_t red[4];
+    const int64_t base = (int64_t)blockIdx.x * kReadChunkVec;
+    u32x4 x[kReadChunkVec / 256];
+#pragma unroll
+    for (int u = 0; u < kReadChunkVec / 256; ++u) {
+        const int64_t i = base + threadIdx.x + 256 * u;
+        x[u] = i < nv ? __builtin_nontemporal_load(src + i) : u32x4{0, 0, 0, 0};
+    }
+    uint32_t a = 0;
+#pragma unroll
+    for (int u = 0; u < kReadChunkVec / 256; ++u) a ^= x[u].x ^ x[u].y ^ x[u].z ^ x[u].w;
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) a ^= tail[threadIdx.x];
+    for (int d = 32; d > 0; d >>= 1) a ^= __shfl_xor(a, d);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = a;
+    __syncthreads();
+    // spread over kReadSlots words: one shared word would serialise the
+    // blocks' atomics at one L2 channel
+    if (threadIdx.x == 0) atomicXor(xor_out + (blockIdx.x & (kReadSlots - 1)), red[0] ^ red[1] ^ red[2] ^ red[3]);
+}
+
 }  // namespace mx
 
 using namespace mx;
@@ -111,6 +139,7 @@ size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux) {
         return kCounterBytes + align256((size_t)tiles * 8);
     }
     case MX_WS_HISTOGRAM: return histogram_ws_bytes(n, aux);
+    case MX_WS_SEGMENTED: return segmented_ws_bytes(n);
     }
     return 0;
 }
@@ -174,6 +203,19 @@ mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t s
     hipLaunchKernelGGL(k_copy32, dim3((unsigned)blocks), dim3(256), 0, stream,
                        (const uint32_t *)src_dev, (uint32_t *)dst_dev, n);
     return last_launch("mx_copy32");
+}
+
+mx_status mx_stream_read(const void *src_dev, int64_t n, uint32_t *xor_dev, hipStream_t stream) {
+    MX_REQUIRE(n >= 0, MX_ERR_SHAPE, "mx_stream_read: n < 0");
+    if (n == 0) return MX_OK;
+    MX_REQUIRE(src_dev && xor_dev, MX_ERR_INVALID, "mx_stream_read: null pointer");
+    MX_REQUIRE(((uintptr_t)src_dev % 16) == 0, MX_ERR_INVALID, "mx_stream_read: src must be 16-byte aligned");
+    const int64_t nv = n / 4;
+    const int64_t blocks = std::max<int64_t>(1, ceil_div(nv, kReadChunkVec));
+    MX_REQUIRE(blocks <= 0x7fffffff, MX_ERR_SHAPE, "mx_stream_read: too large");
+    hipLaunchKernelGGL(k_stream_read, dim3((unsigned)blocks), dim3(256), 0, stream, (const u32x4 *)src_dev, nv,
+                       (const uint32_t *)src_dev + nv * 4, (int)(n & 3), xor_dev);
+    return last_launch("mx_stream_read");
 }
 
 }  // extern "C"

@@ -69,10 +69,37 @@ def test_argument_errors_before_any_device_work(lib):
     assert lib.mx_reduce(9, 0, None, 4, ctypes.byref(v), None, None, 0, None) == abi.MX_ERR_INVALID
     fake = ctypes.c_void_p(4096)
     assert lib.mx_reduce(0, 0, fake, 4, ctypes.byref(v), fake, fake, 16, None) == abi.MX_ERR_WORKSPACE
-    assert lib.mx_segmented_reduce(0, 0, None, None, -1, ctypes.byref(v), None, None) == abi.MX_ERR_SHAPE
+    assert lib.mx_segmented_reduce(0, 0, None, 0, None, -1, ctypes.byref(v), None, None, 0, None) == abi.MX_ERR_SHAPE
+    assert lib.mx_segmented_reduce(0, 0, fake, -1, fake, 4, ctypes.byref(v), fake, None, 0, None) == abi.MX_ERR_SHAPE
+    # more than one 16 KB chunk of values needs the workspace
+    assert lib.mx_segmented_reduce(0, 0, fake, 4097, fake, 4, ctypes.byref(v), fake, None, 0,
+                                   None) == abi.MX_ERR_WORKSPACE
+    assert lib.mx_segmented_reduce(0, 0, fake, 4097, fake, 4, ctypes.byref(v), fake, fake, 64,
+                                   None) == abi.MX_ERR_WORKSPACE
     assert lib.mx_map_map_reduce_f32(2, 0, 4, 4, 4, fake, fake, fake, None) == abi.MX_ERR_INVALID
     assert lib.mx_records_to_fields(fake, 4, 17, 4, None, None) == abi.MX_ERR_INVALID
     assert "mx_records_to_fields" in lib.mx_last_error().decode()
+
+
+def test_segmented_workspace_sizes(lib):
+    # one counter and two 16-byte slots per chunk of 2048 elements (the chunk
+    # length of 8-byte types; 4-byte types use half as many chunks)
+    from paper_2211_00621_amd import abi
+    ws = lambda n: lib.mx_workspace_bytes(abi.MX_WS_SEGMENTED, n, 0)  # noqa: E731
+    for n in (0, 1, 2048, 2049, 32101627):
+        nch = -(-n // 2048)
+        need = 256 + (-(-nch * 4 // 256)) * 256 + 2 * (-(-nch * 16 // 256)) * 256
+        assert ws(n) == need, n
+    assert ws(32101627) < 1 << 20
+
+
+def test_nbody_workspace_sizes_at_zero_bodies(lib):
+    # n = 0 is a valid size (nothing to do): the size queries answer it
+    lib.mx_nbody_workspace_bytes.restype = ctypes.c_size_t
+    lib.mx_nbody_pair_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.mx_nbody_pair_workspace_bytes(ctypes.c_int64(0)) == 256
+    assert lib.mx_nbody_workspace_bytes(ctypes.c_int64(0), 20, 5) >= 256
+    assert lib.mx_nbody_workspace_bytes(ctypes.c_int64(1), 20, 5) > lib.mx_nbody_workspace_bytes(ctypes.c_int64(0), 20, 5)
 
 
 def test_histogram_workspace_sizes(lib):

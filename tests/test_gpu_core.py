@@ -354,6 +354,119 @@ def test_segmented_shapes(lengths, dt):
         assert host(gv[:1])[0] == 5.0
 
 
+def _chunk_case(case, dt):
+    """Row lengths that stress the 16 KB chunks (S = 4096 four-byte or 2048
+    eight-byte elements)."""
+    S = 4096 if np.dtype(dt).itemsize == 4 else 2048
+    rng = np.random.default_rng(hash(case) % 1000)
+    if case == "tiny_rows":        # thousands of rows per chunk: several row batches each
+        L = rng.integers(0, 4, 200000)
+    elif case == "chunk_edges":    # rows ending and starting on chunk boundaries, empty rows there
+        pat = [S, 0, 0, S - 1, 1, 0, S + 1, S - 1, 2 * S, 0, 1, S - 2, 1, 0, 3 * S, 0]
+        L = np.array(pat * 7)
+    elif case == "one_long_row":   # one row over ~1000-2000 chunks: the finish folds many head parts
+        L = np.array([0, 3, (1 << 22) + 5, 0, 7, 0])
+    else:                          # mixed: log-uniform up to 5 S, every seventh row empty
+        L = np.floor(np.exp(rng.uniform(0, np.log(5 * S + 1), 3000))).astype(np.int64)
+        L[::7] = 0
+    return np.asarray(L, dtype=np.int64), S
+
+
+@pytest.mark.parametrize("case", ["tiny_rows", "chunk_edges", "one_long_row", "mixed"])
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32, np.int64])
+def test_segmented_chunk_boundaries(case, dt):
+    """Every row against the oracle for layouts around the chunk boundaries
+    (integers bit-exact for every operator); a second call gives the same bits
+    and the workspace is left zero-filled."""
+    say("segmented chunks", case, np.dtype(dt).name)
+    L, S = _chunk_case(case, dt)
+    off = O.offsets_from_lengths(L)
+    nv = int(off[-1])
+    rng = np.random.default_rng(7)
+    ops = [abi.MX_ADD]
+    if np.issubdtype(dt, np.integer):
+        v = rng.integers(-10 ** 6, 10 ** 6, nv).astype(dt)
+        ops = [abi.MX_ADD, abi.MX_MIN, abi.MX_MAX, abi.MX_MUL]
+    else:
+        v = rng.uniform(-1, 1, nv).astype(dt)
+    tv, toff = dev(v), dev(off)
+    ws = torch.zeros(abi.mx_workspace_bytes(abi.MX_WS_SEGMENTED, nv), dtype=torch.uint8, device=DEV)
+    for op in ops:
+        ne = {abi.MX_ADD: 0, abi.MX_MUL: 1, abi.MX_MIN: 2 ** 63 - 1, abi.MX_MAX: -2 ** 63}[op]
+        vin = v
+        if op == abi.MX_MUL:  # small factors keep products in range of the exact check
+            vin = rng.integers(-2, 3, nv).astype(dt)
+            tv = dev(vin)
+        out = torch.empty(len(L), dtype=api.ACC_OF[tv.dtype], device=DEV)
+        abi.mx_segmented_reduce(op, tv, toff, ne if np.issubdtype(dt, np.integer) else 0.0, out, ws)
+        got = host(out).copy()
+        assert not np.any(host(ws)), "workspace left non-zero"
+        out2 = torch.full_like(out, 3)
+        abi.mx_segmented_reduce(op, tv, toff, ne if np.issubdtype(dt, np.integer) else 0.0, out2, ws)
+        assert got.tobytes() == host(out2).tobytes(), "second call differs"
+        if np.issubdtype(dt, np.integer):
+            assert np.array_equal(got, O.segmented_reduce(op, ne, vin, off)), op
+        else:
+            check_vector(got, O.segmented_reduce(O.ADD, 0.0, vin, off),
+                         O.segmented_reduce(O.ADD, 0.0, np.abs(vin), off), L, what=case)
+    if dt == np.float32:
+        g = rng.uniform(-1, 1, len(L)).astype(np.float32)
+        gv = torch.full((nv + 1,), 5.0, device=DEV)
+        abi.mx_segmented_sum_adjoint_f32(dev(g), toff, gv[1:])      # misaligned destination
+        assert np.array_equal(host(gv[1:]), O.segmented_sum_adjoint(g, off).astype(np.float32))
+        gv2 = torch.empty(nv, device=DEV)
+        abi.mx_segmented_sum_adjoint_f32(dev(g), toff, gv2)         # aligned destination
+        assert np.array_equal(host(gv2), O.segmented_sum_adjoint(g, off).astype(np.float32))
+
+
+def test_segmented_all_rows_empty_and_single_chunk():
+    """No values at all (every row gives ne), and one chunk or less (no
+    workspace needed)."""
+    say("segmented empty / single chunk")
+    out = torch.full((5,), 9.0, device=DEV)
+    abi.mx_segmented_reduce(abi.MX_MAX, torch.empty(0, device=DEV), dev(np.zeros(6, np.int64)), -3.5, out, None)
+    assert np.array_equal(host(out), np.full(5, -3.5, np.float32))
+    for L in ([4096], [1, 4094, 1], [0, 4096, 0], [5, 0, 7]):
+        L = np.array(L, np.int64)
+        off = O.offsets_from_lengths(L)
+        v = np.random.default_rng(1).integers(-9, 10, int(off[-1])).astype(np.int32)
+        out = torch.empty(len(L), dtype=torch.int64, device=DEV)
+        abi.mx_segmented_reduce(abi.MX_ADD, dev(v), dev(off), 0, out, None)
+        assert np.array_equal(host(out), O.segmented_reduce(O.ADD, 0, v, off)), L
+
+
+def test_segmented_graph_replay():
+    """The chunked reduce and broadcast captured in a HIP graph: every replay
+    (with eager work between them) equals the eager result bit for bit."""
+    say("segmented graph")
+    L, v, off = _ragged(20000, 5, lmax=6000, empty_rows=50)
+    tv, toff = dev(v), dev(off)
+    ws = torch.zeros(abi.mx_workspace_bytes(abi.MX_WS_SEGMENTED, v.size), dtype=torch.uint8, device=DEV)
+    out = torch.empty(len(L), device=DEV)
+    g = dev(np.random.default_rng(2).uniform(-1, 1, len(L)).astype(np.float32))
+    gv = torch.empty(v.size, device=DEV)
+    abi.mx_segmented_reduce(abi.MX_ADD, tv, toff, 0.0, out, ws)
+    abi.mx_segmented_sum_adjoint_f32(g, toff, gv)
+    ref = (host(out).copy(), host(gv).copy())
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        abi.mx_graph_begin(side)
+        abi.mx_segmented_reduce(abi.MX_ADD, tv, toff, 0.0, out, ws, stream=side)
+        abi.mx_segmented_sum_adjoint_f32(g, toff, gv, stream=side)
+        graph = abi.mx_graph_end(side)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        gv.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.launch(side)
+        side.synchronize()
+        assert host(out).tobytes() == ref[0].tobytes() and host(gv).tobytes() == ref[1].tobytes(), rep
+        abi.mx_segmented_reduce(abi.MX_ADD, tv, toff, 0.0, out, ws)  # eager work between replays
+        torch.cuda.synchronize()
+    abi.mx_graph_destroy(graph)
+
+
 def test_segmented_sum_adjoint_broadcast_exact():
     say("segmented adjoint")
     L, v, off = _ragged(4000, 3, lmax=2000, empty_rows=30)
@@ -372,15 +485,33 @@ def test_debug_mode_rejects_bad_offsets():
     abi.mx_set_debug(True)
     try:
         with pytest.raises(abi.MxError) as e:
-            abi.mx_segmented_reduce(abi.MX_ADD, vals, bad, 0.0, out)
+            abi.mx_segmented_reduce(abi.MX_ADD, vals, bad, 0.0, out, None)
         assert e.value.status == abi.MX_ERR_SHAPE
+        # offsets[nseg] must equal the number of values
+        with pytest.raises(abi.MxError) as e:
+            abi.mx_segmented_reduce(abi.MX_ADD, vals, dev(np.array([0, 3, 5, 8], dtype=np.int64)), 0.0, out, None)
+        assert e.value.status == abi.MX_ERR_SHAPE and "number of values" in str(e.value)
+        with pytest.raises(abi.MxError):
+            abi.mx_segmented_sum_adjoint_f32(dev(np.zeros(3, np.float32)), dev(np.array([0, 3, 5, 8], np.int64)),
+                                             torch.empty(9, device=DEV))
         with pytest.raises(abi.MxError):
             api.offsets_from_lengths(dev(np.array([3, -1, 2], dtype=np.int64)))
     finally:
         abi.mx_set_debug(False)
     # accelerate mode does not check: the call is accepted
-    abi.mx_segmented_reduce(abi.MX_ADD, vals, dev(np.array([0, 3, 5, 9], dtype=np.int64)), 0.0, out)
+    abi.mx_segmented_reduce(abi.MX_ADD, vals, dev(np.array([0, 3, 5, 9], dtype=np.int64)), 0.0, out, None)
     assert np.array_equal(host(out), np.zeros(3, dtype=np.float32))
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 4099, 4096 * 1024 + 7, 1 << 24])
+def test_stream_read_xor(n):
+    """The read-only ceiling kernel reads every word exactly once: its XOR
+    against numpy's."""
+    say("stream read", n)
+    w = np.random.default_rng(n).integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    x = torch.zeros(abi.MX_STREAM_READ_SLOTS, dtype=torch.int32, device=DEV)
+    abi.mx_stream_read(dev(w.view(np.int32)), x)
+    assert int(np.bitwise_xor.reduce(host(x).view(np.uint32))) == int(np.bitwise_xor.reduce(w))
 
 
 # ------------------------------------------------------------------ dense map-map-reduce
