@@ -357,6 +357,25 @@ mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_de
                               const int64_t *offsets_dev, int64_t nseg, const void *ne_host, void *out_dev,
                               void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mx_segmented_reduce without
+ * a workspace argument.  The split-row slots live in a 1 MiB device array
+ * built into the library, one copy per device, held until the process ends;
+ * its address is looked up once per device (in mx_init, else on the first
+ * call there).  No allocation of any kind happens in the call.  Accepts
+ * nvalues up to mx_segmented_noalloc_max_values() (about 59.6 M, for any
+ * dtype) and rejects larger inputs with MX_ERR_WORKSPACE.  Every call on one
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, two threads) race and must not be issued.  A small fill kernel
+ * clears the part of the array a call uses before its reduce, so two launches
+ * per call.  Results equal mx_segmented_reduce's bit for bit (same kernels,
+ * same chunks).  Other errors as mx_segmented_reduce. */
+mx_status mx_segmented_reduce_noalloc(mx_redop op, mx_dtype dtype, const void *values_dev, int64_t nvalues,
+                                      const int64_t *offsets_dev, int64_t nseg, const void *ne_host, void *out_dev,
+                                      hipStream_t stream);
+/* The largest nvalues mx_segmented_reduce_noalloc accepts. */
+int64_t mx_segmented_noalloc_max_values(void);
+
 /* Reference "plain" form of mx_segmented_reduce: one thread folds one row
  * sequentially, left to right from ne (no load balancing, uncoalesced, no
  * workspace).  Same contract otherwise. */

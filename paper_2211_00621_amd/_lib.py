@@ -43,6 +43,8 @@ SIGNATURES = {
     "mx_map2_reduce": (c_status, [c_enum, c_enum, c_enum, c_p, c_p, c_i64, c_p, c_p, c_p, c_size, c_p]),
     "mx_dot_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_p, c_p, c_p]),
     "mx_segmented_reduce": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_size, c_p]),
+    "mx_segmented_reduce_noalloc": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_i64, c_p, c_p, c_p]),
+    "mx_segmented_noalloc_max_values": (c_i64, []),
     "mx_segmented_reduce_plain": (c_status, [c_enum, c_enum, c_p, c_i64, c_p, c_i64, c_p, c_p, c_p]),
     "mx_segmented_sum_adjoint_f32": (c_status, [c_p, c_p, c_i64, c_p, c_i64, c_p]),
     "mx_reduce_adjoint_f32": (c_status, [c_enum, c_p, c_i64, c_p, c_p, c_p, c_p, c_size, c_p]),

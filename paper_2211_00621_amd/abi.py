@@ -244,6 +244,18 @@ def mx_segmented_reduce(op: int, values, offsets, ne, out, ws, stream=None) -> N
                                     _stream(stream)), "mx_segmented_reduce")
 
 
+def mx_segmented_reduce_noalloc(op: int, values, offsets, ne, out, stream=None) -> None:
+    """mx_segmented_reduce with the library's built-in scratch instead of a workspace (no allocation)."""
+    nb = _acc_scalar(ne, values.dtype)
+    _check(_L().mx_segmented_reduce_noalloc(int(op), _dtype(values), _dptr(values), values.numel(), _dptr(offsets),
+                                            offsets.numel() - 1, ctypes.byref(nb), _dptr(out), _stream(stream)),
+           "mx_segmented_reduce_noalloc")
+
+
+def mx_segmented_noalloc_max_values() -> int:
+    return int(_L().mx_segmented_noalloc_max_values())
+
+
 def mx_segmented_reduce_plain(op: int, values, offsets, ne, out, stream=None) -> None:
     nb = _acc_scalar(ne, values.dtype)
     _check(_L().mx_segmented_reduce_plain(int(op), _dtype(values), _dptr(values), values.numel(), _dptr(offsets),

@@ -45,6 +45,8 @@ int segmented_rows_per_block(int64_t nseg, const DeviceInfo *d);
 mx_status check_offsets_debug(const char *who, const int64_t *off, int64_t nseg, hipStream_t s);
 // bytes of the chunked segmented reduce's workspace for nval values (any dtype)
 size_t segmented_ws_bytes(int64_t nval);
+// device address of the no-allocation variant's scratch array (per device)
+mx_status segmented_scratch(void **out);
 // exclusive scan of int64 lengths into nseg + 1 offsets (workspace kind MX_WS_SCAN)
 mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, void *ws, size_t ws_bytes,
                              hipStream_t s);

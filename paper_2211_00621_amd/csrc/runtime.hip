@@ -113,7 +113,9 @@ extern "C" {
 mx_status mx_init(int device) {
     MX_TRY_HIP(hipSetDevice(device));
     const DeviceInfo *d;
-    return device_info(&d);
+    if (mx_status st = device_info(&d)) return st;
+    void *scr = nullptr;
+    return segmented_scratch(&scr);  // the no-allocation entry point's array on this device
 }
 
 const char *mx_last_error(void) { return g_err; }

@@ -2,6 +2,7 @@
 // nested map (reduce) over rows, its reverse (broadcast), the lengths ->
 // offsets scan of marshaling, offset composition for `map flatten`, and the
 // debug-mode validation of offsets (Appendix "Dynamic Assumptions").
+#include <algorithm>
 #include <mutex>
 
 #include "mx_internal.h"
@@ -472,6 +473,20 @@ __global__ void __launch_bounds__(NT) k_seg_chunk(const typename DT<D>::In *__re
     }
 }
 
+// ---- the no-allocation variant's scratch: the split-row slots of
+// mx_segmented_reduce_noalloc live in this fixed array (one copy per device,
+// zero at load).  Host code never passes the array's name to a kernel: it
+// takes the device address from hipGetSymbolAddress once per device.
+constexpr size_t kScratchBytes = (size_t)1 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Zero-fills n 32-bit words (a kernel rather than a memset node, so that the
+// call can sit in a captured graph).
+__global__ void __launch_bounds__(NT) k_zero_words(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
 // Plain: one thread folds one row left to right.
 template <mx_dtype D, int OP>
 __global__ void __launch_bounds__(NT) k_seg_thread(const typename DT<D>::In *__restrict__ values,
@@ -795,7 +810,27 @@ mx_status segmented(const char *who, bool plain, int op, mx_dtype dtype, const v
     return MX_ERR_DTYPE;
 }
 
+std::mutex g_scratch_mu;
+void *g_scratch_addr[64] = {};
+
 }  // namespace
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current).
+mx_status segmented_scratch(void **out) {
+    int dev = 0;
+    MX_TRY_HIP(hipGetDevice(&dev));
+    MX_REQUIRE(dev >= 0 && dev < 64, MX_ERR_INVALID, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        MX_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        MX_REQUIRE(p != nullptr, MX_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return MX_OK;
+}
 
 // Shared with the generated map-body kernels: rows per block of a block-span
 // reduce, and the debug-mode check of an offsets array.
@@ -860,6 +895,40 @@ mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_de
                               void *ws, size_t ws_bytes, hipStream_t stream) {
     return segmented("mx_segmented_reduce", false, op, dtype, values_dev, nvalues, offsets_dev, nseg, ne_host,
                      out_dev, ws, ws_bytes, stream);
+}
+
+mx_status mx_segmented_reduce_noalloc(mx_redop op, mx_dtype dtype, const void *values_dev, int64_t nvalues,
+                                      const int64_t *offsets_dev, int64_t nseg, const void *ne_host, void *out_dev,
+                                      hipStream_t stream) {
+    const char *who = "mx_segmented_reduce_noalloc";
+    MX_REQUIRE(nvalues >= 0, MX_ERR_SHAPE, "%s: nvalues < 0", who);
+    const size_t need = seg_ws_bytes(nvalues);
+    MX_REQUIRE(need <= kScratchBytes, MX_ERR_WORKSPACE,
+               "%s: %lld values need %zu bytes of split-row slots, more than the %zu-byte built-in scratch "
+               "(at most %lld values); use mx_segmented_reduce with a workspace",
+               who, (long long)nvalues, need, kScratchBytes, (long long)mx_segmented_noalloc_max_values());
+    void *ws = nullptr;
+    if (mx_status st = segmented_scratch(&ws)) return st;
+    if (nseg > 0 && nvalues > 0) {
+        // the kernels leave the slots zero; clear the part this call uses all
+        // the same, in case an earlier call on this device did not finish
+        const int64_t words = (int64_t)(need / 4);
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>(ceil_div(words, NT), 1024)), dim3(NT), 0,
+                           stream, (uint32_t *)ws, words);
+        if (mx_status st = last_launch(who)) return st;
+    }
+    return segmented(who, false, op, dtype, values_dev, nvalues, offsets_dev, nseg, ne_host, out_dev, ws,
+                     kScratchBytes, stream);
+}
+
+int64_t mx_segmented_noalloc_max_values(void) {
+    // the largest n with seg_ws_bytes(n) <= kScratchBytes (whole 2048-element chunks)
+    int64_t lo = 0, hi = (int64_t)kScratchBytes * 2048;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (seg_ws_bytes(mid) <= kScratchBytes) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *values_dev, int64_t nvalues,
