@@ -280,16 +280,40 @@ def bench_nested(args):
         for f in fused_parts:
             f()
 
+    # The same step with the ragged half (offsets, row sums, broadcast;
+    # HBM-bound) on a second stream beside the three matrix products
+    # (MFMA-bound): the halves share no data.  Measured slower than one
+    # stream (the products run one 128 x 128 tile per CU, and ragged blocks
+    # on the same CUs stretch the tiles they share a CU with), so it is
+    # reported beside the step, not as the step.  Default priority on both.
+    rag = torch.cuda.Stream()
+    ev_fork, ev_join = torch.cuda.Event(), torch.cuda.Event()
+
+    def two_stream_step():
+        cur = torch.cuda.current_stream()
+        ev_fork.record(cur)
+        rag.wait_event(ev_fork)
+        abi.mx_lengths_to_offsets(d["tL"], offsets, ws, stream=rag)
+        abi.mx_segmented_reduce(abi.MX_ADD, d["tv"], offsets, 0.0, rows, wseg, stream=rag)
+        abi.mx_segmented_sum_adjoint_f32(d["tg"], offsets, gvals, stream=rag)
+        ev_join.record(rag)
+        abi.mx_map_map_reduce_f32(0, 0, d["tA"], d["tB"], C, stream=cur)
+        abi.mx_map_map_reduce_f32(0, 1, d["tG"], d["tB"], gA, stream=cur)
+        abi.mx_map_map_reduce_f32(1, 0, d["tA"], d["tG"], gB, stream=cur)
+        cur.wait_event(ev_join)
+
     def plain_step():
         for f in plain_parts:
             f()
 
     log("nested: fused steps")
     ms = timed_on(torch.cuda.current_stream(), step, args.steps, args.warmup)
+    two_ms = timed_on(torch.cuda.current_stream(), two_stream_step, args.steps, args.warmup)
     side = torch.cuda.Stream()
     graph = capture(side, step)
     graph_ms = timed_on(side, lambda: graph.launch(side), args.steps, args.warmup)
-    log(f"nested: fused {ms:.3f} ms/step (eager), {graph_ms:.3f} ms/step (HIP graph replay)")
+    log(f"nested: fused {ms:.3f} ms/step (eager), {graph_ms:.3f} ms/step (HIP graph replay), "
+        f"{two_ms:.3f} ms/step (ragged half on a second stream)")
     reps = max(50, args.steps)
     # every part: per-launch durations (events around each launch), and the
     # average over back-to-back launches (no marker between them)
@@ -307,6 +331,12 @@ def bench_nested(args):
             d["tg"], offsets, gv)), reps=reps),
     }
     del vcopies, gcopies
+    # context: the vendor library's FP32 product of the same shape (torch.matmul
+    # on the ROCm BLAS stack), per-launch events as for the parts
+    torch.backends.cuda.matmul.allow_tf32 = False
+    C_lib = torch.empty_like(C)
+    lib_mm = launch_stats(lambda: torch.matmul(d["tA"], d["tB"], out=C_lib), reps=reps)
+    del C_lib
     ceiling = hbm_read_ceiling(dev, 4 * nval, reps=reps)
     log(f"nested: read-only ceiling {ceiling['GB/s']} GB/s over {ceiling['bytes'] / 1e6:.1f} MB")
     psteps = max(1, min(args.steps, 3))
@@ -370,13 +400,17 @@ def bench_nested(args):
                 "frac_hbm": round(gbs(bytes_["row_sums"] + bytes_["row_sums_adjoint"], hbm_ms) / HBM_PEAK_GBS, 4),
                 "read_ceiling": ceiling},
         "parts": detail,
+        "library_product": {"what": "torch.matmul FP32 2048^3 (ROCm BLAS), context only", **summary_us(lib_mm),
+                            "TFLOP/s": round(flops / (float(lib_mm.mean()) * 1e-3) / 1e12, 2)},
         "plain": {"ms_per_step": pms, "value": elems / (pms * 1e-3),
-                  "fused_speedup": round(pms / ms, 2)},
+                  "fused_speedup": round(pms / ms, 2), "what": "the six plain kernels on one stream, eager"},
         "graph_ms_per_step": graph_ms,
-        "timing": "value and ms_per_step: K eager steps between two events (graph_ms_per_step: the same step "
-                  "replayed from a HIP graph); parts: per-launch event pairs over >= 50 launches (mean, median, "
-                  "p10, p90) and the back-to-back average (b2b_us); cold: the ragged kernels over four 129 MB "
-                  "copies in turn",
+        "two_streams_ms_per_step": two_ms,
+        "timing": "value and ms_per_step: K eager steps between two events on the launch stream "
+                  "(graph_ms_per_step: the same step replayed from a HIP graph; two_streams_ms_per_step: the "
+                  "ragged half on a second stream beside the products); parts: per-launch event pairs over "
+                  ">= 50 launches (mean, median, p10, p90) and the back-to-back average (b2b_us); cold: the "
+                  "ragged kernels over four 129 MB copies in turn",
     }
     line["marshal"] = marshal_rates(d, dev)
     if not args.no_cpu_baseline:

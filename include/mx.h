@@ -343,11 +343,15 @@ mx_status mx_reduce_adjoint_f32(mx_redop op, const float *x_dev, int64_t n, cons
  * non-decreasing, offsets[0] = 0, offsets[nseg] = nvalues (all three
  * validated in debug mode).  Empty rows give ne.  out: device, accumulator
  * type, nseg values.
- * Work is split by value count: the values are cut into 16 KB chunks, one
- * block each, so the time does not depend on how the lengths are spread.  A
- * row that spans chunks is folded per chunk and the chunk parts are combined
- * in chunk order, so results are deterministic (for floating point they may
- * differ in the last bits from mx_segmented_reduce_plain's left fold).
+ * Two schedules, chosen from nseg and nvalues alone: with at least 32 rows
+ * per compute unit and at most 16384 values per row on average, blocks take
+ * up to 8 consecutive rows each and stream their span (row-span path);
+ * otherwise the values are split evenly: each block streams a range of 16 KB
+ * chunks, owns the rows that start in it, and rows that run more than a chunk
+ * past its range are split across blocks, whose parts are combined in order
+ * through the workspace.  Either way the fold order depends only on the
+ * offsets, so results repeat bit for bit (for floating point they may differ
+ * in the last bits from mx_segmented_reduce_plain's left fold).
  * Workspace: mx_workspace_bytes(MX_WS_SEGMENTED, nvalues, 0) bytes, 256-byte
  * aligned, zero-filled before first use (the call leaves it zero again); NULL
  * is accepted when nvalues <= 2048.  Calls that share a workspace must not
@@ -369,7 +373,7 @@ mx_status mx_segmented_reduce(mx_redop op, mx_dtype dtype, const void *values_de
  * streams, two threads) race and must not be issued.  A small fill kernel
  * clears the part of the array a call uses before its reduce, so two launches
  * per call.  Results equal mx_segmented_reduce's bit for bit (same kernels,
- * same chunks).  Other errors as mx_segmented_reduce. */
+ * same schedule).  Other errors as mx_segmented_reduce. */
 mx_status mx_segmented_reduce_noalloc(mx_redop op, mx_dtype dtype, const void *values_dev, int64_t nvalues,
                                       const int64_t *offsets_dev, int64_t nseg, const void *ne_host, void *out_dev,
                                       hipStream_t stream);
@@ -386,7 +390,8 @@ mx_status mx_segmented_reduce_plain(mx_redop op, mx_dtype dtype, const void *val
 /* Reverse of the row sums out[r] = sum(row r) (F32): every element of row r
  * receives gout[r]: gvalues[e] = gout[r] for offsets[r] <= e < offsets[r+1].
  * gvalues: device float[nvalues], offsets[nseg] = nvalues (debug mode checks
- * it).  Written in 16 KB chunks, one block each, like mx_segmented_reduce.
+ * it).  Same two schedules as mx_segmented_reduce (no row needs a second
+ * block here: every block writes only its own span or range).
  * Errors: MX_ERR_INVALID, MX_ERR_SHAPE. */
 mx_status mx_segmented_sum_adjoint_f32(const float *gout_dev, const int64_t *offsets_dev, int64_t nseg,
                                        float *gvalues_dev, int64_t nvalues, hipStream_t stream);

@@ -419,6 +419,66 @@ def test_segmented_chunk_boundaries(case, dt):
         assert np.array_equal(host(gv2), O.segmented_sum_adjoint(g, off).astype(np.float32))
 
 
+def _span_case(case):
+    """Row layouts for the row-span path (enough rows, short on average)."""
+    rng = np.random.default_rng(11)
+    if case == "log_uniform_empty":   # log-uniform up to 3000, every 13th row empty
+        L = W.ragged_lengths(20000, seed=4, lmax=3000)
+        L[::13] = 0
+    elif case == "few_giant_rows":    # mostly short rows, ten of 200 000 values
+        L = rng.integers(0, 40, 12000)
+        L[rng.choice(12000, 10, replace=False)] = 200000
+    else:                             # runs of empty rows between blocks of long ones
+        L = np.zeros(16384, dtype=np.int64)
+        L[::3] = rng.integers(1000, 9000, len(L[::3]))
+    return np.asarray(L, dtype=np.int64)
+
+
+@pytest.mark.parametrize("case", ["log_uniform_empty", "few_giant_rows", "empty_runs"])
+@pytest.mark.parametrize("dt", [np.float32, np.float64, np.int32, np.int64])
+def test_segmented_row_span_path(case, dt):
+    """The row-span kernels (many rows of ordinary mean length): every row
+    against the oracle, integers bit-exact for every operator, aligned and
+    misaligned value views, the broadcast into aligned and misaligned
+    destinations."""
+    say("segmented row-span", case, np.dtype(dt).name)
+    L = _span_case(case)
+    off = O.offsets_from_lengths(L)
+    nv = int(off[-1])
+    rng = np.random.default_rng(5)
+    toff = dev(off)
+    ws = torch.zeros(abi.mx_workspace_bytes(abi.MX_WS_SEGMENTED, nv), dtype=torch.uint8, device=DEV)
+    integer = np.issubdtype(dt, np.integer)
+    ops = [abi.MX_ADD, abi.MX_MIN, abi.MX_MAX, abi.MX_MUL] if integer else [abi.MX_ADD]
+    for op in ops:
+        if op == abi.MX_MUL:
+            v = rng.integers(-2, 3, nv).astype(dt)
+        elif integer:
+            v = rng.integers(-10 ** 6, 10 ** 6, nv).astype(dt)
+        else:
+            v = rng.uniform(-1, 1, nv).astype(dt)
+        ne = {abi.MX_ADD: 0, abi.MX_MUL: 1, abi.MX_MIN: 2 ** 63 - 1, abi.MX_MAX: -2 ** 63}[op]
+        for shift in (0, 1):
+            full = dev(np.concatenate([np.zeros(shift, dtype=dt), v]))
+            out = torch.empty(len(L), dtype=api.ACC_OF[full.dtype], device=DEV)
+            abi.mx_segmented_reduce(op, full[shift:], toff, ne if integer else 0.0, out, ws)
+            got = host(out)
+            if integer:
+                assert np.array_equal(got, O.segmented_reduce(op, ne, v, off)), (op, shift)
+            else:
+                check_vector(got, O.segmented_reduce(O.ADD, 0.0, v, off),
+                             O.segmented_reduce(O.ADD, 0.0, np.abs(v), off), L, what=f"{case} shift {shift}")
+    if dt == np.float32:
+        g = rng.uniform(-1, 1, len(L)).astype(np.float32)
+        ref = O.segmented_sum_adjoint(g, off).astype(np.float32)
+        gv = torch.full((nv + 1,), 5.0, device=DEV)
+        abi.mx_segmented_sum_adjoint_f32(dev(g), toff, gv[1:])
+        assert np.array_equal(host(gv[1:]), ref) and host(gv[:1])[0] == 5.0
+        gv2 = torch.empty(nv, device=DEV)
+        abi.mx_segmented_sum_adjoint_f32(dev(g), toff, gv2)
+        assert np.array_equal(host(gv2), ref)
+
+
 def test_segmented_all_rows_empty_and_single_chunk():
     """No values at all (every row gives ne), and one chunk or less (no
     workspace needed)."""
