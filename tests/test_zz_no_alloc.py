@@ -33,9 +33,10 @@ def host(t):
 
 def test_noalloc_matches_workspace_entry_point_twice():
     abi.mx_init(0)
-    # the full nested configuration first, then a smaller ragged input with
-    # long rows and empty ones: the second call reuses the array the first left
-    for nseg, seed, lmax, empties in ((65536, 0, 4096, 0), (3000, 1, 9000, 40)):
+    # a ragged input with rows split across blocks (their parts go through the
+    # array), then a smaller one (the second call reuses the array the first
+    # left), then the full nested configuration (row-span schedule)
+    for nseg, seed, lmax, empties in ((6000, 2, 30000, 10), (3000, 1, 9000, 40), (65536, 0, 4096, 0)):
         say("noalloc", nseg, seed)
         L, v = W.ragged_f32(nseg, seed, lmax, empty_rows=empties)
         off = O.offsets_from_lengths(L)
