@@ -7,20 +7,27 @@
 //   c'_j = sum_j / count_j, or c_j when count_j = 0
 //
 // Assignment on the matrix cores: argmin_j dist(x, c_j) = argmin_j f_j with
-// f_j = |c_j|^2 - 2 x.c_j, 64 points x 64 centroids per wave on
-// v_mfma_f32_16x16x4_f32 (X straight from HBM into registers, -2C in LDS, the
-// accumulators starting at the FP32 |c_j|^2).  The FP32 f~_j carry their
-// candidate's slot in the four low mantissa bits (a change of at most 15 ulp,
-// under 2^-19 |f~_j|).  With u = 2^-24 these values p_j satisfy |p_j - f_j| <=
-// E = (2d + 40) u (|x| + max_j |c_j|)^2: the norm (d roundings on |c_j|^2),
-// the d products and d additions of the accumulation (each term at most
-// (|x| + |c_j|)^2 in total), and 32 u for the slot bits.  When the two
-// smallest p differ by more than 2E the smallest is the exact, unique
-// minimiser and also the binary64 oracle's.  Otherwise (a few points in a
-// million on Gaussian blobs) the lane recomputes every distance in binary64 in
-// the oracle's operation order -- subtract, square, add, no fused
-// multiply-add -- and takes the lexicographic minimum, so labels are
-// bit-exact in all cases.
+// f_j = |c_j|^2 - 2 x.c_j, 64 points x 64 centroids per wave (X straight from
+// HBM into registers, -2C in LDS, the accumulators starting at the FP32
+// |c_j|^2).  The products run in bfloat16 on v_mfma_f32_16x16x32_bf16, each
+// FP32 operand split into a high and a middle part (v = v_h + v_m + v_l, each
+// part the nearest bfloat16 to what is left: |v - v_h| <= 2^-8 |v|, |v_l| <=
+// 2^-16 |v|): a.x is taken as a_h x_h + a_h x_m + a_m x_h, three 16x16x32
+// products per tile against eight FP32 16x16x4 ones, each product exact in
+// FP32.  The dropped terms (a_m x_m, a_h x_l, a_l x_h and smaller) are at most
+// 3.02 2^-16 |a_t||x_t| per dimension, so at most 6.03 2^-16 |c||x| in all (a
+// = -2c, Cauchy-Schwarz); the 97 FP32 additions of the three accumulations
+// (2 u each, u = 2^-24, allowing for the matrix core's own rounding) at most
+// 0.76 2^-16 (|c|^2 + 2|c||x|); the FP32 |c|^2 0.13 2^-16 |c|^2; the
+// candidate's slot, carried in the four low mantissa bits (at most 15 ulp),
+// 0.12 2^-16 of the value.  So the computed values p_j satisfy |p_j - f_j| <=
+// E = 2^-13 (|x| + max_j |c_j|)^2, twice the 4.03 2^-16 these add up to.
+// When the two smallest p differ by more than 2E the smallest is the exact,
+// unique minimiser and also the binary64 oracle's.  Otherwise (on the blob
+// data, a few thousand points per million while several centroids share a
+// blob) the lane recomputes every distance in binary64 in the oracle's
+// operation order -- subtract, square, add, no fused multiply-add -- and
+// takes the lexicographic minimum, so labels are bit-exact in all cases.
 //
 // Persistent waves: a fixed grid of at most kMaxBlocks blocks, each wave
 // walking its own sequence of 64-point chunks and loading the next chunk's
@@ -53,6 +60,18 @@ constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
 constexpr int kScrFloats = kPtsWave * 4 * 4 + kPtsWave;  // per wave: publication slots, label and rank
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// v = hi + mid + (a remainder of at most 2^-16 |v|), hi and mid bfloat16
+__device__ __forceinline__ void split_bf16(const float4 &u0, const float4 &u1, bf16x8 &hi, bf16x8 &mid) {
+    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)v[e];
+        hi[e] = h;
+        mid[e] = (__bf16)(v[e] - (float)h);
+    }
+}
 
 // binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
 __device__ __forceinline__ double dist64(const float *__restrict__ x, const float *c, int d) {
@@ -77,6 +96,24 @@ __device__ __forceinline__ double dist64_m2(const float *x, const float *m2) {
         for (int e = 0; e < 4; ++e) {
             const double diff = sub_rn((double)vget<float4, float>(xv, e), -0.5 * (double)vget<float4, float>(cv, e));
             acc = add_rn(acc, mul_rn(diff, diff));
+        }
+    }
+    return acc;
+}
+
+// FP32 direct form sum (x_t - c_t)^2 over an LDS row holding -2c (c = -m2 / 2
+// exactly); past d both rows hold zeros, which add exact zeros.
+template <int DP>
+__device__ __forceinline__ float dist32_m2(const float *x, const float *m2) {
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < DP; t += 4) {
+        const float4 xv = *reinterpret_cast<const float4 *>(x + t);
+        const float4 cv = *reinterpret_cast<const float4 *>(m2 + t);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float diff = vget<float4, float>(xv, e) + 0.5f * vget<float4, float>(cv, e);
+            acc += diff * diff;
         }
     }
     return acc;
@@ -205,7 +242,21 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     }
     __syncthreads();
     const float cmax = cmax_s;
-    const float eps_factor = 2.0f * (float)(2 * d + 40) * 5.9604645e-8f;  // 2 (2d + 40) 2^-24
+    const float eps_factor = 2.0f * 1.220703125e-4f;  // 2E / (|x| + max|c|)^2 = 2 2^-13
+    // A operands (-2c, rows ci*16 + l16 of centroid chunk cc, dimensions
+    // kc*32 + 8g .. +7) as bfloat16 parts: held in registers for the whole
+    // walk when there is one centroid chunk, else split per chunk
+    auto a_ops = [&](int cc, int ci, int kc, bf16x8 &ah, bf16x8 &am) {
+        const float *q = Cs + (cc * 64 + ci * 16 + l16) * LDC + kc * 32 + 8 * g;
+        split_bf16(*reinterpret_cast<const float4 *>(q), *reinterpret_cast<const float4 *>(q + 4), ah, am);
+    };
+    bf16x8 areg_h[KP == 64 ? 4 : 1][DP / 32], areg_m[KP == 64 ? 4 : 1][DP / 32];
+    if constexpr (KP == 64) {
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+            for (int kc = 0; kc < DP / 32; ++kc) a_ops(0, ci, kc, areg_h[ci][kc], areg_m[ci][kc]);
+    }
 
     float *ws = sums_all + wave * k * ldd;
     int *wc = counts_all + wave * k;
@@ -261,24 +312,30 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             }
 #pragma unroll
             for (int kc = 0; kc < DP / 32; ++kc) {
-                float4 cb[4][2];
+                // lane (g, l16) holds dimensions kc*32 + 8g .. +7 of point
+                // pi*16 + l16 (B operand) and of centroid row ci*16 + l16 (A)
+                bf16x8 bh[4], bm[4];
+#pragma unroll
+                for (int pi = 0; pi < 4; ++pi) split_bf16(xa[pi][kc][0], xa[pi][kc][1], bh[pi], bm[pi]);
 #pragma unroll
                 for (int ci = 0; ci < 4; ++ci) {
-                    const float *q = Cs + (cc * 64 + ci * 16 + l16) * LDC + kc * 32 + 8 * g;
-                    cb[ci][0] = *reinterpret_cast<const float4 *>(q);
-                    cb[ci][1] = *reinterpret_cast<const float4 *>(q + 4);
-                }
-#pragma unroll
-                for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                    for (int ci = 0; ci < 4; ++ci) {
-                        const float av = vget<float4, float>(cb[ci][kk >> 2], kk & 3);
-#pragma unroll
-                        for (int pi = 0; pi < 4; ++pi) {
-                            const float bv = vget<float4, float>(xa[pi][kc][kk >> 2], kk & 3);
-                            acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ci][pi], 0, 0, 0);
-                        }
+                    bf16x8 ah, am;
+                    if constexpr (KP == 64) {
+                        ah = areg_h[ci][kc];
+                        am = areg_m[ci][kc];
+                    } else {
+                        a_ops(cc, ci, kc, ah, am);
                     }
+#pragma unroll
+                    for (int pi = 0; pi < 4; ++pi)
+                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[pi], acc[ci][pi], 0, 0, 0);
+#pragma unroll
+                    for (int pi = 0; pi < 4; ++pi)
+                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[pi], acc[ci][pi], 0, 0, 0);
+#pragma unroll
+                    for (int pi = 0; pi < 4; ++pi)
+                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[pi], acc[ci][pi], 0, 0, 0);
+                }
             }
 #pragma unroll
             for (int pi = 0; pi < 4; ++pi) {
@@ -335,18 +392,95 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 label = mj;
             }
             uint64_t todo = __ballot(!certified);
-            if (todo && a.fallbacks && lane == 0) atomicAdd(a.fallbacks, (unsigned long long)__popcll(todo));
-            // the point is staged in this wave's publication slots (read
-            // above): one coalesced load, then LDS broadcasts for every
-            // centroid lane
-            float *xs = reinterpret_cast<float *>(pub);
+            // Uncertified points, four at a time: the points' coordinates go
+            // from the registers that hold them (four lanes each) to this
+            // wave's publication slots (read above); row s of 16 lanes takes
+            // point s, lane l of it centroids j = l, l + 16, ...: the FP32
+            // direct form sum (x_t - c_t)^2 (c_t = -m2_t / 2 exactly), within
+            // (d + 2) u (1 + u)^(d+2) of the exact value, with j in its eight
+            // low bits (a change of at most 255 ulp, under 2^-15 of it; as
+            // bits, non-negative floats order like unsigned integers, so no
+            // denormal flushing can drop the index).  With E = 2 (d + 3 + 512)
+            // u times the second smallest, a gap over 2E makes the smallest
+            // the exact, unique minimiser.  The rest go to binary64 in the
+            // oracle's order.
+            float *xs = reinterpret_cast<float *>(pub);  // [4][DP]
+            uint64_t todo64 = 0;
             while (todo) {
-                const int q = __builtin_ctzll(todo);  // wave-uniform
-                todo &= todo - 1;
+                int qs[4];
+                int nq = 0;
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    qs[s2] = todo ? __builtin_ctzll(todo) : -1;  // wave-uniform
+                    if (todo) {
+                        todo &= todo - 1;
+                        ++nq;
+                    }
+                }
                 wave_sync();
-                if (lane < DP) xs[lane] = lane < d ? a.X[(p0 + q) * d + lane] : 0.f;
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    const int q = qs[s2];
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+                        if (q >= 0 && mi == (q >> 4) && l16 == (q & 15))
+#pragma unroll
+                            for (int kc = 0; kc < DP / 32; ++kc) {
+                                *reinterpret_cast<float4 *>(xs + s2 * DP + kc * 32 + 8 * g) = xa[mi][kc][0];
+                                *reinterpret_cast<float4 *>(xs + s2 * DP + kc * 32 + 8 * g + 4) = xa[mi][kc][1];
+                            }
+                }
+                wave_sync();
+                unsigned u1 = 0xffffffffu, u2 = 0xffffffffu;
+                if (g < nq && cmax < INFINITY) {
+                    for (int j = l16; j < k; j += 16) {
+                        const unsigned v = (__float_as_uint(dist32_m2<DP>(xs + g * DP, Cs + j * LDC)) & ~255u) | (unsigned)j;
+                        u2 = min(u2, max(u1, v));
+                        u1 = min(u1, v);
+                    }
+                }
+                // the two smallest over the 16 lanes of each row
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    unsigned o1, o2;
+                    if (st == 0) { o1 = dpp_move<0xB1, 0xF>(u1, u1); o2 = dpp_move<0xB1, 0xF>(u2, u2); }
+                    else if (st == 1) { o1 = dpp_move<0x4E, 0xF>(u1, u1); o2 = dpp_move<0x4E, 0xF>(u2, u2); }
+                    else if (st == 2) { o1 = dpp_move<0x141, 0xF>(u1, u1); o2 = dpp_move<0x141, 0xF>(u2, u2); }
+                    else { o1 = dpp_move<0x140, 0xF>(u1, u1); o2 = dpp_move<0x140, 0xF>(u2, u2); }
+                    u2 = min(min(u2, o2), max(u1, o1));
+                    u1 = min(u1, o1);
+                }
+                const float f1 = __uint_as_float(u1 & ~255u), f2 = __uint_as_float(u2 & ~255u);
+                const float E2 = 2.0f * (float)(d + 3 + 512) * 5.9604645e-8f * f2;
+                const bool ok = cmax < INFINITY && f2 - f1 > 2.0f * E2;
+                // every lane of row s holds point s's result
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    if (qs[s2] < 0) break;
+                    const int okq = __builtin_amdgcn_readlane((int)ok, 16 * s2);
+                    const int jq = __builtin_amdgcn_readlane((int)(u1 & 255u), 16 * s2);
+                    if (okq) {
+                        if (lane == qs[s2]) label = jq;
+                    } else {
+                        todo64 |= 1ull << qs[s2];
+                    }
+                }
+            }
+            while (todo64) {
+                const int q = __builtin_ctzll(todo64);  // wave-uniform
+                todo64 &= todo64 - 1;
+                wave_sync();
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+                    if (mi == (q >> 4) && l16 == (q & 15))
+#pragma unroll
+                        for (int kc = 0; kc < DP / 32; ++kc) {
+                            *reinterpret_cast<float4 *>(xs + kc * 32 + 8 * g) = xa[mi][kc][0];
+                            *reinterpret_cast<float4 *>(xs + kc * 32 + 8 * g + 4) = xa[mi][kc][1];
+                        }
                 wave_sync();
                 const float *x = xs;
+                if (a.fallbacks && lane == 0) atomicAdd(a.fallbacks, 1ull);
                 double bd = INFINITY;
                 int bj = 0x7fffffff;
                 for (int j = lane; j < k; j += kWave) {
