@@ -800,9 +800,16 @@ def bench_kmeans(args):
         "config": {"workload": "k-means: 2^20 float32 points in d=32 from 64 Gaussian blobs, k=64, 10 steps of "
                                "map(argmin reduce)+reduce-by-key, then SSE and its gradient wrt the points",
                    "n": n, "d": d, "k": k, "iterations": iters},
-        "roofline": {"bound": "mfma", "kernel": "k_kmeans_fused<32,64>", "achieved": round(ach, 2),
-                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_PEAK_TFLOPS, 4),
-                     "traffic": None},
+        # the step's x.c products run as three bfloat16 products each (high and
+        # middle parts), 3 x 2nkd flops at 2.5 PFLOP/s: 5 us, below the 16 us
+        # its 132 MB of HBM traffic need at 8 TB/s, so HBM bounds it
+        "roofline": {"bound": "hbm", "kernel": "k_kmeans_fused<32,64>",
+                     "achieved": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]), 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]) / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "fp32_equivalent": {"TFLOP/s": round(ach, 2), "of_fp32_mfma_peak": round(ach / FP32_MFMA_PEAK_TFLOPS, 4),
+                                         "what": "2nkd flops of the x.c products over the step's time, against the "
+                                                 "FP32 matrix peak (the former FP32 16x16x4 kernel's bound)"}},
         "parts": {"kmeans_step_us": round(parts["kmeans_step"] * 1e3, 1),
                   "kmeans_step_GB/s": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]), 1),
                   "sse_grad_us": round(parts["sse_grad"] * 1e3, 1),
