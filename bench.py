@@ -56,11 +56,12 @@ TRAFFIC = {
     # k_gemm_mfma<128,128,4,2,0,0>, 2048^3: 100.78 MB fetched (A and B panels re-read by each XCD that
     # needs them, plus two clamped slices past the end of K per tile; 33.6 MB is the algorithmic
     # minimum) + 16.78 MB written (C)
-    "gemm_nn": {"file": "gemm.hip", "bytes": 117551940,
-                "source": "e3de6e32d73e713b7af21202564fbc60d4736cd93458aa1021a82736a18a937c"},
-    # k_seg_span, 65536 rows / 32.1 M values: 130.46 MB fetched + 0.26 MB written (1.01x algorithmic)
-    "seg_span": {"file": "segmented.hip", "bytes": 130706799,
-                 "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
+    "gemm_nn": {"file": "gemm.hip", "bytes": 117557162,
+                "source": "cb5d31e73fdf1805aaa927c53045f40347d4e271b1beaf6ca36e09725257686b"},
+    # k_seg_span (row-span path), 65536 rows / 32.1 M values: 131.11 MB fetched + 0.26 MB
+    # written (1.02x algorithmic: 129.19 MB)
+    "seg_span": {"file": "segmented.hip", "bytes": 131372884,
+                 "source": "41a385e9b42d3423d8b8b71015ef1b28e3ec22adc775890c3decf79c03a8516c"},
     # mx_xvjp (generated from expr.hip) for exp(-(a-b)^2)*0.5 + a*b over 2^26 float32 pairs:
     # 536.88 MB fetched + 536.80 MB written (1.00x algorithmic)
     "expr_vjp": {"file": "expr.hip", "bytes": 1073676893,
@@ -73,9 +74,9 @@ TRAFFIC = {
     # below and above it) + 67.10 MB written
     "stencil": {"file": "parboil.hip", "bytes": 140264894,
                 "source": "43811f5900aa96af3dc0bca90ae62f896a5a0aac06bc3e30816ec5f7f6f67ece"},
-    # k_seg_broadcast: 1.61 MB fetched (offsets, gradients) + 128.83 MB written
-    "seg_broadcast": {"file": "segmented.hip", "bytes": 130405516,
-                      "source": "b5f15f5395a0cb0f22227313698c92766ebd1ec556008b9c62f406e5060857f5"},
+    # k_seg_broadcast (row-span path): 2.66 MB fetched (offsets, gradients) + 128.71 MB written
+    "seg_broadcast": {"file": "segmented.hip", "bytes": 131367569,
+                      "source": "41a385e9b42d3423d8b8b71015ef1b28e3ec22adc775890c3decf79c03a8516c"},
 }
 
 
