@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
         //      Each f carries its candidate's slot ci*4 + r in its four low
         //      mantissa bits, so one minimum gives value and index, and one
         //      median of three keeps the second smallest value.
-        float r1[4], r2[4];
+        float r1[4], r2[4], r3[4];  // r3: the third smallest (one centroid chunk only)
         int ri[4];
 #pragma unroll
         for (int cc = 0; cc < KP / 64; ++cc) {
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             }
 #pragma unroll
             for (int pi = 0; pi < 4; ++pi) {
-                float b1 = INFINITY, b2 = INFINITY;
+                float b1 = INFINITY, b2 = INFINITY, b3 = INFINITY;
 #pragma unroll
                 for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
@@ -347,9 +347,11 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                         const float f = __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~15u) |
                                                         (unsigned)(ci * 4 + r));
                         // median forms: no canonicalising of the bit-built f
+                        if constexpr (KP == 64) b3 = __builtin_amdgcn_fmed3f(b2, b3, f);
                         b2 = __builtin_amdgcn_fmed3f(b1, b2, f);
                         b1 = __builtin_amdgcn_fmed3f(b1, f, -FLT_MAX);
                     }
+                r3[pi] = b3;
                 const int slot = (int)(__float_as_uint(b1) & 15u);
                 const int j1 = cc * 64 + (slot >> 2) * 16 + 4 * g + (slot & 3);
                 if (cc == 0) {
@@ -361,35 +363,134 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 }
             }
         }
-        // every lane publishes (best, index, second, |x|^2 part) per point
+        // every lane publishes (best, index, second, |x|^2 part) per point; with
+        // one centroid chunk (best and second with their slots, third, |x|^2
+        // part), the lane group giving the rest of the index
 #pragma unroll
         for (int pi = 0; pi < 4; ++pi)
-            pub[g * kPtsWave + pi * 16 + l16] = make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
+            pub[g * kPtsWave + pi * 16 + l16] =
+                KP == 64 ? make_float4(r1[pi], r2[pi], r3[pi], xpart[pi])
+                         : make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
         wave_sync();
         // ---- certify each label (lane = point); uncertified points are
         //      recomputed in binary64 by the whole wave, lanes over centroids
         {
             const int64_t p = p0 + lane;
             // merge the four lane groups in index order (lexicographic minimum)
-            float4 q = pub[lane];
-            float m1 = q.x, m2 = q.z, xx = q.w;
-            int mj = __float_as_int(q.y);
+            float m1, m2, m3 = INFINITY, xx;
+            int mj, mj2 = -1;
+            if constexpr (KP == 64) {
+                // the two smallest with their indices and the third smallest
+                m1 = m2 = INFINITY;
+                mj = 0x7fffffff;
+                xx = 0.f;
+                auto take = [&](float v, int j) {
+                    if (v < m1 || (v == m1 && j < mj)) {
+                        m3 = m2;
+                        m2 = m1;
+                        mj2 = mj;
+                        m1 = v;
+                        mj = j;
+                    } else if (v < m2 || (v == m2 && j < mj2)) {
+                        m3 = m2;
+                        m2 = v;
+                        mj2 = j;
+                    } else {
+                        m3 = fminf(m3, v);
+                    }
+                };
 #pragma unroll
-            for (int gg = 1; gg < 4; ++gg) {
-                q = pub[gg * kPtsWave + lane];
-                const int qj = __float_as_int(q.y);
-                const bool take = q.x < m1 || (q.x == m1 && qj < mj);
-                m2 = fminf(fmaxf(m1, q.x), fminf(m2, q.z));
-                mj = take ? qj : mj;
-                m1 = fminf(m1, q.x);
-                xx += q.w;
+                for (int gg = 0; gg < 4; ++gg) {
+                    const float4 q = pub[gg * kPtsWave + lane];
+                    const unsigned s1 = __float_as_uint(q.x) & 15u, s2 = __float_as_uint(q.y) & 15u;
+                    take(q.x, (int)((s1 >> 2) * 16 + 4 * gg + (s1 & 3)));
+                    take(q.y, (int)((s2 >> 2) * 16 + 4 * gg + (s2 & 3)));
+                    m3 = fminf(m3, q.z);  // at least this group's second, so never below m2
+                    xx += q.w;
+                }
+            } else {
+                float4 q = pub[lane];
+                m1 = q.x;
+                m2 = q.z;
+                xx = q.w;
+                mj = __float_as_int(q.y);
+#pragma unroll
+                for (int gg = 1; gg < 4; ++gg) {
+                    q = pub[gg * kPtsWave + lane];
+                    const int qj = __float_as_int(q.y);
+                    const bool tk = q.x < m1 || (q.x == m1 && qj < mj);
+                    m2 = fminf(fmaxf(m1, q.x), fminf(m2, q.z));
+                    mj = tk ? qj : mj;
+                    m1 = fminf(m1, q.x);
+                    xx += q.w;
+                }
             }
             int label = -1;
-            bool certified = true;
+            bool certified = true, two = false;
             if (p < a.n) {
                 const float xn_ = sqrtf(xx) + cmax;
-                certified = m2 - m1 > eps_factor * xn_ * xn_;
+                const float margin = eps_factor * xn_ * xn_;
+                certified = m2 - m1 > margin;
+                // every candidate but the best two is at least 2E above the
+                // best: the minimiser is one of those two
+                two = KP == 64 && !certified && m3 - m1 > margin && mj2 >= 0;
                 label = mj;
+            }
+            // ---- the best two, compared in the FP32 direct form by all
+            //      lanes at once: lane (g, l16) adds (x_t - c_t)^2 over its
+            //      dimensions for each of its points, the point's lane adds
+            //      the four parts in lane-group order; within 2 (d + 3) u of
+            //      the larger distance the point goes on to the stages below
+            if constexpr (KP == 64) {
+                if (__ballot(two)) {
+                    int *jj = reinterpret_cast<int *>(pub);                  // [64] both indices
+                    float2 *part = reinterpret_cast<float2 *>(pub + 16);     // [4 lane groups][64 points]
+                    wave_sync();
+                    jj[lane] = two ? (mj | (mj2 << 16)) : -1;
+                    wave_sync();
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi) {
+                        const int v = jj[mi * 16 + l16];
+                        float2 sd = make_float2(0.f, 0.f);
+                        if (v >= 0) {
+                            const float *c1 = Cs + (v & 0xffff) * LDC, *c2 = Cs + (v >> 16) * LDC;
+#pragma unroll
+                            for (int kc = 0; kc < DP / 32; ++kc)
+#pragma unroll
+                                for (int h = 0; h < 2; ++h) {
+                                    const int t = kc * 32 + 8 * g + 4 * h;
+                                    const float4 xv = xa[mi][kc][h];
+                                    const float4 u1 = *reinterpret_cast<const float4 *>(c1 + t);
+                                    const float4 u2 = *reinterpret_cast<const float4 *>(c2 + t);
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e) {
+                                        const float x_ = vget<float4, float>(xv, e);
+                                        const float d1 = x_ + 0.5f * vget<float4, float>(u1, e);
+                                        const float d2 = x_ + 0.5f * vget<float4, float>(u2, e);
+                                        sd.x += d1 * d1;
+                                        sd.y += d2 * d2;
+                                    }
+                                }
+                        }
+                        part[g * kPtsWave + mi * 16 + l16] = sd;
+                    }
+                    wave_sync();
+                    if (two) {
+                        float D1 = 0.f, D2 = 0.f;
+#pragma unroll
+                        for (int gg = 0; gg < 4; ++gg) {
+                            const float2 q = part[gg * kPtsWave + lane];
+                            D1 += q.x;
+                            D2 += q.y;
+                        }
+                        const float E2 = 2.0f * (float)(d + 3) * 5.9604645e-8f * fmaxf(D1, D2);
+                        if (fabsf(D1 - D2) > 2.0f * E2) {
+                            certified = true;
+                            label = D1 < D2 ? mj : mj2;
+                        }
+                    }
+                    wave_sync();
+                }
             }
             uint64_t todo = __ballot(!certified);
             // Uncertified points, four at a time: the points' coordinates go
