@@ -127,23 +127,28 @@ __device__ __forceinline__ void tile_of(int b, int tiles_m, int tiles_n, int &tm
     tn = in / gm;
 }
 
-// MFMA work of one K slice held in LDS: the wave's MI x NI blocks of 16 x 16
+// The wave's operand fragments of one K slice held in LDS: fa[s][i] is the
+// value lane (g, l16) feeds MFMA step s of row block i, fb[s][j] that of column
+// block j.
 template <int BM, int BN, int WM, int WN, bool RA, bool RB>
-__device__ __forceinline__ void mma_slice(v4f (&acc)[BM / WM / 16][BN / WN / 16], const float *__restrict__ as,
-                                          const float *__restrict__ bs, int wrow0, int wcol0, int l16, int g) {
+__device__ __forceinline__ void read_frags(float (&fa)[8][BM / WM / 16], float (&fb)[8][BN / WN / 16],
+                                           const float *__restrict__ as, const float *__restrict__ bs, int wrow0,
+                                           int wcol0, int l16, int g) {
     constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
     using OA = Operand<BM, RA>;
     using OB = Operand<BN, RB>;
-    float a8[RA ? MI : 1][8], b8[RB ? NI : 1][8];
     if constexpr (RA) {
 #pragma unroll
         for (int i = 0; i < MI; ++i) {
             const int row = wrow0 + 16 * i + l16;
             const float4 lo = *reinterpret_cast<const float4 *>(as + swz(row, 2 * g));
             const float4 hi = *reinterpret_cast<const float4 *>(as + swz(row, 2 * g + 1));
-            a8[i][0] = lo.x; a8[i][1] = lo.y; a8[i][2] = lo.z; a8[i][3] = lo.w;
-            a8[i][4] = hi.x; a8[i][5] = hi.y; a8[i][6] = hi.z; a8[i][7] = hi.w;
+            fa[0][i] = lo.x; fa[1][i] = lo.y; fa[2][i] = lo.z; fa[3][i] = lo.w;
+            fa[4][i] = hi.x; fa[5][i] = hi.y; fa[6][i] = hi.z; fa[7][i] = hi.w;
         }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) lds_read<MI>(fa[s], as + (8 * g + s) * OA::LD + wrow0 + MI * l16);
     }
     if constexpr (RB) {
 #pragma unroll
@@ -151,31 +156,33 @@ __device__ __forceinline__ void mma_slice(v4f (&acc)[BM / WM / 16][BN / WN / 16]
             const int row = wcol0 + 16 * j + l16;
             const float4 lo = *reinterpret_cast<const float4 *>(bs + swz(row, 2 * g));
             const float4 hi = *reinterpret_cast<const float4 *>(bs + swz(row, 2 * g + 1));
-            b8[j][0] = lo.x; b8[j][1] = lo.y; b8[j][2] = lo.z; b8[j][3] = lo.w;
-            b8[j][4] = hi.x; b8[j][5] = hi.y; b8[j][6] = hi.z; b8[j][7] = hi.w;
+            fb[0][j] = lo.x; fb[1][j] = lo.y; fb[2][j] = lo.z; fb[3][j] = lo.w;
+            fb[4][j] = hi.x; fb[5][j] = hi.y; fb[6][j] = hi.z; fb[7][j] = hi.w;
         }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) lds_read<NI>(fb[s], bs + (8 * g + s) * OB::LD + wcol0 + NI * l16);
     }
+}
+
+// MFMA work of one K slice from its fragments: the wave's MI x NI blocks of 16 x 16
+template <int MI, int NI>
+__device__ __forceinline__ void mma_frags(v4f (&acc)[MI][NI], const float (&fa)[8][MI], const float (&fb)[8][NI]) {
 #pragma unroll
-    for (int step = 0; step < 8; ++step) {
-        float av[MI], bv[NI];
-        if constexpr (RA) {
-#pragma unroll
-            for (int i = 0; i < MI; ++i) av[i] = a8[i][step];
-        } else {
-            lds_read<MI>(av, as + (8 * g + step) * OA::LD + wrow0 + MI * l16);
-        }
-        if constexpr (RB) {
-#pragma unroll
-            for (int j = 0; j < NI; ++j) bv[j] = b8[j][step];
-        } else {
-            lds_read<NI>(bv, bs + (8 * g + step) * OB::LD + wcol0 + NI * l16);
-        }
+    for (int step = 0; step < 8; ++step)
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int j = 0; j < NI; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[step][i], fb[step][j], acc[i][j], 0, 0, 0);
+}
+
+template <int BM, int BN, int WM, int WN, bool RA, bool RB>
+__device__ __forceinline__ void mma_slice(v4f (&acc)[BM / WM / 16][BN / WN / 16], const float *__restrict__ as,
+                                          const float *__restrict__ bs, int wrow0, int wcol0, int l16, int g) {
+    float fa[8][BM / WM / 16], fb[8][BN / WN / 16];
+    read_frags<BM, BN, WM, WN, RA, RB>(fa, fb, as, bs, wrow0, wcol0, l16, g);
+    mma_frags(acc, fa, fb);
 }
 
 template <int BM, int BN, int WM, int WN, int TA, int TB>
@@ -213,38 +220,62 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
 
     const int wrow0 = wm * (BM / WM), wcol0 = wn * (BN / WN);
     constexpr int NA = BM * BK / 4 / NT, NB = BN * BK / 4 / NT;
-    if (interior && K % (2 * BK) == 0) {
-        // Interior tile, whole slice pairs: a branch-free pipeline.  Slice
-        // kt + 2 is loaded while slice kt is multiplied and stored to LDS only
-        // after slice kt + 1 has been, so every load has two slices of MFMA
-        // work to land; past the end the slice index is clamped (the extra
-        // loads are never read) rather than branched around, which would make
-        // the compiler wait for every load in flight.
-        float4 ra0[NA], rb0[NB], ra1[NA], rb1[NB];
-        load_slice<BM, RA, NT>(ra0, A, lda, m0, 0, M, K, true);
-        load_slice<BN, RB, NT>(rb0, B, ldb, n0, 0, N, K, true);
-        store_slice<BM, RA, NT>(As[0], ra0);
-        store_slice<BN, RB, NT>(Bs[0], rb0);
-        load_slice<BM, RA, NT>(ra1, A, lda, m0, BK, M, K, true);
-        load_slice<BN, RB, NT>(rb1, B, ldb, n0, BK, N, K, true);
+    if (interior && K % (2 * BK) == 0 && nk >= 4) {
+        // Interior tile, an even number (at least four) of whole slices.
+        // Iteration kt multiplies slice kt from fragments already in registers
+        // while the fragments of slice kt + 1 are read from LDS, then stores
+        // slice kt + 2 (loaded two iterations earlier) into the buffer slice kt
+        // occupied and issues the global loads of slice kt + 4; one barrier.
+        // The fragment reads are in flight across the MFMAs and the barrier,
+        // so no wave waits on LDS latency between slices.  The last four
+        // iterations are peeled: nothing is loaded past the end of K.
+        float4 ga[NA], gb[NB], ha[NA], hb[NB];  // staging of two slices in flight
+        float fa0[8][MI], fb0[8][NI], fa1[8][MI], fb1[8][NI];
+        load_slice<BM, RA, NT>(ga, A, lda, m0, 0, M, K, true);
+        load_slice<BN, RB, NT>(gb, B, ldb, n0, 0, N, K, true);
+        load_slice<BM, RA, NT>(ha, A, lda, m0, BK, M, K, true);
+        load_slice<BN, RB, NT>(hb, B, ldb, n0, BK, N, K, true);
+        store_slice<BM, RA, NT>(As[0], ga);
+        store_slice<BN, RB, NT>(Bs[0], gb);
+        load_slice<BM, RA, NT>(ga, A, lda, m0, 2 * BK, M, K, true);
+        load_slice<BN, RB, NT>(gb, B, ldb, n0, 2 * BK, N, K, true);
         __syncthreads();
-        for (int kt = 0; kt < nk; kt += 2) {
-            const int64_t k2 = (int64_t)min(kt + 2, nk - 1) * BK, k3 = (int64_t)min(kt + 3, nk - 1) * BK;
-            load_slice<BM, RA, NT>(ra0, A, lda, m0, k2, M, K, true);
-            load_slice<BN, RB, NT>(rb0, B, ldb, n0, k2, N, K, true);
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
-            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As[0], Bs[0], wrow0, wcol0, l16, g);
-            store_slice<BM, RA, NT>(As[1], ra1);
-            store_slice<BN, RB, NT>(Bs[1], rb1);
-            __syncthreads();
-            load_slice<BM, RA, NT>(ra1, A, lda, m0, k3, M, K, true);
-            load_slice<BN, RB, NT>(rb1, B, ldb, n0, k3, N, K, true);
-            __builtin_amdgcn_sched_barrier(0);
-            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As[1], Bs[1], wrow0, wcol0, l16, g);
-            store_slice<BM, RA, NT>(As[0], ra0);
-            store_slice<BN, RB, NT>(Bs[0], rb0);
-            __syncthreads();
+        read_frags<BM, BN, WM, WN, RA, RB>(fa0, fb0, As[0], Bs[0], wrow0, wcol0, l16, g);
+        store_slice<BM, RA, NT>(As[1], ha);
+        store_slice<BN, RB, NT>(Bs[1], hb);
+        load_slice<BM, RA, NT>(ha, A, lda, m0, 3 * BK, M, K, true);
+        load_slice<BN, RB, NT>(hb, B, ldb, n0, 3 * BK, N, K, true);
+        __syncthreads();
+        // one iteration; buffer (kt + 1) & 1 holds slice kt + 1, buffer kt & 1
+        // is free once slice kt's fragments are in registers
+#define MX_GEMM_ITER(KT, FA, FB, NFA, NFB, SA, SB, DO_R, DO_S, DO_L)                                      \
+        {                                                                                                 \
+            const int b1 = ((KT) + 1) & 1, b0 = (KT) & 1;                                                 \
+            if (DO_R) read_frags<BM, BN, WM, WN, RA, RB>(NFA, NFB, As[b1], Bs[b1], wrow0, wcol0, l16, g); \
+            __builtin_amdgcn_sched_barrier(0);                                                            \
+            mma_frags(acc, FA, FB);                                                                       \
+            __builtin_amdgcn_sched_barrier(0);                                                            \
+            if (DO_S) {                                                                                   \
+                store_slice<BM, RA, NT>(As[b0], SA);                                                      \
+                store_slice<BN, RB, NT>(Bs[b0], SB);                                                      \
+            }                                                                                             \
+            if (DO_L) {                                                                                   \
+                const int64_t kl = (int64_t)((KT) + 4) * BK;                                              \
+                load_slice<BM, RA, NT>(SA, A, lda, m0, kl, M, K, true);                                   \
+                load_slice<BN, RB, NT>(SB, B, ldb, n0, kl, N, K, true);                                   \
+            }                                                                                             \
+            if (DO_S) __syncthreads();                                                                    \
         }
+        int kt = 0;
+        for (; kt + 4 < nk; kt += 2) {
+            MX_GEMM_ITER(kt, fa0, fb0, fa1, fb1, ga, gb, true, true, true)
+            MX_GEMM_ITER(kt + 1, fa1, fb1, fa0, fb0, ha, hb, true, true, true)
+        }
+        MX_GEMM_ITER(kt, fa0, fb0, fa1, fb1, ga, gb, true, true, false)
+        MX_GEMM_ITER(kt + 1, fa1, fb1, fa0, fb0, ha, hb, true, true, false)
+        MX_GEMM_ITER(kt + 2, fa0, fb0, fa1, fb1, ga, gb, true, false, false)
+        MX_GEMM_ITER(kt + 3, fa1, fb1, fa0, fb0, ha, hb, false, false, false)
+#undef MX_GEMM_ITER
     } else {
         // edge tiles and ragged K: bounds-checked loads, one slice ahead
         float4 ra[NA], rb[NB];
@@ -336,12 +367,13 @@ mx_status check(const char *who, int ta, int tb, int64_t M, int64_t N, int64_t K
     return MX_OK;
 }
 
-// Tile shapes, 8 waves each (512 threads hide each other's LDS and barrier
-// waits better than 4 waves with twice the work): 128 x 128 (2 x 4 blocks of
-// 16 x 16 per wave) when there are enough tiles for every CU, 128 x 64
-// (2 x 2 per wave) otherwise and for A B^T, where it measured faster at
-// 2048^3; MX_GEMM_TILE in the environment forces one of the configurations
-// below (for tuning and for testing every tile at small shapes).
+// Tile shapes: 128 x 128 with 16 waves (2 x 2 blocks of 16 x 16 per wave, four
+// waves per SIMD) when there are enough tiles for every CU, else 128 x 64 with
+// 8 waves (2 x 2 per wave); more waves per SIMD hide each other's barrier and
+// LDS waits (at 2048^3 the 16-wave tile measured 2-4 % faster than 8 waves
+// with 2 x 4 blocks each).  MX_GEMM_TILE in the environment forces one of the
+// configurations below (for tuning and for testing every tile at small
+// shapes).
 template <int BM, int BN, int WM, int WN>
 mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const float *A, const float *B, float *C,
                       int vec_ok, hipStream_t s) {
@@ -361,7 +393,7 @@ mx_status launch_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const flo
 }
 
 // Tile configurations: BM x BN block tile, WM x WN waves.
-enum GemmTile { kT128x64 = 1, kT128x128, kT128x64w8, kT128x128w8, kT64x64 };
+enum GemmTile { kT128x64 = 1, kT128x128, kT128x64w8, kT128x128w8, kT64x64, kT128x128w8b, kT128x128w16 };
 
 int gemm_tile_choice(int ta, int tb, int64_t M, int64_t N, const DeviceInfo *d) {
     // read on every call (a getenv is cheap next to a launch), so one process
@@ -369,14 +401,14 @@ int gemm_tile_choice(int ta, int tb, int64_t M, int64_t N, const DeviceInfo *d) 
     if (const char *e = getenv("MX_GEMM_TILE")) {
         static const struct { const char *name; int tile; } names[] = {
             {"128x64", kT128x64}, {"128x128", kT128x128}, {"128x64w8", kT128x64w8},
-            {"128x128w8", kT128x128w8}, {"64x64", kT64x64}};
+            {"128x128w8", kT128x128w8}, {"64x64", kT64x64}, {"128x128w8b", kT128x128w8b},
+            {"128x128w16", kT128x128w16}};
         for (const auto &n : names)
             if (!strcmp(e, n.name)) return n.tile;
     }
-    // 128 x 128 when it still gives every CU a tile, except for A B^T (both
-    // operands [row][k]), where the 128 x 64 tile measured faster
+    // 128 x 128 when it still gives every CU a tile
     const int64_t big = ceil_div(M, 128) * ceil_div(N, 128);
-    if (big >= d->num_cus && !(ta == 0 && tb == 1)) return kT128x128w8;
+    if (big >= d->num_cus) return kT128x128w16;
     return kT128x64w8;
 }
 
@@ -401,6 +433,8 @@ mx_status mx_map_map_reduce_f32(int ta, int tb, int64_t M, int64_t N, int64_t K,
     case kT128x64w8: return launch_gemm<128, 64, 4, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
     case kT128x128w8: return launch_gemm<128, 128, 4, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
     case kT64x64: return launch_gemm<64, 64, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    case kT128x128w8b: return launch_gemm<128, 128, 2, 4>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
+    case kT128x128w16: return launch_gemm<128, 128, 4, 4>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
     default: return launch_gemm<128, 128, 2, 2>(ta, tb, M, N, K, A_dev, B_dev, C_dev, vec_ok, stream);
     }
 }

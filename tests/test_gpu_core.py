@@ -627,7 +627,7 @@ def test_mmr_config_2048_sampled(seed):
         check_scalar(C[i, j], R, S, K, what=f"C[{i},{j}]")
 
 
-TILES = ["128x64", "128x128", "128x64w8", "128x128w8", "64x64"]
+TILES = ["128x64", "128x128", "128x64w8", "128x128w8", "64x64", "128x128w8b", "128x128w16"]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -668,8 +668,8 @@ def _rows_cols_check(C, A, B, seed, what):
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_mmr_config_2048_every_transpose_rows_and_cols(ta, tb):
-    """2048^3 with the default tile choice (256 tiles of 128 x 128 for three of
-    the cases, 128 x 64 for A B^T): 64 whole rows and 64 whole columns."""
+    """2048^3 with the default tile choice (256 tiles of 128 x 128, 16 waves):
+    64 whole rows and 64 whole columns."""
     say("mmr 2048 transposes", ta, tb)
     M = N = K = 2048
     A, B = W.dense_f32(M, N, K, seed=10 + 2 * ta + tb)
@@ -682,7 +682,7 @@ def test_mmr_config_2048_every_transpose_rows_and_cols(ta, tb):
 
 def test_mmr_config_2048_backward_rows_and_cols():
     """The benchmark's products through autograd: C = A B, then dA = dC B^T
-    (128 x 64 tiles) and dB = A^T dC (128 x 128 tiles), at 2048^3."""
+    and dB = A^T dC (128 x 128 tiles of 16 waves each), at 2048^3."""
     say("mmr 2048 backward")
     M = N = K = 2048
     A, B = W.dense_f32(M, N, K, seed=0)
