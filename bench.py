@@ -53,11 +53,16 @@ FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 # taken: once that file changes the figure no longer describes the kernel and
 # the bench reports null.
 TRAFFIC = {
-    # k_gemm_mfma<128,128,4,2,0,0>, 2048^3: 100.78 MB fetched (A and B panels re-read by each XCD that
-    # needs them, plus two clamped slices past the end of K per tile; 33.6 MB is the algorithmic
-    # minimum) + 16.78 MB written (C)
-    "gemm_nn": {"file": "gemm.hip", "bytes": 117557162,
-                "source": "cb5d31e73fdf1805aaa927c53045f40347d4e271b1beaf6ca36e09725257686b"},
+    # k_gemm_mfma<128,128,4,4,TA,TB>, 2048^3, each transpose: 100.77 MB fetched + 16.78 MB written.
+    # Each XCD's L2 fetches the A row panels and B column panels of its own 32 tiles (4 x 8 of them:
+    # 12 panels of 1 MiB, the fewest 32 tiles can need), so each A panel is fetched by two XCDs and
+    # each B panel by four; the algorithmic minimum is 33.6 MB read + 16.8 MB written (2.34x)
+    "gemm_nn": {"file": "gemm.hip", "bytes": 117547962,
+                "source": "15affe50b1c8d6e8324b26246a9548598236273f961bffb9f122c810fb0c8f45"},
+    "gemm_nt": {"file": "gemm.hip", "bytes": 117544890,
+                "source": "15affe50b1c8d6e8324b26246a9548598236273f961bffb9f122c810fb0c8f45"},
+    "gemm_tn": {"file": "gemm.hip", "bytes": 117555130,
+                "source": "15affe50b1c8d6e8324b26246a9548598236273f961bffb9f122c810fb0c8f45"},
     # k_seg_span (row-span path), 65536 rows / 32.1 M values: 131.11 MB fetched + 0.26 MB
     # written (1.02x algorithmic: 129.19 MB)
     "seg_span": {"file": "segmented.hip", "bytes": 131372884,
@@ -352,13 +357,18 @@ def bench_nested(args):
         "row_sums": 4 * nval + 8 * (nseg + 1) + 4 * nseg,
         "row_sums_adjoint": 4 * nval + 8 * (nseg + 1) + 4 * nseg,
     }
-    counted = {"row_sums": traffic_of("seg_span"), "row_sums_adjoint": traffic_of("seg_broadcast")}
+    counted = {"row_sums": traffic_of("seg_span"), "row_sums_adjoint": traffic_of("seg_broadcast"),
+               "mmr_fwd": traffic_of("gemm_nn"), "mmr_adjoint_A": traffic_of("gemm_nt"),
+               "mmr_adjoint_B": traffic_of("gemm_tn")}
+    # algorithmic bytes of each product: both operands read once, C written once
+    mmr_bytes = 4 * (M * K + K * N + M * N)
     detail = {}
     for n in names:
         mean = float(stats[n].mean())
         e = {**summary_us(stats[n]), "b2b_us": round(b2b[n] * 1e3, 2), "plain_us": round(pparts[n] * 1e3, 2)}
         if counted.get(n):
             e["traffic_bytes"] = counted[n]
+            e["traffic_ratio"] = round(counted[n] / bytes_.get(n, mmr_bytes), 3)
         if n in bytes_:
             med = float(np.median(stats[n]))
             e["GB/s"] = round(gbs(bytes_[n], med), 1)
