@@ -16,18 +16,26 @@
 // products per tile against eight FP32 16x16x4 ones, each product exact in
 // FP32.  The dropped terms (a_m x_m, a_h x_l, a_l x_h and smaller) are at most
 // 3.02 2^-16 |a_t||x_t| per dimension, so at most 6.03 2^-16 |c||x| in all (a
-// = -2c, Cauchy-Schwarz); the 97 FP32 additions of the three accumulations
-// (2 u each, u = 2^-24, allowing for the matrix core's own rounding) at most
-// 0.76 2^-16 (|c|^2 + 2|c||x|); the FP32 |c|^2 0.13 2^-16 |c|^2; the
-// candidate's slot, carried in the four low mantissa bits (at most 15 ulp),
-// 0.12 2^-16 of the value.  So the computed values p_j satisfy |p_j - f_j| <=
-// E = 2^-13 (|x| + max_j |c_j|)^2, twice the 4.03 2^-16 these add up to.
-// When the two smallest p differ by more than 2E the smallest is the exact,
-// unique minimiser and also the binary64 oracle's.  Otherwise (on the blob
-// data, a few thousand points per million while several centroids share a
-// blob) the lane recomputes every distance in binary64 in the oracle's
-// operation order -- subtract, square, add, no fused multiply-add -- and
-// takes the lexicographic minimum, so labels are bit-exact in all cases.
+// = -2c, Cauchy-Schwarz); the 3 DP FP32 additions of the three accumulations
+// over DP padded dimensions (2 u each, u = 2^-24, allowing for the matrix
+// core's own rounding) at most (6 DP / 256) 2^-16 times the sum of the
+// magnitudes added, |c|^2 (1 + 2^-10) + 2.032 |c||x|; the FP32 |c|^2
+// ((DP + 1) / 256) 2^-16 |c|^2; the candidate's slot, carried in the four low
+// mantissa bits (at most 15 ulp), 0.12 2^-16 of the value, |c|^2 + 2|c||x|.
+// So the computed values p_j satisfy |p_j - f_j| <= B = 2^-16 (XC |x| C + CC
+// C^2) with C = max_j |c_j|, XC = 7.80 and CC = 1.00 for DP = 32 (9.32 and
+// 1.88 for DP = 64).  With E = 2B: when the two smallest p differ by more
+// than 2E the smallest is the exact, unique minimiser and also the binary64
+// oracle's.  The bound is relative, so it needs the products above the
+// subnormal range, where the matrix core may flush: below C = 2^-40 no label
+// is certified here.  The other points (on the blob data about 2 % of them,
+// where several centroids share a blob) go through up to three more stages:
+// between their best two candidates in the FP32 direct form, when the third
+// best is also above the margin; among all candidates in the FP32 direct
+// form, four points at a time; and, for the few dozen per million left, in
+// binary64 in the oracle's operation order -- subtract, square, add, no
+// fused multiply-add -- taking the lexicographic minimum, so labels are
+// bit-exact in all cases.
 //
 // Persistent waves: a fixed grid of at most kMaxBlocks blocks, each wave
 // walking its own sequence of 64-point chunks and loading the next chunk's
@@ -242,7 +250,11 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     }
     __syncthreads();
     const float cmax = cmax_s;
-    const float eps_factor = 2.0f * 1.220703125e-4f;  // 2E / (|x| + max|c|)^2 = 2 2^-13
+    // 2E = 4B = 2^-16 C (kXC |x| + kCC C): the bound's constants for DP
+    // padded dimensions, times four, rounded up
+    constexpr float kXC = 4.0f * (6.03f + 2.032f * (6.0f * DP / 256.0f) + 0.24f) + 0.05f;
+    constexpr float kCC = 4.0f * (1.001f * (6.0f * DP / 256.0f) + (DP + 1.0f) / 256.0f + 0.12f) + 0.05f;
+    const bool bound_ok = cmax >= 0x1p-40f;  // products above the subnormal range
     // A operands (-2c, rows ci*16 + l16 of centroid chunk cc, dimensions
     // kc*32 + 8g .. +7) as bfloat16 parts: held in registers for the whole
     // walk when there is one centroid chunk, else split per chunk
@@ -428,8 +440,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             int label = -1;
             bool certified = true, two = false;
             if (p < a.n) {
-                const float xn_ = sqrtf(xx) + cmax;
-                const float margin = eps_factor * xn_ * xn_;
+                const float margin = bound_ok ? 0x1p-16f * cmax * (kXC * sqrtf(xx) + kCC * cmax) : INFINITY;
                 certified = m2 - m1 > margin;
                 // every candidate but the best two is at least 2E above the
                 // best: the minimiser is one of those two
@@ -483,8 +494,10 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                             D1 += q.x;
                             D2 += q.y;
                         }
+                        // relative bound: subnormal squares add at most
+                        // 2^-149 each, negligible once the larger sum is 2^-90
                         const float E2 = 2.0f * (float)(d + 3) * 5.9604645e-8f * fmaxf(D1, D2);
-                        if (fabsf(D1 - D2) > 2.0f * E2) {
+                        if (fabsf(D1 - D2) > 2.0f * E2 && fmaxf(D1, D2) >= 0x1p-90f) {
                             certified = true;
                             label = D1 < D2 ? mj : mj2;
                         }
@@ -553,7 +566,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 }
                 const float f1 = __uint_as_float(u1 & ~255u), f2 = __uint_as_float(u2 & ~255u);
                 const float E2 = 2.0f * (float)(d + 3 + 512) * 5.9604645e-8f * f2;
-                const bool ok = cmax < INFINITY && f2 - f1 > 2.0f * E2;
+                const bool ok = cmax < INFINITY && f2 - f1 > 2.0f * E2 && f2 >= 0x1p-90f;
                 // every lane of row s holds point s's result
 #pragma unroll
                 for (int s2 = 0; s2 < 4; ++s2) {

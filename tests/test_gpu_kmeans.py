@@ -99,6 +99,20 @@ def test_kmeans_ties_and_near_ties_take_the_oracle_label():
     assert not np.any(host(lab) == 5)
 
 
+@pytest.mark.parametrize("scale", [1e-25, 1e-15, 1e17, 1e18])
+def test_kmeans_extreme_scales_take_the_oracle_label(scale):
+    """Points and centroids scaled so the products fall below the normal range
+    (1e-25: every certification is refused and binary64 decides; 1e-15: below
+    the matrix stage's 2^-40 floor) or near the top of it (1e17; at 1e18 |x|^2
+    and |c|^2 overflow in FP32 and binary64 decides): labels and
+    counts bit-exact, centroids within the reduction tolerance."""
+    say("kmeans scale", scale)
+    X, _, _ = W.kmeans_blobs(3000, 16, 8, seed=11)
+    X = (X.astype(np.float64) * scale).astype(np.float32)
+    C0 = X[np.random.default_rng(5).choice(len(X), 12, replace=False)].copy()
+    lockstep(X, C0, 1)
+
+
 def test_kmeans_empty_cluster_and_determinism():
     say("kmeans empty")
     X, _, _ = W.kmeans_blobs(20000, 32, 8, seed=3)
