@@ -20,11 +20,12 @@
 // over DP padded dimensions (2 u each, u = 2^-24, allowing for the matrix
 // core's own rounding) at most (6 DP / 256) 2^-16 times the sum of the
 // magnitudes added, |c|^2 (1 + 2^-10) + 2.032 |c||x|; the FP32 |c|^2
-// ((DP + 1) / 256) 2^-16 |c|^2; the candidate's slot, carried in the four low
-// mantissa bits (at most 15 ulp), 0.12 2^-16 of the value, |c|^2 + 2|c||x|.
-// So the computed values p_j satisfy |p_j - f_j| <= B = 2^-16 (XC |x| C + CC
-// C^2) with C = max_j |c_j|, XC = 7.80 and CC = 1.00 for DP = 32 (9.32 and
-// 1.88 for DP = 64).  With E = 2B: when the two smallest p differ by more
+// ((DP + 1) / 256) 2^-16 |c|^2; the candidate's index, carried in the six low
+// mantissa bits with one chunk of 64 centroids (at most 63 ulp, 0.49 2^-16 of
+// the value, |c|^2 + 2|c||x|; with more chunks its slot in the chunk, four
+// bits, 0.12 2^-16).  So the computed values p_j satisfy |p_j - f_j| <= B =
+// 2^-16 (XC |x| C + CC C^2) with C = max_j |c_j|, XC = 8.54 and CC = 1.37
+// for DP = 32 and one chunk (10.06 and 2.25 for DP = 64).  With E = 2B: when the two smallest p differ by more
 // than 2E the smallest is the exact, unique minimiser and also the binary64
 // oracle's.  The bound is relative, so it needs the products above the
 // subnormal range, where the matrix core may flush: below C = 2^-40 no label
@@ -251,9 +252,12 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     __syncthreads();
     const float cmax = cmax_s;
     // 2E = 4B = 2^-16 C (kXC |x| + kCC C): the bound's constants for DP
-    // padded dimensions, times four, rounded up
-    constexpr float kXC = 4.0f * (6.03f + 2.032f * (6.0f * DP / 256.0f) + 0.24f) + 0.05f;
-    constexpr float kCC = 4.0f * (1.001f * (6.0f * DP / 256.0f) + (DP + 1.0f) / 256.0f + 0.12f) + 0.05f;
+    // padded dimensions and kSlot = (2^bits - 1) / 128 for the index bits in
+    // the values (six with one centroid chunk, else four), times four,
+    // rounded up
+    constexpr float kSlot = (KP == 64 ? 63.0f : 15.0f) / 128.0f;
+    constexpr float kXC = 4.0f * (6.03f + 2.032f * (6.0f * DP / 256.0f) + 2.0f * kSlot) + 0.05f;
+    constexpr float kCC = 4.0f * (1.001f * (6.0f * DP / 256.0f) + (DP + 1.0f) / 256.0f + kSlot) + 0.05f;
     const bool bound_ok = cmax >= 0x1p-40f;  // products above the subnormal range
     // A operands (-2c, rows ci*16 + l16 of centroid chunk cc, dimensions
     // kc*32 + 8g .. +7) as bfloat16 parts: held in registers for the whole
@@ -316,11 +320,11 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
 #pragma unroll
         for (int cc = 0; cc < KP / 64; ++cc) {
             v4f acc[4][4];  // [ci][pi]
+            v4f cn[4];      // |c|^2 of rows 4g .. 4g+3 of each centroid block: the first product's source
 #pragma unroll
             for (int ci = 0; ci < 4; ++ci) {
                 const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + cc * 64 + ci * 16 + 4 * g);
-#pragma unroll
-                for (int pi = 0; pi < 4; ++pi) acc[ci][pi] = v4f{c4.x, c4.y, c4.z, c4.w};
+                cn[ci] = v4f{c4.x, c4.y, c4.z, c4.w};
             }
 #pragma unroll
             for (int kc = 0; kc < DP / 32; ++kc) {
@@ -340,7 +344,8 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                     }
 #pragma unroll
                     for (int pi = 0; pi < 4; ++pi)
-                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[pi], acc[ci][pi], 0, 0, 0);
+                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[pi], kc == 0 ? cn[ci] : acc[ci][pi],
+                                                                              0, 0, 0);
 #pragma unroll
                     for (int pi = 0; pi < 4; ++pi)
                         acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[pi], acc[ci][pi], 0, 0, 0);
@@ -356,14 +361,26 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float f = __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~15u) |
-                                                        (unsigned)(ci * 4 + r));
+                        // one chunk: bits 0-1 and 4-5 carry r and ci of the
+                        // index ci*16 + 4g + r, bits 2-3 (the lane group's,
+                        // equal for every candidate of this lane) are set below
+                        const float f = KP == 64 ? __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~63u) |
+                                                                   (unsigned)(ci * 16 + r))
+                                                 : __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~15u) |
+                                                                   (unsigned)(ci * 4 + r));
                         // median forms: no canonicalising of the bit-built f
                         if constexpr (KP == 64) b3 = __builtin_amdgcn_fmed3f(b2, b3, f);
                         b2 = __builtin_amdgcn_fmed3f(b1, b2, f);
                         b1 = __builtin_amdgcn_fmed3f(b1, f, -FLT_MAX);
                     }
-                r3[pi] = b3;
+                if constexpr (KP == 64) {
+                    // the same two bits in every value keep the lane's order
+                    const unsigned gb = 4u * (unsigned)g;
+                    r1[pi] = __uint_as_float(__float_as_uint(b1) | gb);
+                    r2[pi] = __uint_as_float(__float_as_uint(b2) | gb);
+                    r3[pi] = __uint_as_float(__float_as_uint(b3) | gb);
+                    continue;
+                }
                 const int slot = (int)(__float_as_uint(b1) & 15u);
                 const int j1 = cc * 64 + (slot >> 2) * 16 + 4 * g + (slot & 3);
                 if (cc == 0) {
@@ -376,8 +393,8 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             }
         }
         // every lane publishes (best, index, second, |x|^2 part) per point; with
-        // one centroid chunk (best and second with their slots, third, |x|^2
-        // part), the lane group giving the rest of the index
+        // one centroid chunk (best, second, third, |x|^2 part), each value
+        // carrying its whole index
 #pragma unroll
         for (int pi = 0; pi < 4; ++pi)
             pub[g * kPtsWave + pi * 16 + l16] =
@@ -392,34 +409,26 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
             float m1, m2, m3 = INFINITY, xx;
             int mj, mj2 = -1;
             if constexpr (KP == 64) {
-                // the two smallest with their indices and the third smallest
+                // the three smallest of the four lane groups' three smallest:
+                // values with their whole index in the low bits, so float
+                // order is (value, index) order wherever the values differ
+                // by more than the index bits
                 m1 = m2 = INFINITY;
-                mj = 0x7fffffff;
                 xx = 0.f;
-                auto take = [&](float v, int j) {
-                    if (v < m1 || (v == m1 && j < mj)) {
-                        m3 = m2;
-                        m2 = m1;
-                        mj2 = mj;
-                        m1 = v;
-                        mj = j;
-                    } else if (v < m2 || (v == m2 && j < mj2)) {
-                        m3 = m2;
-                        m2 = v;
-                        mj2 = j;
-                    } else {
-                        m3 = fminf(m3, v);
-                    }
-                };
 #pragma unroll
                 for (int gg = 0; gg < 4; ++gg) {
                     const float4 q = pub[gg * kPtsWave + lane];
-                    const unsigned s1 = __float_as_uint(q.x) & 15u, s2 = __float_as_uint(q.y) & 15u;
-                    take(q.x, (int)((s1 >> 2) * 16 + 4 * gg + (s1 & 3)));
-                    take(q.y, (int)((s2 >> 2) * 16 + 4 * gg + (s2 & 3)));
-                    m3 = fminf(m3, q.z);  // at least this group's second, so never below m2
+                    const float v3[3] = {q.x, q.y, q.z};
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        m3 = __builtin_amdgcn_fmed3f(m2, m3, v3[e]);
+                        m2 = __builtin_amdgcn_fmed3f(m1, m2, v3[e]);
+                        m1 = __builtin_amdgcn_fmed3f(m1, v3[e], -FLT_MAX);
+                    }
                     xx += q.w;
                 }
+                mj = (int)(__float_as_uint(m1) & 63u);
+                mj2 = (int)(__float_as_uint(m2) & 63u);
             } else {
                 float4 q = pub[lane];
                 m1 = q.x;
