@@ -160,11 +160,29 @@ __device__ __forceinline__ void wave_sync() {
 // processed: points past n are read from the last point (their labels are
 // never used) and dimensions past d from dimension d - 1 (the centroids are
 // zero there, so only |x|^2 needs them zeroed, which mask_chunk does when the
-// chunk is consumed).  VX: d == DP and X 16-byte aligned (two 16-byte loads).
+// chunk is consumed).  VX: d == DP, X 16-byte aligned and fewer than 2^32
+// 16-byte vectors in X (two 16-byte loads at 32-bit vector offsets).
 template <int DP, bool VX>
 __device__ __forceinline__ void load_chunk(float4 (&xa)[4][DP / 32][2], const KmArgs &a, int64_t c, int l16,
                                            int g) {
     const int d = a.d;
+    if constexpr (VX) {
+        // n * DP / 4 < 2^32, so the point index and the vector offset fit 32 bits
+        const float4 *X4 = reinterpret_cast<const float4 *>(a.X);
+        const uint32_t last = (uint32_t)a.n - 1u;
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            const uint32_t p = (uint32_t)c * (uint32_t)kPtsWave + (uint32_t)(mi * 16 + l16);
+            const uint32_t v0 = min(p, last) * (uint32_t)(DP / 4) + (uint32_t)(2 * g);
+#pragma unroll
+            for (int kc = 0; kc < DP / 32; ++kc) {
+                const float4 *q = X4 + (v0 + (uint32_t)(kc * 8));
+                xa[mi][kc][0] = q[0];
+                xa[mi][kc][1] = q[1];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
         const int64_t p = c * kPtsWave + mi * 16 + l16;
@@ -172,11 +190,7 @@ __device__ __forceinline__ void load_chunk(float4 (&xa)[4][DP / 32][2], const Km
 #pragma unroll
         for (int kc = 0; kc < DP / 32; ++kc) {
             const int t0 = kc * 32 + 8 * g;
-            if constexpr (VX) {
-                const float4 *q = reinterpret_cast<const float4 *>(a.X + pc * d + t0);
-                xa[mi][kc][0] = q[0];
-                xa[mi][kc][1] = q[1];
-            } else {
+            {
                 float v[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) v[e] = a.X[pc * d + (t0 + e < d ? t0 + e : d - 1)];
@@ -940,7 +954,7 @@ unsigned long long *g_fb_counter[64] = {};
 
 template <int DP, int KP>
 void launch_fused(const KmArgs &a, int64_t nb, size_t lds, hipStream_t s) {
-    if (a.d == DP && (uintptr_t)a.X % 16 == 0)
+    if (a.d == DP && (uintptr_t)a.X % 16 == 0 && a.n * DP / 4 < (1LL << 32))
         hipLaunchKernelGGL((k_kmeans_fused<DP, KP, true>), dim3((unsigned)nb), dim3(NT), lds, s, a);
     else
         hipLaunchKernelGGL((k_kmeans_fused<DP, KP, false>), dim3((unsigned)nb), dim3(NT), lds, s, a);
