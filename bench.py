@@ -79,6 +79,10 @@ TRAFFIC = {
     # below and above it) + 67.10 MB written
     "stencil": {"file": "parboil.hip", "bytes": 140264894,
                 "source": "43811f5900aa96af3dc0bca90ae62f896a5a0aac06bc3e30816ec5f7f6f67ece"},
+    # k_kmeans_fused<32,64,true>, 2^20 x 32 points, k = 64: 134.57 MB fetched (X, 1.00x) + 8.52 MB written
+    # (labels and the block partials)
+    "kmeans": {"file": "kmeans.hip", "bytes": 143085207,
+               "source": "748aae8d06a39c6e68669e49103f19a7d1a7a8d7a8437bf10fd2f8063acfd059"},
     # k_seg_broadcast (row-span path): 2.66 MB fetched (offsets, gradients) + 128.71 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 131367569,
                       "source": "41a385e9b42d3423d8b8b71015ef1b28e3ec22adc775890c3decf79c03a8516c"},
@@ -812,12 +816,14 @@ def bench_kmeans(args):
                                "map(argmin reduce)+reduce-by-key, then SSE and its gradient wrt the points",
                    "n": n, "d": d, "k": k, "iterations": iters},
         # the step's x.c products run as three bfloat16 products each (high and
-        # middle parts), 3 x 2nkd flops at 2.5 PFLOP/s: 5 us, below the 16 us
-        # its 132 MB of HBM traffic need at 8 TB/s, so HBM bounds it
+        # middle parts), 3 x 2nkd flops at 2.5 PFLOP/s: 5 us, below the 17 us
+        # its 138 MB of HBM traffic need at 8 TB/s, so HBM is the roofline
         "roofline": {"bound": "hbm", "kernel": "k_kmeans_fused<32,64>",
                      "achieved": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]), 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]) / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": traffic_of("kmeans"),
+                     "limit": "VALU issue: ~1070 vector instructions per 64-point chunk (bfloat16 split, "
+                              "candidate selection, certification, reduce-by-key), two waves per SIMD",
                      "fp32_equivalent": {"TFLOP/s": round(ach, 2), "of_fp32_mfma_peak": round(ach / FP32_MFMA_PEAK_TFLOPS, 4),
                                          "what": "2nkd flops of the x.c products over the step's time, against the "
                                                  "FP32 matrix peak (the former FP32 16x16x4 kernel's bound)"}},
