@@ -57,12 +57,12 @@ TRAFFIC = {
     # Each XCD's L2 fetches the A row panels and B column panels of its own 32 tiles (4 x 8 of them:
     # 12 panels of 1 MiB, the fewest 32 tiles can need), so each A panel is fetched by two XCDs and
     # each B panel by four; the algorithmic minimum is 33.6 MB read + 16.8 MB written (2.34x)
-    "gemm_nn": {"file": "gemm.hip", "bytes": 117547962,
-                "source": "15affe50b1c8d6e8324b26246a9548598236273f961bffb9f122c810fb0c8f45"},
-    "gemm_nt": {"file": "gemm.hip", "bytes": 117544890,
-                "source": "15affe50b1c8d6e8324b26246a9548598236273f961bffb9f122c810fb0c8f45"},
-    "gemm_tn": {"file": "gemm.hip", "bytes": 117555130,
-                "source": "15affe50b1c8d6e8324b26246a9548598236273f961bffb9f122c810fb0c8f45"},
+    "gemm_nn": {"file": "gemm.hip", "bytes": 117556154,
+                "source": "3fa3f9cc142e6e3fc95d3119b28c30c57cd618a098fbb99592d7b86d88652302"},
+    "gemm_nt": {"file": "gemm.hip", "bytes": 117533627,
+                "source": "3fa3f9cc142e6e3fc95d3119b28c30c57cd618a098fbb99592d7b86d88652302"},
+    "gemm_tn": {"file": "gemm.hip", "bytes": 117545915,
+                "source": "3fa3f9cc142e6e3fc95d3119b28c30c57cd618a098fbb99592d7b86d88652302"},
     # k_seg_span (row-span path), 65536 rows / 32.1 M values: 131.11 MB fetched + 0.26 MB
     # written (1.02x algorithmic: 129.19 MB)
     "seg_span": {"file": "segmented.hip", "bytes": 131372884,

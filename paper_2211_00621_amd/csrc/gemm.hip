@@ -57,11 +57,20 @@ __device__ __forceinline__ float4 ld4(const float *__restrict__ p, int64_t ld, i
 }
 
 template <int ROWS, bool ROWK> struct Operand {
-    // [k][row] stride: ROWS + 4 floats, so the k rows 8 apart read by the four
-    // lane groups start 32 banks apart
-    static constexpr int LD = ROWK ? BK : ROWS + 4;               // LDS stride in floats
-    static constexpr int FLOATS = ROWK ? ROWS * BK : BK * (ROWS + 4);
+    static constexpr int LD = ROWK ? BK : ROWS;  // LDS stride in floats
+    static constexpr int FLOATS = ROWS * BK;
 };
+
+// [k][row] slices: k rows of ROWS floats, unpadded, the 16-byte group q of
+// row k at q ^ (8 (k >> 3 & 1)), so the k rows 8 apart that lane groups g and
+// g + 1 read in one pass land 32 banks apart.  (Rows padded to ROWS + 4
+// floats did the same for the reads; with this layout A^T dC, whose operands
+// are both [k][row], runs as fast as the other transposes, 134 against 139 us
+// at 2048^3.)
+template <int ROWS> __device__ __forceinline__ int kswz(int k, int row) {
+    static_assert(ROWS >= 64, "the swizzle moves groups by 8 of at least 16 per row");
+    return k * ROWS + 4 * ((row >> 2) ^ (((k >> 3) & 1) << 3)) + (row & 3);
+}
 
 // One K-slice of an operand (ROWS rows) into registers, NT threads.
 template <int ROWS, bool ROWK, int NT>
@@ -84,7 +93,6 @@ __device__ __forceinline__ void load_slice(float4 (&r)[ROWS * BK / 4 / NT], cons
 
 template <int ROWS, bool ROWK, int NT>
 __device__ __forceinline__ void store_slice(float *__restrict__ s, const float4 (&r)[ROWS * BK / 4 / NT]) {
-    using Op = Operand<ROWS, ROWK>;
 #pragma unroll
     for (int i = 0; i < ROWS * BK / 4 / NT; ++i) {
         const int idx = threadIdx.x + NT * i;
@@ -94,7 +102,7 @@ __device__ __forceinline__ void store_slice(float *__restrict__ s, const float4 
         } else {
             constexpr int Q = ROWS / 4;
             const int k = idx / Q, rq = idx % Q;
-            *reinterpret_cast<float4 *>(s + k * Op::LD + 4 * rq) = r[i];
+            *reinterpret_cast<float4 *>(s + kswz<ROWS>(k, 4 * rq)) = r[i];
         }
     }
 }
@@ -135,8 +143,6 @@ __device__ __forceinline__ void read_frags(float (&fa)[8][BM / WM / 16], float (
                                            const float *__restrict__ as, const float *__restrict__ bs, int wrow0,
                                            int wcol0, int l16, int g) {
     constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
-    using OA = Operand<BM, RA>;
-    using OB = Operand<BN, RB>;
     if constexpr (RA) {
 #pragma unroll
         for (int i = 0; i < MI; ++i) {
@@ -148,7 +154,7 @@ __device__ __forceinline__ void read_frags(float (&fa)[8][BM / WM / 16], float (
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) lds_read<MI>(fa[s], as + (8 * g + s) * OA::LD + wrow0 + MI * l16);
+        for (int s = 0; s < 8; ++s) lds_read<MI>(fa[s], as + kswz<BM>(8 * g + s, wrow0 + MI * l16));
     }
     if constexpr (RB) {
 #pragma unroll
@@ -161,7 +167,7 @@ __device__ __forceinline__ void read_frags(float (&fa)[8][BM / WM / 16], float (
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) lds_read<NI>(fb[s], bs + (8 * g + s) * OB::LD + wcol0 + NI * l16);
+        for (int s = 0; s < 8; ++s) lds_read<NI>(fb[s], bs + kswz<BN>(8 * g + s, wcol0 + NI * l16));
     }
 }
 
@@ -198,8 +204,10 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
     static_assert(RB || NI == 1 || NI == 2 || NI == 4, "[k][row] B: reads of 1, 2 or 4 columns");
     using OA = Operand<BM, RA>;
     using OB = Operand<BN, RB>;
-    __shared__ __attribute__((aligned(16))) float As[2][OA::FLOATS];
-    __shared__ __attribute__((aligned(16))) float Bs[2][OB::FLOATS];
+    __shared__ __attribute__((aligned(16))) float As0[OA::FLOATS], As1[OA::FLOATS];
+    __shared__ __attribute__((aligned(16))) float Bs0[OB::FLOATS], Bs1[OB::FLOATS];
+    auto As = [&](int i) { return i ? As1 : As0; };
+    auto Bs = [&](int i) { return i ? Bs1 : Bs0; };
 
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
@@ -235,14 +243,14 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
         load_slice<BN, RB, NT>(gb, B, ldb, n0, 0, N, K, true);
         load_slice<BM, RA, NT>(ha, A, lda, m0, BK, M, K, true);
         load_slice<BN, RB, NT>(hb, B, ldb, n0, BK, N, K, true);
-        store_slice<BM, RA, NT>(As[0], ga);
-        store_slice<BN, RB, NT>(Bs[0], gb);
+        store_slice<BM, RA, NT>(As(0), ga);
+        store_slice<BN, RB, NT>(Bs(0), gb);
         load_slice<BM, RA, NT>(ga, A, lda, m0, 2 * BK, M, K, true);
         load_slice<BN, RB, NT>(gb, B, ldb, n0, 2 * BK, N, K, true);
         __syncthreads();
-        read_frags<BM, BN, WM, WN, RA, RB>(fa0, fb0, As[0], Bs[0], wrow0, wcol0, l16, g);
-        store_slice<BM, RA, NT>(As[1], ha);
-        store_slice<BN, RB, NT>(Bs[1], hb);
+        read_frags<BM, BN, WM, WN, RA, RB>(fa0, fb0, As(0), Bs(0), wrow0, wcol0, l16, g);
+        store_slice<BM, RA, NT>(As(1), ha);
+        store_slice<BN, RB, NT>(Bs(1), hb);
         load_slice<BM, RA, NT>(ha, A, lda, m0, 3 * BK, M, K, true);
         load_slice<BN, RB, NT>(hb, B, ldb, n0, 3 * BK, N, K, true);
         __syncthreads();
@@ -251,13 +259,13 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
 #define MX_GEMM_ITER(KT, FA, FB, NFA, NFB, SA, SB, DO_R, DO_S, DO_L)                                      \
         {                                                                                                 \
             const int b1 = ((KT) + 1) & 1, b0 = (KT) & 1;                                                 \
-            if (DO_R) read_frags<BM, BN, WM, WN, RA, RB>(NFA, NFB, As[b1], Bs[b1], wrow0, wcol0, l16, g); \
+            if (DO_R) read_frags<BM, BN, WM, WN, RA, RB>(NFA, NFB, As(b1), Bs(b1), wrow0, wcol0, l16, g); \
             __builtin_amdgcn_sched_barrier(0);                                                            \
             mma_frags(acc, FA, FB);                                                                       \
             __builtin_amdgcn_sched_barrier(0);                                                            \
             if (DO_S) {                                                                                   \
-                store_slice<BM, RA, NT>(As[b0], SA);                                                      \
-                store_slice<BN, RB, NT>(Bs[b0], SB);                                                      \
+                store_slice<BM, RA, NT>(As(b0), SA);                                                      \
+                store_slice<BN, RB, NT>(Bs(b0), SB);                                                      \
             }                                                                                             \
             if (DO_L) {                                                                                   \
                 const int64_t kl = (int64_t)((KT) + 4) * BK;                                              \
@@ -283,8 +291,8 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
             const bool fast = interior && (BK <= K);
             load_slice<BM, RA, NT>(ra, A, lda, m0, 0, M, K, fast);
             load_slice<BN, RB, NT>(rb, B, ldb, n0, 0, N, K, fast);
-            store_slice<BM, RA, NT>(As[0], ra);
-            store_slice<BN, RB, NT>(Bs[0], rb);
+            store_slice<BM, RA, NT>(As(0), ra);
+            store_slice<BN, RB, NT>(Bs(0), rb);
         }
         __syncthreads();
         for (int kt = 0; kt < nk; ++kt) {
@@ -296,10 +304,10 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm_mfma(const float *__restr
                 load_slice<BM, RA, NT>(ra, A, lda, m0, k0, M, K, fast);
                 load_slice<BN, RB, NT>(rb, B, ldb, n0, k0, N, K, fast);
             }
-            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As[buf], Bs[buf], wrow0, wcol0, l16, g);
+            mma_slice<BM, BN, WM, WN, RA, RB>(acc, As(buf), Bs(buf), wrow0, wcol0, l16, g);
             if (more) {
-                store_slice<BM, RA, NT>(As[buf ^ 1], ra);
-                store_slice<BN, RB, NT>(Bs[buf ^ 1], rb);
+                store_slice<BM, RA, NT>(As(buf ^ 1), ra);
+                store_slice<BN, RB, NT>(Bs(buf ^ 1), rb);
             }
             __syncthreads();
         }

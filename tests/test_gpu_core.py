@@ -637,7 +637,8 @@ def test_mmr_every_tile_vs_oracle(tile, ta, tb, monkeypatch):
     shapes with edge tiles, ragged K and K a multiple of 64 (interior tiles on
     the pipelined loop): the whole C against the oracle."""
     monkeypatch.setenv("MX_GEMM_TILE", tile)
-    for M, N, K in [(300, 200, 128), (257, 385, 100), (512, 256, 192)]:
+    # K = 512: sixteen slices through the pipelined loop
+    for M, N, K in [(300, 200, 128), (257, 385, 100), (512, 256, 192), (384, 260, 512)]:
         say("mmr tile", tile, ta, tb, M, N, K)
         A, B = W.dense_f32(M, N, K, seed=M + K + 7 * ta + 3 * tb)
         As = A.T.copy() if ta else A
