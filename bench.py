@@ -173,7 +173,7 @@ def rotating(copies, fn):
 
 def hbm_read_ceiling(dev, nbytes, reps=50):
     """What the chip streams read-only: mx_stream_read (one contiguous 16 KB
-    chunk per block, 16-byte loads) over four rotating buffers of nbytes
+    chunk per block, 16-byte loads, one plain store per block) over four rotating buffers of nbytes
     (cold: 4 x nbytes exceeds the 256 MB last-level cache when nbytes is
     ~129 MB).  Per-launch durations, events around each launch."""
     import torch

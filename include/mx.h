@@ -126,13 +126,14 @@ size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux);
 mx_status mx_copy32(const void *src_dev, void *dst_dev, int64_t n, hipStream_t stream);
 
 /* Read-only streaming pass over n 32-bit words (the measured ceiling that
- * the memory-bound kernels are compared with): each block reads one
- * contiguous 16 KB chunk in 16-byte loads and XORs the XOR of its words into
- * xor_dev[block % MX_STREAM_READ_SLOTS]; xor_dev is a device array of
- * MX_STREAM_READ_SLOTS uint32 the caller zero-fills first, and the XOR of all
- * slots is the XOR of all n words (independent of block order).  src must be
- * 16-byte aligned.  Errors: MX_ERR_INVALID, MX_ERR_SHAPE. */
-#define MX_STREAM_READ_SLOTS 1024
+ * the memory-bound kernels are compared with): block b reads contiguous 16 KB
+ * chunks b, b + B, ... in 16-byte loads (B = min(chunks, MX_STREAM_READ_SLOTS):
+ * one chunk per block up to 256 MiB) and stores the XOR of its words into
+ * xor_dev[b] with a plain store (no atomics, which would slow the pass);
+ * xor_dev is a device array of MX_STREAM_READ_SLOTS uint32 the caller
+ * zero-fills first, and the XOR of all slots is the XOR of all n words.  src
+ * must be 16-byte aligned.  Errors: MX_ERR_INVALID, MX_ERR_SHAPE. */
+#define MX_STREAM_READ_SLOTS 16384
 mx_status mx_stream_read(const void *src_dev, int64_t n, uint32_t *xor_dev, hipStream_t stream);
 
 /* ======================================================================= */

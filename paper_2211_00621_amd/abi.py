@@ -119,12 +119,13 @@ def mx_copy32(src, dst, stream=None) -> None:
     _check(_L().mx_copy32(_dptr(src), _dptr(dst), n, _stream(stream)), "mx_copy32")
 
 
-MX_STREAM_READ_SLOTS = 1024
+MX_STREAM_READ_SLOTS = 16384
 
 
 def mx_stream_read(src, xor_slots, stream=None) -> None:
     """Read-only pass over src (16-byte aligned, 4-byte elements); the XOR of its words is XORed, block by
-    block, into the MX_STREAM_READ_SLOTS words of xor_slots (the XOR of the slots is the XOR of src)."""
+    block, into its own word of the MX_STREAM_READ_SLOTS words of xor_slots (the XOR of the slots is the XOR
+    of src)."""
     if src.element_size() != 4:
         raise MxError(MX_ERR_INVALID, "mx_stream_read: 4-byte elements expected")
     if xor_slots.numel() * xor_slots.element_size() < 4 * MX_STREAM_READ_SLOTS:

@@ -85,23 +85,26 @@ __global__ void __launch_bounds__(256) k_stream_read(const u32x4 *__restrict__ s
                                                      const uint32_t *__restrict__ tail, int ntail,
                                                      uint32_t *xor_out) {
     __shared__ uint32_t red[4];
-    const int64_t base = (int64_t)blockIdx.x * kReadChunkVec;
-    u32x4 x[kReadChunkVec / 256];
-#pragma unroll
-    for (int u = 0; u < kReadChunkVec / 256; ++u) {
-        const int64_t i = base + threadIdx.x + 256 * u;
-        x[u] = i < nv ? __builtin_nontemporal_load(src + i) : u32x4{0, 0, 0, 0};
-    }
+    const int64_t nchunks = (nv + kReadChunkVec - 1) / kReadChunkVec;
     uint32_t a = 0;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t base = c * kReadChunkVec;
+        u32x4 x[kReadChunkVec / 256];
 #pragma unroll
-    for (int u = 0; u < kReadChunkVec / 256; ++u) a ^= x[u].x ^ x[u].y ^ x[u].z ^ x[u].w;
+        for (int u = 0; u < kReadChunkVec / 256; ++u) {
+            const int64_t i = base + threadIdx.x + 256 * u;
+            x[u] = i < nv ? __builtin_nontemporal_load(src + i) : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < kReadChunkVec / 256; ++u) a ^= x[u].x ^ x[u].y ^ x[u].z ^ x[u].w;
+    }
     if (blockIdx.x == 0 && (int)threadIdx.x < ntail) a ^= tail[threadIdx.x];
     for (int d = 32; d > 0; d >>= 1) a ^= __shfl_xor(a, d);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = a;
     __syncthreads();
-    // spread over kReadSlots words: one shared word would serialise the
-    // blocks' atomics at one L2 channel
-    if (threadIdx.x == 0) atomicXor(xor_out + (blockIdx.x & (kReadSlots - 1)), red[0] ^ red[1] ^ red[2] ^ red[3]);
+    // one word per block: atomics into shared words measured the pass 20 %
+    // slower than plain stores
+    if (threadIdx.x == 0) xor_out[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
 }
 
 }  // namespace mx
@@ -213,8 +216,7 @@ mx_status mx_stream_read(const void *src_dev, int64_t n, uint32_t *xor_dev, hipS
     MX_REQUIRE(src_dev && xor_dev, MX_ERR_INVALID, "mx_stream_read: null pointer");
     MX_REQUIRE(((uintptr_t)src_dev % 16) == 0, MX_ERR_INVALID, "mx_stream_read: src must be 16-byte aligned");
     const int64_t nv = n / 4;
-    const int64_t blocks = std::max<int64_t>(1, ceil_div(nv, kReadChunkVec));
-    MX_REQUIRE(blocks <= 0x7fffffff, MX_ERR_SHAPE, "mx_stream_read: too large");
+    const int64_t blocks = std::min<int64_t>(kReadSlots, std::max<int64_t>(1, ceil_div(nv, kReadChunkVec)));
     hipLaunchKernelGGL(k_stream_read, dim3((unsigned)blocks), dim3(256), 0, stream, (const u32x4 *)src_dev, nv,
                        (const uint32_t *)src_dev + nv * 4, (int)(n & 3), xor_dev);
     return last_launch("mx_stream_read");

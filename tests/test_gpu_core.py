@@ -563,7 +563,8 @@ def test_debug_mode_rejects_bad_offsets():
     assert np.array_equal(host(out), np.zeros(3, dtype=np.float32))
 
 
-@pytest.mark.parametrize("n", [1, 3, 4, 5, 4099, 4096 * 1024 + 7, 1 << 24])
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 4099, 4096 * 1024 + 7, 1 << 24,
+                               16384 * 4096 + 5 * 4096 + 3])  # the last: blocks loop over chunks
 def test_stream_read_xor(n):
     """The read-only ceiling kernel reads every word exactly once: its XOR
     against numpy's."""
