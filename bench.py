@@ -68,13 +68,13 @@ TRAFFIC = {
     "seg_span": {"file": "segmented.hip", "bytes": 131372884,
                  "source": "41a385e9b42d3423d8b8b71015ef1b28e3ec22adc775890c3decf79c03a8516c"},
     # mx_xvjp (generated from expr.hip) for exp(-(a-b)^2)*0.5 + a*b over 2^26 float32 pairs:
-    # 536.88 MB fetched + 536.80 MB written (1.00x algorithmic)
-    "expr_vjp": {"file": "expr.hip", "bytes": 1073676893,
-                 "source": "69c512abf2ff185acf077b11dc4aa21aa7cc9d06465aee3d177aeccebbfac52c"},
+    # 536.89 MB fetched + 536.83 MB written (1.00x algorithmic)
+    "expr_vjp": {"file": "expr.hip", "bytes": 1073735829,
+                 "source": "61460c2f96be411e8917cad03f7a568e43228502abc50e0cff6db2ebedee319d"},
     # mx_xseg_add, same body over the nested step's 65 536 ragged rows (2 x 32.1 M values):
-    # 261.06 MB fetched + 0.26 MB written (1.01x algorithmic)
-    "expr_seg": {"file": "expr.hip", "bytes": 261321064,
-                 "source": "69c512abf2ff185acf077b11dc4aa21aa7cc9d06465aee3d177aeccebbfac52c"},
+    # 261.14 MB fetched + 0.26 MB written (1.01x algorithmic)
+    "expr_seg": {"file": "expr.hip", "bytes": 261411148,
+                 "source": "61460c2f96be411e8917cad03f7a568e43228502abc50e0cff6db2ebedee319d"},
     # k_stencil7, 512 x 512 x 64 float32: 73.15 MB fetched (1.09x: a 16-plane slab re-reads the planes
     # below and above it) + 67.10 MB written
     "stencil": {"file": "parboil.hip", "bytes": 140264894,
