@@ -40,8 +40,11 @@
 //
 // Persistent waves: a fixed grid of at most kMaxBlocks blocks, each wave
 // walking its own sequence of 64-point chunks and loading the next chunk's
-// points while it works on the current one, so the stream of X from HBM
-// overlaps the matrix-core work.
+// points while it certifies and adds the current one, so the stream of X from
+// HBM overlaps the work.  The products run one block of 16 points at a time
+// and the four lane groups' candidates are merged through lane swaps, not LDS,
+// so that at d = 32, k = 64 three blocks of four waves fit a CU (168
+// registers, 53.5 KB of LDS per block).
 //
 // Reduce-by-key from the registers that already hold the chunk: lane
 // (g, l16) holds dimensions 8g..8g+7 of points mi*16 + l16 and adds them to
@@ -64,9 +67,19 @@ namespace {
 constexpr int NT = 256;       // 4 waves
 constexpr int kWaves = NT / kWave;
 constexpr int kPtsWave = 64;  // points per wave chunk
-constexpr int kMaxBlocks = 512; // persistent grid (two blocks per CU on 256 CUs)
+constexpr int kMaxBlocks = 768; // persistent grid (three blocks per CU on 256 CUs)
 constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
-constexpr int kScrFloats = kPtsWave * 4 * 4 + kPtsWave;  // per wave: publication slots, label and rank
+
+// Per-wave LDS scratch in floats, then 64 ints of rank and label: with one
+// centroid chunk the two-candidate stage's indices and parts (64 + 4 x 64 x
+// 2), with more the publication slots (4 x 64 float4); in both the
+// reduce-by-key's idle slots (DP / 32 x 2 x 64 float4) and four staged points.
+__host__ __device__ constexpr int scr_floats(int DP, int KP) {
+    return ((KP == 64 ? 64 + 4 * kPtsWave * 2 : 4 * kPtsWave * 4) > DP * 16
+                ? (KP == 64 ? 64 + 4 * kPtsWave * 2 : 4 * kPtsWave * 4)
+                : DP * 16) +
+           kPtsWave;
+}
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -80,6 +93,29 @@ __device__ __forceinline__ void split_bf16(const float4 &u0, const float4 &u1, b
         hi[e] = h;
         mid[e] = (__bf16)(v[e] - (float)h);
     }
+}
+
+// inserts v into t1 <= t2 <= t3, keeping the three smallest (median forms: no
+// canonicalising of bit-built values)
+__device__ __forceinline__ void insert3(float &t1, float &t2, float &t3, float v) {
+    t3 = __builtin_amdgcn_fmed3f(t2, t3, v);
+    t2 = __builtin_amdgcn_fmed3f(t1, t2, v);
+    t1 = __builtin_amdgcn_fmed3f(t1, v, -FLT_MAX);
+}
+
+// lanes 32..63 of a trade places with lanes 0..31 of b (v_permlane32_swap)
+__device__ __forceinline__ void swap_halves(float &a, float &b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+// the odd 16-lane rows of a trade places with the even rows of b
+// (v_permlane16_swap)
+__device__ __forceinline__ void swap_rows(float &a, float &b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
 }
 
 // binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
@@ -139,12 +175,13 @@ struct KmArgs {
     unsigned long long *fallbacks;  // optional counter of binary64 recomputations
 };
 
-// Row stride of the LDS sums: d rounded up to 16 bytes, plus 16 bytes when
-// that is a multiple of 32 floats, so consecutive labels start on different
-// banks.
-__host__ __device__ inline int sums_ld(int d) {
-    const int r4 = (d + 3) & ~3;
-    return (r4 & 31) == 0 ? r4 + 4 : r4;
+// Row stride of the LDS sums: d rounded up to 16 bytes.  When that is a
+// multiple of 32 floats, row j keeps its 16-byte groups XOR-permuted by j mod 8
+// within each aligned run of eight, so that one column of consecutive labels
+// falls on different banks.
+__host__ __device__ inline int sums_ld(int d) { return (d + 3) & ~3; }
+__device__ __forceinline__ int sums_at(int j, int t, int ldd) {
+    return j * ldd + ((ldd & 31) == 0 ? t ^ ((j & 7) << 2) : t);
 }
 
 // Orders this wave's LDS writes before its later LDS reads (a wave's LDS
@@ -223,7 +260,7 @@ __device__ __forceinline__ void mask_chunk(float4 (&xa)[4][DP / 32][2], int d, i
 
 // DP: d padded to a multiple of 32; KP: k padded to a multiple of 64.
 template <int DP, int KP, bool VX>
-__global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_fused(KmArgs a) {
+__global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1) k_kmeans_fused(KmArgs a) {
     constexpr int LDC = DP + 4;
     constexpr int LBITS = KP <= 64 ? 6 : KP <= 128 ? 7 : 8;  // bits of a label
     extern __shared__ __attribute__((aligned(16))) float smem[];
@@ -232,34 +269,43 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     float *cnorm = Cs + KP * LDC;                      // [KP]
     float *sums_all = cnorm + KP;                      // [kWaves][k][ldd]
     int *counts_all = (int *)(sums_all + kWaves * k * ldd);  // [kWaves][k]
-    float *scr = (float *)(counts_all + kWaves * k);   // [kWaves][kScrFloats]
+    float *scr = (float *)(counts_all + kWaves * k);   // [kWaves][scr_floats]
     __shared__ float cmax_s;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, g = lane >> 4;
 
-    // -2 c into LDS (zero padded; the scaling is exact), |c|^2 (padding
-    // centroids get FLT_MAX, finite so that index packing keeps them
-    // ordered, and never below a real centroid's value), the largest norm
+    // the first chunk's points are in flight while the centroids are staged
+    const int64_t nchunks = (a.n + kPtsWave - 1) / kPtsWave;
+    const int64_t wstride = (int64_t)gridDim.x * kWaves;
+    int64_t c = (int64_t)blockIdx.x * kWaves + wave;  // wave-uniform
+    float4 xa[4][DP / 32][2];
+    if (c < nchunks) load_chunk<DP, VX>(xa, a, c, l16, g);
+
+    // -2 c into LDS (zero padded; the scaling is exact), then from those rows
+    // |c|^2 (c = -m2 / 2 exactly wherever -2c is finite; where it is not,
+    // |c|^2 overflows as well; padding centroids get FLT_MAX, finite so that
+    // index packing keeps them ordered, and never below a real centroid's
+    // value) and the largest norm
     for (int e = tid; e < KP * LDC; e += NT) {
         const int j = e / LDC, t = e - j * LDC;
         Cs[e] = (j < k && t < d) ? -2.0f * a.C[(int64_t)j * d + t] : 0.f;
     }
     for (int e = tid; e < kWaves * k * ldd; e += NT) sums_all[e] = 0.f;
     for (int e = tid; e < kWaves * k; e += NT) counts_all[e] = 0;
-    if (tid < KP) {
-        float s = 0.f;
-        if (tid < k)
-            for (int t = 0; t < d; ++t) {
-                const float v = a.C[(int64_t)tid * d + t];
-                s += v * v;
-            }
-        cnorm[tid] = tid < k ? s : FLT_MAX;
-    }
     __syncthreads();
     if (wave == 0) {
         float m = 0.f;
-        for (int j = lane; j < k; j += kWave) m = fmaxf(m, cnorm[j]);
+        for (int j = lane; j < KP; j += kWave) {
+            float s = 0.f;
+            if (j < k)
+                for (int t = 0; t < d; ++t) {
+                    const float v = -0.5f * Cs[j * LDC + t];
+                    s += v * v;
+                }
+            cnorm[j] = j < k ? s : FLT_MAX;
+            if (j < k) m = fmaxf(m, s);
+        }
         m = wave_reduce<Red<MX_MAX, float>>(m);
         if (lane == 0) cmax_s = sqrtf(m);
     }
@@ -290,21 +336,13 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
 
     float *ws = sums_all + wave * k * ldd;
     int *wc = counts_all + wave * k;
-    float4 *pub = reinterpret_cast<float4 *>(scr + wave * kScrFloats);  // [4 lane groups][64 points]
-    int *lr = reinterpret_cast<int *>(pub + 4 * kPtsWave);  // [64 points] rank << 16 | label, or -1
+    constexpr int kScr = scr_floats(DP, KP);
+    float4 *pub = reinterpret_cast<float4 *>(scr + wave * kScr);  // scratch, 16-byte aligned
+    int *lr = reinterpret_cast<int *>(scr + wave * kScr + kScr - kPtsWave);  // [64 points] rank << 16 | label, or -1
 
-    const int64_t nchunks = (a.n + kPtsWave - 1) / kPtsWave;
-    const int64_t wstride = (int64_t)gridDim.x * kWaves;
-    int64_t c = (int64_t)blockIdx.x * kWaves + wave;  // wave-uniform
-    float4 xa[4][DP / 32][2];
-    if (c < nchunks) load_chunk<DP, VX>(xa, a, c, l16, g);
     for (; c < nchunks; c += wstride) {
         const int64_t p0 = c * kPtsWave;
         mask_chunk<DP, VX>(xa, d, g);
-        // next chunk's points, in flight while this one is processed (the
-        // last chunk reloads itself rather than branch around the loads)
-        float4 xn[4][DP / 32][2];
-        load_chunk<DP, VX>(xn, a, c + wstride < nchunks ? c + wstride : c, l16, g);
 
         // this lane's part of |x|^2 (its eight or sixteen dimensions)
         float xpart[4];
@@ -326,140 +364,183 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
         //      accumulator starts at |c|^2, so lane (g, l16) ends with f for
         //      rows 4g + r (centroids) of column l16 (point) of each (centroid
         //      block ci, point block pi): 16 candidates per point in one lane.
-        //      Each f carries its candidate's slot ci*4 + r in its four low
-        //      mantissa bits, so one minimum gives value and index, and one
-        //      median of three keeps the second smallest value.
-        float r1[4], r2[4], r3[4];  // r3: the third smallest (one centroid chunk only)
-        int ri[4];
-#pragma unroll
-        for (int cc = 0; cc < KP / 64; ++cc) {
-            v4f acc[4][4];  // [ci][pi]
-            v4f cn[4];      // |c|^2 of rows 4g .. 4g+3 of each centroid block: the first product's source
+        //      Each f carries its candidate's index (one chunk: ci*16 + r in
+        //      its six low mantissa bits, the lane group's 4g added after the
+        //      selection; more chunks: its slot ci*4 + r in four bits), so one
+        //      minimum gives value and index, and medians of three keep the
+        //      next smallest.  Then the four lane groups of each point are
+        //      merged in a fixed order (lexicographic minimum).
+        float m1, m2, m3 = INFINITY, xx;  // m3: the third smallest (one centroid chunk only)
+        int mj, mj2 = -1;
+        if constexpr (KP == 64) {
+            // one point block at a time, so only its 16 accumulators are live
+            v4f cn[4];  // |c|^2 of rows 4g .. 4g+3 of each centroid block: the first product's source
 #pragma unroll
             for (int ci = 0; ci < 4; ++ci) {
-                const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + cc * 64 + ci * 16 + 4 * g);
+                const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + ci * 16 + 4 * g);
                 cn[ci] = v4f{c4.x, c4.y, c4.z, c4.w};
             }
-#pragma unroll
-            for (int kc = 0; kc < DP / 32; ++kc) {
-                // lane (g, l16) holds dimensions kc*32 + 8g .. +7 of point
-                // pi*16 + l16 (B operand) and of centroid row ci*16 + l16 (A)
-                bf16x8 bh[4], bm[4];
-#pragma unroll
-                for (int pi = 0; pi < 4; ++pi) split_bf16(xa[pi][kc][0], xa[pi][kc][1], bh[pi], bm[pi]);
-#pragma unroll
-                for (int ci = 0; ci < 4; ++ci) {
-                    bf16x8 ah, am;
-                    if constexpr (KP == 64) {
-                        ah = areg_h[ci][kc];
-                        am = areg_m[ci][kc];
-                    } else {
-                        a_ops(cc, ci, kc, ah, am);
-                    }
-#pragma unroll
-                    for (int pi = 0; pi < 4; ++pi)
-                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[pi], kc == 0 ? cn[ci] : acc[ci][pi],
-                                                                              0, 0, 0);
-#pragma unroll
-                    for (int pi = 0; pi < 4; ++pi)
-                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[pi], acc[ci][pi], 0, 0, 0);
-#pragma unroll
-                    for (int pi = 0; pi < 4; ++pi)
-                        acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[pi], acc[ci][pi], 0, 0, 0);
-                }
-            }
+            float r1[4], r2[4], r3[4];
 #pragma unroll
             for (int pi = 0; pi < 4; ++pi) {
+                v4f acc[4];
+#pragma unroll
+                for (int kc = 0; kc < DP / 32; ++kc) {
+                    // lane (g, l16) holds dimensions kc*32 + 8g .. +7 of point
+                    // pi*16 + l16 (B operand) and of centroid row ci*16 + l16 (A)
+                    bf16x8 bh, bm;
+                    split_bf16(xa[pi][kc][0], xa[pi][kc][1], bh, bm);
+#pragma unroll
+                    for (int ci = 0; ci < 4; ++ci)
+                        acc[ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(areg_h[ci][kc], bh, kc == 0 ? cn[ci] : acc[ci],
+                                                                          0, 0, 0);
+#pragma unroll
+                    for (int ci = 0; ci < 4; ++ci)
+                        acc[ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(areg_h[ci][kc], bm, acc[ci], 0, 0, 0);
+#pragma unroll
+                    for (int ci = 0; ci < 4; ++ci)
+                        acc[ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(areg_m[ci][kc], bh, acc[ci], 0, 0, 0);
+                }
                 float b1 = INFINITY, b2 = INFINITY, b3 = INFINITY;
 #pragma unroll
                 for (int ci = 0; ci < 4; ++ci)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        // one chunk: bits 0-1 and 4-5 carry r and ci of the
-                        // index ci*16 + 4g + r, bits 2-3 (the lane group's,
-                        // equal for every candidate of this lane) are set below
-                        const float f = KP == 64 ? __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~63u) |
-                                                                   (unsigned)(ci * 16 + r))
-                                                 : __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~15u) |
-                                                                   (unsigned)(ci * 4 + r));
-                        // median forms: no canonicalising of the bit-built f
-                        if constexpr (KP == 64) b3 = __builtin_amdgcn_fmed3f(b2, b3, f);
-                        b2 = __builtin_amdgcn_fmed3f(b1, b2, f);
-                        b1 = __builtin_amdgcn_fmed3f(b1, f, -FLT_MAX);
-                    }
-                if constexpr (KP == 64) {
-                    // the same two bits in every value keep the lane's order
-                    const unsigned gb = 4u * (unsigned)g;
-                    r1[pi] = __uint_as_float(__float_as_uint(b1) | gb);
-                    r2[pi] = __uint_as_float(__float_as_uint(b2) | gb);
-                    r3[pi] = __uint_as_float(__float_as_uint(b3) | gb);
-                    continue;
+                    for (int r = 0; r < 4; ++r)
+                        // bits 0-1 and 4-5 carry r and ci of the index
+                        // ci*16 + 4g + r; bits 2-3 (the lane group's, equal
+                        // for every candidate of this lane) are set below
+                        insert3(b1, b2, b3, __uint_as_float((__float_as_uint(acc[ci][r]) & ~63u) | (unsigned)(ci * 16 + r)));
+                // the same two bits in every value keep the lane's order
+                const unsigned gb = 4u * (unsigned)g;
+                r1[pi] = __uint_as_float(__float_as_uint(b1) | gb);
+                r2[pi] = __uint_as_float(__float_as_uint(b2) | gb);
+                r3[pi] = __uint_as_float(__float_as_uint(b3) | gb);
+            }
+            // The three smallest of the four lane groups' three smallest, in
+            // registers: lanes l and l ^ 32 (groups g and g ^ 2) exchange half
+            // their point blocks and merge, the lower half keeping blocks 0
+            // and 1, the upper 2 and 3; then rows r and r ^ 1 (groups g and
+            // g ^ 1) do the same, and row g is left with block g, whose
+            // column l16 is point 16g + l16: the lane's own.  Every value
+            // carries its whole index, so float order is (value, index)
+            // order wherever the values differ by more than the index bits,
+            // and the three smallest do not depend on the merge order.
+            float xp[4];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) xp[mi] = xpart[mi];
+#pragma unroll
+            for (int pi = 0; pi < 2; ++pi) {
+                swap_halves(r1[pi], r1[pi + 2]);
+                swap_halves(r2[pi], r2[pi + 2]);
+                swap_halves(r3[pi], r3[pi + 2]);
+                swap_halves(xp[pi], xp[pi + 2]);
+                insert3(r1[pi], r2[pi], r3[pi], r1[pi + 2]);
+                insert3(r1[pi], r2[pi], r3[pi], r2[pi + 2]);
+                insert3(r1[pi], r2[pi], r3[pi], r3[pi + 2]);
+                xp[pi] += xp[pi + 2];
+            }
+            swap_rows(r1[0], r1[1]);
+            swap_rows(r2[0], r2[1]);
+            swap_rows(r3[0], r3[1]);
+            swap_rows(xp[0], xp[1]);
+            insert3(r1[0], r2[0], r3[0], r1[1]);
+            insert3(r1[0], r2[0], r3[0], r2[1]);
+            insert3(r1[0], r2[0], r3[0], r3[1]);
+            m1 = r1[0];
+            m2 = r2[0];
+            m3 = r3[0];
+            xx = xp[0] + xp[1];
+            mj = (int)(__float_as_uint(m1) & 63u);
+            mj2 = (int)(__float_as_uint(m2) & 63u);
+        } else {
+            float r1[4], r2[4];
+            int ri[4];
+#pragma unroll
+            for (int cc = 0; cc < KP / 64; ++cc) {
+                v4f acc[4][4];  // [ci][pi]
+                v4f cn[4];
+#pragma unroll
+                for (int ci = 0; ci < 4; ++ci) {
+                    const float4 c4 = *reinterpret_cast<const float4 *>(cnorm + cc * 64 + ci * 16 + 4 * g);
+                    cn[ci] = v4f{c4.x, c4.y, c4.z, c4.w};
                 }
-                const int slot = (int)(__float_as_uint(b1) & 15u);
-                const int j1 = cc * 64 + (slot >> 2) * 16 + 4 * g + (slot & 3);
-                if (cc == 0) {
-                    r1[pi] = b1; ri[pi] = j1; r2[pi] = b2;
-                } else {  // later centroid chunks have larger indices: ties keep the earlier
-                    r2[pi] = fminf(fmaxf(r1[pi], b1), fminf(r2[pi], b2));
-                    ri[pi] = b1 < r1[pi] ? j1 : ri[pi];
-                    r1[pi] = fminf(r1[pi], b1);
+#pragma unroll
+                for (int kc = 0; kc < DP / 32; ++kc) {
+                    bf16x8 bh[4], bm[4];
+#pragma unroll
+                    for (int pi = 0; pi < 4; ++pi) split_bf16(xa[pi][kc][0], xa[pi][kc][1], bh[pi], bm[pi]);
+#pragma unroll
+                    for (int ci = 0; ci < 4; ++ci) {
+                        bf16x8 ah, am;
+                        a_ops(cc, ci, kc, ah, am);
+#pragma unroll
+                        for (int pi = 0; pi < 4; ++pi)
+                            acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[pi], kc == 0 ? cn[ci] : acc[ci][pi],
+                                                                                  0, 0, 0);
+#pragma unroll
+                        for (int pi = 0; pi < 4; ++pi)
+                            acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[pi], acc[ci][pi], 0, 0, 0);
+#pragma unroll
+                        for (int pi = 0; pi < 4; ++pi)
+                            acc[ci][pi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[pi], acc[ci][pi], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int pi = 0; pi < 4; ++pi) {
+                    float b1 = INFINITY, b2 = INFINITY;
+#pragma unroll
+                    for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float f = __uint_as_float((__float_as_uint(acc[ci][pi][r]) & ~15u) | (unsigned)(ci * 4 + r));
+                            // median forms: no canonicalising of the bit-built f
+                            b2 = __builtin_amdgcn_fmed3f(b1, b2, f);
+                            b1 = __builtin_amdgcn_fmed3f(b1, f, -FLT_MAX);
+                        }
+                    const int slot = (int)(__float_as_uint(b1) & 15u);
+                    const int j1 = cc * 64 + (slot >> 2) * 16 + 4 * g + (slot & 3);
+                    if (cc == 0) {
+                        r1[pi] = b1; ri[pi] = j1; r2[pi] = b2;
+                    } else {  // later centroid chunks have larger indices: ties keep the earlier
+                        r2[pi] = fminf(fmaxf(r1[pi], b1), fminf(r2[pi], b2));
+                        ri[pi] = b1 < r1[pi] ? j1 : ri[pi];
+                        r1[pi] = fminf(r1[pi], b1);
+                    }
                 }
             }
-        }
-        // every lane publishes (best, index, second, |x|^2 part) per point; with
-        // one centroid chunk (best, second, third, |x|^2 part), each value
-        // carrying its whole index
+            // every lane publishes (best, index, second, |x|^2 part) per
+            // point; the point's lane merges the four lane groups in order
 #pragma unroll
-        for (int pi = 0; pi < 4; ++pi)
-            pub[g * kPtsWave + pi * 16 + l16] =
-                KP == 64 ? make_float4(r1[pi], r2[pi], r3[pi], xpart[pi])
-                         : make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
-        wave_sync();
+            for (int pi = 0; pi < 4; ++pi)
+                pub[g * kPtsWave + pi * 16 + l16] = make_float4(r1[pi], __int_as_float(ri[pi]), r2[pi], xpart[pi]);
+            wave_sync();
+            float4 q = pub[lane];
+            m1 = q.x;
+            m2 = q.z;
+            xx = q.w;
+            mj = __float_as_int(q.y);
+#pragma unroll
+            for (int gg = 1; gg < 4; ++gg) {
+                q = pub[gg * kPtsWave + lane];
+                const int qj = __float_as_int(q.y);
+                const bool tk = q.x < m1 || (q.x == m1 && qj < mj);
+                m2 = fminf(fmaxf(m1, q.x), fminf(m2, q.z));
+                mj = tk ? qj : mj;
+                m1 = fminf(m1, q.x);
+                xx += q.w;
+            }
+        }
+        // next chunk's points, in flight while this one's labels are
+        // certified and its points added (the last chunk reloads itself
+        // rather than branch around the loads); issued after the products,
+        // so the two chunks' registers are not live across them
+        __builtin_amdgcn_sched_barrier(0);
+        float4 xn[4][DP / 32][2];
+        load_chunk<DP, VX>(xn, a, c + wstride < nchunks ? c + wstride : c, l16, g);
         // ---- certify each label (lane = point); uncertified points are
         //      recomputed in binary64 by the whole wave, lanes over centroids
         {
             const int64_t p = p0 + lane;
-            // merge the four lane groups in index order (lexicographic minimum)
-            float m1, m2, m3 = INFINITY, xx;
-            int mj, mj2 = -1;
-            if constexpr (KP == 64) {
-                // the three smallest of the four lane groups' three smallest:
-                // values with their whole index in the low bits, so float
-                // order is (value, index) order wherever the values differ
-                // by more than the index bits
-                m1 = m2 = INFINITY;
-                xx = 0.f;
-#pragma unroll
-                for (int gg = 0; gg < 4; ++gg) {
-                    const float4 q = pub[gg * kPtsWave + lane];
-                    const float v3[3] = {q.x, q.y, q.z};
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-                        m3 = __builtin_amdgcn_fmed3f(m2, m3, v3[e]);
-                        m2 = __builtin_amdgcn_fmed3f(m1, m2, v3[e]);
-                        m1 = __builtin_amdgcn_fmed3f(m1, v3[e], -FLT_MAX);
-                    }
-                    xx += q.w;
-                }
-                mj = (int)(__float_as_uint(m1) & 63u);
-                mj2 = (int)(__float_as_uint(m2) & 63u);
-            } else {
-                float4 q = pub[lane];
-                m1 = q.x;
-                m2 = q.z;
-                xx = q.w;
-                mj = __float_as_int(q.y);
-#pragma unroll
-                for (int gg = 1; gg < 4; ++gg) {
-                    q = pub[gg * kPtsWave + lane];
-                    const int qj = __float_as_int(q.y);
-                    const bool tk = q.x < m1 || (q.x == m1 && qj < mj);
-                    m2 = fminf(fmaxf(m1, q.x), fminf(m2, q.z));
-                    mj = tk ? qj : mj;
-                    m1 = fminf(m1, q.x);
-                    xx += q.w;
-                }
-            }
             int label = -1;
             bool certified = true, two = false;
             if (p < a.n) {
@@ -655,7 +736,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
         //      atomics run about one lane per clock); each row receives its
         //      points in increasing index order.  A pass issues all its reads
         //      before its writes; lanes with nothing to add in it read and
-        //      write their own slots in the (consumed) publication area.
+        //      write their own slots in the wave's scratch.
         //      Dimensions past d hold zeros in xa, so a 16-byte group that
         //      ends within round4(d) (inside the row) is added whole; groups
         //      past it are skipped.
@@ -677,33 +758,38 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
                 bool act[4];
 #pragma unroll
                 for (int mi = 0; mi < 4; ++mi) act[mi] = __ballot(Rm[mi] == m) != 0;
-                float4 *dst[4][DP / 32][2];
-                float4 sm[4][DP / 32][2];
+                // two point blocks at a time (the rows of a pass are distinct
+                // over all four)
 #pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
+                for (int m0 = 0; m0 < 4; m0 += 2) {
+                    float4 *dst[2][DP / 32][2];
+                    float4 sm[2][DP / 32][2];
 #pragma unroll
-                    for (int kc = 0; kc < DP / 32; ++kc)
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int t = kc * 32 + 8 * g + 4 * h;
-                            const bool live = Rm[mi] == m && (VX || t + 4 <= d4);
-                            dst[mi][kc][h] = live ? reinterpret_cast<float4 *>(ws + Lm[mi] * ldd + t)
-                                                  : junk + (kc * 2 + h) * kPtsWave;
-                            sm[mi][kc][h] = *(act[mi] ? dst[mi][kc][h] : pub);
-                        }
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
-                    if (act[mi]) {
+                    for (int u = 0; u < 2; ++u)
 #pragma unroll
                         for (int kc = 0; kc < DP / 32; ++kc)
 #pragma unroll
                             for (int h = 0; h < 2; ++h) {
-                                float4 v = sm[mi][kc][h];
-                                const float4 x = xa[mi][kc][h];
-                                v.x += x.x; v.y += x.y; v.z += x.z; v.w += x.w;
-                                *dst[mi][kc][h] = v;
+                                const int mi = m0 + u, t = kc * 32 + 8 * g + 4 * h;
+                                const bool live = Rm[mi] == m && (VX || t + 4 <= d4);
+                                dst[u][kc][h] = live ? reinterpret_cast<float4 *>(ws + sums_at(Lm[mi], t, ldd))
+                                                     : junk + (kc * 2 + h) * kPtsWave;
+                                sm[u][kc][h] = *(act[mi] ? dst[u][kc][h] : pub);
                             }
-                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (act[m0 + u]) {
+#pragma unroll
+                            for (int kc = 0; kc < DP / 32; ++kc)
+#pragma unroll
+                                for (int h = 0; h < 2; ++h) {
+                                    float4 v = sm[u][kc][h];
+                                    const float4 x = xa[m0 + u][kc][h];
+                                    v.x += x.x; v.y += x.y; v.z += x.z; v.w += x.w;
+                                    *dst[u][kc][h] = v;
+                                }
+                        }
+                }
             }
         }
         wave_sync();
@@ -721,9 +807,10 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? 2 : 1) k_kmeans_f
     float *ps = a.part_sums + (int64_t)blockIdx.x * kd;
     for (int e = tid; e < kd; e += NT) {
         const int j = e / d, t = e - j * d;
-        float s = sums_all[j * ldd + t];
+        const int at = sums_at(j, t, ldd);
+        float s = sums_all[at];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += sums_all[(w * k + j) * ldd + t];
+        for (int w = 1; w < kWaves; ++w) s += sums_all[w * k * ldd + at];
         ps[e] = s;
     }
     int *pc = a.part_counts + (int64_t)blockIdx.x * k;
@@ -924,7 +1011,7 @@ int64_t fused_blocks(int64_t n) {
 
 size_t fused_lds_bytes(int DP, int KP, int k, int d) {
     return (size_t)KP * (DP + 4) * 4 + (size_t)KP * 4 + (size_t)kWaves * k * sums_ld(d) * 4 + (size_t)kWaves * k * 4 +
-           (size_t)kWaves * kScrFloats * 4;
+           (size_t)kWaves * scr_floats(DP, KP) * 4;
 }
 
 size_t ws_layout(int64_t n, int d, int k, size_t *sums_off, size_t *counts_off, size_t *plain_off) {
