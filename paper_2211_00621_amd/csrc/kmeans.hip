@@ -84,15 +84,26 @@ __host__ __device__ constexpr int scr_floats(int DP, int KP) {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// v = hi + mid + (a remainder of at most 2^-16 |v|), hi and mid bfloat16
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// v = hi + mid + (a remainder of at most 2^-16 |v|), hi and mid bfloat16 (round
+// to nearest even); each pair is converted once and its two high parts read
+// back from the packed word (a bfloat16 is the top half of a float)
 __device__ __forceinline__ void split_bf16(const float4 &u0, const float4 &u1, bf16x8 &hi, bf16x8 &mid) {
     const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    unsigned hw[4], mw[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)v[e];
-        hi[e] = h;
-        mid[e] = (__bf16)(v[e] - (float)h);
+    for (int e = 0; e < 4; ++e) {
+        const unsigned h = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){v[2 * e], v[2 * e + 1]}, bf16x2));
+        const float h0 = __uint_as_float(h << 16), h1 = __uint_as_float(h & 0xffff0000u);
+        hw[e] = h;
+        mw[e] = __builtin_bit_cast(unsigned,
+                                   __builtin_convertvector((f32x2){v[2 * e] - h0, v[2 * e + 1] - h1}, bf16x2));
     }
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    hi = __builtin_bit_cast(bf16x8, (u32x4){hw[0], hw[1], hw[2], hw[3]});
+    mid = __builtin_bit_cast(bf16x8, (u32x4){mw[0], mw[1], mw[2], mw[3]});
 }
 
 // inserts v into t1 <= t2 <= t3, keeping the three smallest (median forms: no
@@ -264,7 +275,8 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
     constexpr int LDC = DP + 4;
     constexpr int LBITS = KP <= 64 ? 6 : KP <= 128 ? 7 : 8;  // bits of a label
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    const int d = a.d, k = a.k, ldd = sums_ld(d);
+    const int d = a.d, k = a.k;
+    const int ldd = VX ? DP : sums_ld(d);              // VX: d == DP
     float *Cs = smem;                                  // [KP][LDC]
     float *cnorm = Cs + KP * LDC;                      // [KP]
     float *sums_all = cnorm + KP;                      // [kWaves][k][ldd]
@@ -718,15 +730,18 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
             if (label >= 0) atomicAdd(&wc[label], 1);  // integer: order-free
             // rank among the chunk's earlier points with the same label: the
             // lanes with an equal label, found one label bit at a time
-            uint64_t same = __ballot(label >= 0);
+            const uint64_t valid = __ballot(label >= 0);
+            uint32_t slo = (uint32_t)valid, shi = (uint32_t)(valid >> 32);
 #pragma unroll
             for (int b = 0; b < LBITS; ++b) {
-                const bool bit = (label >> b) & 1;
-                const uint64_t mb = __ballot(bit);
-                same &= bit ? mb : ~mb;
+                // all ones where bit b of the label is set; the lanes that
+                // agree with it on bit b are ~(ballot ^ m)
+                const uint32_t m = (uint32_t)((int)((uint32_t)label << (31 - b)) >> 31);
+                const uint64_t mb = __ballot(m != 0u);
+                slo &= ~((uint32_t)mb ^ m);
+                shi &= ~((uint32_t)(mb >> 32) ^ m);
             }
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi(shi, __builtin_amdgcn_mbcnt_lo(slo, 0u));
             lr[lane] = label >= 0 ? (rank << 16) | label : -1;
         }
         wave_sync();
