@@ -822,8 +822,8 @@ def bench_kmeans(args):
                      "achieved": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]), 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs(4 * n * d + 4 * n, parts["kmeans_step"]) / HBM_PEAK_GBS, 4),
                      "traffic": traffic_of("kmeans"),
-                     "limit": "VALU issue: ~1070 vector instructions per 64-point chunk (bfloat16 split, "
-                              "candidate selection, certification, reduce-by-key), two waves per SIMD",
+                     "limit": "VALU issue: ~1100 vector instructions per 64-point chunk (bfloat16 split, "
+                              "candidate selection, certification, reduce-by-key), three waves per SIMD",
                      "fp32_equivalent": {"TFLOP/s": round(ach, 2), "of_fp32_mfma_peak": round(ach / FP32_MFMA_PEAK_TFLOPS, 4),
                                          "what": "2nkd flops of the x.c products over the step's time, against the "
                                                  "FP32 matrix peak (the former FP32 16x16x4 kernel's bound)"}},

@@ -309,11 +309,18 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
     if (wave == 0) {
         float m = 0.f;
         for (int j = lane; j < KP; j += kWave) {
+            // over the DP padded dimensions: past d the rows hold zeros, whose
+            // squares add exact zeros
             float s = 0.f;
             if (j < k)
-                for (int t = 0; t < d; ++t) {
-                    const float v = -0.5f * Cs[j * LDC + t];
-                    s += v * v;
+#pragma unroll
+                for (int t = 0; t < DP; t += 4) {
+                    const float4 u = *reinterpret_cast<const float4 *>(Cs + j * LDC + t);
+                    const float v0 = -0.5f * u.x, v1 = -0.5f * u.y, v2 = -0.5f * u.z, v3 = -0.5f * u.w;
+                    s += v0 * v0;
+                    s += v1 * v1;
+                    s += v2 * v2;
+                    s += v3 * v3;
                 }
             cnorm[j] = j < k ? s : FLT_MAX;
             if (j < k) m = fmaxf(m, s);
