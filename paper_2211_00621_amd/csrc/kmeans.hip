@@ -144,7 +144,9 @@ __device__ __forceinline__ double dist64(const float *__restrict__ x, const floa
 template <int DP>
 __device__ __forceinline__ double dist64_m2(const float *x, const float *m2) {
     double acc = 0.0;
-#pragma unroll
+    // two 16-byte groups of each row at a time: the rare paths that call
+    // these keep few registers beside the chunk's
+#pragma unroll 2
     for (int t = 0; t < DP; t += 4) {
         const float4 xv = *reinterpret_cast<const float4 *>(x + t);
         const float4 cv = *reinterpret_cast<const float4 *>(m2 + t);
@@ -162,7 +164,7 @@ __device__ __forceinline__ double dist64_m2(const float *x, const float *m2) {
 template <int DP>
 __device__ __forceinline__ float dist32_m2(const float *x, const float *m2) {
     float acc = 0.f;
-#pragma unroll
+#pragma unroll 2
     for (int t = 0; t < DP; t += 4) {
         const float4 xv = *reinterpret_cast<const float4 *>(x + t);
         const float4 cv = *reinterpret_cast<const float4 *>(m2 + t);
