@@ -69,6 +69,9 @@ constexpr int kWaves = NT / kWave;
 constexpr int kPtsWave = 64;  // points per wave chunk
 constexpr int kMaxBlocks = 768; // persistent grid (three blocks per CU on 256 CUs)
 constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
+// finish kernel: a block owns kFinEntries entries (j, t), its kFinGroups thread
+// groups take the block partials in turn
+constexpr int kFinEntries = 8, kFinGroups = NT / kFinEntries;
 
 // Per-wave LDS scratch in floats, then 64 ints of rank and label: with one
 // centroid chunk the two-candidate stage's indices and parts (64 + 4 x 64 x
@@ -183,8 +186,8 @@ struct KmArgs {
     int d, k;
     const float *C;
     int32_t *labels;
-    float *part_sums;   // [nblocks][k*d]
-    int *part_counts;   // [nblocks][k]
+    float *part_sums;   // [ceil(k*d / 8)][nblocks][8]: entry e of block b at (e / 8 * nblocks + b) * 8 + e % 8
+    int *part_counts;   // [k][nblocks]
     unsigned long long *fallbacks;  // optional counter of binary64 recomputations
 };
 
@@ -828,29 +831,33 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
     __syncthreads();
     // ---- block partial: waves added in wave order
     const int kd = k * d;
-    float *ps = a.part_sums + (int64_t)blockIdx.x * kd;
+    // entry groups of 8 with the blocks side by side, so that the finish
+    // kernel's waves read eight blocks' groups as 256 contiguous bytes
+    float *ps = a.part_sums + (int64_t)blockIdx.x * kFinEntries;
     for (int e = tid; e < kd; e += NT) {
         const int j = e / d, t = e - j * d;
         const int at = sums_at(j, t, ldd);
         float s = sums_all[at];
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) s += sums_all[w * k * ldd + at];
-        ps[e] = s;
+        ps[(int64_t)(e / kFinEntries) * gridDim.x * kFinEntries + e % kFinEntries] = s;
     }
-    int *pc = a.part_counts + (int64_t)blockIdx.x * k;
+    int *pc = a.part_counts + blockIdx.x;  // label j at [j * gridDim.x]
     for (int j = tid; j < k; j += NT) {
         int cn = counts_all[j];
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) cn += counts_all[w * k + j];
-        pc[j] = cn;
+        pc[(int64_t)j * gridDim.x] = cn;
     }
 }
 
 // Adds the block partials in a fixed order (binary64), divides, writes C' and
 // counts.  A block owns 8 entries (j, t); its 32 thread groups take block
 // partials b = group, group + 32, ... and the 32 group sums are added in group
-// order, so the result does not depend on scheduling.
-constexpr int kFinEntries = 8, kFinGroups = NT / kFinEntries;
+// order, so the result does not depend on scheduling.  The partials of one
+// entry group sit block after block, so a wave (eight groups) reads eight
+// consecutive blocks' entries as 256 contiguous bytes, and their counts as
+// eight consecutive ints.
 
 __global__ void __launch_bounds__(NT) k_kmeans_finish(const float *__restrict__ part_sums,
                                                       const int *__restrict__ part_counts, int nblocks,
@@ -861,20 +868,22 @@ __global__ void __launch_bounds__(NT) k_kmeans_finish(const float *__restrict__ 
     const int kd = k * d;
     const int le = threadIdx.x % kFinEntries, grp = threadIdx.x / kFinEntries;
     const int e = blockIdx.x * kFinEntries + le;
+    const float *grp_sums = part_sums + (int64_t)blockIdx.x * nblocks * kFinEntries + le;  // block b at [b * 8]
     const int j = e < kd ? e / d : 0;
+    const int *grp_counts = part_counts + (int64_t)j * nblocks;  // block b at [b]
     double s = 0.0;
     long long c = 0;
     if (e < kd) {
         int b = grp;
         for (; b + 3 * kFinGroups < nblocks; b += 4 * kFinGroups) {
-            const float p0 = part_sums[(int64_t)b * kd + e];
-            const float p1 = part_sums[(int64_t)(b + kFinGroups) * kd + e];
-            const float p2 = part_sums[(int64_t)(b + 2 * kFinGroups) * kd + e];
-            const float p3 = part_sums[(int64_t)(b + 3 * kFinGroups) * kd + e];
-            const int c0 = part_counts[(int64_t)b * k + j];
-            const int c1 = part_counts[(int64_t)(b + kFinGroups) * k + j];
-            const int c2 = part_counts[(int64_t)(b + 2 * kFinGroups) * k + j];
-            const int c3 = part_counts[(int64_t)(b + 3 * kFinGroups) * k + j];
+            const float p0 = grp_sums[(int64_t)b * kFinEntries];
+            const float p1 = grp_sums[(int64_t)(b + kFinGroups) * kFinEntries];
+            const float p2 = grp_sums[(int64_t)(b + 2 * kFinGroups) * kFinEntries];
+            const float p3 = grp_sums[(int64_t)(b + 3 * kFinGroups) * kFinEntries];
+            const int c0 = grp_counts[b];
+            const int c1 = grp_counts[(b + kFinGroups)];
+            const int c2 = grp_counts[(b + 2 * kFinGroups)];
+            const int c3 = grp_counts[(b + 3 * kFinGroups)];
             s += (double)p0;
             s += (double)p1;
             s += (double)p2;
@@ -882,8 +891,8 @@ __global__ void __launch_bounds__(NT) k_kmeans_finish(const float *__restrict__ 
             c += (long long)c0 + c1 + c2 + c3;
         }
         for (; b < nblocks; b += kFinGroups) {
-            s += (double)part_sums[(int64_t)b * kd + e];
-            c += part_counts[(int64_t)b * k + j];
+            s += (double)grp_sums[(int64_t)b * kFinEntries];
+            c += grp_counts[b];
         }
     }
     ssum[grp][le] = s;
@@ -1042,7 +1051,7 @@ size_t ws_layout(int64_t n, int d, int k, size_t *sums_off, size_t *counts_off, 
     const int64_t nb = fused_blocks(n);
     size_t off = kCounterBytes;
     *sums_off = off;
-    off += align256((size_t)nb * (size_t)k * (size_t)d * 4);
+    off += align256((size_t)nb * (size_t)ceil_div(k * d, kFinEntries) * kFinEntries * 4);
     *counts_off = off;
     off += align256((size_t)nb * (size_t)k * 4);
     *plain_off = off;  // plain: sums [k*d] floats then counts [k] ints
