@@ -875,20 +875,19 @@ __global__ void __launch_bounds__(NT) k_kmeans_finish(const float *__restrict__ 
     long long c = 0;
     if (e < kd) {
         int b = grp;
-        for (; b + 3 * kFinGroups < nblocks; b += 4 * kFinGroups) {
-            const float p0 = grp_sums[(int64_t)b * kFinEntries];
-            const float p1 = grp_sums[(int64_t)(b + kFinGroups) * kFinEntries];
-            const float p2 = grp_sums[(int64_t)(b + 2 * kFinGroups) * kFinEntries];
-            const float p3 = grp_sums[(int64_t)(b + 3 * kFinGroups) * kFinEntries];
-            const int c0 = grp_counts[b];
-            const int c1 = grp_counts[(b + kFinGroups)];
-            const int c2 = grp_counts[(b + 2 * kFinGroups)];
-            const int c3 = grp_counts[(b + 3 * kFinGroups)];
-            s += (double)p0;
-            s += (double)p1;
-            s += (double)p2;
-            s += (double)p3;
-            c += (long long)c0 + c1 + c2 + c3;
+        for (; b + 7 * kFinGroups < nblocks; b += 8 * kFinGroups) {
+            float p[8];
+            int cq[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                p[i] = grp_sums[(int64_t)(b + i * kFinGroups) * kFinEntries];
+                cq[i] = grp_counts[b + i * kFinGroups];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                s += (double)p[i];
+                c += cq[i];
+            }
         }
         for (; b < nblocks; b += kFinGroups) {
             s += (double)grp_sums[(int64_t)b * kFinEntries];
