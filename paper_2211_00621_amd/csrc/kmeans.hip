@@ -582,15 +582,21 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
             //      the larger distance the point goes on to the stages below
             if constexpr (KP == 64) {
                 if (__ballot(two)) {
-                    int *jj = reinterpret_cast<int *>(pub);                  // [64] both indices
-                    float2 *part = reinterpret_cast<float2 *>(pub + 16);     // [4 lane groups][64 points]
-                    wave_sync();
-                    jj[lane] = two ? (mj | (mj2 << 16)) : -1;
-                    wave_sync();
+                    // both indices of each point to the four lanes holding
+                    // its dimensions: every lane gets the words of the four
+                    // lanes of its 16-lane column (rows 0 and 1 of the column
+                    // by a row swap, then rows 2 and 3 by a half swap)
+                    float w0 = __int_as_float(two ? (mj | (mj2 << 16)) : -1), w1 = w0;
+                    swap_rows(w0, w1);  // rows 2 (g >> 1) and 2 (g >> 1) + 1
+                    float w2 = w0, w3 = w1;
+                    swap_halves(w0, w2);  // w0: row 0, w2: row 2
+                    swap_halves(w1, w3);  // w1: row 1, w3: row 3
+                    const int vv[4] = {__float_as_int(w0), __float_as_int(w1), __float_as_int(w2), __float_as_int(w3)};
+                    float2 sd[4];
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi) {
-                        const int v = jj[mi * 16 + l16];
-                        float2 sd = make_float2(0.f, 0.f);
+                        const int v = vv[mi];  // point mi * 16 + l16
+                        sd[mi] = make_float2(0.f, 0.f);
                         if (v >= 0) {
                             const float *c1 = Cs + (v & 0xffff) * LDC, *c2 = Cs + (v >> 16) * LDC;
 #pragma unroll
@@ -606,22 +612,26 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
                                         const float x_ = vget<float4, float>(xv, e);
                                         const float d1 = x_ + 0.5f * vget<float4, float>(u1, e);
                                         const float d2 = x_ + 0.5f * vget<float4, float>(u2, e);
-                                        sd.x += d1 * d1;
-                                        sd.y += d2 * d2;
+                                        sd[mi].x += d1 * d1;
+                                        sd[mi].y += d2 * d2;
                                     }
                                 }
                         }
-                        part[g * kPtsWave + mi * 16 + l16] = sd;
                     }
-                    wave_sync();
-                    if (two) {
-                        float D1 = 0.f, D2 = 0.f;
+                    // the four lane groups' parts to the point's lane, as in
+                    // the merge above (a summation tree; the bound below
+                    // holds for any order of the additions)
 #pragma unroll
-                        for (int gg = 0; gg < 4; ++gg) {
-                            const float2 q = part[gg * kPtsWave + lane];
-                            D1 += q.x;
-                            D2 += q.y;
-                        }
+                    for (int pi = 0; pi < 2; ++pi) {
+                        swap_halves(sd[pi].x, sd[pi + 2].x);
+                        swap_halves(sd[pi].y, sd[pi + 2].y);
+                        sd[pi].x += sd[pi + 2].x;
+                        sd[pi].y += sd[pi + 2].y;
+                    }
+                    swap_rows(sd[0].x, sd[1].x);
+                    swap_rows(sd[0].y, sd[1].y);
+                    if (two) {
+                        const float D1 = sd[0].x + sd[1].x, D2 = sd[0].y + sd[1].y;
                         // relative bound: subnormal squares add at most
                         // 2^-149 each, negligible once the larger sum is 2^-90
                         const float E2 = 2.0f * (float)(d + 3) * 5.9604645e-8f * fmaxf(D1, D2);
@@ -630,7 +640,6 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
                             label = D1 < D2 ? mj : mj2;
                         }
                     }
-                    wave_sync();
                 }
             }
             uint64_t todo = __ballot(!certified);
