@@ -73,15 +73,11 @@ constexpr int kMaxD = 64, kMaxK = 256, kMaxKD = 4096;
 // groups take the block partials in turn
 constexpr int kFinEntries = 8, kFinGroups = NT / kFinEntries;
 
-// Per-wave LDS scratch in floats, then 64 ints of rank and label: with one
-// centroid chunk the two-candidate stage's indices and parts (64 + 4 x 64 x
-// 2), with more the publication slots (4 x 64 float4); in both the
-// reduce-by-key's idle slots (DP / 32 x 2 x 64 float4) and four staged points.
+// Per-wave LDS scratch in floats: the reduce-by-key's idle slots (DP / 32 x 2
+// x 64 float4), which also hold four staged points (4 x DP), and with more
+// than one centroid chunk the publication slots (4 x 64 float4).
 __host__ __device__ constexpr int scr_floats(int DP, int KP) {
-    return ((KP == 64 ? 64 + 4 * kPtsWave * 2 : 4 * kPtsWave * 4) > DP * 16
-                ? (KP == 64 ? 64 + 4 * kPtsWave * 2 : 4 * kPtsWave * 4)
-                : DP * 16) +
-           kPtsWave;
+    return (KP > 64 && 4 * kPtsWave * 4 > DP * 16) ? 4 * kPtsWave * 4 : DP * 16;
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -118,18 +114,45 @@ __device__ __forceinline__ void insert3(float &t1, float &t2, float &t3, float v
 }
 
 // lanes 32..63 of a trade places with lanes 0..31 of b (v_permlane32_swap)
+__device__ __forceinline__ void swap_halves(unsigned &a, unsigned &b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
 __device__ __forceinline__ void swap_halves(float &a, float &b) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    a = __uint_as_float(r[0]);
-    b = __uint_as_float(r[1]);
+    unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
+    swap_halves(ua, ub);
+    a = __uint_as_float(ua);
+    b = __uint_as_float(ub);
 }
 
 // the odd 16-lane rows of a trade places with the even rows of b
 // (v_permlane16_swap)
+__device__ __forceinline__ void swap_rows(unsigned &a, unsigned &b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
 __device__ __forceinline__ void swap_rows(float &a, float &b) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    a = __uint_as_float(r[0]);
-    b = __uint_as_float(r[1]);
+    unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
+    swap_rows(ua, ub);
+    a = __uint_as_float(ua);
+    b = __uint_as_float(ub);
+}
+
+// The words of the four lanes of this lane's 16-lane column (the same lane
+// of rows 0..3): rows 2 (g >> 1) and 2 (g >> 1) + 1 by a row swap, then the
+// other half's by a half swap.
+__device__ __forceinline__ void column4(int v, int (&out)[4]) {
+    unsigned w0 = (unsigned)v, w1 = w0;
+    swap_rows(w0, w1);
+    unsigned w2 = w0, w3 = w1;
+    swap_halves(w0, w2);  // w0: row 0, w2: row 2
+    swap_halves(w1, w3);  // w1: row 1, w3: row 3
+    out[0] = (int)w0;
+    out[1] = (int)w1;
+    out[2] = (int)w2;
+    out[3] = (int)w3;
 }
 
 // binary64 distance in the oracle's order: acc = acc + (x_t - c_t)^2, t ascending
@@ -362,7 +385,6 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
     int *wc = counts_all + wave * k;
     constexpr int kScr = scr_floats(DP, KP);
     float4 *pub = reinterpret_cast<float4 *>(scr + wave * kScr);  // scratch, 16-byte aligned
-    int *lr = reinterpret_cast<int *>(scr + wave * kScr + kScr - kPtsWave);  // [64 points] rank << 16 | label, or -1
 
     for (; c < nchunks; c += wstride) {
         const int64_t p0 = c * kPtsWave;
@@ -561,6 +583,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
         __builtin_amdgcn_sched_barrier(0);
         float4 xn[4][DP / 32][2];
         load_chunk<DP, VX>(xn, a, c + wstride < nchunks ? c + wstride : c, l16, g);
+        int lrv;  // this lane's point: rank << 16 | label, or -1
         // ---- certify each label (lane = point); uncertified points are
         //      recomputed in binary64 by the whole wave, lanes over centroids
         {
@@ -583,15 +606,9 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
             if constexpr (KP == 64) {
                 if (__ballot(two)) {
                     // both indices of each point to the four lanes holding
-                    // its dimensions: every lane gets the words of the four
-                    // lanes of its 16-lane column (rows 0 and 1 of the column
-                    // by a row swap, then rows 2 and 3 by a half swap)
-                    float w0 = __int_as_float(two ? (mj | (mj2 << 16)) : -1), w1 = w0;
-                    swap_rows(w0, w1);  // rows 2 (g >> 1) and 2 (g >> 1) + 1
-                    float w2 = w0, w3 = w1;
-                    swap_halves(w0, w2);  // w0: row 0, w2: row 2
-                    swap_halves(w1, w3);  // w1: row 1, w3: row 3
-                    const int vv[4] = {__float_as_int(w0), __float_as_int(w1), __float_as_int(w2), __float_as_int(w3)};
+                    // its dimensions
+                    int vv[4];
+                    column4(two ? (mj | (mj2 << 16)) : -1, vv);
                     float2 sd[4];
 #pragma unroll
                     for (int mi = 0; mi < 4; ++mi) {
@@ -763,7 +780,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
                 shi &= ~((uint32_t)(mb >> 32) ^ m);
             }
             const int rank = (int)__builtin_amdgcn_mbcnt_hi(shi, __builtin_amdgcn_mbcnt_lo(slo, 0u));
-            lr[lane] = label >= 0 ? (rank << 16) | label : -1;
+            lrv = label >= 0 ? (rank << 16) | label : -1;
         }
         wave_sync();
         // ---- reduce-by-key from registers.  Pass m adds every point whose
@@ -777,11 +794,12 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
         //      ends within round4(d) (inside the row) is added whole; groups
         //      past it are skipped.
         {
-            int Lm[4], Rm[4];
+            int Lm[4], Rm[4], lv[4];
             int rmax = -1;
+            column4(lrv, lv);  // the words of points mi * 16 + l16
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) {
-                const int v = lr[mi * 16 + l16];
+                const int v = lv[mi];
                 Lm[mi] = v & 0xffff;
                 Rm[mi] = v >> 16;  // -1 for points past n
                 rmax = max(rmax, Rm[mi]);
