@@ -82,7 +82,7 @@ TRAFFIC = {
     # k_kmeans_fused<32,64,true>, 2^20 x 32 points, k = 64: 134.68 MB fetched (X, 1.00x) + 12.11 MB written
     # (labels, and 768 block partials stored in 32-byte entry groups)
     "kmeans": {"file": "kmeans.hip", "bytes": 146787426,
-               "source": "3db413362bb1a7910b1a47fda713be96fd4d796ee74234e7fa307ffd72982a3e"},
+               "source": "25b5e41069dab98000d6e15e1b18c2272ec8ddfe0a6610b9fd18783f12bd8f78"},
     # k_seg_broadcast (row-span path): 2.66 MB fetched (offsets, gradients) + 128.71 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 131369561,
                       "source": "4591dbff6e2ae985187283e120835b639db112f15889f0bf806ec717990a8de6"},

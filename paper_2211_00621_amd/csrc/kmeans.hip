@@ -662,7 +662,7 @@ __global__ void __launch_bounds__(NT, (DP == 32 && KP == 64) ? (VX ? 3 : 2) : 1)
             uint64_t todo = __ballot(!certified);
             // Uncertified points, four at a time: the points' coordinates go
             // from the registers that hold them (four lanes each) to this
-            // wave's publication slots (read above); row s of 16 lanes takes
+            // wave's LDS scratch; row s of 16 lanes takes
             // point s, lane l of it centroids j = l, l + 16, ...: the FP32
             // direct form sum (x_t - c_t)^2 (c_t = -m2_t / 2 exactly), within
             // (d + 2) u (1 + u)^(d+2) of the exact value, with j in its eight
