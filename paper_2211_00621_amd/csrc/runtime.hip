@@ -139,8 +139,8 @@ size_t mx_workspace_bytes(mx_ws_kind kind, int64_t n, int64_t aux) {
         // counters + one 8-byte partial per block (at most 4096 blocks)
         return kCounterBytes + align256(8 * 4096);
     case MX_WS_SCAN: {
-        // counters + one int64 per scan tile of 4096 rows (+1)
-        int64_t tiles = (n + 4095) / 4096 + 1;
+        // counters + one int64 per scan tile of 1024 rows (+1)
+        int64_t tiles = (n + 1023) / 1024 + 1;
         return kCounterBytes + align256((size_t)tiles * 8);
     }
     case MX_WS_HISTOGRAM: return histogram_ws_bytes(n, aux);

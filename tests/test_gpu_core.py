@@ -206,7 +206,7 @@ def test_dot_gradient_closed_form():
 
 
 # ------------------------------------------------------------------ marshaling
-@pytest.mark.parametrize("nseg", [0, 1, 4095, 4096, 4097, 65536, 9_000_001])
+@pytest.mark.parametrize("nseg", [0, 1, 1023, 1024, 1025, 4095, 4096, 4097, 65536, 9_000_001])
 def test_lengths_to_offsets_exact(nseg):
     say("offsets", nseg)
     L = W.ragged_lengths(nseg, seed=3, lmax=100) if nseg else np.zeros(0, dtype=np.int64)
