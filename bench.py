@@ -82,7 +82,7 @@ TRAFFIC = {
     # k_kmeans_fused<32,64,true>, 2^20 x 32 points, k = 64: 134.68 MB fetched (X, 1.00x) + 12.11 MB written
     # (labels, and 768 block partials stored in 32-byte entry groups)
     "kmeans": {"file": "kmeans.hip", "bytes": 146787426,
-               "source": "25b5e41069dab98000d6e15e1b18c2272ec8ddfe0a6610b9fd18783f12bd8f78"},
+               "source": "95677d42d858d4619795cb5ed38f6f76aab63f86eb15388f06b026b39355abe0"},
     # k_seg_broadcast (row-span path): 2.66 MB fetched (offsets, gradients) + 128.71 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 131368857,
                       "source": "0686cb00be55993e28720ed811452195d1bf6d3521d8f62ab3d08d9c4fe2204a"},

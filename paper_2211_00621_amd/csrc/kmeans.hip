@@ -44,7 +44,7 @@
 // HBM overlaps the work.  The products run one block of 16 points at a time
 // and the four lane groups' candidates are merged through lane swaps, not LDS,
 // so that at d = 32, k = 64 three blocks of four waves fit a CU (168
-// registers, 53.5 KB of LDS per block).
+// registers, 51.5 KB of LDS per block).
 //
 // Reduce-by-key from the registers that already hold the chunk: lane
 // (g, l16) holds dimensions 8g..8g+7 of points mi*16 + l16 and adds them to
