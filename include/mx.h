@@ -147,8 +147,8 @@ mx_status mx_stream_read(const void *src_dev, int64_t n, uint32_t *xor_dev, hipS
  * lengths).  Negative lengths are the caller's error (checked in debug mode,
  * MX_ERR_SHAPE); offsets must stay below 2^62.  Workspace kind MX_WS_SCAN with
  * n = nseg (unused for nseg <= 1024); the call leaves it all zero again.
- * One pass over the lengths: tiles of 1024 rows chained by decoupled
- * look-back through status words in the workspace. */
+ * One pass over the lengths: tiles of 1024 rows (4096 beyond 65 536 rows)
+ * chained by decoupled look-back through status words in the workspace. */
 mx_status mx_lengths_to_offsets(const int64_t *lengths_dev, int64_t nseg, int64_t *offsets_dev,
                                 void *ws, size_t ws_bytes, hipStream_t stream);
 

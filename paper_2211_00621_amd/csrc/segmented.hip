@@ -1144,10 +1144,9 @@ int rows_per_block(int64_t nseg, const DeviceInfo *d) {
 }
 
 // ---------------------------------------------------------------- lengths -> offsets
-// Tiles of 1024 rows (4 per thread; 64 tiles for 65 536 rows, each tile's
-// loads short enough that the look-back, not the load, sets the pace: 5.5 us
-// back to back against 6.7-7.1 us with tiles of 4096), scanned in LDS (one pad
-// slot per 16 entries).  One tile: one block.  More: a single pass with decoupled
+// Tiles of 1024 rows (4 per thread) up to 64 tiles (65 536 rows: 5.5 us back
+// to back against 6.7-7.1 us with tiles of 4096), else tiles of 4096 (16 per
+// thread), scanned in LDS (one pad slot per 16 entries).  One tile: one block.  More: a single pass with decoupled
 // look-back -- blocks claim tiles in order from a counter, publish their
 // tile's total, then walk back over earlier tiles' published totals until one
 // carries its inclusive prefix, and publish their own.  A status word packs
@@ -1155,8 +1154,12 @@ int rows_per_block(int64_t nseg, const DeviceInfo *d) {
 // atomic carries both; tile i waits only on tiles claimed before it, whose
 // blocks are running, so the wait always ends.  The last block to finish
 // clears the status words and counters for the next call.
-constexpr int kScanPer = 4;
-constexpr int kScanTile = NT * kScanPer;
+// rows per thread: 4 (tiles of 1024 rows) up to 64 such tiles, where the
+// tiles' own loads set the pace; 16 (tiles of 4096) beyond, where the
+// look-back over more tiles would (2^20 rows: 16.4 us with tiles of 1024
+// against 11.5 us)
+constexpr int kScanPerSmall = 4, kScanPerLarge = 16;
+constexpr int64_t kScanSmallRows = 64 * NT * kScanPerSmall;
 constexpr uint64_t kStatAgg = 1ull << 62, kStatPre = 2ull << 62, kStatVal = (1ull << 62) - 1;
 // one pad slot per 16 entries
 __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
@@ -1191,11 +1194,11 @@ __device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
 
 // counters[0]: next tile to claim; counters[1]: blocks finished.  LOOKBACK
 // false: a single block scans the single tile.
-template <bool LOOKBACK>
+template <bool LOOKBACK, int PER>
 __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ len, int64_t n,
                                                    int64_t *__restrict__ off, unsigned *counters,
                                                    uint64_t *status, int ntiles) {
-    __shared__ int64_t tile[kScanTile + kScanTile / 16];
+    __shared__ int64_t tile[(NT * PER) + (NT * PER) / 16];
     __shared__ int64_t wsum[NT / kWave];
     __shared__ int64_t sh_prefix;
     __shared__ int sh_tile, sh_last;
@@ -1204,19 +1207,19 @@ __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ l
         __syncthreads();
     }
     const int t = LOOKBACK ? sh_tile : 0;
-    const int64_t base = (int64_t)t * kScanTile;
+    const int64_t base = (int64_t)t * (NT * PER);
     // coalesced load into LDS
 #pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
         int64_t i = base + j * NT + threadIdx.x;
         tile[spad(j * NT + threadIdx.x)] = i < n ? len[i] : 0;
     }
     __syncthreads();
-    int64_t mine[kScanPer];
+    int64_t mine[PER];
     int64_t s = 0;
 #pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
-        mine[j] = tile[spad(threadIdx.x * kScanPer + j)];
+    for (int j = 0; j < PER; ++j) {
+        mine[j] = tile[spad(threadIdx.x * PER + j)];
         s += mine[j];
     }
     int64_t total;
@@ -1256,17 +1259,17 @@ __global__ void __launch_bounds__(NT) k_scan_tiles(const int64_t *__restrict__ l
     const int64_t prefix = sh_prefix;
     int64_t run = prefix + ex;
 #pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
-        tile[spad(threadIdx.x * kScanPer + j)] = run;
+    for (int j = 0; j < PER; ++j) {
+        tile[spad(threadIdx.x * PER + j)] = run;
         run += mine[j];
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
         int64_t i = base + j * NT + threadIdx.x;
         if (i < n) off[i] = tile[spad(j * NT + threadIdx.x)];
     }
-    if (base + kScanTile >= n && threadIdx.x == 0) off[n] = prefix + total;
+    if (base + (NT * PER) >= n && threadIdx.x == 0) off[n] = prefix + total;
     if (LOOKBACK) {
         // every other block has finished its look-back when the last one arrives
         if (threadIdx.x == 0) sh_last = atomicAdd(&counters[1], 1u) == (unsigned)ntiles - 1;
@@ -1497,11 +1500,12 @@ mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, voi
     if (mx_status st = device_info(&d)) return st;
     if (nseg > 0 && debug_mode())
         if (mx_status st = validate_lengths("mx_lengths_to_offsets", len, nseg, s, d)) return st;
-    const int64_t ntiles = ceil_div(nseg, kScanTile);
+    const bool small = nseg <= kScanSmallRows;
+    const int64_t ntiles = ceil_div(nseg, (int64_t)NT * (small ? kScanPerSmall : kScanPerLarge));
     MX_REQUIRE(ntiles <= 0x7fffffff, MX_ERR_SHAPE, "mx_lengths_to_offsets: too many rows");
     if (ntiles <= 1) {
-        hipLaunchKernelGGL(k_scan_tiles<false>, dim3(1), dim3(NT), 0, s, len, nseg, off, (unsigned *)nullptr,
-                           (uint64_t *)nullptr, 1);
+        hipLaunchKernelGGL((k_scan_tiles<false, kScanPerSmall>), dim3(1), dim3(NT), 0, s, len, nseg, off,
+                           (unsigned *)nullptr, (uint64_t *)nullptr, 1);
         return last_launch("mx_lengths_to_offsets");
     }
     size_t need = mx_workspace_bytes(MX_WS_SCAN, nseg, 0);
@@ -1509,8 +1513,12 @@ mx_status lengths_to_offsets(const int64_t *len, int64_t nseg, int64_t *off, voi
     MX_REQUIRE(((uintptr_t)ws & 255) == 0, MX_ERR_INVALID, "mx_lengths_to_offsets: workspace must be 256-byte aligned");
     unsigned *counters = (unsigned *)ws;
     uint64_t *status = (uint64_t *)((char *)ws + kCounterBytes);
-    hipLaunchKernelGGL(k_scan_tiles<true>, dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, off, counters, status,
-                       (int)ntiles);
+    if (small)
+        hipLaunchKernelGGL((k_scan_tiles<true, kScanPerSmall>), dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, off,
+                           counters, status, (int)ntiles);
+    else
+        hipLaunchKernelGGL((k_scan_tiles<true, kScanPerLarge>), dim3((unsigned)ntiles), dim3(NT), 0, s, len, nseg, off,
+                           counters, status, (int)ntiles);
     return last_launch("mx_lengths_to_offsets");
 }
 
