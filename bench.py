@@ -66,7 +66,7 @@ TRAFFIC = {
     # k_seg_span (row-span path, nontemporal loads), 65536 rows / 32.1 M values: 132.97 MB fetched + 0.26 MB
     # written (1.03x algorithmic: 129.19 MB)
     "seg_span": {"file": "segmented.hip", "bytes": 133236853,
-                 "source": "0686cb00be55993e28720ed811452195d1bf6d3521d8f62ab3d08d9c4fe2204a"},
+                 "source": "a8bece18ab4e27185c0dc7f3fd5dd1e17669a291e87375a06719fcbf9360ccc5"},
     # mx_xvjp (generated from expr.hip) for exp(-(a-b)^2)*0.5 + a*b over 2^26 float32 pairs:
     # 536.89 MB fetched + 536.83 MB written (1.00x algorithmic)
     "expr_vjp": {"file": "expr.hip", "bytes": 1073735829,
@@ -85,7 +85,7 @@ TRAFFIC = {
                "source": "95677d42d858d4619795cb5ed38f6f76aab63f86eb15388f06b026b39355abe0"},
     # k_seg_broadcast (row-span path): 2.66 MB fetched (offsets, gradients) + 128.71 MB written
     "seg_broadcast": {"file": "segmented.hip", "bytes": 131368857,
-                      "source": "0686cb00be55993e28720ed811452195d1bf6d3521d8f62ab3d08d9c4fe2204a"},
+                      "source": "a8bece18ab4e27185c0dc7f3fd5dd1e17669a291e87375a06719fcbf9360ccc5"},
 }
 
 
